@@ -1,0 +1,134 @@
+"""Damped normal equations and their explicit Schur complement (FP64).
+
+The linearized, damped least-squares problem is Sec. 4.1, eq.
+linearized_residual: minimize |r + J_p dx_p + J_l dx_l|^2 + lambda |D_p dx_p|^2
++ lambda |D_l dx_l|^2.  Its normal equations are eq. normal_eq with the blocks
+H_pp = J_p^T J_p, H_pl = J_p^T J_l, H_ll = J_l^T J_l, b_p = J_p^T r,
+b_l = J_l^T r (plus lambda D^2 on the diagonal).  The Schur complement
+(Sec. 4.2, eq. red_normal_eq) is
+    H~ = H_pp - H_pl H_ll^-1 H_lp,   b~ = b_p - H_pl H_ll^-1 b_l,
+solved as H~ (-dx_p) = b~, followed by the back-substitution eq. backsub_sc,
+    -dx_l = H_ll^-1 (b_l - H_lp (-dx_p)).
+By Sec. 4.4 (eq. red_H, red_b, and the closing remark on the damped problem)
+this is exactly the reduced camera system that nullspace marginalization
+produces, so it is the reference for the GPU path.
+
+Column scaling (Sec. 5.4): every column of the full Jacobian is scaled to
+unit norm, J~ = J S with s_c = 1 / |J_c| (a zero column keeps s_c = 1).  The
+damping matrix is D^2 = diag(J~^T J~) (Sec. 4.1), which is the identity after
+scaling, so D_p = D_l = I in scaled coordinates and dx = S dx~.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+from .bookkeeping import Bookkeeping
+from .camera import CameraState, linearize_observations
+
+
+@dataclass
+class Linearization:
+    r: np.ndarray  # (n, 2)
+    Jp: np.ndarray  # (n, 2, 9) unscaled
+    Jl: np.ndarray  # (n, 2, 3) unscaled
+    ci: np.ndarray  # (n,)
+    pi: np.ndarray  # (n,)
+    n_cams: int
+    n_points: int
+    cost: float
+    sp: np.ndarray  # (n_cams, 9) column scales
+    sl: np.ndarray  # (n_points, 3)
+
+
+def column_scales(Jp: np.ndarray, Jl: np.ndarray, ci: np.ndarray, pi: np.ndarray,
+                  n_cams: int, n_points: int):
+    """s_c = 1 / |J_c| over all rows of the full Jacobian; empty columns get 1."""
+    cp = np.zeros((n_cams, 9))
+    np.add.at(cp, ci, np.sum(Jp * Jp, axis=1))
+    cl = np.zeros((n_points, 3))
+    np.add.at(cl, pi, np.sum(Jl * Jl, axis=1))
+    sp_ = np.where(cp > 0, 1.0 / np.sqrt(np.where(cp > 0, cp, 1.0)), 1.0)
+    sl_ = np.where(cl > 0, 1.0 / np.sqrt(np.where(cl > 0, cl, 1.0)), 1.0)
+    return sp_, sl_
+
+
+def linearize(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray) -> Linearization:
+    uv = np.asarray(obs_uv, dtype=np.float64)[bk.obs_perm]
+    r, Jp, Jl = linearize_observations(state, bk.ci, bk.pi, uv)
+    sp_, sl_ = column_scales(Jp, Jl, bk.ci, bk.pi, bk.n_cams, bk.n_points)
+    return Linearization(r, Jp, Jl, bk.ci, bk.pi, bk.n_cams, bk.n_points,
+                         float(np.sum(r * r)), sp_, sl_)
+
+
+def scaled_jacobian_sparse(lin: Linearization):
+    """J~_p (2n x 9 n_cams) and J~_l (2n x 3 n_points) as CSR matrices, and r (2n)."""
+    n = lin.r.shape[0]
+    rows = np.arange(2 * n).reshape(n, 2)
+    Jps = lin.Jp * lin.sp[lin.ci][:, None, :]
+    Jls = lin.Jl * lin.sl[lin.pi][:, None, :]
+    rp = np.repeat(rows[:, :, None], 9, axis=2)
+    cp = np.broadcast_to((9 * lin.ci)[:, None, None] + np.arange(9)[None, None, :], (n, 2, 9))
+    Jp_m = sp.csr_matrix((Jps.ravel(), (rp.ravel(), cp.ravel())), shape=(2 * n, 9 * lin.n_cams))
+    rl = np.repeat(rows[:, :, None], 3, axis=2)
+    cl = np.broadcast_to((3 * lin.pi)[:, None, None] + np.arange(3)[None, None, :], (n, 2, 3))
+    Jl_m = sp.csr_matrix((Jls.ravel(), (rl.ravel(), cl.ravel())), shape=(2 * n, 3 * lin.n_points))
+    return Jp_m, Jl_m, lin.r.ravel().copy()
+
+
+@dataclass
+class ReducedSystem:
+    H: np.ndarray  # (9 n_cams, 9 n_cams) dense, damped
+    b: np.ndarray  # (9 n_cams,)
+    lam: float
+    # pieces kept for the back-substitution
+    Hll_inv: sp.csr_matrix
+    Hpl: sp.csr_matrix
+    bl: np.ndarray
+
+
+def reduced_camera_system(lin: Linearization, lam: float) -> ReducedSystem:
+    """Explicit Schur complement of the damped, scaled normal equations (D = I)."""
+    Jp_m, Jl_m, r = scaled_jacobian_sparse(lin)
+    Hpp = (Jp_m.T @ Jp_m).toarray() + lam * np.eye(9 * lin.n_cams)
+    Hpl = (Jp_m.T @ Jl_m).tocsr()
+    bp = Jp_m.T @ r
+    bl = Jl_m.T @ r
+    # H_ll is block diagonal with 3x3 blocks; invert block by block
+    Jls = lin.Jl * lin.sl[lin.pi][:, None, :]
+    Hll = np.zeros((lin.n_points, 3, 3))
+    np.add.at(Hll, lin.pi, np.einsum("nki,nkj->nij", Jls, Jls))
+    Hll += lam * np.eye(3)[None]
+    used = np.zeros(lin.n_points, dtype=bool)
+    used[lin.pi] = True
+    Hll[~used] = np.eye(3)  # landmarks without rows: their columns are empty
+    inv = np.linalg.inv(Hll)
+    inv[~used] = 0.0
+    ii = (3 * np.arange(lin.n_points))[:, None, None] + np.arange(3)[None, :, None]
+    jj = (3 * np.arange(lin.n_points))[:, None, None] + np.arange(3)[None, None, :]
+    Hll_inv = sp.csr_matrix((inv.ravel(), (np.broadcast_to(ii, inv.shape).ravel(),
+                                          np.broadcast_to(jj, inv.shape).ravel())),
+                            shape=(3 * lin.n_points, 3 * lin.n_points))
+    W = (Hpl @ Hll_inv).tocsr()
+    H = Hpp - (W @ Hpl.T).toarray()
+    b = bp - W @ bl
+    return ReducedSystem(H, b, lam, Hll_inv, Hpl, bl)
+
+
+def back_substitute(rs: ReducedSystem, dxp_scaled: np.ndarray) -> np.ndarray:
+    """Scaled landmark increment dx~_l = -H_ll^-1 (b_l + H_lp dx~_p) (eq. backsub_sc)."""
+    return -(rs.Hll_inv @ (rs.bl + rs.Hpl.T @ dxp_scaled))
+
+
+def model_decrease(lin: Linearization, dxp_scaled: np.ndarray, dxl_scaled: np.ndarray) -> float:
+    """E - |r + J~ dx~|^2 evaluated row by row as -sum u (2 r + u), u = J~ dx~.
+
+    The undamped linear model is used, so the damping rows do not enter.
+    """
+    dp = dxp_scaled.reshape(lin.n_cams, 9) * lin.sp
+    dl = dxl_scaled.reshape(lin.n_points, 3) * lin.sl
+    u = np.einsum("nij,nj->ni", lin.Jp, dp[lin.ci]) + np.einsum("nij,nj->ni", lin.Jl, dl[lin.pi])
+    return float(-np.sum(u * (2.0 * lin.r + u)))

@@ -1,0 +1,147 @@
+"""Pins of the oracle's PCG, Levenberg-Marquardt loop, bookkeeping and profile helpers (CPU).
+
+* CG in exact arithmetic terminates in as many iterations as the matrix has
+  distinct eigenvalues (a textbook property): checked on a diagonal matrix.
+* PCG to 1e-12 on a reduced camera system equals a dense Cholesky solve.
+* With x0 = 0, the damped quadratic model decreases monotonically over CG
+  iterations (CG minimizes it over growing Krylov spaces).
+* LM (Sec. 6.1): accepted steps decrease the cost strictly; a noise-free
+  problem converges to ~0; with 1 px noise the final cost is close to its
+  expected value 2 n_obs - (n_unknowns - 7).
+* Bookkeeping equals a brute-force construction with Python loops.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.solvers import pcg
+from bal_synth import make_config, make_ring_problem
+
+
+def test_cg_terminates_after_number_of_distinct_eigenvalues():
+    d = np.repeat([1.0, 3.0, 7.0, 20.0], 10)
+    rng = np.random.default_rng(0)
+    b = rng.normal(size=d.size)
+    res = pcg(lambda v: d * v, b, None, tol=1e-10, max_iters=100)
+    assert res.status == "converged"
+    assert res.iters == 4
+    np.testing.assert_allclose(res.x, -b / d, rtol=1e-10)
+
+
+def test_pcg_matches_dense_solve_on_reduced_system():
+    rng = np.random.default_rng(1)
+    p = make_ring_problem(rng, 8, 200, lambda r, n: r.integers(2, 7, size=n))
+    bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv)
+    lin = oracle.linearize(oracle.state_from_bal(p.cameras, p.points), bk, p.obs_uv)
+    rs = oracle.reduced_camera_system(lin, 1e-4)
+    direct = oracle.dense_spd_solve(rs.H, -rs.b)
+    res = pcg(lambda v: rs.H @ v, rs.b, oracle.block_jacobi_blocks(rs.H), tol=1e-12, max_iters=2000,
+              trace=True)
+    assert res.status == "converged"
+    np.testing.assert_allclose(res.x, direct, rtol=1e-9, atol=1e-9 * np.abs(direct).max())
+    # monotone decrease of the quadratic model q(x) = 1/2 x^T H x + b^T x along the iterates
+    x = np.zeros_like(rs.b)
+    vals = [0.0]
+    rz_x = x
+    # rebuild iterates from the traced search directions: x_{k+1} = x_k + alpha_k p_k with
+    # alpha_k minimizing q along p_k
+    r = -rs.b.copy()
+    for pk, qk in zip(res.trace_p, res.trace_q):
+        alpha = (r @ pk) / (pk @ qk)
+        x = x + alpha * pk
+        r = r - alpha * qk
+        vals.append(0.5 * x @ rs.H @ x + rs.b @ x)
+    assert np.all(np.diff(vals) <= 1e-12 * abs(vals[-1]))
+
+
+def test_lm_noise_free_converges_to_zero():
+    p = make_config(0, noise_px=0.0)
+    res = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv,
+                          oracle.LMOptions(max_iters=20, func_tol=0.0, solver="dense"))
+    # the pixels are float32-rounded, which leaves a floor of about n_obs * (1e-5 px)^2
+    assert res.final_cost <= 1e-10 * res.cost0
+
+
+def test_lm_monotone_and_statistically_sane():
+    p = make_config(0)
+    res = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, oracle.LMOptions(max_iters=10))
+    acc = [h for h in res.history if h["accepted"]]
+    assert acc, "no accepted step"
+    costs = [res.cost0] + [h["new_cost"] for h in acc]
+    assert np.all(np.diff(costs) < 0)
+    dof = 2 * p.n_obs - (9 * p.n_cams + 3 * p.n_points - 7)
+    # chi-square with `dof` degrees of freedom: std sqrt(2 dof) ~ 88 for dof ~ 3.8e3
+    assert abs(res.final_cost - dof) < 5 * np.sqrt(2 * dof) + 0.01 * dof
+
+
+def test_lm_nielsen_rule_sequence():
+    p = make_config(0)
+    res = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, oracle.LMOptions(max_iters=10))
+    lam, nu = 1e-4, 2.0
+    for h in res.history:
+        assert h["lambda"] == pytest.approx(lam, rel=1e-12)
+        if h["accepted"]:
+            lam = lam * max(1 / 3, 1 - (2 * h["rho"] - 1) ** 3)
+            nu = 2.0
+        else:
+            lam, nu = lam * nu, 2 * nu
+
+
+def _brute_bookkeeping(n_cams, n_pts, oc, op):
+    triples = sorted((int(op[i]), int(oc[i]), i) for i in range(len(oc)))
+    counts = {}
+    for l, c, i in triples:
+        counts[l] = counts.get(l, 0) + 1
+    perm = [i for l, c, i in triples if counts[l] >= 2]
+    lm_off = [0]
+    for l in range(n_pts):
+        lm_off.append(lm_off[-1] + (counts.get(l, 0) if counts.get(l, 0) >= 2 else 0))
+    cams_sorted = [int(oc[i]) for i in perm]
+    cam_obs = [j for c in range(n_cams) for j, cc in enumerate(cams_sorted) if cc == c]
+    cam_active = [c in set(cams_sorted) for c in range(n_cams)]
+    return perm, lm_off, cam_obs, cam_active
+
+
+def test_bookkeeping_matches_brute_force():
+    rng = np.random.default_rng(5)
+    n_cams, n_pts = 7, 30
+    pairs = set()
+    while len(pairs) < 90:
+        pairs.add((int(rng.integers(0, n_cams)), int(rng.integers(0, n_pts))))
+    pairs = list(pairs)
+    rng.shuffle(pairs)
+    oc = np.array([a for a, b in pairs], dtype=np.int32)
+    op = np.array([b for a, b in pairs], dtype=np.int32)
+    bk = oracle.build_bookkeeping(n_cams, n_pts, oc, op)
+    perm, lm_off, cam_obs, cam_active = _brute_bookkeeping(n_cams, n_pts, oc, op)
+    assert bk.obs_perm.tolist() == perm
+    assert bk.lm_off.tolist() == lm_off
+    assert bk.cam_obs.tolist() == cam_obs
+    assert bk.cam_active.tolist() == cam_active
+
+
+@pytest.mark.parametrize("case", ["dup", "cam_range", "pt_range", "nan", "empty"])
+def test_bookkeeping_rejects_invalid_input(case):
+    oc = np.array([0, 1, 1, 2], dtype=np.int32)
+    op = np.array([0, 0, 1, 1], dtype=np.int32)
+    uv = np.zeros((4, 2), dtype=np.float32)
+    if case == "dup":
+        oc[1], op[1] = 0, 0
+    elif case == "cam_range":
+        oc[0] = 3
+    elif case == "pt_range":
+        op[0] = -1
+    elif case == "nan":
+        uv[2, 1] = np.nan
+    elif case == "empty":
+        oc, op, uv = oc[:0], op[:0], uv[:0]
+    with pytest.raises(oracle.BookkeepingError):
+        oracle.build_bookkeeping(3, 2, oc, op, uv)
+
+
+def test_time_to_tolerance_definition():
+    f_tau = oracle.cost_threshold(100.0, 10.0, 0.01)
+    assert f_tau == pytest.approx(10.9)
+    assert oracle.time_to_tolerance([1, 2, 3], [50, 10.95, 10.5], f_tau) == 3
+    assert oracle.time_to_tolerance([1, 2], [50, 20], f_tau) == float("inf")
