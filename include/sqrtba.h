@@ -1,0 +1,255 @@
+/*
+ * sqrtba.h -- C ABI of libsqrtba.so: square-root bundle adjustment on one
+ * AMD Instinct MI355X (gfx950), FP32, after Demmel, Sommer, Cremers, Usenko,
+ * "Square Root Bundle Adjustment for Large-Scale Reconstruction" (CVPR 2021).
+ *
+ * The calls follow the problem statement of the paper (Sec. 4): cameras,
+ * landmarks and observations define the energy E = sum |r_ij|^2
+ * (eq. ba_energy); one Levenberg-Marquardt step is linearize (Sec. 4.1,
+ * eq. linearized_residual), marginalize landmarks by QR (Sec. 4.3 and 5.2),
+ * damp (Sec. 5.3), solve the reduced camera system with PCG (Sec. 5.4,
+ * eq. cg_mult), back-substitute (eq. backsub_nm), and update (Sec. 6.1).
+ *
+ * Conventions shared by every call
+ *  - Every function returns a sqrtba_status; no C++ exception crosses the ABI.
+ *    On error the context state is unchanged and sqrtba_last_error() explains.
+ *  - Array arguments are HOST pointers unless stated otherwise; the library
+ *    copies inputs during the call and writes outputs before returning, so the
+ *    caller keeps ownership of all its buffers.  Device memory is owned by the
+ *    context (allocated by the library, or a caller-provided workspace bound
+ *    with sqrtba_bind_workspace) and released by sqrtba_destroy.
+ *  - All kernels run on the HIP stream given at creation (NULL = default).
+ *    Calls that return values synchronize that stream.
+ *  - A context may hold several independent problems (a batch, see
+ *    sqrtba_set_problems).  "[P]" marks an array with one entry per problem;
+ *    a single problem is the batch with P = 1, so a pointer to one scalar is a
+ *    valid [P] array.
+ *  - Cameras are the 9-vector (w, t, f, k1, k2) of the BAL "Snavely" model
+ *    (Sec. 6.2): P = R(w) X + t, p = -P_xy / P_z,
+ *    pixel = f (1 + k1 |p|^2 + k2 |p|^4) p, relative to the image centre.
+ *    Internally R is a matrix updated on the left, R <- Exp(dw) R.
+ *  - A landmark with fewer than two observations and a camera with no
+ *    observation are not errors: they are inactive and held fixed (Sec. 6.2
+ *    removes such landmarks in preprocessing).
+ *  - Not thread-safe: one context must not be used from two threads at once.
+ */
+#ifndef SQRTBA_H
+#define SQRTBA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sqrtba_ctx sqrtba_ctx;
+
+typedef enum {
+  SQRTBA_OK = 0,
+  SQRTBA_E_INVALID = -1,       /* bad argument or invalid input data */
+  SQRTBA_E_OOM = -2,           /* device or host allocation failed, or workspace too small */
+  SQRTBA_E_HIP = -3,           /* a HIP runtime call failed */
+  SQRTBA_E_STATE = -4,         /* call out of order (e.g. solve before marginalize) */
+  SQRTBA_E_NONFINITE = -5,     /* non-finite input value */
+  SQRTBA_E_UNSUPPORTED = -6    /* e.g. a landmark with more observations than SQRTBA_MAX_OBS_PER_LANDMARK */
+} sqrtba_status;
+
+/* Largest number of observations of one landmark the stored-block kernels accept. */
+#define SQRTBA_MAX_OBS_PER_LANDMARK 512
+
+/* Per-problem outcome of a PCG solve and of the LM loop. */
+enum {
+  SQRTBA_PCG_CONVERGED = 0,    /* |r_k| <= tol |r_0| (unpreconditioned) */
+  SQRTBA_PCG_MAX_ITERS = 1,
+  SQRTBA_PCG_BREAKDOWN = 2,    /* p^T A p <= 0 or a non-finite value; last x kept */
+  SQRTBA_PCG_ZERO_RHS = 3,
+  SQRTBA_PCG_INACTIVE = 4
+};
+enum {
+  SQRTBA_LM_MAX_ITERS = 0,
+  SQRTBA_LM_FUNC_TOL = 1,      /* accepted step with (E_old - E_new) / E_old < func_tol */
+  SQRTBA_LM_LAMBDA_MAX = 2,    /* damping reached lambda_max */
+  SQRTBA_LM_NONFINITE = 3
+};
+
+typedef struct {
+  double lambda0;        /* initial LM damping, 1e-4 (Sec. 6.1) */
+  double lambda_min;     /* 1e-16 */
+  double lambda_max;     /* 1e32; reaching it ends the solve */
+  double accept_ratio;   /* accept a step iff rho > accept_ratio, 1e-3 */
+  int32_t max_lm_iters;  /* every attempt counts, 50 (Sec. 6.1) */
+  double func_tol;       /* relative function tolerance, 1e-6 (Sec. 6.1) */
+  int32_t pcg_max_iters; /* 500, no minimum (Sec. 6.1) */
+  double pcg_rel_tol;    /* stop when |r_k| / |r_0| <= tol, 1e-6 */
+  int32_t pcg_check_every; /* host checks convergence every n iterations (device flags stop work in between), 8 */
+  int32_t use_graph;     /* capture chunks of PCG iterations in a HIP graph, 1 */
+} sqrtba_options;
+
+typedef struct {
+  double initial_cost;
+  double final_cost;
+  int32_t iterations;    /* LM attempts, accepted or not */
+  int32_t accepted;
+  int32_t total_pcg_iters;
+  int32_t status;        /* SQRTBA_LM_* */
+  double solve_seconds;  /* wall time from loop start until this problem finished */
+  double time_to_tol;    /* seconds until cost <= tol_cost, or -1 (set by sqrtba_lm_solve_tracked) */
+} sqrtba_lm_report;
+
+typedef struct {
+  int32_t iter;
+  int32_t accepted;
+  int32_t pcg_iters;
+  int32_t pcg_status;
+  double lambda;
+  double cost;           /* cost before the attempt */
+  double new_cost;       /* cost at the tentative state */
+  double model_decrease;
+  double rel_res;
+  double t_seconds;      /* wall time since the start of the LM loop, at the end of the attempt */
+} sqrtba_lm_record;
+
+/* Library version, for ABI checks. */
+int32_t sqrtba_version(void);
+
+/* Fill *opt with the defaults listed above. */
+void sqrtba_default_options(sqrtba_options* opt);
+
+/* Create a context on the current HIP device.  hip_stream is a hipStream_t
+ * (NULL: the default stream).  opt may be NULL for defaults. */
+int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_stream);
+
+/* Free every resource of ctx (NULL is allowed). */
+void sqrtba_destroy(sqrtba_ctx* ctx);
+
+/* Text of the last error of ctx; valid until the next call on ctx. */
+const char* sqrtba_last_error(const sqrtba_ctx* ctx);
+
+/* Optional, before sqrtba_set_cameras: split the context into n_problems
+ * independent problems.  cam_off and pt_off are CSR offsets of length
+ * n_problems + 1 (starting at 0) over the camera and landmark arrays;
+ * every observation must link a camera and a landmark of the same problem. */
+int32_t sqrtba_set_problems(sqrtba_ctx* ctx, int32_t n_problems, const int64_t* cam_off, const int64_t* pt_off);
+
+/* Cameras: n_cams x 9 floats, row-major, BAL order (w0 w1 w2 t0 t1 t2 f k1 k2). */
+int32_t sqrtba_set_cameras(sqrtba_ctx* ctx, int64_t n_cams, const float* params);
+
+/* Landmarks: n_points x 3 floats, row-major. */
+int32_t sqrtba_set_landmarks(sqrtba_ctx* ctx, int64_t n_points, const float* xyz);
+
+/* Observations: camera index, landmark index and pixel (u, v) each.  Sorts
+ * them by (landmark, camera) (the landmark blocks of Sec. 5.1), builds the
+ * CSR bookkeeping and checks them.  Errors: an index out of range, a
+ * duplicate (camera, landmark) pair, an observation linking two problems
+ * (SQRTBA_E_INVALID); a non-finite pixel (SQRTBA_E_NONFINITE); a landmark with
+ * more than SQRTBA_MAX_OBS_PER_LANDMARK observations (SQRTBA_E_UNSUPPORTED). */
+int32_t sqrtba_set_observations(sqrtba_ctx* ctx, int64_t n_obs, const int32_t* cam, const int32_t* pt,
+                                const float* uv);
+
+/* Device bytes the context needs once cameras, landmarks and observations are set. */
+int32_t sqrtba_workspace_bytes(const sqrtba_ctx* ctx, uint64_t* bytes);
+
+/* Use caller-owned DEVICE memory (at least sqrtba_workspace_bytes, 256-byte
+ * aligned) instead of allocating; it must outlive the context.  Uploads the
+ * problem.  Without this call the first compute call allocates and uploads. */
+int32_t sqrtba_bind_workspace(sqrtba_ctx* ctx, void* device_ptr, uint64_t bytes);
+
+/* Problems taking part in the following calls (mask[P], 1 = active).
+ * All problems are active after upload. */
+int32_t sqrtba_set_active(sqrtba_ctx* ctx, const uint8_t* mask);
+
+/* Kernel (a): residuals at the current state, cost[P] (may be NULL), and the
+ * unit-norm column scaling of the camera columns (Sec. 5.4). */
+int32_t sqrtba_linearize(sqrtba_ctx* ctx, double* cost);
+
+/* Kernel (b): for each landmark, linearize its observations, scale its
+ * Jacobian columns to unit norm, QR-factor J_l with three Householder
+ * reflections (Sec. 5.2) and store Q^T [J_p | r] as its landmark block
+ * (Sec. 5.1): the top three rows for back-substitution and the 2k-3
+ * nullspace rows of the reduced camera system (eq. reduced). */
+int32_t sqrtba_marginalize(sqrtba_ctx* ctx);
+
+/* Landmark damping (Sec. 5.3): fold sqrt(lambda) I into each landmark block
+ * with six Givens rotations, starting from the stored undamped rows each time,
+ * so a new lambda after a rejected step needs no new QR.  lambda[P] > 0. */
+int32_t sqrtba_damp(sqrtba_ctx* ctx, const double* lambda);
+
+/* Block-Jacobi preconditioner and right-hand side from the damped blocks,
+ * then PCG on the reduced camera system with the matrix-free product
+ * (B^T B + lambda I) v (Sec. 5.4, eq. cg_mult), from x0 = 0.  iters[P],
+ * rel_res[P] and pcg_status[P] (SQRTBA_PCG_*) may be NULL. */
+int32_t sqrtba_solve(sqrtba_ctx* ctx, int32_t* iters, double* rel_res, int32_t* pcg_status);
+
+/* Back-substitution of every landmark (eq. backsub_nm with the damped
+ * factors) and the decrease predicted by the undamped linear model,
+ * model_decrease[P] (may be NULL). */
+int32_t sqrtba_back_substitute(sqrtba_ctx* ctx, double* model_decrease);
+
+/* Tentative state x (+) dx and its cost new_cost[P] (may be NULL). */
+int32_t sqrtba_update(sqrtba_ctx* ctx, double* new_cost);
+
+/* Keep (accept[P] = 1) or drop the tentative state of each active problem. */
+int32_t sqrtba_commit(sqrtba_ctx* ctx, const uint8_t* accept);
+
+/* The whole Levenberg-Marquardt loop (Sec. 6.1) for every problem at once,
+ * report[P] may be NULL.  With tol_cost[P] (may be NULL) the report's
+ * time_to_tol records when each problem's cost first fell to tol_cost. */
+int32_t sqrtba_lm_solve(sqrtba_ctx* ctx, sqrtba_lm_report* report);
+int32_t sqrtba_lm_solve_tracked(sqrtba_ctx* ctx, const double* tol_cost, sqrtba_lm_report* report);
+
+/* Per-attempt history of problem `problem` from the last LM solve. */
+int32_t sqrtba_get_lm_history(const sqrtba_ctx* ctx, int32_t problem, sqrtba_lm_record* out, int32_t capacity,
+                              int32_t* n_records);
+
+/* Current state: n_cams x 9 (BAL order; w from the rotation matrix, host FP64) and n_points x 3. */
+int32_t sqrtba_get_cameras(sqrtba_ctx* ctx, float* params);
+int32_t sqrtba_get_landmarks(sqrtba_ctx* ctx, float* xyz);
+
+/* ---- inspection exports for tests (small problems) ---- */
+
+/* Canonical bookkeeping: obs_perm[n_active] (input index of each active
+ * observation sorted by (landmark, camera)), lm_off[n_points + 1],
+ * lm_active[n_points], cam_active[n_cams]; *n_active receives the count
+ * (call with NULL arrays first to size them). */
+int32_t sqrtba_debug_bookkeeping(const sqrtba_ctx* ctx, int64_t* n_active, int64_t* obs_perm, int64_t* lm_off,
+                                 uint8_t* lm_active, uint8_t* cam_active);
+
+/* Kernel (a)'s per-observation values at the current state, in obs_perm
+ * order: r[n_active x 2], Jp[n_active x 2 x 9], Jl[n_active x 2 x 3]
+ * (unscaled; any may be NULL). */
+int32_t sqrtba_debug_linearization(sqrtba_ctx* ctx, float* r, float* Jp, float* Jl);
+
+/* Column scales of the last linearize/marginalize: s_cam[n_cams x 9], s_pt[n_points x 3]. */
+int32_t sqrtba_debug_scales(sqrtba_ctx* ctx, float* s_cam, float* s_pt);
+
+/* Damped reduced-camera-system products (B^T B + lambda I) v in scaled
+ * coordinates for m vectors v[m x 9 n_cams] -> out[m x 9 n_cams]; and the
+ * right-hand side b~ = sum B^T (Q2^T r), rhs[9 n_cams].  Needs damp. */
+int32_t sqrtba_debug_rcs_matvec(sqrtba_ctx* ctx, int32_t m, const float* v, float* out);
+int32_t sqrtba_debug_rhs(sqrtba_ctx* ctx, float* rhs);
+
+/* Inverse block-Jacobi blocks [n_cams x 81] of the last solve. */
+int32_t sqrtba_debug_precond(sqrtba_ctx* ctx, float* minv);
+
+/* Landmark block of landmark `pt` after marginalize (and damp): *k receives
+ * its observation count (0: inactive).  If out != NULL it receives
+ * (2k+3) x (9k+4) floats: rows 0..2 the undamped top rows
+ * [Q1^T J_p | R1 | Q1^T r], rows 3..2k+2 the B rows [B | 0 | rho] (the 2k-3
+ * nullspace rows, then the 3 damping rows written by damp); pose columns are
+ * unscaled, landmark columns are scaled.  If factors != NULL it receives 24
+ * floats: R1 upper (6, row-major), Q1^T r (3), damped R upper (6), damped
+ * Q1^T r (3), landmark column scales (3), lambda of the last damp (1), 0, 0. */
+int32_t sqrtba_debug_block(sqrtba_ctx* ctx, int64_t pt, int32_t* k, float* out, float* factors);
+
+/* Solution of the last solve/back-substitution: scaled pose increment
+ * dxp[9 n_cams] and unscaled landmark increment dxl[n_points x 3]. */
+int32_t sqrtba_debug_solution(sqrtba_ctx* ctx, float* dxp_scaled, float* dxl);
+
+/* Replace the scaled pose increment (for testing back-substitution). */
+int32_t sqrtba_debug_set_pose_increment(sqrtba_ctx* ctx, const float* dxp_scaled);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SQRTBA_H */

@@ -46,22 +46,25 @@ def so3_exp(w: np.ndarray) -> np.ndarray:
 
 
 def so3_log(R: np.ndarray) -> np.ndarray:
-    """Angle-axis vector of rotation matrices (..., 3, 3), valid up to and at angle pi."""
+    """Angle-axis vector of rotation matrices (..., 3, 3), valid up to and at angle pi.
+
+    The angle is atan2(|v| / 2, (tr R - 1) / 2), v the antisymmetric part
+    (acos of the trace alone is ill-conditioned near pi).  Above pi/2 the axis
+    is taken from the symmetric part cos(t) I + (1 - cos(t)) a a^T, signed by v.
+    """
     R = np.asarray(R, dtype=np.float64)
     flat = R.reshape(-1, 3, 3)
     out = np.zeros((flat.shape[0], 3))
     for n, M in enumerate(flat):
-        c = np.clip(0.5 * (np.trace(M) - 1.0), -1.0, 1.0)
-        th = np.arccos(c)
+        c = 0.5 * (np.trace(M) - 1.0)
         v = np.array([M[2, 1] - M[1, 2], M[0, 2] - M[2, 0], M[1, 0] - M[0, 1]])
+        s = 0.5 * np.linalg.norm(v)
+        th = np.arctan2(s, c)
         if th < 1e-8:
             out[n] = 0.5 * v
-        elif np.pi - th > 1e-4:
-            out[n] = th / (2.0 * np.sin(th)) * v
+        elif c >= 0.0:
+            out[n] = th * v / (2.0 * s)
         else:
-            # near pi the antisymmetric part vanishes; the symmetric part is
-            # cos(t) I + (1 - cos(t)) a a^T, so a a^T is exact from it and the
-            # axis is its largest column, with the sign taken from v
             B = (0.5 * (M + M.T) - c * np.eye(3)) / (1.0 - c)
             i = int(np.argmax(np.diag(B)))
             a = B[:, i] / np.sqrt(max(B[i, i], 1e-300))

@@ -1,0 +1,1053 @@
+// Host side of libsqrtba.so: the C ABI of include/sqrtba.h, observation
+// bookkeeping, device memory layout and the Levenberg-Marquardt loop.
+// Every floating-point step of the solve runs in the HIP kernels of
+// kernels.hip; the host only sorts indices, moves data, reads back per-problem
+// scalars and takes the accept/reject decisions of Sec. 6.1.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sqrtba.h"
+#include "device.h"
+
+using namespace sqrtba;
+
+namespace {
+
+constexpr int32_t kVersion = 1;
+
+struct HostData {
+  // problem partition
+  int32_t P = 1;
+  std::vector<int64_t> cam_off{0, 0}, pt_off{0, 0};
+  bool problems_set = false;
+  // inputs
+  int64_t NC = -1, NL = -1;
+  std::vector<float> cams_bal;  // NC * 9
+  std::vector<float> pts;       // NL * 3
+  // bookkeeping
+  bool obs_set = false;
+  int64_t n_obs_in = 0, NO = 0, NS = 0;
+  std::vector<int64_t> obs_perm, lm_off;
+  std::vector<uint8_t> lm_active, cam_active;
+  std::vector<int32_t> ocam, olm;
+  std::vector<float> ouv;
+  std::vector<int32_t> cam_obs_off, cam_obs_idx, cam_prob, lm_prob, prob_cam_off, prob_lm_off;
+  std::vector<int32_t> slot_lm, slot_k, slot_obs0, slot_prob, lm_slot;
+  std::vector<int64_t> slot_boff, slot_toff;
+  std::vector<int32_t> wi_first, wi_count;
+  WorkClass wc[NUM_CLASSES];
+  int64_t poolB = 0, poolT = 0;
+};
+
+struct Arena {
+  void* base = nullptr;
+  uint64_t bytes = 0;
+  bool owned = false;
+};
+
+}  // namespace
+
+struct sqrtba_ctx {
+  sqrtba_options opt;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  std::string err;
+  HostData h;
+  Arena arena;
+  bool uploaded = false;
+  Dev d{};
+  Launch L{};
+  // pinned host staging for per-problem scalars
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  // pipeline state
+  bool linearized = false, marginalized = false, damped = false, solved = false, backsubbed = false,
+       updated = false;
+  std::vector<uint8_t> active;
+  // PCG graph
+  hipGraphExec_t graph = nullptr;
+  int graph_iters = 0;
+  // LM history
+  std::vector<std::vector<sqrtba_lm_record>> history;
+};
+
+namespace {
+
+int fail(sqrtba_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(ctx, SQRTBA_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(expr)              \
+  do {                         \
+    int s_ = (expr);           \
+    if (s_ != SQRTBA_OK) return s_; \
+  } while (0)
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Rodrigues' formula in double (half-angle form; series below 1e-8).
+void so3_exp_d(const double w[3], double R[9]) {
+  const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  const double th = std::sqrt(th2);
+  double a, b;
+  if (th < 1e-8) {
+    a = 1.0;
+    b = 0.5;
+  } else {
+    const double sh = std::sin(0.5 * th);
+    a = std::sin(th) / th;
+    b = 2.0 * sh * sh / th2;
+  }
+  const double W[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0;
+      for (int q = 0; q < 3; ++q) s += W[3 * i + q] * W[3 * q + j];
+      R[3 * i + j] = (i == j ? 1.0 : 0.0) + a * W[3 * i + j] + b * s;
+    }
+}
+
+// Angle-axis of a rotation matrix, valid up to and at angle pi.  The angle is
+// atan2(|v| / 2, (tr R - 1) / 2) with v the antisymmetric part (acos of the
+// trace alone loses half the digits near pi); for angles above pi/2 the axis
+// comes from the symmetric part, cos(t) I + (1 - cos(t)) a a^T, with the sign
+// of v.
+void so3_log_d(const double M[9], double w[3]) {
+  const double c = 0.5 * (M[0] + M[4] + M[8] - 1.0);
+  const double v[3] = {M[7] - M[5], M[2] - M[6], M[3] - M[1]};
+  const double s = 0.5 * std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const double th = std::atan2(s, c);
+  if (th < 1e-8) {
+    for (int i = 0; i < 3; ++i) w[i] = 0.5 * v[i];
+  } else if (c >= 0.0) {
+    for (int i = 0; i < 3; ++i) w[i] = th * v[i] / (2.0 * s);
+  } else {
+    double B[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        B[3 * i + j] = (0.5 * (M[3 * i + j] + M[3 * j + i]) - (i == j ? c : 0.0)) / (1.0 - c);
+    int i = 0;
+    if (B[4] > B[3 * i + i]) i = 1;
+    if (B[8] > B[3 * i + i]) i = 2;
+    double a[3];
+    const double nrm = std::sqrt(std::max(B[3 * i + i], 1e-300));
+    for (int j = 0; j < 3; ++j) a[j] = B[3 * j + i] / nrm;
+    const double an = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    double dot = 0;
+    for (int j = 0; j < 3; ++j) {
+      a[j] /= an;
+      dot += a[j] * v[j];
+    }
+    const double sg = dot < 0 ? -1.0 : 1.0;
+    for (int j = 0; j < 3; ++j) w[j] = sg * th * a[j];
+  }
+}
+
+int64_t width_of_h(int64_t k) { return (9 * k + 3) & ~int64_t(3); }
+
+// ------------------------------------------------------------ bookkeeping
+
+int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_t* pt, const float* uv) {
+  HostData& h = c->h;
+  if (n <= 0) return fail(c, SQRTBA_E_INVALID, "n_obs must be positive");
+  if (!cam || !pt || !uv) return fail(c, SQRTBA_E_INVALID, "null observation array");
+  std::vector<int32_t> cprob(h.NC), pprob(h.NL);
+  for (int32_t p = 0; p < h.P; ++p) {
+    for (int64_t i = h.cam_off[p]; i < h.cam_off[p + 1]; ++i) cprob[i] = p;
+    for (int64_t i = h.pt_off[p]; i < h.pt_off[p + 1]; ++i) pprob[i] = p;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (cam[i] < 0 || cam[i] >= h.NC) return fail(c, SQRTBA_E_INVALID, "observation %lld: camera %d out of range", (long long)i, cam[i]);
+    if (pt[i] < 0 || pt[i] >= h.NL) return fail(c, SQRTBA_E_INVALID, "observation %lld: landmark %d out of range", (long long)i, pt[i]);
+    if (!std::isfinite(uv[2 * i]) || !std::isfinite(uv[2 * i + 1]))
+      return fail(c, SQRTBA_E_NONFINITE, "observation %lld: non-finite pixel", (long long)i);
+    if (cprob[cam[i]] != pprob[pt[i]])
+      return fail(c, SQRTBA_E_INVALID, "observation %lld links problems %d and %d", (long long)i, cprob[cam[i]], pprob[pt[i]]);
+  }
+  // sort by (landmark, camera)
+  std::vector<int64_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = i;
+  std::vector<uint64_t> key(n);
+  for (int64_t i = 0; i < n; ++i) key[i] = ((uint64_t)(uint32_t)pt[i] << 32) | (uint32_t)cam[i];
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return key[a] < key[b] || (key[a] == key[b] && a < b); });
+  for (int64_t i = 1; i < n; ++i)
+    if (key[order[i]] == key[order[i - 1]])
+      return fail(c, SQRTBA_E_INVALID, "duplicate observation of landmark %d by camera %d", pt[order[i]], cam[order[i]]);
+  std::vector<int64_t> count(h.NL, 0);
+  for (int64_t i = 0; i < n; ++i) count[pt[i]]++;
+  for (int64_t l = 0; l < h.NL; ++l)
+    if (count[l] > SQRTBA_MAX_OBS_PER_LANDMARK)
+      return fail(c, SQRTBA_E_UNSUPPORTED, "landmark %lld has %lld observations (max %d)", (long long)l,
+                  (long long)count[l], SQRTBA_MAX_OBS_PER_LANDMARK);
+
+  HostData nb = h;  // build into a copy so errors leave the state unchanged
+  nb.n_obs_in = n;
+  nb.lm_active.assign(h.NL, 0);
+  nb.lm_off.assign(h.NL + 1, 0);
+  for (int64_t l = 0; l < h.NL; ++l) {
+    nb.lm_active[l] = count[l] >= 2;
+    nb.lm_off[l + 1] = nb.lm_off[l] + (nb.lm_active[l] ? count[l] : 0);
+  }
+  nb.obs_perm.clear();
+  for (int64_t i = 0; i < n; ++i)
+    if (nb.lm_active[pt[order[i]]]) nb.obs_perm.push_back(order[i]);
+  nb.NO = (int64_t)nb.obs_perm.size();
+  if (nb.NO > INT32_MAX / 64) return fail(c, SQRTBA_E_UNSUPPORTED, "too many observations");
+  nb.ocam.resize(nb.NO);
+  nb.olm.resize(nb.NO);
+  nb.ouv.resize(2 * nb.NO);
+  for (int64_t j = 0; j < nb.NO; ++j) {
+    const int64_t i = nb.obs_perm[j];
+    nb.ocam[j] = cam[i];
+    nb.olm[j] = pt[i];
+    nb.ouv[2 * j] = uv[2 * i];
+    nb.ouv[2 * j + 1] = uv[2 * i + 1];
+  }
+  // per-camera lists of sorted positions (counting sort keeps them ascending)
+  nb.cam_obs_off.assign(h.NC + 1, 0);
+  for (int64_t j = 0; j < nb.NO; ++j) nb.cam_obs_off[nb.ocam[j] + 1]++;
+  for (int64_t q = 0; q < h.NC; ++q) nb.cam_obs_off[q + 1] += nb.cam_obs_off[q];
+  nb.cam_obs_idx.assign(nb.NO, 0);
+  {
+    std::vector<int32_t> fill(nb.cam_obs_off.begin(), nb.cam_obs_off.end() - 1);
+    for (int64_t j = 0; j < nb.NO; ++j) nb.cam_obs_idx[fill[nb.ocam[j]]++] = (int32_t)j;
+  }
+  nb.cam_active.assign(h.NC, 0);
+  for (int64_t q = 0; q < h.NC; ++q) nb.cam_active[q] = nb.cam_obs_off[q + 1] > nb.cam_obs_off[q];
+  nb.cam_prob = cprob;
+  nb.lm_prob = pprob;
+  nb.prob_cam_off.resize(h.P + 1);
+  nb.prob_lm_off.resize(h.P + 1);
+  for (int32_t p = 0; p <= h.P; ++p) {
+    nb.prob_cam_off[p] = (int32_t)h.cam_off[p];
+    nb.prob_lm_off[p] = (int32_t)h.pt_off[p];
+  }
+  // slots: active landmarks by decreasing k (ties by landmark index)
+  std::vector<int32_t> act;
+  for (int64_t l = 0; l < h.NL; ++l)
+    if (nb.lm_active[l]) act.push_back((int32_t)l);
+  std::stable_sort(act.begin(), act.end(), [&](int32_t a, int32_t b) { return count[a] > count[b]; });
+  nb.NS = (int64_t)act.size();
+  nb.slot_lm = act;
+  nb.slot_k.resize(nb.NS);
+  nb.slot_obs0.resize(nb.NS);
+  nb.slot_prob.resize(nb.NS);
+  nb.slot_boff.resize(nb.NS);
+  nb.slot_toff.resize(nb.NS);
+  nb.lm_slot.assign(h.NL, -1);
+  int64_t ob = 0, ot = 0;
+  for (int64_t s = 0; s < nb.NS; ++s) {
+    const int32_t l = act[s];
+    const int64_t k = count[l];
+    nb.slot_k[s] = (int32_t)k;
+    nb.slot_obs0[s] = (int32_t)nb.lm_off[l];
+    nb.slot_prob[s] = pprob[l];
+    nb.slot_boff[s] = ob;
+    nb.slot_toff[s] = ot;
+    nb.lm_slot[l] = (int32_t)s;
+    const int64_t W = width_of_h(k);
+    ob += 2 * k * W;
+    ot += 3 * W;
+  }
+  nb.poolB = ob;
+  nb.poolT = ot;
+  // work items: classes are contiguous k ranges, and slots are sorted by k
+  nb.wi_first.clear();
+  nb.wi_count.clear();
+  for (int cl = NUM_CLASSES - 1; cl >= 0; --cl) {
+    nb.wc[cl].first_wi = (int)nb.wi_first.size();
+    const int tpw = 256 / kClasses[cl].team;
+    int64_t s = 0;
+    while (s < nb.NS && class_of_k(nb.slot_k[s]) != cl) ++s;
+    while (s < nb.NS && class_of_k(nb.slot_k[s]) == cl) {
+      int cnt = 0;
+      const int64_t s0 = s;
+      while (s < nb.NS && cnt < tpw && class_of_k(nb.slot_k[s]) == cl) { ++s; ++cnt; }
+      nb.wi_first.push_back((int32_t)s0);
+      nb.wi_count.push_back(cnt);
+    }
+    nb.wc[cl].count = (int)nb.wi_first.size() - nb.wc[cl].first_wi;
+  }
+  nb.obs_set = true;
+  h = std::move(nb);
+  return SQRTBA_OK;
+}
+
+// ------------------------------------------------------------ device memory
+
+struct Layout {
+  uint64_t total = 0;
+  uint64_t take(uint64_t bytes) {
+    const uint64_t at = total;
+    total += (bytes + 255) & ~uint64_t(255);
+    return at;
+  }
+};
+
+template <typename T>
+T* at(void* base, uint64_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+// Offsets of every device array; when base is null only the size is computed.
+uint64_t layout(const HostData& h, void* base, Dev* d) {
+  Layout L;
+  const uint64_t NC = h.NC, NL = h.NL, NO = h.NO, NS = h.NS, P = h.P, NW = h.wi_first.size();
+  Dev t{};
+  auto f32 = [&](uint64_t n) { return L.take(4 * n); };
+  auto f64 = [&](uint64_t n) { return L.take(8 * n); };
+  uint64_t o_cam = f32(16 * NC), o_camn = f32(16 * NC), o_pts = f32(4 * NL), o_ptsn = f32(4 * NL);
+  uint64_t o_ocam = f32(NO), o_olm = f32(NO), o_ouv = f32(2 * NO), o_coo = f32(NC + 1), o_coi = f32(NO);
+  uint64_t o_cpr = f32(NC), o_lpr = f32(NL), o_pco = f32(P + 1), o_plo = f32(P + 1);
+  uint64_t o_slm = f32(NS), o_sk = f32(NS), o_so = f32(NS), o_sp = f32(NS), o_sb = f64(NS), o_st = f64(NS);
+  uint64_t o_lms = f32(NL), o_wf = f32(NW), o_wc = f32(NW);
+  uint64_t o_pB = f32(h.poolB), o_pT = f32(h.poolT), o_lmd = f32(NS * LMD_STRIDE), o_rho = f32(2 * NO);
+  uint64_t o_sc = f32(9 * NC);
+  uint64_t o_v[6];
+  for (int i = 0; i < 6; ++i) o_v[i] = f32(9 * NC);
+  uint64_t o_minv = f32(81 * NC), o_ob = f32(54 * NO), o_dxl = f32(3 * NL);
+  uint64_t o_cp = f64(NC), o_cp2 = f64(NC), o_lp = f64(NL);
+  uint64_t o_s[8];
+  for (int i = 0; i < 8; ++i) o_s[i] = f64(P);
+  uint64_t o_it = f32(P), o_dn = f32(P), o_ps = f32(P), o_act = L.take(P), o_flag = L.take(P);
+  uint64_t o_cnt = f32(16), o_cf = f32(4);
+  if (base && d) {
+    t.P = (int32_t)P; t.NC = (int32_t)NC; t.NL = (int32_t)NL; t.NS = (int32_t)NS; t.NO = (int32_t)NO;
+    t.cam = at<float>(base, o_cam); t.cam_new = at<float>(base, o_camn);
+    t.pts = at<float4>(base, o_pts); t.pts_new = at<float4>(base, o_ptsn);
+    t.obs_cam = at<int32_t>(base, o_ocam); t.obs_lm = at<int32_t>(base, o_olm); t.obs_uv = at<float2>(base, o_ouv);
+    t.cam_obs_off = at<int32_t>(base, o_coo); t.cam_obs_idx = at<int32_t>(base, o_coi);
+    t.cam_prob = at<int32_t>(base, o_cpr); t.lm_prob = at<int32_t>(base, o_lpr);
+    t.prob_cam_off = at<int32_t>(base, o_pco); t.prob_lm_off = at<int32_t>(base, o_plo);
+    t.slot_lm = at<int32_t>(base, o_slm); t.slot_k = at<int32_t>(base, o_sk); t.slot_obs0 = at<int32_t>(base, o_so);
+    t.slot_prob = at<int32_t>(base, o_sp); t.slot_boff = at<int64_t>(base, o_sb); t.slot_toff = at<int64_t>(base, o_st);
+    t.lm_slot = at<int32_t>(base, o_lms); t.wi_first = at<int32_t>(base, o_wf); t.wi_count = at<int32_t>(base, o_wc);
+    t.poolB = at<float>(base, o_pB); t.poolT = at<float>(base, o_pT); t.lmd = at<float>(base, o_lmd);
+    t.rhoB = at<float>(base, o_rho); t.s_cam = at<float>(base, o_sc);
+    t.vx = at<float>(base, o_v[0]); t.vr = at<float>(base, o_v[1]); t.vz = at<float>(base, o_v[2]);
+    t.vp = at<float>(base, o_v[3]); t.vq = at<float>(base, o_v[4]); t.vb = at<float>(base, o_v[5]);
+    t.minv = at<float>(base, o_minv); t.obsbuf = at<float>(base, o_ob); t.dxl = at<float>(base, o_dxl);
+    t.cam_part = at<double>(base, o_cp); t.cam_part2 = at<double>(base, o_cp2); t.lm_part = at<double>(base, o_lp);
+    t.lambda = at<double>(base, o_s[0]); t.alpha = at<double>(base, o_s[1]); t.beta = at<double>(base, o_s[2]);
+    t.rz = at<double>(base, o_s[3]); t.rr = at<double>(base, o_s[4]); t.rr0 = at<double>(base, o_s[5]);
+    t.pcost = at<double>(base, o_s[6]); t.ppred = at<double>(base, o_s[7]);
+    t.iters = at<int32_t>(base, o_it); t.done = at<int32_t>(base, o_dn); t.pstatus = at<int32_t>(base, o_ps);
+    t.active = at<uint8_t>(base, o_act); t.flag = at<uint8_t>(base, o_flag);
+    t.counters = at<uint32_t>(base, o_cnt); t.chol_fail = at<int32_t>(base, o_cf);
+    *d = t;
+  }
+  return L.total;
+}
+
+int check_ready(sqrtba_ctx* c) {
+  if (c->h.NC < 0 || c->h.NL < 0 || !c->h.obs_set)
+    return fail(c, SQRTBA_E_STATE, "set cameras, landmarks and observations first");
+  return SQRTBA_OK;
+}
+
+template <typename T>
+int upload_vec(sqrtba_ctx* c, T* dst, const std::vector<T>& v) {
+  if (v.empty()) return SQRTBA_OK;
+  HIP_TRY(c, hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return SQRTBA_OK;
+}
+
+int upload_state(sqrtba_ctx* c) {
+  const HostData& h = c->h;
+  std::vector<float> cam(16 * h.NC, 0.f), pts(4 * h.NL, 0.f);
+  for (int64_t i = 0; i < h.NC; ++i) {
+    double w[3] = {h.cams_bal[9 * i], h.cams_bal[9 * i + 1], h.cams_bal[9 * i + 2]}, R[9];
+    so3_exp_d(w, R);
+    for (int j = 0; j < 9; ++j) cam[16 * i + j] = (float)R[j];
+    for (int j = 0; j < 6; ++j) cam[16 * i + 9 + j] = h.cams_bal[9 * i + 3 + j];
+  }
+  for (int64_t i = 0; i < h.NL; ++i)
+    for (int j = 0; j < 3; ++j) pts[4 * i + j] = h.pts[3 * i + j];
+  TRY(upload_vec(c, c->d.cam, cam));
+  TRY(upload_vec(c, reinterpret_cast<float*>(c->d.pts), pts));
+  return SQRTBA_OK;
+}
+
+int upload(sqrtba_ctx* c) {
+  const HostData& h = c->h;
+  Dev& d = c->d;
+  layout(h, c->arena.base, &d);
+  d.pcg_tol = (float)c->opt.pcg_rel_tol;
+  HIP_TRY(c, hipMemsetAsync(c->arena.base, 0, c->arena.bytes, c->stream));
+  TRY(upload_state(c));
+  TRY(upload_vec(c, d.obs_cam, h.ocam));
+  TRY(upload_vec(c, d.obs_lm, h.olm));
+  TRY(upload_vec(c, reinterpret_cast<float*>(d.obs_uv), h.ouv));
+  TRY(upload_vec(c, d.cam_obs_off, h.cam_obs_off));
+  TRY(upload_vec(c, d.cam_obs_idx, h.cam_obs_idx));
+  TRY(upload_vec(c, d.cam_prob, h.cam_prob));
+  TRY(upload_vec(c, d.lm_prob, h.lm_prob));
+  TRY(upload_vec(c, d.prob_cam_off, h.prob_cam_off));
+  TRY(upload_vec(c, d.prob_lm_off, h.prob_lm_off));
+  TRY(upload_vec(c, d.slot_lm, h.slot_lm));
+  TRY(upload_vec(c, d.slot_k, h.slot_k));
+  TRY(upload_vec(c, d.slot_obs0, h.slot_obs0));
+  TRY(upload_vec(c, d.slot_prob, h.slot_prob));
+  TRY(upload_vec(c, d.slot_boff, h.slot_boff));
+  TRY(upload_vec(c, d.slot_toff, h.slot_toff));
+  TRY(upload_vec(c, d.lm_slot, h.lm_slot));
+  TRY(upload_vec(c, d.wi_first, h.wi_first));
+  TRY(upload_vec(c, d.wi_count, h.wi_count));
+  c->active.assign(h.P, 1);
+  TRY(upload_vec(c, d.active, c->active));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->L.stream = c->stream;
+  for (int i = 0; i < NUM_CLASSES; ++i) c->L.wc[i] = h.wc[i];
+  const size_t need = (size_t)h.P * 64 + 64;
+  if (c->pinned_bytes < need) {
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    HIP_TRY(c, hipHostMalloc(&c->pinned, need, hipHostMallocDefault));
+    c->pinned_bytes = need;
+  }
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  c->uploaded = true;
+  c->linearized = c->marginalized = c->damped = c->solved = c->backsubbed = c->updated = false;
+  return SQRTBA_OK;
+}
+
+void release_arena(sqrtba_ctx* c) {
+  if (c->arena.owned && c->arena.base) (void)hipFree(c->arena.base);
+  c->arena = Arena{};
+  c->uploaded = false;
+}
+
+int ensure_uploaded(sqrtba_ctx* c) {
+  if (c->uploaded) return SQRTBA_OK;
+  TRY(check_ready(c));
+  const uint64_t bytes = layout(c->h, nullptr, nullptr);
+  release_arena(c);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(c, SQRTBA_E_OOM, "hipMalloc(%llu) failed: %s", (unsigned long long)bytes, hipGetErrorString(e));
+  c->arena = Arena{p, bytes, true};
+  return upload(c);
+}
+
+// read back n per-problem values of type T from a device array
+template <typename T>
+int readback(sqrtba_ctx* c, const T* dev, T* out, bool sync = true) {
+  const size_t bytes = sizeof(T) * c->h.P;
+  HIP_TRY(c, hipMemcpyAsync(c->pinned, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+  if (sync) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (out) std::memcpy(out, c->pinned, bytes);
+  return SQRTBA_OK;
+}
+
+int set_active_mask(sqrtba_ctx* c, const std::vector<uint8_t>& m) {
+  c->active = m;
+  HIP_TRY(c, hipMemcpyAsync(c->d.active, c->active.data(), c->active.size(), hipMemcpyHostToDevice, c->stream));
+  return SQRTBA_OK;
+}
+
+#define LAUNCH(ctx, expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(ctx, SQRTBA_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int do_linearize(sqrtba_ctx* c, double* cost) {
+  TRY(ensure_uploaded(c));
+  LAUNCH(c, launch_cam_linearize(c->d, c->L, true, false, c->d.active));
+  LAUNCH(c, launch_prob_sum(c->d, c->L, c->d.cam_part, c->d.prob_cam_off, c->d.pcost, c->d.active));
+  TRY(readback(c, c->d.pcost, cost));
+  c->linearized = true;
+  c->marginalized = c->damped = c->solved = c->backsubbed = c->updated = false;
+  return SQRTBA_OK;
+}
+
+int do_marginalize(sqrtba_ctx* c) {
+  TRY(ensure_uploaded(c));
+  if (!c->linearized) return fail(c, SQRTBA_E_STATE, "marginalize needs linearize");
+  LAUNCH(c, launch_marginalize(c->d, c->L, c->d.active));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->marginalized = true;
+  c->damped = c->solved = c->backsubbed = c->updated = false;
+  return SQRTBA_OK;
+}
+
+int do_damp(sqrtba_ctx* c, const double* lambda) {
+  if (!c->marginalized) return fail(c, SQRTBA_E_STATE, "damp needs marginalize");
+  if (!lambda) return fail(c, SQRTBA_E_INVALID, "null lambda");
+  for (int32_t p = 0; p < c->h.P; ++p)
+    if (c->active[p] && !(lambda[p] > 0.0 && std::isfinite(lambda[p])))
+      return fail(c, SQRTBA_E_INVALID, "lambda[%d] = %g must be positive and finite", p, lambda[p]);
+  std::memcpy(c->pinned, lambda, sizeof(double) * c->h.P);
+  HIP_TRY(c, hipMemcpyAsync(c->d.lambda, c->pinned, sizeof(double) * c->h.P, hipMemcpyHostToDevice, c->stream));
+  LAUNCH(c, launch_damp(c->d, c->L, c->d.active));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->damped = true;
+  c->solved = c->backsubbed = c->updated = false;
+  return SQRTBA_OK;
+}
+
+int run_pcg_chunk(sqrtba_ctx* c, int n) {
+  if (c->opt.use_graph && n == c->opt.pcg_check_every) {
+    if (!c->graph) {
+      hipGraph_t g = nullptr;
+      HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      hipError_t le = hipSuccess;
+      for (int i = 0; i < n && le == hipSuccess; ++i) le = launch_pcg_iteration(c->d, c->L);
+      hipError_t ee = hipStreamEndCapture(c->stream, &g);
+      if (le != hipSuccess) return fail(c, SQRTBA_E_HIP, "PCG capture: %s", hipGetErrorString(le));
+      if (ee != hipSuccess) return fail(c, SQRTBA_E_HIP, "PCG capture end: %s", hipGetErrorString(ee));
+      hipError_t ie = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        c->graph = nullptr;
+        return fail(c, SQRTBA_E_HIP, "PCG graph instantiate: %s", hipGetErrorString(ie));
+      }
+      c->graph_iters = n;
+    }
+    HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
+    return SQRTBA_OK;
+  }
+  for (int i = 0; i < n; ++i) LAUNCH(c, launch_pcg_iteration(c->d, c->L));
+  return SQRTBA_OK;
+}
+
+int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
+  if (!c->damped) return fail(c, SQRTBA_E_STATE, "solve needs damp");
+  const int P = c->h.P;
+  LAUNCH(c, launch_precond_rhs(c->d, c->L));
+  LAUNCH(c, launch_pcg_init(c->d, c->L));
+  std::vector<int32_t> done(P);
+  TRY(readback(c, c->d.done, done.data()));
+  auto all_done = [&]() {
+    for (int p = 0; p < P; ++p)
+      if (!done[p]) return false;
+    return true;
+  };
+  int it = 0;
+  const int every = std::max(1, c->opt.pcg_check_every);
+  while (it < c->opt.pcg_max_iters && !all_done()) {
+    const int n = std::min(every, c->opt.pcg_max_iters - it);
+    TRY(run_pcg_chunk(c, n));
+    it += n;
+    TRY(readback(c, c->d.done, done.data()));
+  }
+  std::vector<int32_t> its(P), st(P);
+  std::vector<double> rr(P), rr0(P);
+  TRY(readback(c, c->d.iters, its.data()));
+  TRY(readback(c, c->d.pstatus, st.data()));
+  TRY(readback(c, c->d.rr, rr.data()));
+  TRY(readback(c, c->d.rr0, rr0.data()));
+  for (int p = 0; p < P; ++p) {
+    if (iters) iters[p] = its[p];
+    if (status) status[p] = st[p];
+    if (rel_res) rel_res[p] = rr0[p] > 0 ? std::sqrt(std::max(rr[p], 0.0) / rr0[p]) : 0.0;
+  }
+  c->solved = true;
+  c->backsubbed = c->updated = false;
+  return SQRTBA_OK;
+}
+
+int do_backsub(sqrtba_ctx* c, double* pred) {
+  if (!c->solved) return fail(c, SQRTBA_E_STATE, "back_substitute needs solve");
+  LAUNCH(c, launch_backsub(c->d, c->L));
+  LAUNCH(c, launch_prob_sum(c->d, c->L, c->d.lm_part, c->d.prob_lm_off, c->d.ppred, c->d.active));
+  TRY(readback(c, c->d.ppred, pred));
+  c->backsubbed = true;
+  c->updated = false;
+  return SQRTBA_OK;
+}
+
+int do_update(sqrtba_ctx* c, double* new_cost) {
+  if (!c->backsubbed) return fail(c, SQRTBA_E_STATE, "update needs back_substitute");
+  LAUNCH(c, launch_update(c->d, c->L));
+  LAUNCH(c, launch_cam_linearize(c->d, c->L, false, true, c->d.active));
+  LAUNCH(c, launch_prob_sum(c->d, c->L, c->d.cam_part, c->d.prob_cam_off, c->d.pcost, c->d.active));
+  TRY(readback(c, c->d.pcost, new_cost));
+  c->updated = true;
+  return SQRTBA_OK;
+}
+
+int do_commit(sqrtba_ctx* c, const uint8_t* accept) {
+  if (!c->updated) return fail(c, SQRTBA_E_STATE, "commit needs update");
+  if (!accept) return fail(c, SQRTBA_E_INVALID, "null accept mask");
+  HIP_TRY(c, hipMemcpyAsync(c->d.flag, accept, c->h.P, hipMemcpyHostToDevice, c->stream));
+  LAUNCH(c, launch_commit(c->d, c->L));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  bool any = false;
+  for (int p = 0; p < c->h.P; ++p) any |= (c->active[p] && accept[p]);
+  c->updated = false;
+  if (any) c->linearized = c->marginalized = c->damped = c->solved = c->backsubbed = false;
+  return SQRTBA_OK;
+}
+
+int lm_loop(sqrtba_ctx* c, const double* tol_cost, sqrtba_lm_report* rep) {
+  TRY(ensure_uploaded(c));
+  const int P = c->h.P;
+  const sqrtba_options& o = c->opt;
+  c->history.assign(P, {});
+  std::vector<uint8_t> all(P, 1), fin(P, 0), acc(P, 0), relin(P, 0);
+  std::vector<double> E(P), Enew(P), pred(P), lam(P, o.lambda0), nu(P, 2.0), rel(P), t_tol(P, -1.0), t_fin(P, 0.0);
+  std::vector<int32_t> its(P), st(P), lm_it(P, 0), nacc(P, 0), tot_pcg(P, 0), lm_status(P, SQRTBA_LM_MAX_ITERS);
+  const double t0 = now_s();
+  TRY(set_active_mask(c, all));
+  TRY(do_linearize(c, E.data()));
+  TRY(do_marginalize(c));
+  std::vector<double> E0 = E;
+  for (int p = 0; p < P; ++p) {
+    if (!std::isfinite(E[p])) { fin[p] = 1; lm_status[p] = SQRTBA_LM_NONFINITE; }
+    if (tol_cost && E[p] <= tol_cost[p]) t_tol[p] = 0.0;
+    if (o.max_lm_iters <= 0) fin[p] = 1;
+  }
+  while (true) {
+    std::vector<uint8_t> act(P);
+    bool any = false;
+    for (int p = 0; p < P; ++p) { act[p] = !fin[p]; any |= act[p]; }
+    if (!any) break;
+    TRY(set_active_mask(c, act));
+    TRY(do_damp(c, lam.data()));
+    TRY(do_solve(c, its.data(), rel.data(), st.data()));
+    TRY(do_backsub(c, pred.data()));
+    TRY(do_update(c, Enew.data()));
+    for (int p = 0; p < P; ++p) {
+      acc[p] = 0;
+      if (!act[p]) continue;
+      const double rho = pred[p] > 0 ? (E[p] - Enew[p]) / pred[p] : -INFINITY;
+      acc[p] = std::isfinite(Enew[p]) && rho > o.accept_ratio;
+    }
+    TRY(do_commit(c, acc.data()));
+    const double tnow = now_s() - t0;
+    bool any_relin = false;
+    for (int p = 0; p < P; ++p) {
+      relin[p] = 0;
+      if (!act[p]) continue;
+      const double rho = pred[p] > 0 ? (E[p] - Enew[p]) / pred[p] : -INFINITY;
+      sqrtba_lm_record r{lm_it[p], acc[p], its[p], st[p], lam[p], E[p], Enew[p], pred[p], rel[p], tnow};
+      c->history[p].push_back(r);
+      lm_it[p]++;
+      tot_pcg[p] += its[p];
+      if (acc[p]) {
+        nacc[p]++;
+        const double rel_dec = (E[p] - Enew[p]) / E[p];
+        E[p] = Enew[p];
+        const double q = 2.0 * rho - 1.0;
+        lam[p] = std::min(std::max(lam[p] * std::max(1.0 / 3.0, 1.0 - q * q * q), o.lambda_min), o.lambda_max);
+        nu[p] = 2.0;
+        if (tol_cost && t_tol[p] < 0 && E[p] <= tol_cost[p]) t_tol[p] = tnow;
+        if (rel_dec < o.func_tol) { fin[p] = 1; lm_status[p] = SQRTBA_LM_FUNC_TOL; }
+        else relin[p] = 1;
+      } else {
+        lam[p] *= nu[p];
+        nu[p] *= 2.0;
+        if (lam[p] >= o.lambda_max) { fin[p] = 1; lm_status[p] = SQRTBA_LM_LAMBDA_MAX; }
+        lam[p] = std::max(lam[p], o.lambda_min);
+      }
+      if (!fin[p] && lm_it[p] >= o.max_lm_iters) { fin[p] = 1; lm_status[p] = SQRTBA_LM_MAX_ITERS; }
+      if (fin[p]) { relin[p] = 0; t_fin[p] = tnow; }
+      any_relin |= relin[p];
+    }
+    if (any_relin) {
+      std::vector<double> Er(P);
+      TRY(set_active_mask(c, relin));
+      TRY(do_linearize(c, Er.data()));
+      TRY(do_marginalize(c));
+      for (int p = 0; p < P; ++p)
+        if (relin[p]) E[p] = Er[p];
+    }
+    // problems that did not relinearize keep their blocks (marginalized) for re-damping
+    c->marginalized = true;
+    c->linearized = true;
+  }
+  TRY(set_active_mask(c, all));
+  if (rep)
+    for (int p = 0; p < P; ++p) {
+      rep[p].initial_cost = E0[p];
+      rep[p].final_cost = E[p];
+      rep[p].iterations = lm_it[p];
+      rep[p].accepted = nacc[p];
+      rep[p].total_pcg_iters = tot_pcg[p];
+      rep[p].status = lm_status[p];
+      rep[p].solve_seconds = t_fin[p];
+      rep[p].time_to_tol = t_tol[p];
+    }
+  return SQRTBA_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+
+extern "C" {
+
+int32_t sqrtba_version(void) { return kVersion; }
+
+void sqrtba_default_options(sqrtba_options* o) {
+  if (!o) return;
+  o->lambda0 = 1e-4;
+  o->lambda_min = 1e-16;
+  o->lambda_max = 1e32;
+  o->accept_ratio = 1e-3;
+  o->max_lm_iters = 50;
+  o->func_tol = 1e-6;
+  o->pcg_max_iters = 500;
+  o->pcg_rel_tol = 1e-6;
+  o->pcg_check_every = 8;
+  o->use_graph = 1;
+}
+
+int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_stream) {
+  if (!out) return SQRTBA_E_INVALID;
+  *out = nullptr;
+  sqrtba_ctx* c = new (std::nothrow) sqrtba_ctx();
+  if (!c) return SQRTBA_E_OOM;
+  sqrtba_default_options(&c->opt);
+  if (opt) c->opt = *opt;
+  if (c->opt.pcg_max_iters < 0 || c->opt.max_lm_iters < 0 || !(c->opt.lambda0 > 0) || c->opt.pcg_check_every < 1) {
+    delete c;
+    return SQRTBA_E_INVALID;
+  }
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return SQRTBA_E_HIP;
+  }
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return SQRTBA_E_HIP;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return SQRTBA_OK;
+}
+
+void sqrtba_destroy(sqrtba_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  release_arena(c);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* sqrtba_last_error(const sqrtba_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int32_t sqrtba_set_problems(sqrtba_ctx* c, int32_t n, const int64_t* cam_off, const int64_t* pt_off) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (c->h.NC >= 0 || c->h.NL >= 0) return fail(c, SQRTBA_E_STATE, "set_problems must precede set_cameras/set_landmarks");
+  if (n <= 0 || !cam_off || !pt_off) return fail(c, SQRTBA_E_INVALID, "need n_problems > 0 and offsets");
+  if (cam_off[0] != 0 || pt_off[0] != 0) return fail(c, SQRTBA_E_INVALID, "offsets must start at 0");
+  for (int32_t i = 0; i < n; ++i)
+    if (cam_off[i + 1] < cam_off[i] || pt_off[i + 1] < pt_off[i]) return fail(c, SQRTBA_E_INVALID, "offsets must not decrease");
+  c->h.P = n;
+  c->h.cam_off.assign(cam_off, cam_off + n + 1);
+  c->h.pt_off.assign(pt_off, pt_off + n + 1);
+  c->h.problems_set = true;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_set_cameras(sqrtba_ctx* c, int64_t n, const float* params) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (n <= 0 || !params) return fail(c, SQRTBA_E_INVALID, "need n_cams > 0 and parameters");
+  if (c->h.problems_set && c->h.cam_off.back() != n) return fail(c, SQRTBA_E_INVALID, "n_cams does not match the problem offsets");
+  if (c->h.obs_set && n != c->h.NC) return fail(c, SQRTBA_E_STATE, "camera count cannot change after set_observations");
+  for (int64_t i = 0; i < 9 * n; ++i)
+    if (!std::isfinite(params[i])) return fail(c, SQRTBA_E_NONFINITE, "camera parameter %lld is not finite", (long long)i);
+  c->h.NC = n;
+  c->h.cams_bal.assign(params, params + 9 * n);
+  if (!c->h.problems_set) c->h.cam_off = {0, n};
+  if (c->uploaded) {
+    TRY(upload_state(c));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->linearized = c->marginalized = c->damped = c->solved = c->backsubbed = c->updated = false;
+  }
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_set_landmarks(sqrtba_ctx* c, int64_t n, const float* xyz) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (n <= 0 || !xyz) return fail(c, SQRTBA_E_INVALID, "need n_points > 0 and coordinates");
+  if (c->h.problems_set && c->h.pt_off.back() != n) return fail(c, SQRTBA_E_INVALID, "n_points does not match the problem offsets");
+  if (c->h.obs_set && n != c->h.NL) return fail(c, SQRTBA_E_STATE, "landmark count cannot change after set_observations");
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(xyz[i])) return fail(c, SQRTBA_E_NONFINITE, "landmark coordinate %lld is not finite", (long long)i);
+  c->h.NL = n;
+  c->h.pts.assign(xyz, xyz + 3 * n);
+  if (!c->h.problems_set) c->h.pt_off = {0, n};
+  if (c->uploaded) {
+    TRY(upload_state(c));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->linearized = c->marginalized = c->damped = c->solved = c->backsubbed = c->updated = false;
+  }
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_set_observations(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_t* pt, const float* uv) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (c->h.NC < 0 || c->h.NL < 0) return fail(c, SQRTBA_E_STATE, "set cameras and landmarks first");
+  TRY(build_bookkeeping(c, n, cam, pt, uv));
+  release_arena(c);
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_workspace_bytes(const sqrtba_ctx* c, uint64_t* bytes) {
+  if (!c || !bytes) return SQRTBA_E_INVALID;
+  if (c->h.NC < 0 || c->h.NL < 0 || !c->h.obs_set) return SQRTBA_E_STATE;
+  *bytes = layout(c->h, nullptr, nullptr);
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_bind_workspace(sqrtba_ctx* c, void* ptr, uint64_t bytes) {
+  if (!c) return SQRTBA_E_INVALID;
+  TRY(check_ready(c));
+  const uint64_t need = layout(c->h, nullptr, nullptr);
+  if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255)) return fail(c, SQRTBA_E_INVALID, "workspace must be a 256-byte aligned device pointer");
+  if (bytes < need) return fail(c, SQRTBA_E_OOM, "workspace has %llu bytes, needs %llu", (unsigned long long)bytes, (unsigned long long)need);
+  release_arena(c);
+  c->arena = Arena{ptr, bytes, false};
+  return upload(c);
+}
+
+int32_t sqrtba_set_active(sqrtba_ctx* c, const uint8_t* mask) {
+  if (!c || !mask) return SQRTBA_E_INVALID;
+  TRY(ensure_uploaded(c));
+  std::vector<uint8_t> m(mask, mask + c->h.P);
+  for (auto& v : m) v = v ? 1 : 0;
+  TRY(set_active_mask(c, m));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_linearize(sqrtba_ctx* c, double* cost) {
+  if (!c) return SQRTBA_E_INVALID;
+  return do_linearize(c, cost);
+}
+int32_t sqrtba_marginalize(sqrtba_ctx* c) { return c ? do_marginalize(c) : SQRTBA_E_INVALID; }
+int32_t sqrtba_damp(sqrtba_ctx* c, const double* lambda) { return c ? do_damp(c, lambda) : SQRTBA_E_INVALID; }
+int32_t sqrtba_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
+  return c ? do_solve(c, iters, rel_res, status) : SQRTBA_E_INVALID;
+}
+int32_t sqrtba_back_substitute(sqrtba_ctx* c, double* pred) { return c ? do_backsub(c, pred) : SQRTBA_E_INVALID; }
+int32_t sqrtba_update(sqrtba_ctx* c, double* new_cost) { return c ? do_update(c, new_cost) : SQRTBA_E_INVALID; }
+int32_t sqrtba_commit(sqrtba_ctx* c, const uint8_t* accept) { return c ? do_commit(c, accept) : SQRTBA_E_INVALID; }
+int32_t sqrtba_lm_solve(sqrtba_ctx* c, sqrtba_lm_report* rep) { return c ? lm_loop(c, nullptr, rep) : SQRTBA_E_INVALID; }
+int32_t sqrtba_lm_solve_tracked(sqrtba_ctx* c, const double* tol, sqrtba_lm_report* rep) {
+  return c ? lm_loop(c, tol, rep) : SQRTBA_E_INVALID;
+}
+
+int32_t sqrtba_get_lm_history(const sqrtba_ctx* c, int32_t problem, sqrtba_lm_record* out, int32_t cap, int32_t* n) {
+  if (!c || !n) return SQRTBA_E_INVALID;
+  if (problem < 0 || problem >= (int32_t)c->history.size()) return SQRTBA_E_INVALID;
+  const auto& h = c->history[problem];
+  *n = (int32_t)h.size();
+  if (out)
+    for (int32_t i = 0; i < std::min(cap, *n); ++i) out[i] = h[i];
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_get_cameras(sqrtba_ctx* c, float* params) {
+  if (!c || !params) return SQRTBA_E_INVALID;
+  if (!c->uploaded) {
+    if (c->h.NC < 0) return fail(c, SQRTBA_E_STATE, "no cameras");
+    std::memcpy(params, c->h.cams_bal.data(), sizeof(float) * c->h.cams_bal.size());
+    return SQRTBA_OK;
+  }
+  std::vector<float> cam(16 * c->h.NC);
+  HIP_TRY(c, hipMemcpyAsync(cam.data(), c->d.cam, cam.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int64_t i = 0; i < c->h.NC; ++i) {
+    double R[9], w[3];
+    for (int j = 0; j < 9; ++j) R[j] = cam[16 * i + j];
+    so3_log_d(R, w);
+    for (int j = 0; j < 3; ++j) params[9 * i + j] = (float)w[j];
+    for (int j = 0; j < 6; ++j) params[9 * i + 3 + j] = cam[16 * i + 9 + j];
+  }
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_get_landmarks(sqrtba_ctx* c, float* xyz) {
+  if (!c || !xyz) return SQRTBA_E_INVALID;
+  if (!c->uploaded) {
+    if (c->h.NL < 0) return fail(c, SQRTBA_E_STATE, "no landmarks");
+    std::memcpy(xyz, c->h.pts.data(), sizeof(float) * c->h.pts.size());
+    return SQRTBA_OK;
+  }
+  std::vector<float> p(4 * c->h.NL);
+  HIP_TRY(c, hipMemcpyAsync(p.data(), c->d.pts, p.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int64_t i = 0; i < c->h.NL; ++i)
+    for (int j = 0; j < 3; ++j) xyz[3 * i + j] = p[4 * i + j];
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_bookkeeping(const sqrtba_ctx* c, int64_t* n_active, int64_t* obs_perm, int64_t* lm_off,
+                                 uint8_t* lm_active, uint8_t* cam_active) {
+  if (!c || !n_active) return SQRTBA_E_INVALID;
+  if (!c->h.obs_set) return SQRTBA_E_STATE;
+  const HostData& h = c->h;
+  *n_active = h.NO;
+  if (obs_perm) std::memcpy(obs_perm, h.obs_perm.data(), 8 * h.NO);
+  if (lm_off) std::memcpy(lm_off, h.lm_off.data(), 8 * (h.NL + 1));
+  if (lm_active) std::memcpy(lm_active, h.lm_active.data(), h.NL);
+  if (cam_active) std::memcpy(cam_active, h.cam_active.data(), h.NC);
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_linearization(sqrtba_ctx* c, float* r, float* Jp, float* Jl) {
+  if (!c) return SQRTBA_E_INVALID;
+  TRY(ensure_uploaded(c));
+  const int64_t NO = c->h.NO;
+  float* buf = nullptr;
+  HIP_TRY(c, hipMalloc(&buf, sizeof(float) * 26 * (NO > 0 ? NO : 1)));
+  hipError_t e = launch_debug_linearization(c->d, c->L, buf, buf + 2 * NO, buf + 20 * NO);
+  std::vector<float> hbuf(26 * NO);
+  if (e == hipSuccess) e = hipMemcpyAsync(hbuf.data(), buf, hbuf.size() * 4, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(c, SQRTBA_E_HIP, "debug_linearization: %s", hipGetErrorString(e));
+  if (r) std::memcpy(r, hbuf.data(), 8 * NO);
+  if (Jp) std::memcpy(Jp, hbuf.data() + 2 * NO, 72 * NO);
+  if (Jl) std::memcpy(Jl, hbuf.data() + 20 * NO, 24 * NO);
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_scales(sqrtba_ctx* c, float* s_cam, float* s_pt) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (!c->marginalized) return fail(c, SQRTBA_E_STATE, "scales need linearize and marginalize");
+  const HostData& h = c->h;
+  if (s_cam) {
+    HIP_TRY(c, hipMemcpyAsync(s_cam, c->d.s_cam, 36 * h.NC, hipMemcpyDeviceToHost, c->stream));
+  }
+  std::vector<float> lmd(LMD_STRIDE * h.NS);
+  if (h.NS) HIP_TRY(c, hipMemcpyAsync(lmd.data(), c->d.lmd, 4 * lmd.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (s_pt)
+    for (int64_t l = 0; l < h.NL; ++l)
+      for (int j = 0; j < 3; ++j)
+        s_pt[3 * l + j] = h.lm_slot[l] >= 0 ? lmd[LMD_STRIDE * h.lm_slot[l] + LMD_SL + j] : 1.0f;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_rcs_matvec(sqrtba_ctx* c, int32_t m, const float* v, float* out) {
+  if (!c || m < 0 || (m > 0 && (!v || !out))) return SQRTBA_E_INVALID;
+  if (!c->damped) return fail(c, SQRTBA_E_STATE, "rcs_matvec needs damp");
+  const int64_t N = 9 * c->h.NC;
+  float* buf = nullptr;
+  HIP_TRY(c, hipMalloc(&buf, 8 * N));
+  hipError_t e = hipSuccess;
+  for (int32_t i = 0; i < m && e == hipSuccess; ++i) {
+    e = hipMemcpyAsync(buf, v + N * i, 4 * N, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_matvec_only(c->d, c->L, buf, buf + N);
+    if (e == hipSuccess) e = hipMemcpyAsync(out + N * i, buf + N, 4 * N, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(c, SQRTBA_E_HIP, "rcs_matvec: %s", hipGetErrorString(e));
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_rhs(sqrtba_ctx* c, float* rhs) {
+  if (!c || !rhs) return SQRTBA_E_INVALID;
+  if (!c->damped) return fail(c, SQRTBA_E_STATE, "rhs needs damp");
+  LAUNCH(c, launch_precond_rhs(c->d, c->L));
+  HIP_TRY(c, hipMemcpyAsync(rhs, c->d.vb, 36 * c->h.NC, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_precond(sqrtba_ctx* c, float* minv) {
+  if (!c || !minv) return SQRTBA_E_INVALID;
+  if (!c->damped) return fail(c, SQRTBA_E_STATE, "precond needs damp");
+  LAUNCH(c, launch_precond_rhs(c->d, c->L));
+  HIP_TRY(c, hipMemcpyAsync(minv, c->d.minv, 4 * 81 * c->h.NC, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_block(sqrtba_ctx* c, int64_t pt, int32_t* k_out, float* out, float* factors) {
+  if (!c || !k_out) return SQRTBA_E_INVALID;
+  if (!c->marginalized) return fail(c, SQRTBA_E_STATE, "block needs marginalize");
+  const HostData& h = c->h;
+  if (pt < 0 || pt >= h.NL) return fail(c, SQRTBA_E_INVALID, "landmark out of range");
+  const int32_t s = h.lm_slot[pt];
+  if (s < 0) {
+    *k_out = 0;
+    return SQRTBA_OK;
+  }
+  const int64_t k = h.slot_k[s], W = width_of_h(k), C = 9 * k + 4;
+  *k_out = (int32_t)k;
+  if (!out && !factors) return SQRTBA_OK;
+  std::vector<float> T(3 * W), B(2 * k * W), rho(2 * k), lmd(LMD_STRIDE);
+  HIP_TRY(c, hipMemcpyAsync(T.data(), c->d.poolT + h.slot_toff[s], 4 * T.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(B.data(), c->d.poolB + h.slot_boff[s], 4 * B.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(rho.data(), c->d.rhoB + 2 * h.slot_obs0[s], 4 * rho.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(lmd.data(), c->d.lmd + LMD_STRIDE * s, 4 * LMD_STRIDE, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (out) {
+    std::fill(out, out + (2 * k + 3) * C, 0.f);
+    const float* R = lmd.data() + LMD_R;
+    const float Rfull[9] = {R[0], R[1], R[2], 0, R[3], R[4], 0, 0, R[5]};
+    for (int i = 0; i < 3; ++i) {
+      for (int64_t j = 0; j < 9 * k; ++j) out[i * C + j] = T[i * W + j];
+      for (int j = 0; j < 3; ++j) out[i * C + 9 * k + j] = Rfull[3 * i + j];
+      out[i * C + 9 * k + 3] = lmd[LMD_QR + i];
+    }
+    for (int64_t i = 0; i < 2 * k; ++i) {
+      for (int64_t j = 0; j < 9 * k; ++j) out[(3 + i) * C + j] = B[i * W + j];
+      out[(3 + i) * C + 9 * k + 3] = rho[i];
+    }
+  }
+  if (factors) std::memcpy(factors, lmd.data(), 4 * LMD_STRIDE);
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_solution(sqrtba_ctx* c, float* dxp, float* dxl) {
+  if (!c) return SQRTBA_E_INVALID;
+  TRY(ensure_uploaded(c));
+  if (dxp) HIP_TRY(c, hipMemcpyAsync(dxp, c->d.vx, 36 * c->h.NC, hipMemcpyDeviceToHost, c->stream));
+  if (dxl) HIP_TRY(c, hipMemcpyAsync(dxl, c->d.dxl, 12 * c->h.NL, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_set_pose_increment(sqrtba_ctx* c, const float* dxp) {
+  if (!c || !dxp) return SQRTBA_E_INVALID;
+  if (!c->damped) return fail(c, SQRTBA_E_STATE, "set_pose_increment needs damp");
+  HIP_TRY(c, hipMemcpyAsync(c->d.vx, dxp, 36 * c->h.NC, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->solved = true;
+  c->backsubbed = c->updated = false;
+  return SQRTBA_OK;
+}
+
+}  // extern "C"

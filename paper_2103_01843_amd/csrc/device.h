@@ -1,0 +1,123 @@
+// Internal interface between the host library (api.cpp) and the HIP kernels
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sqrtba {
+
+// Landmark work is split into size classes by observation count k; each class
+// maps one landmark to a "team" of lanes of a fixed size.  The classes are
+// contiguous k ranges; landmarks are ordered by decreasing k so the largest
+// blocks start first.
+enum { NUM_CLASSES = 5 };
+struct ClassInfo {
+  int team;     // lanes per landmark: 8, 16, 64, 256, 256
+  int kmin, kmax;
+  int ncg;      // float4 column groups per lane (only for team 256)
+};
+extern const ClassInfo kClasses[NUM_CLASSES];
+int class_of_k(int k);
+
+// Small per-landmark record (floats): R1 upper (6), Q1^T r (3), damped R upper (6),
+// damped Q1^T r (3), landmark column scales (3), lambda used (1), pad (2).
+enum { LMD_R = 0, LMD_QR = 6, LMD_RH = 9, LMD_QRH = 15, LMD_SL = 18, LMD_LAM = 21, LMD_STRIDE = 24 };
+
+// Device view of the whole context.  All pointers are device pointers.
+struct Dev {
+  int32_t P;       // problems
+  int32_t NC;      // cameras
+  int32_t NL;      // landmarks
+  int32_t NS;      // active landmarks (slots)
+  int32_t NO;      // active observations
+  // camera state: 16 floats per camera: R (row-major 9), t (3), f, k1, k2, pad
+  float* cam;
+  float* cam_new;
+  float4* pts;      // x, y, z, 0
+  float4* pts_new;
+  // sorted active observations (landmark-major, camera ascending)
+  int32_t* obs_cam;
+  int32_t* obs_lm;
+  float2* obs_uv;
+  int32_t* cam_obs_off;  // NC + 1
+  int32_t* cam_obs_idx;  // NO, sorted-observation positions per camera
+  int32_t* cam_prob;     // NC
+  int32_t* lm_prob;      // NL
+  int32_t* prob_cam_off; // P + 1
+  int32_t* prob_lm_off;  // P + 1
+  // slots (active landmarks in processing order)
+  int32_t* slot_lm;
+  int32_t* slot_k;
+  int32_t* slot_obs0;
+  int32_t* slot_prob;
+  int64_t* slot_boff;  // float offset of the B rows (2k x W) in poolB
+  int64_t* slot_toff;  // float offset of the undamped top rows (3 x W) in poolT
+  int32_t* lm_slot;    // NL, -1 when inactive
+  // work items: per class, a list of (first slot, count)
+  int32_t* wi_first;
+  int32_t* wi_count;
+  float* poolB;
+  float* poolT;
+  float* lmd;     // NS * LMD_STRIDE
+  float* rhoB;    // 2 * NO: residual column of the B rows of each landmark
+  float* s_cam;   // NC * 9
+  // PCG vectors (9 NC each)
+  float* vx;
+  float* vr;
+  float* vz;
+  float* vp;
+  float* vq;
+  float* vb;      // right-hand side b~
+  float* minv;    // NC * 81 inverse preconditioner blocks
+  float* obsbuf;  // NO * 54: per-observation partial products (matvec uses the first 9 NO)
+  float* dxl;     // NL * 3, unscaled landmark increment
+  double* cam_part;  // NC, per-camera partial sums
+  double* cam_part2; // NC
+  double* lm_part;   // NL, per-landmark partial sums
+  // per-problem scalars
+  double* lambda;
+  double* alpha;
+  double* beta;
+  double* rz;
+  double* rr;
+  double* rr0;
+  int32_t* iters;
+  int32_t* done;
+  int32_t* pstatus;
+  double* pcost;
+  double* ppred;
+  uint8_t* active;
+  uint8_t* flag;     // generic per-problem mask (relinearize / accept)
+  uint32_t* counters;  // last-block counters (zeroed once; each user resets its own)
+  int32_t* chol_fail;  // count of preconditioner blocks that fell back to the diagonal
+  float pcg_tol;
+};
+
+struct WorkClass {
+  int first_wi;  // first work item of this class
+  int count;     // number of work items (workgroups)
+};
+
+struct Launch {
+  hipStream_t stream;
+  WorkClass wc[NUM_CLASSES];
+};
+
+// kernel launchers (kernels.hip); return hipSuccess or the launch error
+hipError_t launch_cam_linearize(const Dev& d, const Launch& L, bool jac, bool use_new, const uint8_t* mask);
+hipError_t launch_prob_sum(const Dev& d, const Launch& L, const double* vals, const int32_t* off, double* out,
+                           const uint8_t* mask);
+hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask);
+hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask);
+hipError_t launch_precond_rhs(const Dev& d, const Launch& L);
+hipError_t launch_pcg_init(const Dev& d, const Launch& L);
+hipError_t launch_pcg_iteration(const Dev& d, const Launch& L);
+hipError_t launch_backsub(const Dev& d, const Launch& L);
+hipError_t launch_update(const Dev& d, const Launch& L);
+hipError_t launch_commit(const Dev& d, const Launch& L);
+// test helpers
+hipError_t launch_matvec_only(const Dev& d, const Launch& L, const float* v_scaled, float* out);
+hipError_t launch_debug_linearization(const Dev& d, const Launch& L, float* r, float* Jp, float* Jl);
+
+}  // namespace sqrtba

@@ -1,0 +1,1341 @@
+// HIP kernels of the square-root bundle-adjustment hot path, written for
+// gfx950 (CDNA4, 64-lane wavefronts).  FP32 arithmetic throughout; sums across
+// cameras, landmarks and observations of one problem are accumulated in FP64
+// with fixed-shape trees, so every result is run-to-run deterministic.
+//
+// Landmark-centric kernels (marginalize, damp, preconditioner/RHS, matvec,
+// back-substitution) give each landmark a team of 8, 16, 64 or 256 lanes
+// chosen by its observation count k.  A team of <= 64 lanes lives inside one
+// wavefront and reduces with DPP row operations (no LDS, no barrier); a team
+// of 256 lanes is a whole workgroup.  Per-camera sums are never formed with
+// atomics: the landmark kernels write per-observation results and camera
+// kernels sum them over each camera's observation list.
+//
+// The matrix algebra is the paper's: nullspace marginalization by QR of each
+// landmark's J_l (Sec. 4.3, Householder variant of Sec. 5.2), landmark damping
+// by six Givens rotations (Sec. 5.3), and CG on the reduced normal equations
+// with the product (Q2^T J_p)^T (Q2^T J_p v) + lambda v (Sec. 5.4, eq. cg_mult).
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace sqrtba {
+
+const ClassInfo kClasses[NUM_CLASSES] = {
+    {8, 2, 3, 1},        // W <= 28 floats -> 7 column groups
+    {16, 4, 7, 1},       // W <= 64 -> 16 column groups
+    {64, 8, 28, 1},      // W <= 252 -> 63 column groups
+    {256, 29, 113, 4},   // W <= 1020 -> 255 column groups, 4 per lane
+    {256, 114, 512, 18}, // W <= 4608 -> 1152 column groups, 18 per lane
+};
+
+int class_of_k(int k) {
+  for (int c = 0; c < NUM_CLASSES; ++c)
+    if (k >= kClasses[c].kmin && k <= kClasses[c].kmax) return c;
+  return -1;
+}
+
+namespace {
+
+constexpr int WG = 256;
+
+__device__ __forceinline__ int width_of(int k) { return (9 * k + 3) & ~3; }
+
+// ---------------------------------------------------------------- reductions
+
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// All-reduce over aligned groups of TEAM lanes (8, 16 or 64).  Every lane of
+// the group receives the bitwise-identical sum (each step adds a commutative
+// pair).  All lanes of a group must be active together.
+template <int TEAM>
+__device__ __forceinline__ float team_sum(float v) {
+  v += dppf<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dppf<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dppf<0x141>(v);  // row_half_mirror: pairs quads of a half row
+  if constexpr (TEAM >= 16) v += dppf<0x140>(v);  // row_mirror: pairs half rows
+  if constexpr (TEAM >= 64) {
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+  }
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) { return team_sum<64>(v); }
+
+// Workgroup all-reduce of a float (256 lanes = 4 waves), deterministic.
+__device__ __forceinline__ float block_sum(float v, float* red4) {
+  v = wave_sum_f(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red4[w] = v;
+  __syncthreads();
+  return (red4[0] + red4[1]) + (red4[2] + red4[3]);
+}
+
+template <int TEAM>
+__device__ __forceinline__ float tsum(float v, float* red4) {
+  if constexpr (TEAM <= 64)
+    return team_sum<TEAM>(v);
+  else
+    return block_sum(v, red4);
+}
+
+// Visibility of LDS writes to the rest of the team.
+template <int TEAM>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (TEAM <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- camera model
+
+struct Cam {
+  float R[9];
+  float t[3];
+  float f, k1, k2;
+};
+
+__device__ __forceinline__ void load_cam(const float* __restrict__ cam, int c, Cam& C) {
+  const float4* p = reinterpret_cast<const float4*>(cam + 16 * (size_t)c);
+  float4 a = p[0], b = p[1], d = p[2], e = p[3];
+  C.R[0] = a.x; C.R[1] = a.y; C.R[2] = a.z; C.R[3] = a.w;
+  C.R[4] = b.x; C.R[5] = b.y; C.R[6] = b.z; C.R[7] = b.w;
+  C.R[8] = d.x; C.t[0] = d.y; C.t[1] = d.z; C.t[2] = d.w;
+  C.f = e.x; C.k1 = e.y; C.k2 = e.z;
+}
+
+// BAL projection: P = R X + t, p = -P_xy / P_z, pi = f (1 + k1 |p|^2 + k2 |p|^4) p,
+// r = pi - uv.  With JAC, Jp (2x9) w.r.t. (left rotation increment, t, f, k1, k2)
+// and Jl (2x3) w.r.t. X.
+template <bool JAC>
+__device__ __forceinline__ void project(const Cam& C, float X0, float X1, float X2, float u, float v,
+                                        float r[2], float Jp[2][9], float Jl[2][3]) {
+  const float RX0 = C.R[0] * X0 + C.R[1] * X1 + C.R[2] * X2;
+  const float RX1 = C.R[3] * X0 + C.R[4] * X1 + C.R[5] * X2;
+  const float RX2 = C.R[6] * X0 + C.R[7] * X1 + C.R[8] * X2;
+  const float P0 = RX0 + C.t[0], P1 = RX1 + C.t[1], P2 = RX2 + C.t[2];
+  const float iz = 1.0f / P2;
+  const float p0 = -P0 * iz, p1 = -P1 * iz;
+  const float n2 = p0 * p0 + p1 * p1;
+  const float d = 1.0f + n2 * (C.k1 + C.k2 * n2);
+  const float fd = C.f * d;
+  r[0] = fd * p0 - u;
+  r[1] = fd * p1 - v;
+  if constexpr (JAC) {
+    // dpi/dp = f (d I + g p p^T), g = 2 (k1 + 2 k2 |p|^2)
+    const float fg = C.f * 2.0f * (C.k1 + 2.0f * C.k2 * n2);
+    const float a00 = fd + fg * p0 * p0, a01 = fg * p0 * p1, a11 = fd + fg * p1 * p1;
+    // dp/dP = [[-iz, 0, -p0 iz], [0, -iz, -p1 iz]]
+    const float A00 = -a00 * iz, A01 = -a01 * iz, A02 = -(a00 * p0 + a01 * p1) * iz;
+    const float A10 = -a01 * iz, A11 = -a11 * iz, A12 = -(a01 * p0 + a11 * p1) * iz;
+    // rotation: dP/d(dw) = -[RX]_x = [[0, RX2, -RX1], [-RX2, 0, RX0], [RX1, -RX0, 0]]
+    Jp[0][0] = -A01 * RX2 + A02 * RX1;
+    Jp[0][1] = A00 * RX2 - A02 * RX0;
+    Jp[0][2] = -A00 * RX1 + A01 * RX0;
+    Jp[1][0] = -A11 * RX2 + A12 * RX1;
+    Jp[1][1] = A10 * RX2 - A12 * RX0;
+    Jp[1][2] = -A10 * RX1 + A11 * RX0;
+    Jp[0][3] = A00; Jp[0][4] = A01; Jp[0][5] = A02;
+    Jp[1][3] = A10; Jp[1][4] = A11; Jp[1][5] = A12;
+    Jp[0][6] = d * p0;          Jp[1][6] = d * p1;
+    Jp[0][7] = C.f * n2 * p0;   Jp[1][7] = C.f * n2 * p1;
+    Jp[0][8] = C.f * n2 * n2 * p0; Jp[1][8] = C.f * n2 * n2 * p1;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Jl[0][j] = A00 * C.R[j] + A01 * C.R[3 + j] + A02 * C.R[6 + j];
+      Jl[1][j] = A10 * C.R[j] + A11 * C.R[3 + j] + A12 * C.R[6 + j];
+    }
+  }
+}
+
+// ---------------------------------------------------- kernel (a): per camera
+
+// One wavefront per camera: cost (FP64 sum of FP32 squared residuals) and,
+// with JAC, the unit-norm scale of each of the camera's 9 Jacobian columns
+// (1 / column norm; an empty column keeps scale 1).
+template <bool JAC>
+__global__ __launch_bounds__(64) void k_cam_linearize(Dev d, const float* __restrict__ cam,
+                                                      const float4* __restrict__ pts, const uint8_t* mask) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (mask && !mask[d.cam_prob[c]]) return;
+  Cam C;
+  load_cam(cam, c, C);
+  float n2[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) n2[j] = 0.f;
+  double cost = 0.0;
+  const int b = d.cam_obs_off[c], e = d.cam_obs_off[c + 1];
+  for (int i = b + lane; i < e; i += 64) {
+    const int o = d.cam_obs_idx[i];
+    const float4 X = pts[d.obs_lm[o]];
+    const float2 uv = d.obs_uv[o];
+    float r[2], Jp[2][9], Jl[2][3];
+    project<JAC>(C, X.x, X.y, X.z, uv.x, uv.y, r, Jp, Jl);
+    cost += (double)(r[0] * r[0] + r[1] * r[1]);
+    if constexpr (JAC) {
+#pragma unroll
+      for (int j = 0; j < 9; ++j) n2[j] += Jp[0][j] * Jp[0][j] + Jp[1][j] * Jp[1][j];
+    }
+  }
+  cost = wave_sum_d(cost);
+  if constexpr (JAC) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) n2[j] = wave_sum_f(n2[j]);
+    if (lane < 9) {
+      float v = n2[0];
+#pragma unroll
+      for (int j = 1; j < 9; ++j) v = (lane == j) ? n2[j] : v;
+      d.s_cam[9 * c + lane] = v > 0.f ? 1.0f / sqrtf(v) : 1.0f;
+    }
+  }
+  if (lane == 0) d.cam_part[c] = cost;
+}
+
+// One wavefront per problem: out[p] = sum of vals[off[p] .. off[p+1]) (fixed tree).
+__global__ __launch_bounds__(64) void k_prob_sum(const double* __restrict__ vals, const int32_t* __restrict__ off,
+                                                 double* out, const uint8_t* mask) {
+  const int p = blockIdx.x;
+  if (mask && !mask[p]) return;
+  double s = 0.0;
+  for (int i = off[p] + (int)threadIdx.x; i < off[p + 1]; i += 64) s += vals[i];
+  s = wave_sum_d(s);
+  if (threadIdx.x == 0) out[p] = s;
+}
+
+// ------------------------------------------- kernel (b): marginalize by QR
+
+// Per landmark (team): linearize its k observations, scale the landmark columns
+// to unit norm, factor J_l (2k x 3) = Q R with three Householder reflections
+// H_j = I - tau_j v_j v_j^T, v_j = x + sign(x_j) |x| e_j (sign(0) = +1), and
+// write Q^T [J_p | r].  Q^T = I - V T^T V^T (compact WY form, T upper
+// triangular), so each output entry is the sparse J_p entry minus a rank-3
+// correction: only O(k) values are combined, and the O(k^2) output is written
+// once, coalesced, as float4 rows.
+//   rows 0..2   -> undamped top rows [Q1^T J_p | R1 | Q1^T r] (poolT, lmd)
+//   rows 3..2k-1 -> nullspace rows [Q2^T J_p | 0 | Q2^T r]    (poolB, rhoB)
+template <int TEAM, int KMAX>
+__global__ __launch_bounds__(WG) void k_marginalize(Dev d, int wi0, const uint8_t* mask) {
+  constexpr int TPW = WG / TEAM;  // teams per workgroup
+  // LDS per team: A (2k x 4, J_l scaled, updated in place), V (2k x 4), r (2k), Jp (k x 18)
+  constexpr int STRIDE = 8 * 2 * KMAX + 2 * KMAX + 18 * KMAX;
+  __shared__ float lds[TPW * STRIDE];
+  __shared__ float red4[4];
+  const int team = threadIdx.x / TEAM;
+  const int lane = threadIdx.x % TEAM;
+  const int wi = wi0 + blockIdx.x;
+  if (team >= d.wi_count[wi]) return;  // whole teams drop out together
+  const int slot = d.wi_first[wi] + team;
+  const int prob = d.slot_prob[slot];
+  if (mask && !mask[prob]) return;
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const int n = 2 * k;
+  const int W = width_of(k);
+  const int G = W >> 2;
+  float4* A = reinterpret_cast<float4*>(lds + team * STRIDE);
+  float4* V = A + 2 * KMAX;
+  float* rr = reinterpret_cast<float*>(V + 2 * KMAX);
+  float* Jpc = rr + 2 * KMAX;
+  const float4 X = d.pts[d.slot_lm[slot]];
+
+  // phase 1: residuals and Jacobians of the landmark's observations
+  float cl0 = 0.f, cl1 = 0.f, cl2 = 0.f;
+  for (int o = lane; o < k; o += TEAM) {
+    Cam C;
+    load_cam(d.cam, d.obs_cam[obs0 + o], C);
+    const float2 uv = d.obs_uv[obs0 + o];
+    float r[2], Jp[2][9], Jl[2][3];
+    project<true>(C, X.x, X.y, X.z, uv.x, uv.y, r, Jp, Jl);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      Jpc[18 * o + j] = Jp[0][j];
+      Jpc[18 * o + 9 + j] = Jp[1][j];
+    }
+    A[2 * o] = make_float4(Jl[0][0], Jl[0][1], Jl[0][2], 0.f);
+    A[2 * o + 1] = make_float4(Jl[1][0], Jl[1][1], Jl[1][2], 0.f);
+    rr[2 * o] = r[0];
+    rr[2 * o + 1] = r[1];
+    cl0 += Jl[0][0] * Jl[0][0] + Jl[1][0] * Jl[1][0];
+    cl1 += Jl[0][1] * Jl[0][1] + Jl[1][1] * Jl[1][1];
+    cl2 += Jl[0][2] * Jl[0][2] + Jl[1][2] * Jl[1][2];
+  }
+  cl0 = tsum<TEAM>(cl0, red4);
+  cl1 = tsum<TEAM>(cl1, red4);
+  cl2 = tsum<TEAM>(cl2, red4);
+  const float sl0 = cl0 > 0.f ? 1.0f / sqrtf(cl0) : 1.0f;
+  const float sl1 = cl1 > 0.f ? 1.0f / sqrtf(cl1) : 1.0f;
+  const float sl2 = cl2 > 0.f ? 1.0f / sqrtf(cl2) : 1.0f;
+  team_sync<TEAM>();
+  for (int i = lane; i < n; i += TEAM) {
+    float4 a = A[i];
+    a.x *= sl0; a.y *= sl1; a.z *= sl2;
+    A[i] = a;
+  }
+  team_sync<TEAM>();
+
+  // phase 2: three Householder reflections on the scaled J_l
+  float tau[3], Rm[3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    float part = 0.f;
+    for (int i = lane; i < n; i += TEAM) {
+      if (i >= j) {
+        const float4 a = A[i];
+        const float x = j == 0 ? a.x : (j == 1 ? a.y : a.z);
+        part += x * x;
+      }
+    }
+    const float sig = tsum<TEAM>(part, red4);
+    const float4 aj = A[j];
+    const float xj = j == 0 ? aj.x : (j == 1 ? aj.y : aj.z);
+    const float nrm = sqrtf(sig);
+    float alpha = 0.f, vj = 0.f, tj = 0.f;
+    if (nrm > 0.f) {
+      alpha = xj >= 0.f ? -nrm : nrm;
+      vj = xj - alpha;
+      const float vtv = sig - xj * xj + vj * vj;
+      tj = vtv > 0.f ? 2.0f / vtv : 0.f;
+    }
+    tau[j] = tj;
+    // reflector column j of V
+    for (int i = lane; i < n; i += TEAM) {
+      const float4 a = A[i];
+      const float x = j == 0 ? a.x : (j == 1 ? a.y : a.z);
+      const float vi = (tj == 0.f || i < j) ? 0.f : (i == j ? vj : x);
+      float4 vv = (j == 0) ? make_float4(0.f, 0.f, 0.f, 0.f) : V[i];
+      if (j == 0) vv.x = vi; else if (j == 1) vv.y = vi; else vv.z = vi;
+      V[i] = vv;
+    }
+    team_sync<TEAM>();
+    // apply H_j to the remaining columns m > j
+    float w1 = 0.f, w2 = 0.f;
+    for (int i = lane; i < n; i += TEAM) {
+      const float4 vv = V[i];
+      const float vi = j == 0 ? vv.x : (j == 1 ? vv.y : vv.z);
+      const float4 a = A[i];
+      if (j == 0) { w1 += vi * a.y; w2 += vi * a.z; }
+      else if (j == 1) { w2 += vi * a.z; }
+    }
+    if (j == 0) { w1 = tsum<TEAM>(w1, red4); w2 = tsum<TEAM>(w2, red4); }
+    else if (j == 1) { w2 = tsum<TEAM>(w2, red4); }
+    for (int i = lane; i < n; i += TEAM) {
+      const float4 vv = V[i];
+      const float vi = j == 0 ? vv.x : (j == 1 ? vv.y : vv.z);
+      float4 a = A[i];
+      if (j == 0) { a.y -= tj * vi * w1; a.z -= tj * vi * w2; }
+      else if (j == 1) { a.z -= tj * vi * w2; }
+      A[i] = a;
+    }
+    team_sync<TEAM>();
+    const float4 arow = A[j];
+    Rm[j][0] = 0.f; Rm[j][1] = 0.f; Rm[j][2] = 0.f;
+    if (j == 0) { Rm[0][0] = nrm > 0.f ? alpha : arow.x; Rm[0][1] = arow.y; Rm[0][2] = arow.z; }
+    if (j == 1) { Rm[1][1] = nrm > 0.f ? alpha : arow.y; Rm[1][2] = arow.z; }
+    if (j == 2) { Rm[2][2] = nrm > 0.f ? alpha : arow.z; }
+  }
+
+  // phase 3: T of the compact WY form (LAPACK larft, forward columnwise)
+  float d01 = 0.f, d02 = 0.f, d12 = 0.f, wr0 = 0.f, wr1 = 0.f, wr2 = 0.f;
+  for (int i = lane; i < n; i += TEAM) {
+    const float4 vv = V[i];
+    const float ri = rr[i];
+    d01 += vv.x * vv.y; d02 += vv.x * vv.z; d12 += vv.y * vv.z;
+    wr0 += vv.x * ri; wr1 += vv.y * ri; wr2 += vv.z * ri;
+  }
+  d01 = tsum<TEAM>(d01, red4); d02 = tsum<TEAM>(d02, red4); d12 = tsum<TEAM>(d12, red4);
+  wr0 = tsum<TEAM>(wr0, red4); wr1 = tsum<TEAM>(wr1, red4); wr2 = tsum<TEAM>(wr2, red4);
+  const float T00 = tau[0], T11 = tau[1], T22 = tau[2];
+  const float T01 = -tau[1] * T00 * d01;
+  const float T02 = -tau[2] * (T00 * d02 + T01 * d12);
+  const float T12 = -tau[2] * (T11 * d12);
+  // residual column: Q^T r = r - V (T^T (V^T r))
+  const float mr0 = T00 * wr0;
+  const float mr1 = T01 * wr0 + T11 * wr1;
+  const float mr2 = T02 * wr0 + T12 * wr1 + T22 * wr2;
+  float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  for (int i = lane; i < n; i += TEAM) {
+    const float4 vv = V[i];
+    const float val = rr[i] - (vv.x * mr0 + vv.y * mr1 + vv.z * mr2);
+    if (i < 3) lmd[LMD_QR + i] = val;
+    else d.rhoB[2 * (size_t)obs0 + (i - 3)] = val;
+  }
+  if (lane == 0) {
+    lmd[LMD_R + 0] = Rm[0][0]; lmd[LMD_R + 1] = Rm[0][1]; lmd[LMD_R + 2] = Rm[0][2];
+    lmd[LMD_R + 3] = Rm[1][1]; lmd[LMD_R + 4] = Rm[1][2]; lmd[LMD_R + 5] = Rm[2][2];
+    lmd[LMD_SL + 0] = sl0; lmd[LMD_SL + 1] = sl1; lmd[LMD_SL + 2] = sl2;
+  }
+
+  // phase 4: pose columns, Q^T J_p = J_p - V M with M = T^T (V^T J_p)
+  float* outT = d.poolT + d.slot_toff[slot];
+  float* outB = d.poolB + d.slot_boff[slot];
+  for (int g = lane; g < G; g += TEAM) {
+    float M0[4], M1[4], M2[4], j0[4], j1[4];
+    int row0[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * g + q;
+      M0[q] = M1[q] = M2[q] = j0[q] = j1[q] = 0.f;
+      row0[q] = -4;
+      if (c < 9 * k) {
+        const int o = (unsigned)c / 9u;
+        const int m = c - 9 * o;
+        const float a0 = Jpc[18 * o + m], a1 = Jpc[18 * o + 9 + m];
+        const float4 va = V[2 * o], vb = V[2 * o + 1];
+        const float W0 = va.x * a0 + vb.x * a1;
+        const float W1 = va.y * a0 + vb.y * a1;
+        const float W2 = va.z * a0 + vb.z * a1;
+        M0[q] = T00 * W0;
+        M1[q] = T01 * W0 + T11 * W1;
+        M2[q] = T02 * W0 + T12 * W1 + T22 * W2;
+        j0[q] = a0;
+        j1[q] = a1;
+        row0[q] = 2 * o;
+      }
+    }
+    for (int i = 0; i < n; ++i) {
+      const float4 vv = V[i];
+      float out[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float base = (i == row0[q]) ? j0[q] : ((i == row0[q] + 1) ? j1[q] : 0.f);
+        out[q] = base - (vv.x * M0[q] + vv.y * M1[q] + vv.z * M2[q]);
+      }
+      const float4 o4 = make_float4(out[0], out[1], out[2], out[3]);
+      if (i < 3)
+        reinterpret_cast<float4*>(outT + (size_t)i * W)[g] = o4;
+      else
+        reinterpret_cast<float4*>(outB + (size_t)(i - 3) * W)[g] = o4;
+    }
+  }
+}
+
+// ---------------------------------------------------- landmark damping
+
+// The six Givens rotations that fold sqrt(lambda) I (three rows appended
+// below R1) into the upper triangle: for damping row e = 0, 1, 2 and pivot
+// row j = e..2, rotate (top row j, damping row e) so that entry (e, j) of the
+// damping rows vanishes.  c = a / rho, s = b / rho with rho = hypot(a, b) of
+// the pivot entry a and the entry b to remove; rho = 0 gives the identity.
+// On return Rh holds the damped upper triangle, qrh the damped Q1^T r and
+// dr the residuals of the three rotated damping rows.
+struct Givens6 {
+  float c[6], s[6];
+};
+
+__device__ __forceinline__ void damping_rotations(const float* lmd, float sqlam, Givens6& G, float Rh[3][3],
+                                                  float qrh[3], float dr[3]) {
+  float t[3][4];  // top rows: 3 landmark columns + residual
+  t[0][0] = lmd[LMD_R + 0]; t[0][1] = lmd[LMD_R + 1]; t[0][2] = lmd[LMD_R + 2]; t[0][3] = lmd[LMD_QR + 0];
+  t[1][0] = 0.f;            t[1][1] = lmd[LMD_R + 3]; t[1][2] = lmd[LMD_R + 4]; t[1][3] = lmd[LMD_QR + 1];
+  t[2][0] = 0.f;            t[2][1] = 0.f;            t[2][2] = lmd[LMD_R + 5]; t[2][3] = lmd[LMD_QR + 2];
+  int idx = 0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    float dd[4] = {0.f, 0.f, 0.f, 0.f};
+    dd[e] = sqlam;
+#pragma unroll
+    for (int j = e; j < 3; ++j) {
+      const float a = t[j][j], b = dd[j];
+      const float rho = hypotf(a, b);
+      float c = 1.f, s = 0.f;
+      if (rho > 0.f) { c = a / rho; s = b / rho; }
+      G.c[idx] = c; G.s[idx] = s; ++idx;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const float tm = t[j][m], dm = dd[m];
+        t[j][m] = c * tm + s * dm;
+        dd[m] = -s * tm + c * dm;
+      }
+      dd[j] = 0.f;  // exactly eliminated
+    }
+    dr[e] = dd[3];
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    Rh[j][0] = t[j][0]; Rh[j][1] = t[j][1]; Rh[j][2] = t[j][2];
+    qrh[j] = t[j][3];
+  }
+  Rh[1][0] = 0.f; Rh[2][0] = 0.f; Rh[2][1] = 0.f;
+}
+
+// Apply the same rotation sequence to one column: top rows t[3] (in: undamped,
+// out: damped) and damping rows dd[3] (in: 0, out: the three new B rows).
+__device__ __forceinline__ void rotate_column(const Givens6& G, float t[3], float dd[3]) {
+  int idx = 0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    dd[e] = 0.f;
+#pragma unroll
+    for (int j = e; j < 3; ++j) {
+      const float c = G.c[idx], s = G.s[idx];
+      ++idx;
+      const float tm = t[j], dm = dd[e];
+      t[j] = c * tm + s * dm;
+      dd[e] = -s * tm + c * dm;
+    }
+  }
+}
+
+// Damping of every landmark block from its stored undamped top rows (so a new
+// lambda never needs a new QR): writes the three damping rows of B, their
+// residuals, and the damped R and Q1^T r into the landmark record.
+template <int TEAM>
+__global__ __launch_bounds__(WG) void k_damp(Dev d, int wi0, const uint8_t* mask) {
+  const int team = threadIdx.x / TEAM;
+  const int lane = threadIdx.x % TEAM;
+  const int wi = wi0 + blockIdx.x;
+  if (team >= d.wi_count[wi]) return;
+  const int slot = d.wi_first[wi] + team;
+  const int prob = d.slot_prob[slot];
+  if (mask && !mask[prob]) return;
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const int W = width_of(k);
+  const int G = W >> 2;
+  float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const float lam = (float)d.lambda[prob];
+  Givens6 Gv;
+  float Rh[3][3], qrh[3], dr[3];
+  damping_rotations(lmd, sqrtf(lam), Gv, Rh, qrh, dr);
+  if (lane == 0) {
+    lmd[LMD_RH + 0] = Rh[0][0]; lmd[LMD_RH + 1] = Rh[0][1]; lmd[LMD_RH + 2] = Rh[0][2];
+    lmd[LMD_RH + 3] = Rh[1][1]; lmd[LMD_RH + 4] = Rh[1][2]; lmd[LMD_RH + 5] = Rh[2][2];
+    lmd[LMD_QRH + 0] = qrh[0]; lmd[LMD_QRH + 1] = qrh[1]; lmd[LMD_QRH + 2] = qrh[2];
+    lmd[LMD_LAM] = lam;
+  }
+  if (lane < 3) d.rhoB[2 * (size_t)obs0 + 2 * k - 3 + lane] = dr[lane];
+  const float4* T = reinterpret_cast<const float4*>(d.poolT + d.slot_toff[slot]);
+  float4* B = reinterpret_cast<float4*>(d.poolB + d.slot_boff[slot] + (size_t)(2 * k - 3) * W);
+  for (int g = lane; g < G; g += TEAM) {
+    const float4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
+    float a[3], b[3];
+    float4 o0, o1, o2;
+    a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b); o0.x = b[0]; o1.x = b[1]; o2.x = b[2];
+    a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b); o0.y = b[0]; o1.y = b[1]; o2.y = b[2];
+    a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, b); o0.z = b[0]; o1.z = b[1]; o2.z = b[2];
+    a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, b); o0.w = b[0]; o1.w = b[1]; o2.w = b[2];
+    B[g] = o0;
+    B[G + g] = o1;
+    B[2 * G + g] = o2;
+  }
+}
+
+// ------------------------------------- block-Jacobi blocks and right-hand side
+
+// Per landmark and observation (camera slab j of its B rows, 2k x 9):
+// G_j = B_j^T B_j (45 upper entries) and g_j = B_j^T rho_B, unscaled, written
+// to obsbuf[obs][0..53].  One lane owns one observation and walks the rows.
+template <int TEAM>
+__global__ __launch_bounds__(WG) void k_precond_obs(Dev d, int wi0) {
+  const int team = threadIdx.x / TEAM;
+  const int lane = threadIdx.x % TEAM;
+  const int wi = wi0 + blockIdx.x;
+  if (team >= d.wi_count[wi]) return;
+  const int slot = d.wi_first[wi] + team;
+  const int prob = d.slot_prob[slot];
+  if (!d.active[prob]) return;
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const int W = width_of(k);
+  const float* B = d.poolB + d.slot_boff[slot];
+  const float* rho = d.rhoB + 2 * (size_t)obs0;
+  for (int o = lane; o < k; o += TEAM) {
+    float g[45], h[9];
+#pragma unroll
+    for (int e = 0; e < 45; ++e) g[e] = 0.f;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) h[e] = 0.f;
+    for (int r = 0; r < 2 * k; ++r) {
+      const float* row = B + (size_t)r * W + 9 * o;
+      float b[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) b[e] = row[e];
+      const float rr = rho[r];
+      int e = 0;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        h[a] += b[a] * rr;
+#pragma unroll
+        for (int c = a; c < 9; ++c) g[e++] += b[a] * b[c];
+      }
+    }
+    float* out = d.obsbuf + (size_t)(obs0 + o) * 54;
+#pragma unroll
+    for (int e = 0; e < 45; ++e) out[e] = g[e];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) out[45 + e] = h[e];
+  }
+}
+
+// Per camera (one wavefront): sum the per-observation blocks, scale, add
+// lambda I, Cholesky-factor and invert the 9x9 block (a non-positive pivot
+// falls back to the inverse diagonal and is counted), and form b~ = S g.
+__global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int prob = d.cam_prob[c];
+  if (!d.active[prob]) return;
+  float acc[54];
+#pragma unroll
+  for (int e = 0; e < 54; ++e) acc[e] = 0.f;
+  const int b = d.cam_obs_off[c], e1 = d.cam_obs_off[c + 1];
+  for (int i = b + lane; i < e1; i += 64) {
+    const float* src = d.obsbuf + (size_t)d.cam_obs_idx[i] * 54;
+#pragma unroll
+    for (int e = 0; e < 54; ++e) acc[e] += src[e];
+  }
+#pragma unroll
+  for (int e = 0; e < 54; ++e) acc[e] = wave_sum_f(acc[e]);
+  if (lane != 0) return;
+  float s[9];
+#pragma unroll
+  for (int a = 0; a < 9; ++a) s[a] = d.s_cam[9 * c + a];
+  const float lam = (float)d.lambda[prob];
+  float P[9][9];
+  int e = 0;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+#pragma unroll
+    for (int q = a; q < 9; ++q) {
+      const float v = s[a] * acc[e++] * s[q];
+      P[a][q] = v;
+      P[q][a] = v;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    P[a][a] += lam;
+    d.vb[9 * c + a] = s[a] * acc[45 + a];
+  }
+  // Cholesky P = L L^T (lower, in place)
+  float L[9][9];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    float dj = P[j][j];
+#pragma unroll
+    for (int q = 0; q < j; ++q) dj -= L[j][q] * L[j][q];
+    if (!(dj > 0.f)) { ok = false; dj = 1.f; }
+    const float ljj = sqrtf(dj);
+    L[j][j] = ljj;
+    const float il = 1.0f / ljj;
+#pragma unroll
+    for (int i = j + 1; i < 9; ++i) {
+      float v = P[i][j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) v -= L[i][q] * L[j][q];
+      L[i][j] = v * il;
+    }
+#pragma unroll
+    for (int i = 0; i < j; ++i) L[i][j] = 0.f;
+  }
+  float* mi = d.minv + 81 * (size_t)c;
+  if (!ok) {
+    atomicAdd(d.chol_fail, 1);
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) mi[9 * a + q] = (a == q) ? 1.0f / P[a][a] : 0.f;
+    return;
+  }
+  // inverse of L (lower), then M^-1 = L^-T L^-1
+  float Li[9][9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Li[i][j] = 0.f;
+    Li[j][j] = 1.0f / L[j][j];
+#pragma unroll
+    for (int i = j + 1; i < 9; ++i) {
+      float v = 0.f;
+#pragma unroll
+      for (int q = j; q < i; ++q) v -= L[i][q] * Li[q][j];
+      Li[i][j] = v / L[i][i];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      float v = 0.f;
+#pragma unroll
+      for (int i = (a > q ? a : q); i < 9; ++i) v += Li[i][a] * Li[i][q];
+      mi[9 * a + q] = v;
+    }
+  }
+}
+
+// ----------------------------------------------------- kernel (c): matvec
+
+// Gather of the landmark's slice of the (scaled) direction vector for the 4
+// columns of column group g: p'[c] = s[cam, m] * (z + beta p)[cam, m] when
+// FOLD (the PCG update of p folded into the gather), else s * v.
+template <bool FOLD>
+__device__ __forceinline__ float4 gather_cols(const Dev& d, const float* __restrict__ v, float beta, int obs0, int k,
+                                              int g) {
+  float out[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = 4 * g + q;
+    out[q] = 0.f;
+    if (c < 9 * k) {
+      const int o = (unsigned)c / 9u;
+      const int m = c - 9 * o;
+      const int idx = 9 * d.obs_cam[obs0 + o] + m;
+      const float val = FOLD ? (d.vz[idx] + beta * d.vp[idx]) : v[idx];
+      out[q] = d.s_cam[idx] * val;
+    }
+  }
+  return make_float4(out[0], out[1], out[2], out[3]);
+}
+
+__device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
+
+__device__ __forceinline__ void store_cols(float* __restrict__ zo, int k, int g, float4 z) {
+  const int c = 4 * g;
+  if (c + 0 < 9 * k) zo[c + 0] = z.x;
+  if (c + 1 < 9 * k) zo[c + 1] = z.y;
+  if (c + 2 < 9 * k) zo[c + 2] = z.z;
+  if (c + 3 < 9 * k) zo[c + 3] = z.w;
+}
+
+// Matrix-free product for teams of <= 64 lanes: one float4 column group per
+// lane; for every B row the team forms y_r = B_r . p' with a DPP all-reduce
+// and accumulates z += y_r B_r, so each B entry is read from memory once.
+// Writes z (unscaled, 9 values per observation) to obsbuf.
+template <int TEAM, bool FOLD>
+__device__ __forceinline__ void matvec_small(const Dev& d, int slot, int lane, const float* __restrict__ v) {
+  const int prob = d.slot_prob[slot];
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const int G = width_of(k) >> 2;
+  const bool on = lane < G;
+  const int g = on ? lane : 0;
+  const float beta = FOLD ? (float)d.beta[prob] : 0.f;
+  const float4 pv = on ? gather_cols<FOLD>(d, v, beta, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
+  float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  const int n = 2 * k;  // always even
+  for (int r = 0; r < n; r += 2) {
+    const float4 b0 = on ? B[(size_t)r * G + g] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 b1 = on ? B[(size_t)(r + 1) * G + g] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float y0 = team_sum<TEAM>(dot4(b0, pv));
+    const float y1 = team_sum<TEAM>(dot4(b1, pv));
+    z.x += y0 * b0.x + y1 * b1.x;
+    z.y += y0 * b0.y + y1 * b1.y;
+    z.z += y0 * b0.z + y1 * b1.z;
+    z.w += y0 * b0.w + y1 * b1.w;
+  }
+  if (on) store_cols(d.obsbuf + 9 * (size_t)obs0, k, g, z);
+}
+
+template <int TEAM, bool FOLD>
+__global__ __launch_bounds__(WG) void k_matvec_small(Dev d, int wi0, const float* v) {
+  const int team = threadIdx.x / TEAM;
+  const int lane = threadIdx.x % TEAM;
+  const int wi = wi0 + blockIdx.x;
+  if (team >= d.wi_count[wi]) return;
+  const int slot = d.wi_first[wi] + team;
+  const int prob = d.slot_prob[slot];
+  if (!d.active[prob] || (FOLD && d.done[prob])) return;
+  matvec_small<TEAM, FOLD>(d, slot, lane, v);
+}
+
+// Matrix-free product for large landmarks: a workgroup of 4 wavefronts per
+// landmark.  Wave w takes rows w, w+4, ...; each lane owns up to NCG column
+// groups (strided by 64).  The 4 partial z vectors are summed through LDS in
+// a fixed order.
+template <int NCG, bool FOLD>
+__global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int wi0, const float* v) {
+  __shared__ float4 zred[4][64];
+  const int wi = wi0 + blockIdx.x;
+  const int slot = d.wi_first[wi];
+  const int prob = d.slot_prob[slot];
+  if (!d.active[prob] || (FOLD && d.done[prob])) return;
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const int G = width_of(k) >> 2;
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const float beta = FOLD ? (float)d.beta[prob] : 0.f;
+  float4 pv[NCG], z[NCG];
+#pragma unroll
+  for (int j = 0; j < NCG; ++j) {
+    const int g = lane + 64 * j;
+    pv[j] = g < G ? gather_cols<FOLD>(d, v, beta, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
+    z[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
+  for (int r = w; r < 2 * k; r += 4) {
+    const float4* row = B + (size_t)r * G;
+    float4 b[NCG];
+    float y = 0.f;
+#pragma unroll
+    for (int j = 0; j < NCG; ++j) {
+      const int g = lane + 64 * j;
+      b[j] = g < G ? row[g] : make_float4(0.f, 0.f, 0.f, 0.f);
+      y += dot4(b[j], pv[j]);
+    }
+    y = wave_sum_f(y);
+#pragma unroll
+    for (int j = 0; j < NCG; ++j) {
+      z[j].x += y * b[j].x; z[j].y += y * b[j].y; z[j].z += y * b[j].z; z[j].w += y * b[j].w;
+    }
+  }
+  float* zo = d.obsbuf + 9 * (size_t)obs0;
+#pragma unroll
+  for (int j = 0; j < NCG; ++j) {
+    if (64 * j >= G) break;  // uniform across the workgroup
+    zred[w][lane] = z[j];
+    __syncthreads();
+    if (w == 0) {
+      const float4 a = zred[0][lane], b2 = zred[1][lane], c = zred[2][lane], e = zred[3][lane];
+      const float4 s = make_float4((a.x + b2.x) + (c.x + e.x), (a.y + b2.y) + (c.y + e.y),
+                                   (a.z + b2.z) + (c.z + e.z), (a.w + b2.w) + (c.w + e.w));
+      const int g = lane + 64 * j;
+      if (g < G) store_cols(zo, k, g, s);
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------- PCG vector kernels
+
+// Last-workgroup-done reduction: every workgroup writes per-camera partials,
+// then one atomic per workgroup; the workgroup that arrives last sums the
+// partials of each problem (one wavefront per problem, fixed order) and runs
+// `fin(problem, sum_a, sum_b)`.  The counter is reset for the next use.
+template <typename Fin>
+__device__ __forceinline__ void last_block_reduce(const Dev& d, uint32_t* counter, const double* pa,
+                                                  const double* pb, Fin fin) {
+  __shared__ bool is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev = atomicAdd(counter, 1u);
+    is_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int p = w; p < d.P; p += nw) {
+    double sa = 0.0, sb = 0.0;
+    for (int c = d.prob_cam_off[p] + lane; c < d.prob_cam_off[p + 1]; c += 64) {
+      sa += __builtin_nontemporal_load(pa + c);
+      if (pb) sb += __builtin_nontemporal_load(pb + c);
+    }
+    sa = wave_sum_d(sa);
+    sb = wave_sum_d(sb);
+    if (lane == 0) fin(p, sa, sb);
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+__device__ __forceinline__ void minv_apply(const float* __restrict__ mi, const float r[9], float z[9]) {
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    float v = 0.f;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) v += mi[9 * a + q] * r[q];
+    z[a] = v;
+  }
+}
+
+// x = 0, r = -b, z = M^-1 r, p = 0, beta = 0; rz = r.z and rr0 = r.r per problem.
+__global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < d.NC) {
+    const int prob = d.cam_prob[c];
+    double rz = 0.0, rr = 0.0;
+    if (d.active[prob]) {
+      float r[9], z[9];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        r[a] = -d.vb[9 * c + a];
+        d.vx[9 * c + a] = 0.f;
+        d.vr[9 * c + a] = r[a];
+        d.vp[9 * c + a] = 0.f;
+      }
+      minv_apply(d.minv + 81 * (size_t)c, r, z);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        d.vz[9 * c + a] = z[a];
+        rz += (double)(r[a] * z[a]);
+        rr += (double)(r[a] * r[a]);
+      }
+    }
+    d.cam_part[c] = rz;
+    d.cam_part2[c] = rr;
+  }
+  last_block_reduce(d, d.counters + 0, d.cam_part, d.cam_part2, [&](int p, double rz, double rr) {
+    d.rz[p] = rz;
+    d.rr0[p] = rr;
+    d.rr[p] = rr;
+    d.beta[p] = 0.0;
+    d.alpha[p] = 0.0;
+    d.iters[p] = 0;
+    if (!d.active[p]) { d.done[p] = 1; d.pstatus[p] = 4; }
+    else if (!(rr > 0.0)) { d.done[p] = 1; d.pstatus[p] = (rr == 0.0) ? 3 : 2; }
+    else { d.done[p] = 0; d.pstatus[p] = 1; }
+  });
+}
+
+// Per camera (one wavefront): p = z + beta p, q = S sum_obs z_obs + lambda p,
+// partial p.q; the last workgroup forms alpha = rz / p^T q per problem.
+__global__ __launch_bounds__(WG) void k_pcg_reduce(Dev d) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + w;
+  double pq = 0.0;
+  if (c < d.NC) {
+    const int prob = d.cam_prob[c];
+    if (d.active[prob] && !d.done[prob]) {
+      float acc[9];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) acc[a] = 0.f;
+      const int b = d.cam_obs_off[c], e = d.cam_obs_off[c + 1];
+      for (int i = b + lane; i < e; i += 64) {
+        const float* src = d.obsbuf + (size_t)d.cam_obs_idx[i] * 9;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) acc[a] += src[a];
+      }
+#pragma unroll
+      for (int a = 0; a < 9; ++a) acc[a] = wave_sum_f(acc[a]);
+      if (lane < 9) {
+        float s = acc[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) s = (lane == a) ? acc[a] : s;
+        const int idx = 9 * c + lane;
+        const float beta = (float)d.beta[prob];
+        const float pn = d.vz[idx] + beta * d.vp[idx];
+        const float q = d.s_cam[idx] * s + (float)d.lambda[prob] * pn;
+        d.vp[idx] = pn;
+        d.vq[idx] = q;
+        pq = (double)(pn * q);
+      }
+    }
+    // 9 lanes hold products; sum them in a fixed order
+    pq = wave_sum_d(pq);
+    if (lane == 0) d.cam_part[c] = pq;
+  }
+  last_block_reduce(d, d.counters + 1, d.cam_part, nullptr, [&](int p, double pq, double) {
+    if (!d.active[p] || d.done[p]) return;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      d.alpha[p] = 0.0;
+      d.done[p] = 1;
+      d.pstatus[p] = 2;  // breakdown: keep x
+    } else {
+      d.alpha[p] = d.rz[p] / pq;
+    }
+  });
+}
+
+// Per camera: x += alpha p, r -= alpha q, z = M^-1 r; partials r.z and r.r;
+// the last workgroup counts the iteration, tests |r| <= tol |r0| and forms beta.
+__global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < d.NC) {
+    const int prob = d.cam_prob[c];
+    double rz = 0.0, rr = 0.0;
+    if (d.active[prob] && !d.done[prob]) {
+      const float alpha = (float)d.alpha[prob];
+      float r[9], z[9];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        const int idx = 9 * c + a;
+        d.vx[idx] += alpha * d.vp[idx];
+        r[a] = d.vr[idx] - alpha * d.vq[idx];
+        d.vr[idx] = r[a];
+      }
+      minv_apply(d.minv + 81 * (size_t)c, r, z);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        d.vz[9 * c + a] = z[a];
+        rz += (double)(r[a] * z[a]);
+        rr += (double)(r[a] * r[a]);
+      }
+    }
+    d.cam_part[c] = rz;
+    d.cam_part2[c] = rr;
+  }
+  last_block_reduce(d, d.counters + 2, d.cam_part, d.cam_part2, [&](int p, double rz, double rr) {
+    if (!d.active[p] || d.done[p]) return;
+    d.iters[p] += 1;
+    d.rr[p] = rr;
+    const double tol = (double)d.pcg_tol;
+    if (!isfinite(rr) || !isfinite(rz)) {
+      d.done[p] = 1;
+      d.pstatus[p] = 2;
+    } else if (rr <= tol * tol * d.rr0[p]) {
+      d.done[p] = 1;
+      d.pstatus[p] = 0;
+    } else {
+      d.beta[p] = rz / d.rz[p];
+      d.rz[p] = rz;
+    }
+  });
+}
+
+// ----------------------------------------------------- back-substitution
+
+// Per landmark: damped top rows from the stored undamped rows and the Givens
+// rotations, u_top = T^ S dx_p, dx~_l = -R^-1 (Q^1^T r + u_top) (eq. backsub_nm),
+// dx_l = S_l dx~_l, and the landmark's share of the predicted decrease of the
+// undamped linear model, summed over all its rotated rows:
+//   pred_l = -sum u (2 rho + u) + lambda |dx~_l|^2,   u = rows . (S dx_p, dx~_l).
+template <int TEAM, int NCG>
+__global__ __launch_bounds__(WG) void k_backsub(Dev d, int wi0) {
+  __shared__ float red4[4];
+  const int team = threadIdx.x / TEAM;
+  const int lane = threadIdx.x % TEAM;
+  const int wi = wi0 + blockIdx.x;
+  if (team >= d.wi_count[wi]) return;
+  const int slot = d.wi_first[wi] + team;
+  const int prob = d.slot_prob[slot];
+  const int lm = d.slot_lm[slot];
+  if (!d.active[prob]) return;
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const int W = width_of(k);
+  const int G = W >> 2;
+  const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const float lam = (float)d.lambda[prob];
+  Givens6 Gv;
+  float Rh[3][3], qrh[3], dr[3];
+  damping_rotations(lmd, sqrtf(lam), Gv, Rh, qrh, dr);
+  const float4* T = reinterpret_cast<const float4*>(d.poolT + d.slot_toff[slot]);
+  const float4* B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
+  float4 pv[NCG];
+  float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+#pragma unroll
+  for (int j = 0; j < NCG; ++j) {
+    const int g = lane + TEAM * j;
+    pv[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (g < G) {
+      pv[j] = gather_cols<false>(d, d.vx, 0.f, obs0, k, g);
+      const float4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
+      float a[3], b[3];
+      a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b);
+      u0 += a[0] * pv[j].x; u1 += a[1] * pv[j].x; u2 += a[2] * pv[j].x;
+      a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b);
+      u0 += a[0] * pv[j].y; u1 += a[1] * pv[j].y; u2 += a[2] * pv[j].y;
+      a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, b);
+      u0 += a[0] * pv[j].z; u1 += a[1] * pv[j].z; u2 += a[2] * pv[j].z;
+      a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, b);
+      u0 += a[0] * pv[j].w; u1 += a[1] * pv[j].w; u2 += a[2] * pv[j].w;
+    }
+  }
+  u0 = tsum<TEAM>(u0, red4);
+  u1 = tsum<TEAM>(u1, red4);
+  u2 = tsum<TEAM>(u2, red4);
+  // R^ dx~ = -(qrh + u), upper triangular
+  const float c0 = -(qrh[0] + u0), c1 = -(qrh[1] + u1), c2 = -(qrh[2] + u2);
+  const float x2 = c2 / Rh[2][2];
+  const float x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
+  const float x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
+  // predicted decrease: top rows, then the 2k B rows
+  double pred = 0.0;
+  if (lane == 0) {
+    const float ut0 = u0 + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
+    const float ut1 = u1 + Rh[1][1] * x1 + Rh[1][2] * x2;
+    const float ut2 = u2 + Rh[2][2] * x2;
+    pred = -(double)(ut0 * (2.f * qrh[0] + ut0)) - (double)(ut1 * (2.f * qrh[1] + ut1)) -
+           (double)(ut2 * (2.f * qrh[2] + ut2)) + (double)lam * ((double)x0 * x0 + (double)x1 * x1 + (double)x2 * x2);
+  }
+  const float* rho = d.rhoB + 2 * (size_t)obs0;
+  for (int r = 0; r < 2 * k; ++r) {
+    float y = 0.f;
+#pragma unroll
+    for (int j = 0; j < NCG; ++j) {
+      const int g = lane + TEAM * j;
+      if (g < G) y += dot4(B[(size_t)r * G + g], pv[j]);
+    }
+    y = tsum<TEAM>(y, red4);
+    if (lane == 0) pred -= (double)(y * (2.f * rho[r] + y));
+  }
+  if (lane == 0) {
+    const float* sl = lmd + LMD_SL;
+    d.dxl[3 * (size_t)lm + 0] = sl[0] * x0;
+    d.dxl[3 * (size_t)lm + 1] = sl[1] * x1;
+    d.dxl[3 * (size_t)lm + 2] = sl[2] * x2;
+    d.lm_part[lm] = pred;
+  }
+}
+
+// ----------------------------------------------------- update and commit
+
+__device__ __forceinline__ void so3_exp_f(float w0, float w1, float w2, float R[9]) {
+  const float th2 = w0 * w0 + w1 * w1 + w2 * w2;
+  const float th = sqrtf(th2);
+  float a, b;
+  if (th < 1e-4f) {  // series, accurate to FP32 rounding below 1e-4
+    a = 1.0f - th2 / 6.0f;
+    b = 0.5f - th2 / 24.0f;
+  } else {
+    const float sh = sinf(0.5f * th);
+    a = sinf(th) / th;
+    b = 2.0f * sh * sh / th2;
+  }
+  // R = I + a W + b W^2
+  const float W[9] = {0.f, -w2, w1, w2, 0.f, -w0, -w1, w0, 0.f};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float w2ij = 0.f;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) w2ij += W[3 * i + q] * W[3 * q + j];
+      R[3 * i + j] = (i == j ? 1.0f : 0.0f) + a * W[3 * i + j] + b * w2ij;
+    }
+}
+
+// Tentative state of active problems: R' = Exp(dw) R, t' = t + dt, intrinsics
+// additive, with dx_p = S dx~_p; landmarks X' = X + dx_l.
+__global__ __launch_bounds__(WG) void k_update(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.NC) {
+    const int c = i;
+    const float* src = d.cam + 16 * (size_t)c;
+    float* dst = d.cam_new + 16 * (size_t)c;
+    if (!d.active[d.cam_prob[c]]) {
+#pragma unroll
+      for (int a = 0; a < 16; ++a) dst[a] = src[a];
+    } else {
+      float dx[9];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) dx[a] = d.s_cam[9 * c + a] * d.vx[9 * c + a];
+      float E[9], R[9];
+      so3_exp_f(dx[0], dx[1], dx[2], E);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          R[3 * a + b] = E[3 * a + 0] * src[0 + b] + E[3 * a + 1] * src[3 + b] + E[3 * a + 2] * src[6 + b];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) dst[a] = R[a];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) dst[9 + a] = src[9 + a] + dx[3 + a];
+      dst[15] = 0.f;
+    }
+  }
+  if (i < d.NL) {
+    const float4 X = d.pts[i];
+    float4 Y = X;
+    if (d.active[d.lm_prob[i]] && d.lm_slot[i] >= 0) {
+      Y.x += d.dxl[3 * (size_t)i + 0];
+      Y.y += d.dxl[3 * (size_t)i + 1];
+      Y.z += d.dxl[3 * (size_t)i + 2];
+    }
+    d.pts_new[i] = Y;
+  }
+}
+
+// Keep the tentative state of problems with active && flag (accepted).
+__global__ __launch_bounds__(WG) void k_commit(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.NC) {
+    const int p = d.cam_prob[i];
+    if (d.active[p] && d.flag[p]) {
+#pragma unroll
+      for (int a = 0; a < 16; ++a) d.cam[16 * (size_t)i + a] = d.cam_new[16 * (size_t)i + a];
+    }
+  }
+  if (i < d.NL) {
+    const int p = d.lm_prob[i];
+    if (d.active[p] && d.flag[p]) d.pts[i] = d.pts_new[i];
+  }
+}
+
+// ----------------------------------------------------- test helpers
+
+__global__ __launch_bounds__(WG) void k_debug_lin(Dev d, float* r, float* Jp, float* Jl) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= d.NO) return;
+  Cam C;
+  load_cam(d.cam, d.obs_cam[o], C);
+  const float4 X = d.pts[d.obs_lm[o]];
+  const float2 uv = d.obs_uv[o];
+  float rr[2], J[2][9], L[2][3];
+  project<true>(C, X.x, X.y, X.z, uv.x, uv.y, rr, J, L);
+  r[2 * (size_t)o] = rr[0];
+  r[2 * (size_t)o + 1] = rr[1];
+  for (int a = 0; a < 2; ++a) {
+    for (int b = 0; b < 9; ++b) Jp[18 * (size_t)o + 9 * a + b] = J[a][b];
+    for (int b = 0; b < 3; ++b) Jl[6 * (size_t)o + 3 * a + b] = L[a][b];
+  }
+}
+
+// out = S sum_obs z + lambda v_scaled (no PCG state involved)
+__global__ __launch_bounds__(64) void k_cam_gather_product(Dev d, const float* v, float* out) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  float acc[9];
+#pragma unroll
+  for (int a = 0; a < 9; ++a) acc[a] = 0.f;
+  for (int i = d.cam_obs_off[c] + lane; i < d.cam_obs_off[c + 1]; i += 64) {
+    const float* src = d.obsbuf + (size_t)d.cam_obs_idx[i] * 9;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) acc[a] += src[a];
+  }
+#pragma unroll
+  for (int a = 0; a < 9; ++a) acc[a] = wave_sum_f(acc[a]);
+  if (lane < 9) {
+    float s = acc[0];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) s = (lane == a) ? acc[a] : s;
+    const int idx = 9 * c + lane;
+    out[idx] = d.s_cam[idx] * s + (float)d.lambda[d.cam_prob[c]] * v[idx];
+  }
+}
+
+inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ----------------------------------------------------- launchers
+
+#define LAUNCH_CHECK()                       \
+  do {                                       \
+    hipError_t e_ = hipGetLastError();       \
+    if (e_ != hipSuccess) return e_;         \
+  } while (0)
+
+hipError_t launch_cam_linearize(const Dev& d, const Launch& L, bool jac, bool use_new, const uint8_t* mask) {
+  if (d.NC == 0) return hipSuccess;
+  const float* cam = use_new ? d.cam_new : d.cam;
+  const float4* pts = use_new ? d.pts_new : d.pts;
+  if (jac)
+    hipLaunchKernelGGL(k_cam_linearize<true>, dim3(d.NC), dim3(64), 0, L.stream, d, cam, pts, mask);
+  else
+    hipLaunchKernelGGL(k_cam_linearize<false>, dim3(d.NC), dim3(64), 0, L.stream, d, cam, pts, mask);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_prob_sum(const Dev& d, const Launch& L, const double* vals, const int32_t* off, double* out,
+                           const uint8_t* mask) {
+  hipLaunchKernelGGL(k_prob_sum, dim3(d.P), dim3(64), 0, L.stream, vals, off, out, mask);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask) {
+  const WorkClass* w = L.wc;
+  if (w[4].count) hipLaunchKernelGGL((k_marginalize<256, 512>), dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, mask);
+  if (w[3].count) hipLaunchKernelGGL((k_marginalize<256, 113>), dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi, mask);
+  if (w[2].count) hipLaunchKernelGGL((k_marginalize<64, 28>), dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi, mask);
+  if (w[1].count) hipLaunchKernelGGL((k_marginalize<16, 7>), dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi, mask);
+  if (w[0].count) hipLaunchKernelGGL((k_marginalize<8, 3>), dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi, mask);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
+  const WorkClass* w = L.wc;
+  if (w[4].count) hipLaunchKernelGGL(k_damp<256>, dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, mask);
+  if (w[3].count) hipLaunchKernelGGL(k_damp<256>, dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi, mask);
+  if (w[2].count) hipLaunchKernelGGL(k_damp<64>, dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi, mask);
+  if (w[1].count) hipLaunchKernelGGL(k_damp<16>, dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi, mask);
+  if (w[0].count) hipLaunchKernelGGL(k_damp<8>, dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi, mask);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
+  const WorkClass* w = L.wc;
+  if (w[4].count) hipLaunchKernelGGL(k_precond_obs<256>, dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi);
+  if (w[3].count) hipLaunchKernelGGL(k_precond_obs<256>, dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi);
+  if (w[2].count) hipLaunchKernelGGL(k_precond_obs<64>, dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi);
+  if (w[1].count) hipLaunchKernelGGL(k_precond_obs<16>, dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi);
+  if (w[0].count) hipLaunchKernelGGL(k_precond_obs<8>, dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_precond_cam, dim3(d.NC), dim3(64), 0, L.stream, d);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+template <bool FOLD>
+static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
+  const WorkClass* w = L.wc;
+  if (w[4].count) hipLaunchKernelGGL((k_matvec_large<18, FOLD>), dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, v);
+  if (w[3].count) hipLaunchKernelGGL((k_matvec_large<4, FOLD>), dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi, v);
+  if (w[2].count) hipLaunchKernelGGL((k_matvec_small<64, FOLD>), dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi, v);
+  if (w[1].count) hipLaunchKernelGGL((k_matvec_small<16, FOLD>), dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi, v);
+  if (w[0].count) hipLaunchKernelGGL((k_matvec_small<8, FOLD>), dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi, v);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_pcg_init(const Dev& d, const Launch& L) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(nblocks(d.NC, WG)), dim3(WG), 0, L.stream, d);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_pcg_iteration(const Dev& d, const Launch& L) {
+  hipError_t e = launch_matvec<true>(d, L, nullptr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pcg_reduce, dim3(nblocks(d.NC, 4)), dim3(WG), 0, L.stream, d);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(d.NC, WG)), dim3(WG), 0, L.stream, d);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_backsub(const Dev& d, const Launch& L) {
+  const WorkClass* w = L.wc;
+  if (w[4].count) hipLaunchKernelGGL((k_backsub<256, 5>), dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi);
+  if (w[3].count) hipLaunchKernelGGL((k_backsub<256, 1>), dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi);
+  if (w[2].count) hipLaunchKernelGGL((k_backsub<64, 1>), dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi);
+  if (w[1].count) hipLaunchKernelGGL((k_backsub<16, 1>), dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi);
+  if (w[0].count) hipLaunchKernelGGL((k_backsub<8, 1>), dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_update(const Dev& d, const Launch& L) {
+  const long long n = d.NC > d.NL ? d.NC : d.NL;
+  hipLaunchKernelGGL(k_update, dim3(nblocks(n, WG)), dim3(WG), 0, L.stream, d);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_commit(const Dev& d, const Launch& L) {
+  const long long n = d.NC > d.NL ? d.NC : d.NL;
+  hipLaunchKernelGGL(k_commit, dim3(nblocks(n, WG)), dim3(WG), 0, L.stream, d);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_matvec_only(const Dev& d, const Launch& L, const float* v_scaled, float* out) {
+  hipError_t e = launch_matvec<false>(d, L, v_scaled);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cam_gather_product, dim3(d.NC), dim3(64), 0, L.stream, d, v_scaled, out);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_debug_linearization(const Dev& d, const Launch& L, float* r, float* Jp, float* Jl) {
+  if (d.NO == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_debug_lin, dim3(nblocks(d.NO, WG)), dim3(WG), 0, L.stream, d, r, Jp, Jl);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+}  // namespace sqrtba

@@ -1,0 +1,381 @@
+"""Python binding of libsqrtba.so (ctypes).  Argument marshalling only.
+
+Every numerical step runs in the library's HIP kernels; this module converts
+numpy arrays to the C ABI of include/sqrtba.h, raises SqrtBAError on a
+non-zero status, and uses PyTorch only for device memory (the workspace) and
+the HIP stream.  It fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsqrtba.so")
+
+OK, E_INVALID, E_OOM, E_HIP, E_STATE, E_NONFINITE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_OOM", -3: "E_HIP", -4: "E_STATE", -5: "E_NONFINITE",
+                -6: "E_UNSUPPORTED"}
+PCG_STATUS = {0: "converged", 1: "max_iters", 2: "breakdown", 3: "zero_rhs", 4: "inactive"}
+LM_STATUS = {0: "max_iters", 1: "func_tol", 2: "lambda_max", 3: "nonfinite"}
+MAX_OBS_PER_LANDMARK = 512
+
+
+class SqrtBAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("lambda0", C.c_double), ("lambda_min", C.c_double), ("lambda_max", C.c_double),
+        ("accept_ratio", C.c_double), ("max_lm_iters", C.c_int32), ("func_tol", C.c_double),
+        ("pcg_max_iters", C.c_int32), ("pcg_rel_tol", C.c_double), ("pcg_check_every", C.c_int32),
+        ("use_graph", C.c_int32),
+    ]
+
+
+class LMReport(C.Structure):
+    _fields_ = [
+        ("initial_cost", C.c_double), ("final_cost", C.c_double), ("iterations", C.c_int32),
+        ("accepted", C.c_int32), ("total_pcg_iters", C.c_int32), ("status", C.c_int32),
+        ("solve_seconds", C.c_double), ("time_to_tol", C.c_double),
+    ]
+
+
+class LMRecord(C.Structure):
+    _fields_ = [
+        ("iter", C.c_int32), ("accepted", C.c_int32), ("pcg_iters", C.c_int32), ("pcg_status", C.c_int32),
+        ("lambda_", C.c_double), ("cost", C.c_double), ("new_cost", C.c_double),
+        ("model_decrease", C.c_double), ("rel_res", C.c_double), ("t_seconds", C.c_double),
+    ]
+
+
+_lib = None
+
+P = C.c_void_p
+I32, I64, U64 = C.c_int32, C.c_int64, C.c_uint64
+PD, PF, PI32, PI64, PU8 = (C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(C.c_int32),
+                           C.POINTER(C.c_int64), C.POINTER(C.c_uint8))
+
+_SIGS = {
+    "sqrtba_version": (I32, []),
+    "sqrtba_default_options": (None, [C.POINTER(Options)]),
+    "sqrtba_create": (I32, [C.POINTER(P), C.POINTER(Options), P]),
+    "sqrtba_destroy": (None, [P]),
+    "sqrtba_last_error": (C.c_char_p, [P]),
+    "sqrtba_set_problems": (I32, [P, I32, PI64, PI64]),
+    "sqrtba_set_cameras": (I32, [P, I64, PF]),
+    "sqrtba_set_landmarks": (I32, [P, I64, PF]),
+    "sqrtba_set_observations": (I32, [P, I64, PI32, PI32, PF]),
+    "sqrtba_workspace_bytes": (I32, [P, C.POINTER(U64)]),
+    "sqrtba_bind_workspace": (I32, [P, P, U64]),
+    "sqrtba_set_active": (I32, [P, PU8]),
+    "sqrtba_linearize": (I32, [P, PD]),
+    "sqrtba_marginalize": (I32, [P]),
+    "sqrtba_damp": (I32, [P, PD]),
+    "sqrtba_solve": (I32, [P, PI32, PD, PI32]),
+    "sqrtba_back_substitute": (I32, [P, PD]),
+    "sqrtba_update": (I32, [P, PD]),
+    "sqrtba_commit": (I32, [P, PU8]),
+    "sqrtba_lm_solve": (I32, [P, C.POINTER(LMReport)]),
+    "sqrtba_lm_solve_tracked": (I32, [P, PD, C.POINTER(LMReport)]),
+    "sqrtba_get_lm_history": (I32, [P, I32, C.POINTER(LMRecord), I32, PI32]),
+    "sqrtba_get_cameras": (I32, [P, PF]),
+    "sqrtba_get_landmarks": (I32, [P, PF]),
+    "sqrtba_debug_bookkeeping": (I32, [P, PI64, PI64, PI64, PU8, PU8]),
+    "sqrtba_debug_linearization": (I32, [P, PF, PF, PF]),
+    "sqrtba_debug_scales": (I32, [P, PF, PF]),
+    "sqrtba_debug_rcs_matvec": (I32, [P, I32, PF, PF]),
+    "sqrtba_debug_rhs": (I32, [P, PF]),
+    "sqrtba_debug_precond": (I32, [P, PF]),
+    "sqrtba_debug_block": (I32, [P, I64, PI32, PF, PF]),
+    "sqrtba_debug_solution": (I32, [P, PF, PF]),
+    "sqrtba_debug_set_pose_increment": (I32, [P, PF]),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """The loaded library; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_01843_amd.build` "
+                              "(the HIP library is required; there is no fallback)")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray], ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _arr(x, dtype, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(x), dtype=dtype)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().sqrtba_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class Report:
+    initial_cost: float
+    final_cost: float
+    iterations: int
+    accepted: int
+    total_pcg_iters: int
+    status: str
+    solve_seconds: float
+    time_to_tol: float
+
+
+class Context:
+    """One sqrtba context (one or a batch of problems) on the current HIP device."""
+
+    def __init__(self, options: Optional[Options] = None, stream=None, **kw):
+        L = lib()
+        if options is None:
+            options = default_options(**kw)
+        elif kw:
+            raise TypeError("pass either options or keyword options")
+        self.options = options
+        handle = None
+        if stream is not None:
+            handle = int(getattr(stream, "cuda_stream", stream))
+        self._h = P()
+        st = L.sqrtba_create(C.byref(self._h), C.byref(options), P(handle) if handle else None)
+        if st != OK:
+            raise SqrtBAError(st, "sqrtba_create failed")
+        self.n_problems = 1
+        self.n_cams = 0
+        self.n_points = 0
+        self._workspace = None
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sqrtba_destroy(self._h)
+            self._h = None
+        self._workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st: int):
+        if st != OK:
+            msg = lib().sqrtba_last_error(self._h)
+            raise SqrtBAError(st, msg.decode() if msg else "")
+
+    # -- problem definition
+    def set_problems(self, cam_off: Sequence[int], pt_off: Sequence[int]):
+        co, po = _arr(cam_off, np.int64), _arr(pt_off, np.int64)
+        self._check(lib().sqrtba_set_problems(self._h, len(co) - 1, _ptr(co, C.c_int64), _ptr(po, C.c_int64)))
+        self.n_problems = len(co) - 1
+
+    def set_cameras(self, params):
+        a = _arr(params, np.float32)
+        self._check(lib().sqrtba_set_cameras(self._h, a.size // 9 if a.size else 0, _ptr(a, C.c_float)))
+        self.n_cams = a.size // 9
+
+    def set_landmarks(self, xyz):
+        a = _arr(xyz, np.float32)
+        self._check(lib().sqrtba_set_landmarks(self._h, a.size // 3 if a.size else 0, _ptr(a, C.c_float)))
+        self.n_points = a.size // 3
+
+    def set_observations(self, cam, pt, uv):
+        c, p, u = _arr(cam, np.int32), _arr(pt, np.int32), _arr(uv, np.float32)
+        if c.shape != p.shape or u.size != 2 * c.size:
+            raise ValueError("observation arrays have inconsistent shapes")
+        self._check(lib().sqrtba_set_observations(self._h, c.size, _ptr(c, C.c_int32), _ptr(p, C.c_int32),
+                                                  _ptr(u, C.c_float)))
+
+    def load(self, cameras, points, obs_cam, obs_pt, obs_uv, cam_off=None, pt_off=None):
+        if cam_off is not None:
+            self.set_problems(cam_off, pt_off)
+        self.set_cameras(cameras)
+        self.set_landmarks(points)
+        self.set_observations(obs_cam, obs_pt, obs_uv)
+        return self
+
+    def workspace_bytes(self) -> int:
+        n = C.c_uint64()
+        self._check(lib().sqrtba_workspace_bytes(self._h, C.byref(n)))
+        return int(n.value)
+
+    def bind_torch_workspace(self, device="cuda"):
+        """Allocate the device workspace with PyTorch and hand it to the library."""
+        import torch
+        nbytes = self.workspace_bytes()
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        addr = ws.data_ptr()
+        off = (-addr) % 256
+        self._check(lib().sqrtba_bind_workspace(self._h, P(addr + off), nbytes))
+        self._workspace = ws
+        return ws
+
+    def set_active(self, mask):
+        m = _arr(mask, np.uint8)
+        self._check(lib().sqrtba_set_active(self._h, _ptr(m, C.c_uint8)))
+
+    # -- the LM step
+    def linearize(self) -> np.ndarray:
+        out = np.zeros(self.n_problems)
+        self._check(lib().sqrtba_linearize(self._h, _ptr(out, C.c_double)))
+        return out
+
+    def marginalize(self):
+        self._check(lib().sqrtba_marginalize(self._h))
+
+    def damp(self, lam):
+        l = _arr(np.broadcast_to(np.asarray(lam, dtype=np.float64), (self.n_problems,)), np.float64)
+        self._check(lib().sqrtba_damp(self._h, _ptr(l, C.c_double)))
+
+    def solve(self):
+        it = np.zeros(self.n_problems, np.int32)
+        rel = np.zeros(self.n_problems)
+        st = np.zeros(self.n_problems, np.int32)
+        self._check(lib().sqrtba_solve(self._h, _ptr(it, C.c_int32), _ptr(rel, C.c_double), _ptr(st, C.c_int32)))
+        return it, rel, st
+
+    def back_substitute(self) -> np.ndarray:
+        out = np.zeros(self.n_problems)
+        self._check(lib().sqrtba_back_substitute(self._h, _ptr(out, C.c_double)))
+        return out
+
+    def update(self) -> np.ndarray:
+        out = np.zeros(self.n_problems)
+        self._check(lib().sqrtba_update(self._h, _ptr(out, C.c_double)))
+        return out
+
+    def commit(self, accept):
+        a = _arr(np.broadcast_to(np.asarray(accept, dtype=np.uint8), (self.n_problems,)), np.uint8)
+        self._check(lib().sqrtba_commit(self._h, _ptr(a, C.c_uint8)))
+
+    def lm_solve(self, tol_cost=None) -> List[Report]:
+        reps = (LMReport * self.n_problems)()
+        if tol_cost is None:
+            self._check(lib().sqrtba_lm_solve(self._h, reps))
+        else:
+            t = _arr(np.broadcast_to(np.asarray(tol_cost, dtype=np.float64), (self.n_problems,)), np.float64)
+            self._check(lib().sqrtba_lm_solve_tracked(self._h, _ptr(t, C.c_double), reps))
+        return [Report(r.initial_cost, r.final_cost, r.iterations, r.accepted, r.total_pcg_iters,
+                       LM_STATUS.get(r.status, str(r.status)), r.solve_seconds, r.time_to_tol) for r in reps]
+
+    def history(self, problem: int = 0) -> List[dict]:
+        n = C.c_int32()
+        self._check(lib().sqrtba_get_lm_history(self._h, problem, None, 0, C.byref(n)))
+        recs = (LMRecord * max(1, n.value))()
+        self._check(lib().sqrtba_get_lm_history(self._h, problem, recs, n.value, C.byref(n)))
+        return [{"iter": r.iter, "accepted": bool(r.accepted), "pcg_iters": r.pcg_iters,
+                 "pcg_status": PCG_STATUS.get(r.pcg_status, r.pcg_status), "lambda": r.lambda_, "cost": r.cost,
+                 "new_cost": r.new_cost, "pred": r.model_decrease, "rel_res": r.rel_res, "t": r.t_seconds}
+                for r in recs[: n.value]]
+
+    def get_cameras(self) -> np.ndarray:
+        out = np.zeros((self.n_cams, 9), np.float32)
+        self._check(lib().sqrtba_get_cameras(self._h, _ptr(out, C.c_float)))
+        return out
+
+    def get_landmarks(self) -> np.ndarray:
+        out = np.zeros((self.n_points, 3), np.float32)
+        self._check(lib().sqrtba_get_landmarks(self._h, _ptr(out, C.c_float)))
+        return out
+
+    # -- inspection exports
+    def debug_bookkeeping(self) -> dict:
+        n = C.c_int64()
+        self._check(lib().sqrtba_debug_bookkeeping(self._h, C.byref(n), None, None, None, None))
+        perm = np.zeros(n.value, np.int64)
+        lm_off = np.zeros(self.n_points + 1, np.int64)
+        la = np.zeros(self.n_points, np.uint8)
+        ca = np.zeros(self.n_cams, np.uint8)
+        self._check(lib().sqrtba_debug_bookkeeping(self._h, C.byref(n), _ptr(perm, C.c_int64),
+                                                   _ptr(lm_off, C.c_int64), _ptr(la, C.c_uint8),
+                                                   _ptr(ca, C.c_uint8)))
+        return {"obs_perm": perm, "lm_off": lm_off, "lm_active": la.astype(bool), "cam_active": ca.astype(bool)}
+
+    def debug_linearization(self):
+        n = len(self.debug_bookkeeping()["obs_perm"])
+        r = np.zeros((n, 2), np.float32)
+        Jp = np.zeros((n, 2, 9), np.float32)
+        Jl = np.zeros((n, 2, 3), np.float32)
+        self._check(lib().sqrtba_debug_linearization(self._h, _ptr(r, C.c_float), _ptr(Jp, C.c_float),
+                                                     _ptr(Jl, C.c_float)))
+        return r, Jp, Jl
+
+    def debug_scales(self):
+        sc = np.zeros((self.n_cams, 9), np.float32)
+        sp = np.zeros((self.n_points, 3), np.float32)
+        self._check(lib().sqrtba_debug_scales(self._h, _ptr(sc, C.c_float), _ptr(sp, C.c_float)))
+        return sc, sp
+
+    def debug_rcs_matvec(self, V) -> np.ndarray:
+        V = _arr(V, np.float32)
+        V2 = V.reshape(-1, 9 * self.n_cams)
+        out = np.zeros_like(V2)
+        self._check(lib().sqrtba_debug_rcs_matvec(self._h, V2.shape[0], _ptr(V2, C.c_float), _ptr(out, C.c_float)))
+        return out.reshape(V.shape)
+
+    def debug_rhs(self) -> np.ndarray:
+        out = np.zeros(9 * self.n_cams, np.float32)
+        self._check(lib().sqrtba_debug_rhs(self._h, _ptr(out, C.c_float)))
+        return out
+
+    def debug_precond(self) -> np.ndarray:
+        out = np.zeros((self.n_cams, 9, 9), np.float32)
+        self._check(lib().sqrtba_debug_precond(self._h, _ptr(out, C.c_float)))
+        return out
+
+    def debug_block(self, pt: int):
+        k = C.c_int32()
+        self._check(lib().sqrtba_debug_block(self._h, pt, C.byref(k), None, None))
+        if k.value == 0:
+            return 0, None, None
+        kk = k.value
+        out = np.zeros((2 * kk + 3, 9 * kk + 4), np.float32)
+        fac = np.zeros(24, np.float32)
+        self._check(lib().sqrtba_debug_block(self._h, pt, C.byref(k), _ptr(out, C.c_float), _ptr(fac, C.c_float)))
+        return kk, out, fac
+
+    def debug_solution(self):
+        dxp = np.zeros(9 * self.n_cams, np.float32)
+        dxl = np.zeros((self.n_points, 3), np.float32)
+        self._check(lib().sqrtba_debug_solution(self._h, _ptr(dxp, C.c_float), _ptr(dxl, C.c_float)))
+        return dxp, dxl
+
+    def debug_set_pose_increment(self, dxp):
+        a = _arr(dxp, np.float32)
+        self._check(lib().sqrtba_debug_set_pose_increment(self._h, _ptr(a, C.c_float)))

@@ -1,0 +1,60 @@
+"""Shared helpers of the GPU tests: contexts from generated problems, oracle views."""
+
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from bal_synth import Problem, make_ring_problem
+
+
+def gpu_context(p: Problem, **opts):
+    import torch
+    from paper_2103_01843_amd import Context
+
+    ctx = Context(stream=torch.cuda.current_stream(), **opts)
+    ctx.load(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)
+    ctx.bind_torch_workspace()
+    return ctx
+
+
+def oracle_lin(p: Problem):
+    bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)
+    st = oracle.state_from_bal(p.cameras, p.points)
+    return bk, st, oracle.linearize(st, bk, p.obs_uv)
+
+
+def k_mix_sampler(ks):
+    ks = np.asarray(ks)
+
+    def f(rng, n):
+        return ks[np.arange(n) % len(ks)]
+
+    return f
+
+
+# observation counts that exercise every landmark size class of the kernels,
+# including both ends of each class range
+CLASS_EDGES = [2, 3, 4, 7, 8, 28, 29, 60, 113, 114, 150]
+
+
+def mixed_problem(seed: int = 5, n_cams: int = 160, n_points: int = 220) -> Problem:
+    rng = np.random.default_rng(seed)
+    return make_ring_problem(rng, n_cams, n_points, k_mix_sampler(CLASS_EDGES), name="mixed")
+
+
+def landmark_sc_contribution(lin, l: int, lam: float):
+    """Oracle per-landmark Schur-complement term H_pp,l - H_pl,l (H_ll,l + lam I)^-1 H_lp,l
+    (scaled coordinates) and its right-hand side, restricted to the landmark's cameras."""
+    idx = np.nonzero(lin.pi == l)[0]
+    k = idx.size
+    Jp = np.zeros((2 * k, 9 * k))
+    for a, o in enumerate(idx):
+        Jp[2 * a:2 * a + 2, 9 * a:9 * a + 9] = lin.Jp[o] * lin.sp[lin.ci[o]]
+    Jl = (lin.Jl[idx] * lin.sl[l]).reshape(2 * k, 3)
+    r = lin.r[idx].reshape(-1)
+    Hll = Jl.T @ Jl + lam * np.eye(3)
+    Hpl = Jp.T @ Jl
+    H = Jp.T @ Jp - Hpl @ np.linalg.solve(Hll, Hpl.T)
+    b = Jp.T @ r - Hpl @ np.linalg.solve(Hll, Jl.T @ r)
+    return lin.ci[idx], H, b, Jp, Jl, r
