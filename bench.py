@@ -1,0 +1,253 @@
+#!/usr/bin/env python
+"""Benchmark of the square-root BA hot path on one MI355X.
+
+Workload: the ladybug-like problem (500 cameras on a forward trajectory,
+100k landmarks with k = 2 + Geom(1/3) observations clamped to 50, ~400k
+observations), seeded synthetic data, FP32.  One step is one full
+Levenberg-Marquardt solve (at most 20 attempts) from the same perturbed start,
+with every input resident in HBM: each attempt runs linearize, QR
+marginalization, Givens damping, block-Jacobi + right-hand side, PCG,
+back-substitution, update and cost.
+
+Printed JSON line: time-to-1%-cost (the headline value), QR blocks/s, PCG
+matvec GB/s with its roofline (HIP events around every matvec launch of the
+timed region, algorithmic bytes 4 (18 k^2 + 9 k) per landmark), and the FP64
+oracle's CPU baseline on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --calibrate-copy   # known-size copy, for counter scaling
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "time-to-1%-cost (s), QR blocks/s, PCG matvec HBM GB/s; learned vs block-Jacobi"
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_lm_config{}.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "matvec_traffic_ladybug.json")
+KERNELS = os.path.join(ROOT, "paper_2103_01843_amd", "csrc", "kernels.hip")
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernels_hash() -> str:
+    with open(KERNELS, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def time_to_tol(hist, t_tol_cost):
+    for h in hist:
+        if h["accepted"] and h["new_cost"] <= t_tol_cost:
+            return h["t"]
+    return float("inf")
+
+
+def cpu_baseline(problem, f_tau, budget_s: float):
+    """Oracle (FP64, numpy/scipy) timed on a bounded sample and scaled to time-to-1%-cost.
+
+    Sample: the oracle's first LM attempt on the full workload, split into its
+    stages (linearization, explicit Schur complement, PCG per iteration, back-
+    substitution + cost).  The oracle's own trajectory (the stored oracle run)
+    gives the number of attempts and PCG iterations it needs to reach the 1%
+    threshold; the estimate is the sum of the measured stage times over them.
+    """
+    import numpy as np
+    import oracle
+    from oracle.solvers import pcg
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = 1
+    gpath = GOLDEN.format(1)
+    if not os.path.exists(gpath):
+        return None
+    with open(gpath) as f:
+        gold = json.load(f)
+    p = problem
+    t0 = time.perf_counter()
+    bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv)
+    st = oracle.state_from_bal(p.cameras, p.points)
+    ta = time.perf_counter()
+    lin = oracle.linearize(st, bk, p.obs_uv)
+    t_lin = time.perf_counter() - ta
+    ta = time.perf_counter()
+    rs = oracle.reduced_camera_system(lin, 1e-4)
+    t_sc = time.perf_counter() - ta
+    n_pcg = 40
+    ta = time.perf_counter()
+    res = pcg(lambda v: rs.H @ v, rs.b, oracle.block_jacobi_blocks(rs.H), 0.0, n_pcg)
+    t_pcg = (time.perf_counter() - ta) / max(1, res.iters)
+    ta = time.perf_counter()
+    dxl = oracle.back_substitute(rs, res.x)
+    oracle.model_decrease(lin, res.x, dxl)
+    from oracle.lm import cost_of
+    cost_of(oracle.apply_update(st, res.x.reshape(-1, 9) * lin.sp, dxl.reshape(-1, 3) * lin.sl), bk, p.obs_uv)
+    t_bs = time.perf_counter() - ta
+    sample_s = time.perf_counter() - t0
+    # oracle trajectory until its cost first reaches the threshold
+    est, attempts, iters = 0.0, 0, 0
+    reached = False
+    for h in gold["history"]:
+        attempts += 1
+        iters += h["pcg_iters"]
+        est += t_lin + t_sc + t_pcg * h["pcg_iters"] + t_bs
+        if h["accepted"] and h["new_cost"] <= f_tau:
+            reached = True
+            break
+    return {
+        "value": est if reached else None,
+        "unit": "s",
+        "cores": int(blas_threads),
+        "kind": "oracle",
+        "sample": (f"one FP64 oracle LM attempt on the full workload ({sample_s:.1f} s: linearize {t_lin:.2f} s, "
+                   f"explicit Schur complement {t_sc:.2f} s, PCG {1e3 * t_pcg:.1f} ms/iteration over {res.iters} "
+                   f"iterations, back-substitution + cost {t_bs:.2f} s), scaled by the oracle's own trajectory to the "
+                   f"1% threshold: {attempts} attempts, {iters} PCG iterations"),
+    }
+
+
+def calibrate_copy():
+    import torch
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--lm-iters", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}): this build has no multi-GPU path; "
+              "the landmark-sharded design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import numpy as np
+    import torch
+    from bal_synth import make_config, problem_stats
+    from paper_2103_01843_amd import Context
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("generating the ladybug-like workload")
+    p = make_config(1)
+    stats = problem_stats(p)
+    log(f"workload: {stats}")
+    ctx = Context(stream=torch.cuda.current_stream(), max_lm_iters=args.lm_iters)
+    ctx.load(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv)
+    ctx.bind_torch_workspace()
+    ctx.save_state()
+    for w in range(args.warmup):
+        ctx.restore_state()
+        rep = ctx.lm_solve()[0]
+        log(f"warmup {w}: {rep.iterations} attempts, final cost {rep.final_cost:.6g}, {rep.solve_seconds:.3f} s")
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    runs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ctx.restore_state()
+        rep = ctx.lm_solve()[0]
+        runs.append((rep, ctx.history(0)))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for s, (rep, h) in enumerate(runs):
+        log(f"step {s}: {rep.iterations} attempts, {rep.total_pcg_iters} PCG iterations, "
+            f"final cost {rep.final_cost:.6g}, {rep.solve_seconds:.3f} s")
+    prof = ctx.profile()
+    ctx.close()
+
+    f0 = runs[0][0].initial_cost
+    finals = [r.final_cost for r, _ in runs]
+    gold = None
+    if os.path.exists(GOLDEN.format(1)):
+        with open(GOLDEN.format(1)) as f:
+            gold = json.load(f)
+    fstar = min(finals + ([gold["final_cost"]] if gold else []))
+    f_tau = fstar + 0.01 * (f0 - fstar)
+    ttt = [time_to_tol(h, f_tau) for _, h in runs]
+    value = statistics.median(ttt)
+
+    mv, qr = prof["matvec"], prof["marginalize"]
+    mv_avg_ms = mv["ms"] / max(1, mv["launches"])
+    mv_bytes = mv["bytes"] / max(1, mv["launches"])
+    achieved = mv_bytes / (mv_avg_ms * 1e-3) / 1e9 if mv_avg_ms > 0 else None
+    traffic = None
+    if os.path.exists(TRAFFIC):
+        with open(TRAFFIC) as f:
+            tr = json.load(f)
+        if tr.get("kernels_sha") == kernels_hash():
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": traffic,
+                "kernel": "k_matvec (PCG product, all landmark blocks, one launch)",
+                "avg_launch_ms": mv_avg_ms, "algorithmic_bytes_per_launch": mv_bytes,
+                "launches_timed": mv["launches"]}
+    qr_blocks_per_s = qr["units"] / (qr["ms"] * 1e-3) if qr["ms"] > 0 else None
+    qr_gbps = qr["bytes"] / (qr["ms"] * 1e-3) / 1e9 if qr["ms"] > 0 else None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample")
+        try:
+            cpu = cpu_baseline(p, f_tau, 30.0)
+        except Exception as e:  # the baseline is reported, never required
+            log(f"cpu baseline failed: {e!r}")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ladybug-like: 500 cameras on a forward trajectory, 100k landmarks, "
+                               "k = 2 + Geom(1/3) clamped to 50, BAL camera model, 1 px noise",
+                   "n_cams": stats["n_cams"], "n_points": stats["n_points"], "n_obs": stats["n_obs"],
+                   "lm_iters": args.lm_iters, "pcg_tol": 1e-6, "pcg_max_iters": 500},
+        "time_to_1pct_cost_s": ttt,
+        "f0": f0, "f_star": fstar, "f_tau": f_tau, "final_costs": finals,
+        "oracle_final_cost": gold["final_cost"] if gold else None,
+        "qr_blocks_per_s": qr_blocks_per_s,
+        "qr_GBps": qr_gbps,
+        "matvec_GBps": achieved,
+        "stage_ms": {k: v["ms"] for k, v in prof.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -248,6 +248,43 @@ int32_t sqrtba_debug_solution(sqrtba_ctx* ctx, float* dxp_scaled, float* dxl);
 /* Replace the scaled pose increment (for testing back-substitution). */
 int32_t sqrtba_debug_set_pose_increment(sqrtba_ctx* ctx, const float* dxp_scaled);
 
+/* ---- measurement and state snapshots ---- */
+
+/* Stages timed by the profiler (HIP events on the context stream). */
+enum {
+  SQRTBA_STAGE_LINEARIZE = 0,   /* kernel (a): cost and column scales */
+  SQRTBA_STAGE_MARGINALIZE = 1, /* kernel (b): per-landmark QR into landmark blocks */
+  SQRTBA_STAGE_DAMP = 2,        /* Givens landmark damping */
+  SQRTBA_STAGE_PRECOND = 3,     /* block-Jacobi blocks, right-hand side, PCG start */
+  SQRTBA_STAGE_MATVEC = 4,      /* kernel (c): one PCG product over all landmark blocks */
+  SQRTBA_STAGE_PCG_VECTOR = 5,  /* unused (vector work is inside the PCG loop) */
+  SQRTBA_STAGE_BACKSUB = 6,     /* back-substitution and model decrease */
+  SQRTBA_STAGE_UPDATE = 7,      /* tentative update and its cost */
+  SQRTBA_NUM_STAGES = 8
+};
+
+/* Accumulated per-stage figures since profiling was enabled: total
+ * milliseconds, number of timed executions, algorithmic bytes (the method's
+ * own traffic: for MATVEC 4 (18k^2 + 9k) per landmark and product, for
+ * MARGINALIZE 4 (2k (9k+1) + 12) + 12k + 16 per landmark) and units
+ * (landmark blocks processed). */
+typedef struct {
+  double ms[SQRTBA_NUM_STAGES];
+  int64_t launches[SQRTBA_NUM_STAGES];
+  double bytes[SQRTBA_NUM_STAGES];
+  int64_t units[SQRTBA_NUM_STAGES];
+} sqrtba_profile;
+
+/* Enable (on != 0) or disable the profiler; either way the counters restart. */
+int32_t sqrtba_profile_enable(sqrtba_ctx* ctx, int32_t on);
+int32_t sqrtba_profile_get(const sqrtba_ctx* ctx, sqrtba_profile* out);
+
+/* Save the current camera and landmark state on the device, and restore it
+ * (restoring invalidates the linearization).  For repeated solves from one
+ * start and for checkpoint/resume of the LM state. */
+int32_t sqrtba_save_state(sqrtba_ctx* ctx);
+int32_t sqrtba_restore_state(sqrtba_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,22 @@ struct sqrtba_ctx {
   // PCG graph
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
+  bool graph_profiled = false;
+  // stage profiler
+  bool prof_on = false;
+  sqrtba_profile prof{};
+  struct Pending {
+    int stage;
+    hipEvent_t a, b;
+    double bytes;
+    int64_t units;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  // per-problem algorithmic bytes of one matvec and one marginalization
+  std::vector<double> mv_bytes, qr_bytes;
+  std::vector<int64_t> blocks;
+  bool snapshot = false;
   // LM history
   std::vector<std::vector<sqrtba_lm_record>> history;
 };
@@ -336,6 +352,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
   for (int i = 0; i < 8; ++i) o_s[i] = f64(P);
   uint64_t o_it = f32(P), o_dn = f32(P), o_ps = f32(P), o_act = L.take(P), o_flag = L.take(P);
   uint64_t o_cnt = f32(16), o_cf = f32(4);
+  uint64_t o_csnap = f32(16 * NC), o_psnap = f32(4 * NL);
   if (base && d) {
     t.P = (int32_t)P; t.NC = (int32_t)NC; t.NL = (int32_t)NL; t.NS = (int32_t)NS; t.NO = (int32_t)NO;
     t.cam = at<float>(base, o_cam); t.cam_new = at<float>(base, o_camn);
@@ -359,9 +376,66 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
     t.iters = at<int32_t>(base, o_it); t.done = at<int32_t>(base, o_dn); t.pstatus = at<int32_t>(base, o_ps);
     t.active = at<uint8_t>(base, o_act); t.flag = at<uint8_t>(base, o_flag);
     t.counters = at<uint32_t>(base, o_cnt); t.chol_fail = at<int32_t>(base, o_cf);
+    t.cam_snap = at<float>(base, o_csnap); t.pts_snap = at<float4>(base, o_psnap);
     *d = t;
   }
   return L.total;
+}
+
+hipEvent_t take_event(sqrtba_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Resolve recorded stage events (the stream has been synchronized by the caller).
+void flush_profile(sqrtba_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->prof.ms[p.stage] += ms;
+      c->prof.launches[p.stage] += 1;
+      c->prof.bytes[p.stage] += p.bytes;
+      c->prof.units[p.stage] += p.units;
+    } else {
+      (void)hipGetLastError();
+    }
+    c->event_pool.push_back(p.a);
+    c->event_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+// Run `launches` between two events on the context stream when profiling.
+template <typename F>
+int timed(sqrtba_ctx* c, int stage, double bytes, int64_t units, F launches) {
+  if (!c->prof_on) return launches();
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return fail(c, SQRTBA_E_HIP, "hipEventCreate failed");
+  HIP_TRY(c, hipEventRecord(a, c->stream));
+  const int st = launches();
+  HIP_TRY(c, hipEventRecord(b, c->stream));
+  c->pending.push_back({stage, a, b, bytes, units});
+  return st;
+}
+
+double active_sum(const sqrtba_ctx* c, const std::vector<double>& v) {
+  double s = 0;
+  for (int p = 0; p < c->h.P; ++p)
+    if (c->active[p]) s += v[p];
+  return s;
+}
+
+int64_t active_blocks(const sqrtba_ctx* c) {
+  int64_t s = 0;
+  for (int p = 0; p < c->h.P; ++p)
+    if (c->active[p]) s += c->blocks[p];
+  return s;
 }
 
 int check_ready(sqrtba_ctx* c) {
@@ -434,6 +508,20 @@ int upload(sqrtba_ctx* c) {
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
   }
+  c->mv_bytes.assign(h.P, 0.0);
+  c->qr_bytes.assign(h.P, 0.0);
+  c->blocks.assign(h.P, 0);
+  for (int64_t sl = 0; sl < h.NS; ++sl) {
+    const double k = h.slot_k[sl];
+    const int p = h.slot_prob[sl];
+    // matvec: read the 2k x 9k B rows, write 9k per-observation outputs
+    c->mv_bytes[p] += 4.0 * (18.0 * k * k + 9.0 * k);
+    // QR: write 2k rotated rows (9k pose columns + residual) and the 12-float
+    // landmark record; read camera index and pixel per observation, the landmark
+    c->qr_bytes[p] += 4.0 * (2.0 * k * (9.0 * k + 1.0) + 12.0) + 12.0 * k + 16.0;
+    c->blocks[p] += 1;
+  }
+  c->snapshot = false;
   c->uploaded = true;
   c->linearized = c->marginalized = c->damped = c->solved = c->backsubbed = c->updated = false;
   return SQRTBA_OK;
@@ -481,9 +569,13 @@ int set_active_mask(sqrtba_ctx* c, const std::vector<uint8_t>& m) {
 
 int do_linearize(sqrtba_ctx* c, double* cost) {
   TRY(ensure_uploaded(c));
-  LAUNCH(c, launch_cam_linearize(c->d, c->L, true, false, c->d.active));
-  LAUNCH(c, launch_prob_sum(c->d, c->L, c->d.cam_part, c->d.prob_cam_off, c->d.pcost, c->d.active));
+  TRY(timed(c, SQRTBA_STAGE_LINEARIZE, 0.0, 0, [&]() {
+    LAUNCH(c, launch_cam_linearize(c->d, c->L, true, false, c->d.active));
+    LAUNCH(c, launch_prob_sum(c->d, c->L, c->d.cam_part, c->d.prob_cam_off, c->d.pcost, c->d.active));
+    return (int)SQRTBA_OK;
+  }));
   TRY(readback(c, c->d.pcost, cost));
+  flush_profile(c);
   c->linearized = true;
   c->marginalized = c->damped = c->solved = c->backsubbed = c->updated = false;
   return SQRTBA_OK;
@@ -492,8 +584,12 @@ int do_linearize(sqrtba_ctx* c, double* cost) {
 int do_marginalize(sqrtba_ctx* c) {
   TRY(ensure_uploaded(c));
   if (!c->linearized) return fail(c, SQRTBA_E_STATE, "marginalize needs linearize");
-  LAUNCH(c, launch_marginalize(c->d, c->L, c->d.active));
+  TRY(timed(c, SQRTBA_STAGE_MARGINALIZE, active_sum(c, c->qr_bytes), active_blocks(c), [&]() {
+    LAUNCH(c, launch_marginalize(c->d, c->L, c->d.active));
+    return (int)SQRTBA_OK;
+  }));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  flush_profile(c);
   c->marginalized = true;
   c->damped = c->solved = c->backsubbed = c->updated = false;
   return SQRTBA_OK;
@@ -507,20 +603,42 @@ int do_damp(sqrtba_ctx* c, const double* lambda) {
       return fail(c, SQRTBA_E_INVALID, "lambda[%d] = %g must be positive and finite", p, lambda[p]);
   std::memcpy(c->pinned, lambda, sizeof(double) * c->h.P);
   HIP_TRY(c, hipMemcpyAsync(c->d.lambda, c->pinned, sizeof(double) * c->h.P, hipMemcpyHostToDevice, c->stream));
-  LAUNCH(c, launch_damp(c->d, c->L, c->d.active));
+  TRY(timed(c, SQRTBA_STAGE_DAMP, 0.0, active_blocks(c), [&]() {
+    LAUNCH(c, launch_damp(c->d, c->L, c->d.active));
+    return (int)SQRTBA_OK;
+  }));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  flush_profile(c);
   c->damped = true;
   c->solved = c->backsubbed = c->updated = false;
   return SQRTBA_OK;
 }
 
-int run_pcg_chunk(sqrtba_ctx* c, int n) {
-  if (c->opt.use_graph && n == c->opt.pcg_check_every) {
+// One chunk of n PCG iterations, as a captured graph or as plain launches.
+// With profiling on, every matvec is bracketed by events and the caller turns
+// the first `live` pairs into stage time after synchronizing.
+int run_pcg_chunk(sqrtba_ctx* c, int n, std::vector<std::pair<hipEvent_t, hipEvent_t>>* mv_events) {
+  const bool prof = c->prof_on;
+  auto iteration = [&](hipEvent_t a, hipEvent_t b) -> hipError_t {
+    hipError_t e = hipSuccess;
+    if (a) e = hipEventRecord(a, c->stream);
+    if (e == hipSuccess) e = launch_matvec(c->d, c->L);
+    if (e == hipSuccess && b) e = hipEventRecord(b, c->stream);
+    if (e == hipSuccess) e = launch_pcg_vector(c->d, c->L);
+    return e;
+  };
+  // with the profiler on, iterations are launched one by one (an event pair
+  // around every matvec); the kernels are the same as in the graph
+  if (c->opt.use_graph && !prof && n == c->opt.pcg_check_every) {
+    if (c->graph && c->graph_profiled != prof) {
+      (void)hipGraphExecDestroy(c->graph);
+      c->graph = nullptr;
+    }
     if (!c->graph) {
       hipGraph_t g = nullptr;
       HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
       hipError_t le = hipSuccess;
-      for (int i = 0; i < n && le == hipSuccess; ++i) le = launch_pcg_iteration(c->d, c->L);
+      for (int i = 0; i < n && le == hipSuccess; ++i) le = iteration(nullptr, nullptr);
       hipError_t ee = hipStreamEndCapture(c->stream, &g);
       if (le != hipSuccess) return fail(c, SQRTBA_E_HIP, "PCG capture: %s", hipGetErrorString(le));
       if (ee != hipSuccess) return fail(c, SQRTBA_E_HIP, "PCG capture end: %s", hipGetErrorString(ee));
@@ -531,21 +649,30 @@ int run_pcg_chunk(sqrtba_ctx* c, int n) {
         return fail(c, SQRTBA_E_HIP, "PCG graph instantiate: %s", hipGetErrorString(ie));
       }
       c->graph_iters = n;
+      c->graph_profiled = prof;
     }
     HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
     return SQRTBA_OK;
   }
-  for (int i = 0; i < n; ++i) LAUNCH(c, launch_pcg_iteration(c->d, c->L));
+  for (int i = 0; i < n; ++i) {
+    hipEvent_t a = prof ? take_event(c) : nullptr, b = prof ? take_event(c) : nullptr;
+    LAUNCH(c, iteration(a, b));
+    if (prof && mv_events) mv_events->push_back({a, b});
+  }
   return SQRTBA_OK;
 }
 
 int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
   if (!c->damped) return fail(c, SQRTBA_E_STATE, "solve needs damp");
   const int P = c->h.P;
-  LAUNCH(c, launch_precond_rhs(c->d, c->L));
-  LAUNCH(c, launch_pcg_init(c->d, c->L));
+  TRY(timed(c, SQRTBA_STAGE_PRECOND, 0.0, active_blocks(c), [&]() {
+    LAUNCH(c, launch_precond_rhs(c->d, c->L));
+    LAUNCH(c, launch_pcg_init(c->d, c->L));
+    return (int)SQRTBA_OK;
+  }));
   std::vector<int32_t> done(P);
   TRY(readback(c, c->d.done, done.data()));
+  flush_profile(c);
   auto all_done = [&]() {
     for (int p = 0; p < P; ++p)
       if (!done[p]) return false;
@@ -553,11 +680,44 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
   };
   int it = 0;
   const int every = std::max(1, c->opt.pcg_check_every);
+  std::vector<int32_t> its_before(P, 0), its_after(P, 0);
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> mv;
   while (it < c->opt.pcg_max_iters && !all_done()) {
     const int n = std::min(every, c->opt.pcg_max_iters - it);
-    TRY(run_pcg_chunk(c, n));
+    mv.clear();
+    TRY(run_pcg_chunk(c, n, &mv));
     it += n;
     TRY(readback(c, c->d.done, done.data()));
+    if (c->prof_on) {
+      // matvecs of iterations that did work; later ones in the chunk exit at once
+      TRY(readback(c, c->d.iters, its_after.data()));
+      int live = 0;
+      double bytes = 0.0;
+      int64_t units = 0;
+      for (int p = 0; p < P; ++p) {
+        const int di = its_after[p] - its_before[p];
+        live = std::max(live, di);
+        bytes += c->mv_bytes[p] * di;
+        units += c->blocks[p] * di;
+      }
+      double ms_sum = 0.0;
+      for (int i = 0; i < (int)mv.size(); ++i) {
+        float ms = 0.f;
+        if (i < live) {
+          if (hipEventElapsedTime(&ms, mv[i].first, mv[i].second) == hipSuccess)
+            ms_sum += ms;
+          else
+            (void)hipGetLastError();
+        }
+        c->event_pool.push_back(mv[i].first);
+        c->event_pool.push_back(mv[i].second);
+      }
+      c->prof.ms[SQRTBA_STAGE_MATVEC] += ms_sum;
+      c->prof.launches[SQRTBA_STAGE_MATVEC] += live;
+      c->prof.bytes[SQRTBA_STAGE_MATVEC] += bytes;
+      c->prof.units[SQRTBA_STAGE_MATVEC] += units;
+      its_before = its_after;
+    }
   }
   std::vector<int32_t> its(P), st(P);
   std::vector<double> rr(P), rr0(P);
@@ -577,9 +737,13 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
 
 int do_backsub(sqrtba_ctx* c, double* pred) {
   if (!c->solved) return fail(c, SQRTBA_E_STATE, "back_substitute needs solve");
-  LAUNCH(c, launch_backsub(c->d, c->L));
-  LAUNCH(c, launch_prob_sum(c->d, c->L, c->d.lm_part, c->d.prob_lm_off, c->d.ppred, c->d.active));
+  TRY(timed(c, SQRTBA_STAGE_BACKSUB, 0.0, active_blocks(c), [&]() {
+    LAUNCH(c, launch_backsub(c->d, c->L));
+    LAUNCH(c, launch_prob_sum(c->d, c->L, c->d.lm_part, c->d.prob_lm_off, c->d.ppred, c->d.active));
+    return (int)SQRTBA_OK;
+  }));
   TRY(readback(c, c->d.ppred, pred));
+  flush_profile(c);
   c->backsubbed = true;
   c->updated = false;
   return SQRTBA_OK;
@@ -587,10 +751,14 @@ int do_backsub(sqrtba_ctx* c, double* pred) {
 
 int do_update(sqrtba_ctx* c, double* new_cost) {
   if (!c->backsubbed) return fail(c, SQRTBA_E_STATE, "update needs back_substitute");
-  LAUNCH(c, launch_update(c->d, c->L));
-  LAUNCH(c, launch_cam_linearize(c->d, c->L, false, true, c->d.active));
-  LAUNCH(c, launch_prob_sum(c->d, c->L, c->d.cam_part, c->d.prob_cam_off, c->d.pcost, c->d.active));
+  TRY(timed(c, SQRTBA_STAGE_UPDATE, 0.0, 0, [&]() {
+    LAUNCH(c, launch_update(c->d, c->L));
+    LAUNCH(c, launch_cam_linearize(c->d, c->L, false, true, c->d.active));
+    LAUNCH(c, launch_prob_sum(c->d, c->L, c->d.cam_part, c->d.prob_cam_off, c->d.pcost, c->d.active));
+    return (int)SQRTBA_OK;
+  }));
   TRY(readback(c, c->d.pcost, new_cost));
+  flush_profile(c);
   c->updated = true;
   return SQRTBA_OK;
 }
@@ -754,6 +922,11 @@ void sqrtba_destroy(sqrtba_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : c->event_pool) (void)hipEventDestroy(e);
   release_arena(c);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -1047,6 +1220,41 @@ int32_t sqrtba_debug_set_pose_increment(sqrtba_ctx* c, const float* dxp) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->solved = true;
   c->backsubbed = c->updated = false;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_profile_enable(sqrtba_ctx* c, int32_t on) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (c->stream) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  flush_profile(c);
+  c->prof = sqrtba_profile{};
+  c->prof_on = on != 0;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_profile_get(const sqrtba_ctx* c, sqrtba_profile* out) {
+  if (!c || !out) return SQRTBA_E_INVALID;
+  *out = c->prof;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_save_state(sqrtba_ctx* c) {
+  if (!c) return SQRTBA_E_INVALID;
+  TRY(ensure_uploaded(c));
+  HIP_TRY(c, hipMemcpyAsync(c->d.cam_snap, c->d.cam, 64 * c->h.NC, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d.pts_snap, c->d.pts, 16 * c->h.NL, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->snapshot = true;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_restore_state(sqrtba_ctx* c) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (!c->uploaded || !c->snapshot) return fail(c, SQRTBA_E_STATE, "restore_state needs save_state");
+  HIP_TRY(c, hipMemcpyAsync(c->d.cam, c->d.cam_snap, 64 * c->h.NC, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d.pts, c->d.pts_snap, 16 * c->h.NL, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->linearized = c->marginalized = c->damped = c->solved = c->backsubbed = c->updated = false;
   return SQRTBA_OK;
 }
 

@@ -91,6 +91,8 @@ struct Dev {
   uint8_t* flag;     // generic per-problem mask (relinearize / accept)
   uint32_t* counters;  // last-block counters (zeroed once; each user resets its own)
   int32_t* chol_fail;  // count of preconditioner blocks that fell back to the diagonal
+  float* cam_snap;     // saved state (save/restore)
+  float4* pts_snap;
   float pcg_tol;
 };
 
@@ -113,6 +115,8 @@ hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask);
 hipError_t launch_precond_rhs(const Dev& d, const Launch& L);
 hipError_t launch_pcg_init(const Dev& d, const Launch& L);
 hipError_t launch_pcg_iteration(const Dev& d, const Launch& L);
+hipError_t launch_matvec(const Dev& d, const Launch& L);      // the PCG product (p folded in)
+hipError_t launch_pcg_vector(const Dev& d, const Launch& L);  // reduce + update of one iteration
 hipError_t launch_backsub(const Dev& d, const Launch& L);
 hipError_t launch_update(const Dev& d, const Launch& L);
 hipError_t launch_commit(const Dev& d, const Launch& L);

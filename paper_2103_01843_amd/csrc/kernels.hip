@@ -746,10 +746,9 @@ __device__ __forceinline__ void matvec_small(const Dev& d, int slot, int lane, c
 }
 
 template <int TEAM, bool FOLD>
-__global__ __launch_bounds__(WG) void k_matvec_small(Dev d, int wi0, const float* v) {
+__device__ __forceinline__ void matvec_small_wi(const Dev& d, int wi, const float* v) {
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
-  const int wi = wi0 + blockIdx.x;
   if (team >= d.wi_count[wi]) return;
   const int slot = d.wi_first[wi] + team;
   const int prob = d.slot_prob[slot];
@@ -762,9 +761,7 @@ __global__ __launch_bounds__(WG) void k_matvec_small(Dev d, int wi0, const float
 // groups (strided by 64).  The 4 partial z vectors are summed through LDS in
 // a fixed order.
 template <int NCG, bool FOLD>
-__global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int wi0, const float* v) {
-  __shared__ float4 zred[4][64];
-  const int wi = wi0 + blockIdx.x;
+__device__ __forceinline__ void matvec_large_wi(const Dev& d, int wi, const float* v, float4 (*zred)[64]) {
   const int slot = d.wi_first[wi];
   const int prob = d.slot_prob[slot];
   if (!d.active[prob] || (FOLD && d.done[prob])) return;
@@ -813,6 +810,33 @@ __global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int wi0, const float
     }
     __syncthreads();
   }
+}
+
+// Size class of a landmark from its observation count (the thresholds of kClasses).
+__device__ __forceinline__ int class_of_k_dev(int k) {
+  return k <= 3 ? 0 : (k <= 7 ? 1 : (k <= 28 ? 2 : (k <= 113 ? 3 : 4)));
+}
+
+// One launch for the size classes 0..3: every workgroup handles one work item
+// (one class), so the whole product over landmarks with k <= 113 is a single
+// kernel with no tail gaps between classes.
+template <bool FOLD>
+__global__ __launch_bounds__(WG) void k_matvec(Dev d, int wi0, const float* v) {
+  __shared__ float4 zred[4][64];
+  const int wi = wi0 + blockIdx.x;
+  switch (class_of_k_dev(d.slot_k[d.wi_first[wi]])) {
+    case 0: matvec_small_wi<8, FOLD>(d, wi, v); break;
+    case 1: matvec_small_wi<16, FOLD>(d, wi, v); break;
+    case 2: matvec_small_wi<64, FOLD>(d, wi, v); break;
+    default: matvec_large_wi<4, FOLD>(d, wi, v, zred); break;
+  }
+}
+
+// Landmarks with k > 113 (up to 512): four wavefronts per landmark.
+template <bool FOLD>
+__global__ __launch_bounds__(WG) void k_matvec_huge(Dev d, int wi0, const float* v) {
+  __shared__ float4 zred[4][64];
+  matvec_large_wi<18, FOLD>(d, wi0 + blockIdx.x, v, zred);
 }
 
 // ----------------------------------------------------- PCG vector kernels
@@ -1273,11 +1297,9 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
 template <bool FOLD>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
   const WorkClass* w = L.wc;
-  if (w[4].count) hipLaunchKernelGGL((k_matvec_large<18, FOLD>), dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, v);
-  if (w[3].count) hipLaunchKernelGGL((k_matvec_large<4, FOLD>), dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi, v);
-  if (w[2].count) hipLaunchKernelGGL((k_matvec_small<64, FOLD>), dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi, v);
-  if (w[1].count) hipLaunchKernelGGL((k_matvec_small<16, FOLD>), dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi, v);
-  if (w[0].count) hipLaunchKernelGGL((k_matvec_small<8, FOLD>), dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi, v);
+  if (w[4].count) hipLaunchKernelGGL(k_matvec_huge<FOLD>, dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, v);
+  const int n = w[3].count + w[2].count + w[1].count + w[0].count;
+  if (n) hipLaunchKernelGGL(k_matvec<FOLD>, dim3(n), dim3(WG), 0, L.stream, d, w[3].first_wi, v);
   LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1288,14 +1310,20 @@ hipError_t launch_pcg_init(const Dev& d, const Launch& L) {
   return hipSuccess;
 }
 
-hipError_t launch_pcg_iteration(const Dev& d, const Launch& L) {
-  hipError_t e = launch_matvec<true>(d, L, nullptr);
-  if (e != hipSuccess) return e;
+hipError_t launch_matvec(const Dev& d, const Launch& L) { return launch_matvec<true>(d, L, nullptr); }
+
+hipError_t launch_pcg_vector(const Dev& d, const Launch& L) {
   hipLaunchKernelGGL(k_pcg_reduce, dim3(nblocks(d.NC, 4)), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(d.NC, WG)), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
   return hipSuccess;
+}
+
+hipError_t launch_pcg_iteration(const Dev& d, const Launch& L) {
+  hipError_t e = launch_matvec(d, L);
+  if (e != hipSuccess) return e;
+  return launch_pcg_vector(d, L);
 }
 
 hipError_t launch_backsub(const Dev& d, const Launch& L) {

@@ -57,6 +57,14 @@ class LMRecord(C.Structure):
     ]
 
 
+STAGES = ["linearize", "marginalize", "damp", "precond", "matvec", "pcg_vector", "backsub", "update"]
+
+
+class Profile(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("bytes", C.c_double * 8),
+                ("units", C.c_int64 * 8)]
+
+
 _lib = None
 
 P = C.c_void_p
@@ -98,6 +106,10 @@ _SIGS = {
     "sqrtba_debug_block": (I32, [P, I64, PI32, PF, PF]),
     "sqrtba_debug_solution": (I32, [P, PF, PF]),
     "sqrtba_debug_set_pose_increment": (I32, [P, PF]),
+    "sqrtba_profile_enable": (I32, [P, I32]),
+    "sqrtba_profile_get": (I32, [P, C.POINTER(Profile)]),
+    "sqrtba_save_state": (I32, [P]),
+    "sqrtba_restore_state": (I32, [P]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -313,6 +325,22 @@ class Context:
         out = np.zeros((self.n_points, 3), np.float32)
         self._check(lib().sqrtba_get_landmarks(self._h, _ptr(out, C.c_float)))
         return out
+
+    # -- measurement and snapshots
+    def profile_enable(self, on: bool = True):
+        self._check(lib().sqrtba_profile_enable(self._h, 1 if on else 0))
+
+    def profile(self) -> dict:
+        pr = Profile()
+        self._check(lib().sqrtba_profile_get(self._h, C.byref(pr)))
+        return {name: {"ms": pr.ms[i], "launches": int(pr.launches[i]), "bytes": pr.bytes[i],
+                       "units": int(pr.units[i])} for i, name in enumerate(STAGES)}
+
+    def save_state(self):
+        self._check(lib().sqrtba_save_state(self._h))
+
+    def restore_state(self):
+        self._check(lib().sqrtba_restore_state(self._h))
 
     # -- inspection exports
     def debug_bookkeeping(self) -> dict:
