@@ -297,7 +297,7 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
   nb.wi_count.clear();
   for (int cl = NUM_CLASSES - 1; cl >= 0; --cl) {
     nb.wc[cl].first_wi = (int)nb.wi_first.size();
-    const int tpw = 256 / kClasses[cl].team;
+    const int tpw = 256 / class_team(cl);
     int64_t s = 0;
     while (s < nb.NS && class_of_k(nb.slot_k[s]) != cl) ++s;
     while (s < nb.NS && class_of_k(nb.slot_k[s]) == cl) {
@@ -347,11 +347,11 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
   uint64_t o_v[6];
   for (int i = 0; i < 6; ++i) o_v[i] = f32(9 * NC);
   uint64_t o_minv = f32(81 * NC), o_ob = f32(54 * NO), o_dxl = f32(3 * NL);
-  uint64_t o_cp = f64(NC), o_cp2 = f64(NC), o_lp = f64(NL);
+  uint64_t o_cp = f64(NC), o_cp2 = f64(NC), o_cp3 = f64(NC), o_lp = f64(NL);
   uint64_t o_s[8];
   for (int i = 0; i < 8; ++i) o_s[i] = f64(P);
   uint64_t o_it = f32(P), o_dn = f32(P), o_ps = f32(P), o_act = L.take(P), o_flag = L.take(P);
-  uint64_t o_cnt = f32(16), o_cf = f32(4);
+  uint64_t o_cf = f32(4);
   uint64_t o_csnap = f32(16 * NC), o_psnap = f32(4 * NL);
   if (base && d) {
     t.P = (int32_t)P; t.NC = (int32_t)NC; t.NL = (int32_t)NL; t.NS = (int32_t)NS; t.NO = (int32_t)NO;
@@ -369,13 +369,14 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
     t.vx = at<float>(base, o_v[0]); t.vr = at<float>(base, o_v[1]); t.vz = at<float>(base, o_v[2]);
     t.vp = at<float>(base, o_v[3]); t.vq = at<float>(base, o_v[4]); t.vb = at<float>(base, o_v[5]);
     t.minv = at<float>(base, o_minv); t.obsbuf = at<float>(base, o_ob); t.dxl = at<float>(base, o_dxl);
-    t.cam_part = at<double>(base, o_cp); t.cam_part2 = at<double>(base, o_cp2); t.lm_part = at<double>(base, o_lp);
+    t.cam_part = at<double>(base, o_cp); t.cam_part2 = at<double>(base, o_cp2); t.cam_part3 = at<double>(base, o_cp3);
+    t.lm_part = at<double>(base, o_lp);
     t.lambda = at<double>(base, o_s[0]); t.alpha = at<double>(base, o_s[1]); t.beta = at<double>(base, o_s[2]);
     t.rz = at<double>(base, o_s[3]); t.rr = at<double>(base, o_s[4]); t.rr0 = at<double>(base, o_s[5]);
     t.pcost = at<double>(base, o_s[6]); t.ppred = at<double>(base, o_s[7]);
     t.iters = at<int32_t>(base, o_it); t.done = at<int32_t>(base, o_dn); t.pstatus = at<int32_t>(base, o_ps);
     t.active = at<uint8_t>(base, o_act); t.flag = at<uint8_t>(base, o_flag);
-    t.counters = at<uint32_t>(base, o_cnt); t.chol_fail = at<int32_t>(base, o_cf);
+    t.chol_fail = at<int32_t>(base, o_cf);
     t.cam_snap = at<float>(base, o_csnap); t.pts_snap = at<float4>(base, o_psnap);
     *d = t;
   }

@@ -10,15 +10,18 @@ namespace sqrtba {
 // Landmark work is split into size classes by observation count k; each class
 // maps one landmark to a "team" of lanes of a fixed size.  The classes are
 // contiguous k ranges; landmarks are ordered by decreasing k so the largest
-// blocks start first.
-enum { NUM_CLASSES = 5 };
-struct ClassInfo {
-  int team;     // lanes per landmark: 8, 16, 64, 256, 256
-  int kmin, kmax;
-  int ncg;      // float4 column groups per lane (only for team 256)
-};
-extern const ClassInfo kClasses[NUM_CLASSES];
-int class_of_k(int k);
+// blocks start first.  One definition serves host bucketing and device dispatch.
+enum { NUM_CLASSES = 6 };
+//                               class:  0   1   2   3    4    5
+__host__ __device__ constexpr int class_kmax(int c) {
+  return c == 0 ? 3 : c == 1 ? 7 : c == 2 ? 14 : c == 3 ? 28 : c == 4 ? 113 : 512;
+}
+__host__ __device__ constexpr int class_team(int c) {
+  return c == 0 ? 8 : c == 1 ? 16 : c == 2 ? 32 : c == 3 ? 64 : 256;
+}
+__host__ __device__ constexpr int class_of_k(int k) {
+  return k <= 3 ? 0 : k <= 7 ? 1 : k <= 14 ? 2 : k <= 28 ? 3 : k <= 113 ? 4 : k <= 512 ? 5 : -1;
+}
 
 // Small per-landmark record (floats): R1 upper (6), Q1^T r (3), damped R upper (6),
 // damped Q1^T r (3), landmark column scales (3), lambda used (1), pad (2).
@@ -70,10 +73,11 @@ struct Dev {
   float* vq;
   float* vb;      // right-hand side b~
   float* minv;    // NC * 81 inverse preconditioner blocks
-  float* obsbuf;  // NO * 54: per-observation partial products (matvec uses the first 9 NO)
+  float* obsbuf;  // NO * 54: per-observation partial products (the matvec uses the first 9 NO)
   float* dxl;     // NL * 3, unscaled landmark increment
   double* cam_part;  // NC, per-camera partial sums
   double* cam_part2; // NC
+  double* cam_part3; // NC
   double* lm_part;   // NL, per-landmark partial sums
   // per-problem scalars
   double* lambda;
@@ -89,7 +93,6 @@ struct Dev {
   double* ppred;
   uint8_t* active;
   uint8_t* flag;     // generic per-problem mask (relinearize / accept)
-  uint32_t* counters;  // last-block counters (zeroed once; each user resets its own)
   int32_t* chol_fail;  // count of preconditioner blocks that fell back to the diagonal
   float* cam_snap;     // saved state (save/restore)
   float4* pts_snap;

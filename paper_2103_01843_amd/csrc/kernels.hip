@@ -22,20 +22,6 @@
 
 namespace sqrtba {
 
-const ClassInfo kClasses[NUM_CLASSES] = {
-    {8, 2, 3, 1},        // W <= 28 floats -> 7 column groups
-    {16, 4, 7, 1},       // W <= 64 -> 16 column groups
-    {64, 8, 28, 1},      // W <= 252 -> 63 column groups
-    {256, 29, 113, 4},   // W <= 1020 -> 255 column groups, 4 per lane
-    {256, 114, 512, 18}, // W <= 4608 -> 1152 column groups, 18 per lane
-};
-
-int class_of_k(int k) {
-  for (int c = 0; c < NUM_CLASSES; ++c)
-    if (k >= kClasses[c].kmin && k <= kClasses[c].kmax) return c;
-  return -1;
-}
-
 namespace {
 
 constexpr int WG = 256;
@@ -49,7 +35,7 @@ __device__ __forceinline__ float dppf(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// All-reduce over aligned groups of TEAM lanes (8, 16 or 64).  Every lane of
+// All-reduce over aligned groups of TEAM lanes (8, 16, 32 or 64).  Every lane of
 // the group receives the bitwise-identical sum (each step adds a commutative
 // pair).  All lanes of a group must be active together.
 template <int TEAM>
@@ -58,10 +44,8 @@ __device__ __forceinline__ float team_sum(float v) {
   v += dppf<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dppf<0x141>(v);  // row_half_mirror: pairs quads of a half row
   if constexpr (TEAM >= 16) v += dppf<0x140>(v);  // row_mirror: pairs half rows
-  if constexpr (TEAM >= 64) {
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-  }
+  if constexpr (TEAM >= 32) v += __shfl_xor(v, 16);  // pairs rows of 16 within 32 lanes
+  if constexpr (TEAM >= 64) v += __shfl_xor(v, 32);
   return v;
 }
 
@@ -207,15 +191,26 @@ __global__ __launch_bounds__(64) void k_cam_linearize(Dev d, const float* __rest
   if (lane == 0) d.cam_part[c] = cost;
 }
 
-// One wavefront per problem: out[p] = sum of vals[off[p] .. off[p+1]) (fixed tree).
-__global__ __launch_bounds__(64) void k_prob_sum(const double* __restrict__ vals, const int32_t* __restrict__ off,
-                                                 double* out, const uint8_t* mask) {
+// One 1024-thread workgroup per problem: out[p] = sum of vals[off[p] .. off[p+1])
+// (strided per thread, then a fixed tree).
+constexpr int SUM_THREADS = 1024;
+
+__global__ __launch_bounds__(SUM_THREADS) void k_prob_sum(const double* __restrict__ vals,
+                                                          const int32_t* __restrict__ off, double* out,
+                                                          const uint8_t* mask) {
+  __shared__ double red[SUM_THREADS / 64];
   const int p = blockIdx.x;
   if (mask && !mask[p]) return;
   double s = 0.0;
-  for (int i = off[p] + (int)threadIdx.x; i < off[p + 1]; i += 64) s += vals[i];
+  for (int i = off[p] + (int)threadIdx.x; i < off[p + 1]; i += SUM_THREADS) s += vals[i];
   s = wave_sum_d(s);
-  if (threadIdx.x == 0) out[p] = s;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < SUM_THREADS / 64; ++w) t += red[w];
+    out[p] = t;
+  }
 }
 
 // ------------------------------------------- kernel (b): marginalize by QR
@@ -307,10 +302,11 @@ __global__ __launch_bounds__(WG) void k_marginalize(Dev d, int wi0, const uint8_
     const float nrm = sqrtf(sig);
     float alpha = 0.f, vj = 0.f, tj = 0.f;
     if (nrm > 0.f) {
+      // v = x + sign(x_j) |x| e_j, so v^T v = 2 |x| (|x| + |x_j|) exactly: tau = 2 / v^T v
+      // without the cancellation of |x|^2 - x_j^2 when x_j dominates the column
       alpha = xj >= 0.f ? -nrm : nrm;
       vj = xj - alpha;
-      const float vtv = sig - xj * xj + vj * vj;
-      tj = vtv > 0.f ? 2.0f / vtv : 0.f;
+      tj = 1.0f / (nrm * (nrm + fabsf(xj)));
     }
     tau[j] = tj;
     // reflector column j of V
@@ -707,7 +703,10 @@ __device__ __forceinline__ float4 gather_cols(const Dev& d, const float* __restr
 
 __device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 
-__device__ __forceinline__ void store_cols(float* __restrict__ zo, int k, int g, float4 z) {
+// Store the 4 output columns of column group g: the landmark's 9k outputs are
+// contiguous (observation-major, 9 per observation) at obsbuf[9 obs0].
+__device__ __forceinline__ void store_cols(const Dev& d, int obs0, int k, int g, float4 z) {
+  float* zo = d.obsbuf + 9 * (size_t)obs0;
   const int c = 4 * g;
   if (c + 0 < 9 * k) zo[c + 0] = z.x;
   if (c + 1 < 9 * k) zo[c + 1] = z.y;
@@ -732,9 +731,26 @@ __device__ __forceinline__ void matvec_small(const Dev& d, int slot, int lane, c
   const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
   float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   const int n = 2 * k;  // always even
-  for (int r = 0; r < n; r += 2) {
-    const float4 b0 = on ? B[(size_t)r * G + g] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 b1 = on ? B[(size_t)(r + 1) * G + g] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  int r = 0;
+  // four rows per step: four independent loads in flight, then four reductions
+  for (; r + 4 <= n; r += 4) {
+    const float4 b0 = on ? B[(size_t)r * G + g] : zero;
+    const float4 b1 = on ? B[(size_t)(r + 1) * G + g] : zero;
+    const float4 b2 = on ? B[(size_t)(r + 2) * G + g] : zero;
+    const float4 b3 = on ? B[(size_t)(r + 3) * G + g] : zero;
+    const float y0 = team_sum<TEAM>(dot4(b0, pv));
+    const float y1 = team_sum<TEAM>(dot4(b1, pv));
+    const float y2 = team_sum<TEAM>(dot4(b2, pv));
+    const float y3 = team_sum<TEAM>(dot4(b3, pv));
+    z.x += (y0 * b0.x + y1 * b1.x) + (y2 * b2.x + y3 * b3.x);
+    z.y += (y0 * b0.y + y1 * b1.y) + (y2 * b2.y + y3 * b3.y);
+    z.z += (y0 * b0.z + y1 * b1.z) + (y2 * b2.z + y3 * b3.z);
+    z.w += (y0 * b0.w + y1 * b1.w) + (y2 * b2.w + y3 * b3.w);
+  }
+  if (r < n) {  // n = 4m + 2
+    const float4 b0 = on ? B[(size_t)r * G + g] : zero;
+    const float4 b1 = on ? B[(size_t)(r + 1) * G + g] : zero;
     const float y0 = team_sum<TEAM>(dot4(b0, pv));
     const float y1 = team_sum<TEAM>(dot4(b1, pv));
     z.x += y0 * b0.x + y1 * b1.x;
@@ -742,7 +758,7 @@ __device__ __forceinline__ void matvec_small(const Dev& d, int slot, int lane, c
     z.z += y0 * b0.z + y1 * b1.z;
     z.w += y0 * b0.w + y1 * b1.w;
   }
-  if (on) store_cols(d.obsbuf + 9 * (size_t)obs0, k, g, z);
+  if (on) store_cols(d, obs0, k, g, z);
 }
 
 template <int TEAM, bool FOLD>
@@ -795,7 +811,6 @@ __device__ __forceinline__ void matvec_large_wi(const Dev& d, int wi, const floa
       z[j].x += y * b[j].x; z[j].y += y * b[j].y; z[j].z += y * b[j].z; z[j].w += y * b[j].w;
     }
   }
-  float* zo = d.obsbuf + 9 * (size_t)obs0;
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
     if (64 * j >= G) break;  // uniform across the workgroup
@@ -806,28 +821,24 @@ __device__ __forceinline__ void matvec_large_wi(const Dev& d, int wi, const floa
       const float4 s = make_float4((a.x + b2.x) + (c.x + e.x), (a.y + b2.y) + (c.y + e.y),
                                    (a.z + b2.z) + (c.z + e.z), (a.w + b2.w) + (c.w + e.w));
       const int g = lane + 64 * j;
-      if (g < G) store_cols(zo, k, g, s);
+      if (g < G) store_cols(d, obs0, k, g, s);
     }
     __syncthreads();
   }
 }
 
-// Size class of a landmark from its observation count (the thresholds of kClasses).
-__device__ __forceinline__ int class_of_k_dev(int k) {
-  return k <= 3 ? 0 : (k <= 7 ? 1 : (k <= 28 ? 2 : (k <= 113 ? 3 : 4)));
-}
-
-// One launch for the size classes 0..3: every workgroup handles one work item
+// One launch for the size classes 0..4: every workgroup handles one work item
 // (one class), so the whole product over landmarks with k <= 113 is a single
 // kernel with no tail gaps between classes.
 template <bool FOLD>
 __global__ __launch_bounds__(WG) void k_matvec(Dev d, int wi0, const float* v) {
   __shared__ float4 zred[4][64];
   const int wi = wi0 + blockIdx.x;
-  switch (class_of_k_dev(d.slot_k[d.wi_first[wi]])) {
+  switch (class_of_k(d.slot_k[d.wi_first[wi]])) {
     case 0: matvec_small_wi<8, FOLD>(d, wi, v); break;
     case 1: matvec_small_wi<16, FOLD>(d, wi, v); break;
-    case 2: matvec_small_wi<64, FOLD>(d, wi, v); break;
+    case 2: matvec_small_wi<32, FOLD>(d, wi, v); break;
+    case 3: matvec_small_wi<64, FOLD>(d, wi, v); break;
     default: matvec_large_wi<4, FOLD>(d, wi, v, zred); break;
   }
 }
@@ -841,35 +852,35 @@ __global__ __launch_bounds__(WG) void k_matvec_huge(Dev d, int wi0, const float*
 
 // ----------------------------------------------------- PCG vector kernels
 
-// Last-workgroup-done reduction: every workgroup writes per-camera partials,
-// then one atomic per workgroup; the workgroup that arrives last sums the
-// partials of each problem (one wavefront per problem, fixed order) and runs
-// `fin(problem, sum_a, sum_b)`.  The counter is reset for the next use.
-template <typename Fin>
-__device__ __forceinline__ void last_block_reduce(const Dev& d, uint32_t* counter, const double* pa,
-                                                  const double* pb, Fin fin) {
-  __shared__ bool is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t prev = atomicAdd(counter, 1u);
-    is_last = (prev == gridDim.x - 1);
+// Kernel boundaries order the phases of one PCG iteration; there are no
+// grid-wide atomics or fences.  Per-camera partial sums are FP64 and every
+// per-problem sum is formed by the same fixed-order wavefront tree
+// (problem_sum), so all workgroups that form a scalar get the same bits.
+
+__device__ __forceinline__ double problem_sum(const Dev& d, const double* __restrict__ part, int p, int lane) {
+  double s = 0.0;
+  const int e = d.prob_cam_off[p + 1];
+#pragma unroll 4
+  for (int c = d.prob_cam_off[p] + lane; c < e; c += 64) s += part[c];
+  return wave_sum_d(s);
+}
+
+// The three per-problem sums of one iteration in one pass (same per-lane order
+// as problem_sum, so the first sum is bitwise equal to problem_sum(part)).
+__device__ __forceinline__ void problem_sum3(const Dev& d, const double* __restrict__ a, const double* __restrict__ b,
+                                             const double* __restrict__ c3, int p, int lane, double& sa, double& sb,
+                                             double& sc) {
+  sa = sb = sc = 0.0;
+  const int e = d.prob_cam_off[p + 1];
+#pragma unroll 4
+  for (int c = d.prob_cam_off[p] + lane; c < e; c += 64) {
+    sa += a[c];
+    sb += b[c];
+    sc += c3[c];
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (int p = w; p < d.P; p += nw) {
-    double sa = 0.0, sb = 0.0;
-    for (int c = d.prob_cam_off[p] + lane; c < d.prob_cam_off[p + 1]; c += 64) {
-      sa += __builtin_nontemporal_load(pa + c);
-      if (pb) sb += __builtin_nontemporal_load(pb + c);
-    }
-    sa = wave_sum_d(sa);
-    sb = wave_sum_d(sb);
-    if (lane == 0) fin(p, sa, sb);
-  }
-  if (threadIdx.x == 0) *counter = 0u;
+  sa = wave_sum_d(sa);
+  sb = wave_sum_d(sb);
+  sc = wave_sum_d(sc);
 }
 
 __device__ __forceinline__ void minv_apply(const float* __restrict__ mi, const float r[9], float z[9]) {
@@ -882,138 +893,200 @@ __device__ __forceinline__ void minv_apply(const float* __restrict__ mi, const f
   }
 }
 
-// x = 0, r = -b, z = M^-1 r, p = 0, beta = 0; rz = r.z and rr0 = r.r per problem.
+// x = 0, r = -b, z = M^-1 r, p = 0; per-camera partials r.z (cam_part2), r.r (cam_part3).
 __global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < d.NC) {
-    const int prob = d.cam_prob[c];
-    double rz = 0.0, rr = 0.0;
-    if (d.active[prob]) {
-      float r[9], z[9];
+  if (c >= d.NC) return;
+  const int prob = d.cam_prob[c];
+  double rz = 0.0, rr = 0.0;
+  if (d.active[prob]) {
+    float r[9], z[9];
 #pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        r[a] = -d.vb[9 * c + a];
-        d.vx[9 * c + a] = 0.f;
-        d.vr[9 * c + a] = r[a];
-        d.vp[9 * c + a] = 0.f;
-      }
-      minv_apply(d.minv + 81 * (size_t)c, r, z);
-#pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        d.vz[9 * c + a] = z[a];
-        rz += (double)(r[a] * z[a]);
-        rr += (double)(r[a] * r[a]);
-      }
+    for (int a = 0; a < 9; ++a) {
+      r[a] = -d.vb[9 * c + a];
+      d.vx[9 * c + a] = 0.f;
+      d.vr[9 * c + a] = r[a];
+      d.vp[9 * c + a] = 0.f;
     }
-    d.cam_part[c] = rz;
-    d.cam_part2[c] = rr;
+    minv_apply(d.minv + 81 * (size_t)c, r, z);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      d.vz[9 * c + a] = z[a];
+      rz += (double)(r[a] * z[a]);
+      rr += (double)(r[a] * r[a]);
+    }
   }
-  last_block_reduce(d, d.counters + 0, d.cam_part, d.cam_part2, [&](int p, double rz, double rr) {
-    d.rz[p] = rz;
-    d.rr0[p] = rr;
-    d.rr[p] = rr;
-    d.beta[p] = 0.0;
-    d.alpha[p] = 0.0;
-    d.iters[p] = 0;
-    if (!d.active[p]) { d.done[p] = 1; d.pstatus[p] = 4; }
-    else if (!(rr > 0.0)) { d.done[p] = 1; d.pstatus[p] = (rr == 0.0) ? 3 : 2; }
-    else { d.done[p] = 0; d.pstatus[p] = 1; }
-  });
+  d.cam_part2[c] = rz;
+  d.cam_part3[c] = rr;
 }
 
-// Per camera (one wavefront): p = z + beta p, q = S sum_obs z_obs + lambda p,
-// partial p.q; the last workgroup forms alpha = rz / p^T q per problem.
-__global__ __launch_bounds__(WG) void k_pcg_reduce(Dev d) {
+// One workgroup: per-problem start scalars (beta = 0, rz, rr0, done).
+__global__ __launch_bounds__(WG) void k_pcg_init_scalars(Dev d) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 4 + w;
-  double pq = 0.0;
-  if (c < d.NC) {
-    const int prob = d.cam_prob[c];
-    if (d.active[prob] && !d.done[prob]) {
-      float acc[9];
-#pragma unroll
-      for (int a = 0; a < 9; ++a) acc[a] = 0.f;
-      const int b = d.cam_obs_off[c], e = d.cam_obs_off[c + 1];
-      for (int i = b + lane; i < e; i += 64) {
-        const float* src = d.obsbuf + (size_t)d.cam_obs_idx[i] * 9;
-#pragma unroll
-        for (int a = 0; a < 9; ++a) acc[a] += src[a];
-      }
-#pragma unroll
-      for (int a = 0; a < 9; ++a) acc[a] = wave_sum_f(acc[a]);
-      if (lane < 9) {
-        float s = acc[0];
-#pragma unroll
-        for (int a = 1; a < 9; ++a) s = (lane == a) ? acc[a] : s;
-        const int idx = 9 * c + lane;
-        const float beta = (float)d.beta[prob];
-        const float pn = d.vz[idx] + beta * d.vp[idx];
-        const float q = d.s_cam[idx] * s + (float)d.lambda[prob] * pn;
-        d.vp[idx] = pn;
-        d.vq[idx] = q;
-        pq = (double)(pn * q);
-      }
+  for (int p = w; p < d.P; p += WG / 64) {
+    const double rz = problem_sum(d, d.cam_part2, p, lane);
+    const double rr = problem_sum(d, d.cam_part3, p, lane);
+    if (lane == 0) {
+      d.rz[p] = rz;
+      d.rr0[p] = rr;
+      d.rr[p] = rr;
+      d.beta[p] = 0.0;
+      d.iters[p] = 0;
+      if (!d.active[p]) { d.done[p] = 1; d.pstatus[p] = 4; }
+      else if (!(rr > 0.0)) { d.done[p] = 1; d.pstatus[p] = (rr == 0.0) ? 3 : 2; }
+      else { d.done[p] = 0; d.pstatus[p] = 1; }
     }
-    // 9 lanes hold products; sum them in a fixed order
-    pq = wave_sum_d(pq);
-    if (lane == 0) d.cam_part[c] = pq;
   }
-  last_block_reduce(d, d.counters + 1, d.cam_part, nullptr, [&](int p, double pq, double) {
-    if (!d.active[p] || d.done[p]) return;
-    if (!(pq > 0.0) || !isfinite(pq)) {
-      d.alpha[p] = 0.0;
-      d.done[p] = 1;
-      d.pstatus[p] = 2;  // breakdown: keep x
-    } else {
-      d.alpha[p] = d.rz[p] / pq;
-    }
-  });
 }
 
-// Per camera: x += alpha p, r -= alpha q, z = M^-1 r; partials r.z and r.r;
-// the last workgroup counts the iteration, tests |r| <= tol |r0| and forms beta.
-__global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < d.NC) {
-    const int prob = d.cam_prob[c];
-    double rz = 0.0, rr = 0.0;
-    if (d.active[prob] && !d.done[prob]) {
-      const float alpha = (float)d.alpha[prob];
-      float r[9], z[9];
+// Per camera (one workgroup): p = z + beta p, q = S sum_obs z_obs + lambda p,
+// partial p.q (cam_part).
+__global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
+  __shared__ float part[4][9];
+  __shared__ float pqs[9];
+  const int c = blockIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int prob = d.cam_prob[c];
+  if (!d.active[prob] || d.done[prob]) return;  // uniform over the workgroup
+  float acc[9];
 #pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        const int idx = 9 * c + a;
-        d.vx[idx] += alpha * d.vp[idx];
-        r[a] = d.vr[idx] - alpha * d.vq[idx];
-        d.vr[idx] = r[a];
-      }
-      minv_apply(d.minv + 81 * (size_t)c, r, z);
+  for (int a = 0; a < 9; ++a) acc[a] = 0.f;
+  const int b = d.cam_obs_off[c], e = d.cam_obs_off[c + 1];
+  for (int i = b + (int)threadIdx.x; i < e; i += WG) {
+    const float* src = d.obsbuf + 9 * (size_t)d.cam_obs_idx[i];
 #pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        d.vz[9 * c + a] = z[a];
-        rz += (double)(r[a] * z[a]);
-        rr += (double)(r[a] * r[a]);
-      }
-    }
-    d.cam_part[c] = rz;
-    d.cam_part2[c] = rr;
+    for (int a = 0; a < 9; ++a) acc[a] += src[a];
   }
-  last_block_reduce(d, d.counters + 2, d.cam_part, d.cam_part2, [&](int p, double rz, double rr) {
-    if (!d.active[p] || d.done[p]) return;
-    d.iters[p] += 1;
-    d.rr[p] = rr;
-    const double tol = (double)d.pcg_tol;
-    if (!isfinite(rr) || !isfinite(rz)) {
-      d.done[p] = 1;
-      d.pstatus[p] = 2;
-    } else if (rr <= tol * tol * d.rr0[p]) {
-      d.done[p] = 1;
-      d.pstatus[p] = 0;
-    } else {
-      d.beta[p] = rz / d.rz[p];
-      d.rz[p] = rz;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) acc[a] = wave_sum_f(acc[a]);
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) part[w][a] = acc[a];
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    const int a = threadIdx.x;
+    const float s = (part[0][a] + part[1][a]) + (part[2][a] + part[3][a]);
+    const int idx = 9 * c + a;
+    const float pn = d.vz[idx] + (float)d.beta[prob] * d.vp[idx];
+    const float q = d.s_cam[idx] * s + (float)d.lambda[prob] * pn;
+    d.vp[idx] = pn;
+    d.vq[idx] = q;
+    pqs[a] = pn * q;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double pq = 0.0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) pq += (double)pqs[a];
+    d.cam_part[c] = pq;
+  }
+}
+
+// One thread per (camera, row), UPD_CAMS cameras per workgroup.  Each
+// workgroup forms alpha = rz / p^T q of its problems itself (the same fixed
+// sum everywhere; alpha = 0 on breakdown, which k_pcg_scalars then reports),
+// then x += alpha p, r -= alpha q, z = M^-1 r (the camera's r through LDS),
+// and per-camera partials r.z (cam_part2) and r.r (cam_part3).
+constexpr int UPD_CAMS = 28;
+constexpr int UPD_THREADS = 9 * UPD_CAMS;  // 252
+
+__global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
+  __shared__ float rs[UPD_CAMS][9];
+  __shared__ float prz[UPD_CAMS][9];
+  __shared__ float prr[UPD_CAMS][9];
+  __shared__ float alpha_s[UPD_CAMS];
+  const int lc = threadIdx.x / 9, a = threadIdx.x - 9 * (threadIdx.x / 9);
+  const int c0 = blockIdx.x * UPD_CAMS;
+  const int c = c0 + lc;
+  const int cl = min(c0 + UPD_CAMS, d.NC);  // cameras [c0, cl) of this workgroup
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // alpha of every problem that owns a camera of this workgroup (wave 0)
+  if (w == 0) {
+    int pprev = -1;
+    float al = 0.f;
+    for (int cc = c0; cc < cl; ++cc) {
+      const int p = d.cam_prob[cc];
+      if (p != pprev) {
+        al = 0.f;
+        if (d.active[p] && !d.done[p]) {
+          const double pq = problem_sum(d, d.cam_part, p, lane);
+          al = (pq > 0.0 && isfinite(pq)) ? (float)(d.rz[p] / pq) : 0.f;
+        }
+        pprev = p;
+      }
+      if (lane == 0) alpha_s[cc - c0] = al;
     }
-  });
+  }
+  __syncthreads();
+  const bool valid = c < d.NC && lc < UPD_CAMS;
+  bool live = false;
+  float r = 0.f, z = 0.f;
+  if (valid) {
+    const int prob = d.cam_prob[c];
+    live = d.active[prob] && !d.done[prob];
+    if (live) {
+      const float alpha = alpha_s[lc];
+      const int idx = 9 * c + a;
+      d.vx[idx] += alpha * d.vp[idx];
+      r = d.vr[idx] - alpha * d.vq[idx];
+      d.vr[idx] = r;
+    }
+  }
+  if (lc < UPD_CAMS) rs[lc][a] = r;
+  __syncthreads();
+  if (live) {
+    const float* mi = d.minv + 81 * (size_t)c + 9 * a;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) z += mi[j] * rs[lc][j];
+    d.vz[9 * c + a] = z;
+  }
+  if (lc < UPD_CAMS) {
+    prz[lc][a] = r * z;
+    prr[lc][a] = r * r;
+  }
+  __syncthreads();
+  if (live && a == 0) {
+    double rz = 0.0, rr = 0.0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      rz += (double)prz[lc][j];
+      rr += (double)prr[lc][j];
+    }
+    d.cam_part2[c] = rz;
+    d.cam_part3[c] = rr;
+  }
+}
+
+// One workgroup: per problem, breakdown test on p^T q, iteration count,
+// convergence |r| <= tol |r0| (unpreconditioned), beta = rz_new / rz.
+__global__ __launch_bounds__(WG) void k_pcg_scalars(Dev d) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int p = w; p < d.P; p += WG / 64) {
+    if (!d.active[p] || d.done[p]) continue;  // uniform over the wavefront
+    double pq, rz, rr;
+    problem_sum3(d, d.cam_part, d.cam_part2, d.cam_part3, p, lane, pq, rz, rr);
+    if (lane == 0) {
+      if (!(pq > 0.0) || !isfinite(pq)) {
+        d.done[p] = 1;
+        d.pstatus[p] = 2;  // breakdown: x kept (alpha was 0)
+      } else {
+        d.iters[p] += 1;
+        d.rr[p] = rr;
+        const double tol = (double)d.pcg_tol;
+        if (!isfinite(rr) || !isfinite(rz)) {
+          d.done[p] = 1;
+          d.pstatus[p] = 2;
+        } else if (rr <= tol * tol * d.rr0[p]) {
+          d.done[p] = 1;
+          d.pstatus[p] = 0;
+        } else {
+          d.beta[p] = rz / d.rz[p];
+          d.rz[p] = rz;
+        }
+      }
+    }
+  }
 }
 
 // ----------------------------------------------------- back-substitution
@@ -1254,16 +1327,17 @@ hipError_t launch_cam_linearize(const Dev& d, const Launch& L, bool jac, bool us
 
 hipError_t launch_prob_sum(const Dev& d, const Launch& L, const double* vals, const int32_t* off, double* out,
                            const uint8_t* mask) {
-  hipLaunchKernelGGL(k_prob_sum, dim3(d.P), dim3(64), 0, L.stream, vals, off, out, mask);
+  hipLaunchKernelGGL(k_prob_sum, dim3(d.P), dim3(SUM_THREADS), 0, L.stream, vals, off, out, mask);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask) {
   const WorkClass* w = L.wc;
-  if (w[4].count) hipLaunchKernelGGL((k_marginalize<256, 512>), dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, mask);
-  if (w[3].count) hipLaunchKernelGGL((k_marginalize<256, 113>), dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi, mask);
-  if (w[2].count) hipLaunchKernelGGL((k_marginalize<64, 28>), dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi, mask);
+  if (w[5].count) hipLaunchKernelGGL((k_marginalize<256, 512>), dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi, mask);
+  if (w[4].count) hipLaunchKernelGGL((k_marginalize<256, 113>), dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, mask);
+  if (w[3].count) hipLaunchKernelGGL((k_marginalize<64, 28>), dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi, mask);
+  if (w[2].count) hipLaunchKernelGGL((k_marginalize<32, 14>), dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi, mask);
   if (w[1].count) hipLaunchKernelGGL((k_marginalize<16, 7>), dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi, mask);
   if (w[0].count) hipLaunchKernelGGL((k_marginalize<8, 3>), dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi, mask);
   LAUNCH_CHECK();
@@ -1272,9 +1346,10 @@ hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask
 
 hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
   const WorkClass* w = L.wc;
+  if (w[5].count) hipLaunchKernelGGL(k_damp<256>, dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi, mask);
   if (w[4].count) hipLaunchKernelGGL(k_damp<256>, dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, mask);
-  if (w[3].count) hipLaunchKernelGGL(k_damp<256>, dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi, mask);
-  if (w[2].count) hipLaunchKernelGGL(k_damp<64>, dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi, mask);
+  if (w[3].count) hipLaunchKernelGGL(k_damp<64>, dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi, mask);
+  if (w[2].count) hipLaunchKernelGGL(k_damp<32>, dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi, mask);
   if (w[1].count) hipLaunchKernelGGL(k_damp<16>, dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi, mask);
   if (w[0].count) hipLaunchKernelGGL(k_damp<8>, dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi, mask);
   LAUNCH_CHECK();
@@ -1283,9 +1358,10 @@ hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
 
 hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
   const WorkClass* w = L.wc;
+  if (w[5].count) hipLaunchKernelGGL(k_precond_obs<256>, dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi);
   if (w[4].count) hipLaunchKernelGGL(k_precond_obs<256>, dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi);
-  if (w[3].count) hipLaunchKernelGGL(k_precond_obs<256>, dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi);
-  if (w[2].count) hipLaunchKernelGGL(k_precond_obs<64>, dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi);
+  if (w[3].count) hipLaunchKernelGGL(k_precond_obs<64>, dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi);
+  if (w[2].count) hipLaunchKernelGGL(k_precond_obs<32>, dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi);
   if (w[1].count) hipLaunchKernelGGL(k_precond_obs<16>, dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi);
   if (w[0].count) hipLaunchKernelGGL(k_precond_obs<8>, dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi);
   LAUNCH_CHECK();
@@ -1297,9 +1373,9 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
 template <bool FOLD>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
   const WorkClass* w = L.wc;
-  if (w[4].count) hipLaunchKernelGGL(k_matvec_huge<FOLD>, dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, v);
-  const int n = w[3].count + w[2].count + w[1].count + w[0].count;
-  if (n) hipLaunchKernelGGL(k_matvec<FOLD>, dim3(n), dim3(WG), 0, L.stream, d, w[3].first_wi, v);
+  if (w[5].count) hipLaunchKernelGGL(k_matvec_huge<FOLD>, dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi, v);
+  const int n = w[4].count + w[3].count + w[2].count + w[1].count + w[0].count;
+  if (n) hipLaunchKernelGGL(k_matvec<FOLD>, dim3(n), dim3(WG), 0, L.stream, d, w[4].first_wi, v);
   LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1307,15 +1383,19 @@ static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
 hipError_t launch_pcg_init(const Dev& d, const Launch& L) {
   hipLaunchKernelGGL(k_pcg_init, dim3(nblocks(d.NC, WG)), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_pcg_init_scalars, dim3(1), dim3(WG), 0, L.stream, d);
+  LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_matvec(const Dev& d, const Launch& L) { return launch_matvec<true>(d, L, nullptr); }
 
 hipError_t launch_pcg_vector(const Dev& d, const Launch& L) {
-  hipLaunchKernelGGL(k_pcg_reduce, dim3(nblocks(d.NC, 4)), dim3(WG), 0, L.stream, d);
+  hipLaunchKernelGGL(k_pcg_q, dim3(d.NC), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(d.NC, WG)), dim3(WG), 0, L.stream, d);
+  hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(d.NC, UPD_CAMS)), dim3(UPD_THREADS), 0, L.stream, d);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1328,9 +1408,10 @@ hipError_t launch_pcg_iteration(const Dev& d, const Launch& L) {
 
 hipError_t launch_backsub(const Dev& d, const Launch& L) {
   const WorkClass* w = L.wc;
-  if (w[4].count) hipLaunchKernelGGL((k_backsub<256, 5>), dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi);
-  if (w[3].count) hipLaunchKernelGGL((k_backsub<256, 1>), dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi);
-  if (w[2].count) hipLaunchKernelGGL((k_backsub<64, 1>), dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi);
+  if (w[5].count) hipLaunchKernelGGL((k_backsub<256, 5>), dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi);
+  if (w[4].count) hipLaunchKernelGGL((k_backsub<256, 1>), dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi);
+  if (w[3].count) hipLaunchKernelGGL((k_backsub<64, 1>), dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi);
+  if (w[2].count) hipLaunchKernelGGL((k_backsub<32, 1>), dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi);
   if (w[1].count) hipLaunchKernelGGL((k_backsub<16, 1>), dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi);
   if (w[0].count) hipLaunchKernelGGL((k_backsub<8, 1>), dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi);
   LAUNCH_CHECK();

@@ -35,10 +35,10 @@ def k_mix_sampler(ks):
 
 # observation counts that exercise every landmark size class of the kernels,
 # including both ends of each class range
-CLASS_EDGES = [2, 3, 4, 7, 8, 28, 29, 60, 113, 114, 150]
+CLASS_EDGES = [2, 3, 4, 7, 8, 14, 15, 28, 29, 60, 113, 114, 150]
 
 
-def mixed_problem(seed: int = 5, n_cams: int = 160, n_points: int = 220) -> Problem:
+def mixed_problem(seed: int = 5, n_cams: int = 160, n_points: int = 260) -> Problem:
     rng = np.random.default_rng(seed)
     return make_ring_problem(rng, n_cams, n_points, k_mix_sampler(CLASS_EDGES), name="mixed")
 

@@ -86,7 +86,11 @@ def test_landmark_block_invariants(case, lam):
         B = rows[:, :9 * k].astype(np.float64) * s[None, :]
         rho = rows[:, 9 * k + 3].astype(np.float64)
         eH = np.linalg.norm(B.T @ B - H) / max(np.linalg.norm(H), 1e-30)
-        eb = np.linalg.norm(B.T @ rho - b) / max(np.linalg.norm(b), 1e-30)
+        # Q2^T r can be orders of magnitude smaller than r (the landmark explains almost all of its
+        # residual); an FP32 orthogonal transform leaves it an absolute error of a few eps32 |r|
+        # (backward stability), so the right-hand side term gets 1e-4 |b| plus 64 eps32 |J_p| |r|
+        tol_b = 1e-4 * np.linalg.norm(b) + 64 * 2.0 ** -24 * np.linalg.norm(Jp, 2) * np.linalg.norm(r)
+        eb = 1e-4 * np.linalg.norm(B.T @ rho - b) / tol_b  # <= 1e-4 when within tolerance
         worst = max(worst, eH, eb)
         # the landmark columns of the B rows are exactly zero (Q2^T J_l = 0) by construction;
         # the top rows carry R1 with R1^T R1 = J_l^T J_l (scaled)
