@@ -43,6 +43,7 @@ struct HostData {
   std::vector<int32_t> cam_obs_off, cam_obs_idx, cam_prob, lm_prob, prob_cam_off, prob_lm_off;
   std::vector<int32_t> slot_lm, slot_k, slot_obs0, slot_prob, lm_slot;
   std::vector<int64_t> slot_boff, slot_toff;
+  std::vector<int32_t> slot_zoff, cam_zpos;
   std::vector<int32_t> wi_first, wi_count;
   WorkClass wc[NUM_CLASSES];
   int64_t poolB = 0, poolT = 0;
@@ -60,6 +61,8 @@ struct sqrtba_ctx {
   sqrtba_options opt;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t side = nullptr;  // side stream for the largest landmark blocks
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device = 0;
   std::string err;
   HostData h;
@@ -276,7 +279,8 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
   nb.slot_boff.resize(nb.NS);
   nb.slot_toff.resize(nb.NS);
   nb.lm_slot.assign(h.NL, -1);
-  int64_t ob = 0, ot = 0;
+  nb.slot_zoff.resize(nb.NS);
+  int64_t ob = 0, ot = 0, oz = 0;
   for (int64_t s = 0; s < nb.NS; ++s) {
     const int32_t l = act[s];
     const int64_t k = count[l];
@@ -287,8 +291,20 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
     nb.slot_toff[s] = ot;
     nb.lm_slot[l] = (int32_t)s;
     const int64_t W = width_of_h(k);
+    nb.slot_zoff[s] = (int32_t)oz;
     ob += 2 * k * W;
     ot += 3 * W;
+    oz += W;
+  }
+  if (oz > 54 * nb.NO || oz > INT32_MAX) return fail(c, SQRTBA_E_UNSUPPORTED, "product output area too large");
+  // offsets of each camera's observation outputs, in camera order
+  {
+    std::vector<int32_t> zpos_of_obs(nb.NO);
+    for (int64_t sl = 0; sl < nb.NS; ++sl)
+      for (int64_t o = 0; o < nb.slot_k[sl]; ++o)
+        zpos_of_obs[nb.slot_obs0[sl] + o] = nb.slot_zoff[sl] + (int32_t)(9 * o);
+    nb.cam_zpos.resize(nb.NO);
+    for (int64_t q = 0; q < nb.NO; ++q) nb.cam_zpos[q] = zpos_of_obs[nb.cam_obs_idx[q]];
   }
   nb.poolB = ob;
   nb.poolT = ot;
@@ -341,6 +357,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
   uint64_t o_ocam = f32(NO), o_olm = f32(NO), o_ouv = f32(2 * NO), o_coo = f32(NC + 1), o_coi = f32(NO);
   uint64_t o_cpr = f32(NC), o_lpr = f32(NL), o_pco = f32(P + 1), o_plo = f32(P + 1);
   uint64_t o_slm = f32(NS), o_sk = f32(NS), o_so = f32(NS), o_sp = f32(NS), o_sb = f64(NS), o_st = f64(NS);
+  uint64_t o_sz = f32(NS), o_czp = f32(NO);
   uint64_t o_lms = f32(NL), o_wf = f32(NW), o_wc = f32(NW);
   uint64_t o_pB = f32(h.poolB), o_pT = f32(h.poolT), o_lmd = f32(NS * LMD_STRIDE), o_rho = f32(2 * NO);
   uint64_t o_sc = f32(9 * NC);
@@ -363,6 +380,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
     t.prob_cam_off = at<int32_t>(base, o_pco); t.prob_lm_off = at<int32_t>(base, o_plo);
     t.slot_lm = at<int32_t>(base, o_slm); t.slot_k = at<int32_t>(base, o_sk); t.slot_obs0 = at<int32_t>(base, o_so);
     t.slot_prob = at<int32_t>(base, o_sp); t.slot_boff = at<int64_t>(base, o_sb); t.slot_toff = at<int64_t>(base, o_st);
+    t.slot_zoff = at<int32_t>(base, o_sz); t.cam_zpos = at<int32_t>(base, o_czp);
     t.lm_slot = at<int32_t>(base, o_lms); t.wi_first = at<int32_t>(base, o_wf); t.wi_count = at<int32_t>(base, o_wc);
     t.poolB = at<float>(base, o_pB); t.poolT = at<float>(base, o_pT); t.lmd = at<float>(base, o_lmd);
     t.rhoB = at<float>(base, o_rho); t.s_cam = at<float>(base, o_sc);
@@ -490,6 +508,8 @@ int upload(sqrtba_ctx* c) {
   TRY(upload_vec(c, d.slot_prob, h.slot_prob));
   TRY(upload_vec(c, d.slot_boff, h.slot_boff));
   TRY(upload_vec(c, d.slot_toff, h.slot_toff));
+  TRY(upload_vec(c, d.slot_zoff, h.slot_zoff));
+  TRY(upload_vec(c, d.cam_zpos, h.cam_zpos));
   TRY(upload_vec(c, d.lm_slot, h.lm_slot));
   TRY(upload_vec(c, d.wi_first, h.wi_first));
   TRY(upload_vec(c, d.wi_count, h.wi_count));
@@ -498,6 +518,14 @@ int upload(sqrtba_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->L.stream = c->stream;
   for (int i = 0; i < NUM_CLASSES; ++i) c->L.wc[i] = h.wc[i];
+  if (!c->side) {
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
+  c->L.side = c->side;
+  c->L.fork = c->ev_fork;
+  c->L.join = c->ev_join;
   const size_t need = (size_t)h.P * 64 + 64;
   if (c->pinned_bytes < need) {
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -930,6 +958,12 @@ void sqrtba_destroy(sqrtba_ctx* c) {
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
   release_arena(c);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

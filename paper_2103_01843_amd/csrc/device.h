@@ -56,6 +56,8 @@ struct Dev {
   int32_t* slot_prob;
   int64_t* slot_boff;  // float offset of the B rows (2k x W) in poolB
   int64_t* slot_toff;  // float offset of the undamped top rows (3 x W) in poolT
+  int32_t* slot_zoff;  // float offset of the landmark's W product outputs in obsbuf (16-byte aligned)
+  int32_t* cam_zpos;   // NO: obsbuf offset of the outputs of each camera's observations (camera order)
   int32_t* lm_slot;    // NL, -1 when inactive
   // work items: per class, a list of (first slot, count)
   int32_t* wi_first;
@@ -73,7 +75,8 @@ struct Dev {
   float* vq;
   float* vb;      // right-hand side b~
   float* minv;    // NC * 81 inverse preconditioner blocks
-  float* obsbuf;  // NO * 54: per-observation partial products (the matvec uses the first 9 NO)
+  float* obsbuf;  // NO * 54 floats: per-observation preconditioner terms; the product outputs
+                  // reuse it in per-landmark aligned regions (slot_zoff)
   float* dxl;     // NL * 3, unscaled landmark increment
   double* cam_part;  // NC, per-camera partial sums
   double* cam_part2; // NC
@@ -106,6 +109,8 @@ struct WorkClass {
 
 struct Launch {
   hipStream_t stream;
+  hipStream_t side;   // second stream for the largest landmarks (may be null)
+  hipEvent_t fork, join;
   WorkClass wc[NUM_CLASSES];
 };
 

@@ -703,15 +703,11 @@ __device__ __forceinline__ float4 gather_cols(const Dev& d, const float* __restr
 
 __device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 
-// Store the 4 output columns of column group g: the landmark's 9k outputs are
-// contiguous (observation-major, 9 per observation) at obsbuf[9 obs0].
-__device__ __forceinline__ void store_cols(const Dev& d, int obs0, int k, int g, float4 z) {
-  float* zo = d.obsbuf + 9 * (size_t)obs0;
-  const int c = 4 * g;
-  if (c + 0 < 9 * k) zo[c + 0] = z.x;
-  if (c + 1 < 9 * k) zo[c + 1] = z.y;
-  if (c + 2 < 9 * k) zo[c + 2] = z.z;
-  if (c + 3 < 9 * k) zo[c + 3] = z.w;
+// Store the outputs of column group g: every landmark owns a 16-byte aligned
+// region of W floats at obsbuf[slot_zoff] (its 9k outputs, observation-major,
+// then padding), written as whole float4s so no cache line is partly written.
+__device__ __forceinline__ void store_cols(const Dev& d, int slot, int g, float4 z) {
+  reinterpret_cast<float4*>(d.obsbuf + d.slot_zoff[slot])[g] = z;
 }
 
 // Matrix-free product for teams of <= 64 lanes: one float4 column group per
@@ -758,7 +754,7 @@ __device__ __forceinline__ void matvec_small(const Dev& d, int slot, int lane, c
     z.z += y0 * b0.z + y1 * b1.z;
     z.w += y0 * b0.w + y1 * b1.w;
   }
-  if (on) store_cols(d, obs0, k, g, z);
+  if (on) store_cols(d, slot, g, z);
 }
 
 template <int TEAM, bool FOLD>
@@ -821,7 +817,7 @@ __device__ __forceinline__ void matvec_large_wi(const Dev& d, int wi, const floa
       const float4 s = make_float4((a.x + b2.x) + (c.x + e.x), (a.y + b2.y) + (c.y + e.y),
                                    (a.z + b2.z) + (c.z + e.z), (a.w + b2.w) + (c.w + e.w));
       const int g = lane + 64 * j;
-      if (g < G) store_cols(d, obs0, k, g, s);
+      if (g < G) store_cols(d, slot, g, s);
     }
     __syncthreads();
   }
@@ -953,7 +949,7 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
   for (int a = 0; a < 9; ++a) acc[a] = 0.f;
   const int b = d.cam_obs_off[c], e = d.cam_obs_off[c + 1];
   for (int i = b + (int)threadIdx.x; i < e; i += WG) {
-    const float* src = d.obsbuf + 9 * (size_t)d.cam_obs_idx[i];
+    const float* src = d.obsbuf + d.cam_zpos[i];
 #pragma unroll
     for (int a = 0; a < 9; ++a) acc[a] += src[a];
   }
@@ -1286,7 +1282,7 @@ __global__ __launch_bounds__(64) void k_cam_gather_product(Dev d, const float* v
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = 0.f;
   for (int i = d.cam_obs_off[c] + lane; i < d.cam_obs_off[c + 1]; i += 64) {
-    const float* src = d.obsbuf + (size_t)d.cam_obs_idx[i] * 9;
+    const float* src = d.obsbuf + d.cam_zpos[i];
 #pragma unroll
     for (int a = 0; a < 9; ++a) acc[a] += src[a];
   }
@@ -1370,13 +1366,30 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
   return hipSuccess;
 }
 
+// The landmarks with k > 113 (few, each a long stream for one workgroup) run
+// on a side stream concurrently with the main product, forked from and joined
+// back into the context stream by events (also inside captured graphs).
 template <bool FOLD>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
   const WorkClass* w = L.wc;
-  if (w[5].count) hipLaunchKernelGGL(k_matvec_huge<FOLD>, dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi, v);
+  const bool fork = w[5].count && L.side && L.fork && L.join;
+  if (fork) {
+    hipError_t e = hipEventRecord(L.fork, L.stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(L.side, L.fork, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_matvec_huge<FOLD>, dim3(w[5].count), dim3(WG), 0, L.side, d, w[5].first_wi, v);
+    LAUNCH_CHECK();
+  } else if (w[5].count) {
+    hipLaunchKernelGGL(k_matvec_huge<FOLD>, dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi, v);
+  }
   const int n = w[4].count + w[3].count + w[2].count + w[1].count + w[0].count;
   if (n) hipLaunchKernelGGL(k_matvec<FOLD>, dim3(n), dim3(WG), 0, L.stream, d, w[4].first_wi, v);
   LAUNCH_CHECK();
+  if (fork) {
+    hipError_t e = hipEventRecord(L.join, L.side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(L.stream, L.join, 0);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
