@@ -248,6 +248,64 @@ int32_t sqrtba_debug_solution(sqrtba_ctx* ctx, float* dxp_scaled, float* dxl);
 /* Replace the scaled pose increment (for testing back-substitution). */
 int32_t sqrtba_debug_set_pose_increment(sqrtba_ctx* ctx, const float* dxp_scaled);
 
+/* ---- learned block preconditioner (the project's extension; not in the paper) ----
+ *
+ * Per camera, an MLP 64 -> 128 -> 128 -> 81 (tanh; bfloat16 weights, FP32
+ * accumulation) maps 64 features of the damped 9x9 block-Jacobi block
+ * P = L L^T (log diagonal, correlations, log(lambda / P_aa), log lambda, the
+ * camera's observation and covisibility counts, mean and max log k, log of the
+ * mean diagonal) to E; the inverse block used by PCG is M^-1 = C C^T with
+ * C = L^-T (I + 0.1 tanh(tril E)), symmetric positive definite by
+ * construction, and exactly P^-1 when E = 0.  Parameters are one FP32 array
+ * [W1 (64x128), b1, W2 (128x128), b2, W3 (128x81), b3], row-major [in][out].
+ * Training minimizes the mean over traced PCG pairs (p, q = A p) and cameras i
+ * of |M_i^-1 q_i - p_i|^2 / |p_i|^2 with Adam, on the GPU. */
+
+/* Number of network parameters (35281). */
+int32_t sqrtba_mlp_num_params(void);
+
+/* Initialize the network (Xavier-uniform hidden layers, zero output layer:
+ * block-Jacobi behaviour) from a seed; resets the optimizer. */
+int32_t sqrtba_mlp_init(sqrtba_ctx* ctx, uint64_t seed);
+
+/* Set / get the FP32 parameters (host arrays of sqrtba_mlp_num_params()). */
+int32_t sqrtba_mlp_set_params(sqrtba_ctx* ctx, const float* params);
+int32_t sqrtba_mlp_get_params(sqrtba_ctx* ctx, float* params);
+
+/* Preconditioner of subsequent solves: 0 = block-Jacobi (default), 1 = learned.
+ * In learned mode a problem whose PCG does not reach the tolerance within 1.5x
+ * the iterations of its last block-Jacobi solve (or breaks down) is solved again
+ * from scratch with block-Jacobi, so the tolerance and the result of the solve
+ * are those of the plain method. */
+int32_t sqrtba_set_preconditioner(sqrtba_ctx* ctx, int32_t mode);
+
+/* Record PCG traces for training: features and factors of up to max_solves
+ * solves and (p, A p) of their first iters_per_solve iterations (device
+ * memory; (0, 0) frees it).  Tracing runs PCG without graph capture. */
+int32_t sqrtba_pcg_trace(sqrtba_ctx* ctx, int32_t max_solves, int32_t iters_per_solve);
+int32_t sqrtba_trace_size(const sqrtba_ctx* ctx, int32_t* n_solves, int32_t* n_records);
+
+/* steps Adam steps (learning rate lr) on minibatches of `batch` (record, camera)
+ * samples drawn uniformly from the traces with a seeded generator; losses[steps]
+ * (may be NULL) receives each minibatch's mean loss before its step. */
+int32_t sqrtba_mlp_train(sqrtba_ctx* ctx, int32_t steps, int32_t batch, double lr, uint64_t seed, double* losses);
+
+/* Loss and gradient at the current parameters for n explicit samples:
+ * feats[n x 64], lfac[n x 45] (lower Cholesky factors, packed rows), p[n x 9],
+ * q[n x 9]; *loss is the mean loss, grad[num_params] its gradient (may be NULL). */
+int32_t sqrtba_mlp_eval(sqrtba_ctx* ctx, int32_t n, const float* feats, const float* lfac, const float* p,
+                        const float* q, double* loss, float* grad);
+
+/* Counters of learned-mode solves, fallbacks to block-Jacobi and the PCG
+ * iterations those fallbacks discarded. */
+int32_t sqrtba_learned_stats(const sqrtba_ctx* ctx, int64_t* learned_solves, int64_t* fallbacks,
+                             int64_t* wasted_iters);
+
+/* Inspection: per-camera features [n_cams x 64] and factors [n_cams x 45] of the
+ * damped blocks, and the learned inverse blocks [n_cams x 81].  Need damp. */
+int32_t sqrtba_debug_features(sqrtba_ctx* ctx, float* feats, float* lfac);
+int32_t sqrtba_debug_learned_precond(sqrtba_ctx* ctx, float* minv);
+
 /* ---- measurement and state snapshots ---- */
 
 /* Stages timed by the profiler (HIP events on the context stream). */

@@ -12,11 +12,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <random>
 #include <string>
 #include <vector>
 
 #include "../../include/sqrtba.h"
 #include "device.h"
+#include "learned.h"
 
 using namespace sqrtba;
 
@@ -44,6 +46,7 @@ struct HostData {
   std::vector<int32_t> slot_lm, slot_k, slot_obs0, slot_prob, lm_slot;
   std::vector<int64_t> slot_boff, slot_toff;
   std::vector<int32_t> slot_zoff, cam_zpos;
+  std::vector<float> cam_stats;  // NC * 4 features of the camera's observation graph
   std::vector<int32_t> wi_first, wi_count;
   WorkClass wc[NUM_CLASSES];
   int64_t poolB = 0, poolT = 0;
@@ -98,6 +101,27 @@ struct sqrtba_ctx {
   bool snapshot = false;
   // LM history
   std::vector<std::vector<sqrtba_lm_record>> history;
+  // learned preconditioner
+  struct Learned {
+    bool alloc = false;
+    float* w32 = nullptr;
+    uint16_t* wbf = nullptr;
+    float *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
+    float* part = nullptr;
+    double* loss_part = nullptr;
+    int part_tiles = 0;
+    int adam_step = 0;
+    int mode = 0;  // 0 block-Jacobi, 1 learned with block-Jacobi fallback
+    // trace store
+    int max_solves = 0, iters_per_solve = 0, n_solves = 0, n_records = 0, cur_solve = -1, cur_iter = 0;
+    float *t_feat = nullptr, *t_lfac = nullptr, *t_p = nullptr, *t_q = nullptr;
+    int32_t* rec_solve = nullptr;
+    std::vector<int32_t> h_rec_solve;
+    int32_t *s_rec = nullptr, *s_cam = nullptr;
+    int s_cap = 0;
+    std::vector<int32_t> last_plain_iters;
+    int64_t learned_solves = 0, fallbacks = 0, wasted_iters = 0;
+  } ln;
 };
 
 namespace {
@@ -325,6 +349,47 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
     }
     nb.wc[cl].count = (int)nb.wi_first.size() - nb.wc[cl].first_wi;
   }
+  // camera statistics for the learned preconditioner: observations, covisible
+  // cameras (bitsets per problem), mean and max log k over the camera's landmarks
+  nb.cam_stats.assign(4 * h.NC, 0.f);
+  for (int32_t p = 0; p < h.P; ++p) {
+    const int64_t c0 = h.cam_off[p], nc = h.cam_off[p + 1] - c0, words = (nc + 63) / 64;
+    if (nc == 0) continue;
+    std::vector<uint64_t> bits(nc * words, 0), lm(words, 0);
+    for (int64_t l = h.pt_off[p]; l < h.pt_off[p + 1]; ++l) {
+      if (!nb.lm_active[l]) continue;
+      const int64_t b = nb.lm_off[l], e = nb.lm_off[l + 1];
+      int64_t wlo = words, whi = -1;
+      for (int64_t o = b; o < e; ++o) {
+        const int64_t cc = nb.ocam[o] - c0;
+        lm[cc >> 6] |= uint64_t(1) << (cc & 63);
+        wlo = std::min(wlo, cc >> 6);
+        whi = std::max(whi, cc >> 6);
+      }
+      for (int64_t o = b; o < e; ++o) {
+        uint64_t* row = bits.data() + (nb.ocam[o] - c0) * words;
+        for (int64_t w = wlo; w <= whi; ++w) row[w] |= lm[w];
+      }
+      for (int64_t w = wlo; w <= whi; ++w) lm[w] = 0;
+    }
+    for (int64_t cc = 0; cc < nc; ++cc) {
+      const int64_t cam = c0 + cc;
+      int64_t cov = 0;
+      for (int64_t w = 0; w < words; ++w) cov += __builtin_popcountll(bits[cc * words + w]);
+      const int64_t nob = nb.cam_obs_off[cam + 1] - nb.cam_obs_off[cam];
+      double sk = 0, mk = 0;
+      for (int64_t i = nb.cam_obs_off[cam]; i < nb.cam_obs_off[cam + 1]; ++i) {
+        const int32_t l = nb.olm[nb.cam_obs_idx[i]];
+        const double lk = std::log((double)count[l]);
+        sk += lk;
+        mk = std::max(mk, lk);
+      }
+      nb.cam_stats[4 * cam + 0] = (float)std::log1p((double)nob);
+      nb.cam_stats[4 * cam + 1] = (float)std::log1p((double)std::max<int64_t>(cov - 1, 0));
+      nb.cam_stats[4 * cam + 2] = nob ? (float)(sk / nob) : 0.f;
+      nb.cam_stats[4 * cam + 3] = (float)mk;
+    }
+  }
   nb.obs_set = true;
   h = std::move(nb);
   return SQRTBA_OK;
@@ -370,6 +435,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
   uint64_t o_it = f32(P), o_dn = f32(P), o_ps = f32(P), o_act = L.take(P), o_flag = L.take(P);
   uint64_t o_cf = f32(4);
   uint64_t o_csnap = f32(16 * NC), o_psnap = f32(4 * NL);
+  uint64_t o_feat = f32(64 * NC), o_lfac = f32(45 * NC), o_cst = f32(4 * NC);
   if (base && d) {
     t.P = (int32_t)P; t.NC = (int32_t)NC; t.NL = (int32_t)NL; t.NS = (int32_t)NS; t.NO = (int32_t)NO;
     t.cam = at<float>(base, o_cam); t.cam_new = at<float>(base, o_camn);
@@ -396,6 +462,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
     t.active = at<uint8_t>(base, o_act); t.flag = at<uint8_t>(base, o_flag);
     t.chol_fail = at<int32_t>(base, o_cf);
     t.cam_snap = at<float>(base, o_csnap); t.pts_snap = at<float4>(base, o_psnap);
+    t.feats = at<float>(base, o_feat); t.lfac = at<float>(base, o_lfac); t.cam_stats = at<float>(base, o_cst);
     *d = t;
   }
   return L.total;
@@ -513,6 +580,7 @@ int upload(sqrtba_ctx* c) {
   TRY(upload_vec(c, d.lm_slot, h.lm_slot));
   TRY(upload_vec(c, d.wi_first, h.wi_first));
   TRY(upload_vec(c, d.wi_count, h.wi_count));
+  TRY(upload_vec(c, d.cam_stats, h.cam_stats));
   c->active.assign(h.P, 1);
   TRY(upload_vec(c, d.active, c->active));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -691,30 +759,98 @@ int run_pcg_chunk(sqrtba_ctx* c, int n, std::vector<std::pair<hipEvent_t, hipEve
   return SQRTBA_OK;
 }
 
-int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
-  if (!c->damped) return fail(c, SQRTBA_E_STATE, "solve needs damp");
+LearnDev learn_dev(sqrtba_ctx* c) {
+  LearnDev m{};
+  m.w32 = c->ln.w32;
+  m.wbf = c->ln.wbf;
+  m.adam_m = c->ln.adam_m;
+  m.adam_v = c->ln.adam_v;
+  m.feats = c->d.feats;
+  m.lfac = c->d.lfac;
+  return m;
+}
+
+int ensure_learned(sqrtba_ctx* c) {
+  auto& L = c->ln;
+  if (L.alloc) return SQRTBA_OK;
+  const size_t n = MLP_PARAMS;
+  HIP_TRY(c, hipMalloc(&L.w32, 4 * n));
+  HIP_TRY(c, hipMalloc(&L.wbf, 2 * n));
+  HIP_TRY(c, hipMalloc(&L.adam_m, 4 * n));
+  HIP_TRY(c, hipMalloc(&L.adam_v, 4 * n));
+  HIP_TRY(c, hipMalloc(&L.grad, 4 * n));
+  L.alloc = true;
+  return SQRTBA_OK;
+}
+
+// Xavier-uniform first two layers, zero biases and zero last layer: the initial
+// network reproduces plain block-Jacobi exactly.
+int init_params(sqrtba_ctx* c, uint64_t seed) {
+  TRY(ensure_learned(c));
+  std::vector<float> w(MLP_PARAMS, 0.f);
+  std::mt19937_64 rng(seed);
+  auto fill = [&](size_t off, int fin, int fout) {
+    const double lim = std::sqrt(6.0 / (fin + fout));
+    std::uniform_real_distribution<double> u(-lim, lim);
+    for (size_t i = 0; i < (size_t)fin * fout; ++i) w[off + i] = (float)u(rng);
+  };
+  fill(0, MLP_IN, MLP_HIDDEN);
+  fill((size_t)MLP_IN * MLP_HIDDEN + MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN);
+  HIP_TRY(c, hipMemcpyAsync(c->ln.w32, w.data(), 4 * w.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->ln.adam_m, 0, 4 * w.size(), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->ln.adam_v, 0, 4 * w.size(), c->stream));
+  LAUNCH(c, launch_to_bf16(learn_dev(c), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->ln.adam_step = 0;
+  return SQRTBA_OK;
+}
+
+// copy p and q of the iteration just launched into the trace store
+int trace_iteration(sqrtba_ctx* c) {
+  auto& L = c->ln;
+  if (L.cur_solve < 0 || L.cur_iter >= L.iters_per_solve) return SQRTBA_OK;
+  const size_t N = 9 * (size_t)c->h.NC;
+  const int r = L.n_records;
+  HIP_TRY(c, hipMemcpyAsync(L.t_p + N * r, c->d.vp, 4 * N, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(L.t_q + N * r, c->d.vq, 4 * N, hipMemcpyDeviceToDevice, c->stream));
+  L.h_rec_solve.push_back(L.cur_solve);
+  L.n_records++;
+  L.cur_iter++;
+  return SQRTBA_OK;
+}
+
+// PCG on the current minv blocks from x0 = 0, at most cap iterations.
+int run_pcg(sqrtba_ctx* c, int cap) {
   const int P = c->h.P;
-  TRY(timed(c, SQRTBA_STAGE_PRECOND, 0.0, active_blocks(c), [&]() {
-    LAUNCH(c, launch_precond_rhs(c->d, c->L));
-    LAUNCH(c, launch_pcg_init(c->d, c->L));
-    return (int)SQRTBA_OK;
-  }));
+  LAUNCH(c, launch_pcg_init(c->d, c->L));
   std::vector<int32_t> done(P);
   TRY(readback(c, c->d.done, done.data()));
-  flush_profile(c);
   auto all_done = [&]() {
     for (int p = 0; p < P; ++p)
       if (!done[p]) return false;
     return true;
   };
   int it = 0;
+  const bool tracing = c->ln.cur_solve >= 0;
   const int every = std::max(1, c->opt.pcg_check_every);
   std::vector<int32_t> its_before(P, 0), its_after(P, 0);
   std::vector<std::pair<hipEvent_t, hipEvent_t>> mv;
-  while (it < c->opt.pcg_max_iters && !all_done()) {
-    const int n = std::min(every, c->opt.pcg_max_iters - it);
+  while (it < cap && !all_done()) {
+    const int n = std::min(every, cap - it);
     mv.clear();
-    TRY(run_pcg_chunk(c, n, &mv));
+    if (tracing) {
+      for (int i = 0; i < n; ++i) {
+        hipEvent_t a = c->prof_on ? take_event(c) : nullptr, b = c->prof_on ? take_event(c) : nullptr;
+        if (a) HIP_TRY(c, hipEventRecord(a, c->stream));
+        LAUNCH(c, launch_matvec(c->d, c->L));
+        if (b) HIP_TRY(c, hipEventRecord(b, c->stream));
+        LAUNCH(c, launch_pcg_vector(c->d, c->L));
+        TRY(trace_iteration(c));
+        if (a) mv.push_back({a, b});
+      }
+    } else {
+      TRY(run_pcg_chunk(c, n, &mv));
+    }
     it += n;
     TRY(readback(c, c->d.done, done.data()));
     if (c->prof_on) {
@@ -748,13 +884,76 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
       its_before = its_after;
     }
   }
+  return SQRTBA_OK;
+}
+
+int precond_stage(sqrtba_ctx* c) {
+  return timed(c, SQRTBA_STAGE_PRECOND, 0.0, active_blocks(c), [&]() {
+    LAUNCH(c, launch_precond_rhs(c->d, c->L));
+    return (int)SQRTBA_OK;
+  });
+}
+
+int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
+  if (!c->damped) return fail(c, SQRTBA_E_STATE, "solve needs damp");
+  const int P = c->h.P;
+  auto& L = c->ln;
+  if ((int)L.last_plain_iters.size() != P) L.last_plain_iters.assign(P, -1);
+  TRY(precond_stage(c));
+  // trace store: features and factors of this solve
+  L.cur_solve = -1;
+  L.cur_iter = 0;
+  if (L.max_solves > 0 && L.n_solves < L.max_solves) {
+    const size_t NC = c->h.NC;
+    HIP_TRY(c, hipMemcpyAsync(L.t_feat + 64 * NC * L.n_solves, c->d.feats, 4 * 64 * NC, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(L.t_lfac + 45 * NC * L.n_solves, c->d.lfac, 4 * 45 * NC, hipMemcpyDeviceToDevice, c->stream));
+    L.cur_solve = L.n_solves++;
+  }
+  const bool learned = L.mode == 1 && L.alloc;
   std::vector<int32_t> its(P), st(P);
+  if (learned) {
+    LAUNCH(c, launch_mlp_precond(c->d, learn_dev(c), c->stream));
+    int cap = c->opt.pcg_max_iters;
+    bool have_all = true;
+    int mx = 0;
+    for (int p = 0; p < P; ++p)
+      if (c->active[p]) {
+        if (L.last_plain_iters[p] < 0) have_all = false;
+        mx = std::max(mx, L.last_plain_iters[p]);
+      }
+    if (have_all) cap = std::min(cap, std::max(1, (3 * mx + 1) / 2));
+    TRY(run_pcg(c, cap));
+    TRY(readback(c, c->d.iters, its.data()));
+    TRY(readback(c, c->d.pstatus, st.data()));
+    L.learned_solves++;
+    // fallback: problems the learned blocks did not bring to the tolerance
+    std::vector<uint8_t> fb(P, 0), keep = c->active;
+    bool any = false;
+    for (int p = 0; p < P; ++p)
+      if (c->active[p] && st[p] != SQRTBA_PCG_CONVERGED && st[p] != SQRTBA_PCG_ZERO_RHS) {
+        fb[p] = 1;
+        any = true;
+        L.fallbacks++;
+        L.wasted_iters += its[p];
+      }
+    if (any) {
+      TRY(set_active_mask(c, fb));
+      TRY(precond_stage(c));  // plain block-Jacobi blocks for these problems
+      TRY(run_pcg(c, c->opt.pcg_max_iters));
+      TRY(set_active_mask(c, keep));
+    }
+  } else {
+    TRY(run_pcg(c, c->opt.pcg_max_iters));
+  }
+  L.cur_solve = -1;
   std::vector<double> rr(P), rr0(P);
   TRY(readback(c, c->d.iters, its.data()));
   TRY(readback(c, c->d.pstatus, st.data()));
   TRY(readback(c, c->d.rr, rr.data()));
   TRY(readback(c, c->d.rr0, rr0.data()));
+  flush_profile(c);
   for (int p = 0; p < P; ++p) {
+    if (!learned && c->active[p]) L.last_plain_iters[p] = its[p];
     if (iters) iters[p] = its[p];
     if (status) status[p] = st[p];
     if (rel_res) rel_res[p] = rr0[p] > 0 ? std::sqrt(std::max(rr[p], 0.0) / rr0[p]) : 0.0;
@@ -956,6 +1155,13 @@ void sqrtba_destroy(sqrtba_ctx* c) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  {
+    auto& L = c->ln;
+    for (void* p : {(void*)L.w32, (void*)L.wbf, (void*)L.adam_m, (void*)L.adam_v, (void*)L.grad, (void*)L.part,
+                    (void*)L.loss_part, (void*)L.t_feat, (void*)L.t_lfac, (void*)L.t_p, (void*)L.t_q,
+                    (void*)L.rec_solve, (void*)L.s_rec, (void*)L.s_cam})
+      if (p) (void)hipFree(p);
+  }
   release_arena(c);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->side) {
@@ -1255,6 +1461,204 @@ int32_t sqrtba_debug_set_pose_increment(sqrtba_ctx* c, const float* dxp) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->solved = true;
   c->backsubbed = c->updated = false;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_mlp_num_params(void) { return MLP_PARAMS; }
+
+int32_t sqrtba_mlp_init(sqrtba_ctx* c, uint64_t seed) {
+  if (!c) return SQRTBA_E_INVALID;
+  return init_params(c, seed);
+}
+
+int32_t sqrtba_mlp_set_params(sqrtba_ctx* c, const float* params) {
+  if (!c || !params) return SQRTBA_E_INVALID;
+  for (int i = 0; i < MLP_PARAMS; ++i)
+    if (!std::isfinite(params[i])) return fail(c, SQRTBA_E_NONFINITE, "parameter %d is not finite", i);
+  TRY(ensure_learned(c));
+  HIP_TRY(c, hipMemcpyAsync(c->ln.w32, params, 4 * (size_t)MLP_PARAMS, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->ln.adam_m, 0, 4 * (size_t)MLP_PARAMS, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->ln.adam_v, 0, 4 * (size_t)MLP_PARAMS, c->stream));
+  LAUNCH(c, launch_to_bf16(learn_dev(c), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->ln.adam_step = 0;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_mlp_get_params(sqrtba_ctx* c, float* params) {
+  if (!c || !params) return SQRTBA_E_INVALID;
+  if (!c->ln.alloc) return fail(c, SQRTBA_E_STATE, "no network: call sqrtba_mlp_init or sqrtba_mlp_set_params");
+  HIP_TRY(c, hipMemcpyAsync(params, c->ln.w32, 4 * (size_t)MLP_PARAMS, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_set_preconditioner(sqrtba_ctx* c, int32_t mode) {
+  if (!c || (mode != 0 && mode != 1)) return SQRTBA_E_INVALID;
+  if (mode == 1 && !c->ln.alloc) return fail(c, SQRTBA_E_STATE, "no network: call sqrtba_mlp_init or sqrtba_mlp_set_params");
+  c->ln.mode = mode;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_pcg_trace(sqrtba_ctx* c, int32_t max_solves, int32_t iters_per_solve) {
+  if (!c || max_solves < 0 || iters_per_solve < 0) return SQRTBA_E_INVALID;
+  TRY(ensure_uploaded(c));
+  auto& L = c->ln;
+  for (void** p : {(void**)&L.t_feat, (void**)&L.t_lfac, (void**)&L.t_p, (void**)&L.t_q})
+    if (*p) {
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+  L.max_solves = L.iters_per_solve = L.n_solves = L.n_records = 0;
+  L.h_rec_solve.clear();
+  if (max_solves == 0 || iters_per_solve == 0) return SQRTBA_OK;
+  const size_t NC = c->h.NC, recs = (size_t)max_solves * iters_per_solve;
+  HIP_TRY(c, hipMalloc(&L.t_feat, 4 * 64 * NC * max_solves));
+  HIP_TRY(c, hipMalloc(&L.t_lfac, 4 * 45 * NC * max_solves));
+  HIP_TRY(c, hipMalloc(&L.t_p, 4 * 9 * NC * recs));
+  HIP_TRY(c, hipMalloc(&L.t_q, 4 * 9 * NC * recs));
+  L.max_solves = max_solves;
+  L.iters_per_solve = iters_per_solve;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_trace_size(const sqrtba_ctx* c, int32_t* n_solves, int32_t* n_records) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (n_solves) *n_solves = c->ln.n_solves;
+  if (n_records) *n_records = c->ln.n_records;
+  return SQRTBA_OK;
+}
+
+static int grow_training(sqrtba_ctx* c, int n) {
+  auto& L = c->ln;
+  const int tiles = mlp_tiles(n);
+  if (tiles > L.part_tiles) {
+    if (L.part) (void)hipFree(L.part);
+    if (L.loss_part) (void)hipFree(L.loss_part);
+    L.part = nullptr;
+    L.loss_part = nullptr;
+    HIP_TRY(c, hipMalloc(&L.part, 4 * (size_t)MLP_PARAMS * tiles));
+    HIP_TRY(c, hipMalloc(&L.loss_part, 8 * (size_t)tiles));
+    L.part_tiles = tiles;
+  }
+  if (n > L.s_cap) {
+    if (L.s_rec) (void)hipFree(L.s_rec);
+    if (L.s_cam) (void)hipFree(L.s_cam);
+    L.s_rec = L.s_cam = nullptr;
+    HIP_TRY(c, hipMalloc(&L.s_rec, 4 * (size_t)n));
+    HIP_TRY(c, hipMalloc(&L.s_cam, 4 * (size_t)n));
+    L.s_cap = n;
+  }
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_mlp_train(sqrtba_ctx* c, int32_t steps, int32_t batch, double lr, uint64_t seed, double* losses) {
+  if (!c || steps < 0 || batch <= 0 || !(lr > 0)) return SQRTBA_E_INVALID;
+  auto& L = c->ln;
+  if (!L.alloc) return fail(c, SQRTBA_E_STATE, "no network: call sqrtba_mlp_init or sqrtba_mlp_set_params");
+  if (L.n_records == 0) return fail(c, SQRTBA_E_STATE, "no traced PCG iterations: enable sqrtba_pcg_trace and solve");
+  TRY(grow_training(c, batch));
+  if (L.rec_solve) (void)hipFree(L.rec_solve);
+  L.rec_solve = nullptr;
+  HIP_TRY(c, hipMalloc(&L.rec_solve, 4 * (size_t)L.n_records));
+  HIP_TRY(c, hipMemcpyAsync(L.rec_solve, L.h_rec_solve.data(), 4 * (size_t)L.n_records, hipMemcpyHostToDevice, c->stream));
+  std::vector<int32_t> cams;
+  for (int64_t q = 0; q < c->h.NC; ++q)
+    if (c->h.cam_active[q]) cams.push_back((int32_t)q);
+  if (cams.empty()) return fail(c, SQRTBA_E_STATE, "no active camera");
+  std::mt19937_64 rng(seed);
+  std::uniform_int_distribution<int32_t> ur(0, L.n_records - 1), uc(0, (int32_t)cams.size() - 1);
+  std::vector<int32_t> hr(batch), hc(batch);
+  const int tiles = mlp_tiles(batch);
+  std::vector<double> lp(tiles);
+  SampleSrc src{};
+  src.mode = 1;
+  src.NC = (int)c->h.NC;
+  src.rec = L.s_rec;
+  src.cam = L.s_cam;
+  src.rec_solve = L.rec_solve;
+  src.t_feat = L.t_feat;
+  src.t_lfac = L.t_lfac;
+  src.t_p = L.t_p;
+  src.t_q = L.t_q;
+  for (int st = 0; st < steps; ++st) {
+    for (int i = 0; i < batch; ++i) {
+      hr[i] = ur(rng);
+      hc[i] = cams[uc(rng)];
+    }
+    HIP_TRY(c, hipMemcpyAsync(L.s_rec, hr.data(), 4 * (size_t)batch, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(L.s_cam, hc.data(), 4 * (size_t)batch, hipMemcpyHostToDevice, c->stream));
+    LAUNCH(c, launch_mlp_grad(learn_dev(c), src, batch, L.part, L.loss_part, L.grad, c->stream));
+    LAUNCH(c, launch_adam(learn_dev(c), L.grad, (float)lr, ++L.adam_step, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(lp.data(), L.loss_part, 8 * (size_t)tiles, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double tot = 0;
+    for (double v : lp) tot += v;
+    if (losses) losses[st] = tot / batch;
+  }
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_mlp_eval(sqrtba_ctx* c, int32_t n, const float* feats, const float* lfac, const float* p,
+                        const float* q, double* loss, float* grad) {
+  if (!c || n <= 0 || !feats || !lfac || !p || !q) return SQRTBA_E_INVALID;
+  auto& L = c->ln;
+  if (!L.alloc) return fail(c, SQRTBA_E_STATE, "no network: call sqrtba_mlp_init or sqrtba_mlp_set_params");
+  TRY(grow_training(c, n));
+  float* buf = nullptr;
+  HIP_TRY(c, hipMalloc(&buf, 4 * (size_t)n * (64 + 45 + 18)));
+  SampleSrc src{};
+  src.mode = 0;
+  src.a_feat = buf;
+  src.a_lfac = buf + 64 * (size_t)n;
+  src.a_p = buf + 109 * (size_t)n;
+  src.a_q = buf + 118 * (size_t)n;
+  hipError_t e = hipMemcpyAsync(buf, feats, 4 * 64 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(buf + 64 * (size_t)n, lfac, 4 * 45 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(buf + 109 * (size_t)n, p, 4 * 9 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(buf + 118 * (size_t)n, q, 4 * 9 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_mlp_grad(learn_dev(c), src, n, L.part, L.loss_part, L.grad, c->stream);
+  const int tiles = mlp_tiles(n);
+  std::vector<double> lp(tiles);
+  if (e == hipSuccess) e = hipMemcpyAsync(lp.data(), L.loss_part, 8 * (size_t)tiles, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && grad) e = hipMemcpyAsync(grad, L.grad, 4 * (size_t)MLP_PARAMS, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(c, SQRTBA_E_HIP, "mlp_eval: %s", hipGetErrorString(e));
+  if (loss) {
+    double tot = 0;
+    for (double v : lp) tot += v;
+    *loss = tot / n;
+  }
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_learned_stats(const sqrtba_ctx* c, int64_t* learned_solves, int64_t* fallbacks, int64_t* wasted_iters) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (learned_solves) *learned_solves = c->ln.learned_solves;
+  if (fallbacks) *fallbacks = c->ln.fallbacks;
+  if (wasted_iters) *wasted_iters = c->ln.wasted_iters;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_features(sqrtba_ctx* c, float* feats, float* lfac) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (!c->damped) return fail(c, SQRTBA_E_STATE, "features need damp");
+  LAUNCH(c, launch_precond_rhs(c->d, c->L));
+  if (feats) HIP_TRY(c, hipMemcpyAsync(feats, c->d.feats, 4 * 64 * (size_t)c->h.NC, hipMemcpyDeviceToHost, c->stream));
+  if (lfac) HIP_TRY(c, hipMemcpyAsync(lfac, c->d.lfac, 4 * 45 * (size_t)c->h.NC, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_debug_learned_precond(sqrtba_ctx* c, float* minv) {
+  if (!c || !minv) return SQRTBA_E_INVALID;
+  if (!c->damped) return fail(c, SQRTBA_E_STATE, "needs damp");
+  if (!c->ln.alloc) return fail(c, SQRTBA_E_STATE, "no network");
+  LAUNCH(c, launch_precond_rhs(c->d, c->L));
+  LAUNCH(c, launch_mlp_precond(c->d, learn_dev(c), c->stream));
+  HIP_TRY(c, hipMemcpyAsync(minv, c->d.minv, 4 * 81 * (size_t)c->h.NC, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return SQRTBA_OK;
 }
 

@@ -97,6 +97,9 @@ struct Dev {
   uint8_t* active;
   uint8_t* flag;     // generic per-problem mask (relinearize / accept)
   int32_t* chol_fail;  // count of preconditioner blocks that fell back to the diagonal
+  float* feats;        // NC * 64 learned-preconditioner features of the last preconditioner build
+  float* lfac;         // NC * 45 lower Cholesky factors of the damped blocks (packed rows)
+  float* cam_stats;    // NC * 4: log(1 + #obs), log(1 + #covisible cameras), mean and max log k
   float* cam_snap;     // saved state (save/restore)
   float4* pts_snap;
   float pcg_tol;

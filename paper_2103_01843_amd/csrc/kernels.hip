@@ -642,6 +642,32 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
     for (int i = 0; i < j; ++i) L[i][j] = 0.f;
   }
   float* mi = d.minv + 81 * (size_t)c;
+  // features of the block for the learned preconditioner, and its Cholesky
+  // factor (a failed factorization is replaced by the square root of the diagonal)
+  {
+    float* f = d.feats + 64 * (size_t)c;
+    float* lf = d.lfac + 45 * (size_t)c;
+    float tr = 0.f;
+    int e2 = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      f[a] = logf(P[a][a]);
+      f[45 + a] = logf(lam / P[a][a]);
+      tr += P[a][a];
+#pragma unroll
+      for (int q = a + 1; q < 9; ++q) f[9 + e2++] = P[a][q] * rsqrtf(P[a][a] * P[q][q]);
+    }
+    f[54] = logf(lam);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) f[55 + a] = d.cam_stats[4 * (size_t)c + a];
+    f[59] = logf(tr / 9.f);
+    f[60] = f[61] = f[62] = f[63] = 0.f;
+    int e3 = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+#pragma unroll
+      for (int q = 0; q <= a; ++q) lf[e3++] = ok ? L[a][q] : (a == q ? sqrtf(P[a][a]) : 0.f);
+  }
   if (!ok) {
     atomicAdd(d.chol_fail, 1);
 #pragma unroll

@@ -110,6 +110,18 @@ _SIGS = {
     "sqrtba_profile_get": (I32, [P, C.POINTER(Profile)]),
     "sqrtba_save_state": (I32, [P]),
     "sqrtba_restore_state": (I32, [P]),
+    "sqrtba_mlp_num_params": (I32, []),
+    "sqrtba_mlp_init": (I32, [P, U64]),
+    "sqrtba_mlp_set_params": (I32, [P, PF]),
+    "sqrtba_mlp_get_params": (I32, [P, PF]),
+    "sqrtba_set_preconditioner": (I32, [P, I32]),
+    "sqrtba_pcg_trace": (I32, [P, I32, I32]),
+    "sqrtba_trace_size": (I32, [P, PI32, PI32]),
+    "sqrtba_mlp_train": (I32, [P, I32, I32, C.c_double, U64, PD]),
+    "sqrtba_mlp_eval": (I32, [P, I32, PF, PF, PF, PF, PD, PF]),
+    "sqrtba_learned_stats": (I32, [P, PI64, PI64, PI64]),
+    "sqrtba_debug_features": (I32, [P, PF, PF]),
+    "sqrtba_debug_learned_precond": (I32, [P, PF]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -324,6 +336,62 @@ class Context:
     def get_landmarks(self) -> np.ndarray:
         out = np.zeros((self.n_points, 3), np.float32)
         self._check(lib().sqrtba_get_landmarks(self._h, _ptr(out, C.c_float)))
+        return out
+
+    # -- learned preconditioner
+    def mlp_init(self, seed: int = 0):
+        self._check(lib().sqrtba_mlp_init(self._h, seed))
+
+    def mlp_set_params(self, params):
+        a = _arr(params, np.float32)
+        if a.size != lib().sqrtba_mlp_num_params():
+            raise ValueError("wrong parameter count")
+        self._check(lib().sqrtba_mlp_set_params(self._h, _ptr(a, C.c_float)))
+
+    def mlp_get_params(self) -> np.ndarray:
+        out = np.zeros(lib().sqrtba_mlp_num_params(), np.float32)
+        self._check(lib().sqrtba_mlp_get_params(self._h, _ptr(out, C.c_float)))
+        return out
+
+    def set_preconditioner(self, mode: str):
+        self._check(lib().sqrtba_set_preconditioner(self._h, {"block_jacobi": 0, "learned": 1}[mode]))
+
+    def pcg_trace(self, max_solves: int, iters_per_solve: int):
+        self._check(lib().sqrtba_pcg_trace(self._h, max_solves, iters_per_solve))
+
+    def trace_size(self):
+        a, b = C.c_int32(), C.c_int32()
+        self._check(lib().sqrtba_trace_size(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def mlp_train(self, steps: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0) -> np.ndarray:
+        out = np.zeros(max(steps, 1))
+        self._check(lib().sqrtba_mlp_train(self._h, steps, batch, lr, seed, _ptr(out, C.c_double)))
+        return out[:steps]
+
+    def mlp_eval(self, feats, lfac, p, q):
+        f, l, pp, qq = (_arr(a, np.float32) for a in (feats, lfac, p, q))
+        n = f.shape[0]
+        loss = C.c_double()
+        grad = np.zeros(lib().sqrtba_mlp_num_params(), np.float32)
+        self._check(lib().sqrtba_mlp_eval(self._h, n, _ptr(f, C.c_float), _ptr(l, C.c_float), _ptr(pp, C.c_float),
+                                          _ptr(qq, C.c_float), C.byref(loss), _ptr(grad, C.c_float)))
+        return loss.value, grad
+
+    def learned_stats(self) -> dict:
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(lib().sqrtba_learned_stats(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"learned_solves": a.value, "fallbacks": b.value, "wasted_iters": c.value}
+
+    def debug_features(self):
+        f = np.zeros((self.n_cams, 64), np.float32)
+        l = np.zeros((self.n_cams, 45), np.float32)
+        self._check(lib().sqrtba_debug_features(self._h, _ptr(f, C.c_float), _ptr(l, C.c_float)))
+        return f, l
+
+    def debug_learned_precond(self) -> np.ndarray:
+        out = np.zeros((self.n_cams, 9, 9), np.float32)
+        self._check(lib().sqrtba_debug_learned_precond(self._h, _ptr(out, C.c_float)))
         return out
 
     # -- measurement and snapshots
