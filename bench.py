@@ -126,6 +126,48 @@ def cpu_baseline(problem, f_tau, budget_s: float):
     }
 
 
+def learned_run(ctx, n_problems: int, lm_iters: int):
+    """Train the learned preconditioner online on the solver's own PCG traces of
+    a separate ladybug-like problem (its own seed), then solve the workload once
+    more from the same start with it.  Training is outside the solve's clock."""
+    import numpy as np
+    import torch
+    from bal_synth import BASE_SEED, make_forward_problem
+    from paper_2103_01843_amd import Context
+
+    t0 = time.perf_counter()
+    tp = make_forward_problem(np.random.default_rng(BASE_SEED + 101))
+    tc = Context(stream=torch.cuda.current_stream(), max_lm_iters=lm_iters)
+    tc.load(tp.cameras, tp.points, tp.obs_cam, tp.obs_pt, tp.obs_uv, tp.cam_off, tp.pt_off)
+    tc.bind_torch_workspace()
+    tc.mlp_init(0)
+    tc.pcg_trace(20, 64)
+    tc.lm_solve()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = []
+    for chunk in range(8):
+        losses.append(float(np.mean(tc.mlp_train(50, batch=4096, lr=1e-3, seed=chunk))))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    theta = tc.mlp_get_params()
+    n_samples = tc.trace_size()
+    tc.close()
+    log(f"learned: trace {t1 - t0:.2f} s, training {t2 - t1:.2f} s, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    ctx.mlp_set_params(theta)
+    ctx.set_preconditioner("learned")
+    ctx.restore_state()
+    reps = ctx.lm_solve()
+    hist = [ctx.history(i) for i in range(n_problems)]
+    stats = ctx.learned_stats()
+    ctx.set_preconditioner("block_jacobi")
+    log(f"learned: {sum(r.total_pcg_iters for r in reps)} PCG iterations, final cost "
+        f"{sum(r.final_cost for r in reps):.6g}, {stats}")
+    return {"reports": reps, "history": hist, "trace_and_generate_s": t1 - t0, "train_s": t2 - t1,
+            "train_steps": 400, "trace_solves_records": list(n_samples),
+            "train_loss_first_last": [losses[0], losses[-1]], **stats}
+
+
 def calibrate_copy():
     import torch
     n = 1 << 28  # 1 GiB of float32
@@ -146,6 +188,7 @@ def main():
     ap.add_argument("--config", type=int, default=1, choices=[1, 2, 3, 4],
                     help="workload: 1 ladybug-like (default), 2 batch of 256, 3 venice-like, 4 dense stress")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -193,6 +236,13 @@ def main():
         log(f"step {s}: {max(r.iterations for r in reps)} attempts, {sum(r.total_pcg_iters for r in reps)} PCG "
             f"iterations, final cost {sum(r.final_cost for r in reps):.6g}, {max(r.solve_seconds for r in reps):.3f} s")
     prof = ctx.profile()
+    ctx.profile_enable(False)
+    learned = None
+    if not args.no_learned:
+        try:
+            learned = learned_run(ctx, p.n_problems, args.lm_iters)
+        except Exception as e:  # reported, never required
+            log(f"learned comparison failed: {e!r}")
     ctx.close()
 
     # time to 1% cost per problem (appendix A.2), f* over the runs (and the oracle where stored)
@@ -204,12 +254,26 @@ def main():
     for i in range(p.n_problems):
         f0 = runs[0][0][i].initial_cost
         finals = [reps[i].final_cost for reps, _ in runs]
+        if learned:
+            finals.append(learned["reports"][i].final_cost)
         fstar = min(finals + ([gold["final_cost"]] if gold and p.n_problems == 1 else []))
         f_tau = fstar + 0.01 * (f0 - fstar)
         f_taus.append((f0, fstar, f_tau))
         ttt_all.append([time_to_tol(h[i], f_tau) for _, h in runs])
     # a batch reaches the threshold when its last problem does
     ttt = [max(t[s] for t in ttt_all) for s in range(len(runs))]
+    learned_out = None
+    if learned:
+        l_ttt = max(time_to_tol(learned["history"][i], f_taus[i][2]) for i in range(p.n_problems))
+        learned_out = {k: v for k, v in learned.items() if k not in ("reports", "history")}
+        learned_out.update({
+            "time_to_1pct_cost_s": l_ttt,
+            "plain_time_to_1pct_cost_s": statistics.median(ttt),
+            "pcg_iters": sum(r.total_pcg_iters for r in learned["reports"]),
+            "plain_pcg_iters": sum(r.total_pcg_iters for r in runs[-1][0]),
+            "final_cost": sum(r.final_cost for r in learned["reports"]),
+            "plain_final_cost": sum(r.final_cost for r in runs[-1][0]),
+        })
     value = statistics.median(ttt)
     f0, fstar, f_tau = f_taus[0]
     finals = [sum(r.final_cost for r in reps) for reps, _ in runs]
@@ -271,6 +335,7 @@ def main():
         "matvec_GBps": achieved,
         "stage_ms": {k: v["ms"] for k, v in prof.items()},
         "roofline": roofline,
+        "learned_vs_block_jacobi": learned_out,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

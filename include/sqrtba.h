@@ -276,7 +276,10 @@ int32_t sqrtba_mlp_get_params(sqrtba_ctx* ctx, float* params);
  * In learned mode a problem whose PCG does not reach the tolerance within 1.5x
  * the iterations of its last block-Jacobi solve (or breaks down) is solved again
  * from scratch with block-Jacobi, so the tolerance and the result of the solve
- * are those of the plain method. */
+ * are those of the plain method.  The one exception: when the last block-Jacobi
+ * solve of that problem also ended at pcg_max_iters, a learned run that ends
+ * there too is kept (status MAX_ITERS), since a restart could not reach the
+ * tolerance either. */
 int32_t sqrtba_set_preconditioner(sqrtba_ctx* ctx, int32_t mode);
 
 /* Record PCG traces for training: features and factors of up to max_solves

@@ -120,6 +120,7 @@ struct sqrtba_ctx {
     int32_t *s_rec = nullptr, *s_cam = nullptr;
     int s_cap = 0;
     std::vector<int32_t> last_plain_iters;
+    std::vector<int32_t> last_plain_status;
     int64_t learned_solves = 0, fallbacks = 0, wasted_iters = 0;
   } ln;
 };
@@ -340,6 +341,7 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
     const int tpw = 256 / class_team(cl);
     int64_t s = 0;
     while (s < nb.NS && class_of_k(nb.slot_k[s]) != cl) ++s;
+    nb.wc[cl].first_slot = (int)s;
     while (s < nb.NS && class_of_k(nb.slot_k[s]) == cl) {
       int cnt = 0;
       const int64_t s0 = s;
@@ -348,6 +350,7 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
       nb.wi_count.push_back(cnt);
     }
     nb.wc[cl].count = (int)nb.wi_first.size() - nb.wc[cl].first_wi;
+    nb.wc[cl].slots = (int)(s - nb.wc[cl].first_slot);
   }
   // camera statistics for the learned preconditioner: observations, covisible
   // cameras (bitsets per problem), mean and max log k over the camera's landmarks
@@ -455,7 +458,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
     t.minv = at<float>(base, o_minv); t.obsbuf = at<float>(base, o_ob); t.dxl = at<float>(base, o_dxl);
     t.cam_part = at<double>(base, o_cp); t.cam_part2 = at<double>(base, o_cp2); t.cam_part3 = at<double>(base, o_cp3);
     t.lm_part = at<double>(base, o_lp);
-    t.lambda = at<double>(base, o_s[0]); t.alpha = at<double>(base, o_s[1]); t.beta = at<double>(base, o_s[2]);
+    t.lambda = at<double>(base, o_s[0]); t.rz_next = at<double>(base, o_s[1]); t.beta = at<double>(base, o_s[2]);
     t.rz = at<double>(base, o_s[3]); t.rr = at<double>(base, o_s[4]); t.rr0 = at<double>(base, o_s[5]);
     t.pcost = at<double>(base, o_s[6]); t.ppred = at<double>(base, o_s[7]);
     t.iters = at<int32_t>(base, o_it); t.done = at<int32_t>(base, o_dn); t.pstatus = at<int32_t>(base, o_ps);
@@ -884,6 +887,7 @@ int run_pcg(sqrtba_ctx* c, int cap) {
       its_before = its_after;
     }
   }
+  LAUNCH(c, launch_pcg_final(c->d, c->L));
   return SQRTBA_OK;
 }
 
@@ -899,6 +903,7 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
   const int P = c->h.P;
   auto& L = c->ln;
   if ((int)L.last_plain_iters.size() != P) L.last_plain_iters.assign(P, -1);
+  if ((int)L.last_plain_status.size() != P) L.last_plain_status.assign(P, -1);
   TRY(precond_stage(c));
   // trace store: features and factors of this solve
   L.cur_solve = -1;
@@ -911,6 +916,7 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
   }
   const bool learned = L.mode == 1 && L.alloc;
   std::vector<int32_t> its(P), st(P);
+  std::vector<uint8_t> fell_back(P, 0);
   if (learned) {
     LAUNCH(c, launch_mlp_precond(c->d, learn_dev(c), c->stream));
     int cap = c->opt.pcg_max_iters;
@@ -926,22 +932,30 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
     TRY(readback(c, c->d.iters, its.data()));
     TRY(readback(c, c->d.pstatus, st.data()));
     L.learned_solves++;
-    // fallback: problems the learned blocks did not bring to the tolerance
+    // fallback: problems the learned blocks did not bring to the tolerance.
+    // A learned run that used the full iteration budget is kept when the
+    // last plain run of that problem also ended at the budget: a restart
+    // could not reach the tolerance either.
     std::vector<uint8_t> fb(P, 0), keep = c->active;
     bool any = false;
-    for (int p = 0; p < P; ++p)
-      if (c->active[p] && st[p] != SQRTBA_PCG_CONVERGED && st[p] != SQRTBA_PCG_ZERO_RHS) {
+    for (int p = 0; p < P; ++p) {
+      if (!c->active[p] || st[p] == SQRTBA_PCG_CONVERGED || st[p] == SQRTBA_PCG_ZERO_RHS) continue;
+      const bool budget = st[p] == SQRTBA_PCG_MAX_ITERS && its[p] >= c->opt.pcg_max_iters &&
+                          L.last_plain_status[p] == SQRTBA_PCG_MAX_ITERS;
+      if (!budget) {
         fb[p] = 1;
         any = true;
         L.fallbacks++;
         L.wasted_iters += its[p];
       }
+    }
     if (any) {
       TRY(set_active_mask(c, fb));
       TRY(precond_stage(c));  // plain block-Jacobi blocks for these problems
       TRY(run_pcg(c, c->opt.pcg_max_iters));
       TRY(set_active_mask(c, keep));
     }
+    fell_back = fb;
   } else {
     TRY(run_pcg(c, c->opt.pcg_max_iters));
   }
@@ -953,7 +967,10 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
   TRY(readback(c, c->d.rr0, rr0.data()));
   flush_profile(c);
   for (int p = 0; p < P; ++p) {
-    if (!learned && c->active[p]) L.last_plain_iters[p] = its[p];
+    if (c->active[p] && (!learned || fell_back[p])) {
+      L.last_plain_iters[p] = its[p];
+      L.last_plain_status[p] = st[p];
+    }
     if (iters) iters[p] = its[p];
     if (status) status[p] = st[p];
     if (rel_res) rel_res[p] = rr0[p] > 0 ? std::sqrt(std::max(rr[p], 0.0) / rr0[p]) : 0.0;

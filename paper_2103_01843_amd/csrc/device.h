@@ -84,7 +84,7 @@ struct Dev {
   double* lm_part;   // NL, per-landmark partial sums
   // per-problem scalars
   double* lambda;
-  double* alpha;
+  double* rz_next;  // r.z of the last update, for alpha
   double* beta;
   double* rz;
   double* rr;
@@ -106,8 +106,10 @@ struct Dev {
 };
 
 struct WorkClass {
-  int first_wi;  // first work item of this class
-  int count;     // number of work items (workgroups)
+  int first_wi;    // first work item of this class
+  int count;       // number of work items (workgroups)
+  int first_slot;  // first slot of this class (slots of a class are contiguous)
+  int slots;       // number of slots
 };
 
 struct Launch {
@@ -127,7 +129,8 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L);
 hipError_t launch_pcg_init(const Dev& d, const Launch& L);
 hipError_t launch_pcg_iteration(const Dev& d, const Launch& L);
 hipError_t launch_matvec(const Dev& d, const Launch& L);      // the PCG product (p folded in)
-hipError_t launch_pcg_vector(const Dev& d, const Launch& L);  // reduce + update of one iteration
+hipError_t launch_pcg_vector(const Dev& d, const Launch& L);  // q and update of one iteration
+hipError_t launch_pcg_final(const Dev& d, const Launch& L);   // test of the last update of a solve
 hipError_t launch_backsub(const Dev& d, const Launch& L);
 hipError_t launch_update(const Dev& d, const Launch& L);
 hipError_t launch_commit(const Dev& d, const Launch& L);

@@ -705,132 +705,184 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
 
 // ----------------------------------------------------- kernel (c): matvec
 
-// Gather of the landmark's slice of the (scaled) direction vector for the 4
-// columns of column group g: p'[c] = s[cam, m] * (z + beta p)[cam, m] when
-// FOLD (the PCG update of p folded into the gather), else s * v.
-template <bool FOLD>
-__device__ __forceinline__ float4 gather_cols(const Dev& d, const float* __restrict__ v, float beta, int obs0, int k,
-                                              int g) {
+// Gather of the landmark's slice of the scaled direction vector for the 4
+// columns of column group g: p'[c] = s[cam, m] * v[cam, m].  Columns past 9k
+// read a valid entry and give 0 (no conditional loads).
+__device__ __forceinline__ float4 gather_cols(const Dev& d, const float* __restrict__ v, int obs0, int k, int g) {
+  const int n = 9 * k;
+  const int c0 = min(4 * g, n - 1), c3 = min(4 * g + 3, n - 1);
+  const int oa = (unsigned)c0 / 9u, ob = (unsigned)c3 / 9u;  // at most two observations
+  const int ca = 9 * d.obs_cam[obs0 + oa], cb = 9 * d.obs_cam[obs0 + ob];
   float out[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int c = 4 * g + q;
-    out[q] = 0.f;
-    if (c < 9 * k) {
-      const int o = (unsigned)c / 9u;
-      const int m = c - 9 * o;
-      const int idx = 9 * d.obs_cam[obs0 + o] + m;
-      const float val = FOLD ? (d.vz[idx] + beta * d.vp[idx]) : v[idx];
-      out[q] = d.s_cam[idx] * val;
-    }
+    const int c = min(4 * g + q, n - 1);
+    const int o = (unsigned)c / 9u;
+    const int idx = (o == oa ? ca : cb) + (c - 9 * o);
+    out[q] = (4 * g + q < n) ? d.s_cam[idx] * v[idx] : 0.f;
   }
   return make_float4(out[0], out[1], out[2], out[3]);
 }
 
 __device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 
+__device__ __forceinline__ void axpy4(float4& z, float y, float4 b) {
+  z.x += y * b.x;
+  z.y += y * b.y;
+  z.z += y * b.z;
+  z.w += y * b.w;
+}
+
 // Store the outputs of column group g: every landmark owns a 16-byte aligned
 // region of W floats at obsbuf[slot_zoff] (its 9k outputs, observation-major,
 // then padding), written as whole float4s so no cache line is partly written.
-__device__ __forceinline__ void store_cols(const Dev& d, int slot, int g, float4 z) {
-  reinterpret_cast<float4*>(d.obsbuf + d.slot_zoff[slot])[g] = z;
+__device__ __forceinline__ void store_cols(const Dev& d, int zoff, int g, float4 z) {
+  reinterpret_cast<float4*>(d.obsbuf + zoff)[g] = z;
 }
 
-// Matrix-free product for teams of <= 64 lanes: one float4 column group per
-// lane; for every B row the team forms y_r = B_r . p' with a DPP all-reduce
-// and accumulates z += y_r B_r, so each B entry is read from memory once.
-// Writes z (unscaled, 9 values per observation) to obsbuf.
-template <int TEAM, bool FOLD>
-__device__ __forceinline__ void matvec_small(const Dev& d, int slot, int lane, const float* __restrict__ v) {
-  const int prob = d.slot_prob[slot];
-  const int k = d.slot_k[slot];
-  const int obs0 = d.slot_obs0[slot];
-  const int G = width_of(k) >> 2;
-  const bool on = lane < G;
-  const int g = on ? lane : 0;
-  const float beta = FOLD ? (float)d.beta[prob] : 0.f;
-  const float4 pv = on ? gather_cols<FOLD>(d, v, beta, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
-  float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  const int n = 2 * k;  // always even
-  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-  int r = 0;
-  // four rows per step: four independent loads in flight, then four reductions
-  for (; r + 4 <= n; r += 4) {
-    const float4 b0 = on ? B[(size_t)r * G + g] : zero;
-    const float4 b1 = on ? B[(size_t)(r + 1) * G + g] : zero;
-    const float4 b2 = on ? B[(size_t)(r + 2) * G + g] : zero;
-    const float4 b3 = on ? B[(size_t)(r + 3) * G + g] : zero;
-    const float y0 = team_sum<TEAM>(dot4(b0, pv));
-    const float y1 = team_sum<TEAM>(dot4(b1, pv));
-    const float y2 = team_sum<TEAM>(dot4(b2, pv));
-    const float y3 = team_sum<TEAM>(dot4(b3, pv));
-    z.x += (y0 * b0.x + y1 * b1.x) + (y2 * b2.x + y3 * b3.x);
-    z.y += (y0 * b0.y + y1 * b1.y) + (y2 * b2.y + y3 * b3.y);
-    z.z += (y0 * b0.z + y1 * b1.z) + (y2 * b2.z + y3 * b3.z);
-    z.w += (y0 * b0.w + y1 * b1.w) + (y2 * b2.w + y3 * b3.w);
-  }
-  if (r < n) {  // n = 4m + 2
-    const float4 b0 = on ? B[(size_t)r * G + g] : zero;
-    const float4 b1 = on ? B[(size_t)(r + 1) * G + g] : zero;
-    const float y0 = team_sum<TEAM>(dot4(b0, pv));
-    const float y1 = team_sum<TEAM>(dot4(b1, pv));
-    z.x += y0 * b0.x + y1 * b1.x;
-    z.y += y0 * b0.y + y1 * b1.y;
-    z.z += y0 * b0.z + y1 * b1.z;
-    z.w += y0 * b0.w + y1 * b1.w;
-  }
-  if (on) store_cols(d, slot, g, z);
-}
+// Slot ranges of the size classes, in launch order (class 4, 3, 2, 1, 0):
+// workgroup b of class j takes slots first[j] + b * per_wg[j] onwards.  The
+// slot of every team follows from blockIdx and these kernel arguments alone.
+struct MvGrid {
+  int nblk[5];
+  int first[5];
+  int end[5];
+};
 
-template <int TEAM, bool FOLD>
-__device__ __forceinline__ void matvec_small_wi(const Dev& d, int wi, const float* v) {
+// In PCG mode (the template flag PCG) the product skips the landmarks of
+// problems whose solve has ended; otherwise every active landmark is done.
+//
+// Matrix-free product for teams of <= 64 lanes, LPT landmarks per team: one
+// float4 column group per lane; for every B row the team forms
+// y_r = B_r . p' with a DPP all-reduce and accumulates z += y_r B_r, so each B
+// entry is read from memory once.  The first four rows of every landmark are
+// requested before its gather, and each batch of four rows is requested
+// before the previous one is reduced.  Rows past 2k of the last batch re-read
+// row 2k-1 (cached) and are given y = 0.  Writes z (unscaled, 9 values per
+// observation) to obsbuf.
+template <int TEAM, int LPT, bool PCG>
+__device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, const float* __restrict__ v) {
+  constexpr int TPW = WG / TEAM;
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
-  if (team >= d.wi_count[wi]) return;
-  const int slot = d.wi_first[wi] + team;
-  const int prob = d.slot_prob[slot];
-  if (!d.active[prob] || (FOLD && d.done[prob])) return;
-  matvec_small<TEAM, FOLD>(d, slot, lane, v);
+  bool live[LPT];
+  int k[LPT], obs0[LPT], zoff[LPT], G[LPT];
+  const float4* B[LPT];
+#pragma unroll
+  for (int j = 0; j < LPT; ++j) {
+    const int slot = s0 + team + j * TPW;
+    live[j] = slot < send;
+    const int sl = live[j] ? slot : s0;
+    const int prob = d.slot_prob[sl];
+    k[j] = d.slot_k[sl];
+    obs0[j] = d.slot_obs0[sl];
+    zoff[j] = d.slot_zoff[sl];
+    B[j] = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[sl]);
+    live[j] = live[j] && d.active[prob] && !(PCG && d.done[prob]);
+    G[j] = width_of(k[j]) >> 2;
+  }
+  float4 b[LPT][4];
+#pragma unroll
+  for (int j = 0; j < LPT; ++j) {
+    const int g = min(lane, G[j] - 1);
+    if (live[j]) {  // 2k >= 4 rows always
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b[j][i] = B[j][i * G[j] + g];
+    }
+  }
+  float4 pv[LPT];
+#pragma unroll
+  for (int j = 0; j < LPT; ++j)
+    if (live[j]) pv[j] = lane < G[j] ? gather_cols(d, v, obs0[j], k[j], lane) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int j = 0; j < LPT; ++j) {
+    if (!live[j]) continue;  // uniform over the team
+    const int Gj = G[j], n = 2 * k[j];
+    const int g = min(lane, Gj - 1);
+    const float4* Bj = B[j] + g;
+    float4 c0 = b[j][0], c1 = b[j][1], c2 = b[j][2], c3 = b[j][3];
+    float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int r = 0; r < n; r += 4) {
+      const int rn = r + 4;
+      float4 n0 = c0, n1 = c1, n2 = c2, n3 = c3;
+      if (rn < n) {  // rn, rn + 1 < n since n is even
+        n0 = Bj[(size_t)rn * Gj];
+        n1 = Bj[(size_t)(rn + 1) * Gj];
+        n2 = Bj[(size_t)min(rn + 2, n - 1) * Gj];
+        n3 = Bj[(size_t)min(rn + 3, n - 1) * Gj];
+      }
+      const float y0 = team_sum<TEAM>(dot4(c0, pv[j]));
+      const float y1 = team_sum<TEAM>(dot4(c1, pv[j]));
+      float y2 = team_sum<TEAM>(dot4(c2, pv[j]));
+      float y3 = team_sum<TEAM>(dot4(c3, pv[j]));
+      if (r + 2 >= n) y2 = y3 = 0.f;
+      axpy4(z, y0, c0);
+      axpy4(z, y1, c1);
+      axpy4(z, y2, c2);
+      axpy4(z, y3, c3);
+      c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    if (lane < Gj) store_cols(d, zoff[j], lane, z);
+  }
 }
 
 // Matrix-free product for large landmarks: a workgroup of 4 wavefronts per
 // landmark.  Wave w takes rows w, w+4, ...; each lane owns up to NCG column
-// groups (strided by 64).  The 4 partial z vectors are summed through LDS in
-// a fixed order.
-template <int NCG, bool FOLD>
-__device__ __forceinline__ void matvec_large_wi(const Dev& d, int wi, const float* v, float4 (*zred)[64]) {
-  const int slot = d.wi_first[wi];
+// groups (strided by 64).  With PREFETCH the next row of the wave is requested
+// before the current one is reduced.  The 4 partial z vectors are summed
+// through LDS in a fixed order.
+template <int NCG, bool PREFETCH, bool PCG>
+__device__ __forceinline__ void matvec_large(const Dev& d, int slot, const float* v, float4 (*zred)[64]) {
   const int prob = d.slot_prob[slot];
-  if (!d.active[prob] || (FOLD && d.done[prob])) return;
   const int k = d.slot_k[slot];
   const int obs0 = d.slot_obs0[slot];
+  const int zoff = d.slot_zoff[slot];
+  const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
+  if (!d.active[prob] || (PCG && d.done[prob])) return;
   const int G = width_of(k) >> 2;
+  const int n = 2 * k;
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const float beta = FOLD ? (float)d.beta[prob] : 0.f;
-  float4 pv[NCG], z[NCG];
+  float4 b[NCG], pv[NCG], z[NCG];
+  if constexpr (PREFETCH) {
+#pragma unroll
+    for (int j = 0; j < NCG; ++j) {
+      b[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (64 * j < G) b[j] = B[(size_t)w * G + min(lane + 64 * j, G - 1)];  // n >= 8 > w
+    }
+  }
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
     const int g = lane + 64 * j;
-    pv[j] = g < G ? gather_cols<FOLD>(d, v, beta, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
+    pv[j] = g < G ? gather_cols(d, v, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
     z[j] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
-  for (int r = w; r < 2 * k; r += 4) {
-    const float4* row = B + (size_t)r * G;
-    float4 b[NCG];
+  for (int r = w; r < n; r += 4) {
+    float4 nb[NCG];
+    if constexpr (PREFETCH) {
+      const bool more = r + 4 < n;
+#pragma unroll
+      for (int j = 0; j < NCG; ++j) {
+        nb[j] = b[j];
+        if (more && 64 * j < G) nb[j] = B[(size_t)(r + 4) * G + min(lane + 64 * j, G - 1)];
+      }
+    } else {
+      const float4* row = B + (size_t)r * G + lane;
+#pragma unroll
+      for (int j = 0; j < NCG; ++j) {
+        b[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane + 64 * j < G) b[j] = row[64 * j];
+      }
+    }
     float y = 0.f;
 #pragma unroll
-    for (int j = 0; j < NCG; ++j) {
-      const int g = lane + 64 * j;
-      b[j] = g < G ? row[g] : make_float4(0.f, 0.f, 0.f, 0.f);
-      y += dot4(b[j], pv[j]);
-    }
+    for (int j = 0; j < NCG; ++j) y += dot4(b[j], pv[j]);
     y = wave_sum_f(y);
 #pragma unroll
-    for (int j = 0; j < NCG; ++j) {
-      z[j].x += y * b[j].x; z[j].y += y * b[j].y; z[j].z += y * b[j].z; z[j].w += y * b[j].w;
+    for (int j = 0; j < NCG; ++j) axpy4(z[j], y, b[j]);
+    if constexpr (PREFETCH) {
+#pragma unroll
+      for (int j = 0; j < NCG; ++j) b[j] = nb[j];
     }
   }
 #pragma unroll
@@ -843,41 +895,62 @@ __device__ __forceinline__ void matvec_large_wi(const Dev& d, int wi, const floa
       const float4 s = make_float4((a.x + b2.x) + (c.x + e.x), (a.y + b2.y) + (c.y + e.y),
                                    (a.z + b2.z) + (c.z + e.z), (a.w + b2.w) + (c.w + e.w));
       const int g = lane + 64 * j;
-      if (g < G) store_cols(d, slot, g, s);
+      if (g < G) store_cols(d, zoff, g, s);
     }
     __syncthreads();
   }
 }
 
-// One launch for the size classes 0..4: every workgroup handles one work item
-// (one class), so the whole product over landmarks with k <= 113 is a single
-// kernel with no tail gaps between classes.
-template <bool FOLD>
-__global__ __launch_bounds__(WG) void k_matvec(Dev d, int wi0, const float* v) {
+// Landmarks per team of the small classes (3, 2, 1, 0 in launch order).
+#ifndef SQRTBA_MV_LPT
+#define SQRTBA_MV_LPT 1, 1, 1, 1
+#endif
+constexpr int MV_LPT[4] = {SQRTBA_MV_LPT};
+__host__ __device__ constexpr int mv_per_wg(int j) {  // j: launch-order class index 0..4
+  return j == 0 ? 1 : (WG / class_team(4 - j)) * MV_LPT[j - 1];
+}
+
+// One launch for the size classes 0..4: every workgroup belongs to one class,
+// so the whole product over landmarks with k <= 113 is a single kernel with
+// no tail gaps between classes.
+template <bool PCG>
+__global__ __launch_bounds__(WG) void k_matvec(Dev d, MvGrid m, const float* v) {
   __shared__ float4 zred[4][64];
-  const int wi = wi0 + blockIdx.x;
-  switch (class_of_k(d.slot_k[d.wi_first[wi]])) {
-    case 0: matvec_small_wi<8, FOLD>(d, wi, v); break;
-    case 1: matvec_small_wi<16, FOLD>(d, wi, v); break;
-    case 2: matvec_small_wi<32, FOLD>(d, wi, v); break;
-    case 3: matvec_small_wi<64, FOLD>(d, wi, v); break;
-    default: matvec_large_wi<4, FOLD>(d, wi, v, zred); break;
-  }
+  int b = blockIdx.x;
+  if (b < m.nblk[0]) { matvec_large<4, true, PCG>(d, m.first[0] + b, v, zred); return; }
+  b -= m.nblk[0];
+  if (b < m.nblk[1]) { matvec_teams<64, MV_LPT[0], PCG>(d, m.first[1] + b * mv_per_wg(1), m.end[1], v); return; }
+  b -= m.nblk[1];
+  if (b < m.nblk[2]) { matvec_teams<32, MV_LPT[1], PCG>(d, m.first[2] + b * mv_per_wg(2), m.end[2], v); return; }
+  b -= m.nblk[2];
+  if (b < m.nblk[3]) { matvec_teams<16, MV_LPT[2], PCG>(d, m.first[3] + b * mv_per_wg(3), m.end[3], v); return; }
+  b -= m.nblk[3];
+  matvec_teams<8, MV_LPT[3], PCG>(d, m.first[4] + b * mv_per_wg(4), m.end[4], v);
 }
 
 // Landmarks with k > 113 (up to 512): four wavefronts per landmark.
-template <bool FOLD>
-__global__ __launch_bounds__(WG) void k_matvec_huge(Dev d, int wi0, const float* v) {
+template <bool PCG>
+__global__ __launch_bounds__(WG) void k_matvec_huge(Dev d, int slot0, const float* v) {
   __shared__ float4 zred[4][64];
-  matvec_large_wi<18, FOLD>(d, wi0 + blockIdx.x, v, zred);
+  matvec_large<18, false, PCG>(d, slot0 + blockIdx.x, v, zred);
 }
 
 // ----------------------------------------------------- PCG vector kernels
 
-// Kernel boundaries order the phases of one PCG iteration; there are no
-// grid-wide atomics or fences.  Per-camera partial sums are FP64 and every
-// per-problem sum is formed by the same fixed-order wavefront tree
-// (problem_sum), so all workgroups that form a scalar get the same bits.
+// One PCG iteration is three kernels, ordered by the kernel boundaries (no
+// grid-wide atomics or fences):
+//   product   w = B^T B S z over the landmark blocks (per-observation outputs),
+//   k_pcg_q   the sums r.z, r.r of the last update -> convergence test and
+//             beta; p = z + beta p, q = A z + beta q (= A p), partial p.q,
+//   k_pcg_update  alpha = r.z / p.q; x += alpha p, r -= alpha q, z = M^-1 r,
+//             partials r.z, r.r.
+// Every workgroup that needs a per-problem scalar forms it itself from the
+// per-camera FP64 partials with the same fixed-order wavefront tree, so all of
+// them hold the same bits.  Per-problem state is written by one designated
+// workgroup (the one holding the problem's first camera) and never read back
+// in the kernel that writes it; the one exception, the done flag, only ever
+// goes from 0 to 1 and every workgroup that reads it makes the same decision
+// from the sums it formed itself.
 
 __device__ __forceinline__ double problem_sum(const Dev& d, const double* __restrict__ part, int p, int lane) {
   double s = 0.0;
@@ -887,22 +960,19 @@ __device__ __forceinline__ double problem_sum(const Dev& d, const double* __rest
   return wave_sum_d(s);
 }
 
-// The three per-problem sums of one iteration in one pass (same per-lane order
-// as problem_sum, so the first sum is bitwise equal to problem_sum(part)).
-__device__ __forceinline__ void problem_sum3(const Dev& d, const double* __restrict__ a, const double* __restrict__ b,
-                                             const double* __restrict__ c3, int p, int lane, double& sa, double& sb,
-                                             double& sc) {
-  sa = sb = sc = 0.0;
+// Two per-problem sums in one pass (same per-lane order as problem_sum, so each
+// is bitwise equal to problem_sum of its array).
+__device__ __forceinline__ void problem_sum2(const Dev& d, const double* __restrict__ a, const double* __restrict__ b,
+                                             int p, int lane, double& sa, double& sb) {
+  sa = sb = 0.0;
   const int e = d.prob_cam_off[p + 1];
 #pragma unroll 4
   for (int c = d.prob_cam_off[p] + lane; c < e; c += 64) {
     sa += a[c];
     sb += b[c];
-    sc += c3[c];
   }
   sa = wave_sum_d(sa);
   sb = wave_sum_d(sb);
-  sc = wave_sum_d(sc);
 }
 
 __device__ __forceinline__ void minv_apply(const float* __restrict__ mi, const float r[9], float z[9]) {
@@ -915,7 +985,7 @@ __device__ __forceinline__ void minv_apply(const float* __restrict__ mi, const f
   }
 }
 
-// x = 0, r = -b, z = M^-1 r, p = 0; per-camera partials r.z (cam_part2), r.r (cam_part3).
+// x = 0, r = -b, z = M^-1 r, p = q = 0; per-camera partials r.z (cam_part2), r.r (cam_part3).
 __global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= d.NC) return;
@@ -929,6 +999,7 @@ __global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
       d.vx[9 * c + a] = 0.f;
       d.vr[9 * c + a] = r[a];
       d.vp[9 * c + a] = 0.f;
+      d.vq[9 * c + a] = 0.f;
     }
     minv_apply(d.minv + 81 * (size_t)c, r, z);
 #pragma unroll
@@ -942,12 +1013,13 @@ __global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
   d.cam_part3[c] = rr;
 }
 
-// One workgroup: per-problem start scalars (beta = 0, rz, rr0, done).
+// One workgroup: per-problem start scalars.  rz holds r0.z0, so the first
+// beta is exactly 1 and p = z0 (p and q start at 0).
 __global__ __launch_bounds__(WG) void k_pcg_init_scalars(Dev d) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int p = w; p < d.P; p += WG / 64) {
-    const double rz = problem_sum(d, d.cam_part2, p, lane);
-    const double rr = problem_sum(d, d.cam_part3, p, lane);
+    double rz, rr;
+    problem_sum2(d, d.cam_part2, d.cam_part3, p, lane, rz, rr);
     if (lane == 0) {
       d.rz[p] = rz;
       d.rr0[p] = rr;
@@ -955,25 +1027,66 @@ __global__ __launch_bounds__(WG) void k_pcg_init_scalars(Dev d) {
       d.beta[p] = 0.0;
       d.iters[p] = 0;
       if (!d.active[p]) { d.done[p] = 1; d.pstatus[p] = 4; }
-      else if (!(rr > 0.0)) { d.done[p] = 1; d.pstatus[p] = (rr == 0.0) ? 3 : 2; }
-      else { d.done[p] = 0; d.pstatus[p] = 1; }
+      else if (!(rr > 0.0) || !(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {
+        d.done[p] = 1;
+        d.pstatus[p] = (rr == 0.0) ? 3 : 2;
+      } else { d.done[p] = 0; d.pstatus[p] = 1; }
     }
   }
 }
 
-// Per camera (one workgroup): p = z + beta p, q = S sum_obs z_obs + lambda p,
-// partial p.q (cam_part).
+// Convergence test of the last update from its sums: 0 continue, 1 converged,
+// 2 breakdown (non-finite or non-positive r.z).
+__device__ __forceinline__ int pcg_test(const Dev& d, int p, double rz, double rr) {
+  if (!isfinite(rr) || !isfinite(rz)) return 2;
+  const double tol = (double)d.pcg_tol;
+  if (rr <= tol * tol * d.rr0[p]) return 1;
+  return rz > 0.0 ? 0 : 2;
+}
+
+// Per camera (one workgroup).
 __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
   __shared__ float part[4][9];
   __shared__ float pqs[9];
+  __shared__ float beta_s;
+  __shared__ int go_s;
   const int c = blockIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // loads that do not depend on the problem's state first
   const int prob = d.cam_prob[c];
+  const int b = d.cam_obs_off[c], e = d.cam_obs_off[c + 1];
+  float zc = 0.f, pc = 0.f, qc = 0.f, sc = 0.f;
+  if (threadIdx.x < 9) {
+    const int idx = 9 * c + threadIdx.x;
+    zc = d.vz[idx];
+    pc = d.vp[idx];
+    qc = d.vq[idx];
+    sc = d.s_cam[idx];
+  }
   if (!d.active[prob] || d.done[prob]) return;  // uniform over the workgroup
+  if (w == 0) {
+    double rz, rr;
+    problem_sum2(d, d.cam_part2, d.cam_part3, prob, lane, rz, rr);
+    if (lane == 0) {
+      const int t = pcg_test(d, prob, rz, rr);
+      const double beta = rz / d.rz[prob];
+      beta_s = (float)beta;
+      go_s = t == 0;
+      if (c == d.prob_cam_off[prob]) {  // designated writer of the problem's scalars
+        d.rr[prob] = rr;
+        if (t) {
+          d.done[prob] = 1;
+          d.pstatus[prob] = t == 1 ? 0 : 2;
+        } else {
+          d.rz_next[prob] = rz;
+          d.beta[prob] = beta;
+        }
+      }
+    }
+  }
   float acc[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = 0.f;
-  const int b = d.cam_obs_off[c], e = d.cam_obs_off[c + 1];
   for (int i = b + (int)threadIdx.x; i < e; i += WG) {
     const float* src = d.obsbuf + d.cam_zpos[i];
 #pragma unroll
@@ -986,15 +1099,18 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
     for (int a = 0; a < 9; ++a) part[w][a] = acc[a];
   }
   __syncthreads();
+  if (!go_s) return;  // uniform: the solve of this problem has ended
   if (threadIdx.x < 9) {
     const int a = threadIdx.x;
-    const float s = (part[0][a] + part[1][a]) + (part[2][a] + part[3][a]);
     const int idx = 9 * c + a;
-    const float pn = d.vz[idx] + (float)d.beta[prob] * d.vp[idx];
-    const float q = d.s_cam[idx] * s + (float)d.lambda[prob] * pn;
+    const float s = (part[0][a] + part[1][a]) + (part[2][a] + part[3][a]);
+    const float beta = beta_s;
+    const float az = sc * s + (float)d.lambda[prob] * zc;  // (A z) of this camera
+    const float pn = zc + beta * pc;
+    const float qn = az + beta * qc;
     d.vp[idx] = pn;
-    d.vq[idx] = q;
-    pqs[a] = pn * q;
+    d.vq[idx] = qn;
+    pqs[a] = pn * qn;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1005,11 +1121,9 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
   }
 }
 
-// One thread per (camera, row), UPD_CAMS cameras per workgroup.  Each
-// workgroup forms alpha = rz / p^T q of its problems itself (the same fixed
-// sum everywhere; alpha = 0 on breakdown, which k_pcg_scalars then reports),
-// then x += alpha p, r -= alpha q, z = M^-1 r (the camera's r through LDS),
-// and per-camera partials r.z (cam_part2) and r.r (cam_part3).
+// One thread per (camera, row), UPD_CAMS cameras per workgroup.  Wave 0 forms
+// alpha = rz / p^T q for each problem that owns cameras of the workgroup
+// (alpha = 0 and a breakdown status when p^T q is not positive and finite).
 constexpr int UPD_CAMS = 28;
 constexpr int UPD_THREADS = 9 * UPD_CAMS;  // 252
 
@@ -1021,37 +1135,60 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
   const int lc = threadIdx.x / 9, a = threadIdx.x - 9 * (threadIdx.x / 9);
   const int c0 = blockIdx.x * UPD_CAMS;
   const int c = c0 + lc;
-  const int cl = min(c0 + UPD_CAMS, d.NC);  // cameras [c0, cl) of this workgroup
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // alpha of every problem that owns a camera of this workgroup (wave 0)
+  const bool valid = c < d.NC && lc < UPD_CAMS;
+  // loads that do not depend on alpha first
+  int prob = 0;
+  float xv = 0.f, pv = 0.f, rv = 0.f, qv = 0.f;
+  const int idx = 9 * c + a;
+  if (valid) {
+    prob = d.cam_prob[c];
+    xv = d.vx[idx];
+    pv = d.vp[idx];
+    rv = d.vr[idx];
+    qv = d.vq[idx];
+  }
   if (w == 0) {
-    int pprev = -1;
-    float al = 0.f;
-    for (int cc = c0; cc < cl; ++cc) {
-      const int p = d.cam_prob[cc];
-      if (p != pprev) {
-        al = 0.f;
-        if (d.active[p] && !d.done[p]) {
-          const double pq = problem_sum(d, d.cam_part, p, lane);
-          al = (pq > 0.0 && isfinite(pq)) ? (float)(d.rz[p] / pq) : 0.f;
+    // the problems of cameras c0 .. c0 + UPD_CAMS - 1 form runs; one alpha per run
+    const int cl = c0 + lane;
+    const bool own = lane < UPD_CAMS && cl < d.NC;
+    const int pl = own ? d.cam_prob[cl] : -1;
+    const int prev = __shfl_up(pl, 1);
+    const bool head = own && (lane == 0 || prev != pl);
+    uint64_t heads = __ballot(head);
+    while (heads) {
+      const int h = __builtin_ctzll(heads);
+      heads &= heads - 1;
+      const int p = __shfl(pl, h);
+      float al = 0.f;
+      if (d.active[p] && !d.done[p]) {
+        const double pq = problem_sum(d, d.cam_part, p, lane);
+        const bool ok = pq > 0.0 && isfinite(pq);
+        al = ok ? (float)(d.rz_next[p] / pq) : 0.f;
+        const int f = d.prob_cam_off[p];
+        if (lane == 0 && f >= c0 && f < c0 + UPD_CAMS) {  // designated writer
+          if (ok) {
+            d.iters[p] += 1;
+            d.rz[p] = d.rz_next[p];
+          } else {
+            d.done[p] = 1;
+            d.pstatus[p] = 2;  // breakdown: x kept
+          }
         }
-        pprev = p;
+        if (!ok) al = 0.f;
       }
-      if (lane == 0) alpha_s[cc - c0] = al;
+      if (own && pl == p) alpha_s[lane] = al;
     }
   }
   __syncthreads();
-  const bool valid = c < d.NC && lc < UPD_CAMS;
   bool live = false;
   float r = 0.f, z = 0.f;
   if (valid) {
-    const int prob = d.cam_prob[c];
-    live = d.active[prob] && !d.done[prob];
+    const float alpha = alpha_s[lc];
+    live = d.active[prob] && alpha != 0.f;
     if (live) {
-      const float alpha = alpha_s[lc];
-      const int idx = 9 * c + a;
-      d.vx[idx] += alpha * d.vp[idx];
-      r = d.vr[idx] - alpha * d.vq[idx];
+      d.vx[idx] = xv + alpha * pv;
+      r = rv - alpha * qv;
       d.vr[idx] = r;
     }
   }
@@ -1061,7 +1198,7 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
     const float* mi = d.minv + 81 * (size_t)c + 9 * a;
 #pragma unroll
     for (int j = 0; j < 9; ++j) z += mi[j] * rs[lc][j];
-    d.vz[9 * c + a] = z;
+    d.vz[idx] = z;
   }
   if (lc < UPD_CAMS) {
     prz[lc][a] = r * z;
@@ -1080,32 +1217,21 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
   }
 }
 
-// One workgroup: per problem, breakdown test on p^T q, iteration count,
-// convergence |r| <= tol |r0| (unpreconditioned), beta = rz_new / rz.
-__global__ __launch_bounds__(WG) void k_pcg_scalars(Dev d) {
+// One workgroup, once after the last iteration of a solve: the convergence
+// test of the last update of every problem still running (its status stays
+// "iteration limit" unless that update reached the tolerance) and its r.r.
+__global__ __launch_bounds__(WG) void k_pcg_final(Dev d) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int p = w; p < d.P; p += WG / 64) {
     if (!d.active[p] || d.done[p]) continue;  // uniform over the wavefront
-    double pq, rz, rr;
-    problem_sum3(d, d.cam_part, d.cam_part2, d.cam_part3, p, lane, pq, rz, rr);
+    double rz, rr;
+    problem_sum2(d, d.cam_part2, d.cam_part3, p, lane, rz, rr);
     if (lane == 0) {
-      if (!(pq > 0.0) || !isfinite(pq)) {
+      const int t = pcg_test(d, p, rz, rr);
+      d.rr[p] = rr;
+      if (t) {
         d.done[p] = 1;
-        d.pstatus[p] = 2;  // breakdown: x kept (alpha was 0)
-      } else {
-        d.iters[p] += 1;
-        d.rr[p] = rr;
-        const double tol = (double)d.pcg_tol;
-        if (!isfinite(rr) || !isfinite(rz)) {
-          d.done[p] = 1;
-          d.pstatus[p] = 2;
-        } else if (rr <= tol * tol * d.rr0[p]) {
-          d.done[p] = 1;
-          d.pstatus[p] = 0;
-        } else {
-          d.beta[p] = rz / d.rz[p];
-          d.rz[p] = rz;
-        }
+        d.pstatus[p] = t == 1 ? 0 : 2;
       }
     }
   }
@@ -1147,7 +1273,7 @@ __global__ __launch_bounds__(WG) void k_backsub(Dev d, int wi0) {
     const int g = lane + TEAM * j;
     pv[j] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (g < G) {
-      pv[j] = gather_cols<false>(d, d.vx, 0.f, obs0, k, g);
+      pv[j] = gather_cols(d, d.vx, obs0, k, g);
       const float4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
       float a[3], b[3];
       a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b);
@@ -1395,21 +1521,30 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
 // The landmarks with k > 113 (few, each a long stream for one workgroup) run
 // on a side stream concurrently with the main product, forked from and joined
 // back into the context stream by events (also inside captured graphs).
-template <bool FOLD>
+template <bool PCG>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
   const WorkClass* w = L.wc;
-  const bool fork = w[5].count && L.side && L.fork && L.join;
+  const bool fork = w[5].slots && L.side && L.fork && L.join;
   if (fork) {
     hipError_t e = hipEventRecord(L.fork, L.stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(L.side, L.fork, 0);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_matvec_huge<FOLD>, dim3(w[5].count), dim3(WG), 0, L.side, d, w[5].first_wi, v);
+    hipLaunchKernelGGL(k_matvec_huge<PCG>, dim3(w[5].slots), dim3(WG), 0, L.side, d, w[5].first_slot, v);
     LAUNCH_CHECK();
-  } else if (w[5].count) {
-    hipLaunchKernelGGL(k_matvec_huge<FOLD>, dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi, v);
+  } else if (w[5].slots) {
+    hipLaunchKernelGGL(k_matvec_huge<PCG>, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot, v);
   }
-  const int n = w[4].count + w[3].count + w[2].count + w[1].count + w[0].count;
-  if (n) hipLaunchKernelGGL(k_matvec<FOLD>, dim3(n), dim3(WG), 0, L.stream, d, w[4].first_wi, v);
+  MvGrid m;
+  int n = 0;
+  for (int j = 0; j < 5; ++j) {
+    const WorkClass& c = w[4 - j];
+    const int per = mv_per_wg(j);
+    m.nblk[j] = (c.slots + per - 1) / per;
+    m.first[j] = c.first_slot;
+    m.end[j] = c.first_slot + c.slots;
+    n += m.nblk[j];
+  }
+  if (n) hipLaunchKernelGGL(k_matvec<PCG>, dim3(n), dim3(WG), 0, L.stream, d, m, v);
   LAUNCH_CHECK();
   if (fork) {
     hipError_t e = hipEventRecord(L.join, L.side);
@@ -1427,14 +1562,18 @@ hipError_t launch_pcg_init(const Dev& d, const Launch& L) {
   return hipSuccess;
 }
 
-hipError_t launch_matvec(const Dev& d, const Launch& L) { return launch_matvec<true>(d, L, nullptr); }
+hipError_t launch_matvec(const Dev& d, const Launch& L) { return launch_matvec<true>(d, L, d.vz); }
 
 hipError_t launch_pcg_vector(const Dev& d, const Launch& L) {
   hipLaunchKernelGGL(k_pcg_q, dim3(d.NC), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(d.NC, UPD_CAMS)), dim3(UPD_THREADS), 0, L.stream, d);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(WG), 0, L.stream, d);
+  return hipSuccess;
+}
+
+hipError_t launch_pcg_final(const Dev& d, const Launch& L) {
+  hipLaunchKernelGGL(k_pcg_final, dim3(1), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
   return hipSuccess;
 }
