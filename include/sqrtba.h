@@ -290,7 +290,9 @@ int32_t sqrtba_trace_size(const sqrtba_ctx* ctx, int32_t* n_solves, int32_t* n_r
 
 /* steps Adam steps (learning rate lr) on minibatches of `batch` (record, camera)
  * samples drawn uniformly from the traces with a seeded generator; losses[steps]
- * (may be NULL) receives each minibatch's mean loss before its step. */
+ * (may be NULL) receives each minibatch's mean loss before its step.  lr = 0
+ * only evaluates the loss on the same seeded minibatches (no update); lr < 0
+ * or NaN is SQRTBA_E_INVALID. */
 int32_t sqrtba_mlp_train(sqrtba_ctx* ctx, int32_t steps, int32_t batch, double lr, uint64_t seed, double* losses);
 
 /* Loss and gradient at the current parameters for n explicit samples:

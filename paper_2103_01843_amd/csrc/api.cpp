@@ -49,6 +49,9 @@ struct HostData {
   std::vector<float> cam_stats;  // NC * 4 features of the camera's observation graph
   std::vector<int32_t> wi_first, wi_count;
   WorkClass wc[NUM_CLASSES];
+  std::vector<int32_t> hjob;   // (slot, row block) pairs of the split class-5 product
+  std::vector<int64_t> hz_off; // per class-5 slot, offset of its partial outputs
+  int64_t hz_floats = 0;
   int64_t poolB = 0, poolT = 0;
 };
 
@@ -352,6 +355,21 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
     nb.wc[cl].count = (int)nb.wi_first.size() - nb.wc[cl].first_wi;
     nb.wc[cl].slots = (int)(s - nb.wc[cl].first_slot);
   }
+  // split product of class 5: row blocks of HUGE_ROWS rows, partial outputs per block
+  nb.hjob.clear();
+  nb.hz_off.clear();
+  nb.hz_floats = 0;
+  for (int64_t i = 0; i < nb.wc[5].slots; ++i) {
+    const int64_t sl = nb.wc[5].first_slot + i, k = nb.slot_k[sl];
+    const int64_t nblk = (2 * k + HUGE_ROWS - 1) / HUGE_ROWS;
+    nb.hz_off.push_back(nb.hz_floats);
+    nb.hz_floats += nblk * width_of_h(k);
+    for (int64_t r = 0; r < nblk; ++r) {
+      nb.hjob.push_back((int32_t)sl);
+      nb.hjob.push_back((int32_t)r);
+    }
+  }
+  if (nb.hjob.size() / 2 > (size_t)INT32_MAX / 2) return fail(c, SQRTBA_E_UNSUPPORTED, "too many row blocks");
   // camera statistics for the learned preconditioner: observations, covisible
   // cameras (bitsets per problem), mean and max log k over the camera's landmarks
   nb.cam_stats.assign(4 * h.NC, 0.f);
@@ -427,6 +445,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
   uint64_t o_slm = f32(NS), o_sk = f32(NS), o_so = f32(NS), o_sp = f32(NS), o_sb = f64(NS), o_st = f64(NS);
   uint64_t o_sz = f32(NS), o_czp = f32(NO);
   uint64_t o_lms = f32(NL), o_wf = f32(NW), o_wc = f32(NW);
+  uint64_t o_hj = f32(h.hjob.size()), o_hzo = f64(h.hz_off.size()), o_zp = f32(h.hz_floats);
   uint64_t o_pB = f32(h.poolB), o_pT = f32(h.poolT), o_lmd = f32(NS * LMD_STRIDE), o_rho = f32(2 * NO);
   uint64_t o_sc = f32(9 * NC);
   uint64_t o_v[6];
@@ -451,6 +470,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
     t.slot_prob = at<int32_t>(base, o_sp); t.slot_boff = at<int64_t>(base, o_sb); t.slot_toff = at<int64_t>(base, o_st);
     t.slot_zoff = at<int32_t>(base, o_sz); t.cam_zpos = at<int32_t>(base, o_czp);
     t.lm_slot = at<int32_t>(base, o_lms); t.wi_first = at<int32_t>(base, o_wf); t.wi_count = at<int32_t>(base, o_wc);
+    t.hjob = at<int2>(base, o_hj); t.hz_off = at<int64_t>(base, o_hzo); t.zpart = at<float>(base, o_zp);
     t.poolB = at<float>(base, o_pB); t.poolT = at<float>(base, o_pT); t.lmd = at<float>(base, o_lmd);
     t.rhoB = at<float>(base, o_rho); t.s_cam = at<float>(base, o_sc);
     t.vx = at<float>(base, o_v[0]); t.vr = at<float>(base, o_v[1]); t.vz = at<float>(base, o_v[2]);
@@ -469,6 +489,13 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
     *d = t;
   }
   return L.total;
+}
+
+// Class 4 of the product gets its own launch (and the small classes a kernel
+// with fewer registers) from this many class-4 landmarks on.
+int large_split_default() {
+  const char* e = getenv("SQRTBA_LARGE_SPLIT");
+  return e ? atoi(e) : 256;
 }
 
 hipEvent_t take_event(sqrtba_ctx* c) {
@@ -583,12 +610,16 @@ int upload(sqrtba_ctx* c) {
   TRY(upload_vec(c, d.lm_slot, h.lm_slot));
   TRY(upload_vec(c, d.wi_first, h.wi_first));
   TRY(upload_vec(c, d.wi_count, h.wi_count));
+  TRY(upload_vec(c, reinterpret_cast<int32_t*>(d.hjob), h.hjob));
+  TRY(upload_vec(c, d.hz_off, h.hz_off));
   TRY(upload_vec(c, d.cam_stats, h.cam_stats));
   c->active.assign(h.P, 1);
   TRY(upload_vec(c, d.active, c->active));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->L.stream = c->stream;
   for (int i = 0; i < NUM_CLASSES; ++i) c->L.wc[i] = h.wc[i];
+  c->L.hjobs = (int)(h.hjob.size() / 2);
+  c->L.large_split = large_split_default();
   if (!c->side) {
     HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
     HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
@@ -1570,7 +1601,7 @@ static int grow_training(sqrtba_ctx* c, int n) {
 }
 
 int32_t sqrtba_mlp_train(sqrtba_ctx* c, int32_t steps, int32_t batch, double lr, uint64_t seed, double* losses) {
-  if (!c || steps < 0 || batch <= 0 || !(lr > 0)) return SQRTBA_E_INVALID;
+  if (!c || steps < 0 || batch <= 0 || !(lr >= 0)) return SQRTBA_E_INVALID;
   auto& L = c->ln;
   if (!L.alloc) return fail(c, SQRTBA_E_STATE, "no network: call sqrtba_mlp_init or sqrtba_mlp_set_params");
   if (L.n_records == 0) return fail(c, SQRTBA_E_STATE, "no traced PCG iterations: enable sqrtba_pcg_trace and solve");
@@ -1606,7 +1637,7 @@ int32_t sqrtba_mlp_train(sqrtba_ctx* c, int32_t steps, int32_t batch, double lr,
     HIP_TRY(c, hipMemcpyAsync(L.s_rec, hr.data(), 4 * (size_t)batch, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(L.s_cam, hc.data(), 4 * (size_t)batch, hipMemcpyHostToDevice, c->stream));
     LAUNCH(c, launch_mlp_grad(learn_dev(c), src, batch, L.part, L.loss_part, L.grad, c->stream));
-    LAUNCH(c, launch_adam(learn_dev(c), L.grad, (float)lr, ++L.adam_step, c->stream));
+    if (lr > 0) LAUNCH(c, launch_adam(learn_dev(c), L.grad, (float)lr, ++L.adam_step, c->stream));
     HIP_TRY(c, hipMemcpyAsync(lp.data(), L.loss_part, 8 * (size_t)tiles, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     double tot = 0;

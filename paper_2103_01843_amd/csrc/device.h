@@ -62,6 +62,11 @@ struct Dev {
   // work items: per class, a list of (first slot, count)
   int32_t* wi_first;
   int32_t* wi_count;
+  // split product of the largest landmarks (class 5): one job per block of
+  // HUGE_ROWS rows (x: slot, y: row block), partial outputs per row block
+  int2* hjob;
+  int64_t* hz_off;  // per class-5 slot: float offset of its partial outputs in zpart (nblocks x W)
+  float* zpart;
   float* poolB;
   float* poolT;
   float* lmd;     // NS * LMD_STRIDE
@@ -112,7 +117,12 @@ struct WorkClass {
   int slots;       // number of slots
 };
 
+// Rows of a landmark block per workgroup in the split product of class 5.
+enum { HUGE_ROWS = 64 };
+
 struct Launch {
+  int hjobs;          // number of split-product jobs (class 5)
+  int large_split;    // class 4 runs as its own launch when it has at least this many landmarks
   hipStream_t stream;
   hipStream_t side;   // second stream for the largest landmarks (may be null)
   hipEvent_t fork, join;

@@ -752,86 +752,59 @@ struct MvGrid {
 // In PCG mode (the template flag PCG) the product skips the landmarks of
 // problems whose solve has ended; otherwise every active landmark is done.
 //
-// Matrix-free product for teams of <= 64 lanes, LPT landmarks per team: one
+// Matrix-free product for teams of <= 64 lanes, one landmark per team: one
 // float4 column group per lane; for every B row the team forms
 // y_r = B_r . p' with a DPP all-reduce and accumulates z += y_r B_r, so each B
-// entry is read from memory once.  The first four rows of every landmark are
-// requested before its gather, and each batch of four rows is requested
-// before the previous one is reduced.  Rows past 2k of the last batch re-read
-// row 2k-1 (cached) and are given y = 0.  Writes z (unscaled, 9 values per
-// observation) to obsbuf.
-template <int TEAM, int LPT, bool PCG>
+// entry is read from memory once.  Rows are taken in batches of RB: the first
+// batch is requested before the gather, and each batch before the previous
+// one is reduced, so up to 2 RB rows are in flight per lane.  Rows past 2k of
+// the last batch re-read row 2k-1 (cached) and are given y = 0.  Writes z
+// (unscaled, 9 values per observation) to obsbuf.
+template <int TEAM, int RB, bool PCG>
 __device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, const float* __restrict__ v) {
-  constexpr int TPW = WG / TEAM;
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
-  bool live[LPT];
-  int k[LPT], obs0[LPT], zoff[LPT], G[LPT];
-  const float4* B[LPT];
+  const int slot = s0 + team;
+  if (slot >= send) return;  // uniform over the team
+  const int prob = d.slot_prob[slot];
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const int zoff = d.slot_zoff[slot];
+  const float4* __restrict__ Bs = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
+  if (!d.active[prob] || (PCG && d.done[prob])) return;
+  const int G = width_of(k) >> 2, n = 2 * k;
+  const float4* __restrict__ Bj = Bs + min(lane, G - 1);
+  float4 c[RB];
 #pragma unroll
-  for (int j = 0; j < LPT; ++j) {
-    const int slot = s0 + team + j * TPW;
-    live[j] = slot < send;
-    const int sl = live[j] ? slot : s0;
-    const int prob = d.slot_prob[sl];
-    k[j] = d.slot_k[sl];
-    obs0[j] = d.slot_obs0[sl];
-    zoff[j] = d.slot_zoff[sl];
-    B[j] = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[sl]);
-    live[j] = live[j] && d.active[prob] && !(PCG && d.done[prob]);
-    G[j] = width_of(k[j]) >> 2;
-  }
-  float4 b[LPT][4];
+  for (int i = 0; i < RB; ++i) c[i] = Bj[(size_t)min(i, n - 1) * G];
+  const float4 pv = lane < G ? gather_cols(d, v, obs0, k, lane) : make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int r = 0; r < n; r += RB) {
+    const int rn = r + RB;
+    float4 nx[RB];
 #pragma unroll
-  for (int j = 0; j < LPT; ++j) {
-    const int g = min(lane, G[j] - 1);
-    if (live[j]) {  // 2k >= 4 rows always
+    for (int i = 0; i < RB; ++i) nx[i] = c[i];
+    if (rn < n) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) b[j][i] = B[j][i * G[j] + g];
+      for (int i = 0; i < RB; ++i) nx[i] = Bj[(size_t)min(rn + i, n - 1) * G];
     }
-  }
-  float4 pv[LPT];
+    float y[RB];
 #pragma unroll
-  for (int j = 0; j < LPT; ++j)
-    if (live[j]) pv[j] = lane < G[j] ? gather_cols(d, v, obs0[j], k[j], lane) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = 0; i < RB; ++i) y[i] = team_sum<TEAM>(dot4(c[i], pv));
 #pragma unroll
-  for (int j = 0; j < LPT; ++j) {
-    if (!live[j]) continue;  // uniform over the team
-    const int Gj = G[j], n = 2 * k[j];
-    const int g = min(lane, Gj - 1);
-    const float4* Bj = B[j] + g;
-    float4 c0 = b[j][0], c1 = b[j][1], c2 = b[j][2], c3 = b[j][3];
-    float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int r = 0; r < n; r += 4) {
-      const int rn = r + 4;
-      float4 n0 = c0, n1 = c1, n2 = c2, n3 = c3;
-      if (rn < n) {  // rn, rn + 1 < n since n is even
-        n0 = Bj[(size_t)rn * Gj];
-        n1 = Bj[(size_t)(rn + 1) * Gj];
-        n2 = Bj[(size_t)min(rn + 2, n - 1) * Gj];
-        n3 = Bj[(size_t)min(rn + 3, n - 1) * Gj];
-      }
-      const float y0 = team_sum<TEAM>(dot4(c0, pv[j]));
-      const float y1 = team_sum<TEAM>(dot4(c1, pv[j]));
-      float y2 = team_sum<TEAM>(dot4(c2, pv[j]));
-      float y3 = team_sum<TEAM>(dot4(c3, pv[j]));
-      if (r + 2 >= n) y2 = y3 = 0.f;
-      axpy4(z, y0, c0);
-      axpy4(z, y1, c1);
-      axpy4(z, y2, c2);
-      axpy4(z, y3, c3);
-      c0 = n0; c1 = n1; c2 = n2; c3 = n3;
-    }
-    if (lane < Gj) store_cols(d, zoff[j], lane, z);
+    for (int i = 0; i < RB; ++i) axpy4(z, r + i < n ? y[i] : 0.f, c[i]);
+#pragma unroll
+    for (int i = 0; i < RB; ++i) c[i] = nx[i];
   }
+  if (lane < G) store_cols(d, zoff, lane, z);
 }
 
 // Matrix-free product for large landmarks: a workgroup of 4 wavefronts per
-// landmark.  Wave w takes rows w, w+4, ...; each lane owns up to NCG column
-// groups (strided by 64).  With PREFETCH the next row of the wave is requested
-// before the current one is reduced.  The 4 partial z vectors are summed
-// through LDS in a fixed order.
-template <int NCG, bool PREFETCH, bool PCG>
+// landmark.  Wave w takes rows w, w+4, ... in steps of RS rows (w, w+4, ...,
+// w+4(RS-1)); each lane owns up to NCG column groups (strided by 64).  The next
+// step's rows are requested before the current ones are reduced.  The 4
+// partial z vectors are summed through LDS in a fixed order.
+template <int NCG, int RS, bool PCG>
 __device__ __forceinline__ void matvec_large(const Dev& d, int slot, const float* v, float4 (*zred)[64]) {
   const int prob = d.slot_prob[slot];
   const int k = d.slot_k[slot];
@@ -843,47 +816,49 @@ __device__ __forceinline__ void matvec_large(const Dev& d, int slot, const float
   const int n = 2 * k;
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  float4 b[NCG], pv[NCG], z[NCG];
-  if constexpr (PREFETCH) {
+  auto load = [&](int r, float4 (&b)[RS][NCG]) {
 #pragma unroll
-    for (int j = 0; j < NCG; ++j) {
-      b[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (64 * j < G) b[j] = B[(size_t)w * G + min(lane + 64 * j, G - 1)];  // n >= 8 > w
+    for (int i = 0; i < RS; ++i) {
+      const int rr = min(r + 4 * i, n - 1);
+#pragma unroll
+      for (int j = 0; j < NCG; ++j) {
+        b[i][j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (64 * j < G) b[i][j] = B[(size_t)rr * G + min(lane + 64 * j, G - 1)];
+      }
     }
-  }
+  };
+  float4 b[RS][NCG], pv[NCG], z[NCG];
+  load(w, b);  // n >= 58 > w
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
     const int g = lane + 64 * j;
     pv[j] = g < G ? gather_cols(d, v, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
     z[j] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  for (int r = w; r < n; r += 4) {
-    float4 nb[NCG];
-    if constexpr (PREFETCH) {
-      const bool more = r + 4 < n;
-#pragma unroll
-      for (int j = 0; j < NCG; ++j) {
-        nb[j] = b[j];
-        if (more && 64 * j < G) nb[j] = B[(size_t)(r + 4) * G + min(lane + 64 * j, G - 1)];
-      }
+  for (int r = w; r < n; r += 4 * RS) {
+    float4 nb[RS][NCG];
+    if (r + 4 * RS < n) {
+      load(r + 4 * RS, nb);
     } else {
-      const float4* row = B + (size_t)r * G + lane;
 #pragma unroll
-      for (int j = 0; j < NCG; ++j) {
-        b[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (lane + 64 * j < G) b[j] = row[64 * j];
-      }
+      for (int i = 0; i < RS; ++i)
+#pragma unroll
+        for (int j = 0; j < NCG; ++j) nb[i][j] = b[i][j];
     }
-    float y = 0.f;
 #pragma unroll
-    for (int j = 0; j < NCG; ++j) y += dot4(b[j], pv[j]);
-    y = wave_sum_f(y);
+    for (int i = 0; i < RS; ++i) {
+      float y = 0.f;
 #pragma unroll
-    for (int j = 0; j < NCG; ++j) axpy4(z[j], y, b[j]);
-    if constexpr (PREFETCH) {
+      for (int j = 0; j < NCG; ++j) y += dot4(b[i][j], pv[j]);
+      y = wave_sum_f(y);
+      if (r + 4 * i >= n) y = 0.f;  // clamped re-read of the last row
 #pragma unroll
-      for (int j = 0; j < NCG; ++j) b[j] = nb[j];
+      for (int j = 0; j < NCG; ++j) axpy4(z[j], y, b[i][j]);
     }
+#pragma unroll
+    for (int i = 0; i < RS; ++i)
+#pragma unroll
+      for (int j = 0; j < NCG; ++j) b[i][j] = nb[i][j];
   }
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
@@ -901,38 +876,132 @@ __device__ __forceinline__ void matvec_large(const Dev& d, int slot, const float
   }
 }
 
-// Landmarks per team of the small classes (3, 2, 1, 0 in launch order).
-#ifndef SQRTBA_MV_LPT
-#define SQRTBA_MV_LPT 1, 1, 1, 1
+// Rows per batch of the small classes (3, 2, 1, 0 in launch order) and rows
+// per wavefront step of class 4.
+#ifndef SQRTBA_MV_RB
+#define SQRTBA_MV_RB 4, 4, 4, 4
 #endif
-constexpr int MV_LPT[4] = {SQRTBA_MV_LPT};
+#ifndef SQRTBA_MV_RS
+#define SQRTBA_MV_RS 1
+#endif
+constexpr int MV_RB[4] = {SQRTBA_MV_RB};
+constexpr int MV_RS = SQRTBA_MV_RS;
 __host__ __device__ constexpr int mv_per_wg(int j) {  // j: launch-order class index 0..4
-  return j == 0 ? 1 : (WG / class_team(4 - j)) * MV_LPT[j - 1];
+  return j == 0 ? 1 : WG / class_team(4 - j);
 }
 
-// One launch for the size classes 0..4: every workgroup belongs to one class,
-// so the whole product over landmarks with k <= 113 is a single kernel with
-// no tail gaps between classes.
-template <bool PCG>
+// One launch for the size classes 0..3 (and 4 when LARGE): every workgroup
+// belongs to one class, so the product over these landmarks is a single
+// kernel with no tail gaps between classes.  Without LARGE the kernel holds no
+// class-4 code and needs fewer registers (more resident wavefronts); class 4
+// then runs as its own launch (k_matvec_large).
+template <bool PCG, bool LARGE>
 __global__ __launch_bounds__(WG) void k_matvec(Dev d, MvGrid m, const float* v) {
-  __shared__ float4 zred[4][64];
   int b = blockIdx.x;
-  if (b < m.nblk[0]) { matvec_large<4, true, PCG>(d, m.first[0] + b, v, zred); return; }
-  b -= m.nblk[0];
-  if (b < m.nblk[1]) { matvec_teams<64, MV_LPT[0], PCG>(d, m.first[1] + b * mv_per_wg(1), m.end[1], v); return; }
+  if constexpr (LARGE) {
+    __shared__ float4 zred[4][64];
+    if (b < m.nblk[0]) { matvec_large<4, MV_RS, PCG>(d, m.first[0] + b, v, zred); return; }
+    b -= m.nblk[0];
+  }
+  if (b < m.nblk[1]) { matvec_teams<64, MV_RB[0], PCG>(d, m.first[1] + b * mv_per_wg(1), m.end[1], v); return; }
   b -= m.nblk[1];
-  if (b < m.nblk[2]) { matvec_teams<32, MV_LPT[1], PCG>(d, m.first[2] + b * mv_per_wg(2), m.end[2], v); return; }
+  if (b < m.nblk[2]) { matvec_teams<32, MV_RB[1], PCG>(d, m.first[2] + b * mv_per_wg(2), m.end[2], v); return; }
   b -= m.nblk[2];
-  if (b < m.nblk[3]) { matvec_teams<16, MV_LPT[2], PCG>(d, m.first[3] + b * mv_per_wg(3), m.end[3], v); return; }
+  if (b < m.nblk[3]) { matvec_teams<16, MV_RB[2], PCG>(d, m.first[3] + b * mv_per_wg(3), m.end[3], v); return; }
   b -= m.nblk[3];
-  matvec_teams<8, MV_LPT[3], PCG>(d, m.first[4] + b * mv_per_wg(4), m.end[4], v);
+  matvec_teams<8, MV_RB[3], PCG>(d, m.first[4] + b * mv_per_wg(4), m.end[4], v);
 }
 
-// Landmarks with k > 113 (up to 512): four wavefronts per landmark.
+// Class 4 on its own: one landmark per workgroup.
 template <bool PCG>
-__global__ __launch_bounds__(WG) void k_matvec_huge(Dev d, int slot0, const float* v) {
+__global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int slot0, const float* v) {
   __shared__ float4 zred[4][64];
-  matvec_large<18, false, PCG>(d, slot0 + blockIdx.x, v, zred);
+  matvec_large<4, MV_RS, PCG>(d, slot0 + blockIdx.x, v, zred);
+}
+
+// Landmarks with k > 113 (up to 512), split into blocks of HUGE_ROWS rows so
+// that a few very large landmarks still spread over the whole chip: job j
+// (slot, row block) runs on one workgroup of four wavefronts (wave w takes
+// rows w, w+4, ... of the block) and writes its partial z for the block; a
+// landmark with a single block writes its outputs directly.
+template <bool PCG>
+__global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, const float* v) {
+  constexpr int NCG = 18;  // ceil(width_of(512) / 4 / 64)
+  __shared__ float4 zred[4][64];
+  const int2 job = d.hjob[blockIdx.x];
+  const int slot = job.x;
+  const int prob = d.slot_prob[slot];
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
+  if (!d.active[prob] || (PCG && d.done[prob])) return;
+  const int G = width_of(k) >> 2;
+  const int n = 2 * k;
+  const int r0 = job.y * HUGE_ROWS, r1 = min(n, r0 + HUGE_ROWS);
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  float4 b[NCG], pv[NCG], z[NCG];
+#pragma unroll
+  for (int j = 0; j < NCG; ++j) {
+    const int g = lane + 64 * j;
+    pv[j] = g < G ? gather_cols(d, v, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
+    z[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  for (int r = r0 + w; r < r1; r += 4) {
+    const float4* row = B + (size_t)r * G + lane;
+#pragma unroll
+    for (int j = 0; j < NCG; ++j) {
+      b[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (lane + 64 * j < G) b[j] = row[64 * j];
+    }
+    float y = 0.f;
+#pragma unroll
+    for (int j = 0; j < NCG; ++j) y += dot4(b[j], pv[j]);
+    y = wave_sum_f(y);
+#pragma unroll
+    for (int j = 0; j < NCG; ++j) axpy4(z[j], y, b[j]);
+  }
+  const bool single = n <= HUGE_ROWS;
+  float4* dst = single ? reinterpret_cast<float4*>(d.obsbuf + d.slot_zoff[slot])
+                       : reinterpret_cast<float4*>(d.zpart + d.hz_off[slot - slot0] + (size_t)job.y * (4 * G));
+#pragma unroll
+  for (int j = 0; j < NCG; ++j) {
+    if (64 * j >= G) break;  // uniform across the workgroup
+    zred[w][lane] = z[j];
+    __syncthreads();
+    if (w == 0) {
+      const float4 a = zred[0][lane], b2 = zred[1][lane], c = zred[2][lane], e = zred[3][lane];
+      const float4 s = make_float4((a.x + b2.x) + (c.x + e.x), (a.y + b2.y) + (c.y + e.y),
+                                   (a.z + b2.z) + (c.z + e.z), (a.w + b2.w) + (c.w + e.w));
+      const int g = lane + 64 * j;
+      if (g < G) dst[g] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Sum of the row-block partials of every class-5 landmark with more than one
+// block, in block order, into its outputs (one workgroup per landmark).
+template <bool PCG>
+__global__ __launch_bounds__(WG) void k_matvec_combine(Dev d, int slot0) {
+  const int slot = slot0 + blockIdx.x;
+  const int prob = d.slot_prob[slot];
+  const int k = d.slot_k[slot];
+  if (!d.active[prob] || (PCG && d.done[prob])) return;
+  const int n = 2 * k;
+  if (n <= HUGE_ROWS) return;
+  const int nblk = (n + HUGE_ROWS - 1) / HUGE_ROWS;
+  const int G = width_of(k) >> 2;
+  const float4* __restrict__ src = reinterpret_cast<const float4*>(d.zpart + d.hz_off[blockIdx.x]);
+  float4* dst = reinterpret_cast<float4*>(d.obsbuf + d.slot_zoff[slot]);
+  for (int g = threadIdx.x; g < G; g += WG) {
+    float4 s = src[g];
+    for (int r = 1; r < nblk; ++r) {
+      const float4 t = src[(size_t)r * G + g];
+      s.x += t.x; s.y += t.y; s.z += t.z; s.w += t.w;
+    }
+    dst[g] = s;
+  }
 }
 
 // ----------------------------------------------------- PCG vector kernels
@@ -1044,7 +1113,21 @@ __device__ __forceinline__ int pcg_test(const Dev& d, int p, double rz, double r
   return rz > 0.0 ? 0 : 2;
 }
 
-// Per camera (one workgroup).
+// Per camera (one workgroup).  The gather takes the camera's observations in
+// rounds of 4 per thread: the 4 output positions of a round are requested
+// together (and those of the next round before the current values are
+// summed), so a camera costs one position latency plus one value latency per
+// round.  Wave 0 forms the problem sums while its first positions load.
+constexpr int Q_UNROLL = 4;
+
+__device__ __forceinline__ void q_positions(const Dev& d, int i0, int e, int zp[Q_UNROLL]) {
+#pragma unroll
+  for (int j = 0; j < Q_UNROLL; ++j) {
+    const int i = i0 + (int)threadIdx.x + j * WG;
+    zp[j] = i < e ? d.cam_zpos[i] : -1;
+  }
+}
+
 __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
   __shared__ float part[4][9];
   __shared__ float pqs[9];
@@ -1064,6 +1147,8 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
     sc = d.s_cam[idx];
   }
   if (!d.active[prob] || d.done[prob]) return;  // uniform over the workgroup
+  int zp[Q_UNROLL];
+  q_positions(d, b, e, zp);
   if (w == 0) {
     double rz, rr;
     problem_sum2(d, d.cam_part2, d.cam_part3, prob, lane, rz, rr);
@@ -1087,10 +1172,22 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
   float acc[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = 0.f;
-  for (int i = b + (int)threadIdx.x; i < e; i += WG) {
-    const float* src = d.obsbuf + d.cam_zpos[i];
+  for (int i0 = b; i0 < e; i0 += Q_UNROLL * WG) {
+    int nz[Q_UNROLL];
+    const bool more = i0 + Q_UNROLL * WG < e;  // uniform
+    if (more) q_positions(d, i0 + Q_UNROLL * WG, e, nz);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) acc[a] += src[a];
+    for (int j = 0; j < Q_UNROLL; ++j) {
+      if (zp[j] >= 0) {
+        const float* src = d.obsbuf + zp[j];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) acc[a] += src[a];
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < Q_UNROLL; ++j) zp[j] = nz[j];
+    }
   }
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = wave_sum_f(acc[a]);
@@ -1139,7 +1236,7 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
   const bool valid = c < d.NC && lc < UPD_CAMS;
   // loads that do not depend on alpha first
   int prob = 0;
-  float xv = 0.f, pv = 0.f, rv = 0.f, qv = 0.f;
+  float xv = 0.f, pv = 0.f, rv = 0.f, qv = 0.f, mrow[9];
   const int idx = 9 * c + a;
   if (valid) {
     prob = d.cam_prob[c];
@@ -1147,6 +1244,9 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
     pv = d.vp[idx];
     rv = d.vr[idx];
     qv = d.vq[idx];
+    const float* mi = d.minv + 81 * (size_t)c + 9 * a;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) mrow[j] = mi[j];
   }
   if (w == 0) {
     // the problems of cameras c0 .. c0 + UPD_CAMS - 1 form runs; one alpha per run
@@ -1195,9 +1295,8 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
   if (lc < UPD_CAMS) rs[lc][a] = r;
   __syncthreads();
   if (live) {
-    const float* mi = d.minv + 81 * (size_t)c + 9 * a;
 #pragma unroll
-    for (int j = 0; j < 9; ++j) z += mi[j] * rs[lc][j];
+    for (int j = 0; j < 9; ++j) z += mrow[j] * rs[lc][j];
     d.vz[idx] = z;
   }
   if (lc < UPD_CAMS) {
@@ -1521,35 +1620,42 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
 // The landmarks with k > 113 (few, each a long stream for one workgroup) run
 // on a side stream concurrently with the main product, forked from and joined
 // back into the context stream by events (also inside captured graphs).
+// Product over all landmark blocks on the context stream: the class-5 row
+// blocks, class 4 (inside the main launch when it is small, else on its own),
+// classes 0..3, then the sum of the class-5 partials.
 template <bool PCG>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
   const WorkClass* w = L.wc;
-  const bool fork = w[5].slots && L.side && L.fork && L.join;
-  if (fork) {
-    hipError_t e = hipEventRecord(L.fork, L.stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(L.side, L.fork, 0);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_matvec_huge<PCG>, dim3(w[5].slots), dim3(WG), 0, L.side, d, w[5].first_slot, v);
+  const bool huge = w[5].slots > 0 && L.hjobs > 0;
+  if (huge) {
+    hipLaunchKernelGGL(k_matvec_rows<PCG>, dim3(L.hjobs), dim3(WG), 0, L.stream, d, w[5].first_slot, v);
     LAUNCH_CHECK();
-  } else if (w[5].slots) {
-    hipLaunchKernelGGL(k_matvec_huge<PCG>, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot, v);
+  }
+  const bool split = w[4].slots >= L.large_split;
+  if (split && w[4].slots) {
+    hipLaunchKernelGGL(k_matvec_large<PCG>, dim3(w[4].slots), dim3(WG), 0, L.stream, d, w[4].first_slot, v);
+    LAUNCH_CHECK();
   }
   MvGrid m;
   int n = 0;
   for (int j = 0; j < 5; ++j) {
     const WorkClass& c = w[4 - j];
     const int per = mv_per_wg(j);
-    m.nblk[j] = (c.slots + per - 1) / per;
+    m.nblk[j] = (j == 0 && split) ? 0 : (c.slots + per - 1) / per;
     m.first[j] = c.first_slot;
     m.end[j] = c.first_slot + c.slots;
     n += m.nblk[j];
   }
-  if (n) hipLaunchKernelGGL(k_matvec<PCG>, dim3(n), dim3(WG), 0, L.stream, d, m, v);
-  LAUNCH_CHECK();
-  if (fork) {
-    hipError_t e = hipEventRecord(L.join, L.side);
-    if (e == hipSuccess) e = hipStreamWaitEvent(L.stream, L.join, 0);
-    if (e != hipSuccess) return e;
+  if (n) {
+    if (m.nblk[0])
+      hipLaunchKernelGGL((k_matvec<PCG, true>), dim3(n), dim3(WG), 0, L.stream, d, m, v);
+    else
+      hipLaunchKernelGGL((k_matvec<PCG, false>), dim3(n), dim3(WG), 0, L.stream, d, m, v);
+    LAUNCH_CHECK();
+  }
+  if (huge) {
+    hipLaunchKernelGGL(k_matvec_combine<PCG>, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot);
+    LAUNCH_CHECK();
   }
   return hipSuccess;
 }
