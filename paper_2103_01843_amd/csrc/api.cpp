@@ -47,7 +47,6 @@ struct HostData {
   std::vector<int64_t> slot_boff, slot_toff;
   std::vector<int32_t> slot_zoff, cam_zpos;
   std::vector<float> cam_stats;  // NC * 4 features of the camera's observation graph
-  std::vector<int32_t> wi_first, wi_count;
   WorkClass wc[NUM_CLASSES];
   std::vector<int32_t> hjob;   // (slot, row block) pairs of the split class-5 product
   std::vector<int64_t> hz_off; // per class-5 slot, offset of its partial outputs
@@ -336,23 +335,12 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
   }
   nb.poolB = ob;
   nb.poolT = ot;
-  // work items: classes are contiguous k ranges, and slots are sorted by k
-  nb.wi_first.clear();
-  nb.wi_count.clear();
+  // size classes: contiguous k ranges, and slots are sorted by decreasing k
   for (int cl = NUM_CLASSES - 1; cl >= 0; --cl) {
-    nb.wc[cl].first_wi = (int)nb.wi_first.size();
-    const int tpw = 256 / class_team(cl);
     int64_t s = 0;
     while (s < nb.NS && class_of_k(nb.slot_k[s]) != cl) ++s;
     nb.wc[cl].first_slot = (int)s;
-    while (s < nb.NS && class_of_k(nb.slot_k[s]) == cl) {
-      int cnt = 0;
-      const int64_t s0 = s;
-      while (s < nb.NS && cnt < tpw && class_of_k(nb.slot_k[s]) == cl) { ++s; ++cnt; }
-      nb.wi_first.push_back((int32_t)s0);
-      nb.wi_count.push_back(cnt);
-    }
-    nb.wc[cl].count = (int)nb.wi_first.size() - nb.wc[cl].first_wi;
+    while (s < nb.NS && class_of_k(nb.slot_k[s]) == cl) ++s;
     nb.wc[cl].slots = (int)(s - nb.wc[cl].first_slot);
   }
   // split product of class 5: row blocks of HUGE_ROWS rows, partial outputs per block
@@ -435,7 +423,7 @@ T* at(void* base, uint64_t off) {
 // Offsets of every device array; when base is null only the size is computed.
 uint64_t layout(const HostData& h, void* base, Dev* d) {
   Layout L;
-  const uint64_t NC = h.NC, NL = h.NL, NO = h.NO, NS = h.NS, P = h.P, NW = h.wi_first.size();
+  const uint64_t NC = h.NC, NL = h.NL, NO = h.NO, NS = h.NS, P = h.P;
   Dev t{};
   auto f32 = [&](uint64_t n) { return L.take(4 * n); };
   auto f64 = [&](uint64_t n) { return L.take(8 * n); };
@@ -444,7 +432,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
   uint64_t o_cpr = f32(NC), o_lpr = f32(NL), o_pco = f32(P + 1), o_plo = f32(P + 1);
   uint64_t o_slm = f32(NS), o_sk = f32(NS), o_so = f32(NS), o_sp = f32(NS), o_sb = f64(NS), o_st = f64(NS);
   uint64_t o_sz = f32(NS), o_czp = f32(NO);
-  uint64_t o_lms = f32(NL), o_wf = f32(NW), o_wc = f32(NW);
+  uint64_t o_lms = f32(NL);
   uint64_t o_hj = f32(h.hjob.size()), o_hzo = f64(h.hz_off.size()), o_zp = f32(h.hz_floats);
   uint64_t o_pB = f32(h.poolB), o_pT = f32(h.poolT), o_lmd = f32(NS * LMD_STRIDE), o_rho = f32(2 * NO);
   uint64_t o_sc = f32(9 * NC);
@@ -469,7 +457,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
     t.slot_lm = at<int32_t>(base, o_slm); t.slot_k = at<int32_t>(base, o_sk); t.slot_obs0 = at<int32_t>(base, o_so);
     t.slot_prob = at<int32_t>(base, o_sp); t.slot_boff = at<int64_t>(base, o_sb); t.slot_toff = at<int64_t>(base, o_st);
     t.slot_zoff = at<int32_t>(base, o_sz); t.cam_zpos = at<int32_t>(base, o_czp);
-    t.lm_slot = at<int32_t>(base, o_lms); t.wi_first = at<int32_t>(base, o_wf); t.wi_count = at<int32_t>(base, o_wc);
+    t.lm_slot = at<int32_t>(base, o_lms);
     t.hjob = at<int2>(base, o_hj); t.hz_off = at<int64_t>(base, o_hzo); t.zpart = at<float>(base, o_zp);
     t.poolB = at<float>(base, o_pB); t.poolT = at<float>(base, o_pT); t.lmd = at<float>(base, o_lmd);
     t.rhoB = at<float>(base, o_rho); t.s_cam = at<float>(base, o_sc);
@@ -608,8 +596,6 @@ int upload(sqrtba_ctx* c) {
   TRY(upload_vec(c, d.slot_zoff, h.slot_zoff));
   TRY(upload_vec(c, d.cam_zpos, h.cam_zpos));
   TRY(upload_vec(c, d.lm_slot, h.lm_slot));
-  TRY(upload_vec(c, d.wi_first, h.wi_first));
-  TRY(upload_vec(c, d.wi_count, h.wi_count));
   TRY(upload_vec(c, reinterpret_cast<int32_t*>(d.hjob), h.hjob));
   TRY(upload_vec(c, d.hz_off, h.hz_off));
   TRY(upload_vec(c, d.cam_stats, h.cam_stats));

@@ -59,9 +59,6 @@ struct Dev {
   int32_t* slot_zoff;  // float offset of the landmark's W product outputs in obsbuf (16-byte aligned)
   int32_t* cam_zpos;   // NO: obsbuf offset of the outputs of each camera's observations (camera order)
   int32_t* lm_slot;    // NL, -1 when inactive
-  // work items: per class, a list of (first slot, count)
-  int32_t* wi_first;
-  int32_t* wi_count;
   // split product of the largest landmarks (class 5): one job per block of
   // HUGE_ROWS rows (x: slot, y: row block), partial outputs per row block
   int2* hjob;
@@ -111,8 +108,6 @@ struct Dev {
 };
 
 struct WorkClass {
-  int first_wi;    // first work item of this class
-  int count;       // number of work items (workgroups)
   int first_slot;  // first slot of this class (slots of a class are contiguous)
   int slots;       // number of slots
 };

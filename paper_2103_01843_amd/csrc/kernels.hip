@@ -224,18 +224,52 @@ __global__ __launch_bounds__(SUM_THREADS) void k_prob_sum(const double* __restri
 // once, coalesced, as float4 rows.
 //   rows 0..2   -> undamped top rows [Q1^T J_p | R1 | Q1^T r] (poolT, lmd)
 //   rows 3..2k-1 -> nullspace rows [Q2^T J_p | 0 | Q2^T r]    (poolB, rhoB)
+// Slot ranges of the size classes, in launch order (class 4, 3, 2, 1, 0):
+// workgroup b of class j takes slots first[j] + b * (WG / team size) onwards
+// (one slot per workgroup for class 4).  The slot of every team follows from
+// blockIdx and these kernel arguments alone.
+struct ClassGrid {
+  int nblk[5];
+  int first[5];
+  int end[5];
+};
+
+// Runs f.run<TEAM, CLASS>(slot, lane, team) for the team of this thread in a
+// launch over the classes 4..0 described by m (classes with nblk 0 are absent).
+template <class F>
+__device__ __forceinline__ void class_dispatch(const ClassGrid& m, const F& f) {
+  int b = blockIdx.x;
+  if (b < m.nblk[0]) { f.template run<256, 4>(m.first[0] + b, threadIdx.x, 0); return; }
+  b -= m.nblk[0];
+  if (b < m.nblk[1]) {
+    const int t = threadIdx.x / 64, slot = m.first[1] + b * (WG / 64) + t;
+    if (slot < m.end[1]) f.template run<64, 3>(slot, threadIdx.x % 64, t);
+    return;
+  }
+  b -= m.nblk[1];
+  if (b < m.nblk[2]) {
+    const int t = threadIdx.x / 32, slot = m.first[2] + b * (WG / 32) + t;
+    if (slot < m.end[2]) f.template run<32, 2>(slot, threadIdx.x % 32, t);
+    return;
+  }
+  b -= m.nblk[2];
+  if (b < m.nblk[3]) {
+    const int t = threadIdx.x / 16, slot = m.first[3] + b * (WG / 16) + t;
+    if (slot < m.end[3]) f.template run<16, 1>(slot, threadIdx.x % 16, t);
+    return;
+  }
+  b -= m.nblk[3];
+  const int t = threadIdx.x / 8, slot = m.first[4] + b * (WG / 8) + t;
+  if (slot < m.end[4]) f.template run<8, 0>(slot, threadIdx.x % 8, t);
+}
+
+// LDS floats per team: A (2k x 4, J_l scaled, updated in place), V (2k x 4),
+// r (2k), Jp (k x 18).
+__host__ __device__ constexpr int marg_stride(int kmax) { return 36 * kmax; }
+
 template <int TEAM, int KMAX>
-__global__ __launch_bounds__(WG) void k_marginalize(Dev d, int wi0, const uint8_t* mask) {
-  constexpr int TPW = WG / TEAM;  // teams per workgroup
-  // LDS per team: A (2k x 4, J_l scaled, updated in place), V (2k x 4), r (2k), Jp (k x 18)
-  constexpr int STRIDE = 8 * 2 * KMAX + 2 * KMAX + 18 * KMAX;
-  __shared__ float lds[TPW * STRIDE];
-  __shared__ float red4[4];
-  const int team = threadIdx.x / TEAM;
-  const int lane = threadIdx.x % TEAM;
-  const int wi = wi0 + blockIdx.x;
-  if (team >= d.wi_count[wi]) return;  // whole teams drop out together
-  const int slot = d.wi_first[wi] + team;
+__device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane, float* lds, float* red4,
+                                                const uint8_t* mask) {
   const int prob = d.slot_prob[slot];
   if (mask && !mask[prob]) return;
   const int k = d.slot_k[slot];
@@ -243,7 +277,7 @@ __global__ __launch_bounds__(WG) void k_marginalize(Dev d, int wi0, const uint8_
   const int n = 2 * k;
   const int W = width_of(k);
   const int G = W >> 2;
-  float4* A = reinterpret_cast<float4*>(lds + team * STRIDE);
+  float4* A = reinterpret_cast<float4*>(lds);
   float4* V = A + 2 * KMAX;
   float* rr = reinterpret_cast<float*>(V + 2 * KMAX);
   float* Jpc = rr + 2 * KMAX;
@@ -492,12 +526,7 @@ __device__ __forceinline__ void rotate_column(const Givens6& G, float t[3], floa
 // lambda never needs a new QR): writes the three damping rows of B, their
 // residuals, and the damped R and Q1^T r into the landmark record.
 template <int TEAM>
-__global__ __launch_bounds__(WG) void k_damp(Dev d, int wi0, const uint8_t* mask) {
-  const int team = threadIdx.x / TEAM;
-  const int lane = threadIdx.x % TEAM;
-  const int wi = wi0 + blockIdx.x;
-  if (team >= d.wi_count[wi]) return;
-  const int slot = d.wi_first[wi] + team;
+__device__ __forceinline__ void damp_one(const Dev& d, int slot, int lane, const uint8_t* mask) {
   const int prob = d.slot_prob[slot];
   if (mask && !mask[prob]) return;
   const int k = d.slot_k[slot];
@@ -538,12 +567,7 @@ __global__ __launch_bounds__(WG) void k_damp(Dev d, int wi0, const uint8_t* mask
 // G_j = B_j^T B_j (45 upper entries) and g_j = B_j^T rho_B, unscaled, written
 // to obsbuf[obs][0..53].  One lane owns one observation and walks the rows.
 template <int TEAM>
-__global__ __launch_bounds__(WG) void k_precond_obs(Dev d, int wi0) {
-  const int team = threadIdx.x / TEAM;
-  const int lane = threadIdx.x % TEAM;
-  const int wi = wi0 + blockIdx.x;
-  if (team >= d.wi_count[wi]) return;
-  const int slot = d.wi_first[wi] + team;
+__device__ __forceinline__ void precond_one(const Dev& d, int slot, int lane) {
   const int prob = d.slot_prob[slot];
   if (!d.active[prob]) return;
   const int k = d.slot_k[slot];
@@ -557,6 +581,7 @@ __global__ __launch_bounds__(WG) void k_precond_obs(Dev d, int wi0) {
     for (int e = 0; e < 45; ++e) g[e] = 0.f;
 #pragma unroll
     for (int e = 0; e < 9; ++e) h[e] = 0.f;
+#pragma unroll 2
     for (int r = 0; r < 2 * k; ++r) {
       const float* row = B + (size_t)r * W + 9 * o;
       float b[9];
@@ -740,14 +765,6 @@ __device__ __forceinline__ void store_cols(const Dev& d, int zoff, int g, float4
   reinterpret_cast<float4*>(d.obsbuf + zoff)[g] = z;
 }
 
-// Slot ranges of the size classes, in launch order (class 4, 3, 2, 1, 0):
-// workgroup b of class j takes slots first[j] + b * per_wg[j] onwards.  The
-// slot of every team follows from blockIdx and these kernel arguments alone.
-struct MvGrid {
-  int nblk[5];
-  int first[5];
-  int end[5];
-};
 
 // In PCG mode (the template flag PCG) the product skips the landmarks of
 // problems whose solve has ended; otherwise every active landmark is done.
@@ -896,7 +913,7 @@ __host__ __device__ constexpr int mv_per_wg(int j) {  // j: launch-order class i
 // class-4 code and needs fewer registers (more resident wavefronts); class 4
 // then runs as its own launch (k_matvec_large).
 template <bool PCG, bool LARGE>
-__global__ __launch_bounds__(WG) void k_matvec(Dev d, MvGrid m, const float* v) {
+__global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, const float* v) {
   int b = blockIdx.x;
   if constexpr (LARGE) {
     __shared__ float4 zred[4][64];
@@ -1344,13 +1361,7 @@ __global__ __launch_bounds__(WG) void k_pcg_final(Dev d) {
 // undamped linear model, summed over all its rotated rows:
 //   pred_l = -sum u (2 rho + u) + lambda |dx~_l|^2,   u = rows . (S dx_p, dx~_l).
 template <int TEAM, int NCG>
-__global__ __launch_bounds__(WG) void k_backsub(Dev d, int wi0) {
-  __shared__ float red4[4];
-  const int team = threadIdx.x / TEAM;
-  const int lane = threadIdx.x % TEAM;
-  const int wi = wi0 + blockIdx.x;
-  if (team >= d.wi_count[wi]) return;
-  const int slot = d.wi_first[wi] + team;
+__device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, float* red4) {
   const int prob = d.slot_prob[slot];
   const int lm = d.slot_lm[slot];
   if (!d.active[prob]) return;
@@ -1420,6 +1431,171 @@ __global__ __launch_bounds__(WG) void k_backsub(Dev d, int wi0) {
     d.dxl[3 * (size_t)lm + 2] = sl[2] * x2;
     d.lm_part[lm] = pred;
   }
+}
+
+// Large landmarks (one workgroup of 4 wavefronts): the B rows are split over
+// the wavefronts as in the product (wave w takes rows w, w+4, ...), with no
+// workgroup barrier per row; wave 0 also forms the damped top-row terms and
+// dx~_l.  The four partial predictions are added in a fixed order.
+template <int NCG>
+__device__ __forceinline__ void backsub_large(const Dev& d, int slot, double* predw) {
+  const int prob = d.slot_prob[slot];
+  const int lm = d.slot_lm[slot];
+  if (!d.active[prob]) return;  // uniform over the workgroup
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const int G = width_of(k) >> 2;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
+  float4 pv[NCG];
+#pragma unroll
+  for (int j = 0; j < NCG; ++j) {
+    const int g = lane + 64 * j;
+    pv[j] = g < G ? gather_cols(d, d.vx, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  const float* rho = d.rhoB + 2 * (size_t)obs0;
+  double pred = 0.0;
+  for (int r = w; r < 2 * k; r += 4) {
+    const float4* row = B + (size_t)r * G + lane;
+    float y = 0.f;
+#pragma unroll
+    for (int j = 0; j < NCG; ++j)
+      if (lane + 64 * j < G) y += dot4(row[64 * j], pv[j]);
+    y = wave_sum_f(y);
+    if (lane == 0) pred -= (double)(y * (2.f * rho[r] + y));
+  }
+  if (lane == 0) predw[w] = pred;
+  if (w == 0) {
+    const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+    const float lam = (float)d.lambda[prob];
+    Givens6 Gv;
+    float Rh[3][3], qrh[3], dr[3];
+    damping_rotations(lmd, sqrtf(lam), Gv, Rh, qrh, dr);
+    const float4* T = reinterpret_cast<const float4*>(d.poolT + d.slot_toff[slot]);
+    float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < NCG; ++j) {
+      const int g = lane + 64 * j;
+      if (g < G) {
+        const float4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
+        float a[3], b[3];
+        a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b);
+        u0 += a[0] * pv[j].x; u1 += a[1] * pv[j].x; u2 += a[2] * pv[j].x;
+        a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b);
+        u0 += a[0] * pv[j].y; u1 += a[1] * pv[j].y; u2 += a[2] * pv[j].y;
+        a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, b);
+        u0 += a[0] * pv[j].z; u1 += a[1] * pv[j].z; u2 += a[2] * pv[j].z;
+        a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, b);
+        u0 += a[0] * pv[j].w; u1 += a[1] * pv[j].w; u2 += a[2] * pv[j].w;
+      }
+    }
+    u0 = wave_sum_f(u0);
+    u1 = wave_sum_f(u1);
+    u2 = wave_sum_f(u2);
+    const float c0 = -(qrh[0] + u0), c1 = -(qrh[1] + u1), c2 = -(qrh[2] + u2);
+    const float x2 = c2 / Rh[2][2];
+    const float x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
+    const float x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
+    if (lane == 0) {
+      const float ut0 = u0 + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
+      const float ut1 = u1 + Rh[1][1] * x1 + Rh[1][2] * x2;
+      const float ut2 = u2 + Rh[2][2] * x2;
+      const double top = -(double)(ut0 * (2.f * qrh[0] + ut0)) - (double)(ut1 * (2.f * qrh[1] + ut1)) -
+                         (double)(ut2 * (2.f * qrh[2] + ut2)) +
+                         (double)lam * ((double)x0 * x0 + (double)x1 * x1 + (double)x2 * x2);
+      const float* sl = lmd + LMD_SL;
+      d.dxl[3 * (size_t)lm + 0] = sl[0] * x0;
+      d.dxl[3 * (size_t)lm + 1] = sl[1] * x1;
+      d.dxl[3 * (size_t)lm + 2] = sl[2] * x2;
+      predw[4] = top;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) d.lm_part[lm] = predw[4] + ((predw[0] + predw[1]) + (predw[2] + predw[3]));
+}
+
+// ---------------------------------------------- per-landmark stage launches
+//
+// Classes 0..4 of each per-landmark stage run as one launch (class_dispatch);
+// class 5 has its own launch.
+
+struct MargF {
+  const Dev& d;
+  const uint8_t* mask;
+  float* lds;
+  float* red4;
+  template <int TEAM, int CLS>
+  __device__ void run(int slot, int lane, int team) const {
+    marginalize_one<TEAM, class_kmax(CLS)>(d, slot, lane, lds + team * marg_stride(class_kmax(CLS)), red4, mask);
+  }
+};
+
+constexpr int MARG_LDS_SMALL = marg_stride(class_kmax(4));  // >= (WG / team) * marg_stride of classes 0..3
+static_assert(MARG_LDS_SMALL >= 32 * marg_stride(3) && MARG_LDS_SMALL >= 16 * marg_stride(7) &&
+                  MARG_LDS_SMALL >= 8 * marg_stride(14) && MARG_LDS_SMALL >= 4 * marg_stride(28),
+              "LDS of the merged marginalization launch");
+
+__global__ __launch_bounds__(WG) void k_marginalize(Dev d, ClassGrid m, const uint8_t* mask) {
+  __shared__ float lds[MARG_LDS_SMALL];
+  __shared__ float red4[4];
+  class_dispatch(m, MargF{d, mask, lds, red4});
+}
+
+__global__ __launch_bounds__(WG) void k_marginalize_huge(Dev d, int slot0, const uint8_t* mask) {
+  __shared__ float lds[marg_stride(class_kmax(5))];
+  __shared__ float red4[4];
+  marginalize_one<256, class_kmax(5)>(d, slot0 + blockIdx.x, threadIdx.x, lds, red4, mask);
+}
+
+struct DampF {
+  const Dev& d;
+  const uint8_t* mask;
+  template <int TEAM, int CLS>
+  __device__ void run(int slot, int lane, int) const { damp_one<TEAM>(d, slot, lane, mask); }
+};
+
+__global__ __launch_bounds__(WG) void k_damp(Dev d, ClassGrid m, const uint8_t* mask) {
+  class_dispatch(m, DampF{d, mask});
+}
+
+__global__ __launch_bounds__(WG) void k_damp_huge(Dev d, int slot0, const uint8_t* mask) {
+  damp_one<256>(d, slot0 + blockIdx.x, threadIdx.x, mask);
+}
+
+struct PrecondF {
+  const Dev& d;
+  template <int TEAM, int CLS>
+  __device__ void run(int slot, int lane, int) const { precond_one<TEAM>(d, slot, lane); }
+};
+
+__global__ __launch_bounds__(WG) void k_precond_obs(Dev d, ClassGrid m) { class_dispatch(m, PrecondF{d}); }
+
+__global__ __launch_bounds__(WG) void k_precond_obs_huge(Dev d, int slot0) {
+  precond_one<256>(d, slot0 + blockIdx.x, threadIdx.x);
+}
+
+struct BacksubF {
+  const Dev& d;
+  float* red4;
+  double* predw;
+  template <int TEAM, int CLS>
+  __device__ void run(int slot, int lane, int) const {
+    if constexpr (TEAM == 256)
+      backsub_large<4>(d, slot, predw);
+    else
+      backsub_one<TEAM, 1>(d, slot, lane, red4);
+  }
+};
+
+__global__ __launch_bounds__(WG) void k_backsub(Dev d, ClassGrid m) {
+  __shared__ float red4[4];
+  __shared__ double predw[5];
+  class_dispatch(m, BacksubF{d, red4, predw});
+}
+
+__global__ __launch_bounds__(WG) void k_backsub_huge(Dev d, int slot0) {
+  __shared__ double predw[5];
+  backsub_large<18>(d, slot0 + blockIdx.x, predw);
 }
 
 // ----------------------------------------------------- update and commit
@@ -1554,6 +1730,22 @@ inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / 
 
 // ----------------------------------------------------- launchers
 
+// Launch description of classes 0..4 (in launch order 4, 3, 2, 1, 0); *n gets
+// the number of workgroups.  With skip4, class 4 is left out.
+static ClassGrid class_grid(const Launch& L, int* n, bool skip4 = false) {
+  ClassGrid m;
+  *n = 0;
+  for (int j = 0; j < 5; ++j) {
+    const WorkClass& c = L.wc[4 - j];
+    const int per = mv_per_wg(j);
+    m.nblk[j] = (j == 0 && skip4) ? 0 : (c.slots + per - 1) / per;
+    m.first[j] = c.first_slot;
+    m.end[j] = c.first_slot + c.slots;
+    *n += m.nblk[j];
+  }
+  return m;
+}
+
 #define LAUNCH_CHECK()                       \
   do {                                       \
     hipError_t e_ = hipGetLastError();       \
@@ -1581,36 +1773,30 @@ hipError_t launch_prob_sum(const Dev& d, const Launch& L, const double* vals, co
 
 hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask) {
   const WorkClass* w = L.wc;
-  if (w[5].count) hipLaunchKernelGGL((k_marginalize<256, 512>), dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi, mask);
-  if (w[4].count) hipLaunchKernelGGL((k_marginalize<256, 113>), dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, mask);
-  if (w[3].count) hipLaunchKernelGGL((k_marginalize<64, 28>), dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi, mask);
-  if (w[2].count) hipLaunchKernelGGL((k_marginalize<32, 14>), dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi, mask);
-  if (w[1].count) hipLaunchKernelGGL((k_marginalize<16, 7>), dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi, mask);
-  if (w[0].count) hipLaunchKernelGGL((k_marginalize<8, 3>), dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi, mask);
+  if (w[5].slots) hipLaunchKernelGGL(k_marginalize_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot, mask);
+  int n = 0;
+  const ClassGrid m = class_grid(L, &n);
+  if (n) hipLaunchKernelGGL(k_marginalize, dim3(n), dim3(WG), 0, L.stream, d, m, mask);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
   const WorkClass* w = L.wc;
-  if (w[5].count) hipLaunchKernelGGL(k_damp<256>, dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi, mask);
-  if (w[4].count) hipLaunchKernelGGL(k_damp<256>, dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi, mask);
-  if (w[3].count) hipLaunchKernelGGL(k_damp<64>, dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi, mask);
-  if (w[2].count) hipLaunchKernelGGL(k_damp<32>, dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi, mask);
-  if (w[1].count) hipLaunchKernelGGL(k_damp<16>, dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi, mask);
-  if (w[0].count) hipLaunchKernelGGL(k_damp<8>, dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi, mask);
+  if (w[5].slots) hipLaunchKernelGGL(k_damp_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot, mask);
+  int n = 0;
+  const ClassGrid m = class_grid(L, &n);
+  if (n) hipLaunchKernelGGL(k_damp, dim3(n), dim3(WG), 0, L.stream, d, m, mask);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
   const WorkClass* w = L.wc;
-  if (w[5].count) hipLaunchKernelGGL(k_precond_obs<256>, dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi);
-  if (w[4].count) hipLaunchKernelGGL(k_precond_obs<256>, dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi);
-  if (w[3].count) hipLaunchKernelGGL(k_precond_obs<64>, dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi);
-  if (w[2].count) hipLaunchKernelGGL(k_precond_obs<32>, dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi);
-  if (w[1].count) hipLaunchKernelGGL(k_precond_obs<16>, dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi);
-  if (w[0].count) hipLaunchKernelGGL(k_precond_obs<8>, dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi);
+  if (w[5].slots) hipLaunchKernelGGL(k_precond_obs_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot);
+  int n = 0;
+  const ClassGrid m = class_grid(L, &n);
+  if (n) hipLaunchKernelGGL(k_precond_obs, dim3(n), dim3(WG), 0, L.stream, d, m);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_precond_cam, dim3(d.NC), dim3(64), 0, L.stream, d);
   LAUNCH_CHECK();
@@ -1636,16 +1822,8 @@ static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
     hipLaunchKernelGGL(k_matvec_large<PCG>, dim3(w[4].slots), dim3(WG), 0, L.stream, d, w[4].first_slot, v);
     LAUNCH_CHECK();
   }
-  MvGrid m;
   int n = 0;
-  for (int j = 0; j < 5; ++j) {
-    const WorkClass& c = w[4 - j];
-    const int per = mv_per_wg(j);
-    m.nblk[j] = (j == 0 && split) ? 0 : (c.slots + per - 1) / per;
-    m.first[j] = c.first_slot;
-    m.end[j] = c.first_slot + c.slots;
-    n += m.nblk[j];
-  }
+  const ClassGrid m = class_grid(L, &n, split);
   if (n) {
     if (m.nblk[0])
       hipLaunchKernelGGL((k_matvec<PCG, true>), dim3(n), dim3(WG), 0, L.stream, d, m, v);
@@ -1692,12 +1870,10 @@ hipError_t launch_pcg_iteration(const Dev& d, const Launch& L) {
 
 hipError_t launch_backsub(const Dev& d, const Launch& L) {
   const WorkClass* w = L.wc;
-  if (w[5].count) hipLaunchKernelGGL((k_backsub<256, 5>), dim3(w[5].count), dim3(WG), 0, L.stream, d, w[5].first_wi);
-  if (w[4].count) hipLaunchKernelGGL((k_backsub<256, 1>), dim3(w[4].count), dim3(WG), 0, L.stream, d, w[4].first_wi);
-  if (w[3].count) hipLaunchKernelGGL((k_backsub<64, 1>), dim3(w[3].count), dim3(WG), 0, L.stream, d, w[3].first_wi);
-  if (w[2].count) hipLaunchKernelGGL((k_backsub<32, 1>), dim3(w[2].count), dim3(WG), 0, L.stream, d, w[2].first_wi);
-  if (w[1].count) hipLaunchKernelGGL((k_backsub<16, 1>), dim3(w[1].count), dim3(WG), 0, L.stream, d, w[1].first_wi);
-  if (w[0].count) hipLaunchKernelGGL((k_backsub<8, 1>), dim3(w[0].count), dim3(WG), 0, L.stream, d, w[0].first_wi);
+  if (w[5].slots) hipLaunchKernelGGL(k_backsub_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot);
+  int n = 0;
+  const ClassGrid m = class_grid(L, &n);
+  if (n) hipLaunchKernelGGL(k_backsub, dim3(n), dim3(WG), 0, L.stream, d, m);
   LAUNCH_CHECK();
   return hipSuccess;
 }
