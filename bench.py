@@ -189,6 +189,7 @@ def main():
                     help="workload: 1 ladybug-like (default), 2 batch of 256, 3 venice-like, 4 dense stress")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default product launch shapes")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -216,6 +217,13 @@ def main():
     ctx.bind_torch_workspace()
     ctx.save_state()
     log(f"uploaded: workspace {ctx.workspace_bytes() / 1e9:.2f} GB")
+    tuning = {"shape": ctx.get_tuning(), "autotuned": False}
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        best, trials = ctx.autotune(reps=10)
+        tuning = {"shape": best, "autotuned": True, "seconds": time.perf_counter() - t0,
+                  "trials": [dict(shape, ms=ms) for shape, ms in trials]}
+        log(f"autotune: {best} from {len(trials)} candidates")
     for w in range(args.warmup):
         ctx.restore_state()
         rep = ctx.lm_solve()
@@ -335,6 +343,7 @@ def main():
         "matvec_GBps": achieved,
         "stage_ms": {k: v["ms"] for k, v in prof.items()},
         "roofline": roofline,
+        "tuning": tuning,
         "learned_vs_block_jacobi": learned_out,
         "cpu_baseline": cpu,
     }

@@ -348,6 +348,44 @@ int32_t sqrtba_profile_get(const sqrtba_ctx* ctx, sqrtba_profile* out);
 int32_t sqrtba_save_state(sqrtba_ctx* ctx);
 int32_t sqrtba_restore_state(sqrtba_ctx* ctx);
 
+/* ---- launch shapes of the PCG product and their autotuner ---- */
+
+/* The product runs size-bucketed kernels (landmarks by observation count k);
+ * these are the shapes that are not fixed by the buckets themselves.  None of
+ * them changes the arithmetic except huge_rows, which sets how the rows of a
+ * k > 113 block are grouped before their partial products are added. */
+typedef struct {
+  int32_t huge_rows;      /* rows per workgroup for k > 113: 64, 128, 256, 512 or
+                             1024 (1024: one workgroup per landmark, no partials) */
+  int32_t huge_side;      /* 1: the k > 113 work runs on a second stream,
+                             concurrently with the rest of the product */
+  int32_t large_separate; /* 1: landmarks with 29 <= k <= 113 get a launch of their
+                             own (the small-class kernel then needs fewer registers) */
+  int32_t small_rows;     /* rows per batch for k <= 28: 4 or 8 */
+} sqrtba_tuning;
+
+typedef struct {
+  sqrtba_tuning shape;
+  double ms;              /* mean milliseconds per product */
+} sqrtba_tuning_trial;
+
+/* Current shapes; set_tuning rejects values outside the lists above with
+ * SQRTBA_E_INVALID.  Both need the problem uploaded (any solver call uploads
+ * it; sqrtba_workspace_bytes/bind_workspace must have been satisfied). */
+int32_t sqrtba_get_tuning(sqrtba_ctx* ctx, sqrtba_tuning* out);
+int32_t sqrtba_set_tuning(sqrtba_ctx* ctx, const sqrtba_tuning* shape);
+
+/* Time the product on the uploaded problem under candidate shapes and keep the
+ * fastest: a coordinate search over the four fields in the order above, each
+ * candidate timed over `reps` products (<= 0: 10) with HIP events on the
+ * context stream.  The timing does not depend on the values in the landmark
+ * blocks, so this may run right after upload; it overwrites only scratch
+ * (the product outputs).  best (may be NULL) receives the chosen shapes,
+ * trials (may be NULL) up to max_trials records and *n_trials (may be NULL)
+ * the number of candidates timed. */
+int32_t sqrtba_autotune(sqrtba_ctx* ctx, int32_t reps, sqrtba_tuning* best, sqrtba_tuning_trial* trials,
+                        int32_t max_trials, int32_t* n_trials);
+
 #ifdef __cplusplus
 }
 #endif

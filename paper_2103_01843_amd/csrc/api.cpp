@@ -216,6 +216,19 @@ void so3_log_d(const double M[9], double w[3]) {
 
 int64_t width_of_h(int64_t k) { return (9 * k + 3) & ~int64_t(3); }
 
+// (slot, row block) jobs of the split class-5 product for blocks of `rows` rows.
+void build_hjobs(const HostData& h, int rows, std::vector<int32_t>& jobs) {
+  jobs.clear();
+  for (int64_t i = 0; i < h.wc[5].slots; ++i) {
+    const int64_t sl = h.wc[5].first_slot + i, k = h.slot_k[sl];
+    const int64_t nblk = (2 * k + rows - 1) / rows;
+    for (int64_t r = 0; r < nblk; ++r) {
+      jobs.push_back((int32_t)sl);
+      jobs.push_back((int32_t)r);
+    }
+  }
+}
+
 // ------------------------------------------------------------ bookkeeping
 
 int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_t* pt, const float* uv) {
@@ -343,20 +356,16 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
     while (s < nb.NS && class_of_k(nb.slot_k[s]) == cl) ++s;
     nb.wc[cl].slots = (int)(s - nb.wc[cl].first_slot);
   }
-  // split product of class 5: row blocks of HUGE_ROWS rows, partial outputs per block
-  nb.hjob.clear();
+  // split product of class 5: partial outputs per row block, sized for the
+  // smallest block (HUGE_ROWS_MIN rows); the job list is built per block size
   nb.hz_off.clear();
   nb.hz_floats = 0;
   for (int64_t i = 0; i < nb.wc[5].slots; ++i) {
     const int64_t sl = nb.wc[5].first_slot + i, k = nb.slot_k[sl];
-    const int64_t nblk = (2 * k + HUGE_ROWS - 1) / HUGE_ROWS;
     nb.hz_off.push_back(nb.hz_floats);
-    nb.hz_floats += nblk * width_of_h(k);
-    for (int64_t r = 0; r < nblk; ++r) {
-      nb.hjob.push_back((int32_t)sl);
-      nb.hjob.push_back((int32_t)r);
-    }
+    nb.hz_floats += ((2 * k + HUGE_ROWS_MIN - 1) / HUGE_ROWS_MIN) * width_of_h(k);
   }
+  build_hjobs(nb, HUGE_ROWS_MIN, nb.hjob);
   if (nb.hjob.size() / 2 > (size_t)INT32_MAX / 2) return fail(c, SQRTBA_E_UNSUPPORTED, "too many row blocks");
   // camera statistics for the learned preconditioner: observations, covisible
   // cameras (bitsets per problem), mean and max log k over the camera's landmarks
@@ -479,13 +488,6 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
   return L.total;
 }
 
-// Class 4 of the product gets its own launch (and the small classes a kernel
-// with fewer registers) from this many class-4 landmarks on.
-int large_split_default() {
-  const char* e = getenv("SQRTBA_LARGE_SPLIT");
-  return e ? atoi(e) : 256;
-}
-
 hipEvent_t take_event(sqrtba_ctx* c) {
   if (!c->event_pool.empty()) {
     hipEvent_t e = c->event_pool.back();
@@ -604,8 +606,12 @@ int upload(sqrtba_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->L.stream = c->stream;
   for (int i = 0; i < NUM_CLASSES; ++i) c->L.wc[i] = h.wc[i];
+  // default launch shapes (the autotuner may replace them)
   c->L.hjobs = (int)(h.hjob.size() / 2);
-  c->L.large_split = large_split_default();
+  c->L.huge_rows = HUGE_ROWS_MIN;
+  c->L.huge_side = 0;
+  c->L.large_sep = h.wc[4].slots >= 256;
+  c->L.mv_rbs = 0;
   if (!c->side) {
     HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
     HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
@@ -1732,3 +1738,114 @@ int32_t sqrtba_restore_state(sqrtba_ctx* c) {
 }
 
 }  // extern "C"
+
+// ---- launch shapes and autotuner
+
+namespace {
+
+bool valid_tuning(const sqrtba_tuning& t) {
+  const int r = t.huge_rows;
+  return (r == 64 || r == 128 || r == 256 || r == 512 || r == 1024) && (t.huge_side == 0 || t.huge_side == 1) &&
+         (t.large_separate == 0 || t.large_separate == 1) && (t.small_rows == 4 || t.small_rows == 8);
+}
+
+sqrtba_tuning current_tuning(const sqrtba_ctx* c) {
+  sqrtba_tuning t;
+  t.huge_rows = c->L.huge_rows;
+  t.huge_side = c->L.huge_side;
+  t.large_separate = c->L.large_sep;
+  t.small_rows = c->L.mv_rbs ? 8 : 4;
+  return t;
+}
+
+int apply_tuning(sqrtba_ctx* c, const sqrtba_tuning& t) {
+  if (t.huge_rows != c->L.huge_rows) {
+    std::vector<int32_t> jobs;
+    build_hjobs(c->h, t.huge_rows, jobs);
+    if (jobs.size() > c->h.hjob.size()) return fail(c, SQRTBA_E_STATE, "row-block job list exceeds its allocation");
+    TRY(upload_vec(c, reinterpret_cast<int32_t*>(c->d.hjob), jobs));
+    c->L.hjobs = (int)(jobs.size() / 2);
+    c->L.huge_rows = t.huge_rows;
+  }
+  c->L.huge_side = t.huge_side;
+  c->L.large_sep = t.large_separate;
+  c->L.mv_rbs = t.small_rows == 8 ? 1 : 0;
+  if (c->graph) {  // the captured PCG iterations hold the old launches
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return SQRTBA_OK;
+}
+
+}  // namespace
+
+int32_t sqrtba_get_tuning(sqrtba_ctx* c, sqrtba_tuning* out) {
+  if (!c || !out) return SQRTBA_E_INVALID;
+  TRY(ensure_uploaded(c));
+  *out = current_tuning(c);
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_set_tuning(sqrtba_ctx* c, const sqrtba_tuning* t) {
+  if (!c || !t || !valid_tuning(*t)) return SQRTBA_E_INVALID;
+  TRY(ensure_uploaded(c));
+  TRY(apply_tuning(c, *t));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_autotune(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, sqrtba_tuning_trial* trials,
+                        int32_t max_trials, int32_t* n_trials) {
+  if (!c || max_trials < 0) return SQRTBA_E_INVALID;
+  TRY(ensure_uploaded(c));
+  if (reps <= 0) reps = 10;
+  hipEvent_t e0 = take_event(c), e1 = take_event(c);
+  if (!e0 || !e1) return fail(c, SQRTBA_E_HIP, "no events");
+  std::vector<sqrtba_tuning_trial> tr;
+  auto measure = [&](const sqrtba_tuning& t, double* ms) -> int {
+    TRY(apply_tuning(c, t));
+    for (int i = 0; i < 2; ++i) LAUNCH(c, launch_matvec_timing(c->d, c->L));
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    for (int i = 0; i < reps; ++i) LAUNCH(c, launch_matvec_timing(c->d, c->L));
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    float f = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&f, e0, e1));
+    *ms = (double)f / reps;
+    tr.push_back({t, *ms});
+    return SQRTBA_OK;
+  };
+  sqrtba_tuning cur = current_tuning(c);
+  double cur_ms = 0.0;
+  TRY(measure(cur, &cur_ms));
+  const bool huge = c->h.wc[5].slots > 0, large = c->h.wc[4].slots > 0;
+  auto try_field = [&](int sqrtba_tuning::*field, std::initializer_list<int> values) -> int {
+    for (int v : values) {
+      if (cur.*field == v) continue;
+      sqrtba_tuning t = cur;
+      t.*field = v;
+      double ms = 0.0;
+      TRY(measure(t, &ms));
+      if (ms < cur_ms) {
+        cur = t;
+        cur_ms = ms;
+      }
+    }
+    return SQRTBA_OK;
+  };
+  if (huge) {
+    TRY(try_field(&sqrtba_tuning::huge_rows, {64, 128, 256, 1024}));
+    TRY(try_field(&sqrtba_tuning::huge_side, {0, 1}));
+  }
+  if (large) TRY(try_field(&sqrtba_tuning::large_separate, {0, 1}));
+  TRY(try_field(&sqrtba_tuning::small_rows, {4, 8}));
+  TRY(apply_tuning(c, cur));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->event_pool.push_back(e0);
+  c->event_pool.push_back(e1);
+  if (best) *best = cur;
+  if (trials)
+    for (int i = 0; i < (int)tr.size() && i < max_trials; ++i) trials[i] = tr[i];
+  if (n_trials) *n_trials = (int32_t)tr.size();
+  return SQRTBA_OK;
+}

@@ -60,7 +60,7 @@ struct Dev {
   int32_t* cam_zpos;   // NO: obsbuf offset of the outputs of each camera's observations (camera order)
   int32_t* lm_slot;    // NL, -1 when inactive
   // split product of the largest landmarks (class 5): one job per block of
-  // HUGE_ROWS rows (x: slot, y: row block), partial outputs per row block
+  // Launch::huge_rows rows (x: slot, y: row block), partial outputs per row block
   int2* hjob;
   int64_t* hz_off;  // per class-5 slot: float offset of its partial outputs in zpart (nblocks x W)
   float* zpart;
@@ -112,12 +112,17 @@ struct WorkClass {
   int slots;       // number of slots
 };
 
-// Rows of a landmark block per workgroup in the split product of class 5.
-enum { HUGE_ROWS = 64 };
+// Smallest row block of the split class-5 product (sizes the job list and the
+// partial outputs); the tuned block size is a multiple of it.
+enum { HUGE_ROWS_MIN = 64 };
 
 struct Launch {
-  int hjobs;          // number of split-product jobs (class 5)
-  int large_split;    // class 4 runs as its own launch when it has at least this many landmarks
+  // launch shapes of the product (set by the autotuner or sqrtba_set_tuning)
+  int hjobs;       // number of split-product jobs (class 5) for huge_rows
+  int huge_rows;   // rows per class-5 job (>= 2 * 512: one job per landmark)
+  int huge_side;   // class-5 jobs on the side stream, concurrent with the rest
+  int large_sep;   // class 4 as its own launch (else inside the small-class launch)
+  int mv_rbs;      // row-batch set of the small classes (0: 4 rows, 1: 8 rows)
   hipStream_t stream;
   hipStream_t side;   // second stream for the largest landmarks (may be null)
   hipEvent_t fork, join;
@@ -141,6 +146,7 @@ hipError_t launch_update(const Dev& d, const Launch& L);
 hipError_t launch_commit(const Dev& d, const Launch& L);
 // test helpers
 hipError_t launch_matvec_only(const Dev& d, const Launch& L, const float* v_scaled, float* out);
+hipError_t launch_matvec_timing(const Dev& d, const Launch& L);  // product of z over all active landmarks
 hipError_t launch_debug_linearization(const Dev& d, const Launch& L, float* r, float* Jp, float* Jl);
 
 }  // namespace sqrtba

@@ -893,16 +893,10 @@ __device__ __forceinline__ void matvec_large(const Dev& d, int slot, const float
   }
 }
 
-// Rows per batch of the small classes (3, 2, 1, 0 in launch order) and rows
-// per wavefront step of class 4.
-#ifndef SQRTBA_MV_RB
-#define SQRTBA_MV_RB 4, 4, 4, 4
-#endif
-#ifndef SQRTBA_MV_RS
-#define SQRTBA_MV_RS 1
-#endif
-constexpr int MV_RB[4] = {SQRTBA_MV_RB};
-constexpr int MV_RS = SQRTBA_MV_RS;
+// Rows per batch of the small classes (3, 2, 1, 0 in launch order), by the
+// tunable row-batch set RBS, and rows per wavefront step of class 4.
+__host__ __device__ constexpr int mv_rb(int rbs, int j) { return rbs == 0 ? 4 : (j == 3 ? 6 : 8); }
+constexpr int MV_RS = 1;
 __host__ __device__ constexpr int mv_per_wg(int j) {  // j: launch-order class index 0..4
   return j == 0 ? 1 : WG / class_team(4 - j);
 }
@@ -912,7 +906,7 @@ __host__ __device__ constexpr int mv_per_wg(int j) {  // j: launch-order class i
 // kernel with no tail gaps between classes.  Without LARGE the kernel holds no
 // class-4 code and needs fewer registers (more resident wavefronts); class 4
 // then runs as its own launch (k_matvec_large).
-template <bool PCG, bool LARGE>
+template <bool PCG, bool LARGE, int RBS>
 __global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, const float* v) {
   int b = blockIdx.x;
   if constexpr (LARGE) {
@@ -920,13 +914,13 @@ __global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, const float* 
     if (b < m.nblk[0]) { matvec_large<4, MV_RS, PCG>(d, m.first[0] + b, v, zred); return; }
     b -= m.nblk[0];
   }
-  if (b < m.nblk[1]) { matvec_teams<64, MV_RB[0], PCG>(d, m.first[1] + b * mv_per_wg(1), m.end[1], v); return; }
+  if (b < m.nblk[1]) { matvec_teams<64, mv_rb(RBS, 0), PCG>(d, m.first[1] + b * mv_per_wg(1), m.end[1], v); return; }
   b -= m.nblk[1];
-  if (b < m.nblk[2]) { matvec_teams<32, MV_RB[1], PCG>(d, m.first[2] + b * mv_per_wg(2), m.end[2], v); return; }
+  if (b < m.nblk[2]) { matvec_teams<32, mv_rb(RBS, 1), PCG>(d, m.first[2] + b * mv_per_wg(2), m.end[2], v); return; }
   b -= m.nblk[2];
-  if (b < m.nblk[3]) { matvec_teams<16, MV_RB[2], PCG>(d, m.first[3] + b * mv_per_wg(3), m.end[3], v); return; }
+  if (b < m.nblk[3]) { matvec_teams<16, mv_rb(RBS, 2), PCG>(d, m.first[3] + b * mv_per_wg(3), m.end[3], v); return; }
   b -= m.nblk[3];
-  matvec_teams<8, MV_RB[3], PCG>(d, m.first[4] + b * mv_per_wg(4), m.end[4], v);
+  matvec_teams<8, mv_rb(RBS, 3), PCG>(d, m.first[4] + b * mv_per_wg(4), m.end[4], v);
 }
 
 // Class 4 on its own: one landmark per workgroup.
@@ -936,13 +930,13 @@ __global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int slot0, const flo
   matvec_large<4, MV_RS, PCG>(d, slot0 + blockIdx.x, v, zred);
 }
 
-// Landmarks with k > 113 (up to 512), split into blocks of HUGE_ROWS rows so
-// that a few very large landmarks still spread over the whole chip: job j
-// (slot, row block) runs on one workgroup of four wavefronts (wave w takes
-// rows w, w+4, ... of the block) and writes its partial z for the block; a
-// landmark with a single block writes its outputs directly.
+// Landmarks with k > 113 (up to 512), split into blocks of `rows` rows so that
+// a few very large landmarks still spread over the whole chip: job j (slot,
+// row block) runs on one workgroup of four wavefronts (wave w takes rows w,
+// w+4, ... of the block) and writes its partial z for the block; a landmark
+// with a single block writes its outputs directly.
 template <bool PCG>
-__global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, const float* v) {
+__global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, int rows, const float* v) {
   constexpr int NCG = 18;  // ceil(width_of(512) / 4 / 64)
   __shared__ float4 zred[4][64];
   const int2 job = d.hjob[blockIdx.x];
@@ -954,7 +948,7 @@ __global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, const floa
   if (!d.active[prob] || (PCG && d.done[prob])) return;
   const int G = width_of(k) >> 2;
   const int n = 2 * k;
-  const int r0 = job.y * HUGE_ROWS, r1 = min(n, r0 + HUGE_ROWS);
+  const int r0 = job.y * rows, r1 = min(n, r0 + rows);
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   float4 b[NCG], pv[NCG], z[NCG];
@@ -978,7 +972,7 @@ __global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, const floa
 #pragma unroll
     for (int j = 0; j < NCG; ++j) axpy4(z[j], y, b[j]);
   }
-  const bool single = n <= HUGE_ROWS;
+  const bool single = n <= rows;
   float4* dst = single ? reinterpret_cast<float4*>(d.obsbuf + d.slot_zoff[slot])
                        : reinterpret_cast<float4*>(d.zpart + d.hz_off[slot - slot0] + (size_t)job.y * (4 * G));
 #pragma unroll
@@ -1000,14 +994,14 @@ __global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, const floa
 // Sum of the row-block partials of every class-5 landmark with more than one
 // block, in block order, into its outputs (one workgroup per landmark).
 template <bool PCG>
-__global__ __launch_bounds__(WG) void k_matvec_combine(Dev d, int slot0) {
+__global__ __launch_bounds__(WG) void k_matvec_combine(Dev d, int slot0, int rows) {
   const int slot = slot0 + blockIdx.x;
   const int prob = d.slot_prob[slot];
   const int k = d.slot_k[slot];
   if (!d.active[prob] || (PCG && d.done[prob])) return;
   const int n = 2 * k;
-  if (n <= HUGE_ROWS) return;
-  const int nblk = (n + HUGE_ROWS - 1) / HUGE_ROWS;
+  if (n <= rows) return;
+  const int nblk = (n + rows - 1) / rows;
   const int G = width_of(k) >> 2;
   const float4* __restrict__ src = reinterpret_cast<const float4*>(d.zpart + d.hz_off[blockIdx.x]);
   float4* dst = reinterpret_cast<float4*>(d.obsbuf + d.slot_zoff[slot]);
@@ -1806,34 +1800,54 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
 // The landmarks with k > 113 (few, each a long stream for one workgroup) run
 // on a side stream concurrently with the main product, forked from and joined
 // back into the context stream by events (also inside captured graphs).
-// Product over all landmark blocks on the context stream: the class-5 row
-// blocks, class 4 (inside the main launch when it is small, else on its own),
-// classes 0..3, then the sum of the class-5 partials.
+// Product over all landmark blocks: the class-5 row blocks (on the side
+// stream, concurrently with the rest, when huge_side), class 4 (inside the
+// main launch, or on its own when large_sep), classes 0..3, then the sum of
+// the class-5 partials.  The launch shapes are the tunables of Launch.
+template <bool PCG, bool LARGE>
+static void launch_small(const Dev& d, const Launch& L, const ClassGrid& m, int n, const float* v) {
+  if (L.mv_rbs == 0)
+    hipLaunchKernelGGL((k_matvec<PCG, LARGE, 0>), dim3(n), dim3(WG), 0, L.stream, d, m, v);
+  else
+    hipLaunchKernelGGL((k_matvec<PCG, LARGE, 1>), dim3(n), dim3(WG), 0, L.stream, d, m, v);
+}
+
 template <bool PCG>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
   const WorkClass* w = L.wc;
   const bool huge = w[5].slots > 0 && L.hjobs > 0;
+  const bool side = huge && L.huge_side && L.side && L.fork && L.join;
+  const hipStream_t hs = side ? L.side : L.stream;
   if (huge) {
-    hipLaunchKernelGGL(k_matvec_rows<PCG>, dim3(L.hjobs), dim3(WG), 0, L.stream, d, w[5].first_slot, v);
+    if (side) {
+      hipError_t e = hipEventRecord(L.fork, L.stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(L.side, L.fork, 0);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_matvec_rows<PCG>, dim3(L.hjobs), dim3(WG), 0, hs, d, w[5].first_slot, L.huge_rows, v);
+    LAUNCH_CHECK();
+    if (L.huge_rows < 2 * class_kmax(5))
+      hipLaunchKernelGGL(k_matvec_combine<PCG>, dim3(w[5].slots), dim3(WG), 0, hs, d, w[5].first_slot, L.huge_rows);
     LAUNCH_CHECK();
   }
-  const bool split = w[4].slots >= L.large_split;
-  if (split && w[4].slots) {
+  const bool sep = L.large_sep && w[4].slots > 0;
+  if (sep) {
     hipLaunchKernelGGL(k_matvec_large<PCG>, dim3(w[4].slots), dim3(WG), 0, L.stream, d, w[4].first_slot, v);
     LAUNCH_CHECK();
   }
   int n = 0;
-  const ClassGrid m = class_grid(L, &n, split);
+  const ClassGrid m = class_grid(L, &n, sep);
   if (n) {
     if (m.nblk[0])
-      hipLaunchKernelGGL((k_matvec<PCG, true>), dim3(n), dim3(WG), 0, L.stream, d, m, v);
+      launch_small<PCG, true>(d, L, m, n, v);
     else
-      hipLaunchKernelGGL((k_matvec<PCG, false>), dim3(n), dim3(WG), 0, L.stream, d, m, v);
+      launch_small<PCG, false>(d, L, m, n, v);
     LAUNCH_CHECK();
   }
-  if (huge) {
-    hipLaunchKernelGGL(k_matvec_combine<PCG>, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot);
-    LAUNCH_CHECK();
+  if (side) {
+    hipError_t e = hipEventRecord(L.join, L.side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(L.stream, L.join, 0);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -1891,6 +1905,8 @@ hipError_t launch_commit(const Dev& d, const Launch& L) {
   LAUNCH_CHECK();
   return hipSuccess;
 }
+
+hipError_t launch_matvec_timing(const Dev& d, const Launch& L) { return launch_matvec<false>(d, L, d.vz); }
 
 hipError_t launch_matvec_only(const Dev& d, const Launch& L, const float* v_scaled, float* out) {
   hipError_t e = launch_matvec<false>(d, L, v_scaled);

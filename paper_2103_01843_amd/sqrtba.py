@@ -60,6 +60,18 @@ class LMRecord(C.Structure):
 STAGES = ["linearize", "marginalize", "damp", "precond", "matvec", "pcg_vector", "backsub", "update"]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("huge_rows", C.c_int32), ("huge_side", C.c_int32), ("large_separate", C.c_int32),
+                ("small_rows", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class TuningTrial(C.Structure):
+    _fields_ = [("shape", Tuning), ("ms", C.c_double)]
+
+
 class Profile(C.Structure):
     _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("bytes", C.c_double * 8),
                 ("units", C.c_int64 * 8)]
@@ -122,6 +134,9 @@ _SIGS = {
     "sqrtba_learned_stats": (I32, [P, PI64, PI64, PI64]),
     "sqrtba_debug_features": (I32, [P, PF, PF]),
     "sqrtba_debug_learned_precond": (I32, [P, PF]),
+    "sqrtba_get_tuning": (I32, [P, C.POINTER(Tuning)]),
+    "sqrtba_set_tuning": (I32, [P, C.POINTER(Tuning)]),
+    "sqrtba_autotune": (I32, [P, I32, C.POINTER(Tuning), C.POINTER(TuningTrial), I32, PI32]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -403,6 +418,25 @@ class Context:
         self._check(lib().sqrtba_profile_get(self._h, C.byref(pr)))
         return {name: {"ms": pr.ms[i], "launches": int(pr.launches[i]), "bytes": pr.bytes[i],
                        "units": int(pr.units[i])} for i, name in enumerate(STAGES)}
+
+    # -- launch shapes of the product
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(lib().sqrtba_get_tuning(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **shape):
+        t = Tuning(**{**self.get_tuning(), **shape})
+        self._check(lib().sqrtba_set_tuning(self._h, C.byref(t)))
+
+    def autotune(self, reps: int = 10):
+        """Pick the fastest product launch shapes on this problem; returns
+        (chosen shapes, [(shapes, ms per product), ...] of every candidate)."""
+        best = Tuning()
+        trials = (TuningTrial * 32)()
+        n = C.c_int32()
+        self._check(lib().sqrtba_autotune(self._h, reps, C.byref(best), trials, 32, C.byref(n)))
+        return best.as_dict(), [(trials[i].shape.as_dict(), trials[i].ms) for i in range(min(n.value, 32))]
 
     def save_state(self):
         self._check(lib().sqrtba_save_state(self._h))
