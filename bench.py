@@ -9,12 +9,14 @@ with every input resident in HBM: each attempt runs linearize, QR
 marginalization, Givens damping, block-Jacobi + right-hand side, PCG,
 back-substitution, update and cost.
 
-Printed JSON line: time-to-1%-cost (the headline value), QR blocks/s, PCG
-matvec GB/s with its roofline (HIP events around every matvec launch of the
-timed region, algorithmic bytes 4 (18 k^2 + 9 k) per landmark), and the FP64
-oracle's CPU baseline on a bounded sample.
+Printed JSON line: time-to-1%-cost (the headline value, from the timed steps in
+the production configuration: graph-captured PCG, no profiler), QR blocks/s
+and the stage breakdown (one more profiled solve), PCG matvec GB/s with its
+roofline (HIP events around back-to-back products on the resident blocks,
+algorithmic bytes 4 (18 k^2 + 9 k) per landmark), the learned preconditioner
+against block-Jacobi, and the FP64 oracle's CPU baseline on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--config {1,2,3,4}]
     python bench.py --calibrate-copy   # known-size copy, for counter scaling
 """
 
@@ -41,7 +43,11 @@ WORKLOADS = {
 }
 METRIC = "time-to-1%-cost (s), QR blocks/s, PCG matvec HBM GB/s; learned vs block-Jacobi"
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_lm_config{}.json")
-TRAFFIC = os.path.join(ROOT, "profiles", "matvec_traffic_ladybug.json")
+# HBM counter readings of the product per workload (valid for the kernels and
+# launch shapes they were taken with)
+TRAFFIC = {1: os.path.join(ROOT, "profiles", "matvec_traffic_ladybug.json"),
+           2: os.path.join(ROOT, "profiles", "matvec_traffic_batch256.json"),
+           3: os.path.join(ROOT, "profiles", "matvec_traffic_venice.json")}
 KERNELS = os.path.join(ROOT, "paper_2103_01843_amd", "csrc", "kernels.hip")
 
 
@@ -190,6 +196,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default product launch shapes")
+    ap.add_argument("--tuning", default=None, metavar="ROWS,SIDE,SEP,BATCH",
+                    help="fixed product launch shapes (huge_rows, huge_side, large_separate, small_rows) "
+                         "instead of autotuning, e.g. for counter runs under a profiler")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -218,7 +227,11 @@ def main():
     ctx.save_state()
     log(f"uploaded: workspace {ctx.workspace_bytes() / 1e9:.2f} GB")
     tuning = {"shape": ctx.get_tuning(), "autotuned": False}
-    if not args.no_autotune:
+    if args.tuning:
+        hr, hs, ls, sr = (int(x) for x in args.tuning.split(","))
+        ctx.set_tuning(huge_rows=hr, huge_side=hs, large_separate=ls, small_rows=sr)
+        tuning = {"shape": ctx.get_tuning(), "autotuned": False}
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         best, trials = ctx.autotune(reps=10)
         tuning = {"shape": best, "autotuned": True, "seconds": time.perf_counter() - t0,
@@ -229,8 +242,7 @@ def main():
         rep = ctx.lm_solve()
         log(f"warmup {w}: {max(r.iterations for r in rep)} attempts, final cost {sum(r.final_cost for r in rep):.6g}, "
             f"{max(r.solve_seconds for r in rep):.3f} s")
-    torch.cuda.synchronize()
-    ctx.profile_enable(True)
+    # timed steps: the production configuration (graph-captured PCG, no profiler)
     runs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -243,6 +255,14 @@ def main():
     for s, (reps, h) in enumerate(runs):
         log(f"step {s}: {max(r.iterations for r in reps)} attempts, {sum(r.total_pcg_iters for r in reps)} PCG "
             f"iterations, final cost {sum(r.final_cost for r in reps):.6g}, {max(r.solve_seconds for r in reps):.3f} s")
+    # the product kernel's duration: HIP events around back-to-back launches on
+    # the resident blocks of the workload (same shapes as the timed steps)
+    mv_ms, mv_bytes = ctx.time_product(reps=50)
+    # stage breakdown: one more solve from the same start with the profiler on
+    # (HIP events around every stage; PCG iterations launched one by one)
+    ctx.restore_state()
+    ctx.profile_enable(True)
+    ctx.lm_solve()
     prof = ctx.profile()
     ctx.profile_enable(False)
     learned = None
@@ -286,21 +306,25 @@ def main():
     f0, fstar, f_tau = f_taus[0]
     finals = [sum(r.final_cost for r in reps) for reps, _ in runs]
 
-    mv, qr = prof["matvec"], prof["marginalize"]
-    mv_avg_ms = mv["ms"] / max(1, mv["launches"])
-    mv_bytes = mv["bytes"] / max(1, mv["launches"])
-    achieved = mv_bytes / (mv_avg_ms * 1e-3) / 1e9 if mv_avg_ms > 0 else None
-    traffic = None
-    if os.path.exists(TRAFFIC):
-        with open(TRAFFIC) as f:
+    qr = prof["marginalize"]
+    achieved = mv_bytes / (mv_ms * 1e-3) / 1e9 if mv_ms > 0 else None
+    traffic, traffic_note = None, None
+    tfile = TRAFFIC.get(cfg)
+    if tfile and os.path.exists(tfile):
+        with open(tfile) as f:
             tr = json.load(f)
-        if tr.get("kernels_sha") == kernels_hash():
+        if tr.get("kernels_sha") == kernels_hash():  # counters of the current kernels only
             traffic = tr.get("bytes_per_launch")
+            traffic_note = (f"FETCH_SIZE x {tr['fetch_scale']:.3f} + WRITE_SIZE x {tr['write_scale']:.3f} per product, "
+                            f"launch shapes {tr['shape']}")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": traffic,
-                "kernel": "k_matvec (+ k_matvec_huge for k > 113): the PCG product over all landmark blocks",
-                "avg_launch_ms": mv_avg_ms, "algorithmic_bytes_per_launch": mv_bytes,
-                "launches_timed": mv["launches"]}
+                "kernel": "the PCG product over all landmark blocks (k_matvec, plus k_matvec_large / "
+                          "k_matvec_rows + k_matvec_combine where those size classes exist)",
+                "avg_launch_ms": mv_ms, "algorithmic_bytes_per_launch": mv_bytes, "launches_timed": 50,
+                "timing": "HIP events around 50 back-to-back products on the resident blocks, context stream",
+                "traffic_source": traffic_note,
+                "profiled_pass_matvec_ms": prof["matvec"]["ms"] / max(1, prof["matvec"]["launches"])}
     qr_blocks_per_s = qr["units"] / (qr["ms"] * 1e-3) if qr["ms"] > 0 else None
     qr_gbps = qr["bytes"] / (qr["ms"] * 1e-3) / 1e9 if qr["ms"] > 0 else None
 

@@ -386,6 +386,13 @@ int32_t sqrtba_set_tuning(sqrtba_ctx* ctx, const sqrtba_tuning* shape);
 int32_t sqrtba_autotune(sqrtba_ctx* ctx, int32_t reps, sqrtba_tuning* best, sqrtba_tuning_trial* trials,
                         int32_t max_trials, int32_t* n_trials);
 
+/* Mean milliseconds of one PCG product (kernel (c), current shapes) over reps
+ * back-to-back launches on the resident landmark blocks of the active
+ * problems, HIP events on the context stream; *bytes (may be NULL) receives
+ * the algorithmic bytes of one product, 4 (18 k^2 + 9 k) per active landmark.
+ * Overwrites only scratch (the product outputs). */
+int32_t sqrtba_time_product(sqrtba_ctx* ctx, int32_t reps, double* ms, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

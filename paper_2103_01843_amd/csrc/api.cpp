@@ -1777,7 +1777,38 @@ int apply_tuning(sqrtba_ctx* c, const sqrtba_tuning& t) {
   return SQRTBA_OK;
 }
 
+// Mean milliseconds of one product over `reps` back-to-back launches (after two
+// untimed ones), HIP events on the context stream.
+int time_products(sqrtba_ctx* c, int reps, double* ms) {
+  hipEvent_t e0 = take_event(c), e1 = take_event(c);
+  if (!e0 || !e1) return fail(c, SQRTBA_E_HIP, "no events");
+  for (int i = 0; i < 2; ++i) LAUNCH(c, launch_matvec_timing(c->d, c->L));
+  HIP_TRY(c, hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i) LAUNCH(c, launch_matvec_timing(c->d, c->L));
+  HIP_TRY(c, hipEventRecord(e1, c->stream));
+  HIP_TRY(c, hipEventSynchronize(e1));
+  float f = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&f, e0, e1));
+  c->event_pool.push_back(e0);
+  c->event_pool.push_back(e1);
+  *ms = (double)f / reps;
+  return SQRTBA_OK;
+}
+
 }  // namespace
+
+int32_t sqrtba_time_product(sqrtba_ctx* c, int32_t reps, double* ms, double* bytes) {
+  if (!c || reps <= 0 || !ms) return SQRTBA_E_INVALID;
+  TRY(ensure_uploaded(c));
+  TRY(time_products(c, reps, ms));
+  if (bytes) {
+    double b = 0.0;
+    for (int p = 0; p < c->h.P; ++p)
+      if (c->active[p]) b += c->mv_bytes[p];
+    *bytes = b;
+  }
+  return SQRTBA_OK;
+}
 
 int32_t sqrtba_get_tuning(sqrtba_ctx* c, sqrtba_tuning* out) {
   if (!c || !out) return SQRTBA_E_INVALID;
@@ -1799,19 +1830,10 @@ int32_t sqrtba_autotune(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, sqrtba
   if (!c || max_trials < 0) return SQRTBA_E_INVALID;
   TRY(ensure_uploaded(c));
   if (reps <= 0) reps = 10;
-  hipEvent_t e0 = take_event(c), e1 = take_event(c);
-  if (!e0 || !e1) return fail(c, SQRTBA_E_HIP, "no events");
   std::vector<sqrtba_tuning_trial> tr;
   auto measure = [&](const sqrtba_tuning& t, double* ms) -> int {
     TRY(apply_tuning(c, t));
-    for (int i = 0; i < 2; ++i) LAUNCH(c, launch_matvec_timing(c->d, c->L));
-    HIP_TRY(c, hipEventRecord(e0, c->stream));
-    for (int i = 0; i < reps; ++i) LAUNCH(c, launch_matvec_timing(c->d, c->L));
-    HIP_TRY(c, hipEventRecord(e1, c->stream));
-    HIP_TRY(c, hipEventSynchronize(e1));
-    float f = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&f, e0, e1));
-    *ms = (double)f / reps;
+    TRY(time_products(c, reps, ms));
     tr.push_back({t, *ms});
     return SQRTBA_OK;
   };
@@ -1841,8 +1863,6 @@ int32_t sqrtba_autotune(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, sqrtba
   TRY(try_field(&sqrtba_tuning::small_rows, {4, 8}));
   TRY(apply_tuning(c, cur));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->event_pool.push_back(e0);
-  c->event_pool.push_back(e1);
   if (best) *best = cur;
   if (trials)
     for (int i = 0; i < (int)tr.size() && i < max_trials; ++i) trials[i] = tr[i];

@@ -137,6 +137,7 @@ _SIGS = {
     "sqrtba_get_tuning": (I32, [P, C.POINTER(Tuning)]),
     "sqrtba_set_tuning": (I32, [P, C.POINTER(Tuning)]),
     "sqrtba_autotune": (I32, [P, I32, C.POINTER(Tuning), C.POINTER(TuningTrial), I32, PI32]),
+    "sqrtba_time_product": (I32, [P, I32, PD, PD]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -437,6 +438,12 @@ class Context:
         n = C.c_int32()
         self._check(lib().sqrtba_autotune(self._h, reps, C.byref(best), trials, 32, C.byref(n)))
         return best.as_dict(), [(trials[i].shape.as_dict(), trials[i].ms) for i in range(min(n.value, 32))]
+
+    def time_product(self, reps: int = 50):
+        """(mean ms per product over reps back-to-back launches, algorithmic bytes per product)."""
+        ms, by = C.c_double(), C.c_double()
+        self._check(lib().sqrtba_time_product(self._h, reps, C.byref(ms), C.byref(by)))
+        return ms.value, by.value
 
     def save_state(self):
         self._check(lib().sqrtba_save_state(self._h))
