@@ -196,9 +196,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default product launch shapes")
-    ap.add_argument("--tuning", default=None, metavar="ROWS,SIDE,SEP,BATCH",
-                    help="fixed product launch shapes (huge_rows, huge_side, large_separate, small_rows) "
-                         "instead of autotuning, e.g. for counter runs under a profiler")
+    ap.add_argument("--tuning", default=None, metavar="EDGE,ROWS,SIDE,SEP,BATCH,PERSIST",
+                    help="fixed product bucket edge and launch shapes (rows_min_k, huge_rows, huge_side, "
+                         "large_separate, small_rows, persist_wgs) instead of autotuning, e.g. for counter runs "
+                         "under a profiler")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -228,8 +229,8 @@ def main():
     log(f"uploaded: workspace {ctx.workspace_bytes() / 1e9:.2f} GB")
     tuning = {"shape": ctx.get_tuning(), "autotuned": False}
     if args.tuning:
-        hr, hs, ls, sr = (int(x) for x in args.tuning.split(","))
-        ctx.set_tuning(huge_rows=hr, huge_side=hs, large_separate=ls, small_rows=sr)
+        keys = ["rows_min_k", "huge_rows", "huge_side", "large_separate", "small_rows", "persist_wgs"]
+        ctx.set_tuning(**dict(zip(keys, (int(x) for x in args.tuning.split(",")))))
         tuning = {"shape": ctx.get_tuning(), "autotuned": False}
     elif not args.no_autotune:
         t0 = time.perf_counter()

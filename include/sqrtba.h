@@ -350,18 +350,23 @@ int32_t sqrtba_restore_state(sqrtba_ctx* ctx);
 
 /* ---- launch shapes of the PCG product and their autotuner ---- */
 
-/* The product runs size-bucketed kernels (landmarks by observation count k);
- * these are the shapes that are not fixed by the buckets themselves.  None of
- * them changes the arithmetic except huge_rows, which sets how the rows of a
- * k > 113 block are grouped before their partial products are added. */
+/* The product runs size-bucketed kernels (landmarks by observation count k).
+ * These are its tunable bucket edge and launch shapes.  None of them changes
+ * the arithmetic except rows_min_k and huge_rows, which decide how the rows
+ * of the largest blocks are grouped before their partial products are added. */
 typedef struct {
-  int32_t huge_rows;      /* rows per workgroup for k > 113: 64, 128, 256, 512 or
-                             1024 (1024: one workgroup per landmark, no partials) */
-  int32_t huge_side;      /* 1: the k > 113 work runs on a second stream,
+  int32_t rows_min_k;     /* bucket edge: landmarks with k >= rows_min_k (114, 61 or 29)
+                             take the row-block kernel, the others with k >= 29 the
+                             four-wavefront landmark kernel */
+  int32_t huge_rows;      /* rows per workgroup of the row-block kernel: 64, 128, 256,
+                             512 or 1024 (1024: one workgroup per landmark, no partials) */
+  int32_t huge_side;      /* 1: the row-block kernel runs on a second stream,
                              concurrently with the rest of the product */
-  int32_t large_separate; /* 1: landmarks with 29 <= k <= 113 get a launch of their
-                             own (the small-class kernel then needs fewer registers) */
+  int32_t large_separate; /* 1: the four-wavefront landmarks get a launch of their own
+                             (the small-class kernel then needs fewer registers) */
   int32_t small_rows;     /* rows per batch for k <= 28: 4 or 8 */
+  int32_t persist_wgs;    /* 0: one workgroup per block of small landmarks; 1024, 2048
+                             or 4096: a persistent launch of that many workgroups */
 } sqrtba_tuning;
 
 typedef struct {
@@ -376,7 +381,7 @@ int32_t sqrtba_get_tuning(sqrtba_ctx* ctx, sqrtba_tuning* out);
 int32_t sqrtba_set_tuning(sqrtba_ctx* ctx, const sqrtba_tuning* shape);
 
 /* Time the product on the uploaded problem under candidate shapes and keep the
- * fastest: a coordinate search over the four fields in the order above, each
+ * fastest: a coordinate search over the fields in the order above, each
  * candidate timed over `reps` products (<= 0: 10) with HIP events on the
  * context stream.  The timing does not depend on the values in the landmark
  * blocks, so this may run right after upload; it overwrites only scratch

@@ -48,8 +48,8 @@ struct HostData {
   std::vector<int32_t> slot_zoff, cam_zpos;
   std::vector<float> cam_stats;  // NC * 4 features of the camera's observation graph
   WorkClass wc[NUM_CLASSES];
-  std::vector<int32_t> hjob;   // (slot, row block) pairs of the split class-5 product
-  std::vector<int64_t> hz_off; // per class-5 slot, offset of its partial outputs
+  std::vector<int32_t> hjob;   // (slot, row block) pairs of the row-block product (capacity)
+  std::vector<int64_t> hz_off; // per slot with k >= ROWS_MIN_K, offset of its partial outputs
   int64_t hz_floats = 0;
   int64_t poolB = 0, poolT = 0;
 };
@@ -216,17 +216,25 @@ void so3_log_d(const double M[9], double w[3]) {
 
 int64_t width_of_h(int64_t k) { return (9 * k + 3) & ~int64_t(3); }
 
-// (slot, row block) jobs of the split class-5 product for blocks of `rows` rows.
-void build_hjobs(const HostData& h, int rows, std::vector<int32_t>& jobs) {
+// (slot, row block) jobs of the row-block product for the first nrows slots
+// (the landmarks with the most observations) and blocks of `rows` rows.
+void build_hjobs(const HostData& h, int rows, int64_t nrows, std::vector<int32_t>& jobs) {
   jobs.clear();
-  for (int64_t i = 0; i < h.wc[5].slots; ++i) {
-    const int64_t sl = h.wc[5].first_slot + i, k = h.slot_k[sl];
+  for (int64_t sl = 0; sl < nrows; ++sl) {
+    const int64_t k = h.slot_k[sl];
     const int64_t nblk = (2 * k + rows - 1) / rows;
     for (int64_t r = 0; r < nblk; ++r) {
       jobs.push_back((int32_t)sl);
       jobs.push_back((int32_t)r);
     }
   }
+}
+
+// Number of leading slots with k >= kmin (slots are ordered by decreasing k).
+int64_t slots_with_k_at_least(const HostData& h, int64_t kmin) {
+  int64_t n = 0;
+  while (n < h.NS && h.slot_k[n] >= kmin) ++n;
+  return n;
 }
 
 // ------------------------------------------------------------ bookkeeping
@@ -356,16 +364,18 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
     while (s < nb.NS && class_of_k(nb.slot_k[s]) == cl) ++s;
     nb.wc[cl].slots = (int)(s - nb.wc[cl].first_slot);
   }
-  // split product of class 5: partial outputs per row block, sized for the
-  // smallest block (HUGE_ROWS_MIN rows); the job list is built per block size
+  // row-block product: partial outputs per row block for every landmark that
+  // can take it (k >= ROWS_MIN_K, a prefix of the slots), sized for the
+  // smallest block (HUGE_ROWS_MIN rows); the job list is built per shape
   nb.hz_off.clear();
   nb.hz_floats = 0;
-  for (int64_t i = 0; i < nb.wc[5].slots; ++i) {
-    const int64_t sl = nb.wc[5].first_slot + i, k = nb.slot_k[sl];
+  const int64_t n45 = slots_with_k_at_least(nb, ROWS_MIN_K);
+  for (int64_t sl = 0; sl < n45; ++sl) {
+    const int64_t k = nb.slot_k[sl];
     nb.hz_off.push_back(nb.hz_floats);
     nb.hz_floats += ((2 * k + HUGE_ROWS_MIN - 1) / HUGE_ROWS_MIN) * width_of_h(k);
   }
-  build_hjobs(nb, HUGE_ROWS_MIN, nb.hjob);
+  build_hjobs(nb, HUGE_ROWS_MIN, n45, nb.hjob);
   if (nb.hjob.size() / 2 > (size_t)INT32_MAX / 2) return fail(c, SQRTBA_E_UNSUPPORTED, "too many row blocks");
   // camera statistics for the learned preconditioner: observations, covisible
   // cameras (bitsets per problem), mean and max log k over the camera's landmarks
@@ -557,6 +567,22 @@ int upload_vec(sqrtba_ctx* c, T* dst, const std::vector<T>& v) {
   return SQRTBA_OK;
 }
 
+// Bucket edge and block size of the row-block product: rebuild and upload its
+// job list when either changes.
+int set_row_blocks(sqrtba_ctx* c, int rows_min_k, int rows) {
+  if (rows_min_k == c->L.rows_min_k && rows == c->L.huge_rows) return SQRTBA_OK;
+  const int64_t nrows = slots_with_k_at_least(c->h, rows_min_k);
+  std::vector<int32_t> jobs;
+  build_hjobs(c->h, rows, nrows, jobs);
+  if (jobs.size() > c->h.hjob.size()) return fail(c, SQRTBA_E_STATE, "row-block job list exceeds its allocation");
+  TRY(upload_vec(c, reinterpret_cast<int32_t*>(c->d.hjob), jobs));
+  c->L.rows_n = (int)nrows;
+  c->L.hjobs = (int)(jobs.size() / 2);
+  c->L.rows_min_k = rows_min_k;
+  c->L.huge_rows = rows;
+  return SQRTBA_OK;
+}
+
 int upload_state(sqrtba_ctx* c) {
   const HostData& h = c->h;
   std::vector<float> cam(16 * h.NC, 0.f), pts(4 * h.NL, 0.f);
@@ -606,12 +632,17 @@ int upload(sqrtba_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->L.stream = c->stream;
   for (int i = 0; i < NUM_CLASSES; ++i) c->L.wc[i] = h.wc[i];
-  // default launch shapes (the autotuner may replace them)
-  c->L.hjobs = (int)(h.hjob.size() / 2);
-  c->L.huge_rows = HUGE_ROWS_MIN;
+  // default launch shapes (the autotuner may replace them): the row-block
+  // kernel takes class 5 in 64-row blocks, class 4 stays in the main launch
+  // unless it is large
+  c->L.n45 = (int)slots_with_k_at_least(h, ROWS_MIN_K);
+  c->L.huge_rows = 0;
+  c->L.rows_min_k = 0;
   c->L.huge_side = 0;
   c->L.large_sep = h.wc[4].slots >= 256;
   c->L.mv_rbs = 0;
+  c->L.persist = 0;
+  TRY(set_row_blocks(c, class_kmax(4) + 1, HUGE_ROWS_MIN));
   if (!c->side) {
     HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
     HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
@@ -1744,32 +1775,29 @@ int32_t sqrtba_restore_state(sqrtba_ctx* c) {
 namespace {
 
 bool valid_tuning(const sqrtba_tuning& t) {
-  const int r = t.huge_rows;
-  return (r == 64 || r == 128 || r == 256 || r == 512 || r == 1024) && (t.huge_side == 0 || t.huge_side == 1) &&
-         (t.large_separate == 0 || t.large_separate == 1) && (t.small_rows == 4 || t.small_rows == 8);
+  const int r = t.huge_rows, e = t.rows_min_k, p = t.persist_wgs;
+  return (r == 64 || r == 128 || r == 256 || r == 512 || r == 1024) && (e == 114 || e == 61 || e == 29) &&
+         (t.huge_side == 0 || t.huge_side == 1) && (t.large_separate == 0 || t.large_separate == 1) &&
+         (t.small_rows == 4 || t.small_rows == 8) && (p == 0 || p == 1024 || p == 2048 || p == 4096);
 }
 
 sqrtba_tuning current_tuning(const sqrtba_ctx* c) {
   sqrtba_tuning t;
+  t.rows_min_k = c->L.rows_min_k;
   t.huge_rows = c->L.huge_rows;
   t.huge_side = c->L.huge_side;
   t.large_separate = c->L.large_sep;
   t.small_rows = c->L.mv_rbs ? 8 : 4;
+  t.persist_wgs = c->L.persist;
   return t;
 }
 
 int apply_tuning(sqrtba_ctx* c, const sqrtba_tuning& t) {
-  if (t.huge_rows != c->L.huge_rows) {
-    std::vector<int32_t> jobs;
-    build_hjobs(c->h, t.huge_rows, jobs);
-    if (jobs.size() > c->h.hjob.size()) return fail(c, SQRTBA_E_STATE, "row-block job list exceeds its allocation");
-    TRY(upload_vec(c, reinterpret_cast<int32_t*>(c->d.hjob), jobs));
-    c->L.hjobs = (int)(jobs.size() / 2);
-    c->L.huge_rows = t.huge_rows;
-  }
+  TRY(set_row_blocks(c, t.rows_min_k, t.huge_rows));
   c->L.huge_side = t.huge_side;
   c->L.large_sep = t.large_separate;
   c->L.mv_rbs = t.small_rows == 8 ? 1 : 0;
+  c->L.persist = t.persist_wgs;
   if (c->graph) {  // the captured PCG iterations hold the old launches
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
@@ -1840,7 +1868,6 @@ int32_t sqrtba_autotune(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, sqrtba
   sqrtba_tuning cur = current_tuning(c);
   double cur_ms = 0.0;
   TRY(measure(cur, &cur_ms));
-  const bool huge = c->h.wc[5].slots > 0, large = c->h.wc[4].slots > 0;
   auto try_field = [&](int sqrtba_tuning::*field, std::initializer_list<int> values) -> int {
     for (int v : values) {
       if (cur.*field == v) continue;
@@ -1855,12 +1882,16 @@ int32_t sqrtba_autotune(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, sqrtba
     }
     return SQRTBA_OK;
   };
-  if (huge) {
+  // bucket edge first (it decides which kernels run), then the shapes of the
+  // kernels that do run
+  if (c->L.n45 > 0) TRY(try_field(&sqrtba_tuning::rows_min_k, {114, 61, 29}));
+  if (c->L.rows_n > 0) {
     TRY(try_field(&sqrtba_tuning::huge_rows, {64, 128, 256, 1024}));
     TRY(try_field(&sqrtba_tuning::huge_side, {0, 1}));
   }
-  if (large) TRY(try_field(&sqrtba_tuning::large_separate, {0, 1}));
+  if (c->L.n45 > c->L.rows_n) TRY(try_field(&sqrtba_tuning::large_separate, {0, 1}));
   TRY(try_field(&sqrtba_tuning::small_rows, {4, 8}));
+  TRY(try_field(&sqrtba_tuning::persist_wgs, {0, 1024, 2048, 4096}));
   TRY(apply_tuning(c, cur));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (best) *best = cur;

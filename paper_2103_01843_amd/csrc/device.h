@@ -59,10 +59,10 @@ struct Dev {
   int32_t* slot_zoff;  // float offset of the landmark's W product outputs in obsbuf (16-byte aligned)
   int32_t* cam_zpos;   // NO: obsbuf offset of the outputs of each camera's observations (camera order)
   int32_t* lm_slot;    // NL, -1 when inactive
-  // split product of the largest landmarks (class 5): one job per block of
-  // Launch::huge_rows rows (x: slot, y: row block), partial outputs per row block
+  // row-block product of the largest landmarks: one job per block of
+  // Launch::huge_rows rows (x: slot, y: row block), partial outputs per block
   int2* hjob;
-  int64_t* hz_off;  // per class-5 slot: float offset of its partial outputs in zpart (nblocks x W)
+  int64_t* hz_off;  // per slot with k >= 29 (a prefix of the slots): offset of its partials in zpart
   float* zpart;
   float* poolB;
   float* poolT;
@@ -112,17 +112,23 @@ struct WorkClass {
   int slots;       // number of slots
 };
 
-// Smallest row block of the split class-5 product (sizes the job list and the
+// Smallest row block of the row-block product (sizes the job list and the
 // partial outputs); the tuned block size is a multiple of it.
 enum { HUGE_ROWS_MIN = 64 };
+// Smallest bucket edge of the row-block product (sizes its slot range).
+enum { ROWS_MIN_K = 29 };
 
 struct Launch {
   // launch shapes of the product (set by the autotuner or sqrtba_set_tuning)
-  int hjobs;       // number of split-product jobs (class 5) for huge_rows
-  int huge_rows;   // rows per class-5 job (>= 2 * 512: one job per landmark)
-  int huge_side;   // class-5 jobs on the side stream, concurrent with the rest
-  int large_sep;   // class 4 as its own launch (else inside the small-class launch)
+  int n45;         // slots with k >= 29 (classes 5 and 4, a prefix of the slots)
+  int rows_min_k;  // bucket edge: landmarks with k >= rows_min_k take the row-block kernel
+  int rows_n;      // their number (a prefix of the slots)
+  int hjobs;       // number of row-block jobs for huge_rows
+  int huge_rows;   // rows per job (>= 2 * 512: one job per landmark)
+  int huge_side;   // row-block jobs on the side stream, concurrent with the rest
+  int large_sep;   // the rest of k >= 29 as its own launch (else inside the small-class launch)
   int mv_rbs;      // row-batch set of the small classes (0: 4 rows, 1: 8 rows)
+  int persist;     // > 0: the small-class launch is persistent with this many workgroups
   hipStream_t stream;
   hipStream_t side;   // second stream for the largest landmarks (may be null)
   hipEvent_t fork, join;

@@ -901,16 +901,15 @@ __host__ __device__ constexpr int mv_per_wg(int j) {  // j: launch-order class i
   return j == 0 ? 1 : WG / class_team(4 - j);
 }
 
-// One launch for the size classes 0..3 (and 4 when LARGE): every workgroup
-// belongs to one class, so the product over these landmarks is a single
-// kernel with no tail gaps between classes.  Without LARGE the kernel holds no
-// class-4 code and needs fewer registers (more resident wavefronts); class 4
-// then runs as its own launch (k_matvec_large).
+// Workgroup b of the product over the size classes 0..3 (and 4 when LARGE):
+// every workgroup belongs to one class, so the product over these landmarks is
+// a single kernel with no tail gaps between classes.  Without LARGE the kernel
+// holds no class-4 code and needs fewer registers (more resident wavefronts);
+// class 4 then runs as its own launch (k_matvec_large).
 template <bool PCG, bool LARGE, int RBS>
-__global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, const float* v) {
-  int b = blockIdx.x;
+__device__ __forceinline__ void matvec_block(const Dev& d, const ClassGrid& m, int b, const float* v,
+                                             float4 (*zred)[64]) {
   if constexpr (LARGE) {
-    __shared__ float4 zred[4][64];
     if (b < m.nblk[0]) { matvec_large<4, MV_RS, PCG>(d, m.first[0] + b, v, zred); return; }
     b -= m.nblk[0];
   }
@@ -923,6 +922,19 @@ __global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, const float* 
   matvec_teams<8, mv_rb(RBS, 3), PCG>(d, m.first[4] + b * mv_per_wg(4), m.end[4], v);
 }
 
+// One launch of the product over classes 0..3 (and 4): one workgroup per
+// block, or, PERSIST, a fixed grid whose workgroups take blocks b, b + grid,
+// ... in turn (largest landmarks first, so the static round-robin balances).
+template <bool PCG, bool LARGE, int RBS, bool PERSIST>
+__global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, int nwork, const float* v) {
+  __shared__ float4 zred[LARGE ? 4 : 1][64];
+  if constexpr (PERSIST) {
+    for (int b = blockIdx.x; b < nwork; b += gridDim.x) matvec_block<PCG, LARGE, RBS>(d, m, b, v, zred);
+  } else {
+    matvec_block<PCG, LARGE, RBS>(d, m, blockIdx.x, v, zred);
+  }
+}
+
 // Class 4 on its own: one landmark per workgroup.
 template <bool PCG>
 __global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int slot0, const float* v) {
@@ -930,11 +942,11 @@ __global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int slot0, const flo
   matvec_large<4, MV_RS, PCG>(d, slot0 + blockIdx.x, v, zred);
 }
 
-// Landmarks with k > 113 (up to 512), split into blocks of `rows` rows so that
-// a few very large landmarks still spread over the whole chip: job j (slot,
-// row block) runs on one workgroup of four wavefronts (wave w takes rows w,
-// w+4, ... of the block) and writes its partial z for the block; a landmark
-// with a single block writes its outputs directly.
+// The largest landmarks (k at least the tuned edge, 29..512), split into blocks
+// of `rows` rows so that a few very large landmarks still spread over the
+// whole chip: job j (slot, row block) runs on one workgroup of four wavefronts
+// (wave w takes rows w, w+4, ... of the block) and writes its partial z for
+// the block; a landmark with a single block writes its outputs directly.
 template <bool PCG>
 __global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, int rows, const float* v) {
   constexpr int NCG = 18;  // ceil(width_of(512) / 4 / 64)
@@ -991,8 +1003,9 @@ __global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, int rows, 
   }
 }
 
-// Sum of the row-block partials of every class-5 landmark with more than one
-// block, in block order, into its outputs (one workgroup per landmark).
+// Sum of the row-block partials of every landmark of the row-block kernel with
+// more than one block, in block order, into its outputs (one workgroup per
+// landmark).
 template <bool PCG>
 __global__ __launch_bounds__(WG) void k_matvec_combine(Dev d, int slot0, int rows) {
   const int slot = slot0 + blockIdx.x;
@@ -1804,39 +1817,59 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
 // stream, concurrently with the rest, when huge_side), class 4 (inside the
 // main launch, or on its own when large_sep), classes 0..3, then the sum of
 // the class-5 partials.  The launch shapes are the tunables of Launch.
+template <bool PCG, bool LARGE, int RBS>
+static void launch_small3(const Dev& d, const Launch& L, const ClassGrid& m, int n, const float* v) {
+  if (L.persist > 0 && n > L.persist)
+    hipLaunchKernelGGL((k_matvec<PCG, LARGE, RBS, true>), dim3(L.persist), dim3(WG), 0, L.stream, d, m, n, v);
+  else
+    hipLaunchKernelGGL((k_matvec<PCG, LARGE, RBS, false>), dim3(n), dim3(WG), 0, L.stream, d, m, n, v);
+}
+
 template <bool PCG, bool LARGE>
 static void launch_small(const Dev& d, const Launch& L, const ClassGrid& m, int n, const float* v) {
   if (L.mv_rbs == 0)
-    hipLaunchKernelGGL((k_matvec<PCG, LARGE, 0>), dim3(n), dim3(WG), 0, L.stream, d, m, v);
+    launch_small3<PCG, LARGE, 0>(d, L, m, n, v);
   else
-    hipLaunchKernelGGL((k_matvec<PCG, LARGE, 1>), dim3(n), dim3(WG), 0, L.stream, d, m, v);
+    launch_small3<PCG, LARGE, 1>(d, L, m, n, v);
 }
 
+// Product over all landmark blocks.  Slots are ordered by decreasing k, so the
+// landmarks with k >= 29 form the prefix [0, n45); its first rows_n slots (k at
+// least the tuned edge) go to the row-block kernel (on the side stream when
+// huge_side), the rest of the prefix to the large-landmark path (inside the
+// main launch, or on its own when large_sep), then classes 0..3, then the sum
+// of the row-block partials.
 template <bool PCG>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
-  const WorkClass* w = L.wc;
-  const bool huge = w[5].slots > 0 && L.hjobs > 0;
-  const bool side = huge && L.huge_side && L.side && L.fork && L.join;
+  const bool rows = L.rows_n > 0 && L.hjobs > 0;
+  const bool side = rows && L.huge_side && L.side && L.fork && L.join;
   const hipStream_t hs = side ? L.side : L.stream;
-  if (huge) {
+  if (rows) {
     if (side) {
       hipError_t e = hipEventRecord(L.fork, L.stream);
       if (e == hipSuccess) e = hipStreamWaitEvent(L.side, L.fork, 0);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_matvec_rows<PCG>, dim3(L.hjobs), dim3(WG), 0, hs, d, w[5].first_slot, L.huge_rows, v);
+    hipLaunchKernelGGL(k_matvec_rows<PCG>, dim3(L.hjobs), dim3(WG), 0, hs, d, 0, L.huge_rows, v);
     LAUNCH_CHECK();
     if (L.huge_rows < 2 * class_kmax(5))
-      hipLaunchKernelGGL(k_matvec_combine<PCG>, dim3(w[5].slots), dim3(WG), 0, hs, d, w[5].first_slot, L.huge_rows);
+      hipLaunchKernelGGL(k_matvec_combine<PCG>, dim3(L.rows_n), dim3(WG), 0, hs, d, 0, L.huge_rows);
     LAUNCH_CHECK();
   }
-  const bool sep = L.large_sep && w[4].slots > 0;
+  const int nlarge = L.n45 - L.rows_n;
+  const bool sep = L.large_sep && nlarge > 0;
   if (sep) {
-    hipLaunchKernelGGL(k_matvec_large<PCG>, dim3(w[4].slots), dim3(WG), 0, L.stream, d, w[4].first_slot, v);
+    hipLaunchKernelGGL(k_matvec_large<PCG>, dim3(nlarge), dim3(WG), 0, L.stream, d, L.rows_n, v);
     LAUNCH_CHECK();
   }
   int n = 0;
-  const ClassGrid m = class_grid(L, &n, sep);
+  ClassGrid m = class_grid(L, &n, true);
+  if (!sep && nlarge > 0) {  // the large-landmark path inside the main launch
+    m.nblk[0] = nlarge;
+    m.first[0] = L.rows_n;
+    m.end[0] = L.n45;
+    n += nlarge;
+  }
   if (n) {
     if (m.nblk[0])
       launch_small<PCG, true>(d, L, m, n, v);

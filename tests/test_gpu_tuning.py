@@ -2,10 +2,11 @@
 
 Every shape must give the oracle's reduced camera system to the same bar as
 the default shape (1e-4 relative in Frobenius norm).  Shapes that do not
-regroup rows give bitwise the default shape's product; huge_rows regroups the
-rows of k > 113 blocks before their partial products are added, so it is held
-to the oracle bar only.  The autotuner must return the fastest of the shapes it
-timed and leave the solver's result unchanged within rounding.
+regroup rows give bitwise the default shape's product; the bucket edge
+rows_min_k and huge_rows regroup the rows of the largest blocks before their
+partial products are added, so they are held to the oracle bar only.  The
+autotuner must return the fastest of the shapes it timed and leave the
+solver's result unchanged within rounding.
 """
 
 import numpy as np
@@ -18,15 +19,19 @@ from gpu_util import gpu_context, mixed_problem, oracle_lin
 
 pytestmark = pytest.mark.gpu
 
-DEFAULT = dict(huge_rows=64, huge_side=0, large_separate=0, small_rows=4)
+DEFAULT = dict(rows_min_k=114, huge_rows=64, huge_side=0, large_separate=0, small_rows=4, persist_wgs=0)
 SHAPES = [
     dict(DEFAULT, huge_side=1),
     dict(DEFAULT, large_separate=1),
     dict(DEFAULT, small_rows=8),
+    dict(DEFAULT, persist_wgs=1024),
+    dict(DEFAULT, persist_wgs=4096, small_rows=8, large_separate=1),
     dict(DEFAULT, huge_rows=128),
     dict(DEFAULT, huge_rows=512),
     dict(DEFAULT, huge_rows=1024),
-    dict(huge_rows=256, huge_side=1, large_separate=1, small_rows=8),
+    dict(DEFAULT, rows_min_k=61),
+    dict(DEFAULT, rows_min_k=29, huge_rows=256, huge_side=1),
+    dict(rows_min_k=29, huge_rows=1024, huge_side=1, large_separate=1, small_rows=8, persist_wgs=2048),
 ]
 
 
@@ -55,13 +60,14 @@ def test_every_shape_gives_the_reduced_system(mixed):
         H = ctx.debug_rcs_matvec(V)
         e = np.linalg.norm(H.astype(np.float64) - rs.H) / np.linalg.norm(rs.H)
         assert e <= 1e-4, (sh, e)
-        if sh["huge_rows"] == DEFAULT["huge_rows"]:
+        if sh["huge_rows"] == DEFAULT["huge_rows"] and sh["rows_min_k"] == DEFAULT["rows_min_k"]:
             np.testing.assert_array_equal(H, ref, err_msg=str(sh))
     ctx.close()
 
 
 @pytest.mark.parametrize("bad", [dict(huge_rows=100), dict(huge_rows=32), dict(small_rows=5),
-                                 dict(huge_side=2), dict(large_separate=-1)])
+                                 dict(huge_side=2), dict(large_separate=-1), dict(rows_min_k=30),
+                                 dict(rows_min_k=200), dict(persist_wgs=1000), dict(persist_wgs=-1)])
 def test_invalid_shapes_are_rejected(mixed, bad):
     p, _ = mixed
     ctx = gpu_context(p)
@@ -82,7 +88,7 @@ def test_autotune_keeps_the_fastest_shape_and_the_result(mixed):
     ctx = gpu_context(p, max_lm_iters=6)
     best, trials = ctx.autotune(reps=3)
     assert best == ctx.get_tuning()
-    assert len(trials) >= 5  # the mixed problem has landmarks in every size class
+    assert len(trials) >= 10  # the mixed problem has landmarks in every size class
     ms = [t for _, t in trials]
     assert all(t > 0 for t in ms)
     assert best == trials[int(np.argmin(ms))][0]
