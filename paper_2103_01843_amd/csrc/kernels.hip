@@ -1043,7 +1043,9 @@ __global__ __launch_bounds__(WG) void k_matvec_combine(Dev d, int slot0, int row
 // workgroup (the one holding the problem's first camera) and never read back
 // in the kernel that writes it; the one exception, the done flag, only ever
 // goes from 0 to 1 and every workgroup that reads it makes the same decision
-// from the sums it formed itself.
+// from the sums it formed itself.  (Waves of one workgroup may read the flag
+// before and after it is set; they then take the same exit, since a wave
+// that went on finds the test failed and the others' partial sums unused.)
 
 __device__ __forceinline__ double problem_sum(const Dev& d, const double* __restrict__ part, int p, int lane) {
   double s = 0.0;
@@ -1159,9 +1161,12 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
   __shared__ int go_s;
   const int c = blockIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // loads that do not depend on the problem's state first
-  const int prob = d.cam_prob[c];
+  // the first output positions are requested together with the problem's
+  // state (one load latency), the outputs only for a problem still solving
   const int b = d.cam_obs_off[c], e = d.cam_obs_off[c + 1];
+  const int prob = d.cam_prob[c];
+  int zp[Q_UNROLL];
+  q_positions(d, b, e, zp);
   float zc = 0.f, pc = 0.f, qc = 0.f, sc = 0.f;
   if (threadIdx.x < 9) {
     const int idx = 9 * c + threadIdx.x;
@@ -1170,18 +1175,16 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
     qc = d.vq[idx];
     sc = d.s_cam[idx];
   }
-  if (!d.active[prob] || d.done[prob]) return;  // uniform over the workgroup
-  int zp[Q_UNROLL];
-  q_positions(d, b, e, zp);
+  if (!d.active[prob] || d.done[prob]) return;  // see the note at the top of this section
   if (w == 0) {
-    double rz, rr;
-    problem_sum2(d, d.cam_part2, d.cam_part3, prob, lane, rz, rr);
-    if (lane == 0) {
-      const int t = pcg_test(d, prob, rz, rr);
-      const double beta = rz / d.rz[prob];
-      beta_s = (float)beta;
-      go_s = t == 0;
-      if (c == d.prob_cam_off[prob]) {  // designated writer of the problem's scalars
+    int t = 3;  // 3: the problem's solve has ended (or it is inactive)
+    double beta = 0.0;
+    {
+      double rz, rr;
+      problem_sum2(d, d.cam_part2, d.cam_part3, prob, lane, rz, rr);
+      t = pcg_test(d, prob, rz, rr);
+      beta = rz / d.rz[prob];
+      if (lane == 0 && c == d.prob_cam_off[prob]) {  // designated writer of the problem's scalars
         d.rr[prob] = rr;
         if (t) {
           d.done[prob] = 1;
@@ -1191,6 +1194,10 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
           d.beta[prob] = beta;
         }
       }
+    }
+    if (lane == 0) {
+      beta_s = (float)beta;
+      go_s = t == 0;
     }
   }
   float acc[9];
@@ -1778,13 +1785,28 @@ hipError_t launch_prob_sum(const Dev& d, const Launch& L, const double* vals, co
   return hipSuccess;
 }
 
+// Class 5 (few, long workgroups) runs on the side stream concurrently with
+// classes 0..4 when both are present.
 hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask) {
   const WorkClass* w = L.wc;
-  if (w[5].slots) hipLaunchKernelGGL(k_marginalize_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot, mask);
   int n = 0;
   const ClassGrid m = class_grid(L, &n);
+  const bool side = w[5].slots && n && L.side && L.fork && L.join;
+  if (side) {
+    hipError_t e = hipEventRecord(L.fork, L.stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(L.side, L.fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  if (w[5].slots)
+    hipLaunchKernelGGL(k_marginalize_huge, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d, w[5].first_slot, mask);
+  LAUNCH_CHECK();
   if (n) hipLaunchKernelGGL(k_marginalize, dim3(n), dim3(WG), 0, L.stream, d, m, mask);
   LAUNCH_CHECK();
+  if (side) {
+    hipError_t e = hipEventRecord(L.join, L.side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(L.stream, L.join, 0);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
