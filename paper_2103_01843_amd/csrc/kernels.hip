@@ -213,17 +213,6 @@ __global__ __launch_bounds__(SUM_THREADS) void k_prob_sum(const double* __restri
   }
 }
 
-// ------------------------------------------- kernel (b): marginalize by QR
-
-// Per landmark (team): linearize its k observations, scale the landmark columns
-// to unit norm, factor J_l (2k x 3) = Q R with three Householder reflections
-// H_j = I - tau_j v_j v_j^T, v_j = x + sign(x_j) |x| e_j (sign(0) = +1), and
-// write Q^T [J_p | r].  Q^T = I - V T^T V^T (compact WY form, T upper
-// triangular), so each output entry is the sparse J_p entry minus a rank-3
-// correction: only O(k) values are combined, and the O(k^2) output is written
-// once, coalesced, as float4 rows.
-//   rows 0..2   -> undamped top rows [Q1^T J_p | R1 | Q1^T r] (poolT, lmd)
-//   rows 3..2k-1 -> nullspace rows [Q2^T J_p | 0 | Q2^T r]    (poolB, rhoB)
 // Slot ranges of the size classes, in launch order (class 4, 3, 2, 1, 0):
 // workgroup b of class j takes slots first[j] + b * (WG / team size) onwards
 // (one slot per workgroup for class 4).  The slot of every team follows from
@@ -263,13 +252,60 @@ __device__ __forceinline__ void class_dispatch(const ClassGrid& m, const F& f) {
   if (slot < m.end[4]) f.template run<8, 0>(slot, threadIdx.x % 8, t);
 }
 
-// LDS floats per team: A (2k x 4, J_l scaled, updated in place), V (2k x 4),
-// r (2k), Jp (k x 18).
-__host__ __device__ constexpr int marg_stride(int kmax) { return 36 * kmax; }
+// ------------------------------------------- kernel (b): marginalize by QR
+
+// Per landmark (team): linearize its k observations, scale the landmark columns
+// to unit norm, factor J_l (2k x 3) = Q R with three Householder reflections
+// H_j = I - tau_j v_j v_j^T, v_j = x + sign(x_j) |x| e_j (sign(0) = +1), and
+// write Q^T [J_p | r].  Q^T = I - V T^T V^T (compact WY form, T upper
+// triangular), so each output entry is the sparse J_p entry minus a rank-3
+// correction: only O(k) values are combined, and the O(k^2) output is written
+// once, coalesced, as float4 rows.
+//   rows 0..2   -> undamped top rows [Q1^T J_p | R1 | Q1^T r] (poolT, lmd)
+//   rows 3..2k-1 -> nullspace rows [Q2^T J_p | 0 | Q2^T r]    (poolB, rhoB)
+//
+// Each lane owns the observations o = lane, lane + TEAM, ... and their two rows
+// (rows 2o, 2o + 1) from linearization through the reflections, in registers,
+// so phases 1-3 need no LDS and no barrier besides the reductions; several
+// independent sums are reduced together.  Only the reflectors V and the pose
+// Jacobians go to LDS, for phase 4, where every lane needs every row.
+
+// Sum over the team of N values per lane; every lane gets the same bits.  For
+// TEAM <= 64 a DPP all-reduce; for a workgroup team, one barrier, with the
+// wavefront partials in one of two LDS buffers (alternating, so a buffer is
+// rewritten only after every thread has passed the barrier that follows the
+// reads of its previous use).
+template <int TEAM, int N>
+__device__ __forceinline__ void team_sum_n(float (&v)[N], float* red, int& buf) {
+  if constexpr (TEAM <= 64) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = team_sum<TEAM>(v[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = wave_sum_f(v[i]);
+    float* r = red + buf * (4 * 8);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) r[8 * w + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = (r[i] + r[8 + i]) + (r[16 + i] + r[24 + i]);
+    buf ^= 1;
+  }
+}
+
+// LDS floats per team: V (2k x 4) and the pose Jacobians (k x 18), rounded up
+// to whole float4s so that every team's V is 16-byte aligned.
+__host__ __device__ constexpr int marg_stride(int kmax) { return (26 * kmax + 3) & ~3; }
+// LDS floats of the reductions of a workgroup team (two buffers of 4 x 8).
+constexpr int MARG_RED = 64;
 
 template <int TEAM, int KMAX>
-__device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane, float* lds, float* red4,
+__device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane, float* lds, float* red,
                                                 const uint8_t* mask) {
+  constexpr int OPL = (KMAX + TEAM - 1) / TEAM;  // observations per lane
   const int prob = d.slot_prob[slot];
   if (mask && !mask[prob]) return;
   const int k = d.slot_k[slot];
@@ -277,63 +313,71 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
   const int n = 2 * k;
   const int W = width_of(k);
   const int G = W >> 2;
-  float4* A = reinterpret_cast<float4*>(lds);
-  float4* V = A + 2 * KMAX;
-  float* rr = reinterpret_cast<float*>(V + 2 * KMAX);
-  float* Jpc = rr + 2 * KMAX;
+  float4* V = reinterpret_cast<float4*>(lds);
+  float* Jpc = lds + 8 * KMAX;
   const float4 X = d.pts[d.slot_lm[slot]];
+  int buf = 0;
 
-  // phase 1: residuals and Jacobians of the landmark's observations
-  float cl0 = 0.f, cl1 = 0.f, cl2 = 0.f;
-  for (int o = lane; o < k; o += TEAM) {
-    Cam C;
-    load_cam(d.cam, d.obs_cam[obs0 + o], C);
-    const float2 uv = d.obs_uv[obs0 + o];
-    float r[2], Jp[2][9], Jl[2][3];
-    project<true>(C, X.x, X.y, X.z, uv.x, uv.y, r, Jp, Jl);
+  // phase 1: residuals and Jacobians of the lane's observations
+  float3 A[2 * OPL];   // rows 2o, 2o+1 of J_l (scaled below), o = lane + TEAM m
+  float rr[2 * OPL];
+  float cl[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      Jpc[18 * o + j] = Jp[0][j];
-      Jpc[18 * o + 9 + j] = Jp[1][j];
+  for (int m = 0; m < OPL; ++m) {
+    const int o = lane + TEAM * m;
+    A[2 * m] = A[2 * m + 1] = make_float3(0.f, 0.f, 0.f);
+    rr[2 * m] = rr[2 * m + 1] = 0.f;
+    if (o < k) {
+      Cam C;
+      load_cam(d.cam, d.obs_cam[obs0 + o], C);
+      const float2 uv = d.obs_uv[obs0 + o];
+      float r[2], Jp[2][9], Jl[2][3];
+      project<true>(C, X.x, X.y, X.z, uv.x, uv.y, r, Jp, Jl);
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        Jpc[18 * o + j] = Jp[0][j];
+        Jpc[18 * o + 9 + j] = Jp[1][j];
+      }
+      A[2 * m] = make_float3(Jl[0][0], Jl[0][1], Jl[0][2]);
+      A[2 * m + 1] = make_float3(Jl[1][0], Jl[1][1], Jl[1][2]);
+      rr[2 * m] = r[0];
+      rr[2 * m + 1] = r[1];
+      cl[0] += Jl[0][0] * Jl[0][0] + Jl[1][0] * Jl[1][0];
+      cl[1] += Jl[0][1] * Jl[0][1] + Jl[1][1] * Jl[1][1];
+      cl[2] += Jl[0][2] * Jl[0][2] + Jl[1][2] * Jl[1][2];
     }
-    A[2 * o] = make_float4(Jl[0][0], Jl[0][1], Jl[0][2], 0.f);
-    A[2 * o + 1] = make_float4(Jl[1][0], Jl[1][1], Jl[1][2], 0.f);
-    rr[2 * o] = r[0];
-    rr[2 * o + 1] = r[1];
-    cl0 += Jl[0][0] * Jl[0][0] + Jl[1][0] * Jl[1][0];
-    cl1 += Jl[0][1] * Jl[0][1] + Jl[1][1] * Jl[1][1];
-    cl2 += Jl[0][2] * Jl[0][2] + Jl[1][2] * Jl[1][2];
   }
-  cl0 = tsum<TEAM>(cl0, red4);
-  cl1 = tsum<TEAM>(cl1, red4);
-  cl2 = tsum<TEAM>(cl2, red4);
-  const float sl0 = cl0 > 0.f ? 1.0f / sqrtf(cl0) : 1.0f;
-  const float sl1 = cl1 > 0.f ? 1.0f / sqrtf(cl1) : 1.0f;
-  const float sl2 = cl2 > 0.f ? 1.0f / sqrtf(cl2) : 1.0f;
-  team_sync<TEAM>();
-  for (int i = lane; i < n; i += TEAM) {
-    float4 a = A[i];
-    a.x *= sl0; a.y *= sl1; a.z *= sl2;
-    A[i] = a;
+  team_sum_n<TEAM, 3>(cl, red, buf);
+  const float sl0 = cl[0] > 0.f ? 1.0f / sqrtf(cl[0]) : 1.0f;
+  const float sl1 = cl[1] > 0.f ? 1.0f / sqrtf(cl[1]) : 1.0f;
+  const float sl2 = cl[2] > 0.f ? 1.0f / sqrtf(cl[2]) : 1.0f;
+#pragma unroll
+  for (int i = 0; i < 2 * OPL; ++i) {
+    A[i].x *= sl0;
+    A[i].y *= sl1;
+    A[i].z *= sl2;
   }
-  team_sync<TEAM>();
+  auto row_of = [&](int i) { return 2 * (lane + TEAM * (i >> 1)) + (i & 1); };  // own row i -> block row
+  auto comp = [](const float3& a, int j) { return j == 0 ? a.x : (j == 1 ? a.y : a.z); };
 
   // phase 2: three Householder reflections on the scaled J_l
-  float tau[3], Rm[3][3];
+  float3 Vr[2 * OPL];
+#pragma unroll
+  for (int i = 0; i < 2 * OPL; ++i) Vr[i] = make_float3(0.f, 0.f, 0.f);
+  float tau[3], alph[3], nrms[3], Rrow[3][3];  // Rrow: row j of R1 as seen by its owner
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    float part = 0.f;
-    for (int i = lane; i < n; i += TEAM) {
-      if (i >= j) {
-        const float4 a = A[i];
-        const float x = j == 0 ? a.x : (j == 1 ? a.y : a.z);
-        part += x * x;
-      }
+    // |x|^2 over rows >= j and x_j itself (contributed by the owner of row j)
+    float sx[2] = {0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 2 * OPL; ++i) {
+      const int gi = row_of(i);
+      const float x = comp(A[i], j);
+      if (gi < n && gi >= j) sx[0] += x * x;
+      if (gi == j) sx[1] = x;
     }
-    const float sig = tsum<TEAM>(part, red4);
-    const float4 aj = A[j];
-    const float xj = j == 0 ? aj.x : (j == 1 ? aj.y : aj.z);
-    const float nrm = sqrtf(sig);
+    team_sum_n<TEAM, 2>(sx, red, buf);
+    const float nrm = sqrtf(sx[0]), xj = sx[1];
     float alpha = 0.f, vj = 0.f, tj = 0.f;
     if (nrm > 0.f) {
       // v = x + sign(x_j) |x| e_j, so v^T v = 2 |x| (|x| + |x_j|) exactly: tau = 2 / v^T v
@@ -343,53 +387,51 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
       tj = 1.0f / (nrm * (nrm + fabsf(xj)));
     }
     tau[j] = tj;
-    // reflector column j of V
-    for (int i = lane; i < n; i += TEAM) {
-      const float4 a = A[i];
-      const float x = j == 0 ? a.x : (j == 1 ? a.y : a.z);
-      const float vi = (tj == 0.f || i < j) ? 0.f : (i == j ? vj : x);
-      float4 vv = (j == 0) ? make_float4(0.f, 0.f, 0.f, 0.f) : V[i];
-      if (j == 0) vv.x = vi; else if (j == 1) vv.y = vi; else vv.z = vi;
-      V[i] = vv;
+    alph[j] = alpha;
+    nrms[j] = nrm;
+    // reflector j on the lane's rows, and w_m = v^T a_m for the columns m > j
+    float wv[2] = {0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 2 * OPL; ++i) {
+      const int gi = row_of(i);
+      const float x = comp(A[i], j);
+      const float vi = (tj == 0.f || gi < j || gi >= n) ? 0.f : (gi == j ? vj : x);
+      if (j == 0) Vr[i].x = vi; else if (j == 1) Vr[i].y = vi; else Vr[i].z = vi;
+      if (j == 0) { wv[0] += vi * A[i].y; wv[1] += vi * A[i].z; }
+      else if (j == 1) { wv[0] += vi * A[i].z; }
     }
-    team_sync<TEAM>();
-    // apply H_j to the remaining columns m > j
-    float w1 = 0.f, w2 = 0.f;
-    for (int i = lane; i < n; i += TEAM) {
-      const float4 vv = V[i];
-      const float vi = j == 0 ? vv.x : (j == 1 ? vv.y : vv.z);
-      const float4 a = A[i];
-      if (j == 0) { w1 += vi * a.y; w2 += vi * a.z; }
-      else if (j == 1) { w2 += vi * a.z; }
+    if (j == 0) {
+      team_sum_n<TEAM, 2>(wv, red, buf);
+    } else if (j == 1) {
+      float w1[1] = {wv[0]};
+      team_sum_n<TEAM, 1>(w1, red, buf);
+      wv[0] = w1[0];
     }
-    if (j == 0) { w1 = tsum<TEAM>(w1, red4); w2 = tsum<TEAM>(w2, red4); }
-    else if (j == 1) { w2 = tsum<TEAM>(w2, red4); }
-    for (int i = lane; i < n; i += TEAM) {
-      const float4 vv = V[i];
-      const float vi = j == 0 ? vv.x : (j == 1 ? vv.y : vv.z);
-      float4 a = A[i];
-      if (j == 0) { a.y -= tj * vi * w1; a.z -= tj * vi * w2; }
-      else if (j == 1) { a.z -= tj * vi * w2; }
-      A[i] = a;
+    // apply H_j to the remaining columns m > j of the lane's rows
+#pragma unroll
+    for (int i = 0; i < 2 * OPL; ++i) {
+      const float vi = comp(Vr[i], j);
+      if (j == 0) { A[i].y -= tj * vi * wv[0]; A[i].z -= tj * vi * wv[1]; }
+      else if (j == 1) { A[i].z -= tj * vi * wv[0]; }
     }
-    team_sync<TEAM>();
-    const float4 arow = A[j];
-    Rm[j][0] = 0.f; Rm[j][1] = 0.f; Rm[j][2] = 0.f;
-    if (j == 0) { Rm[0][0] = nrm > 0.f ? alpha : arow.x; Rm[0][1] = arow.y; Rm[0][2] = arow.z; }
-    if (j == 1) { Rm[1][1] = nrm > 0.f ? alpha : arow.y; Rm[1][2] = arow.z; }
-    if (j == 2) { Rm[2][2] = nrm > 0.f ? alpha : arow.z; }
+    // the owner of row j keeps it (entries of R1 right of the diagonal)
+#pragma unroll
+    for (int i = 0; i < 2 * OPL; ++i)
+      if (row_of(i) == j) { Rrow[j][0] = A[i].x; Rrow[j][1] = A[i].y; Rrow[j][2] = A[i].z; }
   }
 
-  // phase 3: T of the compact WY form (LAPACK larft, forward columnwise)
-  float d01 = 0.f, d02 = 0.f, d12 = 0.f, wr0 = 0.f, wr1 = 0.f, wr2 = 0.f;
-  for (int i = lane; i < n; i += TEAM) {
-    const float4 vv = V[i];
+  // phase 3: T of the compact WY form (LAPACK larft, forward columnwise) and
+  // V^T r, reduced together
+  float dv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < 2 * OPL; ++i) {
+    const float3 vv = Vr[i];
     const float ri = rr[i];
-    d01 += vv.x * vv.y; d02 += vv.x * vv.z; d12 += vv.y * vv.z;
-    wr0 += vv.x * ri; wr1 += vv.y * ri; wr2 += vv.z * ri;
+    dv[0] += vv.x * vv.y; dv[1] += vv.x * vv.z; dv[2] += vv.y * vv.z;
+    dv[3] += vv.x * ri; dv[4] += vv.y * ri; dv[5] += vv.z * ri;
   }
-  d01 = tsum<TEAM>(d01, red4); d02 = tsum<TEAM>(d02, red4); d12 = tsum<TEAM>(d12, red4);
-  wr0 = tsum<TEAM>(wr0, red4); wr1 = tsum<TEAM>(wr1, red4); wr2 = tsum<TEAM>(wr2, red4);
+  team_sum_n<TEAM, 6>(dv, red, buf);
+  const float d01 = dv[0], d02 = dv[1], d12 = dv[2], wr0 = dv[3], wr1 = dv[4], wr2 = dv[5];
   const float T00 = tau[0], T11 = tau[1], T22 = tau[2];
   const float T01 = -tau[1] * T00 * d01;
   const float T02 = -tau[2] * (T00 * d02 + T01 * d12);
@@ -399,30 +441,51 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
   const float mr1 = T01 * wr0 + T11 * wr1;
   const float mr2 = T02 * wr0 + T12 * wr1 + T22 * wr2;
   float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
-  for (int i = lane; i < n; i += TEAM) {
-    const float4 vv = V[i];
-    const float val = rr[i] - (vv.x * mr0 + vv.y * mr1 + vv.z * mr2);
-    if (i < 3) lmd[LMD_QR + i] = val;
-    else d.rhoB[2 * (size_t)obs0 + (i - 3)] = val;
+#pragma unroll
+  for (int i = 0; i < 2 * OPL; ++i) {
+    const int gi = row_of(i);
+    if (gi < n) {
+      const float3 vv = Vr[i];
+      const float val = rr[i] - (vv.x * mr0 + vv.y * mr1 + vv.z * mr2);
+      if (gi < 3) lmd[LMD_QR + gi] = val;
+      else d.rhoB[2 * (size_t)obs0 + (gi - 3)] = val;
+      V[gi] = make_float4(vv.x, vv.y, vv.z, 0.f);
+    }
+    // R1: the diagonal is alpha_j (or the untouched entry when |x| = 0), the
+    // rest of row j comes from its owner
+    if (gi == 0) {
+      lmd[LMD_R + 0] = nrms[0] > 0.f ? alph[0] : Rrow[0][0];
+      lmd[LMD_R + 1] = Rrow[0][1];
+      lmd[LMD_R + 2] = Rrow[0][2];
+    } else if (gi == 1) {
+      lmd[LMD_R + 3] = nrms[1] > 0.f ? alph[1] : Rrow[1][1];
+      lmd[LMD_R + 4] = Rrow[1][2];
+    } else if (gi == 2) {
+      lmd[LMD_R + 5] = nrms[2] > 0.f ? alph[2] : Rrow[2][2];
+    }
   }
   if (lane == 0) {
-    lmd[LMD_R + 0] = Rm[0][0]; lmd[LMD_R + 1] = Rm[0][1]; lmd[LMD_R + 2] = Rm[0][2];
-    lmd[LMD_R + 3] = Rm[1][1]; lmd[LMD_R + 4] = Rm[1][2]; lmd[LMD_R + 5] = Rm[2][2];
     lmd[LMD_SL + 0] = sl0; lmd[LMD_SL + 1] = sl1; lmd[LMD_SL + 2] = sl2;
   }
+  team_sync<TEAM>();  // V and the pose Jacobians of every row, for phase 4
 
-  // phase 4: pose columns, Q^T J_p = J_p - V M with M = T^T (V^T J_p)
+  // phase 4: pose columns, Q^T J_p = J_p - V M with M = T^T (V^T J_p).  Lane
+  // g-groups are g = lane + TEAM jg; for a workgroup team the rows are the
+  // outer loop, so every output row (up to 18 KB) is written whole, in order.
   float* outT = d.poolT + d.slot_toff[slot];
   float* outB = d.poolB + d.slot_boff[slot];
-  for (int g = lane; g < G; g += TEAM) {
-    float M0[4], M1[4], M2[4], j0[4], j1[4];
-    int row0[4];
+  constexpr int NG = (((9 * KMAX + 3) / 4) + TEAM - 1) / TEAM;  // column groups per lane
+  float M0[NG][4], M1[NG][4], M2[NG][4], j0[NG][4], j1[NG][4];
+  int row0[NG][4];
+#pragma unroll
+  for (int jg = 0; jg < NG; ++jg) {
+    const int g = lane + TEAM * jg;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int c = 4 * g + q;
-      M0[q] = M1[q] = M2[q] = j0[q] = j1[q] = 0.f;
-      row0[q] = -4;
-      if (c < 9 * k) {
+      M0[jg][q] = M1[jg][q] = M2[jg][q] = j0[jg][q] = j1[jg][q] = 0.f;
+      row0[jg][q] = -4;
+      if (g < G && c < 9 * k) {
         const int o = (unsigned)c / 9u;
         const int m = c - 9 * o;
         const float a0 = Jpc[18 * o + m], a1 = Jpc[18 * o + 9 + m];
@@ -430,27 +493,30 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
         const float W0 = va.x * a0 + vb.x * a1;
         const float W1 = va.y * a0 + vb.y * a1;
         const float W2 = va.z * a0 + vb.z * a1;
-        M0[q] = T00 * W0;
-        M1[q] = T01 * W0 + T11 * W1;
-        M2[q] = T02 * W0 + T12 * W1 + T22 * W2;
-        j0[q] = a0;
-        j1[q] = a1;
-        row0[q] = 2 * o;
+        M0[jg][q] = T00 * W0;
+        M1[jg][q] = T01 * W0 + T11 * W1;
+        M2[jg][q] = T02 * W0 + T12 * W1 + T22 * W2;
+        j0[jg][q] = a0;
+        j1[jg][q] = a1;
+        row0[jg][q] = 2 * o;
       }
     }
-    for (int i = 0; i < n; ++i) {
-      const float4 vv = V[i];
-      float out[4];
+  }
+  for (int i = 0; i < n; ++i) {
+    const float4 vv = V[i];
+    float4* row = reinterpret_cast<float4*>(i < 3 ? outT + (size_t)i * W : outB + (size_t)(i - 3) * W);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float base = (i == row0[q]) ? j0[q] : ((i == row0[q] + 1) ? j1[q] : 0.f);
-        out[q] = base - (vv.x * M0[q] + vv.y * M1[q] + vv.z * M2[q]);
+    for (int jg = 0; jg < NG; ++jg) {
+      const int g = lane + TEAM * jg;
+      if (g < G) {
+        float out[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float base = (i == row0[jg][q]) ? j0[jg][q] : ((i == row0[jg][q] + 1) ? j1[jg][q] : 0.f);
+          out[q] = base - (vv.x * M0[jg][q] + vv.y * M1[jg][q] + vv.z * M2[jg][q]);
+        }
+        row[g] = make_float4(out[0], out[1], out[2], out[3]);
       }
-      const float4 o4 = make_float4(out[0], out[1], out[2], out[3]);
-      if (i < 3)
-        reinterpret_cast<float4*>(outT + (size_t)i * W)[g] = o4;
-      else
-        reinterpret_cast<float4*>(outB + (size_t)(i - 3) * W)[g] = o4;
     }
   }
 }
@@ -1537,28 +1603,30 @@ struct MargF {
   const Dev& d;
   const uint8_t* mask;
   float* lds;
-  float* red4;
+  float* red;
   template <int TEAM, int CLS>
   __device__ void run(int slot, int lane, int team) const {
-    marginalize_one<TEAM, class_kmax(CLS)>(d, slot, lane, lds + team * marg_stride(class_kmax(CLS)), red4, mask);
+    marginalize_one<TEAM, class_kmax(CLS)>(d, slot, lane, lds + team * marg_stride(class_kmax(CLS)), red, mask);
   }
 };
 
-constexpr int MARG_LDS_SMALL = marg_stride(class_kmax(4));  // >= (WG / team) * marg_stride of classes 0..3
-static_assert(MARG_LDS_SMALL >= 32 * marg_stride(3) && MARG_LDS_SMALL >= 16 * marg_stride(7) &&
-                  MARG_LDS_SMALL >= 8 * marg_stride(14) && MARG_LDS_SMALL >= 4 * marg_stride(28),
-              "LDS of the merged marginalization launch");
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// LDS of the merged launch: the largest (teams per workgroup) x (floats per team) of classes 0..4
+constexpr int MARG_LDS_SMALL =
+    cmax(cmax(cmax(32 * marg_stride(class_kmax(0)), 16 * marg_stride(class_kmax(1))),
+              cmax(8 * marg_stride(class_kmax(2)), 4 * marg_stride(class_kmax(3)))),
+         marg_stride(class_kmax(4)));
 
 __global__ __launch_bounds__(WG) void k_marginalize(Dev d, ClassGrid m, const uint8_t* mask) {
-  __shared__ float lds[MARG_LDS_SMALL];
-  __shared__ float red4[4];
-  class_dispatch(m, MargF{d, mask, lds, red4});
+  __shared__ __align__(16) float lds[MARG_LDS_SMALL];
+  __shared__ float red[MARG_RED];
+  class_dispatch(m, MargF{d, mask, lds, red});
 }
 
 __global__ __launch_bounds__(WG) void k_marginalize_huge(Dev d, int slot0, const uint8_t* mask) {
-  __shared__ float lds[marg_stride(class_kmax(5))];
-  __shared__ float red4[4];
-  marginalize_one<256, class_kmax(5)>(d, slot0 + blockIdx.x, threadIdx.x, lds, red4, mask);
+  __shared__ __align__(16) float lds[marg_stride(class_kmax(5))];
+  __shared__ float red[MARG_RED];
+  marginalize_one<256, class_kmax(5)>(d, slot0 + blockIdx.x, threadIdx.x, lds, red, mask);
 }
 
 struct DampF {
@@ -1798,7 +1866,8 @@ hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask
     if (e != hipSuccess) return e;
   }
   if (w[5].slots)
-    hipLaunchKernelGGL(k_marginalize_huge, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d, w[5].first_slot, mask);
+    hipLaunchKernelGGL(k_marginalize_huge, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d, w[5].first_slot,
+                       mask);
   LAUNCH_CHECK();
   if (n) hipLaunchKernelGGL(k_marginalize, dim3(n), dim3(WG), 0, L.stream, d, m, mask);
   LAUNCH_CHECK();
