@@ -36,6 +36,6 @@ from .normal_equations import (  # noqa: F401
     back_substitute,
     model_decrease,
 )
-from .solvers import dense_spd_solve, block_jacobi_blocks, pcg  # noqa: F401
+from .solvers import dense_spd_solve, block_jacobi_blocks, pcg, quadratic_model  # noqa: F401
 from .lm import LMOptions, LMResult, lm_solve, lm_attempt  # noqa: F401
 from .profile import cost_threshold, time_to_tolerance  # noqa: F401

@@ -35,6 +35,7 @@ class LMOptions:
     func_tol: float = 1e-6
     pcg_tol: float = 1e-6
     pcg_max_iters: int = 500
+    pcg_eta: float = 0.0  # > 0: also the Nash-Sofer forcing test of oracle.solvers.pcg
     solver: str = "pcg"  # "pcg" (block-Jacobi) or "dense" (Cholesky)
     lambda_min: float = 1e-16
     lambda_max: float = 1e32
@@ -70,7 +71,7 @@ def lm_attempt(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray, lin: Lin
         iters, rel, status, pres = 0, 0.0, "direct", None
     else:
         pres = pcg(lambda v: rs.H @ v, rs.b, block_jacobi_blocks(rs.H), opts.pcg_tol,
-                   opts.pcg_max_iters, trace=trace)
+                   opts.pcg_max_iters, trace=trace, eta=opts.pcg_eta)
         dxp, iters, rel, status = pres.x, pres.iters, pres.rel_res, pres.status
     dxl = back_substitute(rs, dxp)
     pred = model_decrease(lin, dxp, dxl)

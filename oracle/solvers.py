@@ -38,9 +38,20 @@ class PCGResult:
     trace_q: List[np.ndarray] = field(default_factory=list)
 
 
+def quadratic_model(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, x: np.ndarray) -> float:
+    """Q(x) = 1/2 x^T A x + b^T x, the quadratic whose minimizer solves A x = -b (Q(0) = 0)."""
+    return float(0.5 * (x @ matvec(x)) + b @ x)
+
+
 def pcg(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, blocks: Optional[np.ndarray],
-        tol: float = 1e-6, max_iters: int = 500, trace: bool = False) -> PCGResult:
-    """Solve A x = -b with block-Jacobi PCG from x_0 = 0 (blocks: (n, bs, bs) or None)."""
+        tol: float = 1e-6, max_iters: int = 500, trace: bool = False, eta: float = 0.0) -> PCGResult:
+    """Solve A x = -b with block-Jacobi PCG from x_0 = 0 (blocks: (n, bs, bs) or None).
+
+    Stops when |r_k| <= tol |r_0| (recurrence residual) or after max_iters.  With
+    eta > 0 it also stops at the first iteration i >= 1 with
+    i (Q_i - Q_{i-1}) / Q_i < eta, Q the quadratic model evaluated directly at the
+    iterates: the truncated-Newton test of Nash and Sofer (1990), which the paper
+    uses through its "same forcing sequence as Ceres" (Sec. 6.1)."""
     n = b.shape[0]
     if blocks is not None:
         bs = blocks.shape[1]
@@ -64,6 +75,7 @@ def pcg(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, blocks: Optio
     status = "max_iters"
     k = 0
     rn = r0
+    q_prev = 0.0  # Q(x_0) = 0
     while k < max_iters:
         q = matvec(p)
         pq = float(p @ q)
@@ -81,6 +93,12 @@ def pcg(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, blocks: Optio
         if rn <= tol * r0:
             status = "converged"
             break
+        if eta > 0.0:
+            q_cur = quadratic_model(matvec, b, x)
+            if q_cur < 0.0 and k * (q_cur - q_prev) / q_cur < eta:
+                status = "converged"
+                break
+            q_prev = q_cur
         z = prec(r)
         rz_new = float(r @ z)
         beta = rz_new / rz

@@ -145,3 +145,57 @@ def test_time_to_tolerance_definition():
     assert f_tau == pytest.approx(10.9)
     assert oracle.time_to_tolerance([1, 2, 3], [50, 10.95, 10.5], f_tau) == 3
     assert oracle.time_to_tolerance([1, 2], [50, 20], f_tau) == float("inf")
+
+
+def _spd_system(seed=3, n=63):
+    rng = np.random.default_rng(seed)
+    Qm, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    A = (Qm * np.logspace(0, 4, n)) @ Qm.T
+    A = 0.5 * (A + A.T)
+    b = rng.normal(size=n)
+    return A, b, oracle.block_jacobi_blocks(A)
+
+
+def test_forcing_test_stops_at_first_qualifying_iteration():
+    """Nash-Sofer truncation (Sec. 6.1 "forcing sequence"): the solve stops at the first
+    i >= 1 with i (Q_i - Q_{i-1}) / Q_i < eta; checked by brute force over truncated solves,
+    with Q evaluated from its definition here (independent of the solver's own evaluation)."""
+    A, b, blocks = _spd_system()
+    mv = lambda v: A @ v  # noqa: E731
+    eta = 0.1
+    res = oracle.pcg(mv, b, blocks, tol=1e-14, max_iters=200, eta=eta)
+    i_stop = res.iters
+    assert res.status == "converged" and 1 <= i_stop < 63
+    Q = [0.0]
+    for j in range(1, i_stop + 1):
+        xj = oracle.pcg(mv, b, blocks, tol=1e-14, max_iters=j).x
+        Q.append(0.5 * xj @ A @ xj + b @ xj)
+    Q = np.array(Q)
+    assert np.all(np.diff(Q) < 0)  # CG decreases the model monotonically
+    ratio = [j * (Q[j] - Q[j - 1]) / Q[j] for j in range(1, i_stop + 1)]
+    assert ratio[-1] < eta and all(r >= eta for r in ratio[:-1]), ratio
+    np.testing.assert_allclose(res.x, oracle.pcg(mv, b, blocks, tol=1e-14, max_iters=i_stop).x, rtol=1e-12)
+    # the model's minimizer is the solution of A x = -b, and every iterate lies above it
+    xs = np.linalg.solve(A, -b)
+    qs = 0.5 * xs @ A @ xs + b @ xs
+    assert oracle.quadratic_model(mv, b, xs) == pytest.approx(qs, rel=1e-12)
+    assert Q[-1] > qs
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        d = 1e-3 * rng.normal(size=b.shape)
+        assert oracle.quadratic_model(mv, b, xs + d) > qs
+
+
+def test_forcing_test_limits():
+    A, b, blocks = _spd_system(seed=4)
+    mv = lambda v: A @ v  # noqa: E731
+    plain = oracle.pcg(mv, b, blocks, tol=1e-8)
+    off = oracle.pcg(mv, b, blocks, tol=1e-8, eta=0.0)
+    assert off.iters == plain.iters and np.array_equal(off.x, plain.x)
+    # eta > 1: i (Q_1 - Q_0) / Q_1 = 1 at i = 1, so one iteration
+    assert oracle.pcg(mv, b, blocks, tol=1e-8, eta=1.5).iters == 1
+    # a tiny eta does not truncate while the model still decreases measurably (a residual
+    # tolerance of 1e-4 is reached long before the FP64 model stagnates; near 1e-8 it does
+    # stagnate, and then the test stops the solve, as intended)
+    loose = oracle.pcg(mv, b, blocks, tol=1e-4)
+    assert oracle.pcg(mv, b, blocks, tol=1e-4, eta=1e-30).iters == loose.iters
