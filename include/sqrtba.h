@@ -83,6 +83,13 @@ typedef struct {
   double pcg_rel_tol;    /* stop when |r_k| / |r_0| <= tol, 1e-6 */
   int32_t pcg_check_every; /* host checks convergence every n iterations (device flags stop work in between), 8 */
   int32_t use_graph;     /* capture chunks of PCG iterations in a HIP graph, 1 */
+  double pcg_forcing_eta; /* 0 (default): PCG stops on pcg_rel_tol or pcg_max_iters only.  > 0:
+                             it also stops at the first iteration i >= 1 with
+                             i (Q_i - Q_{i-1}) / Q_i < eta, Q the quadratic model of the
+                             reduced system at the iterates (tracked as Q_{i+1} = Q_i -
+                             alpha_i r_i.z_i / 2): the truncated-Newton test of Nash and Sofer
+                             (1990), read as the "same forcing sequence as Ceres" of Sec. 6.1,
+                             where eta = 0.1 */
 } sqrtba_options;
 
 typedef struct {
@@ -118,6 +125,12 @@ void sqrtba_default_options(sqrtba_options* opt);
 /* Create a context on the current HIP device.  hip_stream is a hipStream_t
  * (NULL: the default stream).  opt may be NULL for defaults. */
 int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_stream);
+
+/* Replace the options of an existing context (same validation as create:
+ * SQRTBA_E_INVALID on negative limits, lambda0 <= 0, pcg_check_every < 1 or a
+ * negative or non-finite pcg_forcing_eta; the context is then unchanged).
+ * Takes effect from the next call. */
+int32_t sqrtba_set_options(sqrtba_ctx* ctx, const sqrtba_options* opt);
 
 /* Free every resource of ctx (NULL is allowed). */
 void sqrtba_destroy(sqrtba_ctx* ctx);

@@ -459,8 +459,8 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
   for (int i = 0; i < 6; ++i) o_v[i] = f32(9 * NC);
   uint64_t o_minv = f32(81 * NC), o_ob = f32(54 * NO), o_dxl = f32(3 * NL);
   uint64_t o_cp = f64(NC), o_cp2 = f64(NC), o_cp3 = f64(NC), o_lp = f64(NL);
-  uint64_t o_s[8];
-  for (int i = 0; i < 8; ++i) o_s[i] = f64(P);
+  uint64_t o_s[10];
+  for (int i = 0; i < 10; ++i) o_s[i] = f64(P);
   uint64_t o_it = f32(P), o_dn = f32(P), o_ps = f32(P), o_act = L.take(P), o_flag = L.take(P);
   uint64_t o_cf = f32(4);
   uint64_t o_csnap = f32(16 * NC), o_psnap = f32(4 * NL);
@@ -488,6 +488,7 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
     t.lambda = at<double>(base, o_s[0]); t.rz_next = at<double>(base, o_s[1]); t.beta = at<double>(base, o_s[2]);
     t.rz = at<double>(base, o_s[3]); t.rr = at<double>(base, o_s[4]); t.rr0 = at<double>(base, o_s[5]);
     t.pcost = at<double>(base, o_s[6]); t.ppred = at<double>(base, o_s[7]);
+    t.qmod = at<double>(base, o_s[8]); t.dqmod = at<double>(base, o_s[9]);
     t.iters = at<int32_t>(base, o_it); t.done = at<int32_t>(base, o_dn); t.pstatus = at<int32_t>(base, o_ps);
     t.active = at<uint8_t>(base, o_act); t.flag = at<uint8_t>(base, o_flag);
     t.chol_fail = at<int32_t>(base, o_cf);
@@ -604,6 +605,7 @@ int upload(sqrtba_ctx* c) {
   Dev& d = c->d;
   layout(h, c->arena.base, &d);
   d.pcg_tol = (float)c->opt.pcg_rel_tol;
+  d.pcg_eta = (float)c->opt.pcg_forcing_eta;
   HIP_TRY(c, hipMemsetAsync(c->arena.base, 0, c->arena.bytes, c->stream));
   TRY(upload_state(c));
   TRY(upload_vec(c, d.obs_cam, h.ocam));
@@ -1187,6 +1189,12 @@ void sqrtba_default_options(sqrtba_options* o) {
   o->pcg_rel_tol = 1e-6;
   o->pcg_check_every = 8;
   o->use_graph = 1;
+  o->pcg_forcing_eta = 0.0;
+}
+
+static bool valid_options(const sqrtba_options& o) {
+  return o.pcg_max_iters >= 0 && o.max_lm_iters >= 0 && o.lambda0 > 0 && o.pcg_check_every >= 1 &&
+         std::isfinite(o.pcg_forcing_eta) && o.pcg_forcing_eta >= 0.0;
 }
 
 int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_stream) {
@@ -1196,7 +1204,7 @@ int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_str
   if (!c) return SQRTBA_E_OOM;
   sqrtba_default_options(&c->opt);
   if (opt) c->opt = *opt;
-  if (c->opt.pcg_max_iters < 0 || c->opt.max_lm_iters < 0 || !(c->opt.lambda0 > 0) || c->opt.pcg_check_every < 1) {
+  if (!valid_options(c->opt)) {
     delete c;
     return SQRTBA_E_INVALID;
   }
@@ -1214,6 +1222,18 @@ int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_str
     c->own_stream = true;
   }
   *out = c;
+  return SQRTBA_OK;
+}
+
+int32_t sqrtba_set_options(sqrtba_ctx* c, const sqrtba_options* opt) {
+  if (!c || !opt || !valid_options(*opt)) return SQRTBA_E_INVALID;
+  c->opt = *opt;
+  c->d.pcg_tol = (float)c->opt.pcg_rel_tol;
+  c->d.pcg_eta = (float)c->opt.pcg_forcing_eta;
+  if (c->graph) {  // captured launches hold the old Dev values
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
   return SQRTBA_OK;
 }
 

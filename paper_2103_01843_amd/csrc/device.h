@@ -94,6 +94,8 @@ struct Dev {
   int32_t* iters;
   int32_t* done;
   int32_t* pstatus;
+  double* qmod;      // PCG quadratic model at the current iterate (forcing test)
+  double* dqmod;     // its change in the last update
   double* pcost;
   double* ppred;
   uint8_t* active;
@@ -105,6 +107,7 @@ struct Dev {
   float* cam_snap;     // saved state (save/restore)
   float4* pts_snap;
   float pcg_tol;
+  float pcg_eta;     // > 0: Nash-Sofer truncation of PCG
 };
 
 struct WorkClass {

@@ -1187,6 +1187,8 @@ __global__ __launch_bounds__(WG) void k_pcg_init_scalars(Dev d) {
       d.rr[p] = rr;
       d.beta[p] = 0.0;
       d.iters[p] = 0;
+      d.qmod[p] = 0.0;  // Q(x_0) = 0
+      d.dqmod[p] = 0.0;
       if (!d.active[p]) { d.done[p] = 1; d.pstatus[p] = 4; }
       else if (!(rr > 0.0) || !(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {
         d.done[p] = 1;
@@ -1202,6 +1204,11 @@ __device__ __forceinline__ int pcg_test(const Dev& d, int p, double rz, double r
   if (!isfinite(rr) || !isfinite(rz)) return 2;
   const double tol = (double)d.pcg_tol;
   if (rr <= tol * tol * d.rr0[p]) return 1;
+  if (d.pcg_eta > 0.f) {  // Nash-Sofer: i (Q_i - Q_{i-1}) / Q_i < eta after update i >= 1
+    const int i = d.iters[p];
+    const double q = d.qmod[p];
+    if (i >= 1 && q < 0.0 && (double)i * d.dqmod[p] / q < (double)d.pcg_eta) return 1;
+  }
   return rz > 0.0 ? 0 : 2;
 }
 
@@ -1367,6 +1374,9 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
           if (ok) {
             d.iters[p] += 1;
             d.rz[p] = d.rz_next[p];
+            const double dq = -0.5 * (d.rz_next[p] / pq) * d.rz_next[p];  // -alpha r.z / 2
+            d.qmod[p] += dq;
+            d.dqmod[p] = dq;
           } else {
             d.done[p] = 1;
             d.pstatus[p] = 2;  // breakdown: x kept

@@ -37,7 +37,7 @@ class Options(C.Structure):
         ("lambda0", C.c_double), ("lambda_min", C.c_double), ("lambda_max", C.c_double),
         ("accept_ratio", C.c_double), ("max_lm_iters", C.c_int32), ("func_tol", C.c_double),
         ("pcg_max_iters", C.c_int32), ("pcg_rel_tol", C.c_double), ("pcg_check_every", C.c_int32),
-        ("use_graph", C.c_int32),
+        ("use_graph", C.c_int32), ("pcg_forcing_eta", C.c_double),
     ]
 
 
@@ -88,6 +88,7 @@ _SIGS = {
     "sqrtba_version": (I32, []),
     "sqrtba_default_options": (None, [C.POINTER(Options)]),
     "sqrtba_create": (I32, [C.POINTER(P), C.POINTER(Options), P]),
+    "sqrtba_set_options": (I32, [P, C.POINTER(Options)]),
     "sqrtba_destroy": (None, [P]),
     "sqrtba_last_error": (C.c_char_p, [P]),
     "sqrtba_set_problems": (I32, [P, I32, PI64, PI64]),
@@ -214,6 +215,17 @@ class Context:
         self.n_cams = 0
         self.n_points = 0
         self._workspace = None
+
+    def set_options(self, **kw):
+        """Change options of this context (validated by the library), e.g. pcg_forcing_eta=0.1."""
+        opt = Options()
+        C.memmove(C.byref(opt), C.byref(self.options), C.sizeof(Options))
+        for k, v in kw.items():
+            if k not in dict(Options._fields_):
+                raise TypeError(f"unknown option {k}")
+            setattr(opt, k, v)
+        self._check(lib().sqrtba_set_options(self._h, C.byref(opt)))
+        self.options = opt
 
     # -- lifetime
     def close(self):

@@ -167,6 +167,35 @@ def test_pcg_and_back_substitution(case):
     assert abs(pred - pred_o) <= 1e-4 * abs(pred_o), (pred, pred_o)
 
 
+@pytest.mark.parametrize("lam", [1e-4, 1e-2])
+def test_pcg_forcing_truncation(case, lam):
+    """With the Nash-Sofer forcing test (eta = 0.1, Sec. 6.1 "forcing sequence"), the GPU
+    stops within one iteration of the oracle (the GPU tracks Q by its recurrence in FP32-fed
+    FP64 sums, the oracle evaluates it from its definition), and its iterate equals the
+    oracle's after the same number of iterations."""
+    p, bk, st, lin, ctx = case
+    ctx.set_options(pcg_forcing_eta=0.1)
+    try:
+        ctx.linearize()
+        ctx.marginalize()
+        ctx.damp(lam)
+        its, rel, status = ctx.solve()
+    finally:
+        ctx.set_options(pcg_forcing_eta=0.0)
+    rs = oracle.reduced_camera_system(lin, lam)
+    blocks = oracle.block_jacobi_blocks(rs.H)
+    mv = lambda v: rs.H @ v  # noqa: E731
+    ref = oracle.pcg(mv, rs.b, blocks, tol=1e-6, eta=0.1)
+    plain = oracle.pcg(mv, rs.b, blocks, tol=1e-6)
+    assert status[0] == 0
+    assert abs(int(its[0]) - ref.iters) <= 1, (its[0], ref.iters)
+    assert ref.iters < plain.iters  # the truncation does cut the solve short here
+    same = oracle.pcg(mv, rs.b, blocks, tol=0.0, max_iters=int(its[0]))
+    dxp, _ = ctx.debug_solution()
+    e = np.linalg.norm(dxp - same.x) / np.linalg.norm(same.x)
+    assert e <= 1e-3, e
+
+
 def test_update_cost_matches_oracle(case):
     p, bk, st, lin, ctx = case
     lam = 1e-3
