@@ -175,6 +175,38 @@ def learned_run(ctx, n_problems: int, lm_iters: int):
             "train_loss_first_last": [losses[0], losses[-1]], **stats}
 
 
+def other_blocks_run(p, args, blocks: int):
+    """Timed solves (same steps and warm-up) and the product timing with the given
+    landmark-block form; returns its reports, histories and figures."""
+    import torch
+    from paper_2103_01843_amd import Context
+
+    ctx = Context(stream=torch.cuda.current_stream(), max_lm_iters=args.lm_iters, landmark_blocks=blocks)
+    ctx.load(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)
+    ctx.bind_torch_workspace()
+    ctx.save_state()
+    ws = ctx.workspace_bytes()
+    for _ in range(args.warmup):
+        ctx.restore_state()
+        ctx.lm_solve()
+    runs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.restore_state()
+        reps = ctx.lm_solve()
+        runs.append((reps, [ctx.history(i) for i in range(p.n_problems)]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mv_ms, mv_bytes = ctx.time_product(reps=50)
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    log(f"{'implicit' if blocks else 'explicit'} blocks: {1e3 * wall / args.steps:.1f} ms per solve, "
+        f"product {1e3 * mv_ms:.1f} us, workspace {ws / 1e9:.2f} GB")
+    return {"runs": runs, "wall": wall, "mv_ms": mv_ms, "mv_bytes": mv_bytes, "workspace_bytes": ws}
+
+
 def calibrate_copy():
     import torch
     n = 1 << 28  # 1 GiB of float32
@@ -197,6 +229,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default product launch shapes")
+    ap.add_argument("--blocks", choices=["explicit", "implicit"], default="explicit",
+                    help="landmark blocks of the timed solves: explicit (the paper's stored blocks, default) or "
+                         "implicit (J_p and Q1 per observation)")
+    ap.add_argument("--no-implicit", action="store_true",
+                    help="skip the extra measurement of the implicit landmark blocks")
     ap.add_argument("--no-forcing", action="store_true",
                     help="skip the solve with the forcing-sequence PCG truncation (eta = 0.1)")
     ap.add_argument("--tuning", default=None, metavar="EDGE,ROWS,SIDE,SEP,BATCH,PERSIST",
@@ -227,7 +264,8 @@ def main():
     log(f"workload: {stats}")
     torch.cuda.synchronize()
     t_up = time.perf_counter()
-    ctx = Context(stream=torch.cuda.current_stream(), max_lm_iters=args.lm_iters)
+    blocks = 1 if args.blocks == "implicit" else 0
+    ctx = Context(stream=torch.cuda.current_stream(), max_lm_iters=args.lm_iters, landmark_blocks=blocks)
     ctx.load(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)
     ctx.bind_torch_workspace()
     ctx.save_state()  # first device use: host bookkeeping, then upload over PCIe
@@ -294,6 +332,14 @@ def main():
         except Exception as e:  # reported, never required
             log(f"learned comparison failed: {e!r}")
     ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+
+    # the other landmark-block form on the same workload and start (implicit
+    # blocks need no O(k^2) storage): timed solves and its product
+    other = None
+    if not args.no_implicit and args.blocks == "explicit":
+        other = other_blocks_run(p, args, 1)
 
     # time to 1% cost per problem (appendix A.2), f* over the runs (and the oracle where stored)
     gold = None
@@ -308,12 +354,28 @@ def main():
             finals.append(learned["reports"][i].final_cost)
         if forcing:
             finals.append(forcing["reports"][i].final_cost)
+        if other:
+            finals += [reps[i].final_cost for reps, _ in other["runs"]]
         fstar = min(finals + ([gold["final_cost"]] if gold and p.n_problems == 1 else []))
         f_tau = fstar + 0.01 * (f0 - fstar)
         f_taus.append((f0, fstar, f_tau))
         ttt_all.append([time_to_tol(h[i], f_tau) for _, h in runs])
     # a batch reaches the threshold when its last problem does
     ttt = [max(t[s] for t in ttt_all) for s in range(len(runs))]
+    implicit_out = None
+    if other:
+        ttt_o = [max(time_to_tol(h[i], f_taus[i][2]) for i in range(p.n_problems)) for _, h in other["runs"]]
+        ach = other["mv_bytes"] / (other["mv_ms"] * 1e-3) / 1e9 if other["mv_ms"] > 0 else None
+        implicit_out = {
+            "landmark_blocks": "implicit",
+            "time_to_1pct_cost_s": statistics.median(ttt_o),
+            "ms_per_step": 1e3 * other["wall"] / args.steps,
+            "final_costs": [sum(r.final_cost for r in reps) for reps, _ in other["runs"]],
+            "pcg_iters": sum(r.total_pcg_iters for r in other["runs"][-1][0]),
+            "workspace_bytes": other["workspace_bytes"],
+            "product": {"avg_launch_ms": other["mv_ms"], "algorithmic_bytes_per_launch": other["mv_bytes"],
+                        "achieved_GBps": ach, "frac_of_hbm_peak": ach / HBM_PEAK_GBPS if ach else None},
+        }
     forcing_out = None
     if forcing:
         forcing_out = {
@@ -344,7 +406,7 @@ def main():
     achieved = mv_bytes / (mv_ms * 1e-3) / 1e9 if mv_ms > 0 else None
     traffic, traffic_note = None, None
     tfile = TRAFFIC.get(cfg)
-    if tfile and os.path.exists(tfile):
+    if tfile and os.path.exists(tfile) and args.blocks == "explicit":
         with open(tfile) as f:
             tr = json.load(f)
         if tr.get("kernels_sha") == kernels_hash():  # counters of the current kernels only
@@ -353,8 +415,9 @@ def main():
                             f"launch shapes {tr['shape']}")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": traffic,
-                "kernel": "the PCG product over all landmark blocks (k_matvec, plus k_matvec_large / "
-                          "k_matvec_rows + k_matvec_combine where those size classes exist)",
+                "kernel": ("the PCG product over all landmark blocks (k_matvec, plus k_matvec_large / "
+                           "k_matvec_rows + k_matvec_combine where those size classes exist)")
+                          if args.blocks == "explicit" else "the PCG product over implicit blocks (k_matvec_implicit)",
                 "avg_launch_ms": mv_ms, "algorithmic_bytes_per_launch": mv_bytes, "launches_timed": 50,
                 "timing": "HIP events around 50 back-to-back products on the resident blocks, context stream",
                 "traffic_source": traffic_note,
@@ -388,7 +451,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[cfg], "n_problems": p.n_problems,
+        "config": {"workload": WORKLOADS[cfg], "landmark_blocks": args.blocks, "n_problems": p.n_problems,
                    "n_cams": stats["n_cams"], "n_points": stats["n_points"], "n_obs": stats["n_obs"],
                    "bhat_bytes": stats["bhat_bytes"], "lm_iters": args.lm_iters, "pcg_tol": 1e-6,
                    "pcg_max_iters": 500},
@@ -405,6 +468,7 @@ def main():
         "roofline": roofline,
         "tuning": tuning,
         "forcing_sequence": forcing_out,
+        "implicit_blocks": implicit_out,
         "learned_vs_block_jacobi": learned_out,
         "cpu_baseline": cpu,
     }

@@ -90,6 +90,15 @@ typedef struct {
                              alpha_i r_i.z_i / 2): the truncated-Newton test of Nash and Sofer
                              (1990), read as the "same forcing sequence as Ceres" of Sec. 6.1,
                              where eta = 0.1 */
+  int32_t landmark_blocks; /* 0 (default): explicit landmark blocks, the 2k x 9k rows
+                              [Q2^T J_p; damping rows] stored per landmark (Sec. 5.1).
+                              1: implicit blocks: only the pose Jacobian rows and the thin
+                              factor Q1 (24 floats per observation) are stored; the product
+                              and everything else use B^T B = J_p^T (I - Q1 P Q1^T) J_p with
+                              P = R1 (R1^T R1 + lambda I)^-1 R1^T, the same reduced system
+                              (eq. red_H) at O(k) memory and traffic per landmark.  Chosen
+                              before the workspace is sized; sqrtba_set_options refuses to
+                              change it after upload (SQRTBA_E_STATE). */
 } sqrtba_options;
 
 typedef struct {
@@ -251,7 +260,9 @@ int32_t sqrtba_debug_precond(sqrtba_ctx* ctx, float* minv);
  * nullspace rows, then the 3 damping rows written by damp); pose columns are
  * unscaled, landmark columns are scaled.  If factors != NULL it receives 24
  * floats: R1 upper (6, row-major), Q1^T r (3), damped R upper (6), damped
- * Q1^T r (3), landmark column scales (3), lambda of the last damp (1), 0, 0. */
+ * Q1^T r (3), landmark column scales (3), lambda of the last damp (1), 0, 0.
+ * With implicit landmark blocks there are no block rows: out must be NULL
+ * (else SQRTBA_E_UNSUPPORTED); factors as above. */
 int32_t sqrtba_debug_block(sqrtba_ctx* ctx, int64_t pt, int32_t* k, float* out, float* factors);
 
 /* Solution of the last solve/back-substitution: scaled pose increment

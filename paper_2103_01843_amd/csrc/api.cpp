@@ -440,7 +440,7 @@ T* at(void* base, uint64_t off) {
 }
 
 // Offsets of every device array; when base is null only the size is computed.
-uint64_t layout(const HostData& h, void* base, Dev* d) {
+uint64_t layout(const HostData& h, bool implicit, void* base, Dev* d) {
   Layout L;
   const uint64_t NC = h.NC, NL = h.NL, NO = h.NO, NS = h.NS, P = h.P;
   Dev t{};
@@ -453,7 +453,9 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
   uint64_t o_sz = f32(NS), o_czp = f32(NO);
   uint64_t o_lms = f32(NL);
   uint64_t o_hj = f32(h.hjob.size()), o_hzo = f64(h.hz_off.size()), o_zp = f32(h.hz_floats);
-  uint64_t o_pB = f32(h.poolB), o_pT = f32(h.poolT), o_lmd = f32(NS * LMD_STRIDE), o_rho = f32(2 * NO);
+  const uint64_t nB = implicit ? 0 : h.poolB, nT = implicit ? 0 : h.poolT, nrho = implicit ? 0 : 2 * NO;
+  uint64_t o_pB = f32(nB), o_pT = f32(nT), o_lmd = f32(NS * LMD_STRIDE), o_rho = f32(nrho);
+  uint64_t o_rec = f32(implicit ? (uint64_t)REC_STRIDE * NO : 0);
   uint64_t o_sc = f32(9 * NC);
   uint64_t o_v[6];
   for (int i = 0; i < 6; ++i) o_v[i] = f32(9 * NC);
@@ -479,7 +481,10 @@ uint64_t layout(const HostData& h, void* base, Dev* d) {
     t.lm_slot = at<int32_t>(base, o_lms);
     t.hjob = at<int2>(base, o_hj); t.hz_off = at<int64_t>(base, o_hzo); t.zpart = at<float>(base, o_zp);
     t.poolB = at<float>(base, o_pB); t.poolT = at<float>(base, o_pT); t.lmd = at<float>(base, o_lmd);
-    t.rhoB = at<float>(base, o_rho); t.s_cam = at<float>(base, o_sc);
+    t.rhoB = implicit ? nullptr : at<float>(base, o_rho); t.s_cam = at<float>(base, o_sc);
+    if (implicit) { t.poolB = nullptr; t.poolT = nullptr; }
+    t.obsrec = implicit ? at<float>(base, o_rec) : nullptr;
+    t.implicit = implicit ? 1 : 0;
     t.vx = at<float>(base, o_v[0]); t.vr = at<float>(base, o_v[1]); t.vz = at<float>(base, o_v[2]);
     t.vp = at<float>(base, o_v[3]); t.vq = at<float>(base, o_v[4]); t.vb = at<float>(base, o_v[5]);
     t.minv = at<float>(base, o_minv); t.obsbuf = at<float>(base, o_ob); t.dxl = at<float>(base, o_dxl);
@@ -603,7 +608,7 @@ int upload_state(sqrtba_ctx* c) {
 int upload(sqrtba_ctx* c) {
   const HostData& h = c->h;
   Dev& d = c->d;
-  layout(h, c->arena.base, &d);
+  layout(h, c->opt.landmark_blocks == 1, c->arena.base, &d);
   d.pcg_tol = (float)c->opt.pcg_rel_tol;
   d.pcg_eta = (float)c->opt.pcg_forcing_eta;
   HIP_TRY(c, hipMemsetAsync(c->arena.base, 0, c->arena.bytes, c->stream));
@@ -670,11 +675,18 @@ int upload(sqrtba_ctx* c) {
   for (int64_t sl = 0; sl < h.NS; ++sl) {
     const double k = h.slot_k[sl];
     const int p = h.slot_prob[sl];
-    // matvec: read the 2k x 9k B rows, write 9k per-observation outputs
-    c->mv_bytes[p] += 4.0 * (18.0 * k * k + 9.0 * k);
-    // QR: write 2k rotated rows (9k pose columns + residual) and the 12-float
-    // landmark record; read camera index and pixel per observation, the landmark
-    c->qr_bytes[p] += 4.0 * (2.0 * k * (9.0 * k + 1.0) + 12.0) + 12.0 * k + 16.0;
+    if (c->opt.landmark_blocks == 1) {
+      // implicit: read the 24 Jacobian and Q1 floats per observation and the 6 of P,
+      // write 9k per-observation outputs; the QR writes the 28-float records
+      c->mv_bytes[p] += 4.0 * (24.0 * k + 6.0 + 9.0 * k);
+      c->qr_bytes[p] += 4.0 * (28.0 * k + 12.0) + 12.0 * k + 16.0;
+    } else {
+      // matvec: read the 2k x 9k B rows, write 9k per-observation outputs
+      c->mv_bytes[p] += 4.0 * (18.0 * k * k + 9.0 * k);
+      // QR: write 2k rotated rows (9k pose columns + residual) and the 12-float
+      // landmark record; read camera index and pixel per observation, the landmark
+      c->qr_bytes[p] += 4.0 * (2.0 * k * (9.0 * k + 1.0) + 12.0) + 12.0 * k + 16.0;
+    }
     c->blocks[p] += 1;
   }
   c->snapshot = false;
@@ -692,7 +704,7 @@ void release_arena(sqrtba_ctx* c) {
 int ensure_uploaded(sqrtba_ctx* c) {
   if (c->uploaded) return SQRTBA_OK;
   TRY(check_ready(c));
-  const uint64_t bytes = layout(c->h, nullptr, nullptr);
+  const uint64_t bytes = layout(c->h, c->opt.landmark_blocks == 1, nullptr, nullptr);
   release_arena(c);
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
@@ -1190,11 +1202,13 @@ void sqrtba_default_options(sqrtba_options* o) {
   o->pcg_check_every = 8;
   o->use_graph = 1;
   o->pcg_forcing_eta = 0.0;
+  o->landmark_blocks = 0;
 }
 
 static bool valid_options(const sqrtba_options& o) {
   return o.pcg_max_iters >= 0 && o.max_lm_iters >= 0 && o.lambda0 > 0 && o.pcg_check_every >= 1 &&
-         std::isfinite(o.pcg_forcing_eta) && o.pcg_forcing_eta >= 0.0;
+         std::isfinite(o.pcg_forcing_eta) && o.pcg_forcing_eta >= 0.0 &&
+         (o.landmark_blocks == 0 || o.landmark_blocks == 1);
 }
 
 int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_stream) {
@@ -1227,6 +1241,8 @@ int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_str
 
 int32_t sqrtba_set_options(sqrtba_ctx* c, const sqrtba_options* opt) {
   if (!c || !opt || !valid_options(*opt)) return SQRTBA_E_INVALID;
+  if (opt->landmark_blocks != c->opt.landmark_blocks && (c->uploaded || c->arena.base))
+    return fail(c, SQRTBA_E_STATE, "landmark_blocks is chosen before the workspace is bound");
   c->opt = *opt;
   c->d.pcg_tol = (float)c->opt.pcg_rel_tol;
   c->d.pcg_eta = (float)c->opt.pcg_forcing_eta;
@@ -1328,14 +1344,14 @@ int32_t sqrtba_set_observations(sqrtba_ctx* c, int64_t n, const int32_t* cam, co
 int32_t sqrtba_workspace_bytes(const sqrtba_ctx* c, uint64_t* bytes) {
   if (!c || !bytes) return SQRTBA_E_INVALID;
   if (c->h.NC < 0 || c->h.NL < 0 || !c->h.obs_set) return SQRTBA_E_STATE;
-  *bytes = layout(c->h, nullptr, nullptr);
+  *bytes = layout(c->h, c->opt.landmark_blocks == 1, nullptr, nullptr);
   return SQRTBA_OK;
 }
 
 int32_t sqrtba_bind_workspace(sqrtba_ctx* c, void* ptr, uint64_t bytes) {
   if (!c) return SQRTBA_E_INVALID;
   TRY(check_ready(c));
-  const uint64_t need = layout(c->h, nullptr, nullptr);
+  const uint64_t need = layout(c->h, c->opt.landmark_blocks == 1, nullptr, nullptr);
   if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255)) return fail(c, SQRTBA_E_INVALID, "workspace must be a 256-byte aligned device pointer");
   if (bytes < need) return fail(c, SQRTBA_E_OOM, "workspace has %llu bytes, needs %llu", (unsigned long long)bytes, (unsigned long long)need);
   release_arena(c);
@@ -1512,6 +1528,14 @@ int32_t sqrtba_debug_block(sqrtba_ctx* c, int64_t pt, int32_t* k_out, float* out
   const int64_t k = h.slot_k[s], W = width_of_h(k), C = 9 * k + 4;
   *k_out = (int32_t)k;
   if (!out && !factors) return SQRTBA_OK;
+  if (c->opt.landmark_blocks == 1) {
+    if (out) return fail(c, SQRTBA_E_UNSUPPORTED, "implicit landmark blocks store no block rows");
+    std::vector<float> lmd(LMD_STRIDE);
+    HIP_TRY(c, hipMemcpyAsync(lmd.data(), c->d.lmd + LMD_STRIDE * s, 4 * LMD_STRIDE, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::memcpy(factors, lmd.data(), 4 * 24);
+    return SQRTBA_OK;
+  }
   std::vector<float> T(3 * W), B(2 * k * W), rho(2 * k), lmd(LMD_STRIDE);
   HIP_TRY(c, hipMemcpyAsync(T.data(), c->d.poolT + h.slot_toff[s], 4 * T.size(), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(B.data(), c->d.poolB + h.slot_boff[s], 4 * B.size(), hipMemcpyDeviceToHost, c->stream));
@@ -1532,7 +1556,7 @@ int32_t sqrtba_debug_block(sqrtba_ctx* c, int64_t pt, int32_t* k_out, float* out
       out[(3 + i) * C + 9 * k + 3] = rho[i];
     }
   }
-  if (factors) std::memcpy(factors, lmd.data(), 4 * LMD_STRIDE);
+  if (factors) std::memcpy(factors, lmd.data(), 4 * 24);
   return SQRTBA_OK;
 }
 

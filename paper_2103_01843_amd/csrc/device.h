@@ -24,8 +24,18 @@ __host__ __device__ constexpr int class_of_k(int k) {
 }
 
 // Small per-landmark record (floats): R1 upper (6), Q1^T r (3), damped R upper (6),
-// damped Q1^T r (3), landmark column scales (3), lambda used (1), pad (2).
-enum { LMD_R = 0, LMD_QR = 6, LMD_RH = 9, LMD_QRH = 15, LMD_SL = 18, LMD_LAM = 21, LMD_STRIDE = 24 };
+// damped Q1^T r (3), landmark column scales (3), lambda used (1), and for implicit
+// landmark blocks the projection matrix P = R1 (R1^T R1 + lambda I)^-1 R1^T (6,
+// upper triangle row by row) and the damping rows' residuals (3), pad (1).
+enum {
+  LMD_R = 0, LMD_QR = 6, LMD_RH = 9, LMD_QRH = 15, LMD_SL = 18, LMD_LAM = 21, LMD_P = 22, LMD_DR = 28,
+  LMD_STRIDE = 32
+};
+
+// Implicit landmark blocks: per sorted observation 28 floats (7 float4) holding
+// the unscaled pose Jacobian rows (2 x 9), the observation's two rows of the
+// thin QR factor Q1 (2 x 3), the residual (2) and 2 pad.
+enum { REC_JP = 0, REC_Q1 = 18, REC_R = 24, REC_STRIDE = 28 };
 
 // Device view of the whole context.  All pointers are device pointers.
 struct Dev {
@@ -77,6 +87,8 @@ struct Dev {
   float* vq;
   float* vb;      // right-hand side b~
   float* minv;    // NC * 81 inverse preconditioner blocks
+  float* obsrec;  // implicit blocks: NO * REC_STRIDE per-observation records (else null)
+  int32_t implicit;  // 1: implicit landmark blocks (no poolB / poolT / rhoB)
   float* obsbuf;  // NO * 54 floats: per-observation preconditioner terms; the product outputs
                   // reuse it in per-landmark aligned regions (slot_zoff)
   float* dxl;     // NL * 3, unscaled landmark increment

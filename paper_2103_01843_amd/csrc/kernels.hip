@@ -35,14 +35,14 @@ __device__ __forceinline__ float dppf(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// All-reduce over aligned groups of TEAM lanes (8, 16, 32 or 64).  Every lane of
-// the group receives the bitwise-identical sum (each step adds a commutative
+// All-reduce over aligned groups of TEAM lanes (4, 8, 16, 32 or 64).  Every lane
+// of the group receives the bitwise-identical sum (each step adds a commutative
 // pair).  All lanes of a group must be active together.
 template <int TEAM>
 __device__ __forceinline__ float team_sum(float v) {
   v += dppf<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dppf<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dppf<0x141>(v);  // row_half_mirror: pairs quads of a half row
+  if constexpr (TEAM >= 8) v += dppf<0x141>(v);  // row_half_mirror: pairs quads of a half row
   if constexpr (TEAM >= 16) v += dppf<0x140>(v);  // row_mirror: pairs half rows
   if constexpr (TEAM >= 32) v += __shfl_xor(v, 16);  // pairs rows of 16 within 32 lanes
   if constexpr (TEAM >= 64) v += __shfl_xor(v, 32);
@@ -302,7 +302,7 @@ __host__ __device__ constexpr int marg_stride(int kmax) { return (26 * kmax + 3)
 // LDS floats of the reductions of a workgroup team (two buffers of 4 x 8).
 constexpr int MARG_RED = 64;
 
-template <int TEAM, int KMAX>
+template <int TEAM, int KMAX, bool IMPLICIT>
 __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane, float* lds, float* red,
                                                 const uint8_t* mask) {
   constexpr int OPL = (KMAX + TEAM - 1) / TEAM;  // observations per lane
@@ -448,7 +448,7 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
       const float3 vv = Vr[i];
       const float val = rr[i] - (vv.x * mr0 + vv.y * mr1 + vv.z * mr2);
       if (gi < 3) lmd[LMD_QR + gi] = val;
-      else d.rhoB[2 * (size_t)obs0 + (gi - 3)] = val;
+      else if (!IMPLICIT) d.rhoB[2 * (size_t)obs0 + (gi - 3)] = val;
       V[gi] = make_float4(vv.x, vv.y, vv.z, 0.f);
     }
     // R1: the diagonal is alpha_j (or the untouched entry when |x| = 0), the
@@ -468,6 +468,47 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
     lmd[LMD_SL + 0] = sl0; lmd[LMD_SL + 1] = sl1; lmd[LMD_SL + 2] = sl2;
   }
   team_sync<TEAM>();  // V and the pose Jacobians of every row, for phase 4
+
+  if constexpr (IMPLICIT) {
+    // phase 4 (implicit blocks): per observation its record: the pose Jacobian
+    // rows, its two rows of the thin factor Q1 = Q[:, 0:3] = E - V T V3^T (V3 the
+    // top three rows of V, lower triangular) and its residual
+    float K[3][3];  // K = T V3^T
+    {
+      const float4 v0 = V[0], v1 = V[1], v2 = V[2];
+      const float v3[3][3] = {{v0.x, v0.y, v0.z}, {v1.x, v1.y, v1.z}, {v2.x, v2.y, v2.z}};
+      const float T[3][3] = {{T00, T01, T02}, {0.f, T11, T12}, {0.f, 0.f, T22}};
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) K[m][j] = T[m][0] * v3[j][0] + T[m][1] * v3[j][1] + T[m][2] * v3[j][2];
+    }
+#pragma unroll
+    for (int m = 0; m < OPL; ++m) {
+      const int o = lane + TEAM * m;
+      if (o < k) {
+        float q[2][3];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const float3 vv = Vr[2 * m + h];
+          const int gi = 2 * o + h;
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            q[h][j] = (gi == j ? 1.f : 0.f) - (vv.x * K[0][j] + vv.y * K[1][j] + vv.z * K[2][j]);
+        }
+        const float* J = Jpc + 18 * o;
+        float4* rec = reinterpret_cast<float4*>(d.obsrec + (size_t)(obs0 + o) * REC_STRIDE);
+        rec[0] = make_float4(J[0], J[1], J[2], J[3]);
+        rec[1] = make_float4(J[4], J[5], J[6], J[7]);
+        rec[2] = make_float4(J[8], J[9], J[10], J[11]);
+        rec[3] = make_float4(J[12], J[13], J[14], J[15]);
+        rec[4] = make_float4(J[16], J[17], q[0][0], q[0][1]);
+        rec[5] = make_float4(q[0][2], q[1][0], q[1][1], q[1][2]);
+        rec[6] = make_float4(rr[2 * m], rr[2 * m + 1], 0.f, 0.f);
+      }
+    }
+    return;
+  }
 
   // phase 4: pose columns, Q^T J_p = J_p - V M with M = T^T (V^T J_p).  Lane
   // g-groups are g = lane + TEAM jg; for a workgroup team the rows are the
@@ -1609,6 +1650,7 @@ __device__ __forceinline__ void backsub_large(const Dev& d, int slot, double* pr
 // Classes 0..4 of each per-landmark stage run as one launch (class_dispatch);
 // class 5 has its own launch.
 
+template <bool IMPLICIT>
 struct MargF {
   const Dev& d;
   const uint8_t* mask;
@@ -1616,7 +1658,8 @@ struct MargF {
   float* red;
   template <int TEAM, int CLS>
   __device__ void run(int slot, int lane, int team) const {
-    marginalize_one<TEAM, class_kmax(CLS)>(d, slot, lane, lds + team * marg_stride(class_kmax(CLS)), red, mask);
+    marginalize_one<TEAM, class_kmax(CLS), IMPLICIT>(d, slot, lane, lds + team * marg_stride(class_kmax(CLS)), red,
+                                                     mask);
   }
 };
 
@@ -1627,16 +1670,18 @@ constexpr int MARG_LDS_SMALL =
               cmax(8 * marg_stride(class_kmax(2)), 4 * marg_stride(class_kmax(3)))),
          marg_stride(class_kmax(4)));
 
+template <bool IMPLICIT>
 __global__ __launch_bounds__(WG) void k_marginalize(Dev d, ClassGrid m, const uint8_t* mask) {
   __shared__ __align__(16) float lds[MARG_LDS_SMALL];
   __shared__ float red[MARG_RED];
-  class_dispatch(m, MargF{d, mask, lds, red});
+  class_dispatch(m, MargF<IMPLICIT>{d, mask, lds, red});
 }
 
+template <bool IMPLICIT>
 __global__ __launch_bounds__(WG) void k_marginalize_huge(Dev d, int slot0, const uint8_t* mask) {
   __shared__ __align__(16) float lds[marg_stride(class_kmax(5))];
   __shared__ float red[MARG_RED];
-  marginalize_one<256, class_kmax(5)>(d, slot0 + blockIdx.x, threadIdx.x, lds, red, mask);
+  marginalize_one<256, class_kmax(5), IMPLICIT>(d, slot0 + blockIdx.x, threadIdx.x, lds, red, mask);
 }
 
 struct DampF {
@@ -1816,6 +1861,300 @@ __global__ __launch_bounds__(64) void k_cam_gather_product(Dev d, const float* v
   }
 }
 
+// ----------------------------------------------- implicit landmark blocks
+//
+// With implicit blocks the rows of B are never formed.  In scaled pose
+// coordinates B^T B = J_p^T (I - Q1 P Q1^T) J_p and B^T rho = J_p^T (I - Q1 P
+// Q1^T) r, with P = R1 (R1^T R1 + lambda I)^-1 R1^T = M M^T, M = R1 Rh^-1 (Rh the
+// damped R of the Givens damping, Rh^T Rh = R1^T R1 + lambda I): the landmark
+// term of eq. red_H taken from the QR of J_l, never from its normal equations.
+// Each observation carries its record (pose Jacobian rows, its two rows of Q1,
+// residual), so every stage below is O(k) per landmark.
+
+// Per landmark (one thread): the damped factors (as the explicit damping), the
+// damping rows' residuals and P.
+__global__ __launch_bounds__(WG) void k_damp_implicit(Dev d, const uint8_t* mask) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= d.NS) return;
+  const int prob = d.slot_prob[slot];
+  if (mask && !mask[prob]) return;
+  float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const float lam = (float)d.lambda[prob];
+  Givens6 Gv;
+  float Rh[3][3], qrh[3], dr[3];
+  damping_rotations(lmd, sqrtf(lam), Gv, Rh, qrh, dr);
+  lmd[LMD_RH + 0] = Rh[0][0]; lmd[LMD_RH + 1] = Rh[0][1]; lmd[LMD_RH + 2] = Rh[0][2];
+  lmd[LMD_RH + 3] = Rh[1][1]; lmd[LMD_RH + 4] = Rh[1][2]; lmd[LMD_RH + 5] = Rh[2][2];
+  lmd[LMD_QRH + 0] = qrh[0]; lmd[LMD_QRH + 1] = qrh[1]; lmd[LMD_QRH + 2] = qrh[2];
+  lmd[LMD_LAM] = lam;
+  lmd[LMD_DR + 0] = dr[0]; lmd[LMD_DR + 1] = dr[1]; lmd[LMD_DR + 2] = dr[2];
+  const float R1[3][3] = {{lmd[LMD_R + 0], lmd[LMD_R + 1], lmd[LMD_R + 2]},
+                          {0.f, lmd[LMD_R + 3], lmd[LMD_R + 4]},
+                          {0.f, 0.f, lmd[LMD_R + 5]}};
+  // M Rh = R1 for the upper triangular M (a zero pivot, only possible at lambda = 0
+  // for a rank-deficient J_l, drops that column)
+  float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      float v = R1[i][j];
+#pragma unroll
+      for (int m = i; m < j; ++m) v -= M[i][m] * Rh[m][j];
+      M[i][j] = Rh[j][j] != 0.f ? v / Rh[j][j] : 0.f;
+    }
+  float P[6];
+  int e = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) P[e++] = M[a][0] * M[b][0] + M[a][1] * M[b][1] + M[a][2] * M[b][2];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) lmd[LMD_P + i] = P[i];
+}
+
+__device__ __forceinline__ void load_p(const float* lmd, float P[3][3]) {
+  P[0][0] = lmd[LMD_P + 0]; P[0][1] = P[1][0] = lmd[LMD_P + 1]; P[0][2] = P[2][0] = lmd[LMD_P + 2];
+  P[1][1] = lmd[LMD_P + 3]; P[1][2] = P[2][1] = lmd[LMD_P + 4]; P[2][2] = lmd[LMD_P + 5];
+}
+
+// The pose Jacobian rows (2 x 9) and Q1 rows (2 x 3) of an observation's record.
+__device__ __forceinline__ void load_rec(const Dev& d, int q, float J[2][9], float Q[2][3]) {
+  const float4* rec = reinterpret_cast<const float4*>(d.obsrec + (size_t)q * REC_STRIDE);
+  const float4 a = rec[0], b = rec[1], c = rec[2], e = rec[3], f = rec[4], g = rec[5];
+  J[0][0] = a.x; J[0][1] = a.y; J[0][2] = a.z; J[0][3] = a.w; J[0][4] = b.x; J[0][5] = b.y; J[0][6] = b.z;
+  J[0][7] = b.w; J[0][8] = c.x;
+  J[1][0] = c.y; J[1][1] = c.z; J[1][2] = c.w; J[1][3] = e.x; J[1][4] = e.y; J[1][5] = e.z; J[1][6] = e.w;
+  J[1][7] = f.x; J[1][8] = f.y;
+  Q[0][0] = f.z; Q[0][1] = f.w; Q[0][2] = g.x;
+  Q[1][0] = g.y; Q[1][1] = g.z; Q[1][2] = g.w;
+}
+
+// Per observation (one thread): its block-Jacobi terms G = J_o^T Pi J_o (45 upper
+// entries, Pi = I - Q1o P Q1o^T the observation's 2 x 2 block of the projector)
+// and right-hand side g = J_o^T (r_o - Q1o P Q1^T r), unscaled, to obsbuf[obs][0..53]
+// (the layout of the explicit pass).
+__global__ __launch_bounds__(WG) void k_precond_obs_implicit(Dev d) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= d.NO) return;
+  const int slot = d.lm_slot[d.obs_lm[q]];
+  const int prob = d.slot_prob[slot];
+  if (!d.active[prob]) return;
+  const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  float P[3][3], J[2][9], Q[2][3];
+  load_p(lmd, P);
+  load_rec(d, q, J, Q);
+  const float2 rv = reinterpret_cast<const float2*>(d.obsrec + (size_t)q * REC_STRIDE + REC_R)[0];
+  const float qr[3] = {lmd[LMD_QR + 0], lmd[LMD_QR + 1], lmd[LMD_QR + 2]};
+  float PQ[2][3], Pqr[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    PQ[0][a] = P[a][0] * Q[0][0] + P[a][1] * Q[0][1] + P[a][2] * Q[0][2];
+    PQ[1][a] = P[a][0] * Q[1][0] + P[a][1] * Q[1][1] + P[a][2] * Q[1][2];
+    Pqr[a] = P[a][0] * qr[0] + P[a][1] * qr[1] + P[a][2] * qr[2];
+  }
+  float Pi[2][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2)
+      Pi[h][h2] = (h == h2 ? 1.f : 0.f) - (Q[h][0] * PQ[h2][0] + Q[h][1] * PQ[h2][1] + Q[h][2] * PQ[h2][2]);
+  const float rp[2] = {rv.x - (Q[0][0] * Pqr[0] + Q[0][1] * Pqr[1] + Q[0][2] * Pqr[2]),
+                       rv.y - (Q[1][0] * Pqr[0] + Q[1][1] * Pqr[1] + Q[1][2] * Pqr[2])};
+  float K[2][9];  // Pi J
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int b = 0; b < 9; ++b) K[h][b] = Pi[h][0] * J[0][b] + Pi[h][1] * J[1][b];
+  float* out = d.obsbuf + (size_t)q * 54;
+  int e = 0;
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+#pragma unroll
+    for (int b = a; b < 9; ++b) out[e++] = J[0][a] * K[0][b] + J[1][a] * K[1][b];
+#pragma unroll
+  for (int a = 0; a < 9; ++a) out[45 + a] = J[0][a] * rp[0] + J[1][a] * rp[1];
+}
+
+// Launch description of all six classes for the implicit kernels, launch order
+// 5, 4, 3, 2, 1, 0; teams of 64, 64, 32, 16, 8, 4 lanes with 8, 2, 1, 1, 1, 1
+// observations per lane.
+struct ImplGrid {
+  int nblk[6];
+  int first[6];
+  int end[6];
+};
+__host__ __device__ constexpr int impl_team(int j) { return j <= 1 ? 64 : 128 >> j; }
+
+template <class F>
+__device__ __forceinline__ void impl_dispatch(const ImplGrid& m, const F& f) {
+  int b = blockIdx.x;
+#define SQRTBA_IMPL_CASE(J, TEAM, OPL)                                             \
+  if (b < m.nblk[J]) {                                                           \
+    const int t = threadIdx.x / TEAM, slot = m.first[J] + b * (WG / TEAM) + t;   \
+    if (slot < m.end[J]) f.template run<TEAM, OPL>(slot, threadIdx.x % TEAM);    \
+    return;                                                                      \
+  }                                                                              \
+  b -= m.nblk[J];
+  SQRTBA_IMPL_CASE(0, 64, 8)
+  SQRTBA_IMPL_CASE(1, 64, 2)
+  SQRTBA_IMPL_CASE(2, 32, 1)
+  SQRTBA_IMPL_CASE(3, 16, 1)
+  SQRTBA_IMPL_CASE(4, 8, 1)
+  SQRTBA_IMPL_CASE(5, 4, 1)
+#undef SQRTBA_IMPL_CASE
+}
+
+// Product for one landmark: u_o = J_o p'_o per observation, c = Q1^T u (team sum),
+// e = P c, z_o = J_o^T (u_o - Q1o e), written to the same per-observation output
+// positions as the explicit product.  The records are read twice (the second
+// time from cache) so that a lane never holds more than u of its observations.
+template <int TEAM, int OPL, bool PCG>
+__device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane, const float* __restrict__ v) {
+  const int prob = d.slot_prob[slot];
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const int zoff = d.slot_zoff[slot];
+  if (!d.active[prob] || (PCG && d.done[prob])) return;  // uniform over the team
+  float u[OPL][2];
+  float c[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int m = 0; m < OPL; ++m) {
+    const int o = lane + TEAM * m;
+    u[m][0] = u[m][1] = 0.f;
+    if (o < k) {
+      float J[2][9], Q[2][3];
+      load_rec(d, obs0 + o, J, Q);
+      const int cam = 9 * d.obs_cam[obs0 + o];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        const float pa = d.s_cam[cam + a] * v[cam + a];
+        u[m][0] += J[0][a] * pa;
+        u[m][1] += J[1][a] * pa;
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) c[j] += Q[0][j] * u[m][0] + Q[1][j] * u[m][1];
+    }
+  }
+  int buf = 0;
+  team_sum_n<TEAM, 3>(c, nullptr, buf);
+  float P[3][3];
+  load_p(d.lmd + (size_t)slot * LMD_STRIDE, P);
+  const float e[3] = {P[0][0] * c[0] + P[0][1] * c[1] + P[0][2] * c[2], P[1][0] * c[0] + P[1][1] * c[1] + P[1][2] * c[2],
+                      P[2][0] * c[0] + P[2][1] * c[1] + P[2][2] * c[2]};
+#pragma unroll
+  for (int m = 0; m < OPL; ++m) {
+    const int o = lane + TEAM * m;
+    if (o < k) {
+      float J[2][9], Q[2][3];
+      load_rec(d, obs0 + o, J, Q);
+      const float w0 = u[m][0] - (Q[0][0] * e[0] + Q[0][1] * e[1] + Q[0][2] * e[2]);
+      const float w1 = u[m][1] - (Q[1][0] * e[0] + Q[1][1] * e[1] + Q[1][2] * e[2]);
+      float* z = d.obsbuf + zoff + 9 * o;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) z[a] = J[0][a] * w0 + J[1][a] * w1;
+    }
+  }
+}
+
+template <bool PCG>
+struct MatvecImplF {
+  const Dev& d;
+  const float* v;
+  template <int TEAM, int OPL>
+  __device__ void run(int slot, int lane) const { matvec_implicit<TEAM, OPL, PCG>(d, slot, lane, v); }
+};
+
+template <bool PCG>
+__global__ __launch_bounds__(WG) void k_matvec_implicit(Dev d, ImplGrid m, const float* v) {
+  impl_dispatch(m, MatvecImplF<PCG>{d, v});
+}
+
+// Back-substitution for one landmark: u = J_p p' (p' = S dx_p), c = Q1^T u, the
+// damped top rows T^ p' and damping rows D p' by the Givens rotations of c,
+// dx~_l = -Rh^-1 (Q^1^T r + T^ p') (eq. backsub_nm), and the model decrease over
+// the rotated rows: top rows as in the explicit form, and for the B rows
+// sum u (2 rho + u) = 2 (u'.r + d.dr) + |u'|^2 + |d|^2 with u' = u - Q1 c.
+template <int TEAM, int OPL>
+__device__ __forceinline__ void backsub_implicit(const Dev& d, int slot, int lane) {
+  const int prob = d.slot_prob[slot];
+  const int lm = d.slot_lm[slot];
+  if (!d.active[prob]) return;  // uniform over the team
+  const int k = d.slot_k[slot];
+  const int obs0 = d.slot_obs0[slot];
+  const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const float lam = (float)d.lambda[prob];
+  float u[OPL][2];
+  float c[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int m = 0; m < OPL; ++m) {
+    const int o = lane + TEAM * m;
+    u[m][0] = u[m][1] = 0.f;
+    if (o < k) {
+      float J[2][9], Q[2][3];
+      load_rec(d, obs0 + o, J, Q);
+      const int cam = 9 * d.obs_cam[obs0 + o];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        const float pa = d.s_cam[cam + a] * d.vx[cam + a];
+        u[m][0] += J[0][a] * pa;
+        u[m][1] += J[1][a] * pa;
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) c[j] += Q[0][j] * u[m][0] + Q[1][j] * u[m][1];
+    }
+  }
+  int buf = 0;
+  team_sum_n<TEAM, 3>(c, nullptr, buf);
+  float s2[2] = {0.f, 0.f};  // |u'|^2, u'.r
+#pragma unroll
+  for (int m = 0; m < OPL; ++m) {
+    const int o = lane + TEAM * m;
+    if (o < k) {
+      float J[2][9], Q[2][3];
+      load_rec(d, obs0 + o, J, Q);
+      const float2 rv = reinterpret_cast<const float2*>(d.obsrec + (size_t)(obs0 + o) * REC_STRIDE + REC_R)[0];
+      const float w0 = u[m][0] - (Q[0][0] * c[0] + Q[0][1] * c[1] + Q[0][2] * c[2]);
+      const float w1 = u[m][1] - (Q[1][0] * c[0] + Q[1][1] * c[1] + Q[1][2] * c[2]);
+      s2[0] += w0 * w0 + w1 * w1;
+      s2[1] += w0 * rv.x + w1 * rv.y;
+    }
+  }
+  team_sum_n<TEAM, 2>(s2, nullptr, buf);
+  if (lane == 0) {
+    Givens6 Gv;
+    float Rh[3][3], qrh[3], dr[3];
+    damping_rotations(lmd, sqrtf(lam), Gv, Rh, qrh, dr);
+    float t[3] = {c[0], c[1], c[2]}, dd[3];
+    rotate_column(Gv, t, dd);  // t = T^ p', dd = D p'
+    const float c0 = -(qrh[0] + t[0]), c1 = -(qrh[1] + t[1]), c2 = -(qrh[2] + t[2]);
+    const float x2 = c2 / Rh[2][2];
+    const float x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
+    const float x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
+    const float ut0 = t[0] + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
+    const float ut1 = t[1] + Rh[1][1] * x1 + Rh[1][2] * x2;
+    const float ut2 = t[2] + Rh[2][2] * x2;
+    double pred = -(double)(ut0 * (2.f * qrh[0] + ut0)) - (double)(ut1 * (2.f * qrh[1] + ut1)) -
+                  (double)(ut2 * (2.f * qrh[2] + ut2)) + (double)lam * ((double)x0 * x0 + (double)x1 * x1 + (double)x2 * x2);
+    const double ddr = (double)dd[0] * dr[0] + (double)dd[1] * dr[1] + (double)dd[2] * dr[2];
+    const double dd2 = (double)dd[0] * dd[0] + (double)dd[1] * dd[1] + (double)dd[2] * dd[2];
+    pred -= 2.0 * ((double)s2[1] + ddr) + (double)s2[0] + dd2;
+    const float* sl = lmd + LMD_SL;
+    d.dxl[3 * (size_t)lm + 0] = sl[0] * x0;
+    d.dxl[3 * (size_t)lm + 1] = sl[1] * x1;
+    d.dxl[3 * (size_t)lm + 2] = sl[2] * x2;
+    d.lm_part[lm] = pred;
+  }
+}
+
+struct BacksubImplF {
+  const Dev& d;
+  template <int TEAM, int OPL>
+  __device__ void run(int slot, int lane) const { backsub_implicit<TEAM, OPL>(d, slot, lane); }
+};
+
+__global__ __launch_bounds__(WG) void k_backsub_implicit(Dev d, ImplGrid m) { impl_dispatch(m, BacksubImplF{d}); }
+
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -1831,6 +2170,21 @@ static ClassGrid class_grid(const Launch& L, int* n, bool skip4 = false) {
     const WorkClass& c = L.wc[4 - j];
     const int per = mv_per_wg(j);
     m.nblk[j] = (j == 0 && skip4) ? 0 : (c.slots + per - 1) / per;
+    m.first[j] = c.first_slot;
+    m.end[j] = c.first_slot + c.slots;
+    *n += m.nblk[j];
+  }
+  return m;
+}
+
+// Launch description of all six classes for the implicit kernels.
+static ImplGrid impl_grid(const Launch& L, int* n) {
+  ImplGrid m;
+  *n = 0;
+  for (int j = 0; j < 6; ++j) {
+    const WorkClass& c = L.wc[5 - j];
+    const int per = WG / impl_team(j);
+    m.nblk[j] = (c.slots + per - 1) / per;
     m.first[j] = c.first_slot;
     m.end[j] = c.first_slot + c.slots;
     *n += m.nblk[j];
@@ -1875,11 +2229,21 @@ hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask
     if (e == hipSuccess) e = hipStreamWaitEvent(L.side, L.fork, 0);
     if (e != hipSuccess) return e;
   }
-  if (w[5].slots)
-    hipLaunchKernelGGL(k_marginalize_huge, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d, w[5].first_slot,
-                       mask);
+  if (w[5].slots) {
+    if (d.implicit)
+      hipLaunchKernelGGL(k_marginalize_huge<true>, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d,
+                         w[5].first_slot, mask);
+    else
+      hipLaunchKernelGGL(k_marginalize_huge<false>, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d,
+                         w[5].first_slot, mask);
+  }
   LAUNCH_CHECK();
-  if (n) hipLaunchKernelGGL(k_marginalize, dim3(n), dim3(WG), 0, L.stream, d, m, mask);
+  if (n) {
+    if (d.implicit)
+      hipLaunchKernelGGL(k_marginalize<true>, dim3(n), dim3(WG), 0, L.stream, d, m, mask);
+    else
+      hipLaunchKernelGGL(k_marginalize<false>, dim3(n), dim3(WG), 0, L.stream, d, m, mask);
+  }
   LAUNCH_CHECK();
   if (side) {
     hipError_t e = hipEventRecord(L.join, L.side);
@@ -1891,6 +2255,11 @@ hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask
 
 hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
   const WorkClass* w = L.wc;
+  if (d.implicit) {
+    if (d.NS) hipLaunchKernelGGL(k_damp_implicit, dim3(nblocks(d.NS, WG)), dim3(WG), 0, L.stream, d, mask);
+    LAUNCH_CHECK();
+    return hipSuccess;
+  }
   if (w[5].slots) hipLaunchKernelGGL(k_damp_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot, mask);
   int n = 0;
   const ClassGrid m = class_grid(L, &n);
@@ -1901,6 +2270,13 @@ hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
 
 hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
   const WorkClass* w = L.wc;
+  if (d.implicit) {
+    if (d.NO) hipLaunchKernelGGL(k_precond_obs_implicit, dim3(nblocks(d.NO, WG)), dim3(WG), 0, L.stream, d);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_precond_cam, dim3(d.NC), dim3(64), 0, L.stream, d);
+    LAUNCH_CHECK();
+    return hipSuccess;
+  }
   if (w[5].slots) hipLaunchKernelGGL(k_precond_obs_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot);
   int n = 0;
   const ClassGrid m = class_grid(L, &n);
@@ -1942,6 +2318,13 @@ static void launch_small(const Dev& d, const Launch& L, const ClassGrid& m, int 
 // of the row-block partials.
 template <bool PCG>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
+  if (d.implicit) {
+    int n = 0;
+    const ImplGrid m = impl_grid(L, &n);
+    if (n) hipLaunchKernelGGL(k_matvec_implicit<PCG>, dim3(n), dim3(WG), 0, L.stream, d, m, v);
+    LAUNCH_CHECK();
+    return hipSuccess;
+  }
   const bool rows = L.rows_n > 0 && L.hjobs > 0;
   const bool side = rows && L.huge_side && L.side && L.fork && L.join;
   const hipStream_t hs = side ? L.side : L.stream;
@@ -2018,6 +2401,13 @@ hipError_t launch_pcg_iteration(const Dev& d, const Launch& L) {
 
 hipError_t launch_backsub(const Dev& d, const Launch& L) {
   const WorkClass* w = L.wc;
+  if (d.implicit) {
+    int n = 0;
+    const ImplGrid m = impl_grid(L, &n);
+    if (n) hipLaunchKernelGGL(k_backsub_implicit, dim3(n), dim3(WG), 0, L.stream, d, m);
+    LAUNCH_CHECK();
+    return hipSuccess;
+  }
   if (w[5].slots) hipLaunchKernelGGL(k_backsub_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot);
   int n = 0;
   const ClassGrid m = class_grid(L, &n);

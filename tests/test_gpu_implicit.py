@@ -1,0 +1,170 @@
+"""Implicit landmark blocks (option landmark_blocks = 1) against the FP64 oracle.
+
+The implicit form never stores the rows of B: with the thin QR factor Q1 and
+P = R1 (R1^T R1 + lambda I)^-1 R1^T it applies B^T B = J_p^T (I - Q1 P Q1^T) J_p,
+the landmark term of eq. red_H.  It is held to the explicit path's bar: the dense
+reduced system and right-hand side to 1e-4 relative (Frobenius), block-Jacobi
+blocks, the PCG solution and the back-substitution and model decrease from the
+oracle's exact pose step to 1e-4, the LM final cost to 1e-3; it agrees with the
+explicit form on the same problem, runs are bitwise deterministic, and at the
+ladybug-like and venice-like sizes the product and the final cost are checked
+on properties and the oracle's cost at the GPU's final state.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.lm import cost_of
+from bal_synth import make_config, concat_problems, make_ring_problem
+from paper_2103_01843_amd import SqrtBAError
+
+from gpu_util import gpu_context, mixed_problem, oracle_lin
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", params=["tiny", "mixed"])
+def case(request):
+    p = make_config(0) if request.param == "tiny" else mixed_problem()
+    bk, st, lin = oracle_lin(p)
+    ctx = gpu_context(p, landmark_blocks=1)
+    yield p, bk, st, lin, ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("lam", [1e-4, 0.3])
+def test_reduced_camera_system_dense(case, lam):
+    p, bk, st, lin, ctx = case
+    ctx.linearize()
+    ctx.marginalize()
+    ctx.damp(lam)
+    rs = oracle.reduced_camera_system(lin, lam)
+    N = rs.H.shape[0]
+    Hg = ctx.debug_rcs_matvec(np.eye(N, dtype=np.float32)).astype(np.float64)
+    eH = np.linalg.norm(Hg - rs.H) / np.linalg.norm(rs.H)
+    assert eH <= 1e-4, eH
+    bg = ctx.debug_rhs().astype(np.float64)
+    eb = np.linalg.norm(bg - rs.b) / np.linalg.norm(rs.b)
+    assert eb <= 1e-4, eb
+    Mi = ctx.debug_precond().astype(np.float64)
+    Bo = oracle.block_jacobi_blocks(rs.H)
+    for i in range(0, len(Bo), max(1, len(Bo) // 20)):
+        np.testing.assert_allclose(Mi[i] @ Bo[i], np.eye(9), atol=5e-3)
+
+
+def test_pcg_and_back_substitution(case):
+    p, bk, st, lin, ctx = case
+    lam = 1e-4
+    ctx.linearize()
+    ctx.marginalize()
+    ctx.damp(lam)
+    its, rel, status = ctx.solve()
+    rs = oracle.reduced_camera_system(lin, lam)
+    dxp, _ = ctx.debug_solution()
+    assert status[0] == 0 and rel[0] <= 1e-6
+    res = np.linalg.norm(rs.H @ dxp + rs.b) / np.linalg.norm(rs.b)
+    assert res < 1e-3, res
+    ref = oracle.dense_spd_solve(rs.H, -rs.b)
+    ctx.debug_set_pose_increment(ref.astype(np.float32))
+    pred = ctx.back_substitute()[0]
+    _, dxl = ctx.debug_solution()
+    dxl_o = (oracle.back_substitute(rs, ref).reshape(-1, 3) * lin.sl)
+    act = bk.lm_active
+    e = np.linalg.norm(dxl[act] - dxl_o[act]) / np.linalg.norm(dxl_o[act])
+    assert e <= 1e-4, e
+    pred_o = oracle.model_decrease(lin, ref, oracle.back_substitute(rs, ref))
+    assert abs(pred - pred_o) <= 1e-4 * abs(pred_o), (pred, pred_o)
+
+
+def test_lm_final_cost_and_agreement_with_explicit_blocks():
+    for p in [make_config(0), mixed_problem(seed=9, n_cams=40, n_points=120)]:
+        bk, st, lin = oracle_lin(p)
+        res = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, oracle.LMOptions(max_iters=10), bk=bk)
+        imp = gpu_context(p, max_lm_iters=10, landmark_blocks=1)
+        rep = imp.lm_solve()[0]
+        exp = gpu_context(p, max_lm_iters=10)
+        rep_e = exp.lm_solve()[0]
+        assert abs(rep.final_cost - res.final_cost) <= 1e-3 * res.final_cost, (rep.final_cost, res.final_cost)
+        assert abs(rep.final_cost - rep_e.final_cost) <= 1e-4 * rep_e.final_cost
+        c = cost_of(oracle.state_from_bal(imp.get_cameras(), imp.get_landmarks()), bk, p.obs_uv)
+        assert abs(c - rep.final_cost) <= 1e-5 * rep.final_cost
+        imp.close()
+        exp.close()
+
+
+def test_deterministic_and_batch_equals_single():
+    rng = np.random.default_rng(11)
+    ps = [make_ring_problem(rng, 12, 200, lambda r, n: r.integers(2, 9, size=n)) for _ in range(3)]
+    out = []
+    for _ in range(2):
+        ctx = gpu_context(ps[1], landmark_blocks=1)
+        ctx.linearize()
+        ctx.marginalize()
+        ctx.damp(1e-3)
+        ctx.solve()
+        pred = ctx.back_substitute()
+        out.append((ctx.debug_solution()[0].copy(), pred.copy()))
+        ctx.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    batch = gpu_context(concat_problems(ps), max_lm_iters=6, landmark_blocks=1)
+    reps = batch.lm_solve()
+    for i, p in enumerate(ps):
+        single = gpu_context(p, max_lm_iters=6, landmark_blocks=1)
+        r = single.lm_solve()[0]
+        assert r.final_cost == reps[i].final_cost and r.total_pcg_iters == reps[i].total_pcg_iters
+        single.close()
+    batch.close()
+
+
+def test_block_rows_are_not_stored_and_mode_is_fixed_after_upload():
+    p = make_config(0)
+    ctx = gpu_context(p, landmark_blocks=1)
+    ctx.linearize()
+    ctx.marginalize()
+    ctx.damp(1e-3)
+    l = int(np.nonzero(np.bincount(p.obs_pt, minlength=p.n_points) >= 2)[0][0])
+    with pytest.raises(SqrtBAError) as ei:
+        ctx.debug_block(l)
+    assert ei.value.status == -6
+    with pytest.raises(SqrtBAError) as ei:
+        ctx.set_options(landmark_blocks=0)
+    assert ei.value.status == -4
+    ctx.set_options(pcg_forcing_eta=0.1)  # other options may change
+    ctx.close()
+    with pytest.raises(SqrtBAError):
+        gpu_context(p, landmark_blocks=2)
+
+
+@pytest.mark.parametrize("cfg", [1, 3])
+def test_full_size_product_and_final_cost(cfg):
+    p = make_config(cfg)
+    bk, st, lin = oracle_lin(p)
+    imp = gpu_context(p, max_lm_iters=20, landmark_blocks=1)
+    exp = gpu_context(p, max_lm_iters=20)
+    lam = 1e-4
+    n = 9 * p.n_cams
+    V = np.random.default_rng(7).normal(size=(2, n)).astype(np.float32)
+    prods = []
+    for ctx in (imp, exp):
+        ctx.linearize()
+        ctx.marginalize()
+        ctx.damp(lam)
+        prods.append(ctx.debug_rcs_matvec(V).astype(np.float64))
+    A, B = prods
+    assert np.linalg.norm(A - B) <= 1e-4 * np.linalg.norm(B)
+    v, w = V.astype(np.float64)
+    assert abs(v @ A[1] - w @ A[0]) <= 1e-5 * (np.linalg.norm(v) * np.linalg.norm(A[1]) + np.linalg.norm(w) * np.linalg.norm(A[0]))
+    exp.close()
+    rep = imp.lm_solve()[0]
+    c = cost_of(oracle.state_from_bal(imp.get_cameras(), imp.get_landmarks()), bk, p.obs_uv)
+    assert abs(c - rep.final_cost) <= 1e-5 * rep.final_cost
+    golden = os.path.join(os.path.dirname(__file__), "golden", f"oracle_lm_config{cfg}.json")
+    if os.path.exists(golden):
+        with open(golden) as f:
+            gold = json.load(f)["final_cost"]
+        assert abs(rep.final_cost - gold) <= 1e-3 * gold, (rep.final_cost, gold)
+    imp.close()
