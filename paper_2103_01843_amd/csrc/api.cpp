@@ -455,7 +455,8 @@ uint64_t layout(const HostData& h, bool implicit, void* base, Dev* d) {
   uint64_t o_hj = f32(h.hjob.size()), o_hzo = f64(h.hz_off.size()), o_zp = f32(h.hz_floats);
   const uint64_t nB = implicit ? 0 : h.poolB, nT = implicit ? 0 : h.poolT, nrho = implicit ? 0 : 2 * NO;
   uint64_t o_pB = f32(nB), o_pT = f32(nT), o_lmd = f32(NS * LMD_STRIDE), o_rho = f32(nrho);
-  uint64_t o_rec = f32(implicit ? (uint64_t)REC_STRIDE * NO : 0);
+  uint64_t o_rec = f32(implicit ? 4 * (uint64_t)REC_PLANES * NO : 0), o_rcam = f32(implicit ? NO : 0);
+  uint64_t o_vzs = f32(12 * NC);
   uint64_t o_sc = f32(9 * NC);
   uint64_t o_v[6];
   for (int i = 0; i < 6; ++i) o_v[i] = f32(9 * NC);
@@ -484,6 +485,8 @@ uint64_t layout(const HostData& h, bool implicit, void* base, Dev* d) {
     t.rhoB = implicit ? nullptr : at<float>(base, o_rho); t.s_cam = at<float>(base, o_sc);
     if (implicit) { t.poolB = nullptr; t.poolT = nullptr; }
     t.obsrec = implicit ? at<float>(base, o_rec) : nullptr;
+    t.rec_cam = implicit ? at<int32_t>(base, o_rcam) : nullptr;
+    t.vzs = at<float>(base, o_vzs);
     t.implicit = implicit ? 1 : 0;
     t.vx = at<float>(base, o_v[0]); t.vr = at<float>(base, o_v[1]); t.vz = at<float>(base, o_v[2]);
     t.vp = at<float>(base, o_v[3]); t.vq = at<float>(base, o_v[4]); t.vb = at<float>(base, o_v[5]);
@@ -628,8 +631,24 @@ int upload(sqrtba_ctx* c) {
   TRY(upload_vec(c, d.slot_prob, h.slot_prob));
   TRY(upload_vec(c, d.slot_boff, h.slot_boff));
   TRY(upload_vec(c, d.slot_toff, h.slot_toff));
-  TRY(upload_vec(c, d.slot_zoff, h.slot_zoff));
-  TRY(upload_vec(c, d.cam_zpos, h.cam_zpos));
+  if (d.implicit) {
+    // records in slot order; the product writes 12 floats (3 float4) per record
+    std::vector<int32_t> rec0(h.NS), zpos(h.NO);
+    int64_t r = 0;
+    for (int64_t s = 0; s < h.NS; ++s) {
+      rec0[s] = (int32_t)r;
+      r += h.slot_k[s];
+    }
+    for (int64_t q = 0; q < h.NO; ++q) {
+      const int32_t j = h.cam_obs_idx[q], s = h.lm_slot[h.olm[j]];
+      zpos[q] = 12 * (rec0[s] + (j - h.slot_obs0[s]));
+    }
+    TRY(upload_vec(c, d.slot_zoff, rec0));
+    TRY(upload_vec(c, d.cam_zpos, zpos));
+  } else {
+    TRY(upload_vec(c, d.slot_zoff, h.slot_zoff));
+    TRY(upload_vec(c, d.cam_zpos, h.cam_zpos));
+  }
   TRY(upload_vec(c, d.lm_slot, h.lm_slot));
   TRY(upload_vec(c, reinterpret_cast<int32_t*>(d.hjob), h.hjob));
   TRY(upload_vec(c, d.hz_off, h.hz_off));
@@ -676,10 +695,11 @@ int upload(sqrtba_ctx* c) {
     const double k = h.slot_k[sl];
     const int p = h.slot_prob[sl];
     if (c->opt.landmark_blocks == 1) {
-      // implicit: read the 24 Jacobian and Q1 floats per observation and the 6 of P,
-      // write 9k per-observation outputs; the QR writes the 28-float records
-      c->mv_bytes[p] += 4.0 * (24.0 * k + 6.0 + 9.0 * k);
-      c->qr_bytes[p] += 4.0 * (28.0 * k + 12.0) + 12.0 * k + 16.0;
+      // implicit: read the 24 Jacobian and Q1 floats and the camera index per
+      // observation and the 6 floats of P, write 9k per-observation outputs; the QR
+      // writes the 28-float records and the camera indices
+      c->mv_bytes[p] += 4.0 * (25.0 * k + 6.0 + 9.0 * k);
+      c->qr_bytes[p] += 4.0 * (29.0 * k + 12.0) + 12.0 * k + 16.0;
     } else {
       // matvec: read the 2k x 9k B rows, write 9k per-observation outputs
       c->mv_bytes[p] += 4.0 * (18.0 * k * k + 9.0 * k);
@@ -1854,6 +1874,7 @@ int apply_tuning(sqrtba_ctx* c, const sqrtba_tuning& t) {
 int time_products(sqrtba_ctx* c, int reps, double* ms) {
   hipEvent_t e0 = take_event(c), e1 = take_event(c);
   if (!e0 || !e1) return fail(c, SQRTBA_E_HIP, "no events");
+  if (c->d.implicit) LAUNCH(c, launch_prescale_z(c->d, c->L));
   for (int i = 0; i < 2; ++i) LAUNCH(c, launch_matvec_timing(c->d, c->L));
   HIP_TRY(c, hipEventRecord(e0, c->stream));
   for (int i = 0; i < reps; ++i) LAUNCH(c, launch_matvec_timing(c->d, c->L));

@@ -24,18 +24,22 @@ __host__ __device__ constexpr int class_of_k(int k) {
 }
 
 // Small per-landmark record (floats): R1 upper (6), Q1^T r (3), damped R upper (6),
-// damped Q1^T r (3), landmark column scales (3), lambda used (1), and for implicit
-// landmark blocks the projection matrix P = R1 (R1^T R1 + lambda I)^-1 R1^T (6,
-// upper triangle row by row) and the damping rows' residuals (3), pad (1).
+// damped Q1^T r (3), landmark column scales (3), lambda used (1), pad (2), and for
+// implicit landmark blocks the projection matrix P = R1 (R1^T R1 + lambda I)^-1 R1^T
+// (6, upper triangle row by row, 16-byte aligned), pad (2).
 enum {
-  LMD_R = 0, LMD_QR = 6, LMD_RH = 9, LMD_QRH = 15, LMD_SL = 18, LMD_LAM = 21, LMD_P = 22, LMD_DR = 28,
-  LMD_STRIDE = 32
+  LMD_R = 0, LMD_QR = 6, LMD_RH = 9, LMD_QRH = 15, LMD_SL = 18, LMD_LAM = 21, LMD_P = 24, LMD_STRIDE = 32
 };
 
-// Implicit landmark blocks: per sorted observation 28 floats (7 float4) holding
-// the unscaled pose Jacobian rows (2 x 9), the observation's two rows of the
-// thin QR factor Q1 (2 x 3), the residual (2) and 2 pad.
-enum { REC_JP = 0, REC_Q1 = 18, REC_R = 24, REC_STRIDE = 28 };
+// Implicit landmark blocks: per observation a record of 7 float4 "planes" holding
+// the unscaled pose Jacobian rows (2 x 9, row by row, planes 0..4), the
+// observation's two rows of the thin QR factor Q1 (2 x 3, planes 4..5), and in
+// plane 6 the residual (2) and 2 zeros; the camera index is in rec_cam.  Records are in
+// slot order (slot_zoff[slot] + o for observation o of a slot) and plane-major:
+// plane p of record i is float4 p * NO + i, so a team reading one plane of its
+// landmark's observations, and consecutive teams of consecutive landmarks, read
+// contiguous memory.
+enum { REC_PLANES = 7 };
 
 // Device view of the whole context.  All pointers are device pointers.
 struct Dev {
@@ -66,7 +70,8 @@ struct Dev {
   int32_t* slot_prob;
   int64_t* slot_boff;  // float offset of the B rows (2k x W) in poolB
   int64_t* slot_toff;  // float offset of the undamped top rows (3 x W) in poolT
-  int32_t* slot_zoff;  // float offset of the landmark's W product outputs in obsbuf (16-byte aligned)
+  int32_t* slot_zoff;  // float offset of the landmark's W product outputs in obsbuf (16-byte aligned);
+                       // implicit blocks: index of the landmark's first record (outputs at 12 x record)
   int32_t* cam_zpos;   // NO: obsbuf offset of the outputs of each camera's observations (camera order)
   int32_t* lm_slot;    // NL, -1 when inactive
   // row-block product of the largest landmarks: one job per block of
@@ -83,11 +88,14 @@ struct Dev {
   float* vx;
   float* vr;
   float* vz;
+  float* vzs;     // NC * 12: S z per camera, 9 floats and 3 zero pad (16-byte aligned), kept by the
+                  // PCG kernels for the implicit product's gather
   float* vp;
   float* vq;
   float* vb;      // right-hand side b~
   float* minv;    // NC * 81 inverse preconditioner blocks
-  float* obsrec;  // implicit blocks: NO * REC_STRIDE per-observation records (else null)
+  float* obsrec;  // implicit blocks: REC_PLANES * NO float4 per-observation records (else null)
+  int32_t* rec_cam;  // implicit blocks: NO camera indices of the records (else null)
   int32_t implicit;  // 1: implicit landmark blocks (no poolB / poolT / rhoB)
   float* obsbuf;  // NO * 54 floats: per-observation preconditioner terms; the product outputs
                   // reuse it in per-landmark aligned regions (slot_zoff)
@@ -168,6 +176,8 @@ hipError_t launch_commit(const Dev& d, const Launch& L);
 // test helpers
 hipError_t launch_matvec_only(const Dev& d, const Launch& L, const float* v_scaled, float* out);
 hipError_t launch_matvec_timing(const Dev& d, const Launch& L);  // product of z over all active landmarks
+// implicit blocks: S z into vzs once, before timed launch_matvec_timing calls (which then read it)
+hipError_t launch_prescale_z(const Dev& d, const Launch& L);
 hipError_t launch_debug_linearization(const Dev& d, const Launch& L, float* r, float* Jp, float* Jl);
 
 }  // namespace sqrtba

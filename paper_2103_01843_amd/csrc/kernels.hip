@@ -296,6 +296,11 @@ __device__ __forceinline__ void team_sum_n(float (&v)[N], float* red, int& buf) 
   }
 }
 
+// Plane p of the implicit per-observation records (REC_PLANES planes of NO float4).
+__device__ __forceinline__ float4* rec_plane(const Dev& d, int p) {
+  return reinterpret_cast<float4*>(d.obsrec) + (size_t)p * d.NO;
+}
+
 // LDS floats per team: V (2k x 4) and the pose Jacobians (k x 18), rounded up
 // to whole float4s so that every team's V is 16-byte aligned.
 __host__ __device__ constexpr int marg_stride(int kmax) { return (26 * kmax + 3) & ~3; }
@@ -497,14 +502,16 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
             q[h][j] = (gi == j ? 1.f : 0.f) - (vv.x * K[0][j] + vv.y * K[1][j] + vv.z * K[2][j]);
         }
         const float* J = Jpc + 18 * o;
-        float4* rec = reinterpret_cast<float4*>(d.obsrec + (size_t)(obs0 + o) * REC_STRIDE);
+        float4* rec = rec_plane(d, 0) + d.slot_zoff[slot] + o;
+        const size_t P = (size_t)d.NO;
         rec[0] = make_float4(J[0], J[1], J[2], J[3]);
-        rec[1] = make_float4(J[4], J[5], J[6], J[7]);
-        rec[2] = make_float4(J[8], J[9], J[10], J[11]);
-        rec[3] = make_float4(J[12], J[13], J[14], J[15]);
-        rec[4] = make_float4(J[16], J[17], q[0][0], q[0][1]);
-        rec[5] = make_float4(q[0][2], q[1][0], q[1][1], q[1][2]);
-        rec[6] = make_float4(rr[2 * m], rr[2 * m + 1], 0.f, 0.f);
+        rec[P] = make_float4(J[4], J[5], J[6], J[7]);
+        rec[2 * P] = make_float4(J[8], J[9], J[10], J[11]);
+        rec[3 * P] = make_float4(J[12], J[13], J[14], J[15]);
+        rec[4 * P] = make_float4(J[16], J[17], q[0][0], q[0][1]);
+        rec[5 * P] = make_float4(q[0][2], q[1][0], q[1][1], q[1][2]);
+        rec[6 * P] = make_float4(rr[2 * m], rr[2 * m + 1], 0.f, 0.f);
+        d.rec_cam[d.slot_zoff[slot] + o] = d.obs_cam[obs0 + o];
       }
     }
     return;
@@ -1187,7 +1194,7 @@ __device__ __forceinline__ void minv_apply(const float* __restrict__ mi, const f
   }
 }
 
-// x = 0, r = -b, z = M^-1 r, p = q = 0; per-camera partials r.z (cam_part2), r.r (cam_part3).
+// x = 0, r = -b, z = M^-1 r (and S z), p = q = 0; per-camera partials r.z (cam_part2), r.r (cam_part3).
 __global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= d.NC) return;
@@ -1207,6 +1214,7 @@ __global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       d.vz[9 * c + a] = z[a];
+      d.vzs[12 * c + a] = d.s_cam[9 * c + a] * z[a];
       rz += (double)(r[a] * z[a]);
       rr += (double)(r[a] * r[a]);
     }
@@ -1381,10 +1389,11 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
   const bool valid = c < d.NC && lc < UPD_CAMS;
   // loads that do not depend on alpha first
   int prob = 0;
-  float xv = 0.f, pv = 0.f, rv = 0.f, qv = 0.f, mrow[9];
+  float xv = 0.f, pv = 0.f, rv = 0.f, qv = 0.f, sv = 0.f, mrow[9];
   const int idx = 9 * c + a;
   if (valid) {
     prob = d.cam_prob[c];
+    sv = d.s_cam[idx];
     xv = d.vx[idx];
     pv = d.vp[idx];
     rv = d.vr[idx];
@@ -1446,6 +1455,7 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
 #pragma unroll
     for (int j = 0; j < 9; ++j) z += mrow[j] * rs[lc][j];
     d.vz[idx] = z;
+    d.vzs[12 * c + a] = sv * z;
   }
   if (lc < UPD_CAMS) {
     prz[lc][a] = r * z;
@@ -1657,7 +1667,7 @@ struct MargF {
   float* lds;
   float* red;
   template <int TEAM, int CLS>
-  __device__ void run(int slot, int lane, int team) const {
+  __device__ __forceinline__ void run(int slot, int lane, int team) const {
     marginalize_one<TEAM, class_kmax(CLS), IMPLICIT>(d, slot, lane, lds + team * marg_stride(class_kmax(CLS)), red,
                                                      mask);
   }
@@ -1688,7 +1698,7 @@ struct DampF {
   const Dev& d;
   const uint8_t* mask;
   template <int TEAM, int CLS>
-  __device__ void run(int slot, int lane, int) const { damp_one<TEAM>(d, slot, lane, mask); }
+  __device__ __forceinline__ void run(int slot, int lane, int) const { damp_one<TEAM>(d, slot, lane, mask); }
 };
 
 __global__ __launch_bounds__(WG) void k_damp(Dev d, ClassGrid m, const uint8_t* mask) {
@@ -1702,7 +1712,7 @@ __global__ __launch_bounds__(WG) void k_damp_huge(Dev d, int slot0, const uint8_
 struct PrecondF {
   const Dev& d;
   template <int TEAM, int CLS>
-  __device__ void run(int slot, int lane, int) const { precond_one<TEAM>(d, slot, lane); }
+  __device__ __forceinline__ void run(int slot, int lane, int) const { precond_one<TEAM>(d, slot, lane); }
 };
 
 __global__ __launch_bounds__(WG) void k_precond_obs(Dev d, ClassGrid m) { class_dispatch(m, PrecondF{d}); }
@@ -1716,7 +1726,7 @@ struct BacksubF {
   float* red4;
   double* predw;
   template <int TEAM, int CLS>
-  __device__ void run(int slot, int lane, int) const {
+  __device__ __forceinline__ void run(int slot, int lane, int) const {
     if constexpr (TEAM == 256)
       backsub_large<4>(d, slot, predw);
     else
@@ -1871,8 +1881,7 @@ __global__ __launch_bounds__(64) void k_cam_gather_product(Dev d, const float* v
 // Each observation carries its record (pose Jacobian rows, its two rows of Q1,
 // residual), so every stage below is O(k) per landmark.
 
-// Per landmark (one thread): the damped factors (as the explicit damping), the
-// damping rows' residuals and P.
+// Per landmark (one thread): the damped factors (as the explicit damping) and P.
 __global__ __launch_bounds__(WG) void k_damp_implicit(Dev d, const uint8_t* mask) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= d.NS) return;
@@ -1887,7 +1896,6 @@ __global__ __launch_bounds__(WG) void k_damp_implicit(Dev d, const uint8_t* mask
   lmd[LMD_RH + 3] = Rh[1][1]; lmd[LMD_RH + 4] = Rh[1][2]; lmd[LMD_RH + 5] = Rh[2][2];
   lmd[LMD_QRH + 0] = qrh[0]; lmd[LMD_QRH + 1] = qrh[1]; lmd[LMD_QRH + 2] = qrh[2];
   lmd[LMD_LAM] = lam;
-  lmd[LMD_DR + 0] = dr[0]; lmd[LMD_DR + 1] = dr[1]; lmd[LMD_DR + 2] = dr[2];
   const float R1[3][3] = {{lmd[LMD_R + 0], lmd[LMD_R + 1], lmd[LMD_R + 2]},
                           {0.f, lmd[LMD_R + 3], lmd[LMD_R + 4]},
                           {0.f, 0.f, lmd[LMD_R + 5]}};
@@ -1909,19 +1917,22 @@ __global__ __launch_bounds__(WG) void k_damp_implicit(Dev d, const uint8_t* mask
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = a; b < 3; ++b) P[e++] = M[a][0] * M[b][0] + M[a][1] * M[b][1] + M[a][2] * M[b][2];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) lmd[LMD_P + i] = P[i];
+  reinterpret_cast<float4*>(lmd + LMD_P)[0] = make_float4(P[0], P[1], P[2], P[3]);
+  reinterpret_cast<float2*>(lmd + LMD_P + 4)[0] = make_float2(P[4], P[5]);
 }
 
 __device__ __forceinline__ void load_p(const float* lmd, float P[3][3]) {
-  P[0][0] = lmd[LMD_P + 0]; P[0][1] = P[1][0] = lmd[LMD_P + 1]; P[0][2] = P[2][0] = lmd[LMD_P + 2];
-  P[1][1] = lmd[LMD_P + 3]; P[1][2] = P[2][1] = lmd[LMD_P + 4]; P[2][2] = lmd[LMD_P + 5];
+  const float4 a = reinterpret_cast<const float4*>(lmd + LMD_P)[0];
+  const float2 b = reinterpret_cast<const float2*>(lmd + LMD_P + 4)[0];
+  P[0][0] = a.x; P[0][1] = P[1][0] = a.y; P[0][2] = P[2][0] = a.z;
+  P[1][1] = a.w; P[1][2] = P[2][1] = b.x; P[2][2] = b.y;
 }
 
-// The pose Jacobian rows (2 x 9) and Q1 rows (2 x 3) of an observation's record.
-__device__ __forceinline__ void load_rec(const Dev& d, int q, float J[2][9], float Q[2][3]) {
-  const float4* rec = reinterpret_cast<const float4*>(d.obsrec + (size_t)q * REC_STRIDE);
-  const float4 a = rec[0], b = rec[1], c = rec[2], e = rec[3], f = rec[4], g = rec[5];
+// The pose Jacobian rows (2 x 9) and Q1 rows (2 x 3) of record i.
+__device__ __forceinline__ void load_rec(const Dev& d, int i, float (&J)[2][9], float (&Q)[2][3]) {
+  const float4* rec = rec_plane(d, 0) + i;
+  const size_t P = (size_t)d.NO;
+  const float4 a = rec[0], b = rec[P], c = rec[2 * P], e = rec[3 * P], f = rec[4 * P], g = rec[5 * P];
   J[0][0] = a.x; J[0][1] = a.y; J[0][2] = a.z; J[0][3] = a.w; J[0][4] = b.x; J[0][5] = b.y; J[0][6] = b.z;
   J[0][7] = b.w; J[0][8] = c.x;
   J[1][0] = c.y; J[1][1] = c.z; J[1][2] = c.w; J[1][3] = e.x; J[1][4] = e.y; J[1][5] = e.z; J[1][6] = e.w;
@@ -1941,10 +1952,11 @@ __global__ __launch_bounds__(WG) void k_precond_obs_implicit(Dev d) {
   const int prob = d.slot_prob[slot];
   if (!d.active[prob]) return;
   const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const int ri = d.slot_zoff[slot] + (q - d.slot_obs0[slot]);
   float P[3][3], J[2][9], Q[2][3];
   load_p(lmd, P);
-  load_rec(d, q, J, Q);
-  const float2 rv = reinterpret_cast<const float2*>(d.obsrec + (size_t)q * REC_STRIDE + REC_R)[0];
+  load_rec(d, ri, J, Q);
+  const float4 rv = rec_plane(d, 6)[ri];
   const float qr[3] = {lmd[LMD_QR + 0], lmd[LMD_QR + 1], lmd[LMD_QR + 2]};
   float PQ[2][3], Pqr[3];
 #pragma unroll
@@ -2005,35 +2017,37 @@ __device__ __forceinline__ void impl_dispatch(const ImplGrid& m, const F& f) {
 #undef SQRTBA_IMPL_CASE
 }
 
-// Product for one landmark: u_o = J_o p'_o per observation, c = Q1^T u (team sum),
-// e = P c, z_o = J_o^T (u_o - Q1o e), written to the same per-observation output
-// positions as the explicit product.  The records are read twice (the second
-// time from cache) so that a lane never holds more than u of its observations.
+// Product for one landmark: u_o = J_o p'_o per observation (p' = S z, gathered
+// from vzs), c = Q1^T u (team sum),
+// e = P c, z_o = J_o^T (u_o - Q1o e), written as 12 floats (3 float4, the last 3
+// zero) per record.  Teams with at most two observations per lane keep their
+// records in registers; the others read them again (from cache) after the sum.
 template <int TEAM, int OPL, bool PCG>
-__device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane, const float* __restrict__ v) {
+__device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane) {
+  constexpr bool KEEP = OPL <= 2;
   const int prob = d.slot_prob[slot];
   const int k = d.slot_k[slot];
-  const int obs0 = d.slot_obs0[slot];
-  const int zoff = d.slot_zoff[slot];
+  const int r0 = d.slot_zoff[slot];
   if (!d.active[prob] || (PCG && d.done[prob])) return;  // uniform over the team
   float u[OPL][2];
+  float J[OPL][2][9], Q[OPL][2][3];
   float c[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     u[m][0] = u[m][1] = 0.f;
     if (o < k) {
-      float J[2][9], Q[2][3];
-      load_rec(d, obs0 + o, J, Q);
-      const int cam = 9 * d.obs_cam[obs0 + o];
+      const float4* vs = reinterpret_cast<const float4*>(d.vzs) + 3 * (size_t)d.rec_cam[r0 + o];
+      load_rec(d, r0 + o, J[m], Q[m]);
+      const float4 v0 = vs[0], v1 = vs[1], v2 = vs[2];
+      const float pa[9] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x};
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
-        const float pa = d.s_cam[cam + a] * v[cam + a];
-        u[m][0] += J[0][a] * pa;
-        u[m][1] += J[1][a] * pa;
+        u[m][0] += J[m][0][a] * pa[a];
+        u[m][1] += J[m][1][a] * pa[a];
       }
 #pragma unroll
-      for (int j = 0; j < 3; ++j) c[j] += Q[0][j] * u[m][0] + Q[1][j] * u[m][1];
+      for (int j = 0; j < 3; ++j) c[j] += Q[m][0][j] * u[m][0] + Q[m][1][j] * u[m][1];
     }
   }
   int buf = 0;
@@ -2046,13 +2060,16 @@ __device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     if (o < k) {
-      float J[2][9], Q[2][3];
-      load_rec(d, obs0 + o, J, Q);
-      const float w0 = u[m][0] - (Q[0][0] * e[0] + Q[0][1] * e[1] + Q[0][2] * e[2]);
-      const float w1 = u[m][1] - (Q[1][0] * e[0] + Q[1][1] * e[1] + Q[1][2] * e[2]);
-      float* z = d.obsbuf + zoff + 9 * o;
+      if constexpr (!KEEP) load_rec(d, r0 + o, J[m], Q[m]);
+      const float w0 = u[m][0] - (Q[m][0][0] * e[0] + Q[m][0][1] * e[1] + Q[m][0][2] * e[2]);
+      const float w1 = u[m][1] - (Q[m][1][0] * e[0] + Q[m][1][1] * e[1] + Q[m][1][2] * e[2]);
+      float z[9];
 #pragma unroll
-      for (int a = 0; a < 9; ++a) z[a] = J[0][a] * w0 + J[1][a] * w1;
+      for (int a = 0; a < 9; ++a) z[a] = J[m][0][a] * w0 + J[m][1][a] * w1;
+      float4* out = reinterpret_cast<float4*>(d.obsbuf) + 3 * (size_t)(r0 + o);
+      out[0] = make_float4(z[0], z[1], z[2], z[3]);
+      out[1] = make_float4(z[4], z[5], z[6], z[7]);
+      out[2] = make_float4(z[8], 0.f, 0.f, 0.f);
     }
   }
 }
@@ -2060,14 +2077,21 @@ __device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane
 template <bool PCG>
 struct MatvecImplF {
   const Dev& d;
-  const float* v;
   template <int TEAM, int OPL>
-  __device__ void run(int slot, int lane) const { matvec_implicit<TEAM, OPL, PCG>(d, slot, lane, v); }
+  __device__ __forceinline__ void run(int slot, int lane) const { matvec_implicit<TEAM, OPL, PCG>(d, slot, lane); }
 };
 
 template <bool PCG>
-__global__ __launch_bounds__(WG) void k_matvec_implicit(Dev d, ImplGrid m, const float* v) {
-  impl_dispatch(m, MatvecImplF<PCG>{d, v});
+__global__ __launch_bounds__(WG) void k_matvec_implicit(Dev d, ImplGrid m) {
+  impl_dispatch(m, MatvecImplF<PCG>{d});
+}
+
+// vzs = S v (12 floats per camera, the pad stays zero) for a product outside PCG.
+__global__ __launch_bounds__(WG) void k_prescale(Dev d, const float* v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 9 * d.NC) return;
+  const int c = i / 9, a = i - 9 * c;
+  d.vzs[12 * c + a] = d.s_cam[i] * v[i];
 }
 
 // Back-substitution for one landmark: u = J_p p' (p' = S dx_p), c = Q1^T u, the
@@ -2081,7 +2105,7 @@ __device__ __forceinline__ void backsub_implicit(const Dev& d, int slot, int lan
   const int lm = d.slot_lm[slot];
   if (!d.active[prob]) return;  // uniform over the team
   const int k = d.slot_k[slot];
-  const int obs0 = d.slot_obs0[slot];
+  const int r0 = d.slot_zoff[slot];
   const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
   const float lam = (float)d.lambda[prob];
   float u[OPL][2];
@@ -2092,8 +2116,8 @@ __device__ __forceinline__ void backsub_implicit(const Dev& d, int slot, int lan
     u[m][0] = u[m][1] = 0.f;
     if (o < k) {
       float J[2][9], Q[2][3];
-      load_rec(d, obs0 + o, J, Q);
-      const int cam = 9 * d.obs_cam[obs0 + o];
+      load_rec(d, r0 + o, J, Q);
+      const int cam = 9 * d.rec_cam[r0 + o];
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
         const float pa = d.s_cam[cam + a] * d.vx[cam + a];
@@ -2112,8 +2136,8 @@ __device__ __forceinline__ void backsub_implicit(const Dev& d, int slot, int lan
     const int o = lane + TEAM * m;
     if (o < k) {
       float J[2][9], Q[2][3];
-      load_rec(d, obs0 + o, J, Q);
-      const float2 rv = reinterpret_cast<const float2*>(d.obsrec + (size_t)(obs0 + o) * REC_STRIDE + REC_R)[0];
+      load_rec(d, r0 + o, J, Q);
+      const float4 rv = rec_plane(d, 6)[r0 + o];
       const float w0 = u[m][0] - (Q[0][0] * c[0] + Q[0][1] * c[1] + Q[0][2] * c[2]);
       const float w1 = u[m][1] - (Q[1][0] * c[0] + Q[1][1] * c[1] + Q[1][2] * c[2]);
       s2[0] += w0 * w0 + w1 * w1;
@@ -2150,7 +2174,7 @@ __device__ __forceinline__ void backsub_implicit(const Dev& d, int slot, int lan
 struct BacksubImplF {
   const Dev& d;
   template <int TEAM, int OPL>
-  __device__ void run(int slot, int lane) const { backsub_implicit<TEAM, OPL>(d, slot, lane); }
+  __device__ __forceinline__ void run(int slot, int lane) const { backsub_implicit<TEAM, OPL>(d, slot, lane); }
 };
 
 __global__ __launch_bounds__(WG) void k_backsub_implicit(Dev d, ImplGrid m) { impl_dispatch(m, BacksubImplF{d}); }
@@ -2319,9 +2343,15 @@ static void launch_small(const Dev& d, const Launch& L, const ClassGrid& m, int 
 template <bool PCG>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
   if (d.implicit) {
+    // in PCG the update kernels keep vzs = S z; otherwise it is formed from v here
+    // (v == nullptr: already formed)
+    if (!PCG && v && d.NC) {
+      hipLaunchKernelGGL(k_prescale, dim3(nblocks(9 * d.NC, WG)), dim3(WG), 0, L.stream, d, v);
+      LAUNCH_CHECK();
+    }
     int n = 0;
     const ImplGrid m = impl_grid(L, &n);
-    if (n) hipLaunchKernelGGL(k_matvec_implicit<PCG>, dim3(n), dim3(WG), 0, L.stream, d, m, v);
+    if (n) hipLaunchKernelGGL(k_matvec_implicit<PCG>, dim3(n), dim3(WG), 0, L.stream, d, m);
     LAUNCH_CHECK();
     return hipSuccess;
   }
@@ -2430,7 +2460,15 @@ hipError_t launch_commit(const Dev& d, const Launch& L) {
   return hipSuccess;
 }
 
-hipError_t launch_matvec_timing(const Dev& d, const Launch& L) { return launch_matvec<false>(d, L, d.vz); }
+hipError_t launch_matvec_timing(const Dev& d, const Launch& L) {
+  return launch_matvec<false>(d, L, d.implicit ? nullptr : d.vz);
+}
+
+hipError_t launch_prescale_z(const Dev& d, const Launch& L) {
+  if (d.NC) hipLaunchKernelGGL(k_prescale, dim3(nblocks(9 * d.NC, WG)), dim3(WG), 0, L.stream, d, d.vz);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
 
 hipError_t launch_matvec_only(const Dev& d, const Launch& L, const float* v_scaled, float* out) {
   hipError_t e = launch_matvec<false>(d, L, v_scaled);
