@@ -46,9 +46,7 @@ METRIC = "time-to-1%-cost (s), QR blocks/s, PCG matvec HBM GB/s; learned vs bloc
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_lm_config{}.json")
 # HBM counter readings of the product per workload (valid for the kernels and
 # launch shapes they were taken with)
-TRAFFIC = {1: os.path.join(ROOT, "profiles", "matvec_traffic_ladybug.json"),
-           2: os.path.join(ROOT, "profiles", "matvec_traffic_batch256.json"),
-           3: os.path.join(ROOT, "profiles", "matvec_traffic_venice.json")}
+TRAFFIC_TAG = {1: "ladybug", 2: "batch256", 3: "venice"}  # profiles/matvec_traffic_<tag>_<blocks>.json
 KERNELS = os.path.join(ROOT, "paper_2103_01843_amd", "csrc", "kernels.hip")
 
 
@@ -230,10 +228,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default product launch shapes")
     ap.add_argument("--blocks", choices=["explicit", "implicit"], default="explicit",
-                    help="landmark blocks of the timed solves: explicit (the paper's stored blocks, default) or "
-                         "implicit (J_p and Q1 per observation)")
-    ap.add_argument("--no-implicit", action="store_true",
-                    help="skip the extra measurement of the implicit landmark blocks")
+                    help="landmark blocks of the timed solves: explicit (the paper's stored nullspace blocks "
+                         "Q2^T J_p, O(k^2) per landmark; default) or implicit (J_p and Q1 per observation, O(k))")
+    ap.add_argument("--no-other-blocks", action="store_true",
+                    help="skip the extra measurement of the other landmark-block form")
     ap.add_argument("--no-forcing", action="store_true",
                     help="skip the solve with the forcing-sequence PCG truncation (eta = 0.1)")
     ap.add_argument("--tuning", default=None, metavar="EDGE,ROWS,SIDE,SEP,BATCH,PERSIST",
@@ -277,6 +275,8 @@ def main():
         keys = ["rows_min_k", "huge_rows", "huge_side", "large_separate", "small_rows", "persist_wgs"]
         ctx.set_tuning(**dict(zip(keys, (int(x) for x in args.tuning.split(",")))))
         tuning = {"shape": ctx.get_tuning(), "autotuned": False}
+    elif blocks == 1:
+        tuning["note"] = "the launch shapes belong to the explicit-block product; the implicit product has one"
     elif not args.no_autotune:
         t0 = time.perf_counter()
         best, trials = ctx.autotune(reps=10)
@@ -338,8 +338,8 @@ def main():
     # the other landmark-block form on the same workload and start (implicit
     # blocks need no O(k^2) storage): timed solves and its product
     other = None
-    if not args.no_implicit and args.blocks == "explicit":
-        other = other_blocks_run(p, args, 1)
+    if not args.no_other_blocks:
+        other = other_blocks_run(p, args, 0 if blocks else 1)
 
     # time to 1% cost per problem (appendix A.2), f* over the runs (and the oracle where stored)
     gold = None
@@ -362,12 +362,12 @@ def main():
         ttt_all.append([time_to_tol(h[i], f_tau) for _, h in runs])
     # a batch reaches the threshold when its last problem does
     ttt = [max(t[s] for t in ttt_all) for s in range(len(runs))]
-    implicit_out = None
+    other_out = None
     if other:
         ttt_o = [max(time_to_tol(h[i], f_taus[i][2]) for i in range(p.n_problems)) for _, h in other["runs"]]
         ach = other["mv_bytes"] / (other["mv_ms"] * 1e-3) / 1e9 if other["mv_ms"] > 0 else None
-        implicit_out = {
-            "landmark_blocks": "implicit",
+        other_out = {
+            "landmark_blocks": "explicit" if blocks else "implicit",
             "time_to_1pct_cost_s": statistics.median(ttt_o),
             "ms_per_step": 1e3 * other["wall"] / args.steps,
             "final_costs": [sum(r.final_cost for r in reps) for reps, _ in other["runs"]],
@@ -405,8 +405,9 @@ def main():
     qr = prof["marginalize"]
     achieved = mv_bytes / (mv_ms * 1e-3) / 1e9 if mv_ms > 0 else None
     traffic, traffic_note = None, None
-    tfile = TRAFFIC.get(cfg)
-    if tfile and os.path.exists(tfile) and args.blocks == "explicit":
+    tfile = (os.path.join(ROOT, "profiles", f"matvec_traffic_{TRAFFIC_TAG[cfg]}_{args.blocks}.json")
+             if cfg in TRAFFIC_TAG else None)
+    if tfile and os.path.exists(tfile):
         with open(tfile) as f:
             tr = json.load(f)
         if tr.get("kernels_sha") == kernels_hash():  # counters of the current kernels only
@@ -468,7 +469,7 @@ def main():
         "roofline": roofline,
         "tuning": tuning,
         "forcing_sequence": forcing_out,
-        "implicit_blocks": implicit_out,
+        ("explicit_blocks" if blocks else "implicit_blocks"): other_out,
         "learned_vs_block_jacobi": learned_out,
         "cpu_baseline": cpu,
     }

@@ -411,7 +411,9 @@ int32_t sqrtba_set_tuning(sqrtba_ctx* ctx, const sqrtba_tuning* shape);
  * blocks, so this may run right after upload; it overwrites only scratch
  * (the product outputs).  best (may be NULL) receives the chosen shapes,
  * trials (may be NULL) up to max_trials records and *n_trials (may be NULL)
- * the number of candidates timed. */
+ * the number of candidates timed.  The shapes belong to the explicit-block
+ * product; with implicit landmark blocks only the current shape is timed (one
+ * trial) and kept. */
 int32_t sqrtba_autotune(sqrtba_ctx* ctx, int32_t reps, sqrtba_tuning* best, sqrtba_tuning_trial* trials,
                         int32_t max_trials, int32_t* n_trials);
 

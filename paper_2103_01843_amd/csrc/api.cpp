@@ -633,7 +633,7 @@ int upload(sqrtba_ctx* c) {
   TRY(upload_vec(c, d.slot_toff, h.slot_toff));
   if (d.implicit) {
     // records in slot order; the product writes 12 floats (3 float4) per record
-    std::vector<int32_t> rec0(h.NS), zpos(h.NO);
+    std::vector<int32_t> rec0(h.NS), zpos(h.NO), rcam(h.NO);
     int64_t r = 0;
     for (int64_t s = 0; s < h.NS; ++s) {
       rec0[s] = (int32_t)r;
@@ -641,10 +641,13 @@ int upload(sqrtba_ctx* c) {
     }
     for (int64_t q = 0; q < h.NO; ++q) {
       const int32_t j = h.cam_obs_idx[q], s = h.lm_slot[h.olm[j]];
-      zpos[q] = 12 * (rec0[s] + (j - h.slot_obs0[s]));
+      const int32_t ri = rec0[s] + (j - h.slot_obs0[s]);
+      zpos[q] = 12 * ri;
+      rcam[ri] = h.ocam[j];
     }
     TRY(upload_vec(c, d.slot_zoff, rec0));
     TRY(upload_vec(c, d.cam_zpos, zpos));
+    TRY(upload_vec(c, d.rec_cam, rcam));
   } else {
     TRY(upload_vec(c, d.slot_zoff, h.slot_zoff));
     TRY(upload_vec(c, d.cam_zpos, h.cam_zpos));
@@ -696,10 +699,10 @@ int upload(sqrtba_ctx* c) {
     const int p = h.slot_prob[sl];
     if (c->opt.landmark_blocks == 1) {
       // implicit: read the 24 Jacobian and Q1 floats and the camera index per
-      // observation and the 6 floats of P, write 9k per-observation outputs; the QR
-      // writes the 28-float records and the camera indices
+      // observation and the 6 floats of P, write 9k per-observation outputs; the
+      // QR writes the 28-float records
       c->mv_bytes[p] += 4.0 * (25.0 * k + 6.0 + 9.0 * k);
-      c->qr_bytes[p] += 4.0 * (29.0 * k + 12.0) + 12.0 * k + 16.0;
+      c->qr_bytes[p] += 4.0 * (28.0 * k + 12.0) + 12.0 * k + 16.0;
     } else {
       // matvec: read the 2k x 9k B rows, write 9k per-observation outputs
       c->mv_bytes[p] += 4.0 * (18.0 * k * k + 9.0 * k);
@@ -1949,14 +1952,18 @@ int32_t sqrtba_autotune(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, sqrtba
   };
   // bucket edge first (it decides which kernels run), then the shapes of the
   // kernels that do run
-  if (c->L.n45 > 0) TRY(try_field(&sqrtba_tuning::rows_min_k, {114, 61, 29}));
-  if (c->L.rows_n > 0) {
-    TRY(try_field(&sqrtba_tuning::huge_rows, {64, 128, 256, 1024}));
-    TRY(try_field(&sqrtba_tuning::huge_side, {0, 1}));
+  // (the shapes are those of the explicit-block product kernels; with implicit
+  // blocks only the current shape is timed)
+  if (!c->d.implicit) {
+    if (c->L.n45 > 0) TRY(try_field(&sqrtba_tuning::rows_min_k, {114, 61, 29}));
+    if (c->L.rows_n > 0) {
+      TRY(try_field(&sqrtba_tuning::huge_rows, {64, 128, 256, 1024}));
+      TRY(try_field(&sqrtba_tuning::huge_side, {0, 1}));
+    }
+    if (c->L.n45 > c->L.rows_n) TRY(try_field(&sqrtba_tuning::large_separate, {0, 1}));
+    TRY(try_field(&sqrtba_tuning::small_rows, {4, 8}));
+    TRY(try_field(&sqrtba_tuning::persist_wgs, {0, 1024, 2048, 4096}));
   }
-  if (c->L.n45 > c->L.rows_n) TRY(try_field(&sqrtba_tuning::large_separate, {0, 1}));
-  TRY(try_field(&sqrtba_tuning::small_rows, {4, 8}));
-  TRY(try_field(&sqrtba_tuning::persist_wgs, {0, 1024, 2048, 4096}));
   TRY(apply_tuning(c, cur));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (best) *best = cur;

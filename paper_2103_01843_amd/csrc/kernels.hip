@@ -511,7 +511,6 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
         rec[4 * P] = make_float4(J[16], J[17], q[0][0], q[0][1]);
         rec[5 * P] = make_float4(q[0][2], q[1][0], q[1][1], q[1][2]);
         rec[6 * P] = make_float4(rr[2 * m], rr[2 * m + 1], 0.f, 0.f);
-        d.rec_cam[d.slot_zoff[slot] + o] = d.obs_cam[obs0 + o];
       }
     }
     return;
@@ -1332,9 +1331,17 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
 #pragma unroll
     for (int j = 0; j < Q_UNROLL; ++j) {
       if (zp[j] >= 0) {
-        const float* src = d.obsbuf + zp[j];
+        if (d.implicit) {  // 16-byte aligned rows of 12 floats
+          const float4* s4 = reinterpret_cast<const float4*>(d.obsbuf + zp[j]);
+          const float4 a0 = s4[0], a1 = s4[1], a2 = s4[2];
+          acc[0] += a0.x; acc[1] += a0.y; acc[2] += a0.z; acc[3] += a0.w;
+          acc[4] += a1.x; acc[5] += a1.y; acc[6] += a1.z; acc[7] += a1.w;
+          acc[8] += a2.x;
+        } else {
+          const float* src = d.obsbuf + zp[j];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) acc[a] += src[a];
+          for (int a = 0; a < 9; ++a) acc[a] += src[a];
+        }
       }
     }
     if (more) {

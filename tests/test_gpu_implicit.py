@@ -136,6 +136,8 @@ def test_block_rows_are_not_stored_and_mode_is_fixed_after_upload():
         ctx.set_options(landmark_blocks=0)
     assert ei.value.status == -4
     ctx.set_options(pcg_forcing_eta=0.1)  # other options may change
+    best, trials = ctx.autotune(reps=2)  # the shapes do not apply: one trial, shape kept
+    assert len(trials) == 1 and best == ctx.get_tuning()
     ctx.close()
     with pytest.raises(SqrtBAError):
         gpu_context(p, landmark_blocks=2)
