@@ -49,6 +49,7 @@ struct HostData {
   std::vector<float> cam_stats;  // NC * 4 features of the camera's observation graph
   WorkClass wc[NUM_CLASSES];
   std::vector<int32_t> hjob;   // (slot, row block) pairs of the row-block product (capacity)
+  std::vector<int32_t> qjob;   // (slot, first row | end row << 16) chunks of the class-5 QR
   std::vector<int64_t> hz_off; // per slot with k >= ROWS_MIN_K, offset of its partial outputs
   int64_t hz_floats = 0;
   int64_t poolB = 0, poolT = 0;
@@ -377,6 +378,18 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
   }
   build_hjobs(nb, HUGE_ROWS_MIN, n45, nb.hjob);
   if (nb.hjob.size() / 2 > (size_t)INT32_MAX / 2) return fail(c, SQRTBA_E_UNSUPPORTED, "too many row blocks");
+  // QR of class 5 (explicit blocks) in row chunks of about QR_CHUNK_BYTES each,
+  // so that no single workgroup writes a whole multi-megabyte block
+  nb.qjob.clear();
+  for (int64_t sl = nb.wc[5].first_slot; sl < nb.wc[5].first_slot + nb.wc[5].slots; ++sl) {
+    const int64_t n = 2 * nb.slot_k[sl];
+    const int64_t rows = std::max<int64_t>(1, QR_CHUNK_BYTES / (4 * width_of_h(nb.slot_k[sl])));
+    for (int64_t r = 0; r < n; r += rows) {
+      nb.qjob.push_back((int32_t)sl);
+      nb.qjob.push_back((int32_t)(r | (std::min(n, r + rows) << 16)));
+    }
+  }
+  if (nb.qjob.size() / 2 > (size_t)INT32_MAX) return fail(c, SQRTBA_E_UNSUPPORTED, "too many QR chunks");
   // camera statistics for the learned preconditioner: observations, covisible
   // cameras (bitsets per problem), mean and max log k over the camera's landmarks
   nb.cam_stats.assign(4 * h.NC, 0.f);
@@ -452,7 +465,7 @@ uint64_t layout(const HostData& h, bool implicit, void* base, Dev* d) {
   uint64_t o_slm = f32(NS), o_sk = f32(NS), o_so = f32(NS), o_sp = f32(NS), o_sb = f64(NS), o_st = f64(NS);
   uint64_t o_sz = f32(NS), o_czp = f32(NO);
   uint64_t o_lms = f32(NL);
-  uint64_t o_hj = f32(h.hjob.size()), o_hzo = f64(h.hz_off.size()), o_zp = f32(h.hz_floats);
+  uint64_t o_qj = f32(h.qjob.size()), o_hj = f32(h.hjob.size()), o_hzo = f64(h.hz_off.size()), o_zp = f32(h.hz_floats);
   const uint64_t nB = implicit ? 0 : h.poolB, nT = implicit ? 0 : h.poolT, nrho = implicit ? 0 : 2 * NO;
   uint64_t o_pB = f32(nB), o_pT = f32(nT), o_lmd = f32(NS * LMD_STRIDE), o_rho = f32(nrho);
   uint64_t o_rec = f32(implicit ? 4 * (uint64_t)REC_PLANES * NO : 0), o_rcam = f32(implicit ? NO : 0);
@@ -480,7 +493,7 @@ uint64_t layout(const HostData& h, bool implicit, void* base, Dev* d) {
     t.slot_prob = at<int32_t>(base, o_sp); t.slot_boff = at<int64_t>(base, o_sb); t.slot_toff = at<int64_t>(base, o_st);
     t.slot_zoff = at<int32_t>(base, o_sz); t.cam_zpos = at<int32_t>(base, o_czp);
     t.lm_slot = at<int32_t>(base, o_lms);
-    t.hjob = at<int2>(base, o_hj); t.hz_off = at<int64_t>(base, o_hzo); t.zpart = at<float>(base, o_zp);
+    t.qjob = at<int2>(base, o_qj); t.hjob = at<int2>(base, o_hj); t.hz_off = at<int64_t>(base, o_hzo); t.zpart = at<float>(base, o_zp);
     t.poolB = at<float>(base, o_pB); t.poolT = at<float>(base, o_pT); t.lmd = at<float>(base, o_lmd);
     t.rhoB = implicit ? nullptr : at<float>(base, o_rho); t.s_cam = at<float>(base, o_sc);
     if (implicit) { t.poolB = nullptr; t.poolT = nullptr; }
@@ -654,6 +667,7 @@ int upload(sqrtba_ctx* c) {
   }
   TRY(upload_vec(c, d.lm_slot, h.lm_slot));
   TRY(upload_vec(c, reinterpret_cast<int32_t*>(d.hjob), h.hjob));
+  TRY(upload_vec(c, reinterpret_cast<int32_t*>(d.qjob), h.qjob));
   TRY(upload_vec(c, d.hz_off, h.hz_off));
   TRY(upload_vec(c, d.cam_stats, h.cam_stats));
   c->active.assign(h.P, 1);
@@ -661,6 +675,7 @@ int upload(sqrtba_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->L.stream = c->stream;
   for (int i = 0; i < NUM_CLASSES; ++i) c->L.wc[i] = h.wc[i];
+  c->L.qjobs = (int)(h.qjob.size() / 2);
   // default launch shapes (the autotuner may replace them): the row-block
   // kernel takes class 5 in 64-row blocks, class 4 stays in the main launch
   // unless it is large

@@ -76,6 +76,7 @@ struct Dev {
   int32_t* lm_slot;    // NL, -1 when inactive
   // row-block product of the largest landmarks: one job per block of
   // Launch::huge_rows rows (x: slot, y: row block), partial outputs per block
+  int2* qjob;     // class-5 QR row chunks: (slot, first row | end row << 16)
   int2* hjob;
   int64_t* hz_off;  // per slot with k >= 29 (a prefix of the slots): offset of its partials in zpart
   float* zpart;
@@ -138,6 +139,8 @@ struct WorkClass {
 // Smallest row block of the row-block product (sizes the job list and the
 // partial outputs); the tuned block size is a multiple of it.
 enum { HUGE_ROWS_MIN = 64 };
+// Bytes of rotated rows per workgroup of the class-5 QR (explicit blocks).
+enum { QR_CHUNK_BYTES = 2 << 20 };
 // Smallest bucket edge of the row-block product (sizes its slot range).
 enum { ROWS_MIN_K = 29 };
 
@@ -152,6 +155,7 @@ struct Launch {
   int large_sep;   // the rest of k >= 29 as its own launch (else inside the small-class launch)
   int mv_rbs;      // row-batch set of the small classes (0: 4 rows, 1: 8 rows)
   int persist;     // > 0: the small-class launch is persistent with this many workgroups
+  int qjobs;       // row-chunk jobs of the class-5 QR (explicit blocks)
   hipStream_t stream;
   hipStream_t side;   // second stream for the largest landmarks (may be null)
   hipEvent_t fork, join;

@@ -307,9 +307,12 @@ __host__ __device__ constexpr int marg_stride(int kmax) { return (26 * kmax + 3)
 // LDS floats of the reductions of a workgroup team (two buffers of 4 x 8).
 constexpr int MARG_RED = 64;
 
+// Rows [row_lo, row_hi) of the rotated block are written (the whole block for
+// 0, >= 2k); the landmark record and the residual rows are written by the
+// chunk with row_lo = 0.
 template <int TEAM, int KMAX, bool IMPLICIT>
 __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane, float* lds, float* red,
-                                                const uint8_t* mask) {
+                                                const uint8_t* mask, int row_lo = 0, int row_hi = 1 << 30) {
   constexpr int OPL = (KMAX + TEAM - 1) / TEAM;  // observations per lane
   const int prob = d.slot_prob[slot];
   if (mask && !mask[prob]) return;
@@ -446,16 +449,20 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
   const float mr1 = T01 * wr0 + T11 * wr1;
   const float mr2 = T02 * wr0 + T12 * wr1 + T22 * wr2;
   float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const bool head = row_lo == 0;  // this chunk writes the landmark record
 #pragma unroll
   for (int i = 0; i < 2 * OPL; ++i) {
     const int gi = row_of(i);
     if (gi < n) {
       const float3 vv = Vr[i];
       const float val = rr[i] - (vv.x * mr0 + vv.y * mr1 + vv.z * mr2);
-      if (gi < 3) lmd[LMD_QR + gi] = val;
-      else if (!IMPLICIT) d.rhoB[2 * (size_t)obs0 + (gi - 3)] = val;
+      if (head) {
+        if (gi < 3) lmd[LMD_QR + gi] = val;
+        else if (!IMPLICIT) d.rhoB[2 * (size_t)obs0 + (gi - 3)] = val;
+      }
       V[gi] = make_float4(vv.x, vv.y, vv.z, 0.f);
     }
+    if (!head) continue;
     // R1: the diagonal is alpha_j (or the untouched entry when |x| = 0), the
     // rest of row j comes from its owner
     if (gi == 0) {
@@ -469,7 +476,7 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
       lmd[LMD_R + 5] = nrms[2] > 0.f ? alph[2] : Rrow[2][2];
     }
   }
-  if (lane == 0) {
+  if (lane == 0 && head) {
     lmd[LMD_SL + 0] = sl0; lmd[LMD_SL + 1] = sl1; lmd[LMD_SL + 2] = sl2;
   }
   team_sync<TEAM>();  // V and the pose Jacobians of every row, for phase 4
@@ -549,7 +556,8 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
       }
     }
   }
-  for (int i = 0; i < n; ++i) {
+  const int i_end = row_hi < n ? row_hi : n;
+  for (int i = row_lo; i < i_end; ++i) {
     const float4 vv = V[i];
     float4* row = reinterpret_cast<float4*>(i < 3 ? outT + (size_t)i * W : outB + (size_t)(i - 3) * W);
 #pragma unroll
@@ -1701,6 +1709,16 @@ __global__ __launch_bounds__(WG) void k_marginalize_huge(Dev d, int slot0, const
   marginalize_one<256, class_kmax(5), IMPLICIT>(d, slot0 + blockIdx.x, threadIdx.x, lds, red, mask);
 }
 
+// Explicit blocks of class 5 in row chunks (qjob: slot, first row | end row << 16):
+// a block of up to 1024 x 4608 floats is written by several workgroups, each
+// repeating the landmark's QR (O(k)) and writing its rows.
+__global__ __launch_bounds__(WG) void k_marginalize_chunks(Dev d, const uint8_t* mask) {
+  __shared__ __align__(16) float lds[marg_stride(class_kmax(5))];
+  __shared__ float red[MARG_RED];
+  const int2 j = d.qjob[blockIdx.x];
+  marginalize_one<256, class_kmax(5), false>(d, j.x, threadIdx.x, lds, red, mask, j.y & 0xffff, j.y >> 16);
+}
+
 struct DampF {
   const Dev& d;
   const uint8_t* mask;
@@ -2265,8 +2283,7 @@ hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask
       hipLaunchKernelGGL(k_marginalize_huge<true>, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d,
                          w[5].first_slot, mask);
     else
-      hipLaunchKernelGGL(k_marginalize_huge<false>, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d,
-                         w[5].first_slot, mask);
+      hipLaunchKernelGGL(k_marginalize_chunks, dim3(L.qjobs), dim3(WG), 0, side ? L.side : L.stream, d, mask);
   }
   LAUNCH_CHECK();
   if (n) {

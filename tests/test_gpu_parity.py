@@ -103,6 +103,40 @@ def test_landmark_block_invariants(case, lam):
     assert worst < 1e-4, worst
 
 
+@pytest.mark.parametrize("lam", [0.0, 1e-4])
+def test_largest_landmarks_in_row_chunks(lam):
+    """Landmarks with k = 170 .. 512 observations: the QR of a block wider than one
+    workgroup's chunk of rows (2 MiB) is written by several workgroups; every
+    chunk must carry the same rotation.  Same invariants as above (eq. red_H /
+    red_b), on every landmark, plus R1^T R1 = J_l^T J_l."""
+    rng = np.random.default_rng(21)
+    p = make_ring_problem(rng, 520, 8, lambda r, n: np.array([170, 171, 300, 512, 2, 5, 113, 114])[:n])
+    bk, st, lin = oracle_lin(p)
+    ctx = gpu_context(p)
+    ctx.linearize()
+    ctx.marginalize()
+    if lam > 0:
+        ctx.damp(lam)
+    sc, _ = ctx.debug_scales()
+    worst = 0.0
+    for l in np.nonzero(bk.lm_active)[0]:
+        cams, H, b, Jp, Jl, r = landmark_sc_contribution(lin, l, lam)
+        k, blk, fac = ctx.debug_block(int(l))
+        assert k == len(cams)
+        rows = blk[3:] if lam > 0 else blk[3:3 + 2 * k - 3]
+        s = np.concatenate([sc[c] for c in cams]).astype(np.float64)
+        B = rows[:, :9 * k].astype(np.float64) * s[None, :]
+        rho = rows[:, 9 * k + 3].astype(np.float64)
+        eH = np.linalg.norm(B.T @ B - H) / max(np.linalg.norm(H), 1e-30)
+        tol_b = 1e-4 * np.linalg.norm(b) + 64 * 2.0 ** -24 * np.linalg.norm(Jp, 2) * np.linalg.norm(r)
+        eb = 1e-4 * np.linalg.norm(B.T @ rho - b) / tol_b
+        worst = max(worst, eH, eb)
+        R1 = blk[:3, 9 * k:9 * k + 3].astype(np.float64)
+        np.testing.assert_allclose(R1.T @ R1, Jl.T @ Jl, atol=2e-5 * np.abs(Jl.T @ Jl).max())
+    ctx.close()
+    assert worst < 1e-4, worst
+
+
 def test_orthogonal_transform_preserves_columns(case):
     """Undamped block rows are Q^T [J_p | J_l S_l | r]: column Gram matrices are preserved."""
     p, bk, st, lin, ctx = case
