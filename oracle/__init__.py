@@ -10,10 +10,12 @@ reduced system, so the oracle forms the damped normal equations (Sec. 4.1,
 eq. normal_eq), reduces them with an explicit Schur complement (Sec. 4.2,
 eq. red_normal_eq, back-substitution eq. backsub_sc), solves the reduced
 camera system with a dense Cholesky factorization or block-Jacobi PCG
-(Sec. 5.4), and drives it with Levenberg-Marquardt (Sec. 6.1).  It shares no
+(Sec. 5.4), and drives it with Levenberg-Marquardt (Sec. 6.1), optionally with
+the Huber loss of the experiments applied by IRLS (Sec. 6.2, ``robust``).  It shares no
 code with the HIP path; only the input generator ``bal_synth`` serves both.
 
-Readings of points the paper leaves open are listed in ``oracle/readings.py``.
+Readings of points the paper leaves open are stated in the docstrings of the
+modules that implement them.
 """
 
 from .camera import (  # noqa: F401
@@ -39,3 +41,4 @@ from .normal_equations import (  # noqa: F401
 from .solvers import dense_spd_solve, block_jacobi_blocks, pcg, quadratic_model  # noqa: F401
 from .lm import LMOptions, LMResult, lm_solve, lm_attempt  # noqa: F401
 from .profile import cost_threshold, time_to_tolerance  # noqa: F401
+from .robust import huber_terms, huber_weights  # noqa: F401

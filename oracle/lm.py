@@ -11,6 +11,8 @@ with lambda clamped to [1e-16, 1e32] (reaching the top ends the solve).
 Every attempt, accepted or rejected, counts as one iteration.  After an
 accepted step the solve stops if (E_old - E_new) / E_old < func_tol.
 The expected reduction is the undamped linear model's, E - |r + J dx|^2.
+With a Huber loss (huber_delta, Sec. 6.2) E is the robust cost of
+oracle.robust and the linear model is that of the reweighted rows (IRLS).
 """
 
 from __future__ import annotations
@@ -25,6 +27,7 @@ from .bookkeeping import Bookkeeping, build_bookkeeping
 from .camera import CameraState, apply_update, bal_from_state, project_residuals, state_from_bal
 from .normal_equations import (Linearization, back_substitute, linearize, model_decrease,
                                reduced_camera_system)
+from .robust import huber_terms
 from .solvers import block_jacobi_blocks, dense_spd_solve, pcg
 
 
@@ -36,6 +39,7 @@ class LMOptions:
     pcg_tol: float = 1e-6
     pcg_max_iters: int = 500
     pcg_eta: float = 0.0  # > 0: also the Nash-Sofer forcing test of oracle.solvers.pcg
+    huber_delta: Optional[float] = None  # Huber loss parameter in pixels (None: squared loss)
     solver: str = "pcg"  # "pcg" (block-Jacobi) or "dense" (Cholesky)
     lambda_min: float = 1e-16
     lambda_max: float = 1e32
@@ -56,10 +60,13 @@ class LMResult:
         return bal_from_state(self.state)
 
 
-def cost_of(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray) -> float:
+def cost_of(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray,
+            huber_delta: Optional[float] = None) -> float:
     uv = np.asarray(obs_uv, dtype=np.float64)[bk.obs_perm]
     r = project_residuals(state, bk.ci, bk.pi, uv)
-    return float(np.sum(r * r))
+    if huber_delta is None:
+        return float(np.sum(r * r))
+    return float(np.sum(huber_terms(np.sum(r * r, axis=1), huber_delta)))
 
 
 def lm_attempt(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray, lin: Linearization,
@@ -78,7 +85,7 @@ def lm_attempt(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray, lin: Lin
     dp = dxp.reshape(lin.n_cams, 9) * lin.sp
     dl = dxl.reshape(lin.n_points, 3) * lin.sl
     new_state = apply_update(state, dp, dl)
-    new_cost = cost_of(new_state, bk, obs_uv)
+    new_cost = cost_of(new_state, bk, obs_uv, opts.huber_delta)
     return {"dxp_scaled": dxp, "dxl_scaled": dxl, "dxp": dp, "dxl": dl, "pred": pred,
             "new_state": new_state, "new_cost": new_cost, "pcg_iters": iters, "rel_res": rel,
             "pcg_status": status, "rs": rs, "pcg": pres}
@@ -92,7 +99,7 @@ def lm_solve(cameras: np.ndarray, points: np.ndarray, obs_cam: np.ndarray, obs_p
         bk = build_bookkeeping(cameras.shape[0], points.shape[0], obs_cam, obs_pt, obs_uv)
     state = state_from_bal(cameras, points)
     t0 = time.perf_counter()
-    lin = linearize(state, bk, obs_uv)
+    lin = linearize(state, bk, obs_uv, opts.huber_delta)
     E = lin.cost
     res = LMResult(state, E, E, 0, "max_iters")
     lam, nu = opts.lambda0, 2.0
@@ -114,7 +121,7 @@ def lm_solve(cameras: np.ndarray, points: np.ndarray, obs_cam: np.ndarray, obs_p
             if rel_dec < opts.func_tol:
                 res.status = "func_tol"
                 break
-            lin = linearize(state, bk, obs_uv)
+            lin = linearize(state, bk, obs_uv, opts.huber_delta)
         else:
             lam = lam * nu
             nu = 2.0 * nu

@@ -13,6 +13,11 @@ By Sec. 4.4 (eq. red_H, red_b, and the closing remark on the damped problem)
 this is exactly the reduced camera system that nullspace marginalization
 produces, so it is the reference for the GPU path.
 
+With a Huber loss (Sec. 6.2, oracle.robust) the residual and Jacobian rows of
+each observation are reweighted by sqrt(rho'(|r_o|^2)) at the linearization
+point (IRLS) and the cost is sum_o rho(|r_o|^2); everything below then works on
+the reweighted rows.
+
 Column scaling (Sec. 5.4): every column of the full Jacobian is scaled to
 unit norm, J~ = J S with s_c = 1 / |J_c| (a zero column keeps s_c = 1).  The
 damping matrix is D^2 = diag(J~^T J~) (Sec. 4.1), which is the identity after
@@ -26,8 +31,11 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.sparse as sp
 
+from typing import Optional
+
 from .bookkeeping import Bookkeeping
 from .camera import CameraState, linearize_observations
+from .robust import huber_terms, huber_weights
 
 
 @dataclass
@@ -56,12 +64,19 @@ def column_scales(Jp: np.ndarray, Jl: np.ndarray, ci: np.ndarray, pi: np.ndarray
     return sp_, sl_
 
 
-def linearize(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray) -> Linearization:
+def linearize(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray,
+              huber_delta: Optional[float] = None) -> Linearization:
     uv = np.asarray(obs_uv, dtype=np.float64)[bk.obs_perm]
     r, Jp, Jl = linearize_observations(state, bk.ci, bk.pi, uv)
+    if huber_delta is None:
+        cost = float(np.sum(r * r))
+    else:
+        s = np.sum(r * r, axis=1)
+        cost = float(np.sum(huber_terms(s, huber_delta)))
+        sw = np.sqrt(huber_weights(s, huber_delta))
+        r, Jp, Jl = r * sw[:, None], Jp * sw[:, None, None], Jl * sw[:, None, None]
     sp_, sl_ = column_scales(Jp, Jl, bk.ci, bk.pi, bk.n_cams, bk.n_points)
-    return Linearization(r, Jp, Jl, bk.ci, bk.pi, bk.n_cams, bk.n_points,
-                         float(np.sum(r * r)), sp_, sl_)
+    return Linearization(r, Jp, Jl, bk.ci, bk.pi, bk.n_cams, bk.n_points, cost, sp_, sl_)
 
 
 def scaled_jacobian_sparse(lin: Linearization):
