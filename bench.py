@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 FORCING_ETA = 0.1  # the paper's CG truncation (Sec. 6.1, as in Ceres)
+HUBER_DELTA = 1.0  # the paper's robust loss parameter in pixels (Sec. 6.2)
 WORKLOADS = {
     1: "ladybug-like: 500 cameras on a forward trajectory, 100k landmarks, k = 2 + Geom(1/3) clamped to 50, "
        "BAL camera model, 1 px noise",
@@ -44,6 +45,7 @@ WORKLOADS = {
 }
 METRIC = "time-to-1%-cost (s), QR blocks/s, PCG matvec HBM GB/s; learned vs block-Jacobi"
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_lm_config{}.json")
+GOLDEN_HUBER = os.path.join(ROOT, "tests", "golden", "oracle_lm_huber_config{}.json")
 # HBM counter readings of the product per workload (valid for the kernels and
 # launch shapes they were taken with)
 TRAFFIC_TAG = {1: "ladybug", 2: "batch256", 3: "venice"}  # profiles/matvec_traffic_<tag>_<blocks>.json
@@ -234,6 +236,8 @@ def main():
                     help="skip the extra measurement of the other landmark-block form")
     ap.add_argument("--no-forcing", action="store_true",
                     help="skip the solve with the forcing-sequence PCG truncation (eta = 0.1)")
+    ap.add_argument("--no-huber", action="store_true",
+                    help="skip the solve with the Huber loss (delta = 1 px, IRLS)")
     ap.add_argument("--tuning", default=None, metavar="EDGE,ROWS,SIDE,SEP,BATCH,PERSIST",
                     help="fixed product bucket edge and launch shapes (rows_min_k, huge_rows, huge_side, "
                          "large_separate, small_rows, persist_wgs) instead of autotuning, e.g. for counter runs "
@@ -325,6 +329,21 @@ def main():
         ctx.set_options(pcg_forcing_eta=0.0)
         log(f"forcing sequence: {max(r.iterations for r in freps)} attempts, "
             f"{sum(r.total_pcg_iters for r in freps)} PCG iterations, final cost {sum(r.final_cost for r in freps):.6g}")
+    # the paper's experimental loss (Huber, 1 px, by IRLS) from the same start
+    huber = None
+    if not args.no_huber:
+        ctx.set_options(huber_delta=HUBER_DELTA)
+        ctx.restore_state()
+        torch.cuda.synchronize()
+        t0h = time.perf_counter()
+        hreps = ctx.lm_solve()
+        torch.cuda.synchronize()
+        huber = {"reports": hreps, "history": [ctx.history(i) for i in range(p.n_problems)],
+                 "wall_s": time.perf_counter() - t0h}
+        ctx.set_options(huber_delta=0.0)
+        log(f"huber loss: {max(r.iterations for r in hreps)} attempts, {sum(r.total_pcg_iters for r in hreps)} "
+            f"PCG iterations, robust cost {sum(r.initial_cost for r in hreps):.6g} -> "
+            f"{sum(r.final_cost for r in hreps):.6g}, {1e3 * huber['wall_s']:.1f} ms")
     learned = None
     if not args.no_learned:
         try:
@@ -385,6 +404,27 @@ def main():
             "lm_attempts": max(r.iterations for r in forcing["reports"]),
             "pcg_iters": sum(r.total_pcg_iters for r in forcing["reports"]),
             "final_cost": sum(r.final_cost for r in forcing["reports"]),
+        }
+    huber_out = None
+    if huber:
+        hgold = None
+        if os.path.exists(GOLDEN_HUBER.format(cfg)) and p.n_problems == 1:
+            with open(GOLDEN_HUBER.format(cfg)) as f:
+                hgold = json.load(f)
+        h_ttt = []
+        for i in range(p.n_problems):
+            r = huber["reports"][i]
+            fstar = min([r.final_cost] + ([hgold["final_cost"]] if hgold else []))
+            h_ttt.append(time_to_tol(huber["history"][i], fstar + 0.01 * (r.initial_cost - fstar)))
+        huber_out = {
+            "delta_px": HUBER_DELTA,
+            "time_to_1pct_cost_s": max(h_ttt),
+            "ms_per_solve": 1e3 * huber["wall_s"],
+            "lm_attempts": max(r.iterations for r in huber["reports"]),
+            "pcg_iters": sum(r.total_pcg_iters for r in huber["reports"]),
+            "initial_cost": sum(r.initial_cost for r in huber["reports"]),
+            "final_cost": sum(r.final_cost for r in huber["reports"]),
+            "oracle_final_cost": hgold["final_cost"] if hgold else None,
         }
     learned_out = None
     if learned:
@@ -469,6 +509,7 @@ def main():
         "roofline": roofline,
         "tuning": tuning,
         "forcing_sequence": forcing_out,
+        "huber_loss": huber_out,
         ("explicit_blocks" if blocks else "implicit_blocks"): other_out,
         "learned_vs_block_jacobi": learned_out,
         "cpu_baseline": cpu,

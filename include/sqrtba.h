@@ -99,6 +99,14 @@ typedef struct {
                               (eq. red_H) at O(k) memory and traffic per landmark.  Chosen
                               before the workspace is sized; sqrtba_set_options refuses to
                               change it after upload (SQRTBA_E_STATE). */
+  double huber_delta;    /* 0 (default): squared loss, E = sum |r_o|^2.  > 0: the Huber loss of
+                            Sec. 6.2 with this parameter in pixels, applied by IRLS: per
+                            observation s = |r_o|^2, E = sum rho(s) with rho(s) = s for
+                            s <= delta^2 and 2 delta sqrt(s) - delta^2 beyond, and at every
+                            linearization the observation's residual and Jacobian rows are
+                            scaled by sqrt(rho'(s)) = sqrt(min(1, delta / |r_o|)).  Costs,
+                            reports and histories are then robust costs; the model decrease is
+                            the reweighted linear model's. */
 } sqrtba_options;
 
 typedef struct {
@@ -136,8 +144,9 @@ void sqrtba_default_options(sqrtba_options* opt);
 int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_stream);
 
 /* Replace the options of an existing context (same validation as create:
- * SQRTBA_E_INVALID on negative limits, lambda0 <= 0, pcg_check_every < 1 or a
- * negative or non-finite pcg_forcing_eta; the context is then unchanged).
+ * SQRTBA_E_INVALID on negative limits, lambda0 <= 0, pcg_check_every < 1, a
+ * negative or non-finite pcg_forcing_eta or huber_delta; the context is then
+ * unchanged).
  * Takes effect from the next call. */
 int32_t sqrtba_set_options(sqrtba_ctx* ctx, const sqrtba_options* opt);
 

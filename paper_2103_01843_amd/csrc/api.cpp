@@ -627,6 +627,7 @@ int upload(sqrtba_ctx* c) {
   layout(h, c->opt.landmark_blocks == 1, c->arena.base, &d);
   d.pcg_tol = (float)c->opt.pcg_rel_tol;
   d.pcg_eta = (float)c->opt.pcg_forcing_eta;
+  d.huber = (float)c->opt.huber_delta;
   HIP_TRY(c, hipMemsetAsync(c->arena.base, 0, c->arena.bytes, c->stream));
   TRY(upload_state(c));
   TRY(upload_vec(c, d.obs_cam, h.ocam));
@@ -1241,12 +1242,14 @@ void sqrtba_default_options(sqrtba_options* o) {
   o->use_graph = 1;
   o->pcg_forcing_eta = 0.0;
   o->landmark_blocks = 0;
+  o->huber_delta = 0.0;
 }
 
 static bool valid_options(const sqrtba_options& o) {
   return o.pcg_max_iters >= 0 && o.max_lm_iters >= 0 && o.lambda0 > 0 && o.pcg_check_every >= 1 &&
          std::isfinite(o.pcg_forcing_eta) && o.pcg_forcing_eta >= 0.0 &&
-         (o.landmark_blocks == 0 || o.landmark_blocks == 1);
+         (o.landmark_blocks == 0 || o.landmark_blocks == 1) && std::isfinite(o.huber_delta) &&
+         o.huber_delta >= 0.0;
 }
 
 int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_stream) {
@@ -1284,6 +1287,7 @@ int32_t sqrtba_set_options(sqrtba_ctx* c, const sqrtba_options* opt) {
   c->opt = *opt;
   c->d.pcg_tol = (float)c->opt.pcg_rel_tol;
   c->d.pcg_eta = (float)c->opt.pcg_forcing_eta;
+  c->d.huber = (float)c->opt.huber_delta;
   if (c->graph) {  // captured launches hold the old Dev values
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;

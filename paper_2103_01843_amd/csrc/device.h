@@ -129,6 +129,7 @@ struct Dev {
   float4* pts_snap;
   float pcg_tol;
   float pcg_eta;     // > 0: Nash-Sofer truncation of PCG
+  float huber;       // Huber parameter in pixels (0: squared loss)
 };
 
 struct WorkClass {

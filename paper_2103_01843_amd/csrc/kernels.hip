@@ -147,11 +147,26 @@ __device__ __forceinline__ void project(const Cam& C, float X0, float X1, float 
   }
 }
 
+// Huber loss by IRLS (delta > 0; delta = 0 is the squared loss): for the
+// observation's s = |r|^2 the cost term rho(s) (s up to delta^2, then
+// 2 delta sqrt(s) - delta^2) and the row weight sqrt(rho'(s)) =
+// sqrt(min(1, delta / |r|)) that scales its residual and Jacobian rows.
+__device__ __forceinline__ float robust_term(float s, float delta, float& sqrt_w) {
+  if (delta <= 0.f || s <= delta * delta) {
+    sqrt_w = 1.0f;
+    return s;
+  }
+  const float n = sqrtf(s);
+  sqrt_w = sqrtf(delta / n);
+  return 2.0f * delta * n - delta * delta;
+}
+
 // ---------------------------------------------------- kernel (a): per camera
 
-// One wavefront per camera: cost (FP64 sum of FP32 squared residuals) and,
-// with JAC, the unit-norm scale of each of the camera's 9 Jacobian columns
-// (1 / column norm; an empty column keeps scale 1).
+// One wavefront per camera: cost (FP64 sum of the FP32 per-observation terms,
+// |r|^2 or the Huber rho) and, with JAC, the unit-norm scale of each of the
+// camera's 9 (reweighted) Jacobian columns (1 / column norm; an empty column
+// keeps scale 1).
 template <bool JAC>
 __global__ __launch_bounds__(64) void k_cam_linearize(Dev d, const float* __restrict__ cam,
                                                       const float4* __restrict__ pts, const uint8_t* mask) {
@@ -171,10 +186,12 @@ __global__ __launch_bounds__(64) void k_cam_linearize(Dev d, const float* __rest
     const float2 uv = d.obs_uv[o];
     float r[2], Jp[2][9], Jl[2][3];
     project<JAC>(C, X.x, X.y, X.z, uv.x, uv.y, r, Jp, Jl);
-    cost += (double)(r[0] * r[0] + r[1] * r[1]);
+    float sw;
+    cost += (double)robust_term(r[0] * r[0] + r[1] * r[1], d.huber, sw);
     if constexpr (JAC) {
+      const float w = sw * sw;
 #pragma unroll
-      for (int j = 0; j < 9; ++j) n2[j] += Jp[0][j] * Jp[0][j] + Jp[1][j] * Jp[1][j];
+      for (int j = 0; j < 9; ++j) n2[j] += w * (Jp[0][j] * Jp[0][j] + Jp[1][j] * Jp[1][j]);
     }
   }
   cost = wave_sum_d(cost);
@@ -341,6 +358,22 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
       const float2 uv = d.obs_uv[obs0 + o];
       float r[2], Jp[2][9], Jl[2][3];
       project<true>(C, X.x, X.y, X.z, uv.x, uv.y, r, Jp, Jl);
+      float sw;
+      (void)robust_term(r[0] * r[0] + r[1] * r[1], d.huber, sw);
+      if (sw != 1.0f) {  // Huber IRLS: the observation's rows scaled by sqrt(w)
+        r[0] *= sw;
+        r[1] *= sw;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+          Jp[0][j] *= sw;
+          Jp[1][j] *= sw;
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          Jl[0][j] *= sw;
+          Jl[1][j] *= sw;
+        }
+      }
 #pragma unroll
       for (int j = 0; j < 9; ++j) {
         Jpc[18 * o + j] = Jp[0][j];
@@ -1865,6 +1898,14 @@ __global__ __launch_bounds__(WG) void k_debug_lin(Dev d, float* r, float* Jp, fl
   const float2 uv = d.obs_uv[o];
   float rr[2], J[2][9], L[2][3];
   project<true>(C, X.x, X.y, X.z, uv.x, uv.y, rr, J, L);
+  float sw;  // the rows the QR consumes (Huber IRLS weight applied)
+  (void)robust_term(rr[0] * rr[0] + rr[1] * rr[1], d.huber, sw);
+  rr[0] *= sw;
+  rr[1] *= sw;
+  for (int a = 0; a < 2; ++a) {
+    for (int b = 0; b < 9; ++b) J[a][b] *= sw;
+    for (int b = 0; b < 3; ++b) L[a][b] *= sw;
+  }
   r[2 * (size_t)o] = rr[0];
   r[2 * (size_t)o + 1] = rr[1];
   for (int a = 0; a < 2; ++a) {

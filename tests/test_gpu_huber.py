@@ -1,0 +1,128 @@
+"""Huber loss by IRLS (option huber_delta, Sec. 6.2) against the FP64 oracle.
+
+Same bar as the squared loss: the reweighted per-observation residuals to
+1e-4 px and Jacobians to 1e-4 relative, the robust cost and column scales to
+1e-5, the dense reduced camera system and right-hand side to 1e-4 relative
+(Frobenius), the back-substitution and model decrease from the oracle's exact
+pose step to 1e-4, the LM final robust cost to 1e-3 of the oracle's Huber LM
+and to 1e-5 of the oracle's robust cost at the GPU's final state; both
+landmark-block forms.  The delta of the tests is 1 px, the paper's; at the
+perturbed start most observations lie beyond it and a few percent inside.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.lm import cost_of
+from bal_synth import make_config
+
+from gpu_util import gpu_context, mixed_problem
+
+pytestmark = pytest.mark.gpu
+
+DELTA = 1.0
+
+
+@pytest.fixture(scope="module", params=["tiny", "mixed"])
+def case(request):
+    p = make_config(0) if request.param == "tiny" else mixed_problem()
+    bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)
+    st = oracle.state_from_bal(p.cameras, p.points)
+    lin = oracle.linearize(st, bk, p.obs_uv, huber_delta=DELTA)
+    ctx = gpu_context(p, huber_delta=DELTA)
+    yield p, bk, st, lin, ctx
+    ctx.close()
+
+
+def test_reweighted_linearization_cost_and_scales(case):
+    p, bk, st, lin, ctx = case
+    plain = oracle.linearize(st, bk, p.obs_uv)
+    beyond = np.mean(np.sum(plain.r ** 2, axis=1) > DELTA ** 2)
+    assert 0.01 < beyond < 0.99, beyond  # both branches of the loss are exercised
+    r, Jp, Jl = ctx.debug_linearization()
+    assert np.abs(r - lin.r).max() <= 1e-4
+    n = len(r)
+    ep = np.linalg.norm((Jp - lin.Jp).reshape(n, -1), axis=1) / np.linalg.norm(lin.Jp.reshape(n, -1), axis=1)
+    el = np.linalg.norm((Jl - lin.Jl).reshape(n, -1), axis=1) / np.linalg.norm(lin.Jl.reshape(n, -1), axis=1)
+    assert ep.max() < 1e-4 and el.max() < 1e-4
+    cost = ctx.linearize()[0]
+    assert abs(cost - lin.cost) <= 1e-5 * lin.cost, (cost, lin.cost)
+    assert lin.cost < plain.cost
+    ctx.marginalize()
+    sc, sp = ctx.debug_scales()
+    np.testing.assert_allclose(sc, lin.sp, rtol=1e-5)
+
+
+def test_reduced_system_and_back_substitution(case):
+    p, bk, st, lin, ctx = case
+    lam = 1e-4
+    ctx.linearize()
+    ctx.marginalize()
+    ctx.damp(lam)
+    rs = oracle.reduced_camera_system(lin, lam)
+    N = rs.H.shape[0]
+    Hg = ctx.debug_rcs_matvec(np.eye(N, dtype=np.float32)).astype(np.float64)
+    assert np.linalg.norm(Hg - rs.H) <= 1e-4 * np.linalg.norm(rs.H)
+    bg = ctx.debug_rhs().astype(np.float64)
+    assert np.linalg.norm(bg - rs.b) <= 1e-4 * np.linalg.norm(rs.b)
+    ref = oracle.dense_spd_solve(rs.H, -rs.b)
+    ctx.debug_set_pose_increment(ref.astype(np.float32))
+    pred = ctx.back_substitute()[0]
+    _, dxl = ctx.debug_solution()
+    dxl_o = oracle.back_substitute(rs, ref).reshape(-1, 3) * lin.sl
+    act = bk.lm_active
+    assert np.linalg.norm(dxl[act] - dxl_o[act]) <= 1e-4 * np.linalg.norm(dxl_o[act])
+    pred_o = oracle.model_decrease(lin, ref, oracle.back_substitute(rs, ref))
+    assert abs(pred - pred_o) <= 1e-4 * abs(pred_o), (pred, pred_o)
+
+
+@pytest.mark.parametrize("blocks", [0, 1])
+def test_lm_final_robust_cost(blocks):
+    for p in [make_config(0), mixed_problem(seed=9, n_cams=40, n_points=120)]:
+        bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)
+        ref = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv,
+                              oracle.LMOptions(max_iters=10, huber_delta=DELTA), bk=bk)
+        ctx = gpu_context(p, max_lm_iters=10, huber_delta=DELTA, landmark_blocks=blocks)
+        rep = ctx.lm_solve()[0]
+        hist = ctx.history(0)
+        acc = [h["new_cost"] for h in hist if h["accepted"]]
+        assert all(b < a for a, b in zip([rep.initial_cost] + acc, acc))
+        assert abs(rep.initial_cost - ref.cost0) <= 1e-5 * ref.cost0
+        assert abs(rep.final_cost - ref.final_cost) <= 1e-3 * ref.final_cost, (rep.final_cost, ref.final_cost)
+        c = cost_of(oracle.state_from_bal(ctx.get_cameras(), ctx.get_landmarks()), bk, p.obs_uv, DELTA)
+        assert abs(c - rep.final_cost) <= 1e-5 * rep.final_cost
+        ctx.close()
+
+
+def test_invalid_delta_is_rejected():
+    p = make_config(0)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(Exception):
+            gpu_context(p, huber_delta=bad)
+
+
+def test_full_size_ladybug_like():
+    """At the ladybug-like size (delta 1 px): the robust start cost and the first LM
+    attempt (model decrease 1e-5, new cost 1e-3) against the oracle's stored Huber
+    run, the final cost against the oracle's robust cost at the GPU's final state
+    (1e-5), and within 40 attempts a cost at or below the oracle's after 20 (1e-3);
+    later attempts depend on FP32 rounding, so a fixed attempt count is not compared."""
+    import json
+    import os
+    golden = os.path.join(os.path.dirname(__file__), "golden", "oracle_lm_huber_config1.json")
+    with open(golden) as f:
+        gold = json.load(f)
+    p = make_config(1)
+    bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)
+    ctx = gpu_context(p, max_lm_iters=40, huber_delta=DELTA)
+    rep = ctx.lm_solve()[0]
+    h0 = ctx.history(0)[0]
+    g0 = gold["history"][0]
+    assert abs(rep.initial_cost - gold["initial_cost"]) <= 1e-5 * gold["initial_cost"]
+    assert abs(h0["pred"] - g0["pred"]) <= 1e-5 * abs(g0["pred"]), (h0["pred"], g0["pred"])
+    assert abs(h0["new_cost"] - g0["new_cost"]) <= 1e-3 * g0["new_cost"], (h0["new_cost"], g0["new_cost"])
+    c = cost_of(oracle.state_from_bal(ctx.get_cameras(), ctx.get_landmarks()), bk, p.obs_uv, DELTA)
+    assert abs(c - rep.final_cost) <= 1e-5 * rep.final_cost
+    assert rep.final_cost <= (1 + 1e-3) * gold["final_cost"], (rep.final_cost, gold["final_cost"])
+    ctx.close()
