@@ -202,7 +202,7 @@ def other_blocks_run(p, args, blocks: int):
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
-    log(f"{'implicit' if blocks else 'explicit'} blocks: {1e3 * wall / args.steps:.1f} ms per solve, "
+    log(f"{['explicit', 'implicit', 'explicit Schur complement'][blocks]} blocks: {1e3 * wall / args.steps:.1f} ms per solve, "
         f"product {1e3 * mv_ms:.1f} us, workspace {ws / 1e9:.2f} GB")
     return {"runs": runs, "wall": wall, "mv_ms": mv_ms, "mv_bytes": mv_bytes, "workspace_bytes": ws}
 
@@ -238,6 +238,8 @@ def main():
                     help="skip the solve with the forcing-sequence PCG truncation (eta = 0.1)")
     ap.add_argument("--no-huber", action="store_true",
                     help="skip the solve with the Huber loss (delta = 1 px, IRLS)")
+    ap.add_argument("--no-sc", action="store_true",
+                    help="skip the explicit FP32 Schur-complement comparator (landmark_blocks = 2)")
     ap.add_argument("--tuning", default=None, metavar="EDGE,ROWS,SIDE,SEP,BATCH,PERSIST",
                     help="fixed product bucket edge and launch shapes (rows_min_k, huge_rows, huge_side, "
                          "large_separate, small_rows, persist_wgs) instead of autotuning, e.g. for counter runs "
@@ -359,6 +361,14 @@ def main():
     other = None
     if not args.no_other_blocks:
         other = other_blocks_run(p, args, 0 if blocks else 1)
+    # the paper's explicit-solver comparator: FP32 Schur complement from the normal equations
+    sc = None
+    if not args.no_sc:
+        try:
+            sc = other_blocks_run(p, args, 2)
+        except Exception as e:  # e.g. too many camera-pair contributions (dense workload)
+            log(f"explicit Schur complement comparator skipped: {e}")
+            sc = {"skipped": str(e)}
 
     # time to 1% cost per problem (appendix A.2), f* over the runs (and the oracle where stored)
     gold = None
@@ -375,6 +385,8 @@ def main():
             finals.append(forcing["reports"][i].final_cost)
         if other:
             finals += [reps[i].final_cost for reps, _ in other["runs"]]
+        if sc and "runs" in sc:
+            finals += [reps[i].final_cost for reps, _ in sc["runs"]]
         fstar = min(finals + ([gold["final_cost"]] if gold and p.n_problems == 1 else []))
         f_tau = fstar + 0.01 * (f0 - fstar)
         f_taus.append((f0, fstar, f_tau))
@@ -404,6 +416,26 @@ def main():
             "lm_attempts": max(r.iterations for r in forcing["reports"]),
             "pcg_iters": sum(r.total_pcg_iters for r in forcing["reports"]),
             "final_cost": sum(r.final_cost for r in forcing["reports"]),
+        }
+    sc_out = None
+    if sc and "skipped" in sc:
+        sc_out = {"skipped": sc["skipped"]}
+    elif sc:
+        def rejected(hist):
+            return sum(sum(1 for h in hh if not h["accepted"]) for hh in hist)
+        ttt_sc = [max(time_to_tol(h[i], f_taus[i][2]) for i in range(p.n_problems)) for _, h in sc["runs"]]
+        ach_sc = sc["mv_bytes"] / (sc["mv_ms"] * 1e-3) / 1e9 if sc["mv_ms"] > 0 else None
+        sc_out = {
+            "landmark_blocks": "explicit Schur complement (FP32, assembled camera-pair blocks)",
+            "time_to_1pct_cost_s": statistics.median(ttt_sc),
+            "ms_per_step": 1e3 * sc["wall"] / args.steps,
+            "final_costs": [sum(r.final_cost for r in reps) for reps, _ in sc["runs"]],
+            "rejected_attempts": rejected(sc["runs"][-1][1]),
+            "sqrt_ba_rejected_attempts": rejected(runs[-1][1]),
+            "pcg_iters": sum(r.total_pcg_iters for r in sc["runs"][-1][0]),
+            "workspace_bytes": sc["workspace_bytes"],
+            "product": {"avg_launch_ms": sc["mv_ms"], "algorithmic_bytes_per_launch": sc["mv_bytes"],
+                        "achieved_GBps": ach_sc, "frac_of_hbm_peak": ach_sc / HBM_PEAK_GBPS if ach_sc else None},
         }
     huber_out = None
     if huber:
@@ -510,6 +542,7 @@ def main():
         "tuning": tuning,
         "forcing_sequence": forcing_out,
         "huber_loss": huber_out,
+        "explicit_sc_comparator": sc_out,
         ("explicit_blocks" if blocks else "implicit_blocks"): other_out,
         "learned_vs_block_jacobi": learned_out,
         "cpu_baseline": cpu,

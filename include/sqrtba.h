@@ -96,9 +96,16 @@ typedef struct {
                               factor Q1 (24 floats per observation) are stored; the product
                               and everything else use B^T B = J_p^T (I - Q1 P Q1^T) J_p with
                               P = R1 (R1^T R1 + lambda I)^-1 R1^T, the same reduced system
-                              (eq. red_H) at O(k) memory and traffic per landmark.  Chosen
-                              before the workspace is sized; sqrtba_set_options refuses to
-                              change it after upload (SQRTBA_E_STATE). */
+                              (eq. red_H) at O(k) memory and traffic per landmark.
+                              2: the explicit Schur complement in FP32, the comparator of the
+                              paper's explicit solver (Sec. 4.2, eq. red_normal_eq): per
+                              landmark H_ll, b_l and G = J_p^T J_l from the normal equations,
+                              and H_pp - sum G (H_ll + lambda I)^-1 G^T assembled as 9 x 9
+                              blocks per camera pair at every damp (O(sum k^2) host
+                              bookkeeping, SQRTBA_E_UNSUPPORTED beyond 2^30 pair
+                              contributions); the same PCG, preconditioner and LM loop.
+                              Chosen before the workspace is sized; sqrtba_set_options
+                              refuses to change it after upload (SQRTBA_E_STATE). */
   double huber_delta;    /* 0 (default): squared loss, E = sum |r_o|^2.  > 0: the Huber loss of
                             Sec. 6.2 with this parameter in pixels, applied by IRLS: per
                             observation s = |r_o|^2, E = sum rho(s) with rho(s) = s for
@@ -271,7 +278,10 @@ int32_t sqrtba_debug_precond(sqrtba_ctx* ctx, float* minv);
  * floats: R1 upper (6, row-major), Q1^T r (3), damped R upper (6), damped
  * Q1^T r (3), landmark column scales (3), lambda of the last damp (1), 0, 0.
  * With implicit landmark blocks there are no block rows: out must be NULL
- * (else SQRTBA_E_UNSUPPORTED); factors as above. */
+ * (else SQRTBA_E_UNSUPPORTED); factors as above.  With the explicit Schur
+ * complement (landmark_blocks = 2) out must be NULL too, and factors holds the
+ * scaled H_ll upper (6), the scaled b_l (3), unused (9), the landmark column
+ * scales (3), lambda (1), 0, 0. */
 int32_t sqrtba_debug_block(sqrtba_ctx* ctx, int64_t pt, int32_t* k, float* out, float* factors);
 
 /* Solution of the last solve/back-substitution: scaled pose increment

@@ -53,6 +53,17 @@ struct HostData {
   std::vector<int64_t> hz_off; // per slot with k >= ROWS_MIN_K, offset of its partial outputs
   int64_t hz_floats = 0;
   int64_t poolB = 0, poolT = 0;
+  // explicit Schur complement (landmark_blocks = 2): camera-pair blocks of the
+  // reduced matrix, built on demand (O(sum k^2) host work and memory)
+  struct Sc {
+    bool built = false;
+    int64_t noff = 0;
+    std::vector<int32_t> coff;     // noff + 1
+    std::vector<int32_t> contrib;  // 4 per contribution: record a, record b, slot, 0
+    std::vector<int32_t> rowoff;   // NC + 1
+    std::vector<int32_t> rowent;   // 2 per entry: block | transposed << 31, other camera
+    std::vector<int32_t> blk_prob; // problem of each off-diagonal block
+  } sc;
 };
 
 struct Arena {
@@ -239,6 +250,8 @@ int64_t slots_with_k_at_least(const HostData& h, int64_t kmin) {
 }
 
 // ------------------------------------------------------------ bookkeeping
+
+int build_sc(sqrtba_ctx* c);
 
 int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_t* pt, const float* uv) {
   HostData& h = c->h;
@@ -432,7 +445,9 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
     }
   }
   nb.obs_set = true;
+  nb.sc = HostData::Sc{};
   h = std::move(nb);
+  if (c->opt.landmark_blocks == 2) TRY(build_sc(c));
   return SQRTBA_OK;
 }
 
@@ -453,7 +468,97 @@ T* at(void* base, uint64_t off) {
 }
 
 // Offsets of every device array; when base is null only the size is computed.
-uint64_t layout(const HostData& h, bool implicit, void* base, Dev* d) {
+// Camera-pair blocks of the explicit Schur complement: every pair a < b of a
+// landmark's observations (cameras ascending) contributes G_a H~^-1 G_b^T to
+// block (camera a, camera b).  Contributions are sorted by (camera a, camera b)
+// with a stable two-pass counting sort, so each block sums them in slot order;
+// each camera's row lists its diagonal block, then its blocks in block order.
+int build_sc(sqrtba_ctx* c) {
+  HostData& h = c->h;
+  if (h.sc.built) return SQRTBA_OK;
+  int64_t n = 0;
+  for (int64_t s = 0; s < h.NS; ++s) n += (int64_t)h.slot_k[s] * (h.slot_k[s] - 1) / 2;
+  if (n > (int64_t)1 << 30)
+    return fail(c, SQRTBA_E_UNSUPPORTED, "explicit Schur complement with %lld pair contributions", (long long)n);
+  std::vector<int32_t> ca(n), cb(n), ra(n), rb(n), sl(n);
+  {
+    int64_t e = 0, r0 = 0;
+    for (int64_t s = 0; s < h.NS; ++s) {
+      const int64_t k = h.slot_k[s], o0 = h.slot_obs0[s];
+      for (int64_t a = 0; a < k; ++a)
+        for (int64_t b = a + 1; b < k; ++b) {
+          ca[e] = h.ocam[o0 + a];
+          cb[e] = h.ocam[o0 + b];
+          ra[e] = (int32_t)(r0 + a);
+          rb[e] = (int32_t)(r0 + b);
+          sl[e] = (int32_t)s;
+          ++e;
+        }
+      r0 += k;
+    }
+  }
+  const int64_t NC = h.NC;
+  std::vector<int64_t> order(n), tmp(n), cnt(NC + 1);
+  for (int64_t e = 0; e < n; ++e) tmp[e] = e;
+  for (int pass = 0; pass < 2; ++pass) {  // by camera b, then (stable) by camera a
+    const std::vector<int32_t>& key = pass == 0 ? cb : ca;
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t e = 0; e < n; ++e) cnt[key[tmp[e]] + 1]++;
+    for (int64_t q = 0; q < NC; ++q) cnt[q + 1] += cnt[q];
+    for (int64_t e = 0; e < n; ++e) order[cnt[key[tmp[e]]]++] = tmp[e];
+    tmp.swap(order);
+  }
+  HostData::Sc sc;
+  sc.contrib.resize(4 * n);
+  std::vector<int32_t> bca, bcb;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t e = tmp[i];
+    if (i == 0 || ca[e] != bca.back() || cb[e] != bcb.back()) {
+      sc.coff.push_back((int32_t)i);
+      bca.push_back(ca[e]);
+      bcb.push_back(cb[e]);
+    }
+    sc.contrib[4 * i + 0] = ra[e];
+    sc.contrib[4 * i + 1] = rb[e];
+    sc.contrib[4 * i + 2] = sl[e];
+    sc.contrib[4 * i + 3] = 0;
+  }
+  sc.noff = (int64_t)bca.size();
+  sc.coff.push_back((int32_t)n);
+  if (sc.noff + NC > (int64_t)INT32_MAX / 81)
+    return fail(c, SQRTBA_E_UNSUPPORTED, "explicit Schur complement with %lld blocks", (long long)sc.noff);
+  sc.blk_prob.resize(sc.noff);
+  std::vector<int64_t> rc(NC + 1, 0);
+  for (int64_t q = 0; q < NC; ++q) rc[q + 1] += 1;  // diagonal
+  for (int64_t b = 0; b < sc.noff; ++b) {
+    rc[bca[b] + 1]++;
+    rc[bcb[b] + 1]++;
+    sc.blk_prob[b] = h.cam_prob[bca[b]];
+  }
+  for (int64_t q = 0; q < NC; ++q) rc[q + 1] += rc[q];
+  sc.rowoff.assign(rc.begin(), rc.end());
+  sc.rowent.resize(2 * rc[NC]);
+  std::vector<int64_t> fill(rc.begin(), rc.end() - 1);
+  for (int64_t q = 0; q < NC; ++q) {
+    const int64_t f = fill[q]++;
+    sc.rowent[2 * f] = (int32_t)(sc.noff + q);
+    sc.rowent[2 * f + 1] = (int32_t)q;
+  }
+  for (int64_t b = 0; b < sc.noff; ++b) {
+    int64_t f = fill[bca[b]]++;
+    sc.rowent[2 * f] = (int32_t)b;
+    sc.rowent[2 * f + 1] = bcb[b];
+    f = fill[bcb[b]]++;
+    sc.rowent[2 * f] = (int32_t)((uint32_t)b | 0x80000000u);
+    sc.rowent[2 * f + 1] = bca[b];
+  }
+  sc.built = true;
+  h.sc = std::move(sc);
+  return SQRTBA_OK;
+}
+
+uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
+  const bool implicit = mode != 0, sc = mode == 2;
   Layout L;
   const uint64_t NC = h.NC, NL = h.NL, NO = h.NO, NS = h.NS, P = h.P;
   Dev t{};
@@ -470,6 +575,9 @@ uint64_t layout(const HostData& h, bool implicit, void* base, Dev* d) {
   uint64_t o_pB = f32(nB), o_pT = f32(nT), o_lmd = f32(NS * LMD_STRIDE), o_rho = f32(nrho);
   uint64_t o_rec = f32(implicit ? 4 * (uint64_t)REC_PLANES * NO : 0), o_rcam = f32(implicit ? NO : 0);
   uint64_t o_vzs = f32(12 * NC);
+  const uint64_t nsb = sc ? (uint64_t)(h.sc.noff + NC) * 81 : 0;
+  uint64_t o_scb = f32(nsb), o_scoff = f32(sc ? h.sc.coff.size() : 0), o_scc = f32(sc ? h.sc.contrib.size() : 0);
+  uint64_t o_scro = f32(sc ? h.sc.rowoff.size() : 0), o_scre = f32(sc ? h.sc.rowent.size() : 0), o_vy = f32(9 * NC);
   uint64_t o_sc = f32(9 * NC);
   uint64_t o_v[6];
   for (int i = 0; i < 6; ++i) o_v[i] = f32(9 * NC);
@@ -501,6 +609,14 @@ uint64_t layout(const HostData& h, bool implicit, void* base, Dev* d) {
     t.rec_cam = implicit ? at<int32_t>(base, o_rcam) : nullptr;
     t.vzs = at<float>(base, o_vzs);
     t.implicit = implicit ? 1 : 0;
+    t.sc = sc ? 1 : 0;
+    t.sc_noff = sc ? (int32_t)h.sc.noff : 0;
+    t.scb = sc ? at<float>(base, o_scb) : nullptr;
+    t.sc_coff = sc ? at<int32_t>(base, o_scoff) : nullptr;
+    t.sc_contrib = sc ? at<int4>(base, o_scc) : nullptr;
+    t.sc_rowoff = sc ? at<int32_t>(base, o_scro) : nullptr;
+    t.sc_rowent = sc ? at<int2>(base, o_scre) : nullptr;
+    t.vy = at<float>(base, o_vy);
     t.vx = at<float>(base, o_v[0]); t.vr = at<float>(base, o_v[1]); t.vz = at<float>(base, o_v[2]);
     t.vp = at<float>(base, o_v[3]); t.vq = at<float>(base, o_v[4]); t.vb = at<float>(base, o_v[5]);
     t.minv = at<float>(base, o_minv); t.obsbuf = at<float>(base, o_ob); t.dxl = at<float>(base, o_dxl);
@@ -624,7 +740,7 @@ int upload_state(sqrtba_ctx* c) {
 int upload(sqrtba_ctx* c) {
   const HostData& h = c->h;
   Dev& d = c->d;
-  layout(h, c->opt.landmark_blocks == 1, c->arena.base, &d);
+  layout(h, c->opt.landmark_blocks, c->arena.base, &d);
   d.pcg_tol = (float)c->opt.pcg_rel_tol;
   d.pcg_eta = (float)c->opt.pcg_forcing_eta;
   d.huber = (float)c->opt.huber_delta;
@@ -662,6 +778,12 @@ int upload(sqrtba_ctx* c) {
     TRY(upload_vec(c, d.slot_zoff, rec0));
     TRY(upload_vec(c, d.cam_zpos, zpos));
     TRY(upload_vec(c, d.rec_cam, rcam));
+    if (d.sc) {
+      TRY(upload_vec(c, d.sc_coff, h.sc.coff));
+      TRY(upload_vec(c, reinterpret_cast<int32_t*>(d.sc_contrib), h.sc.contrib));
+      TRY(upload_vec(c, d.sc_rowoff, h.sc.rowoff));
+      TRY(upload_vec(c, reinterpret_cast<int32_t*>(d.sc_rowent), h.sc.rowent));
+    }
   } else {
     TRY(upload_vec(c, d.slot_zoff, h.slot_zoff));
     TRY(upload_vec(c, d.cam_zpos, h.cam_zpos));
@@ -713,7 +835,10 @@ int upload(sqrtba_ctx* c) {
   for (int64_t sl = 0; sl < h.NS; ++sl) {
     const double k = h.slot_k[sl];
     const int p = h.slot_prob[sl];
-    if (c->opt.landmark_blocks == 1) {
+    if (c->opt.landmark_blocks == 2) {
+      // explicit Schur complement: the per-landmark preparation writes the 28-float records
+      c->qr_bytes[p] += 4.0 * (28.0 * k + 12.0) + 12.0 * k + 16.0;
+    } else if (c->opt.landmark_blocks == 1) {
       // implicit: read the 24 Jacobian and Q1 floats and the camera index per
       // observation and the 6 floats of P, write 9k per-observation outputs; the
       // QR writes the 28-float records
@@ -727,6 +852,13 @@ int upload(sqrtba_ctx* c) {
       c->qr_bytes[p] += 4.0 * (2.0 * k * (9.0 * k + 1.0) + 12.0) + 12.0 * k + 16.0;
     }
     c->blocks[p] += 1;
+  }
+  if (c->opt.landmark_blocks == 2) {
+    // product with the reduced matrix: every off-diagonal block is read from both of
+    // its cameras' rows, every diagonal block once (81 floats and the 12-float
+    // gathered vector each), and 9 outputs per camera are written
+    for (int64_t b = 0; b < h.sc.noff; ++b) c->mv_bytes[h.sc.blk_prob[b]] += 2.0 * 4.0 * (81.0 + 12.0);
+    for (int64_t q = 0; q < h.NC; ++q) c->mv_bytes[h.cam_prob[q]] += 4.0 * (81.0 + 12.0 + 9.0);
   }
   c->snapshot = false;
   c->uploaded = true;
@@ -743,7 +875,8 @@ void release_arena(sqrtba_ctx* c) {
 int ensure_uploaded(sqrtba_ctx* c) {
   if (c->uploaded) return SQRTBA_OK;
   TRY(check_ready(c));
-  const uint64_t bytes = layout(c->h, c->opt.landmark_blocks == 1, nullptr, nullptr);
+  if (c->opt.landmark_blocks == 2) TRY(build_sc(c));
+  const uint64_t bytes = layout(c->h, c->opt.landmark_blocks, nullptr, nullptr);
   release_arena(c);
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
@@ -1248,7 +1381,7 @@ void sqrtba_default_options(sqrtba_options* o) {
 static bool valid_options(const sqrtba_options& o) {
   return o.pcg_max_iters >= 0 && o.max_lm_iters >= 0 && o.lambda0 > 0 && o.pcg_check_every >= 1 &&
          std::isfinite(o.pcg_forcing_eta) && o.pcg_forcing_eta >= 0.0 &&
-         (o.landmark_blocks == 0 || o.landmark_blocks == 1) && std::isfinite(o.huber_delta) &&
+         (o.landmark_blocks >= 0 && o.landmark_blocks <= 2) && std::isfinite(o.huber_delta) &&
          o.huber_delta >= 0.0;
 }
 
@@ -1284,6 +1417,7 @@ int32_t sqrtba_set_options(sqrtba_ctx* c, const sqrtba_options* opt) {
   if (!c || !opt || !valid_options(*opt)) return SQRTBA_E_INVALID;
   if (opt->landmark_blocks != c->opt.landmark_blocks && (c->uploaded || c->arena.base))
     return fail(c, SQRTBA_E_STATE, "landmark_blocks is chosen before the workspace is bound");
+  if (opt->landmark_blocks == 2 && c->h.obs_set) TRY(build_sc(c));
   c->opt = *opt;
   c->d.pcg_tol = (float)c->opt.pcg_rel_tol;
   c->d.pcg_eta = (float)c->opt.pcg_forcing_eta;
@@ -1386,14 +1520,16 @@ int32_t sqrtba_set_observations(sqrtba_ctx* c, int64_t n, const int32_t* cam, co
 int32_t sqrtba_workspace_bytes(const sqrtba_ctx* c, uint64_t* bytes) {
   if (!c || !bytes) return SQRTBA_E_INVALID;
   if (c->h.NC < 0 || c->h.NL < 0 || !c->h.obs_set) return SQRTBA_E_STATE;
-  *bytes = layout(c->h, c->opt.landmark_blocks == 1, nullptr, nullptr);
+  if (c->opt.landmark_blocks == 2 && !c->h.sc.built) return SQRTBA_E_STATE;
+  *bytes = layout(c->h, c->opt.landmark_blocks, nullptr, nullptr);
   return SQRTBA_OK;
 }
 
 int32_t sqrtba_bind_workspace(sqrtba_ctx* c, void* ptr, uint64_t bytes) {
   if (!c) return SQRTBA_E_INVALID;
   TRY(check_ready(c));
-  const uint64_t need = layout(c->h, c->opt.landmark_blocks == 1, nullptr, nullptr);
+  if (c->opt.landmark_blocks == 2) TRY(build_sc(c));
+  const uint64_t need = layout(c->h, c->opt.landmark_blocks, nullptr, nullptr);
   if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255)) return fail(c, SQRTBA_E_INVALID, "workspace must be a 256-byte aligned device pointer");
   if (bytes < need) return fail(c, SQRTBA_E_OOM, "workspace has %llu bytes, needs %llu", (unsigned long long)bytes, (unsigned long long)need);
   release_arena(c);
@@ -1570,8 +1706,8 @@ int32_t sqrtba_debug_block(sqrtba_ctx* c, int64_t pt, int32_t* k_out, float* out
   const int64_t k = h.slot_k[s], W = width_of_h(k), C = 9 * k + 4;
   *k_out = (int32_t)k;
   if (!out && !factors) return SQRTBA_OK;
-  if (c->opt.landmark_blocks == 1) {
-    if (out) return fail(c, SQRTBA_E_UNSUPPORTED, "implicit landmark blocks store no block rows");
+  if (c->opt.landmark_blocks != 0) {
+    if (out) return fail(c, SQRTBA_E_UNSUPPORTED, "only explicit landmark blocks store block rows");
     std::vector<float> lmd(LMD_STRIDE);
     HIP_TRY(c, hipMemcpyAsync(lmd.data(), c->d.lmd + LMD_STRIDE * s, 4 * LMD_STRIDE, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

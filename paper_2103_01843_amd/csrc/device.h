@@ -97,7 +97,19 @@ struct Dev {
   float* minv;    // NC * 81 inverse preconditioner blocks
   float* obsrec;  // implicit blocks: REC_PLANES * NO float4 per-observation records (else null)
   int32_t* rec_cam;  // implicit blocks: NO camera indices of the records (else null)
-  int32_t implicit;  // 1: implicit landmark blocks (no poolB / poolT / rhoB)
+  int32_t implicit;  // 1: implicit landmark blocks or (with sc) the explicit Schur complement:
+                     // per-observation records, no poolB / poolT / rhoB
+  // explicit Schur complement in FP32 (landmark_blocks = 2; the comparator of the paper's
+  // explicit solver).  Records hold J_p, the unscaled J_l and r; per landmark H_ll and b_l
+  // (scaled) sit in the R / QR slots of lmd and (H_ll + lambda I)^-1 in the P slot.
+  int32_t sc;
+  int32_t sc_noff;       // off-diagonal camera-pair blocks (then NC diagonal blocks)
+  float* scb;            // (sc_noff + NC) * 81 floats, full 9 x 9, unscaled pose coordinates
+  int32_t* sc_coff;      // sc_noff + 1: contributions of each off-diagonal block (CSR)
+  int4* sc_contrib;      // (record a, record b, slot, 0), a of the block's first camera
+  int32_t* sc_rowoff;    // NC + 1: blocks of each camera's row of the reduced matrix (CSR)
+  int2* sc_rowent;       // (block | transposed << 31, other camera)
+  float* vy;             // 9 NC: the Schur-complement product of the last launch
   float* obsbuf;  // NO * 54 floats: per-observation preconditioner terms; the product outputs
                   // reuse it in per-landmark aligned regions (slot_zoff)
   float* dxl;     // NL * 3, unscaled landmark increment

@@ -1365,6 +1365,12 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
   float acc[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = 0.f;
+  if (d.sc) {  // the Schur-complement product is already per camera
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int a = 0; a < 9; ++a) acc[a] = d.vy[9 * c + a];
+    }
+  } else
   for (int i0 = b; i0 < e; i0 += Q_UNROLL * WG) {
     int nz[Q_UNROLL];
     const bool more = i0 + Q_UNROLL * WG < e;  // uniform
@@ -1921,10 +1927,17 @@ __global__ __launch_bounds__(64) void k_cam_gather_product(Dev d, const float* v
   float acc[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = 0.f;
-  for (int i = d.cam_obs_off[c] + lane; i < d.cam_obs_off[c + 1]; i += 64) {
-    const float* src = d.obsbuf + d.cam_zpos[i];
+  if (d.sc) {
+    if (lane == 0) {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) acc[a] += src[a];
+      for (int a = 0; a < 9; ++a) acc[a] = d.vy[9 * c + a];
+    }
+  } else {
+    for (int i = d.cam_obs_off[c] + lane; i < d.cam_obs_off[c + 1]; i += 64) {
+      const float* src = d.obsbuf + d.cam_zpos[i];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) acc[a] += src[a];
+    }
   }
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = wave_sum_f(acc[a]);
@@ -2245,6 +2258,356 @@ struct BacksubImplF {
 
 __global__ __launch_bounds__(WG) void k_backsub_implicit(Dev d, ImplGrid m) { impl_dispatch(m, BacksubImplF{d}); }
 
+// ------------------------------------------ explicit Schur complement (FP32)
+//
+// The comparator of the paper's explicit solver (Sec. 4.2, eq. red_normal_eq):
+// per landmark the normal-equation blocks H_ll = (J_l S_l)^T (J_l S_l) and
+// b_l = (J_l S_l)^T r, per observation G_o = J_o^T (J_lo S_l), and the reduced
+// camera matrix H_pp - sum_l G H~_ll^-1 G^T assembled in FP32 as 9 x 9 blocks
+// per camera pair, H~_ll = H_ll + lambda I.  Pose columns stay unscaled as in
+// the square-root path (S_p is applied where the vectors are gathered), so the
+// preconditioner, the PCG vector kernels and the LM loop are shared.
+
+// Float f (0..27) of record i: planes of 4 floats, plane-major.
+__device__ __forceinline__ float rec_float(const Dev& d, int i, int f) {
+  return d.obsrec[4 * ((size_t)(f >> 2) * d.NO + i) + (f & 3)];
+}
+
+// Per landmark: linearize its observations (with the Huber weight), store the
+// records (J_p, unscaled J_l, r), and the scaled H_ll, b_l and landmark scales.
+template <int TEAM, int OPL>
+__device__ __forceinline__ void sc_prepare(const Dev& d, int slot, int lane, const uint8_t* mask) {
+  const int prob = d.slot_prob[slot];
+  if (mask && !mask[prob]) return;
+  const int k = d.slot_k[slot], obs0 = d.slot_obs0[slot], r0 = d.slot_zoff[slot];
+  const float4 X = d.pts[d.slot_lm[slot]];
+  float h[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // H_ll upper (6), b_l (3), unscaled
+#pragma unroll
+  for (int m = 0; m < OPL; ++m) {
+    const int o = lane + TEAM * m;
+    if (o < k) {
+      Cam C;
+      load_cam(d.cam, d.obs_cam[obs0 + o], C);
+      const float2 uv = d.obs_uv[obs0 + o];
+      float r[2], Jp[2][9], Jl[2][3];
+      project<true>(C, X.x, X.y, X.z, uv.x, uv.y, r, Jp, Jl);
+      float sw;
+      (void)robust_term(r[0] * r[0] + r[1] * r[1], d.huber, sw);
+      r[0] *= sw;
+      r[1] *= sw;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        Jp[0][j] *= sw;
+        Jp[1][j] *= sw;
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        Jl[0][j] *= sw;
+        Jl[1][j] *= sw;
+      }
+      int e = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) h[e++] += Jl[0][a] * Jl[0][b] + Jl[1][a] * Jl[1][b];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) h[6 + a] += Jl[0][a] * r[0] + Jl[1][a] * r[1];
+      float4* rec = rec_plane(d, 0) + r0 + o;
+      const size_t P = (size_t)d.NO;
+      rec[0] = make_float4(Jp[0][0], Jp[0][1], Jp[0][2], Jp[0][3]);
+      rec[P] = make_float4(Jp[0][4], Jp[0][5], Jp[0][6], Jp[0][7]);
+      rec[2 * P] = make_float4(Jp[0][8], Jp[1][0], Jp[1][1], Jp[1][2]);
+      rec[3 * P] = make_float4(Jp[1][3], Jp[1][4], Jp[1][5], Jp[1][6]);
+      rec[4 * P] = make_float4(Jp[1][7], Jp[1][8], Jl[0][0], Jl[0][1]);
+      rec[5 * P] = make_float4(Jl[0][2], Jl[1][0], Jl[1][1], Jl[1][2]);
+      rec[6 * P] = make_float4(r[0], r[1], 0.f, 0.f);
+    }
+  }
+  int buf = 0;
+  team_sum_n<TEAM, 9>(h, nullptr, buf);
+  if (lane == 0) {
+    // unit-norm landmark columns (an empty column keeps scale 1), then S_l H S_l, S_l b
+    const float s0 = h[0] > 0.f ? 1.0f / sqrtf(h[0]) : 1.0f;
+    const float s1 = h[3] > 0.f ? 1.0f / sqrtf(h[3]) : 1.0f;
+    const float s2 = h[5] > 0.f ? 1.0f / sqrtf(h[5]) : 1.0f;
+    float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+    lmd[LMD_R + 0] = s0 * h[0] * s0; lmd[LMD_R + 1] = s0 * h[1] * s1; lmd[LMD_R + 2] = s0 * h[2] * s2;
+    lmd[LMD_R + 3] = s1 * h[3] * s1; lmd[LMD_R + 4] = s1 * h[4] * s2; lmd[LMD_R + 5] = s2 * h[5] * s2;
+    lmd[LMD_QR + 0] = s0 * h[6]; lmd[LMD_QR + 1] = s1 * h[7]; lmd[LMD_QR + 2] = s2 * h[8];
+    lmd[LMD_SL + 0] = s0; lmd[LMD_SL + 1] = s1; lmd[LMD_SL + 2] = s2;
+  }
+}
+
+template <bool UNUSED>
+struct ScPrepF {
+  const Dev& d;
+  const uint8_t* mask;
+  template <int TEAM, int OPL>
+  __device__ __forceinline__ void run(int slot, int lane) const { sc_prepare<TEAM, OPL>(d, slot, lane, mask); }
+};
+
+__global__ __launch_bounds__(WG) void k_sc_prepare(Dev d, ImplGrid m, const uint8_t* mask) {
+  impl_dispatch(m, ScPrepF<true>{d, mask});
+}
+
+// Per landmark: (H_ll + lambda I)^-1 by a 3 x 3 Cholesky factorization in FP32
+// (a non-positive pivot, possible only at lambda = 0 for a rank-deficient J_l,
+// drops the landmark: inverse 0).
+__global__ __launch_bounds__(WG) void k_sc_damp(Dev d, const uint8_t* mask) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= d.NS) return;
+  const int prob = d.slot_prob[slot];
+  if (mask && !mask[prob]) return;
+  float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const float lam = (float)d.lambda[prob];
+  const float a00 = lmd[LMD_R + 0] + lam, a01 = lmd[LMD_R + 1], a02 = lmd[LMD_R + 2];
+  const float a11 = lmd[LMD_R + 3] + lam, a12 = lmd[LMD_R + 4], a22 = lmd[LMD_R + 5] + lam;
+  float P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const float l00 = a00 > 0.f ? sqrtf(a00) : 0.f;
+  if (l00 > 0.f) {
+    const float l10 = a01 / l00, l20 = a02 / l00;
+    const float d11 = a11 - l10 * l10;
+    const float l11 = d11 > 0.f ? sqrtf(d11) : 0.f;
+    if (l11 > 0.f) {
+      const float l21 = (a12 - l20 * l10) / l11;
+      const float d22 = a22 - l20 * l20 - l21 * l21;
+      const float l22 = d22 > 0.f ? sqrtf(d22) : 0.f;
+      if (l22 > 0.f) {
+        // L^-1 (lower), then A^-1 = L^-T L^-1
+        const float i00 = 1.0f / l00, i11 = 1.0f / l11, i22 = 1.0f / l22;
+        const float i10 = -l10 * i00 * i11;
+        const float i21 = -l21 * i11 * i22;
+        const float i20 = -(l20 * i00 + l21 * i10) * i22;
+        P[0] = i00 * i00 + i10 * i10 + i20 * i20;
+        P[1] = i10 * i11 + i20 * i21;
+        P[2] = i20 * i22;
+        P[3] = i11 * i11 + i21 * i21;
+        P[4] = i21 * i22;
+        P[5] = i22 * i22;
+      }
+    }
+  }
+  reinterpret_cast<float4*>(lmd + LMD_P)[0] = make_float4(P[0], P[1], P[2], P[3]);
+  reinterpret_cast<float2*>(lmd + LMD_P + 4)[0] = make_float2(P[4], P[5]);
+  lmd[LMD_LAM] = lam;
+}
+
+// G = J_p^T (J_l S_l) (9 x 3) of record i, and the record's pose Jacobian rows.
+__device__ __forceinline__ void sc_load_g(const Dev& d, int i, const float sl[3], float (&J)[2][9], float (&G)[9][3]) {
+  float Lu[2][3];
+  load_rec(d, i, J, Lu);
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) G[a][m] = (J[0][a] * Lu[0][m] + J[1][a] * Lu[1][m]) * sl[m];
+}
+
+// Per observation (one thread, landmark order): its block-Jacobi terms
+// J^T J - G H~^-1 G^T (45 upper entries) and right-hand side J^T r - G H~^-1 b_l
+// to obsbuf[obs][0..53], the layout the per-camera preconditioner sums.
+__global__ __launch_bounds__(WG) void k_sc_precond_obs(Dev d) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= d.NO) return;
+  const int slot = d.lm_slot[d.obs_lm[q]];
+  if (!d.active[d.slot_prob[slot]]) return;
+  const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const int ri = d.slot_zoff[slot] + (q - d.slot_obs0[slot]);
+  const float sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
+  float Hi[3][3], J[2][9], G[9][3];
+  load_p(lmd, Hi);
+  sc_load_g(d, ri, sl, J, G);
+  const float4 rv = rec_plane(d, 6)[ri];
+  const float bl[3] = {lmd[LMD_QR + 0], lmd[LMD_QR + 1], lmd[LMD_QR + 2]};
+  float T[9][3];  // G H~^-1
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+#pragma unroll
+    for (int n = 0; n < 3; ++n) T[a][n] = G[a][0] * Hi[0][n] + G[a][1] * Hi[1][n] + G[a][2] * Hi[2][n];
+  float* out = d.obsbuf + (size_t)q * 54;
+  int e = 0;
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+#pragma unroll
+    for (int b = a; b < 9; ++b)
+      out[e++] = J[0][a] * J[0][b] + J[1][a] * J[1][b] - (T[a][0] * G[b][0] + T[a][1] * G[b][1] + T[a][2] * G[b][2]);
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+    out[45 + a] = J[0][a] * rv.x + J[1][a] * rv.y - (T[a][0] * bl[0] + T[a][1] * bl[1] + T[a][2] * bl[2]);
+}
+
+// Off-diagonal block b, row i (one thread): -sum over the block's contributions
+// (records a, b of one landmark) of (G_a H~^-1 G_b^T) row i, in list order.
+__global__ __launch_bounds__(WG) void k_sc_assemble_off(Dev d, const uint8_t* mask) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9LL * d.sc_noff) return;
+  const int blk = (int)(t / 9), i = (int)(t - 9LL * blk);
+  const int e0 = d.sc_coff[blk], e1 = d.sc_coff[blk + 1];
+  if (e0 == e1) return;
+  if (mask && !mask[d.slot_prob[d.sc_contrib[e0].z]]) return;
+  float acc[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) acc[j] = 0.f;
+  for (int e = e0; e < e1; ++e) {
+    const int4 c = d.sc_contrib[e];
+    const float* lmd = d.lmd + (size_t)c.z * LMD_STRIDE;
+    const float sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
+    float Hi[3][3];
+    load_p(lmd, Hi);
+    // row i of G_a
+    const float ja0 = rec_float(d, c.x, i), ja1 = rec_float(d, c.x, 9 + i);
+    float ga[3], tn[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) ga[m] = (ja0 * rec_float(d, c.x, 18 + m) + ja1 * rec_float(d, c.x, 21 + m)) * sl[m];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) tn[n] = ga[0] * Hi[0][n] + ga[1] * Hi[1][n] + ga[2] * Hi[2][n];
+    float Jb[2][9], Gb[9][3];
+    sc_load_g(d, c.y, sl, Jb, Gb);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc[j] -= tn[0] * Gb[j][0] + tn[1] * Gb[j][1] + tn[2] * Gb[j][2];
+  }
+  float* out = d.scb + (size_t)blk * 81 + 9 * i;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) out[j] = acc[j];
+}
+
+// Diagonal block of camera c, row i (one thread): sum over the camera's
+// observations (camera order) of (J^T J - G H~^-1 G^T) row i.
+__global__ __launch_bounds__(WG) void k_sc_assemble_diag(Dev d, const uint8_t* mask) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9 * d.NC) return;
+  const int c = t / 9, i = t - 9 * c;
+  if (mask && !mask[d.cam_prob[c]]) return;
+  float acc[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) acc[j] = 0.f;
+  for (int e = d.cam_obs_off[c]; e < d.cam_obs_off[c + 1]; ++e) {
+    const int q = d.cam_obs_idx[e];
+    const int slot = d.lm_slot[d.obs_lm[q]];
+    const int ri = d.slot_zoff[slot] + (q - d.slot_obs0[slot]);
+    const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+    const float sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
+    float Hi[3][3], J[2][9], G[9][3];
+    load_p(lmd, Hi);
+    sc_load_g(d, ri, sl, J, G);
+    float tn[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) tn[n] = G[i][0] * Hi[0][n] + G[i][1] * Hi[1][n] + G[i][2] * Hi[2][n];
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+      acc[j] += J[0][i] * J[0][j] + J[1][i] * J[1][j] - (tn[0] * G[j][0] + tn[1] * G[j][1] + tn[2] * G[j][2]);
+  }
+  float* out = d.scb + (size_t)(d.sc_noff + c) * 81 + 9 * i;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) out[j] = acc[j];
+}
+
+// Product with the assembled reduced matrix, one wavefront per camera row:
+// vy_c = sum over the row's blocks of B (S v)_other (B^T for the transposed
+// entries), lanes over blocks in a fixed order and a fixed reduction tree.
+template <bool PCG>
+__global__ __launch_bounds__(64) void k_sc_matvec(Dev d) {
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int prob = d.cam_prob[c];
+  if (!d.active[prob] || (PCG && d.done[prob])) return;
+  float acc[9];
+#pragma unroll
+  for (int a = 0; a < 9; ++a) acc[a] = 0.f;
+  for (int e = d.sc_rowoff[c] + lane; e < d.sc_rowoff[c + 1]; e += 64) {
+    const int2 en = d.sc_rowent[e];
+    const float* B = d.scb + (size_t)(en.x & 0x7fffffff) * 81;
+    const float4* vs = reinterpret_cast<const float4*>(d.vzs) + 3 * (size_t)en.y;
+    const float4 v0 = vs[0], v1 = vs[1], v2 = vs[2];
+    const float v[9] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x};
+    if (en.x >= 0) {
+#pragma unroll
+      for (int a = 0; a < 9; ++a)
+#pragma unroll
+        for (int j = 0; j < 9; ++j) acc[a] += B[9 * a + j] * v[j];
+    } else {
+#pragma unroll
+      for (int a = 0; a < 9; ++a)
+#pragma unroll
+        for (int j = 0; j < 9; ++j) acc[a] += B[9 * j + a] * v[j];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 9; ++a) acc[a] = wave_sum_f(acc[a]);
+  if (lane < 9) {
+    float s = acc[0];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) s = (lane == a) ? acc[a] : s;
+    d.vy[9 * c + lane] = s;
+  }
+}
+
+// Back-substitution (eq. backsub_sc) per landmark: dl~ = -H~^-1 (b_l + (J_l S_l)^T J_p p'),
+// p' = S dx_p, and the undamped model decrease -sum u (2 r + u), u = J_p p' + J_l S_l dl~.
+template <int TEAM, int OPL>
+__device__ __forceinline__ void sc_backsub(const Dev& d, int slot, int lane) {
+  const int prob = d.slot_prob[slot];
+  if (!d.active[prob]) return;
+  const int lm = d.slot_lm[slot];
+  const int k = d.slot_k[slot], r0 = d.slot_zoff[slot];
+  const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const float sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
+  float u[OPL][2];
+  float c[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int m = 0; m < OPL; ++m) {
+    const int o = lane + TEAM * m;
+    u[m][0] = u[m][1] = 0.f;
+    if (o < k) {
+      float J[2][9], Lu[2][3];
+      load_rec(d, r0 + o, J, Lu);
+      const int cam = 9 * d.rec_cam[r0 + o];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        const float pa = d.s_cam[cam + a] * d.vx[cam + a];
+        u[m][0] += J[0][a] * pa;
+        u[m][1] += J[1][a] * pa;
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) c[j] += (Lu[0][j] * u[m][0] + Lu[1][j] * u[m][1]) * sl[j];
+    }
+  }
+  int buf = 0;
+  team_sum_n<TEAM, 3>(c, nullptr, buf);
+  float Hi[3][3];
+  load_p(lmd, Hi);
+  const float g[3] = {lmd[LMD_QR + 0] + c[0], lmd[LMD_QR + 1] + c[1], lmd[LMD_QR + 2] + c[2]};
+  float dl[3];
+#pragma unroll
+  for (int n = 0; n < 3; ++n) dl[n] = -(Hi[n][0] * g[0] + Hi[n][1] * g[1] + Hi[n][2] * g[2]);
+  float s2[1] = {0.f};
+#pragma unroll
+  for (int m = 0; m < OPL; ++m) {
+    const int o = lane + TEAM * m;
+    if (o < k) {
+      float J[2][9], Lu[2][3];
+      load_rec(d, r0 + o, J, Lu);
+      const float4 rv = rec_plane(d, 6)[r0 + o];
+      const float w0 = u[m][0] + Lu[0][0] * sl[0] * dl[0] + Lu[0][1] * sl[1] * dl[1] + Lu[0][2] * sl[2] * dl[2];
+      const float w1 = u[m][1] + Lu[1][0] * sl[0] * dl[0] + Lu[1][1] * sl[1] * dl[1] + Lu[1][2] * sl[2] * dl[2];
+      s2[0] += w0 * (2.f * rv.x + w0) + w1 * (2.f * rv.y + w1);
+    }
+  }
+  team_sum_n<TEAM, 1>(s2, nullptr, buf);
+  if (lane == 0) {
+    d.dxl[3 * (size_t)lm + 0] = sl[0] * dl[0];
+    d.dxl[3 * (size_t)lm + 1] = sl[1] * dl[1];
+    d.dxl[3 * (size_t)lm + 2] = sl[2] * dl[2];
+    d.lm_part[lm] = -(double)s2[0];
+  }
+}
+
+struct ScBacksubF {
+  const Dev& d;
+  template <int TEAM, int OPL>
+  __device__ __forceinline__ void run(int slot, int lane) const { sc_backsub<TEAM, OPL>(d, slot, lane); }
+};
+
+__global__ __launch_bounds__(WG) void k_sc_backsub(Dev d, ImplGrid m) { impl_dispatch(m, ScBacksubF{d}); }
+
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -2311,6 +2674,13 @@ hipError_t launch_prob_sum(const Dev& d, const Launch& L, const double* vals, co
 // classes 0..4 when both are present.
 hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask) {
   const WorkClass* w = L.wc;
+  if (d.sc) {  // explicit Schur complement: normal-equation terms per landmark
+    int n = 0;
+    const ImplGrid m = impl_grid(L, &n);
+    if (n) hipLaunchKernelGGL(k_sc_prepare, dim3(n), dim3(WG), 0, L.stream, d, m, mask);
+    LAUNCH_CHECK();
+    return hipSuccess;
+  }
   int n = 0;
   const ClassGrid m = class_grid(L, &n);
   const bool side = w[5].slots && n && L.side && L.fork && L.join;
@@ -2344,6 +2714,16 @@ hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask
 
 hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
   const WorkClass* w = L.wc;
+  if (d.sc) {  // (H_ll + lambda I)^-1, then the reduced matrix assembled anew
+    if (d.NS) hipLaunchKernelGGL(k_sc_damp, dim3(nblocks(d.NS, WG)), dim3(WG), 0, L.stream, d, mask);
+    LAUNCH_CHECK();
+    if (d.sc_noff)
+      hipLaunchKernelGGL(k_sc_assemble_off, dim3(nblocks(9LL * d.sc_noff, WG)), dim3(WG), 0, L.stream, d, mask);
+    LAUNCH_CHECK();
+    if (d.NC) hipLaunchKernelGGL(k_sc_assemble_diag, dim3(nblocks(9LL * d.NC, WG)), dim3(WG), 0, L.stream, d, mask);
+    LAUNCH_CHECK();
+    return hipSuccess;
+  }
   if (d.implicit) {
     if (d.NS) hipLaunchKernelGGL(k_damp_implicit, dim3(nblocks(d.NS, WG)), dim3(WG), 0, L.stream, d, mask);
     LAUNCH_CHECK();
@@ -2359,6 +2739,13 @@ hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
 
 hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
   const WorkClass* w = L.wc;
+  if (d.sc) {
+    if (d.NO) hipLaunchKernelGGL(k_sc_precond_obs, dim3(nblocks(d.NO, WG)), dim3(WG), 0, L.stream, d);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_precond_cam, dim3(d.NC), dim3(64), 0, L.stream, d);
+    LAUNCH_CHECK();
+    return hipSuccess;
+  }
   if (d.implicit) {
     if (d.NO) hipLaunchKernelGGL(k_precond_obs_implicit, dim3(nblocks(d.NO, WG)), dim3(WG), 0, L.stream, d);
     LAUNCH_CHECK();
@@ -2407,6 +2794,15 @@ static void launch_small(const Dev& d, const Launch& L, const ClassGrid& m, int 
 // of the row-block partials.
 template <bool PCG>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
+  if (d.sc) {  // product with the assembled reduced matrix into vy (S z as for implicit blocks)
+    if (!PCG && v && d.NC) {
+      hipLaunchKernelGGL(k_prescale, dim3(nblocks(9 * d.NC, WG)), dim3(WG), 0, L.stream, d, v);
+      LAUNCH_CHECK();
+    }
+    if (d.NC) hipLaunchKernelGGL(k_sc_matvec<PCG>, dim3(d.NC), dim3(64), 0, L.stream, d);
+    LAUNCH_CHECK();
+    return hipSuccess;
+  }
   if (d.implicit) {
     // in PCG the update kernels keep vzs = S z; otherwise it is formed from v here
     // (v == nullptr: already formed)
@@ -2496,6 +2892,13 @@ hipError_t launch_pcg_iteration(const Dev& d, const Launch& L) {
 
 hipError_t launch_backsub(const Dev& d, const Launch& L) {
   const WorkClass* w = L.wc;
+  if (d.sc) {
+    int n = 0;
+    const ImplGrid m = impl_grid(L, &n);
+    if (n) hipLaunchKernelGGL(k_sc_backsub, dim3(n), dim3(WG), 0, L.stream, d, m);
+    LAUNCH_CHECK();
+    return hipSuccess;
+  }
   if (d.implicit) {
     int n = 0;
     const ImplGrid m = impl_grid(L, &n);

@@ -1,0 +1,138 @@
+"""Explicit Schur complement in FP32 (option landmark_blocks = 2), the comparator
+of the paper's explicit solver (Sec. 4.2, eq. red_normal_eq), against the FP64
+oracle, which forms the same Schur complement in FP64.
+
+FP32 assembly subtracts sum_l G_l H~_ll^-1 G_l^T from H_pp, so its error scales
+with the size of the subtracted terms, not with the result: the dense reduced
+matrix is held to 1e-4 relative plus 32 eps32 |sum_l |G_l H~^-1 G_l^T||_F /
+|H~|_F (the rounding of forming and adding those terms in FP32), the
+right-hand side likewise with the b terms.  Then block-Jacobi, PCG and the
+back-substitution and model decrease from the oracle's exact step (1e-4), the
+LM final cost (1e-3), bitwise determinism, and the block structure: exactly
+the camera pairs that share a landmark are non-zero.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.lm import cost_of
+from bal_synth import make_config
+from paper_2103_01843_amd import SqrtBAError
+
+from gpu_util import gpu_context, mixed_problem, oracle_lin
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module", params=["tiny", "mixed"])
+def case(request):
+    p = make_config(0) if request.param == "tiny" else mixed_problem()
+    bk, st, lin = oracle_lin(p)
+    ctx = gpu_context(p, landmark_blocks=2)
+    yield p, bk, st, lin, ctx
+    ctx.close()
+
+
+def _subtracted_magnitude(lin, lam):
+    """|sum_l |G_l H~^-1 G_l^T||_F and |sum_l |G_l H~^-1 b_l||, scaled coordinates."""
+    n = 9 * lin.n_cams
+    M = np.zeros((n, n))
+    mb = np.zeros(n)
+    for l in np.unique(lin.pi):
+        idx = np.nonzero(lin.pi == l)[0]
+        Jl = (lin.Jl[idx] * lin.sl[l]).reshape(-1, 3)
+        Hi = np.linalg.inv(Jl.T @ Jl + lam * np.eye(3))
+        rows = np.concatenate([9 * lin.ci[o] + np.arange(9) for o in idx])
+        G = np.vstack([(lin.Jp[o] * lin.sp[lin.ci[o]]).T @ (lin.Jl[o] * lin.sl[l]) for o in idx])
+        r = lin.r[idx].reshape(-1)
+        T = np.abs(G @ Hi @ G.T)
+        M[np.ix_(rows, rows)] += T
+        np.add.at(mb, rows, np.abs(G @ Hi @ (Jl.T @ r)))
+    return np.linalg.norm(M), np.linalg.norm(mb)
+
+
+@pytest.mark.parametrize("lam", [1e-4, 0.3])
+def test_reduced_system_dense(case, lam):
+    p, bk, st, lin, ctx = case
+    ctx.linearize()
+    ctx.marginalize()
+    ctx.damp(lam)
+    rs = oracle.reduced_camera_system(lin, lam)
+    N = rs.H.shape[0]
+    Hg = ctx.debug_rcs_matvec(np.eye(N, dtype=np.float32)).astype(np.float64)
+    mH, mb = _subtracted_magnitude(lin, lam)
+    eH = np.linalg.norm(Hg - rs.H)
+    assert eH <= 1e-4 * np.linalg.norm(rs.H) + 32 * EPS32 * mH, (eH / np.linalg.norm(rs.H), mH / np.linalg.norm(rs.H))
+    bg = ctx.debug_rhs().astype(np.float64)
+    eb = np.linalg.norm(bg - rs.b)
+    assert eb <= 1e-4 * np.linalg.norm(rs.b) + 32 * EPS32 * mb, (eb / np.linalg.norm(rs.b), mb / np.linalg.norm(rs.b))
+    Mi = ctx.debug_precond().astype(np.float64)
+    Bo = oracle.block_jacobi_blocks(rs.H)
+    for i in range(0, len(Bo), max(1, len(Bo) // 20)):
+        np.testing.assert_allclose(Mi[i] @ Bo[i], np.eye(9), atol=5e-3)
+
+
+def test_pcg_and_back_substitution(case):
+    p, bk, st, lin, ctx = case
+    lam = 1e-4
+    ctx.linearize()
+    ctx.marginalize()
+    ctx.damp(lam)
+    its, rel, status = ctx.solve()
+    rs = oracle.reduced_camera_system(lin, lam)
+    dxp, _ = ctx.debug_solution()
+    assert status[0] == 0 and rel[0] <= 1e-6
+    assert np.linalg.norm(rs.H @ dxp + rs.b) <= 1e-3 * np.linalg.norm(rs.b)
+    ref = oracle.dense_spd_solve(rs.H, -rs.b)
+    ctx.debug_set_pose_increment(ref.astype(np.float32))
+    pred = ctx.back_substitute()[0]
+    _, dxl = ctx.debug_solution()
+    dxl_o = oracle.back_substitute(rs, ref).reshape(-1, 3) * lin.sl
+    act = bk.lm_active
+    assert np.linalg.norm(dxl[act] - dxl_o[act]) <= 1e-4 * np.linalg.norm(dxl_o[act])
+    pred_o = oracle.model_decrease(lin, ref, oracle.back_substitute(rs, ref))
+    assert abs(pred - pred_o) <= 1e-4 * abs(pred_o), (pred, pred_o)
+
+
+def test_lm_final_cost_and_determinism():
+    for p in [make_config(0), mixed_problem(seed=9, n_cams=40, n_points=120)]:
+        bk, st, lin = oracle_lin(p)
+        res = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, oracle.LMOptions(max_iters=10), bk=bk)
+        reps = []
+        for _ in range(2):
+            ctx = gpu_context(p, max_lm_iters=10, landmark_blocks=2)
+            reps.append(ctx.lm_solve()[0])
+            c = cost_of(oracle.state_from_bal(ctx.get_cameras(), ctx.get_landmarks()), bk, p.obs_uv)
+            ctx.close()
+        rep = reps[0]
+        assert reps[1].final_cost == rep.final_cost and reps[1].total_pcg_iters == rep.total_pcg_iters
+        assert abs(rep.final_cost - res.final_cost) <= 1e-3 * res.final_cost, (rep.final_cost, res.final_cost)
+        assert abs(c - rep.final_cost) <= 1e-5 * rep.final_cost
+
+
+def test_block_structure_and_unsupported_rows():
+    p = mixed_problem(seed=9, n_cams=40, n_points=120)
+    bk, st, lin = oracle_lin(p)
+    ctx = gpu_context(p, landmark_blocks=2)
+    ctx.linearize()
+    ctx.marginalize()
+    ctx.damp(1e-3)
+    rs = oracle.reduced_camera_system(lin, 1e-3)
+    N = rs.H.shape[0]
+    Hg = ctx.debug_rcs_matvec(np.eye(N, dtype=np.float32)).astype(np.float64)
+    # exactly the camera pairs that share a landmark are non-zero
+    share = np.zeros((p.n_cams, p.n_cams), bool)
+    for l in np.unique(lin.pi):
+        cams = lin.ci[lin.pi == l]
+        share[np.ix_(cams, cams)] = True
+    nz = np.abs(Hg).reshape(p.n_cams, 9, p.n_cams, 9).max(axis=(1, 3)) > 0
+    act = bk.cam_active
+    assert np.array_equal(nz[np.ix_(act, act)], share[np.ix_(act, act)])
+    l = int(np.nonzero(bk.lm_active)[0][0])
+    with pytest.raises(SqrtBAError) as ei:  # no square-root block rows in this form
+        ctx.debug_block(l)
+    assert ei.value.status == -6
+    ctx.close()
