@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 from oracle.lm import cost_of
-from bal_synth import make_config
+from bal_synth import make_config, make_ring_problem, concat_problems
 from paper_2103_01843_amd import SqrtBAError
 
 from gpu_util import gpu_context, mixed_problem, oracle_lin
@@ -136,3 +136,18 @@ def test_block_structure_and_unsupported_rows():
         ctx.debug_block(l)
     assert ei.value.status == -6
     ctx.close()
+
+
+def test_batch_equals_single_problem_runs():
+    """Camera-pair blocks never link two problems, so a batch of three problems solves
+    each exactly as a run on its own (bitwise)."""
+    rng = np.random.default_rng(11)
+    ps = [make_ring_problem(rng, 12, 200, lambda r, n: r.integers(2, 9, size=n)) for _ in range(3)]
+    batch = gpu_context(concat_problems(ps), max_lm_iters=6, landmark_blocks=2)
+    reps = batch.lm_solve()
+    for i, p in enumerate(ps):
+        single = gpu_context(p, max_lm_iters=6, landmark_blocks=2)
+        r = single.lm_solve()[0]
+        assert r.final_cost == reps[i].final_cost and r.total_pcg_iters == reps[i].total_pcg_iters
+        single.close()
+    batch.close()

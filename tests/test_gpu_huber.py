@@ -6,7 +6,7 @@ Same bar as the squared loss: the reweighted per-observation residuals to
 (Frobenius), the back-substitution and model decrease from the oracle's exact
 pose step to 1e-4, the LM final robust cost to 1e-3 of the oracle's Huber LM
 and to 1e-5 of the oracle's robust cost at the GPU's final state; both
-landmark-block forms.  The delta of the tests is 1 px, the paper's; at the
+landmark-block forms and the explicit Schur-complement comparator.  The delta of the tests is 1 px, the paper's; at the
 perturbed start most observations lie beyond it and a few percent inside.
 """
 
@@ -77,7 +77,7 @@ def test_reduced_system_and_back_substitution(case):
     assert abs(pred - pred_o) <= 1e-4 * abs(pred_o), (pred, pred_o)
 
 
-@pytest.mark.parametrize("blocks", [0, 1])
+@pytest.mark.parametrize("blocks", [0, 1, 2])
 def test_lm_final_robust_cost(blocks):
     for p in [make_config(0), mixed_problem(seed=9, n_cams=40, n_points=120)]:
         bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)

@@ -140,7 +140,7 @@ def test_block_rows_are_not_stored_and_mode_is_fixed_after_upload():
     assert len(trials) == 1 and best == ctx.get_tuning()
     ctx.close()
     with pytest.raises(SqrtBAError):
-        gpu_context(p, landmark_blocks=2)
+        gpu_context(p, landmark_blocks=3)
 
 
 @pytest.mark.parametrize("cfg", [1, 3])
