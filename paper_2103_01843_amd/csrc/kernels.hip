@@ -4,17 +4,22 @@
 // with fixed-shape trees, so every result is run-to-run deterministic.
 //
 // Landmark-centric kernels (marginalize, damp, preconditioner/RHS, matvec,
-// back-substitution) give each landmark a team of 8, 16, 64 or 256 lanes
-// chosen by its observation count k.  A team of <= 64 lanes lives inside one
-// wavefront and reduces with DPP row operations (no LDS, no barrier); a team
-// of 256 lanes is a whole workgroup.  Per-camera sums are never formed with
-// atomics: the landmark kernels write per-observation results and camera
-// kernels sum them over each camera's observation list.
+// back-substitution) give each landmark a team of 8, 16, 32, 64 or 256 lanes
+// chosen by its observation count k (4 to 64 lanes in the per-observation
+// forms).  A team of <= 64 lanes lives inside one wavefront and reduces with
+// DPP row operations (no LDS, no barrier); a team of 256 lanes is a whole
+// workgroup.  Per-camera sums are never formed with atomics: the landmark
+// kernels write per-observation results and camera kernels sum them over each
+// camera's observation list.
 //
 // The matrix algebra is the paper's: nullspace marginalization by QR of each
 // landmark's J_l (Sec. 4.3, Householder variant of Sec. 5.2), landmark damping
 // by six Givens rotations (Sec. 5.3), and CG on the reduced normal equations
 // with the product (Q2^T J_p)^T (Q2^T J_p v) + lambda v (Sec. 5.4, eq. cg_mult).
+// Beside the stored blocks: the same reduced system from per-observation
+// records (implicit blocks, J_p^T (I - Q1 P Q1^T) J_p), the explicit FP32
+// Schur complement of the paper's comparison solver (Sec. 4.2), and the Huber
+// loss of the experiments applied by IRLS (Sec. 6.2).
 
 #include <hip/hip_runtime.h>
 
