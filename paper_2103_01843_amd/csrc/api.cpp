@@ -354,8 +354,10 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
     nb.lm_slot[l] = (int32_t)s;
     const int64_t W = width_of_h(k);
     nb.slot_zoff[s] = (int32_t)oz;
-    ob += 2 * k * W;
-    ot += 3 * W;
+    // each landmark's rows start on a 128-byte line, so neighbouring blocks
+    // never share a cache line (the QR writes them from different wavefronts)
+    ob += (2 * k * W + 31) & ~int64_t(31);
+    ot += (3 * W + 31) & ~int64_t(31);
     oz += W;
   }
   if (oz > 54 * nb.NO || oz > INT32_MAX) return fail(c, SQRTBA_E_UNSUPPORTED, "product output area too large");

@@ -68,8 +68,8 @@ struct Dev {
   int32_t* slot_k;
   int32_t* slot_obs0;
   int32_t* slot_prob;
-  int64_t* slot_boff;  // float offset of the B rows (2k x W) in poolB
-  int64_t* slot_toff;  // float offset of the undamped top rows (3 x W) in poolT
+  int64_t* slot_boff;  // float offset of the B rows (2k x W) in poolB (128-byte aligned)
+  int64_t* slot_toff;  // float offset of the undamped top rows (3 x W) in poolT (128-byte aligned)
   int32_t* slot_zoff;  // float offset of the landmark's W product outputs in obsbuf (16-byte aligned);
                        // implicit blocks: index of the landmark's first record (outputs at 12 x record)
   int32_t* cam_zpos;   // NO: obsbuf offset of the outputs of each camera's observations (camera order)
