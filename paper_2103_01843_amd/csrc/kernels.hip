@@ -947,17 +947,13 @@ __device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, con
   const int obs0 = d.slot_obs0[slot];
   const int zoff = d.slot_zoff[slot];
   const float4* __restrict__ Bs = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
-  // the problem's flags, then the first rows and the camera gather, all requested
-  // before the flags are tested (every address is in bounds whatever they say)
-  const int act = d.active[prob];
-  const int dn = PCG ? d.done[prob] : 0;
+  if (!d.active[prob] || (PCG && d.done[prob])) return;
   const int G = width_of(k) >> 2, n = 2 * k;
   const float4* __restrict__ Bj = Bs + min(lane, G - 1);
   float4 c[RB];
 #pragma unroll
   for (int i = 0; i < RB; ++i) c[i] = Bj[(size_t)min(i, n - 1) * G];
   const float4 pv = lane < G ? gather_cols(d, v, obs0, k, lane) : make_float4(0.f, 0.f, 0.f, 0.f);
-  if (!act || dn) return;  // uniform over the team
   float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int r = 0; r < n; r += RB) {
     const int rn = r + RB;
