@@ -2112,33 +2112,17 @@ __device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane
   const int prob = d.slot_prob[slot];
   const int k = d.slot_k[slot];
   const int r0 = d.slot_zoff[slot];
-  const int act = d.active[prob];
-  const int dn = PCG ? d.done[prob] : 0;
+  if (!d.active[prob] || (PCG && d.done[prob])) return;  // uniform over the team
   float u[OPL][2];
   float J[OPL][2][9], Q[OPL][2][3];
-  int cm[OPL];
-  // the records of the lane's first observations are requested before the
-  // problem's flags arrive (in bounds whatever the flags say)
-#pragma unroll
-  for (int m = 0; m < (KEEP ? OPL : 1); ++m) {
-    const int o = lane + TEAM * m;
-    if (o < k) {
-      cm[m] = d.rec_cam[r0 + o];
-      load_rec(d, r0 + o, J[m], Q[m]);
-    }
-  }
-  if (!act || dn) return;  // uniform over the team
   float c[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     u[m][0] = u[m][1] = 0.f;
     if (o < k) {
-      if (m >= (KEEP ? OPL : 1)) {
-        cm[m] = d.rec_cam[r0 + o];
-        load_rec(d, r0 + o, J[m], Q[m]);
-      }
-      const float4* vs = reinterpret_cast<const float4*>(d.vzs) + 3 * (size_t)cm[m];
+      const float4* vs = reinterpret_cast<const float4*>(d.vzs) + 3 * (size_t)d.rec_cam[r0 + o];
+      load_rec(d, r0 + o, J[m], Q[m]);
       const float4 v0 = vs[0], v1 = vs[1], v2 = vs[2];
       const float pa[9] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x};
 #pragma unroll
