@@ -229,9 +229,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default product launch shapes")
-    ap.add_argument("--blocks", choices=["explicit", "implicit"], default="explicit",
+    ap.add_argument("--blocks", choices=["explicit", "implicit", "sc"], default="explicit",
                     help="landmark blocks of the timed solves: explicit (the paper's stored nullspace blocks "
-                         "Q2^T J_p, O(k^2) per landmark; default) or implicit (J_p and Q1 per observation, O(k))")
+                         "Q2^T J_p, O(k^2) per landmark; default), implicit (J_p and Q1 per observation, O(k)) "
+                         "or sc (the explicit FP32 Schur-complement comparator, camera-pair blocks)")
     ap.add_argument("--no-other-blocks", action="store_true",
                     help="skip the extra measurement of the other landmark-block form")
     ap.add_argument("--no-forcing", action="store_true",
@@ -268,7 +269,7 @@ def main():
     log(f"workload: {stats}")
     torch.cuda.synchronize()
     t_up = time.perf_counter()
-    blocks = 1 if args.blocks == "implicit" else 0
+    blocks = {"explicit": 0, "implicit": 1, "sc": 2}[args.blocks]
     ctx = Context(stream=torch.cuda.current_stream(), max_lm_iters=args.lm_iters, landmark_blocks=blocks)
     ctx.load(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)
     ctx.bind_torch_workspace()
@@ -360,10 +361,10 @@ def main():
     # blocks need no O(k^2) storage): timed solves and its product
     other = None
     if not args.no_other_blocks:
-        other = other_blocks_run(p, args, 0 if blocks else 1)
+        other = other_blocks_run(p, args, 1 if blocks == 0 else 0)
     # the paper's explicit-solver comparator: FP32 Schur complement from the normal equations
     sc = None
-    if not args.no_sc:
+    if not args.no_sc and blocks != 2:
         try:
             sc = other_blocks_run(p, args, 2)
         except Exception as e:  # e.g. too many camera-pair contributions (dense workload)
@@ -490,7 +491,9 @@ def main():
                 "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": traffic,
                 "kernel": ("the PCG product over all landmark blocks (k_matvec, plus k_matvec_large / "
                            "k_matvec_rows + k_matvec_combine where those size classes exist)")
-                          if args.blocks == "explicit" else "the PCG product over implicit blocks (k_matvec_implicit)",
+                          if args.blocks == "explicit" else
+                          "the PCG product over implicit blocks (k_matvec_implicit)" if args.blocks == "implicit" else
+                          "the product with the assembled FP32 Schur complement (k_sc_matvec)",
                 "avg_launch_ms": mv_ms, "algorithmic_bytes_per_launch": mv_bytes, "launches_timed": 50,
                 "timing": "HIP events around 50 back-to-back products on the resident blocks, context stream",
                 "traffic_source": traffic_note,
