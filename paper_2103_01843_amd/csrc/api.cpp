@@ -588,7 +588,7 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
   uint64_t o_s[10];
   for (int i = 0; i < 10; ++i) o_s[i] = f64(P);
   uint64_t o_it = f32(P), o_dn = f32(P), o_ps = f32(P), o_act = L.take(P), o_flag = L.take(P);
-  uint64_t o_cf = f32(4);
+  uint64_t o_cf = f32(4), o_skip = f32(1);
   uint64_t o_csnap = f32(16 * NC), o_psnap = f32(4 * NL);
   uint64_t o_feat = f32(64 * NC), o_lfac = f32(45 * NC), o_cst = f32(4 * NC);
   if (base && d) {
@@ -631,6 +631,7 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
     t.iters = at<int32_t>(base, o_it); t.done = at<int32_t>(base, o_dn); t.pstatus = at<int32_t>(base, o_ps);
     t.active = at<uint8_t>(base, o_act); t.flag = at<uint8_t>(base, o_flag);
     t.chol_fail = at<int32_t>(base, o_cf);
+    t.pcg_skip = at<int32_t>(base, o_skip);
     t.cam_snap = at<float>(base, o_csnap); t.pts_snap = at<float4>(base, o_psnap);
     t.feats = at<float>(base, o_feat); t.lfac = at<float>(base, o_lfac); t.cam_stats = at<float>(base, o_cst);
     *d = t;

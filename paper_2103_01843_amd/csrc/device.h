@@ -110,6 +110,8 @@ struct Dev {
   int32_t* sc_rowoff;    // NC + 1: blocks of each camera's row of the reduced matrix (CSR)
   int2* sc_rowent;       // (block | transposed << 31, other camera)
   float* vy;             // 9 NC: the Schur-complement product of the last launch
+  int32_t* pcg_skip;     // 1 int: some problem is inactive or done in the running PCG solve (the
+                         // products then test a landmark's problem before reading its data)
   float* obsbuf;  // NO * 54 floats: per-observation preconditioner terms; the product outputs
                   // reuse it in per-landmark aligned regions (slot_zoff)
   float* dxl;     // NL * 3, unscaled landmark increment

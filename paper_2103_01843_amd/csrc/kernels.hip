@@ -947,13 +947,20 @@ __device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, con
   const int obs0 = d.slot_obs0[slot];
   const int zoff = d.slot_zoff[slot];
   const float4* __restrict__ Bs = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
-  if (!d.active[prob] || (PCG && d.done[prob])) return;
+  // While every problem of the PCG solve is still running, the first rows and the
+  // camera gather are requested before the problem's flags are tested (all these
+  // addresses are in bounds whatever the flags say); once one has stopped, its
+  // landmarks are tested first so that their blocks are not read.
+  const int act = d.active[prob];
+  const int dn = PCG ? d.done[prob] : 0;
+  if (PCG && d.pcg_skip[0] && (!act || dn)) return;
   const int G = width_of(k) >> 2, n = 2 * k;
   const float4* __restrict__ Bj = Bs + min(lane, G - 1);
   float4 c[RB];
 #pragma unroll
   for (int i = 0; i < RB; ++i) c[i] = Bj[(size_t)min(i, n - 1) * G];
   const float4 pv = lane < G ? gather_cols(d, v, obs0, k, lane) : make_float4(0.f, 0.f, 0.f, 0.f);
+  if (!act || dn) return;  // uniform over the team
   float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int r = 0; r < n; r += RB) {
     const int rn = r + RB;
@@ -1272,6 +1279,8 @@ __global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
 // beta is exactly 1 and p = z0 (p and q start at 0).
 __global__ __launch_bounds__(WG) void k_pcg_init_scalars(Dev d) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) d.pcg_skip[0] = 0;
+  __syncthreads();
   for (int p = w; p < d.P; p += WG / 64) {
     double rz, rr;
     problem_sum2(d, d.cam_part2, d.cam_part3, p, lane, rz, rr);
@@ -1283,10 +1292,11 @@ __global__ __launch_bounds__(WG) void k_pcg_init_scalars(Dev d) {
       d.iters[p] = 0;
       d.qmod[p] = 0.0;  // Q(x_0) = 0
       d.dqmod[p] = 0.0;
-      if (!d.active[p]) { d.done[p] = 1; d.pstatus[p] = 4; }
+      if (!d.active[p]) { d.done[p] = 1; d.pstatus[p] = 4; d.pcg_skip[0] = 1; }
       else if (!(rr > 0.0) || !(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {
         d.done[p] = 1;
         d.pstatus[p] = (rr == 0.0) ? 3 : 2;
+        d.pcg_skip[0] = 1;
       } else { d.done[p] = 0; d.pstatus[p] = 1; }
     }
   }
@@ -1356,6 +1366,7 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
         if (t) {
           d.done[prob] = 1;
           d.pstatus[prob] = t == 1 ? 0 : 2;
+          d.pcg_skip[0] = 1;
         } else {
           d.rz_next[prob] = rz;
           d.beta[prob] = beta;
@@ -1489,6 +1500,7 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
           } else {
             d.done[p] = 1;
             d.pstatus[p] = 2;  // breakdown: x kept
+            d.pcg_skip[0] = 1;
           }
         }
         if (!ok) al = 0.f;
@@ -1548,6 +1560,7 @@ __global__ __launch_bounds__(WG) void k_pcg_final(Dev d) {
       if (t) {
         d.done[p] = 1;
         d.pstatus[p] = t == 1 ? 0 : 2;
+        d.pcg_skip[0] = 1;
       }
     }
   }
@@ -2112,17 +2125,35 @@ __device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane
   const int prob = d.slot_prob[slot];
   const int k = d.slot_k[slot];
   const int r0 = d.slot_zoff[slot];
-  if (!d.active[prob] || (PCG && d.done[prob])) return;  // uniform over the team
+  // the records of the lane's first observations are requested before the
+  // problem's flags are tested while every problem of the PCG solve is running
+  // (in bounds whatever the flags say), after the test once one has stopped
+  const int act = d.active[prob];
+  const int dn = PCG ? d.done[prob] : 0;
+  if (PCG && d.pcg_skip[0] && (!act || dn)) return;
   float u[OPL][2];
   float J[OPL][2][9], Q[OPL][2][3];
+  int cm[OPL];
+#pragma unroll
+  for (int m = 0; m < (KEEP ? OPL : 1); ++m) {
+    const int o = lane + TEAM * m;
+    if (o < k) {
+      cm[m] = d.rec_cam[r0 + o];
+      load_rec(d, r0 + o, J[m], Q[m]);
+    }
+  }
+  if (!act || dn) return;  // uniform over the team
   float c[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     u[m][0] = u[m][1] = 0.f;
     if (o < k) {
-      const float4* vs = reinterpret_cast<const float4*>(d.vzs) + 3 * (size_t)d.rec_cam[r0 + o];
-      load_rec(d, r0 + o, J[m], Q[m]);
+      if (m >= (KEEP ? OPL : 1)) {
+        cm[m] = d.rec_cam[r0 + o];
+        load_rec(d, r0 + o, J[m], Q[m]);
+      }
+      const float4* vs = reinterpret_cast<const float4*>(d.vzs) + 3 * (size_t)cm[m];
       const float4 v0 = vs[0], v1 = vs[1], v2 = vs[2];
       const float pa[9] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x};
 #pragma unroll
