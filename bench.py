@@ -14,9 +14,11 @@ the production configuration: graph-captured PCG, no profiler), QR blocks/s
 and the stage breakdown (one more profiled solve), PCG matvec GB/s with its
 roofline (HIP events around back-to-back products on the resident blocks,
 algorithmic bytes 4 (18 k^2 + 9 k) per landmark), the learned preconditioner
-against block-Jacobi, and the FP64 oracle's CPU baseline on a bounded sample.
+against block-Jacobi, the same solve in FP64 (libsqrtba64.so, "sqrt_ba_64"), and
+the FP64 oracle's CPU baseline on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--config {1,2,3,4}]
+    python bench.py --precision 64     # the FP64 library as the timed path
     python bench.py --calibrate-copy   # known-size copy, for counter scaling
 """
 
@@ -175,17 +177,20 @@ def learned_run(ctx, n_problems: int, lm_iters: int):
             "train_loss_first_last": [losses[0], losses[-1]], **stats}
 
 
-def other_blocks_run(p, args, blocks: int):
+def other_blocks_run(p, args, blocks: int, precision: int = 32):
     """Timed solves (same steps and warm-up) and the product timing with the given
-    landmark-block form; returns its reports, histories and figures."""
+    landmark-block form and precision; returns its reports, histories and figures."""
     import torch
     from paper_2103_01843_amd import Context
 
-    ctx = Context(stream=torch.cuda.current_stream(), max_lm_iters=args.lm_iters, landmark_blocks=blocks)
+    ctx = Context(stream=torch.cuda.current_stream(), max_lm_iters=args.lm_iters, landmark_blocks=blocks,
+                  precision=precision)
     ctx.load(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)
     ctx.bind_torch_workspace()
     ctx.save_state()
     ws = ctx.workspace_bytes()
+    if blocks == 0 and not args.no_autotune:
+        ctx.autotune(reps=10)
     for _ in range(args.warmup):
         ctx.restore_state()
         ctx.lm_solve()
@@ -202,7 +207,8 @@ def other_blocks_run(p, args, blocks: int):
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
-    log(f"{['explicit', 'implicit', 'explicit Schur complement'][blocks]} blocks: {1e3 * wall / args.steps:.1f} ms per solve, "
+    log(f"{['explicit', 'implicit', 'explicit Schur complement'][blocks]} blocks, FP{precision}: "
+        f"{1e3 * wall / args.steps:.1f} ms per solve, "
         f"product {1e3 * mv_ms:.1f} us, workspace {ws / 1e9:.2f} GB")
     return {"runs": runs, "wall": wall, "mv_ms": mv_ms, "mv_bytes": mv_bytes, "workspace_bytes": ws}
 
@@ -239,6 +245,10 @@ def main():
                     help="skip the solve with the forcing-sequence PCG truncation (eta = 0.1)")
     ap.add_argument("--no-huber", action="store_true",
                     help="skip the solve with the Huber loss (delta = 1 px, IRLS)")
+    ap.add_argument("--precision", type=int, choices=[32, 64], default=32,
+                    help="element type of the timed path: 32 (libsqrtba.so, the default) or 64 (libsqrtba64.so)")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 solve of the same workload (reported as sqrt_ba_64)")
     ap.add_argument("--no-sc", action="store_true",
                     help="skip the explicit FP32 Schur-complement comparator (landmark_blocks = 2)")
     ap.add_argument("--tuning", default=None, metavar="EDGE,ROWS,SIDE,SEP,BATCH,PERSIST",
@@ -270,7 +280,8 @@ def main():
     torch.cuda.synchronize()
     t_up = time.perf_counter()
     blocks = {"explicit": 0, "implicit": 1, "sc": 2}[args.blocks]
-    ctx = Context(stream=torch.cuda.current_stream(), max_lm_iters=args.lm_iters, landmark_blocks=blocks)
+    ctx = Context(stream=torch.cuda.current_stream(), max_lm_iters=args.lm_iters, landmark_blocks=blocks,
+                  precision=args.precision)
     ctx.load(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, p.cam_off, p.pt_off)
     ctx.bind_torch_workspace()
     ctx.save_state()  # first device use: host bookkeeping, then upload over PCIe
@@ -348,7 +359,7 @@ def main():
             f"PCG iterations, robust cost {sum(r.initial_cost for r in hreps):.6g} -> "
             f"{sum(r.final_cost for r in hreps):.6g}, {1e3 * huber['wall_s']:.1f} ms")
     learned = None
-    if not args.no_learned:
+    if not args.no_learned and args.precision == 32:
         try:
             learned = learned_run(ctx, p.n_problems, args.lm_iters)
         except Exception as e:  # reported, never required
@@ -361,15 +372,24 @@ def main():
     # blocks need no O(k^2) storage): timed solves and its product
     other = None
     if not args.no_other_blocks:
-        other = other_blocks_run(p, args, 1 if blocks == 0 else 0)
+        other = other_blocks_run(p, args, 1 if blocks == 0 else 0, args.precision)
     # the paper's explicit-solver comparator: FP32 Schur complement from the normal equations
     sc = None
-    if not args.no_sc and blocks != 2:
+    if not args.no_sc and blocks != 2 and args.precision == 32:
         try:
             sc = other_blocks_run(p, args, 2)
         except Exception as e:  # e.g. too many camera-pair contributions (dense workload)
             log(f"explicit Schur complement comparator skipped: {e}")
             sc = {"skipped": str(e)}
+
+    # square-root BA in FP64 (the paper's double-precision variant), same form and start
+    fp64 = None
+    if not args.no_fp64 and args.precision == 32:
+        try:
+            fp64 = other_blocks_run(p, args, blocks, 64)
+        except Exception as e:  # e.g. the FP64 workspace exceeds the GPU's memory (dense workload)
+            log(f"FP64 solve skipped: {e}")
+            fp64 = {"skipped": str(e)}
 
     # time to 1% cost per problem (appendix A.2), f* over the runs (and the oracle where stored)
     gold = None
@@ -388,6 +408,8 @@ def main():
             finals += [reps[i].final_cost for reps, _ in other["runs"]]
         if sc and "runs" in sc:
             finals += [reps[i].final_cost for reps, _ in sc["runs"]]
+        if fp64 and "runs" in fp64:
+            finals += [reps[i].final_cost for reps, _ in fp64["runs"]]
         fstar = min(finals + ([gold["final_cost"]] if gold and p.n_problems == 1 else []))
         f_tau = fstar + 0.01 * (f0 - fstar)
         f_taus.append((f0, fstar, f_tau))
@@ -438,6 +460,25 @@ def main():
             "product": {"avg_launch_ms": sc["mv_ms"], "algorithmic_bytes_per_launch": sc["mv_bytes"],
                         "achieved_GBps": ach_sc, "frac_of_hbm_peak": ach_sc / HBM_PEAK_GBPS if ach_sc else None},
         }
+    fp64_out = None
+    if fp64 and "skipped" in fp64:
+        fp64_out = {"skipped": fp64["skipped"]}
+    elif fp64:
+        ttt_64 = [max(time_to_tol(h[i], f_taus[i][2]) for i in range(p.n_problems)) for _, h in fp64["runs"]]
+        ach_64 = fp64["mv_bytes"] / (fp64["mv_ms"] * 1e-3) / 1e9 if fp64["mv_ms"] > 0 else None
+        fp64_out = {
+            "landmark_blocks": args.blocks,
+            "time_to_1pct_cost_s": statistics.median(ttt_64),
+            "ms_per_step": 1e3 * fp64["wall"] / args.steps,
+            "fp64_over_fp32_ms_per_step": fp64["wall"] / wall,
+            "final_costs": [sum(r.final_cost for r in reps) for reps, _ in fp64["runs"]],
+            "pcg_iters": sum(r.total_pcg_iters for r in fp64["runs"][-1][0]),
+            "rejected_attempts": sum(sum(1 for x in hh if not x["accepted"]) for hh in fp64["runs"][-1][1]),
+            "workspace_bytes": fp64["workspace_bytes"],
+            "product": {"avg_launch_ms": fp64["mv_ms"], "algorithmic_bytes_per_launch": fp64["mv_bytes"],
+                        "achieved_GBps": ach_64, "frac_of_hbm_peak": ach_64 / HBM_PEAK_GBPS if ach_64 else None,
+                        "fp64_over_fp32_ms": fp64["mv_ms"] / mv_ms if mv_ms > 0 else None},
+        }
     huber_out = None
     if huber:
         hgold = None
@@ -478,7 +519,8 @@ def main():
     qr = prof["marginalize"]
     achieved = mv_bytes / (mv_ms * 1e-3) / 1e9 if mv_ms > 0 else None
     traffic, traffic_note = None, None
-    tfile = (os.path.join(ROOT, "profiles", f"matvec_traffic_{TRAFFIC_TAG[cfg]}_{args.blocks}.json")
+    ptag = "_fp64" if args.precision == 64 else ""
+    tfile = (os.path.join(ROOT, "profiles", f"matvec_traffic_{TRAFFIC_TAG[cfg]}_{args.blocks}{ptag}.json")
              if cfg in TRAFFIC_TAG else None)
     if tfile and os.path.exists(tfile):
         with open(tfile) as f:
@@ -489,11 +531,12 @@ def main():
                             f"launch shapes {tr['shape']}")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": traffic,
-                "kernel": ("the PCG product over all landmark blocks (k_matvec, plus k_matvec_large / "
+                "kernel": (("the PCG product over all landmark blocks (k_matvec, plus k_matvec_large / "
                            "k_matvec_rows + k_matvec_combine where those size classes exist)")
                           if args.blocks == "explicit" else
                           "the PCG product over implicit blocks (k_matvec_implicit)" if args.blocks == "implicit" else
-                          "the product with the assembled FP32 Schur complement (k_sc_matvec)",
+                          "the product with the assembled FP32 Schur complement (k_sc_matvec)")
+                + (", FP64 build (libsqrtba64.so)" if args.precision == 64 else ""),
                 "avg_launch_ms": mv_ms, "algorithmic_bytes_per_launch": mv_bytes, "launches_timed": 50,
                 "timing": "HIP events around 50 back-to-back products on the resident blocks, context stream",
                 "traffic_source": traffic_note,
@@ -525,7 +568,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.precision == 64 else "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[cfg], "landmark_blocks": args.blocks, "n_problems": p.n_problems,
                    "n_cams": stats["n_cams"], "n_points": stats["n_points"], "n_obs": stats["n_obs"],
@@ -548,6 +591,7 @@ def main():
         "explicit_sc_comparator": sc_out,
         ("explicit_blocks" if blocks else "implicit_blocks"): other_out,
         "learned_vs_block_jacobi": learned_out,
+        "sqrt_ba_64": fp64_out,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -1,7 +1,10 @@
-"""Build libsqrtba.so (HIP for gfx950) in-tree with hipcc.
+"""Build libsqrtba.so (FP32) and libsqrtba64.so (FP64) for gfx950 in-tree with hipcc.
 
-    python -m paper_2103_01843_amd.build          # release build
-    python -m paper_2103_01843_amd.build --check  # print the command only
+Both libraries come from the same sources; the FP64 one is compiled with
+SQRTBA_FP64, which makes the element type of every kernel and buffer double.
+
+    python -m paper_2103_01843_amd.build          # release build of both
+    python -m paper_2103_01843_amd.build --check  # print the commands only
 """
 
 from __future__ import annotations
@@ -14,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsqrtba.so")
+LIB64 = os.path.join(HERE, "libsqrtba64.so")
 SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "learned.hip"), os.path.join(CSRC, "api.cpp")]
 ARCH = "gfx950"
 
@@ -34,27 +38,37 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def command(out: str = LIB):
-    return [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), *SOURCES, "-o", out]
+def command(out: str = LIB, fp64: bool = False):
+    return [hipcc(), *FLAGS, *(["-DSQRTBA_FP64"] if fp64 else []), "-I", os.path.join(ROOT, "include"), *SOURCES,
+            "-o", out]
 
 
 def build(verbose: bool = True) -> str:
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    errs = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{errs}")
-    if verbose and errs:
-        print(errs, file=sys.stderr)
-    os.replace(tmp, LIB)
+    """Compile both libraries (concurrently) and move them into place; returns the FP32 path."""
+    jobs = []
+    for lib, fp64 in ((LIB, False), (LIB64, True)):
+        cmd = command(lib + ".tmp", fp64)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        jobs.append((lib, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    failed = []
+    for lib, proc in jobs:
+        _, err = proc.communicate()
+        errs = "\n".join(l for l in err.splitlines() if "packed-fp32-ops" not in l and l.strip())
+        if proc.returncode != 0:
+            failed.append(f"{os.path.basename(lib)}: hipcc failed ({proc.returncode}):\n{errs}")
+        elif verbose and errs:
+            print(errs, file=sys.stderr)
+    if failed:
+        raise RuntimeError("\n".join(failed))
+    for lib, _ in jobs:
+        os.replace(lib + ".tmp", lib)
     return LIB
 
 
 if __name__ == "__main__":
     if "--check" in sys.argv:
         print(" ".join(command()))
+        print(" ".join(command(LIB64, True)))
     else:
         build()

@@ -1,4 +1,5 @@
-// Host side of libsqrtba.so: the C ABI of include/sqrtba.h, observation
+// Host side of libsqrtba.so (and, built with SQRTBA_FP64, of libsqrtba64.so):
+// the C ABI of include/sqrtba.h (include/sqrtba64.h), observation
 // bookkeeping, device memory layout and the Levenberg-Marquardt loop.
 // Every floating-point step of the solve runs in the HIP kernels of
 // kernels.hip; the host only sorts indices, moves data, reads back per-problem
@@ -16,7 +17,15 @@
 #include <string>
 #include <vector>
 
+#ifdef SQRTBA_FP64
+// libsqrtba64.so: the same host code over FP64 kernels, with its own context type
+#define sqrtba_ctx sqrtba64_ctx
+#include "../../include/sqrtba64.h"
+#define SQRTBA_API(name) sqrtba64_##name
+#else
 #include "../../include/sqrtba.h"
+#define SQRTBA_API(name) sqrtba_##name
+#endif
 #include "device.h"
 #include "learned.h"
 
@@ -33,15 +42,15 @@ struct HostData {
   bool problems_set = false;
   // inputs
   int64_t NC = -1, NL = -1;
-  std::vector<float> cams_bal;  // NC * 9
-  std::vector<float> pts;       // NL * 3
+  std::vector<real> cams_bal;  // NC * 9
+  std::vector<real> pts;       // NL * 3
   // bookkeeping
   bool obs_set = false;
   int64_t n_obs_in = 0, NO = 0, NS = 0;
   std::vector<int64_t> obs_perm, lm_off;
   std::vector<uint8_t> lm_active, cam_active;
   std::vector<int32_t> ocam, olm;
-  std::vector<float> ouv;
+  std::vector<real> ouv;
   std::vector<int32_t> cam_obs_off, cam_obs_idx, cam_prob, lm_prob, prob_cam_off, prob_lm_off;
   std::vector<int32_t> slot_lm, slot_k, slot_obs0, slot_prob, lm_slot;
   std::vector<int64_t> slot_boff, slot_toff;
@@ -253,7 +262,7 @@ int64_t slots_with_k_at_least(const HostData& h, int64_t kmin) {
 
 int build_sc(sqrtba_ctx* c);
 
-int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_t* pt, const float* uv) {
+int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_t* pt, const real* uv) {
   HostData& h = c->h;
   if (n <= 0) return fail(c, SQRTBA_E_INVALID, "n_obs must be positive");
   if (!cam || !pt || !uv) return fail(c, SQRTBA_E_INVALID, "null observation array");
@@ -398,7 +407,7 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
   nb.qjob.clear();
   for (int64_t sl = nb.wc[5].first_slot; sl < nb.wc[5].first_slot + nb.wc[5].slots; ++sl) {
     const int64_t n = 2 * nb.slot_k[sl];
-    const int64_t rows = std::max<int64_t>(1, QR_CHUNK_BYTES / (4 * width_of_h(nb.slot_k[sl])));
+    const int64_t rows = std::max<int64_t>(1, QR_CHUNK_BYTES / ((int64_t)sizeof(real) * width_of_h(nb.slot_k[sl])));
     for (int64_t r = 0; r < n; r += rows) {
       nb.qjob.push_back((int32_t)sl);
       nb.qjob.push_back((int32_t)(r | (std::min(n, r + rows) << 16)));
@@ -566,36 +575,37 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
   Dev t{};
   auto f32 = [&](uint64_t n) { return L.take(4 * n); };
   auto f64 = [&](uint64_t n) { return L.take(8 * n); };
-  uint64_t o_cam = f32(16 * NC), o_camn = f32(16 * NC), o_pts = f32(4 * NL), o_ptsn = f32(4 * NL);
-  uint64_t o_ocam = f32(NO), o_olm = f32(NO), o_ouv = f32(2 * NO), o_coo = f32(NC + 1), o_coi = f32(NO);
+  auto fr = [&](uint64_t n) { return L.take(sizeof(real) * n); };
+  uint64_t o_cam = fr(16 * NC), o_camn = fr(16 * NC), o_pts = fr(4 * NL), o_ptsn = fr(4 * NL);
+  uint64_t o_ocam = f32(NO), o_olm = f32(NO), o_ouv = fr(2 * NO), o_coo = f32(NC + 1), o_coi = f32(NO);
   uint64_t o_cpr = f32(NC), o_lpr = f32(NL), o_pco = f32(P + 1), o_plo = f32(P + 1);
   uint64_t o_slm = f32(NS), o_sk = f32(NS), o_so = f32(NS), o_sp = f32(NS), o_sb = f64(NS), o_st = f64(NS);
   uint64_t o_sz = f32(NS), o_czp = f32(NO);
   uint64_t o_lms = f32(NL);
-  uint64_t o_qj = f32(h.qjob.size()), o_hj = f32(h.hjob.size()), o_hzo = f64(h.hz_off.size()), o_zp = f32(h.hz_floats);
+  uint64_t o_qj = f32(h.qjob.size()), o_hj = f32(h.hjob.size()), o_hzo = f64(h.hz_off.size()), o_zp = fr(h.hz_floats);
   const uint64_t nB = implicit ? 0 : h.poolB, nT = implicit ? 0 : h.poolT, nrho = implicit ? 0 : 2 * NO;
-  uint64_t o_pB = f32(nB), o_pT = f32(nT), o_lmd = f32(NS * LMD_STRIDE), o_rho = f32(nrho);
-  uint64_t o_rec = f32(implicit ? 4 * (uint64_t)REC_PLANES * NO : 0), o_rcam = f32(implicit ? NO : 0);
-  uint64_t o_vzs = f32(12 * NC);
+  uint64_t o_pB = fr(nB), o_pT = fr(nT), o_lmd = fr(NS * LMD_STRIDE), o_rho = fr(nrho);
+  uint64_t o_rec = fr(implicit ? 4 * (uint64_t)REC_PLANES * NO : 0), o_rcam = f32(implicit ? NO : 0);
+  uint64_t o_vzs = fr(12 * NC);
   const uint64_t nsb = sc ? (uint64_t)(h.sc.noff + NC) * 81 : 0;
-  uint64_t o_scb = f32(nsb), o_scoff = f32(sc ? h.sc.coff.size() : 0), o_scc = f32(sc ? h.sc.contrib.size() : 0);
-  uint64_t o_scro = f32(sc ? h.sc.rowoff.size() : 0), o_scre = f32(sc ? h.sc.rowent.size() : 0), o_vy = f32(9 * NC);
-  uint64_t o_sc = f32(9 * NC);
+  uint64_t o_scb = fr(nsb), o_scoff = f32(sc ? h.sc.coff.size() : 0), o_scc = f32(sc ? h.sc.contrib.size() : 0);
+  uint64_t o_scro = f32(sc ? h.sc.rowoff.size() : 0), o_scre = f32(sc ? h.sc.rowent.size() : 0), o_vy = fr(9 * NC);
+  uint64_t o_sc = fr(9 * NC);
   uint64_t o_v[6];
-  for (int i = 0; i < 6; ++i) o_v[i] = f32(9 * NC);
-  uint64_t o_minv = f32(81 * NC), o_ob = f32(54 * NO), o_dxl = f32(3 * NL);
+  for (int i = 0; i < 6; ++i) o_v[i] = fr(9 * NC);
+  uint64_t o_minv = fr(81 * NC), o_ob = fr(54 * NO), o_dxl = fr(3 * NL);
   uint64_t o_cp = f64(NC), o_cp2 = f64(NC), o_cp3 = f64(NC), o_lp = f64(NL);
   uint64_t o_s[10];
   for (int i = 0; i < 10; ++i) o_s[i] = f64(P);
   uint64_t o_it = f32(P), o_dn = f32(P), o_ps = f32(P), o_act = L.take(P), o_flag = L.take(P);
   uint64_t o_cf = f32(4), o_skip = f32(1);
-  uint64_t o_csnap = f32(16 * NC), o_psnap = f32(4 * NL);
+  uint64_t o_csnap = fr(16 * NC), o_psnap = fr(4 * NL);
   uint64_t o_feat = f32(64 * NC), o_lfac = f32(45 * NC), o_cst = f32(4 * NC);
   if (base && d) {
     t.P = (int32_t)P; t.NC = (int32_t)NC; t.NL = (int32_t)NL; t.NS = (int32_t)NS; t.NO = (int32_t)NO;
-    t.cam = at<float>(base, o_cam); t.cam_new = at<float>(base, o_camn);
-    t.pts = at<float4>(base, o_pts); t.pts_new = at<float4>(base, o_ptsn);
-    t.obs_cam = at<int32_t>(base, o_ocam); t.obs_lm = at<int32_t>(base, o_olm); t.obs_uv = at<float2>(base, o_ouv);
+    t.cam = at<real>(base, o_cam); t.cam_new = at<real>(base, o_camn);
+    t.pts = at<real4>(base, o_pts); t.pts_new = at<real4>(base, o_ptsn);
+    t.obs_cam = at<int32_t>(base, o_ocam); t.obs_lm = at<int32_t>(base, o_olm); t.obs_uv = at<real2>(base, o_ouv);
     t.cam_obs_off = at<int32_t>(base, o_coo); t.cam_obs_idx = at<int32_t>(base, o_coi);
     t.cam_prob = at<int32_t>(base, o_cpr); t.lm_prob = at<int32_t>(base, o_lpr);
     t.prob_cam_off = at<int32_t>(base, o_pco); t.prob_lm_off = at<int32_t>(base, o_plo);
@@ -603,25 +613,25 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
     t.slot_prob = at<int32_t>(base, o_sp); t.slot_boff = at<int64_t>(base, o_sb); t.slot_toff = at<int64_t>(base, o_st);
     t.slot_zoff = at<int32_t>(base, o_sz); t.cam_zpos = at<int32_t>(base, o_czp);
     t.lm_slot = at<int32_t>(base, o_lms);
-    t.qjob = at<int2>(base, o_qj); t.hjob = at<int2>(base, o_hj); t.hz_off = at<int64_t>(base, o_hzo); t.zpart = at<float>(base, o_zp);
-    t.poolB = at<float>(base, o_pB); t.poolT = at<float>(base, o_pT); t.lmd = at<float>(base, o_lmd);
-    t.rhoB = implicit ? nullptr : at<float>(base, o_rho); t.s_cam = at<float>(base, o_sc);
+    t.qjob = at<int2>(base, o_qj); t.hjob = at<int2>(base, o_hj); t.hz_off = at<int64_t>(base, o_hzo); t.zpart = at<real>(base, o_zp);
+    t.poolB = at<real>(base, o_pB); t.poolT = at<real>(base, o_pT); t.lmd = at<real>(base, o_lmd);
+    t.rhoB = implicit ? nullptr : at<real>(base, o_rho); t.s_cam = at<real>(base, o_sc);
     if (implicit) { t.poolB = nullptr; t.poolT = nullptr; }
-    t.obsrec = implicit ? at<float>(base, o_rec) : nullptr;
+    t.obsrec = implicit ? at<real>(base, o_rec) : nullptr;
     t.rec_cam = implicit ? at<int32_t>(base, o_rcam) : nullptr;
-    t.vzs = at<float>(base, o_vzs);
+    t.vzs = at<real>(base, o_vzs);
     t.implicit = implicit ? 1 : 0;
     t.sc = sc ? 1 : 0;
     t.sc_noff = sc ? (int32_t)h.sc.noff : 0;
-    t.scb = sc ? at<float>(base, o_scb) : nullptr;
+    t.scb = sc ? at<real>(base, o_scb) : nullptr;
     t.sc_coff = sc ? at<int32_t>(base, o_scoff) : nullptr;
     t.sc_contrib = sc ? at<int4>(base, o_scc) : nullptr;
     t.sc_rowoff = sc ? at<int32_t>(base, o_scro) : nullptr;
     t.sc_rowent = sc ? at<int2>(base, o_scre) : nullptr;
-    t.vy = at<float>(base, o_vy);
-    t.vx = at<float>(base, o_v[0]); t.vr = at<float>(base, o_v[1]); t.vz = at<float>(base, o_v[2]);
-    t.vp = at<float>(base, o_v[3]); t.vq = at<float>(base, o_v[4]); t.vb = at<float>(base, o_v[5]);
-    t.minv = at<float>(base, o_minv); t.obsbuf = at<float>(base, o_ob); t.dxl = at<float>(base, o_dxl);
+    t.vy = at<real>(base, o_vy);
+    t.vx = at<real>(base, o_v[0]); t.vr = at<real>(base, o_v[1]); t.vz = at<real>(base, o_v[2]);
+    t.vp = at<real>(base, o_v[3]); t.vq = at<real>(base, o_v[4]); t.vb = at<real>(base, o_v[5]);
+    t.minv = at<real>(base, o_minv); t.obsbuf = at<real>(base, o_ob); t.dxl = at<real>(base, o_dxl);
     t.cam_part = at<double>(base, o_cp); t.cam_part2 = at<double>(base, o_cp2); t.cam_part3 = at<double>(base, o_cp3);
     t.lm_part = at<double>(base, o_lp);
     t.lambda = at<double>(base, o_s[0]); t.rz_next = at<double>(base, o_s[1]); t.beta = at<double>(base, o_s[2]);
@@ -632,7 +642,7 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
     t.active = at<uint8_t>(base, o_act); t.flag = at<uint8_t>(base, o_flag);
     t.chol_fail = at<int32_t>(base, o_cf);
     t.pcg_skip = at<int32_t>(base, o_skip);
-    t.cam_snap = at<float>(base, o_csnap); t.pts_snap = at<float4>(base, o_psnap);
+    t.cam_snap = at<real>(base, o_csnap); t.pts_snap = at<real4>(base, o_psnap);
     t.feats = at<float>(base, o_feat); t.lfac = at<float>(base, o_lfac); t.cam_stats = at<float>(base, o_cst);
     *d = t;
   }
@@ -726,17 +736,17 @@ int set_row_blocks(sqrtba_ctx* c, int rows_min_k, int rows) {
 
 int upload_state(sqrtba_ctx* c) {
   const HostData& h = c->h;
-  std::vector<float> cam(16 * h.NC, 0.f), pts(4 * h.NL, 0.f);
+  std::vector<real> cam(16 * h.NC, 0.f), pts(4 * h.NL, 0.f);
   for (int64_t i = 0; i < h.NC; ++i) {
     double w[3] = {h.cams_bal[9 * i], h.cams_bal[9 * i + 1], h.cams_bal[9 * i + 2]}, R[9];
     so3_exp_d(w, R);
-    for (int j = 0; j < 9; ++j) cam[16 * i + j] = (float)R[j];
+    for (int j = 0; j < 9; ++j) cam[16 * i + j] = (real)R[j];
     for (int j = 0; j < 6; ++j) cam[16 * i + 9 + j] = h.cams_bal[9 * i + 3 + j];
   }
   for (int64_t i = 0; i < h.NL; ++i)
     for (int j = 0; j < 3; ++j) pts[4 * i + j] = h.pts[3 * i + j];
   TRY(upload_vec(c, c->d.cam, cam));
-  TRY(upload_vec(c, reinterpret_cast<float*>(c->d.pts), pts));
+  TRY(upload_vec(c, reinterpret_cast<real*>(c->d.pts), pts));
   return SQRTBA_OK;
 }
 
@@ -744,14 +754,14 @@ int upload(sqrtba_ctx* c) {
   const HostData& h = c->h;
   Dev& d = c->d;
   layout(h, c->opt.landmark_blocks, c->arena.base, &d);
-  d.pcg_tol = (float)c->opt.pcg_rel_tol;
-  d.pcg_eta = (float)c->opt.pcg_forcing_eta;
-  d.huber = (float)c->opt.huber_delta;
+  d.pcg_tol = (real)c->opt.pcg_rel_tol;
+  d.pcg_eta = (real)c->opt.pcg_forcing_eta;
+  d.huber = (real)c->opt.huber_delta;
   HIP_TRY(c, hipMemsetAsync(c->arena.base, 0, c->arena.bytes, c->stream));
   TRY(upload_state(c));
   TRY(upload_vec(c, d.obs_cam, h.ocam));
   TRY(upload_vec(c, d.obs_lm, h.olm));
-  TRY(upload_vec(c, reinterpret_cast<float*>(d.obs_uv), h.ouv));
+  TRY(upload_vec(c, reinterpret_cast<real*>(d.obs_uv), h.ouv));
   TRY(upload_vec(c, d.cam_obs_off, h.cam_obs_off));
   TRY(upload_vec(c, d.cam_obs_idx, h.cam_obs_idx));
   TRY(upload_vec(c, d.cam_prob, h.cam_prob));
@@ -832,6 +842,7 @@ int upload(sqrtba_ctx* c) {
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
   }
+  const double RB = sizeof(real);  // bytes per element
   c->mv_bytes.assign(h.P, 0.0);
   c->qr_bytes.assign(h.P, 0.0);
   c->blocks.assign(h.P, 0);
@@ -840,19 +851,19 @@ int upload(sqrtba_ctx* c) {
     const int p = h.slot_prob[sl];
     if (c->opt.landmark_blocks == 2) {
       // explicit Schur complement: the per-landmark preparation writes the 28-float records
-      c->qr_bytes[p] += 4.0 * (28.0 * k + 12.0) + 12.0 * k + 16.0;
+      c->qr_bytes[p] += RB * (28.0 * k + 12.0) + (4.0 + 2.0 * RB) * k + 4.0 * RB;
     } else if (c->opt.landmark_blocks == 1) {
       // implicit: read the 24 Jacobian and Q1 floats and the camera index per
       // observation and the 6 floats of P, write 9k per-observation outputs; the
       // QR writes the 28-float records
-      c->mv_bytes[p] += 4.0 * (25.0 * k + 6.0 + 9.0 * k);
-      c->qr_bytes[p] += 4.0 * (28.0 * k + 12.0) + 12.0 * k + 16.0;
+      c->mv_bytes[p] += RB * (25.0 * k + 6.0 + 9.0 * k);
+      c->qr_bytes[p] += RB * (28.0 * k + 12.0) + (4.0 + 2.0 * RB) * k + 4.0 * RB;
     } else {
       // matvec: read the 2k x 9k B rows, write 9k per-observation outputs
-      c->mv_bytes[p] += 4.0 * (18.0 * k * k + 9.0 * k);
+      c->mv_bytes[p] += RB * (18.0 * k * k + 9.0 * k);
       // QR: write 2k rotated rows (9k pose columns + residual) and the 12-float
       // landmark record; read camera index and pixel per observation, the landmark
-      c->qr_bytes[p] += 4.0 * (2.0 * k * (9.0 * k + 1.0) + 12.0) + 12.0 * k + 16.0;
+      c->qr_bytes[p] += RB * (2.0 * k * (9.0 * k + 1.0) + 12.0) + (4.0 + 2.0 * RB) * k + 4.0 * RB;
     }
     c->blocks[p] += 1;
   }
@@ -860,8 +871,8 @@ int upload(sqrtba_ctx* c) {
     // product with the reduced matrix: every off-diagonal block is read from both of
     // its cameras' rows, every diagonal block once (81 floats and the 12-float
     // gathered vector each), and 9 outputs per camera are written
-    for (int64_t b = 0; b < h.sc.noff; ++b) c->mv_bytes[h.sc.blk_prob[b]] += 2.0 * 4.0 * (81.0 + 12.0);
-    for (int64_t q = 0; q < h.NC; ++q) c->mv_bytes[h.cam_prob[q]] += 4.0 * (81.0 + 12.0 + 9.0);
+    for (int64_t b = 0; b < h.sc.noff; ++b) c->mv_bytes[h.sc.blk_prob[b]] += 2.0 * RB * (81.0 + 12.0);
+    for (int64_t q = 0; q < h.NC; ++q) c->mv_bytes[h.cam_prob[q]] += RB * (81.0 + 12.0 + 9.0);
   }
   c->snapshot = false;
   c->uploaded = true;
@@ -1362,9 +1373,9 @@ int lm_loop(sqrtba_ctx* c, const double* tol_cost, sqrtba_lm_report* rep) {
 
 extern "C" {
 
-int32_t sqrtba_version(void) { return kVersion; }
+int32_t SQRTBA_API(version)(void) { return kVersion; }
 
-void sqrtba_default_options(sqrtba_options* o) {
+void SQRTBA_API(default_options)(sqrtba_options* o) {
   if (!o) return;
   o->lambda0 = 1e-4;
   o->lambda_min = 1e-16;
@@ -1388,12 +1399,12 @@ static bool valid_options(const sqrtba_options& o) {
          o.huber_delta >= 0.0;
 }
 
-int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_stream) {
+int32_t SQRTBA_API(create)(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_stream) {
   if (!out) return SQRTBA_E_INVALID;
   *out = nullptr;
   sqrtba_ctx* c = new (std::nothrow) sqrtba_ctx();
   if (!c) return SQRTBA_E_OOM;
-  sqrtba_default_options(&c->opt);
+  SQRTBA_API(default_options)(&c->opt);
   if (opt) c->opt = *opt;
   if (!valid_options(c->opt)) {
     delete c;
@@ -1416,15 +1427,15 @@ int32_t sqrtba_create(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_str
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_set_options(sqrtba_ctx* c, const sqrtba_options* opt) {
+int32_t SQRTBA_API(set_options)(sqrtba_ctx* c, const sqrtba_options* opt) {
   if (!c || !opt || !valid_options(*opt)) return SQRTBA_E_INVALID;
   if (opt->landmark_blocks != c->opt.landmark_blocks && (c->uploaded || c->arena.base))
     return fail(c, SQRTBA_E_STATE, "landmark_blocks is chosen before the workspace is bound");
   if (opt->landmark_blocks == 2 && c->h.obs_set) TRY(build_sc(c));
   c->opt = *opt;
-  c->d.pcg_tol = (float)c->opt.pcg_rel_tol;
-  c->d.pcg_eta = (float)c->opt.pcg_forcing_eta;
-  c->d.huber = (float)c->opt.huber_delta;
+  c->d.pcg_tol = (real)c->opt.pcg_rel_tol;
+  c->d.pcg_eta = (real)c->opt.pcg_forcing_eta;
+  c->d.huber = (real)c->opt.huber_delta;
   if (c->graph) {  // captured launches hold the old Dev values
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
@@ -1432,7 +1443,7 @@ int32_t sqrtba_set_options(sqrtba_ctx* c, const sqrtba_options* opt) {
   return SQRTBA_OK;
 }
 
-void sqrtba_destroy(sqrtba_ctx* c) {
+void SQRTBA_API(destroy)(sqrtba_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
@@ -1460,9 +1471,9 @@ void sqrtba_destroy(sqrtba_ctx* c) {
   delete c;
 }
 
-const char* sqrtba_last_error(const sqrtba_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* SQRTBA_API(last_error)(const sqrtba_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-int32_t sqrtba_set_problems(sqrtba_ctx* c, int32_t n, const int64_t* cam_off, const int64_t* pt_off) {
+int32_t SQRTBA_API(set_problems)(sqrtba_ctx* c, int32_t n, const int64_t* cam_off, const int64_t* pt_off) {
   if (!c) return SQRTBA_E_INVALID;
   if (c->h.NC >= 0 || c->h.NL >= 0) return fail(c, SQRTBA_E_STATE, "set_problems must precede set_cameras/set_landmarks");
   if (n <= 0 || !cam_off || !pt_off) return fail(c, SQRTBA_E_INVALID, "need n_problems > 0 and offsets");
@@ -1476,7 +1487,7 @@ int32_t sqrtba_set_problems(sqrtba_ctx* c, int32_t n, const int64_t* cam_off, co
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_set_cameras(sqrtba_ctx* c, int64_t n, const float* params) {
+int32_t SQRTBA_API(set_cameras)(sqrtba_ctx* c, int64_t n, const real* params) {
   if (!c) return SQRTBA_E_INVALID;
   if (n <= 0 || !params) return fail(c, SQRTBA_E_INVALID, "need n_cams > 0 and parameters");
   if (c->h.problems_set && c->h.cam_off.back() != n) return fail(c, SQRTBA_E_INVALID, "n_cams does not match the problem offsets");
@@ -1494,7 +1505,7 @@ int32_t sqrtba_set_cameras(sqrtba_ctx* c, int64_t n, const float* params) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_set_landmarks(sqrtba_ctx* c, int64_t n, const float* xyz) {
+int32_t SQRTBA_API(set_landmarks)(sqrtba_ctx* c, int64_t n, const real* xyz) {
   if (!c) return SQRTBA_E_INVALID;
   if (n <= 0 || !xyz) return fail(c, SQRTBA_E_INVALID, "need n_points > 0 and coordinates");
   if (c->h.problems_set && c->h.pt_off.back() != n) return fail(c, SQRTBA_E_INVALID, "n_points does not match the problem offsets");
@@ -1512,7 +1523,7 @@ int32_t sqrtba_set_landmarks(sqrtba_ctx* c, int64_t n, const float* xyz) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_set_observations(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_t* pt, const float* uv) {
+int32_t SQRTBA_API(set_observations)(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_t* pt, const real* uv) {
   if (!c) return SQRTBA_E_INVALID;
   if (c->h.NC < 0 || c->h.NL < 0) return fail(c, SQRTBA_E_STATE, "set cameras and landmarks first");
   TRY(build_bookkeeping(c, n, cam, pt, uv));
@@ -1520,7 +1531,7 @@ int32_t sqrtba_set_observations(sqrtba_ctx* c, int64_t n, const int32_t* cam, co
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_workspace_bytes(const sqrtba_ctx* c, uint64_t* bytes) {
+int32_t SQRTBA_API(workspace_bytes)(const sqrtba_ctx* c, uint64_t* bytes) {
   if (!c || !bytes) return SQRTBA_E_INVALID;
   if (c->h.NC < 0 || c->h.NL < 0 || !c->h.obs_set) return SQRTBA_E_STATE;
   if (c->opt.landmark_blocks == 2 && !c->h.sc.built) return SQRTBA_E_STATE;
@@ -1528,7 +1539,7 @@ int32_t sqrtba_workspace_bytes(const sqrtba_ctx* c, uint64_t* bytes) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_bind_workspace(sqrtba_ctx* c, void* ptr, uint64_t bytes) {
+int32_t SQRTBA_API(bind_workspace)(sqrtba_ctx* c, void* ptr, uint64_t bytes) {
   if (!c) return SQRTBA_E_INVALID;
   TRY(check_ready(c));
   if (c->opt.landmark_blocks == 2) TRY(build_sc(c));
@@ -1540,7 +1551,7 @@ int32_t sqrtba_bind_workspace(sqrtba_ctx* c, void* ptr, uint64_t bytes) {
   return upload(c);
 }
 
-int32_t sqrtba_set_active(sqrtba_ctx* c, const uint8_t* mask) {
+int32_t SQRTBA_API(set_active)(sqrtba_ctx* c, const uint8_t* mask) {
   if (!c || !mask) return SQRTBA_E_INVALID;
   TRY(ensure_uploaded(c));
   std::vector<uint8_t> m(mask, mask + c->h.P);
@@ -1550,24 +1561,24 @@ int32_t sqrtba_set_active(sqrtba_ctx* c, const uint8_t* mask) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_linearize(sqrtba_ctx* c, double* cost) {
+int32_t SQRTBA_API(linearize)(sqrtba_ctx* c, double* cost) {
   if (!c) return SQRTBA_E_INVALID;
   return do_linearize(c, cost);
 }
-int32_t sqrtba_marginalize(sqrtba_ctx* c) { return c ? do_marginalize(c) : SQRTBA_E_INVALID; }
-int32_t sqrtba_damp(sqrtba_ctx* c, const double* lambda) { return c ? do_damp(c, lambda) : SQRTBA_E_INVALID; }
-int32_t sqrtba_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
+int32_t SQRTBA_API(marginalize)(sqrtba_ctx* c) { return c ? do_marginalize(c) : SQRTBA_E_INVALID; }
+int32_t SQRTBA_API(damp)(sqrtba_ctx* c, const double* lambda) { return c ? do_damp(c, lambda) : SQRTBA_E_INVALID; }
+int32_t SQRTBA_API(solve)(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
   return c ? do_solve(c, iters, rel_res, status) : SQRTBA_E_INVALID;
 }
-int32_t sqrtba_back_substitute(sqrtba_ctx* c, double* pred) { return c ? do_backsub(c, pred) : SQRTBA_E_INVALID; }
-int32_t sqrtba_update(sqrtba_ctx* c, double* new_cost) { return c ? do_update(c, new_cost) : SQRTBA_E_INVALID; }
-int32_t sqrtba_commit(sqrtba_ctx* c, const uint8_t* accept) { return c ? do_commit(c, accept) : SQRTBA_E_INVALID; }
-int32_t sqrtba_lm_solve(sqrtba_ctx* c, sqrtba_lm_report* rep) { return c ? lm_loop(c, nullptr, rep) : SQRTBA_E_INVALID; }
-int32_t sqrtba_lm_solve_tracked(sqrtba_ctx* c, const double* tol, sqrtba_lm_report* rep) {
+int32_t SQRTBA_API(back_substitute)(sqrtba_ctx* c, double* pred) { return c ? do_backsub(c, pred) : SQRTBA_E_INVALID; }
+int32_t SQRTBA_API(update)(sqrtba_ctx* c, double* new_cost) { return c ? do_update(c, new_cost) : SQRTBA_E_INVALID; }
+int32_t SQRTBA_API(commit)(sqrtba_ctx* c, const uint8_t* accept) { return c ? do_commit(c, accept) : SQRTBA_E_INVALID; }
+int32_t SQRTBA_API(lm_solve)(sqrtba_ctx* c, sqrtba_lm_report* rep) { return c ? lm_loop(c, nullptr, rep) : SQRTBA_E_INVALID; }
+int32_t SQRTBA_API(lm_solve_tracked)(sqrtba_ctx* c, const double* tol, sqrtba_lm_report* rep) {
   return c ? lm_loop(c, tol, rep) : SQRTBA_E_INVALID;
 }
 
-int32_t sqrtba_get_lm_history(const sqrtba_ctx* c, int32_t problem, sqrtba_lm_record* out, int32_t cap, int32_t* n) {
+int32_t SQRTBA_API(get_lm_history)(const sqrtba_ctx* c, int32_t problem, sqrtba_lm_record* out, int32_t cap, int32_t* n) {
   if (!c || !n) return SQRTBA_E_INVALID;
   if (problem < 0 || problem >= (int32_t)c->history.size()) return SQRTBA_E_INVALID;
   const auto& h = c->history[problem];
@@ -1577,42 +1588,42 @@ int32_t sqrtba_get_lm_history(const sqrtba_ctx* c, int32_t problem, sqrtba_lm_re
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_get_cameras(sqrtba_ctx* c, float* params) {
+int32_t SQRTBA_API(get_cameras)(sqrtba_ctx* c, real* params) {
   if (!c || !params) return SQRTBA_E_INVALID;
   if (!c->uploaded) {
     if (c->h.NC < 0) return fail(c, SQRTBA_E_STATE, "no cameras");
-    std::memcpy(params, c->h.cams_bal.data(), sizeof(float) * c->h.cams_bal.size());
+    std::memcpy(params, c->h.cams_bal.data(), sizeof(real) * c->h.cams_bal.size());
     return SQRTBA_OK;
   }
-  std::vector<float> cam(16 * c->h.NC);
-  HIP_TRY(c, hipMemcpyAsync(cam.data(), c->d.cam, cam.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  std::vector<real> cam(16 * c->h.NC);
+  HIP_TRY(c, hipMemcpyAsync(cam.data(), c->d.cam, cam.size() * sizeof(real), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (int64_t i = 0; i < c->h.NC; ++i) {
     double R[9], w[3];
     for (int j = 0; j < 9; ++j) R[j] = cam[16 * i + j];
     so3_log_d(R, w);
-    for (int j = 0; j < 3; ++j) params[9 * i + j] = (float)w[j];
+    for (int j = 0; j < 3; ++j) params[9 * i + j] = (real)w[j];
     for (int j = 0; j < 6; ++j) params[9 * i + 3 + j] = cam[16 * i + 9 + j];
   }
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_get_landmarks(sqrtba_ctx* c, float* xyz) {
+int32_t SQRTBA_API(get_landmarks)(sqrtba_ctx* c, real* xyz) {
   if (!c || !xyz) return SQRTBA_E_INVALID;
   if (!c->uploaded) {
     if (c->h.NL < 0) return fail(c, SQRTBA_E_STATE, "no landmarks");
-    std::memcpy(xyz, c->h.pts.data(), sizeof(float) * c->h.pts.size());
+    std::memcpy(xyz, c->h.pts.data(), sizeof(real) * c->h.pts.size());
     return SQRTBA_OK;
   }
-  std::vector<float> p(4 * c->h.NL);
-  HIP_TRY(c, hipMemcpyAsync(p.data(), c->d.pts, p.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  std::vector<real> p(4 * c->h.NL);
+  HIP_TRY(c, hipMemcpyAsync(p.data(), c->d.pts, p.size() * sizeof(real), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (int64_t i = 0; i < c->h.NL; ++i)
     for (int j = 0; j < 3; ++j) xyz[3 * i + j] = p[4 * i + j];
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_bookkeeping(const sqrtba_ctx* c, int64_t* n_active, int64_t* obs_perm, int64_t* lm_off,
+int32_t SQRTBA_API(debug_bookkeeping)(const sqrtba_ctx* c, int64_t* n_active, int64_t* obs_perm, int64_t* lm_off,
                                  uint8_t* lm_active, uint8_t* cam_active) {
   if (!c || !n_active) return SQRTBA_E_INVALID;
   if (!c->h.obs_set) return SQRTBA_E_STATE;
@@ -1625,33 +1636,33 @@ int32_t sqrtba_debug_bookkeeping(const sqrtba_ctx* c, int64_t* n_active, int64_t
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_linearization(sqrtba_ctx* c, float* r, float* Jp, float* Jl) {
+int32_t SQRTBA_API(debug_linearization)(sqrtba_ctx* c, real* r, real* Jp, real* Jl) {
   if (!c) return SQRTBA_E_INVALID;
   TRY(ensure_uploaded(c));
   const int64_t NO = c->h.NO;
-  float* buf = nullptr;
-  HIP_TRY(c, hipMalloc(&buf, sizeof(float) * 26 * (NO > 0 ? NO : 1)));
+  real* buf = nullptr;
+  HIP_TRY(c, hipMalloc(&buf, sizeof(real) * 26 * (NO > 0 ? NO : 1)));
   hipError_t e = launch_debug_linearization(c->d, c->L, buf, buf + 2 * NO, buf + 20 * NO);
-  std::vector<float> hbuf(26 * NO);
-  if (e == hipSuccess) e = hipMemcpyAsync(hbuf.data(), buf, hbuf.size() * 4, hipMemcpyDeviceToHost, c->stream);
+  std::vector<real> hbuf(26 * NO);
+  if (e == hipSuccess) e = hipMemcpyAsync(hbuf.data(), buf, hbuf.size() * sizeof(real), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(buf);
   if (e != hipSuccess) return fail(c, SQRTBA_E_HIP, "debug_linearization: %s", hipGetErrorString(e));
-  if (r) std::memcpy(r, hbuf.data(), 8 * NO);
-  if (Jp) std::memcpy(Jp, hbuf.data() + 2 * NO, 72 * NO);
-  if (Jl) std::memcpy(Jl, hbuf.data() + 20 * NO, 24 * NO);
+  if (r) std::memcpy(r, hbuf.data(), sizeof(real) * 2 * NO);
+  if (Jp) std::memcpy(Jp, hbuf.data() + 2 * NO, sizeof(real) * 18 * NO);
+  if (Jl) std::memcpy(Jl, hbuf.data() + 20 * NO, sizeof(real) * 6 * NO);
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_scales(sqrtba_ctx* c, float* s_cam, float* s_pt) {
+int32_t SQRTBA_API(debug_scales)(sqrtba_ctx* c, real* s_cam, real* s_pt) {
   if (!c) return SQRTBA_E_INVALID;
   if (!c->marginalized) return fail(c, SQRTBA_E_STATE, "scales need linearize and marginalize");
   const HostData& h = c->h;
   if (s_cam) {
-    HIP_TRY(c, hipMemcpyAsync(s_cam, c->d.s_cam, 36 * h.NC, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(s_cam, c->d.s_cam, sizeof(real) * 9 * h.NC, hipMemcpyDeviceToHost, c->stream));
   }
-  std::vector<float> lmd(LMD_STRIDE * h.NS);
-  if (h.NS) HIP_TRY(c, hipMemcpyAsync(lmd.data(), c->d.lmd, 4 * lmd.size(), hipMemcpyDeviceToHost, c->stream));
+  std::vector<real> lmd(LMD_STRIDE * h.NS);
+  if (h.NS) HIP_TRY(c, hipMemcpyAsync(lmd.data(), c->d.lmd, sizeof(real) * lmd.size(), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (s_pt)
     for (int64_t l = 0; l < h.NL; ++l)
@@ -1660,17 +1671,17 @@ int32_t sqrtba_debug_scales(sqrtba_ctx* c, float* s_cam, float* s_pt) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_rcs_matvec(sqrtba_ctx* c, int32_t m, const float* v, float* out) {
+int32_t SQRTBA_API(debug_rcs_matvec)(sqrtba_ctx* c, int32_t m, const real* v, real* out) {
   if (!c || m < 0 || (m > 0 && (!v || !out))) return SQRTBA_E_INVALID;
   if (!c->damped) return fail(c, SQRTBA_E_STATE, "rcs_matvec needs damp");
   const int64_t N = 9 * c->h.NC;
-  float* buf = nullptr;
-  HIP_TRY(c, hipMalloc(&buf, 8 * N));
+  real* buf = nullptr;
+  HIP_TRY(c, hipMalloc(&buf, sizeof(real) * 2 * N));
   hipError_t e = hipSuccess;
   for (int32_t i = 0; i < m && e == hipSuccess; ++i) {
-    e = hipMemcpyAsync(buf, v + N * i, 4 * N, hipMemcpyHostToDevice, c->stream);
+    e = hipMemcpyAsync(buf, v + N * i, sizeof(real) * N, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_matvec_only(c->d, c->L, buf, buf + N);
-    if (e == hipSuccess) e = hipMemcpyAsync(out + N * i, buf + N, 4 * N, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out + N * i, buf + N, sizeof(real) * N, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   }
   (void)hipFree(buf);
@@ -1678,25 +1689,25 @@ int32_t sqrtba_debug_rcs_matvec(sqrtba_ctx* c, int32_t m, const float* v, float*
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_rhs(sqrtba_ctx* c, float* rhs) {
+int32_t SQRTBA_API(debug_rhs)(sqrtba_ctx* c, real* rhs) {
   if (!c || !rhs) return SQRTBA_E_INVALID;
   if (!c->damped) return fail(c, SQRTBA_E_STATE, "rhs needs damp");
   LAUNCH(c, launch_precond_rhs(c->d, c->L));
-  HIP_TRY(c, hipMemcpyAsync(rhs, c->d.vb, 36 * c->h.NC, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(rhs, c->d.vb, sizeof(real) * 9 * c->h.NC, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_precond(sqrtba_ctx* c, float* minv) {
+int32_t SQRTBA_API(debug_precond)(sqrtba_ctx* c, real* minv) {
   if (!c || !minv) return SQRTBA_E_INVALID;
   if (!c->damped) return fail(c, SQRTBA_E_STATE, "precond needs damp");
   LAUNCH(c, launch_precond_rhs(c->d, c->L));
-  HIP_TRY(c, hipMemcpyAsync(minv, c->d.minv, 4 * 81 * c->h.NC, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(minv, c->d.minv, sizeof(real) * 81 * c->h.NC, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_block(sqrtba_ctx* c, int64_t pt, int32_t* k_out, float* out, float* factors) {
+int32_t SQRTBA_API(debug_block)(sqrtba_ctx* c, int64_t pt, int32_t* k_out, real* out, real* factors) {
   if (!c || !k_out) return SQRTBA_E_INVALID;
   if (!c->marginalized) return fail(c, SQRTBA_E_STATE, "block needs marginalize");
   const HostData& h = c->h;
@@ -1711,22 +1722,22 @@ int32_t sqrtba_debug_block(sqrtba_ctx* c, int64_t pt, int32_t* k_out, float* out
   if (!out && !factors) return SQRTBA_OK;
   if (c->opt.landmark_blocks != 0) {
     if (out) return fail(c, SQRTBA_E_UNSUPPORTED, "only explicit landmark blocks store block rows");
-    std::vector<float> lmd(LMD_STRIDE);
-    HIP_TRY(c, hipMemcpyAsync(lmd.data(), c->d.lmd + LMD_STRIDE * s, 4 * LMD_STRIDE, hipMemcpyDeviceToHost, c->stream));
+    std::vector<real> lmd(LMD_STRIDE);
+    HIP_TRY(c, hipMemcpyAsync(lmd.data(), c->d.lmd + LMD_STRIDE * s, sizeof(real) * LMD_STRIDE, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    std::memcpy(factors, lmd.data(), 4 * 24);
+    std::memcpy(factors, lmd.data(), sizeof(real) * 24);
     return SQRTBA_OK;
   }
-  std::vector<float> T(3 * W), B(2 * k * W), rho(2 * k), lmd(LMD_STRIDE);
-  HIP_TRY(c, hipMemcpyAsync(T.data(), c->d.poolT + h.slot_toff[s], 4 * T.size(), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(B.data(), c->d.poolB + h.slot_boff[s], 4 * B.size(), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(rho.data(), c->d.rhoB + 2 * h.slot_obs0[s], 4 * rho.size(), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(lmd.data(), c->d.lmd + LMD_STRIDE * s, 4 * LMD_STRIDE, hipMemcpyDeviceToHost, c->stream));
+  std::vector<real> T(3 * W), B(2 * k * W), rho(2 * k), lmd(LMD_STRIDE);
+  HIP_TRY(c, hipMemcpyAsync(T.data(), c->d.poolT + h.slot_toff[s], sizeof(real) * T.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(B.data(), c->d.poolB + h.slot_boff[s], sizeof(real) * B.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(rho.data(), c->d.rhoB + 2 * h.slot_obs0[s], sizeof(real) * rho.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(lmd.data(), c->d.lmd + LMD_STRIDE * s, sizeof(real) * LMD_STRIDE, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (out) {
     std::fill(out, out + (2 * k + 3) * C, 0.f);
-    const float* R = lmd.data() + LMD_R;
-    const float Rfull[9] = {R[0], R[1], R[2], 0, R[3], R[4], 0, 0, R[5]};
+    const real* R = lmd.data() + LMD_R;
+    const real Rfull[9] = {R[0], R[1], R[2], 0, R[3], R[4], 0, 0, R[5]};
     for (int i = 0; i < 3; ++i) {
       for (int64_t j = 0; j < 9 * k; ++j) out[i * C + j] = T[i * W + j];
       for (int j = 0; j < 3; ++j) out[i * C + 9 * k + j] = Rfull[3 * i + j];
@@ -1737,37 +1748,39 @@ int32_t sqrtba_debug_block(sqrtba_ctx* c, int64_t pt, int32_t* k_out, float* out
       out[(3 + i) * C + 9 * k + 3] = rho[i];
     }
   }
-  if (factors) std::memcpy(factors, lmd.data(), 4 * 24);
+  if (factors) std::memcpy(factors, lmd.data(), sizeof(real) * 24);
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_solution(sqrtba_ctx* c, float* dxp, float* dxl) {
+int32_t SQRTBA_API(debug_solution)(sqrtba_ctx* c, real* dxp, real* dxl) {
   if (!c) return SQRTBA_E_INVALID;
   TRY(ensure_uploaded(c));
-  if (dxp) HIP_TRY(c, hipMemcpyAsync(dxp, c->d.vx, 36 * c->h.NC, hipMemcpyDeviceToHost, c->stream));
-  if (dxl) HIP_TRY(c, hipMemcpyAsync(dxl, c->d.dxl, 12 * c->h.NL, hipMemcpyDeviceToHost, c->stream));
+  if (dxp) HIP_TRY(c, hipMemcpyAsync(dxp, c->d.vx, sizeof(real) * 9 * c->h.NC, hipMemcpyDeviceToHost, c->stream));
+  if (dxl) HIP_TRY(c, hipMemcpyAsync(dxl, c->d.dxl, sizeof(real) * 3 * c->h.NL, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_set_pose_increment(sqrtba_ctx* c, const float* dxp) {
+int32_t SQRTBA_API(debug_set_pose_increment)(sqrtba_ctx* c, const real* dxp) {
   if (!c || !dxp) return SQRTBA_E_INVALID;
   if (!c->damped) return fail(c, SQRTBA_E_STATE, "set_pose_increment needs damp");
-  HIP_TRY(c, hipMemcpyAsync(c->d.vx, dxp, 36 * c->h.NC, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d.vx, dxp, sizeof(real) * 9 * c->h.NC, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->solved = true;
   c->backsubbed = c->updated = false;
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_mlp_num_params(void) { return MLP_PARAMS; }
+#ifndef SQRTBA_FP64  // the learned preconditioner and its training are FP32 only
 
-int32_t sqrtba_mlp_init(sqrtba_ctx* c, uint64_t seed) {
+int32_t SQRTBA_API(mlp_num_params)(void) { return MLP_PARAMS; }
+
+int32_t SQRTBA_API(mlp_init)(sqrtba_ctx* c, uint64_t seed) {
   if (!c) return SQRTBA_E_INVALID;
   return init_params(c, seed);
 }
 
-int32_t sqrtba_mlp_set_params(sqrtba_ctx* c, const float* params) {
+int32_t SQRTBA_API(mlp_set_params)(sqrtba_ctx* c, const float* params) {
   if (!c || !params) return SQRTBA_E_INVALID;
   for (int i = 0; i < MLP_PARAMS; ++i)
     if (!std::isfinite(params[i])) return fail(c, SQRTBA_E_NONFINITE, "parameter %d is not finite", i);
@@ -1781,7 +1794,7 @@ int32_t sqrtba_mlp_set_params(sqrtba_ctx* c, const float* params) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_mlp_get_params(sqrtba_ctx* c, float* params) {
+int32_t SQRTBA_API(mlp_get_params)(sqrtba_ctx* c, float* params) {
   if (!c || !params) return SQRTBA_E_INVALID;
   if (!c->ln.alloc) return fail(c, SQRTBA_E_STATE, "no network: call sqrtba_mlp_init or sqrtba_mlp_set_params");
   HIP_TRY(c, hipMemcpyAsync(params, c->ln.w32, 4 * (size_t)MLP_PARAMS, hipMemcpyDeviceToHost, c->stream));
@@ -1789,14 +1802,14 @@ int32_t sqrtba_mlp_get_params(sqrtba_ctx* c, float* params) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_set_preconditioner(sqrtba_ctx* c, int32_t mode) {
+int32_t SQRTBA_API(set_preconditioner)(sqrtba_ctx* c, int32_t mode) {
   if (!c || (mode != 0 && mode != 1)) return SQRTBA_E_INVALID;
   if (mode == 1 && !c->ln.alloc) return fail(c, SQRTBA_E_STATE, "no network: call sqrtba_mlp_init or sqrtba_mlp_set_params");
   c->ln.mode = mode;
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_pcg_trace(sqrtba_ctx* c, int32_t max_solves, int32_t iters_per_solve) {
+int32_t SQRTBA_API(pcg_trace)(sqrtba_ctx* c, int32_t max_solves, int32_t iters_per_solve) {
   if (!c || max_solves < 0 || iters_per_solve < 0) return SQRTBA_E_INVALID;
   TRY(ensure_uploaded(c));
   auto& L = c->ln;
@@ -1818,7 +1831,7 @@ int32_t sqrtba_pcg_trace(sqrtba_ctx* c, int32_t max_solves, int32_t iters_per_so
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_trace_size(const sqrtba_ctx* c, int32_t* n_solves, int32_t* n_records) {
+int32_t SQRTBA_API(trace_size)(const sqrtba_ctx* c, int32_t* n_solves, int32_t* n_records) {
   if (!c) return SQRTBA_E_INVALID;
   if (n_solves) *n_solves = c->ln.n_solves;
   if (n_records) *n_records = c->ln.n_records;
@@ -1848,7 +1861,7 @@ static int grow_training(sqrtba_ctx* c, int n) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_mlp_train(sqrtba_ctx* c, int32_t steps, int32_t batch, double lr, uint64_t seed, double* losses) {
+int32_t SQRTBA_API(mlp_train)(sqrtba_ctx* c, int32_t steps, int32_t batch, double lr, uint64_t seed, double* losses) {
   if (!c || steps < 0 || batch <= 0 || !(lr >= 0)) return SQRTBA_E_INVALID;
   auto& L = c->ln;
   if (!L.alloc) return fail(c, SQRTBA_E_STATE, "no network: call sqrtba_mlp_init or sqrtba_mlp_set_params");
@@ -1895,7 +1908,7 @@ int32_t sqrtba_mlp_train(sqrtba_ctx* c, int32_t steps, int32_t batch, double lr,
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_mlp_eval(sqrtba_ctx* c, int32_t n, const float* feats, const float* lfac, const float* p,
+int32_t SQRTBA_API(mlp_eval)(sqrtba_ctx* c, int32_t n, const float* feats, const float* lfac, const float* p,
                         const float* q, double* loss, float* grad) {
   if (!c || n <= 0 || !feats || !lfac || !p || !q) return SQRTBA_E_INVALID;
   auto& L = c->ln;
@@ -1929,7 +1942,7 @@ int32_t sqrtba_mlp_eval(sqrtba_ctx* c, int32_t n, const float* feats, const floa
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_learned_stats(const sqrtba_ctx* c, int64_t* learned_solves, int64_t* fallbacks, int64_t* wasted_iters) {
+int32_t SQRTBA_API(learned_stats)(const sqrtba_ctx* c, int64_t* learned_solves, int64_t* fallbacks, int64_t* wasted_iters) {
   if (!c) return SQRTBA_E_INVALID;
   if (learned_solves) *learned_solves = c->ln.learned_solves;
   if (fallbacks) *fallbacks = c->ln.fallbacks;
@@ -1937,7 +1950,7 @@ int32_t sqrtba_learned_stats(const sqrtba_ctx* c, int64_t* learned_solves, int64
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_features(sqrtba_ctx* c, float* feats, float* lfac) {
+int32_t SQRTBA_API(debug_features)(sqrtba_ctx* c, float* feats, float* lfac) {
   if (!c) return SQRTBA_E_INVALID;
   if (!c->damped) return fail(c, SQRTBA_E_STATE, "features need damp");
   LAUNCH(c, launch_precond_rhs(c->d, c->L));
@@ -1947,7 +1960,7 @@ int32_t sqrtba_debug_features(sqrtba_ctx* c, float* feats, float* lfac) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_debug_learned_precond(sqrtba_ctx* c, float* minv) {
+int32_t SQRTBA_API(debug_learned_precond)(sqrtba_ctx* c, float* minv) {
   if (!c || !minv) return SQRTBA_E_INVALID;
   if (!c->damped) return fail(c, SQRTBA_E_STATE, "needs damp");
   if (!c->ln.alloc) return fail(c, SQRTBA_E_STATE, "no network");
@@ -1958,7 +1971,9 @@ int32_t sqrtba_debug_learned_precond(sqrtba_ctx* c, float* minv) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_profile_enable(sqrtba_ctx* c, int32_t on) {
+#endif  // SQRTBA_FP64
+
+int32_t SQRTBA_API(profile_enable)(sqrtba_ctx* c, int32_t on) {
   if (!c) return SQRTBA_E_INVALID;
   if (c->stream) HIP_TRY(c, hipStreamSynchronize(c->stream));
   flush_profile(c);
@@ -1967,27 +1982,27 @@ int32_t sqrtba_profile_enable(sqrtba_ctx* c, int32_t on) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_profile_get(const sqrtba_ctx* c, sqrtba_profile* out) {
+int32_t SQRTBA_API(profile_get)(const sqrtba_ctx* c, sqrtba_profile* out) {
   if (!c || !out) return SQRTBA_E_INVALID;
   *out = c->prof;
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_save_state(sqrtba_ctx* c) {
+int32_t SQRTBA_API(save_state)(sqrtba_ctx* c) {
   if (!c) return SQRTBA_E_INVALID;
   TRY(ensure_uploaded(c));
-  HIP_TRY(c, hipMemcpyAsync(c->d.cam_snap, c->d.cam, 64 * c->h.NC, hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->d.pts_snap, c->d.pts, 16 * c->h.NL, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d.cam_snap, c->d.cam, sizeof(real) * 16 * c->h.NC, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d.pts_snap, c->d.pts, sizeof(real) * 4 * c->h.NL, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->snapshot = true;
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_restore_state(sqrtba_ctx* c) {
+int32_t SQRTBA_API(restore_state)(sqrtba_ctx* c) {
   if (!c) return SQRTBA_E_INVALID;
   if (!c->uploaded || !c->snapshot) return fail(c, SQRTBA_E_STATE, "restore_state needs save_state");
-  HIP_TRY(c, hipMemcpyAsync(c->d.cam, c->d.cam_snap, 64 * c->h.NC, hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->d.pts, c->d.pts_snap, 16 * c->h.NL, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d.cam, c->d.cam_snap, sizeof(real) * 16 * c->h.NC, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d.pts, c->d.pts_snap, sizeof(real) * 4 * c->h.NL, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->linearized = c->marginalized = c->damped = c->solved = c->backsubbed = c->updated = false;
   return SQRTBA_OK;
@@ -2051,7 +2066,7 @@ int time_products(sqrtba_ctx* c, int reps, double* ms) {
 
 }  // namespace
 
-int32_t sqrtba_time_product(sqrtba_ctx* c, int32_t reps, double* ms, double* bytes) {
+int32_t SQRTBA_API(time_product)(sqrtba_ctx* c, int32_t reps, double* ms, double* bytes) {
   if (!c || reps <= 0 || !ms) return SQRTBA_E_INVALID;
   TRY(ensure_uploaded(c));
   TRY(time_products(c, reps, ms));
@@ -2064,14 +2079,14 @@ int32_t sqrtba_time_product(sqrtba_ctx* c, int32_t reps, double* ms, double* byt
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_get_tuning(sqrtba_ctx* c, sqrtba_tuning* out) {
+int32_t SQRTBA_API(get_tuning)(sqrtba_ctx* c, sqrtba_tuning* out) {
   if (!c || !out) return SQRTBA_E_INVALID;
   TRY(ensure_uploaded(c));
   *out = current_tuning(c);
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_set_tuning(sqrtba_ctx* c, const sqrtba_tuning* t) {
+int32_t SQRTBA_API(set_tuning)(sqrtba_ctx* c, const sqrtba_tuning* t) {
   if (!c || !t || !valid_tuning(*t)) return SQRTBA_E_INVALID;
   TRY(ensure_uploaded(c));
   TRY(apply_tuning(c, *t));
@@ -2079,7 +2094,7 @@ int32_t sqrtba_set_tuning(sqrtba_ctx* c, const sqrtba_tuning* t) {
   return SQRTBA_OK;
 }
 
-int32_t sqrtba_autotune(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, sqrtba_tuning_trial* trials,
+int32_t SQRTBA_API(autotune)(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, sqrtba_tuning_trial* trials,
                         int32_t max_trials, int32_t* n_trials) {
   if (!c || max_trials < 0) return SQRTBA_E_INVALID;
   TRY(ensure_uploaded(c));

@@ -7,6 +7,27 @@
 
 namespace sqrtba {
 
+// Element type of the whole path: FP32 (square-root BA-32), or FP64 when built
+// with SQRTBA_FP64 (square-root BA-64, the double-precision variant of Sec. 6).
+// Per-problem sums are FP64 in both.
+#ifdef SQRTBA_FP64
+typedef double real;
+typedef double2 real2;
+typedef double3 real3;
+typedef double4 real4;
+__host__ __device__ inline real2 make_real2(real a, real b) { return make_double2(a, b); }
+__host__ __device__ inline real3 make_real3(real a, real b, real c) { return make_double3(a, b, c); }
+__host__ __device__ inline real4 make_real4(real a, real b, real c, real d) { return make_double4(a, b, c, d); }
+#else
+typedef float real;
+typedef float2 real2;
+typedef float3 real3;
+typedef float4 real4;
+__host__ __device__ inline real2 make_real2(real a, real b) { return make_float2(a, b); }
+__host__ __device__ inline real3 make_real3(real a, real b, real c) { return make_float3(a, b, c); }
+__host__ __device__ inline real4 make_real4(real a, real b, real c, real d) { return make_float4(a, b, c, d); }
+#endif
+
 // Landmark work is split into size classes by observation count k; each class
 // maps one landmark to a "team" of lanes of a fixed size.  The classes are
 // contiguous k ranges; landmarks are ordered by decreasing k so the largest
@@ -23,20 +44,20 @@ __host__ __device__ constexpr int class_of_k(int k) {
   return k <= 3 ? 0 : k <= 7 ? 1 : k <= 14 ? 2 : k <= 28 ? 3 : k <= 113 ? 4 : k <= 512 ? 5 : -1;
 }
 
-// Small per-landmark record (floats): R1 upper (6), Q1^T r (3), damped R upper (6),
+// Small per-landmark record (elements): R1 upper (6), Q1^T r (3), damped R upper (6),
 // damped Q1^T r (3), landmark column scales (3), lambda used (1), pad (2), and for
 // implicit landmark blocks the projection matrix P = R1 (R1^T R1 + lambda I)^-1 R1^T
-// (6, upper triangle row by row, 16-byte aligned), pad (2).
+// (6, upper triangle row by row, 4-element aligned), pad (2).
 enum {
   LMD_R = 0, LMD_QR = 6, LMD_RH = 9, LMD_QRH = 15, LMD_SL = 18, LMD_LAM = 21, LMD_P = 24, LMD_STRIDE = 32
 };
 
-// Implicit landmark blocks: per observation a record of 7 float4 "planes" holding
+// Implicit landmark blocks: per observation a record of 7 real4 "planes" holding
 // the unscaled pose Jacobian rows (2 x 9, row by row, planes 0..4), the
 // observation's two rows of the thin QR factor Q1 (2 x 3, planes 4..5), and in
 // plane 6 the residual (2) and 2 zeros; the camera index is in rec_cam.  Records are in
 // slot order (slot_zoff[slot] + o for observation o of a slot) and plane-major:
-// plane p of record i is float4 p * NO + i, so a team reading one plane of its
+// plane p of record i is real4 p * NO + i, so a team reading one plane of its
 // landmark's observations, and consecutive teams of consecutive landmarks, read
 // contiguous memory.
 enum { REC_PLANES = 7 };
@@ -48,15 +69,15 @@ struct Dev {
   int32_t NL;      // landmarks
   int32_t NS;      // active landmarks (slots)
   int32_t NO;      // active observations
-  // camera state: 16 floats per camera: R (row-major 9), t (3), f, k1, k2, pad
-  float* cam;
-  float* cam_new;
-  float4* pts;      // x, y, z, 0
-  float4* pts_new;
+  // camera state: 16 elements per camera: R (row-major 9), t (3), f, k1, k2, pad
+  real* cam;
+  real* cam_new;
+  real4* pts;      // x, y, z, 0
+  real4* pts_new;
   // sorted active observations (landmark-major, camera ascending)
   int32_t* obs_cam;
   int32_t* obs_lm;
-  float2* obs_uv;
+  real2* obs_uv;
   int32_t* cam_obs_off;  // NC + 1
   int32_t* cam_obs_idx;  // NO, sorted-observation positions per camera
   int32_t* cam_prob;     // NC
@@ -68,9 +89,9 @@ struct Dev {
   int32_t* slot_k;
   int32_t* slot_obs0;
   int32_t* slot_prob;
-  int64_t* slot_boff;  // float offset of the B rows (2k x W) in poolB (128-byte aligned)
-  int64_t* slot_toff;  // float offset of the undamped top rows (3 x W) in poolT (128-byte aligned)
-  int32_t* slot_zoff;  // float offset of the landmark's W product outputs in obsbuf (16-byte aligned);
+  int64_t* slot_boff;  // element offset of the B rows (2k x W) in poolB (32-element aligned)
+  int64_t* slot_toff;  // element offset of the undamped top rows (3 x W) in poolT (32-element aligned)
+  int32_t* slot_zoff;  // element offset of the landmark's W product outputs in obsbuf (4-element aligned);
                        // implicit blocks: index of the landmark's first record (outputs at 12 x record)
   int32_t* cam_zpos;   // NO: obsbuf offset of the outputs of each camera's observations (camera order)
   int32_t* lm_slot;    // NL, -1 when inactive
@@ -79,23 +100,23 @@ struct Dev {
   int2* qjob;     // class-5 QR row chunks: (slot, first row | end row << 16)
   int2* hjob;
   int64_t* hz_off;  // per slot with k >= 29 (a prefix of the slots): offset of its partials in zpart
-  float* zpart;
-  float* poolB;
-  float* poolT;
-  float* lmd;     // NS * LMD_STRIDE
-  float* rhoB;    // 2 * NO: residual column of the B rows of each landmark
-  float* s_cam;   // NC * 9
+  real* zpart;
+  real* poolB;
+  real* poolT;
+  real* lmd;     // NS * LMD_STRIDE
+  real* rhoB;    // 2 * NO: residual column of the B rows of each landmark
+  real* s_cam;   // NC * 9
   // PCG vectors (9 NC each)
-  float* vx;
-  float* vr;
-  float* vz;
-  float* vzs;     // NC * 12: S z per camera, 9 floats and 3 zero pad (16-byte aligned), kept by the
+  real* vx;
+  real* vr;
+  real* vz;
+  real* vzs;     // NC * 12: S z per camera, 9 elements and 3 zero pad (4-element aligned), kept by the
                   // PCG kernels for the implicit product's gather
-  float* vp;
-  float* vq;
-  float* vb;      // right-hand side b~
-  float* minv;    // NC * 81 inverse preconditioner blocks
-  float* obsrec;  // implicit blocks: REC_PLANES * NO float4 per-observation records (else null)
+  real* vp;
+  real* vq;
+  real* vb;      // right-hand side b~
+  real* minv;    // NC * 81 inverse preconditioner blocks
+  real* obsrec;  // implicit blocks: REC_PLANES * NO real4 per-observation records (else null)
   int32_t* rec_cam;  // implicit blocks: NO camera indices of the records (else null)
   int32_t implicit;  // 1: implicit landmark blocks or (with sc) the explicit Schur complement:
                      // per-observation records, no poolB / poolT / rhoB
@@ -104,17 +125,17 @@ struct Dev {
   // (scaled) sit in the R / QR slots of lmd and (H_ll + lambda I)^-1 in the P slot.
   int32_t sc;
   int32_t sc_noff;       // off-diagonal camera-pair blocks (then NC diagonal blocks)
-  float* scb;            // (sc_noff + NC) * 81 floats, full 9 x 9, unscaled pose coordinates
+  real* scb;            // (sc_noff + NC) * 81 elements, full 9 x 9, unscaled pose coordinates
   int32_t* sc_coff;      // sc_noff + 1: contributions of each off-diagonal block (CSR)
   int4* sc_contrib;      // (record a, record b, slot, 0), a of the block's first camera
   int32_t* sc_rowoff;    // NC + 1: blocks of each camera's row of the reduced matrix (CSR)
   int2* sc_rowent;       // (block | transposed << 31, other camera)
-  float* vy;             // 9 NC: the Schur-complement product of the last launch
+  real* vy;             // 9 NC: the Schur-complement product of the last launch
   int32_t* pcg_skip;     // 1 int: some problem is inactive or done in the running PCG solve (the
                          // products then test a landmark's problem before reading its data)
-  float* obsbuf;  // NO * 54 floats: per-observation preconditioner terms; the product outputs
+  real* obsbuf;  // NO * 54 elements: per-observation preconditioner terms; the product outputs
                   // reuse it in per-landmark aligned regions (slot_zoff)
-  float* dxl;     // NL * 3, unscaled landmark increment
+  real* dxl;     // NL * 3, unscaled landmark increment
   double* cam_part;  // NC, per-camera partial sums
   double* cam_part2; // NC
   double* cam_part3; // NC
@@ -139,11 +160,11 @@ struct Dev {
   float* feats;        // NC * 64 learned-preconditioner features of the last preconditioner build
   float* lfac;         // NC * 45 lower Cholesky factors of the damped blocks (packed rows)
   float* cam_stats;    // NC * 4: log(1 + #obs), log(1 + #covisible cameras), mean and max log k
-  float* cam_snap;     // saved state (save/restore)
-  float4* pts_snap;
-  float pcg_tol;
-  float pcg_eta;     // > 0: Nash-Sofer truncation of PCG
-  float huber;       // Huber parameter in pixels (0: squared loss)
+  real* cam_snap;     // saved state (save/restore)
+  real4* pts_snap;
+  real pcg_tol;
+  real pcg_eta;     // > 0: Nash-Sofer truncation of PCG
+  real huber;       // Huber parameter in pixels (0: squared loss)
 };
 
 struct WorkClass {
@@ -193,10 +214,10 @@ hipError_t launch_backsub(const Dev& d, const Launch& L);
 hipError_t launch_update(const Dev& d, const Launch& L);
 hipError_t launch_commit(const Dev& d, const Launch& L);
 // test helpers
-hipError_t launch_matvec_only(const Dev& d, const Launch& L, const float* v_scaled, float* out);
+hipError_t launch_matvec_only(const Dev& d, const Launch& L, const real* v_scaled, real* out);
 hipError_t launch_matvec_timing(const Dev& d, const Launch& L);  // product of z over all active landmarks
 // implicit blocks: S z into vzs once, before timed launch_matvec_timing calls (which then read it)
 hipError_t launch_prescale_z(const Dev& d, const Launch& L);
-hipError_t launch_debug_linearization(const Dev& d, const Launch& L, float* r, float* Jp, float* Jl);
+hipError_t launch_debug_linearization(const Dev& d, const Launch& L, real* r, real* Jp, real* Jl);
 
 }  // namespace sqrtba

@@ -1,7 +1,9 @@
 // HIP kernels of the square-root bundle-adjustment hot path, written for
-// gfx950 (CDNA4, 64-lane wavefronts).  FP32 arithmetic throughout; sums across
-// cameras, landmarks and observations of one problem are accumulated in FP64
-// with fixed-shape trees, so every result is run-to-run deterministic.
+// gfx950 (CDNA4, 64-lane wavefronts).  The element type `real` is FP32, or FP64
+// when built with SQRTBA_FP64 (the double-precision variant of the method);
+// sums across cameras, landmarks and observations of one problem are
+// accumulated in FP64 with fixed-shape trees, so every result is run-to-run
+// deterministic.
 //
 // Landmark-centric kernels (marginalize, damp, preconditioner/RHS, matvec,
 // back-substitution) give each landmark a team of 8, 16, 32, 64 or 256 lanes
@@ -36,19 +38,28 @@ __device__ __forceinline__ int width_of(int k) { return (9 * k + 3) & ~3; }
 // ---------------------------------------------------------------- reductions
 
 template <int CTRL>
-__device__ __forceinline__ float dppf(float v) {
+__device__ __forceinline__ float dpp_mov(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// A 64-bit value moves as its two 32-bit halves under the same lane pattern.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // All-reduce over aligned groups of TEAM lanes (4, 8, 16, 32 or 64).  Every lane
 // of the group receives the bitwise-identical sum (each step adds a commutative
 // pair).  All lanes of a group must be active together.
 template <int TEAM>
-__device__ __forceinline__ float team_sum(float v) {
-  v += dppf<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dppf<0x4E>(v);   // quad_perm [2,3,0,1]
-  if constexpr (TEAM >= 8) v += dppf<0x141>(v);  // row_half_mirror: pairs quads of a half row
-  if constexpr (TEAM >= 16) v += dppf<0x140>(v);  // row_mirror: pairs half rows
+__device__ __forceinline__ real team_sum(real v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (TEAM >= 8) v += dpp_mov<0x141>(v);  // row_half_mirror: pairs quads of a half row
+  if constexpr (TEAM >= 16) v += dpp_mov<0x140>(v);  // row_mirror: pairs half rows
   if constexpr (TEAM >= 32) v += __shfl_xor(v, 16);  // pairs rows of 16 within 32 lanes
   if constexpr (TEAM >= 64) v += __shfl_xor(v, 32);
   return v;
@@ -60,10 +71,10 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-__device__ __forceinline__ float wave_sum_f(float v) { return team_sum<64>(v); }
+__device__ __forceinline__ real wave_sum_f(real v) { return team_sum<64>(v); }
 
 // Workgroup all-reduce of a float (256 lanes = 4 waves), deterministic.
-__device__ __forceinline__ float block_sum(float v, float* red4) {
+__device__ __forceinline__ real block_sum(real v, real* red4) {
   v = wave_sum_f(v);
   const int w = threadIdx.x >> 6;
   __syncthreads();
@@ -73,7 +84,7 @@ __device__ __forceinline__ float block_sum(float v, float* red4) {
 }
 
 template <int TEAM>
-__device__ __forceinline__ float tsum(float v, float* red4) {
+__device__ __forceinline__ real tsum(real v, real* red4) {
   if constexpr (TEAM <= 64)
     return team_sum<TEAM>(v);
   else
@@ -94,14 +105,14 @@ __device__ __forceinline__ void team_sync() {
 // ------------------------------------------------------------- camera model
 
 struct Cam {
-  float R[9];
-  float t[3];
-  float f, k1, k2;
+  real R[9];
+  real t[3];
+  real f, k1, k2;
 };
 
-__device__ __forceinline__ void load_cam(const float* __restrict__ cam, int c, Cam& C) {
-  const float4* p = reinterpret_cast<const float4*>(cam + 16 * (size_t)c);
-  float4 a = p[0], b = p[1], d = p[2], e = p[3];
+__device__ __forceinline__ void load_cam(const real* __restrict__ cam, int c, Cam& C) {
+  const real4* p = reinterpret_cast<const real4*>(cam + 16 * (size_t)c);
+  real4 a = p[0], b = p[1], d = p[2], e = p[3];
   C.R[0] = a.x; C.R[1] = a.y; C.R[2] = a.z; C.R[3] = a.w;
   C.R[4] = b.x; C.R[5] = b.y; C.R[6] = b.z; C.R[7] = b.w;
   C.R[8] = d.x; C.t[0] = d.y; C.t[1] = d.z; C.t[2] = d.w;
@@ -112,26 +123,26 @@ __device__ __forceinline__ void load_cam(const float* __restrict__ cam, int c, C
 // r = pi - uv.  With JAC, Jp (2x9) w.r.t. (left rotation increment, t, f, k1, k2)
 // and Jl (2x3) w.r.t. X.
 template <bool JAC>
-__device__ __forceinline__ void project(const Cam& C, float X0, float X1, float X2, float u, float v,
-                                        float r[2], float Jp[2][9], float Jl[2][3]) {
-  const float RX0 = C.R[0] * X0 + C.R[1] * X1 + C.R[2] * X2;
-  const float RX1 = C.R[3] * X0 + C.R[4] * X1 + C.R[5] * X2;
-  const float RX2 = C.R[6] * X0 + C.R[7] * X1 + C.R[8] * X2;
-  const float P0 = RX0 + C.t[0], P1 = RX1 + C.t[1], P2 = RX2 + C.t[2];
-  const float iz = 1.0f / P2;
-  const float p0 = -P0 * iz, p1 = -P1 * iz;
-  const float n2 = p0 * p0 + p1 * p1;
-  const float d = 1.0f + n2 * (C.k1 + C.k2 * n2);
-  const float fd = C.f * d;
+__device__ __forceinline__ void project(const Cam& C, real X0, real X1, real X2, real u, real v,
+                                        real r[2], real Jp[2][9], real Jl[2][3]) {
+  const real RX0 = C.R[0] * X0 + C.R[1] * X1 + C.R[2] * X2;
+  const real RX1 = C.R[3] * X0 + C.R[4] * X1 + C.R[5] * X2;
+  const real RX2 = C.R[6] * X0 + C.R[7] * X1 + C.R[8] * X2;
+  const real P0 = RX0 + C.t[0], P1 = RX1 + C.t[1], P2 = RX2 + C.t[2];
+  const real iz = 1.0f / P2;
+  const real p0 = -P0 * iz, p1 = -P1 * iz;
+  const real n2 = p0 * p0 + p1 * p1;
+  const real d = 1.0f + n2 * (C.k1 + C.k2 * n2);
+  const real fd = C.f * d;
   r[0] = fd * p0 - u;
   r[1] = fd * p1 - v;
   if constexpr (JAC) {
     // dpi/dp = f (d I + g p p^T), g = 2 (k1 + 2 k2 |p|^2)
-    const float fg = C.f * 2.0f * (C.k1 + 2.0f * C.k2 * n2);
-    const float a00 = fd + fg * p0 * p0, a01 = fg * p0 * p1, a11 = fd + fg * p1 * p1;
+    const real fg = C.f * 2.0f * (C.k1 + 2.0f * C.k2 * n2);
+    const real a00 = fd + fg * p0 * p0, a01 = fg * p0 * p1, a11 = fd + fg * p1 * p1;
     // dp/dP = [[-iz, 0, -p0 iz], [0, -iz, -p1 iz]]
-    const float A00 = -a00 * iz, A01 = -a01 * iz, A02 = -(a00 * p0 + a01 * p1) * iz;
-    const float A10 = -a01 * iz, A11 = -a11 * iz, A12 = -(a01 * p0 + a11 * p1) * iz;
+    const real A00 = -a00 * iz, A01 = -a01 * iz, A02 = -(a00 * p0 + a01 * p1) * iz;
+    const real A10 = -a01 * iz, A11 = -a11 * iz, A12 = -(a01 * p0 + a11 * p1) * iz;
     // rotation: dP/d(dw) = -[RX]_x = [[0, RX2, -RX1], [-RX2, 0, RX0], [RX1, -RX0, 0]]
     Jp[0][0] = -A01 * RX2 + A02 * RX1;
     Jp[0][1] = A00 * RX2 - A02 * RX0;
@@ -156,13 +167,13 @@ __device__ __forceinline__ void project(const Cam& C, float X0, float X1, float 
 // observation's s = |r|^2 the cost term rho(s) (s up to delta^2, then
 // 2 delta sqrt(s) - delta^2) and the row weight sqrt(rho'(s)) =
 // sqrt(min(1, delta / |r|)) that scales its residual and Jacobian rows.
-__device__ __forceinline__ float robust_term(float s, float delta, float& sqrt_w) {
+__device__ __forceinline__ real robust_term(real s, real delta, real& sqrt_w) {
   if (delta <= 0.f || s <= delta * delta) {
     sqrt_w = 1.0f;
     return s;
   }
-  const float n = sqrtf(s);
-  sqrt_w = sqrtf(delta / n);
+  const real n = sqrt(s);
+  sqrt_w = sqrt(delta / n);
   return 2.0f * delta * n - delta * delta;
 }
 
@@ -173,28 +184,28 @@ __device__ __forceinline__ float robust_term(float s, float delta, float& sqrt_w
 // camera's 9 (reweighted) Jacobian columns (1 / column norm; an empty column
 // keeps scale 1).
 template <bool JAC>
-__global__ __launch_bounds__(64) void k_cam_linearize(Dev d, const float* __restrict__ cam,
-                                                      const float4* __restrict__ pts, const uint8_t* mask) {
+__global__ __launch_bounds__(64) void k_cam_linearize(Dev d, const real* __restrict__ cam,
+                                                      const real4* __restrict__ pts, const uint8_t* mask) {
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
   if (mask && !mask[d.cam_prob[c]]) return;
   Cam C;
   load_cam(cam, c, C);
-  float n2[9];
+  real n2[9];
 #pragma unroll
   for (int j = 0; j < 9; ++j) n2[j] = 0.f;
   double cost = 0.0;
   const int b = d.cam_obs_off[c], e = d.cam_obs_off[c + 1];
   for (int i = b + lane; i < e; i += 64) {
     const int o = d.cam_obs_idx[i];
-    const float4 X = pts[d.obs_lm[o]];
-    const float2 uv = d.obs_uv[o];
-    float r[2], Jp[2][9], Jl[2][3];
+    const real4 X = pts[d.obs_lm[o]];
+    const real2 uv = d.obs_uv[o];
+    real r[2], Jp[2][9], Jl[2][3];
     project<JAC>(C, X.x, X.y, X.z, uv.x, uv.y, r, Jp, Jl);
-    float sw;
+    real sw;
     cost += (double)robust_term(r[0] * r[0] + r[1] * r[1], d.huber, sw);
     if constexpr (JAC) {
-      const float w = sw * sw;
+      const real w = sw * sw;
 #pragma unroll
       for (int j = 0; j < 9; ++j) n2[j] += w * (Jp[0][j] * Jp[0][j] + Jp[1][j] * Jp[1][j]);
     }
@@ -204,10 +215,10 @@ __global__ __launch_bounds__(64) void k_cam_linearize(Dev d, const float* __rest
 #pragma unroll
     for (int j = 0; j < 9; ++j) n2[j] = wave_sum_f(n2[j]);
     if (lane < 9) {
-      float v = n2[0];
+      real v = n2[0];
 #pragma unroll
       for (int j = 1; j < 9; ++j) v = (lane == j) ? n2[j] : v;
-      d.s_cam[9 * c + lane] = v > 0.f ? 1.0f / sqrtf(v) : 1.0f;
+      d.s_cam[9 * c + lane] = v > 0.f ? 1.0f / sqrt(v) : 1.0f;
     }
   }
   if (lane == 0) d.cam_part[c] = cost;
@@ -298,14 +309,14 @@ __device__ __forceinline__ void class_dispatch(const ClassGrid& m, const F& f) {
 // rewritten only after every thread has passed the barrier that follows the
 // reads of its previous use).
 template <int TEAM, int N>
-__device__ __forceinline__ void team_sum_n(float (&v)[N], float* red, int& buf) {
+__device__ __forceinline__ void team_sum_n(real (&v)[N], real* red, int& buf) {
   if constexpr (TEAM <= 64) {
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = team_sum<TEAM>(v[i]);
   } else {
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = wave_sum_f(v[i]);
-    float* r = red + buf * (4 * 8);
+    real* r = red + buf * (4 * 8);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
@@ -319,8 +330,8 @@ __device__ __forceinline__ void team_sum_n(float (&v)[N], float* red, int& buf) 
 }
 
 // Plane p of the implicit per-observation records (REC_PLANES planes of NO float4).
-__device__ __forceinline__ float4* rec_plane(const Dev& d, int p) {
-  return reinterpret_cast<float4*>(d.obsrec) + (size_t)p * d.NO;
+__device__ __forceinline__ real4* rec_plane(const Dev& d, int p) {
+  return reinterpret_cast<real4*>(d.obsrec) + (size_t)p * d.NO;
 }
 
 // LDS floats per team: V (2k x 4) and the pose Jacobians (k x 18), rounded up
@@ -333,7 +344,7 @@ constexpr int MARG_RED = 64;
 // 0, >= 2k); the landmark record and the residual rows are written by the
 // chunk with row_lo = 0.
 template <int TEAM, int KMAX, bool IMPLICIT>
-__device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane, float* lds, float* red,
+__device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane, real* lds, real* red,
                                                 const uint8_t* mask, int row_lo = 0, int row_hi = 1 << 30) {
   constexpr int OPL = (KMAX + TEAM - 1) / TEAM;  // observations per lane
   const int prob = d.slot_prob[slot];
@@ -343,27 +354,27 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
   const int n = 2 * k;
   const int W = width_of(k);
   const int G = W >> 2;
-  float4* V = reinterpret_cast<float4*>(lds);
-  float* Jpc = lds + 8 * KMAX;
-  const float4 X = d.pts[d.slot_lm[slot]];
+  real4* V = reinterpret_cast<real4*>(lds);
+  real* Jpc = lds + 8 * KMAX;
+  const real4 X = d.pts[d.slot_lm[slot]];
   int buf = 0;
 
   // phase 1: residuals and Jacobians of the lane's observations
-  float3 A[2 * OPL];   // rows 2o, 2o+1 of J_l (scaled below), o = lane + TEAM m
-  float rr[2 * OPL];
-  float cl[3] = {0.f, 0.f, 0.f};
+  real3 A[2 * OPL];   // rows 2o, 2o+1 of J_l (scaled below), o = lane + TEAM m
+  real rr[2 * OPL];
+  real cl[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
-    A[2 * m] = A[2 * m + 1] = make_float3(0.f, 0.f, 0.f);
+    A[2 * m] = A[2 * m + 1] = make_real3(0.f, 0.f, 0.f);
     rr[2 * m] = rr[2 * m + 1] = 0.f;
     if (o < k) {
       Cam C;
       load_cam(d.cam, d.obs_cam[obs0 + o], C);
-      const float2 uv = d.obs_uv[obs0 + o];
-      float r[2], Jp[2][9], Jl[2][3];
+      const real2 uv = d.obs_uv[obs0 + o];
+      real r[2], Jp[2][9], Jl[2][3];
       project<true>(C, X.x, X.y, X.z, uv.x, uv.y, r, Jp, Jl);
-      float sw;
+      real sw;
       (void)robust_term(r[0] * r[0] + r[1] * r[1], d.huber, sw);
       if (sw != 1.0f) {  // Huber IRLS: the observation's rows scaled by sqrt(w)
         r[0] *= sw;
@@ -384,8 +395,8 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
         Jpc[18 * o + j] = Jp[0][j];
         Jpc[18 * o + 9 + j] = Jp[1][j];
       }
-      A[2 * m] = make_float3(Jl[0][0], Jl[0][1], Jl[0][2]);
-      A[2 * m + 1] = make_float3(Jl[1][0], Jl[1][1], Jl[1][2]);
+      A[2 * m] = make_real3(Jl[0][0], Jl[0][1], Jl[0][2]);
+      A[2 * m + 1] = make_real3(Jl[1][0], Jl[1][1], Jl[1][2]);
       rr[2 * m] = r[0];
       rr[2 * m + 1] = r[1];
       cl[0] += Jl[0][0] * Jl[0][0] + Jl[1][0] * Jl[1][0];
@@ -394,9 +405,9 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
     }
   }
   team_sum_n<TEAM, 3>(cl, red, buf);
-  const float sl0 = cl[0] > 0.f ? 1.0f / sqrtf(cl[0]) : 1.0f;
-  const float sl1 = cl[1] > 0.f ? 1.0f / sqrtf(cl[1]) : 1.0f;
-  const float sl2 = cl[2] > 0.f ? 1.0f / sqrtf(cl[2]) : 1.0f;
+  const real sl0 = cl[0] > 0.f ? 1.0f / sqrt(cl[0]) : 1.0f;
+  const real sl1 = cl[1] > 0.f ? 1.0f / sqrt(cl[1]) : 1.0f;
+  const real sl2 = cl[2] > 0.f ? 1.0f / sqrt(cl[2]) : 1.0f;
 #pragma unroll
   for (int i = 0; i < 2 * OPL; ++i) {
     A[i].x *= sl0;
@@ -404,44 +415,44 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
     A[i].z *= sl2;
   }
   auto row_of = [&](int i) { return 2 * (lane + TEAM * (i >> 1)) + (i & 1); };  // own row i -> block row
-  auto comp = [](const float3& a, int j) { return j == 0 ? a.x : (j == 1 ? a.y : a.z); };
+  auto comp = [](const real3& a, int j) { return j == 0 ? a.x : (j == 1 ? a.y : a.z); };
 
   // phase 2: three Householder reflections on the scaled J_l
-  float3 Vr[2 * OPL];
+  real3 Vr[2 * OPL];
 #pragma unroll
-  for (int i = 0; i < 2 * OPL; ++i) Vr[i] = make_float3(0.f, 0.f, 0.f);
-  float tau[3], alph[3], nrms[3], Rrow[3][3];  // Rrow: row j of R1 as seen by its owner
+  for (int i = 0; i < 2 * OPL; ++i) Vr[i] = make_real3(0.f, 0.f, 0.f);
+  real tau[3], alph[3], nrms[3], Rrow[3][3];  // Rrow: row j of R1 as seen by its owner
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     // |x|^2 over rows >= j and x_j itself (contributed by the owner of row j)
-    float sx[2] = {0.f, 0.f};
+    real sx[2] = {0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < 2 * OPL; ++i) {
       const int gi = row_of(i);
-      const float x = comp(A[i], j);
+      const real x = comp(A[i], j);
       if (gi < n && gi >= j) sx[0] += x * x;
       if (gi == j) sx[1] = x;
     }
     team_sum_n<TEAM, 2>(sx, red, buf);
-    const float nrm = sqrtf(sx[0]), xj = sx[1];
-    float alpha = 0.f, vj = 0.f, tj = 0.f;
+    const real nrm = sqrt(sx[0]), xj = sx[1];
+    real alpha = 0.f, vj = 0.f, tj = 0.f;
     if (nrm > 0.f) {
       // v = x + sign(x_j) |x| e_j, so v^T v = 2 |x| (|x| + |x_j|) exactly: tau = 2 / v^T v
       // without the cancellation of |x|^2 - x_j^2 when x_j dominates the column
       alpha = xj >= 0.f ? -nrm : nrm;
       vj = xj - alpha;
-      tj = 1.0f / (nrm * (nrm + fabsf(xj)));
+      tj = 1.0f / (nrm * (nrm + fabs(xj)));
     }
     tau[j] = tj;
     alph[j] = alpha;
     nrms[j] = nrm;
     // reflector j on the lane's rows, and w_m = v^T a_m for the columns m > j
-    float wv[2] = {0.f, 0.f};
+    real wv[2] = {0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < 2 * OPL; ++i) {
       const int gi = row_of(i);
-      const float x = comp(A[i], j);
-      const float vi = (tj == 0.f || gi < j || gi >= n) ? 0.f : (gi == j ? vj : x);
+      const real x = comp(A[i], j);
+      const real vi = (tj == 0.f || gi < j || gi >= n) ? 0.f : (gi == j ? vj : x);
       if (j == 0) Vr[i].x = vi; else if (j == 1) Vr[i].y = vi; else Vr[i].z = vi;
       if (j == 0) { wv[0] += vi * A[i].y; wv[1] += vi * A[i].z; }
       else if (j == 1) { wv[0] += vi * A[i].z; }
@@ -449,14 +460,14 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
     if (j == 0) {
       team_sum_n<TEAM, 2>(wv, red, buf);
     } else if (j == 1) {
-      float w1[1] = {wv[0]};
+      real w1[1] = {wv[0]};
       team_sum_n<TEAM, 1>(w1, red, buf);
       wv[0] = w1[0];
     }
     // apply H_j to the remaining columns m > j of the lane's rows
 #pragma unroll
     for (int i = 0; i < 2 * OPL; ++i) {
-      const float vi = comp(Vr[i], j);
+      const real vi = comp(Vr[i], j);
       if (j == 0) { A[i].y -= tj * vi * wv[0]; A[i].z -= tj * vi * wv[1]; }
       else if (j == 1) { A[i].z -= tj * vi * wv[0]; }
     }
@@ -468,37 +479,37 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
 
   // phase 3: T of the compact WY form (LAPACK larft, forward columnwise) and
   // V^T r, reduced together
-  float dv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  real dv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < 2 * OPL; ++i) {
-    const float3 vv = Vr[i];
-    const float ri = rr[i];
+    const real3 vv = Vr[i];
+    const real ri = rr[i];
     dv[0] += vv.x * vv.y; dv[1] += vv.x * vv.z; dv[2] += vv.y * vv.z;
     dv[3] += vv.x * ri; dv[4] += vv.y * ri; dv[5] += vv.z * ri;
   }
   team_sum_n<TEAM, 6>(dv, red, buf);
-  const float d01 = dv[0], d02 = dv[1], d12 = dv[2], wr0 = dv[3], wr1 = dv[4], wr2 = dv[5];
-  const float T00 = tau[0], T11 = tau[1], T22 = tau[2];
-  const float T01 = -tau[1] * T00 * d01;
-  const float T02 = -tau[2] * (T00 * d02 + T01 * d12);
-  const float T12 = -tau[2] * (T11 * d12);
+  const real d01 = dv[0], d02 = dv[1], d12 = dv[2], wr0 = dv[3], wr1 = dv[4], wr2 = dv[5];
+  const real T00 = tau[0], T11 = tau[1], T22 = tau[2];
+  const real T01 = -tau[1] * T00 * d01;
+  const real T02 = -tau[2] * (T00 * d02 + T01 * d12);
+  const real T12 = -tau[2] * (T11 * d12);
   // residual column: Q^T r = r - V (T^T (V^T r))
-  const float mr0 = T00 * wr0;
-  const float mr1 = T01 * wr0 + T11 * wr1;
-  const float mr2 = T02 * wr0 + T12 * wr1 + T22 * wr2;
-  float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const real mr0 = T00 * wr0;
+  const real mr1 = T01 * wr0 + T11 * wr1;
+  const real mr2 = T02 * wr0 + T12 * wr1 + T22 * wr2;
+  real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
   const bool head = row_lo == 0;  // this chunk writes the landmark record
 #pragma unroll
   for (int i = 0; i < 2 * OPL; ++i) {
     const int gi = row_of(i);
     if (gi < n) {
-      const float3 vv = Vr[i];
-      const float val = rr[i] - (vv.x * mr0 + vv.y * mr1 + vv.z * mr2);
+      const real3 vv = Vr[i];
+      const real val = rr[i] - (vv.x * mr0 + vv.y * mr1 + vv.z * mr2);
       if (head) {
         if (gi < 3) lmd[LMD_QR + gi] = val;
         else if (!IMPLICIT) d.rhoB[2 * (size_t)obs0 + (gi - 3)] = val;
       }
-      V[gi] = make_float4(vv.x, vv.y, vv.z, 0.f);
+      V[gi] = make_real4(vv.x, vv.y, vv.z, 0.f);
     }
     if (!head) continue;
     // R1: the diagonal is alpha_j (or the untouched entry when |x| = 0), the
@@ -523,11 +534,11 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
     // phase 4 (implicit blocks): per observation its record: the pose Jacobian
     // rows, its two rows of the thin factor Q1 = Q[:, 0:3] = E - V T V3^T (V3 the
     // top three rows of V, lower triangular) and its residual
-    float K[3][3];  // K = T V3^T
+    real K[3][3];  // K = T V3^T
     {
-      const float4 v0 = V[0], v1 = V[1], v2 = V[2];
-      const float v3[3][3] = {{v0.x, v0.y, v0.z}, {v1.x, v1.y, v1.z}, {v2.x, v2.y, v2.z}};
-      const float T[3][3] = {{T00, T01, T02}, {0.f, T11, T12}, {0.f, 0.f, T22}};
+      const real4 v0 = V[0], v1 = V[1], v2 = V[2];
+      const real v3[3][3] = {{v0.x, v0.y, v0.z}, {v1.x, v1.y, v1.z}, {v2.x, v2.y, v2.z}};
+      const real T[3][3] = {{T00, T01, T02}, {0.f, T11, T12}, {0.f, 0.f, T22}};
 #pragma unroll
       for (int m = 0; m < 3; ++m)
 #pragma unroll
@@ -537,25 +548,25 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
     for (int m = 0; m < OPL; ++m) {
       const int o = lane + TEAM * m;
       if (o < k) {
-        float q[2][3];
+        real q[2][3];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const float3 vv = Vr[2 * m + h];
+          const real3 vv = Vr[2 * m + h];
           const int gi = 2 * o + h;
 #pragma unroll
           for (int j = 0; j < 3; ++j)
             q[h][j] = (gi == j ? 1.f : 0.f) - (vv.x * K[0][j] + vv.y * K[1][j] + vv.z * K[2][j]);
         }
-        const float* J = Jpc + 18 * o;
-        float4* rec = rec_plane(d, 0) + d.slot_zoff[slot] + o;
+        const real* J = Jpc + 18 * o;
+        real4* rec = rec_plane(d, 0) + d.slot_zoff[slot] + o;
         const size_t P = (size_t)d.NO;
-        rec[0] = make_float4(J[0], J[1], J[2], J[3]);
-        rec[P] = make_float4(J[4], J[5], J[6], J[7]);
-        rec[2 * P] = make_float4(J[8], J[9], J[10], J[11]);
-        rec[3 * P] = make_float4(J[12], J[13], J[14], J[15]);
-        rec[4 * P] = make_float4(J[16], J[17], q[0][0], q[0][1]);
-        rec[5 * P] = make_float4(q[0][2], q[1][0], q[1][1], q[1][2]);
-        rec[6 * P] = make_float4(rr[2 * m], rr[2 * m + 1], 0.f, 0.f);
+        rec[0] = make_real4(J[0], J[1], J[2], J[3]);
+        rec[P] = make_real4(J[4], J[5], J[6], J[7]);
+        rec[2 * P] = make_real4(J[8], J[9], J[10], J[11]);
+        rec[3 * P] = make_real4(J[12], J[13], J[14], J[15]);
+        rec[4 * P] = make_real4(J[16], J[17], q[0][0], q[0][1]);
+        rec[5 * P] = make_real4(q[0][2], q[1][0], q[1][1], q[1][2]);
+        rec[6 * P] = make_real4(rr[2 * m], rr[2 * m + 1], 0.f, 0.f);
       }
     }
     return;
@@ -564,10 +575,10 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
   // phase 4: pose columns, Q^T J_p = J_p - V M with M = T^T (V^T J_p).  Lane
   // g-groups are g = lane + TEAM jg; for a workgroup team the rows are the
   // outer loop, so every output row (up to 18 KB) is written whole, in order.
-  float* outT = d.poolT + d.slot_toff[slot];
-  float* outB = d.poolB + d.slot_boff[slot];
+  real* outT = d.poolT + d.slot_toff[slot];
+  real* outB = d.poolB + d.slot_boff[slot];
   constexpr int NG = (((9 * KMAX + 3) / 4) + TEAM - 1) / TEAM;  // column groups per lane
-  float M0[NG][4], M1[NG][4], M2[NG][4], j0[NG][4], j1[NG][4];
+  real M0[NG][4], M1[NG][4], M2[NG][4], j0[NG][4], j1[NG][4];
   int row0[NG][4];
 #pragma unroll
   for (int jg = 0; jg < NG; ++jg) {
@@ -580,11 +591,11 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
       if (g < G && c < 9 * k) {
         const int o = (unsigned)c / 9u;
         const int m = c - 9 * o;
-        const float a0 = Jpc[18 * o + m], a1 = Jpc[18 * o + 9 + m];
-        const float4 va = V[2 * o], vb = V[2 * o + 1];
-        const float W0 = va.x * a0 + vb.x * a1;
-        const float W1 = va.y * a0 + vb.y * a1;
-        const float W2 = va.z * a0 + vb.z * a1;
+        const real a0 = Jpc[18 * o + m], a1 = Jpc[18 * o + 9 + m];
+        const real4 va = V[2 * o], vb = V[2 * o + 1];
+        const real W0 = va.x * a0 + vb.x * a1;
+        const real W1 = va.y * a0 + vb.y * a1;
+        const real W2 = va.z * a0 + vb.z * a1;
         M0[jg][q] = T00 * W0;
         M1[jg][q] = T01 * W0 + T11 * W1;
         M2[jg][q] = T02 * W0 + T12 * W1 + T22 * W2;
@@ -596,19 +607,19 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
   }
   const int i_end = row_hi < n ? row_hi : n;
   for (int i = row_lo; i < i_end; ++i) {
-    const float4 vv = V[i];
-    float4* row = reinterpret_cast<float4*>(i < 3 ? outT + (size_t)i * W : outB + (size_t)(i - 3) * W);
+    const real4 vv = V[i];
+    real4* row = reinterpret_cast<real4*>(i < 3 ? outT + (size_t)i * W : outB + (size_t)(i - 3) * W);
 #pragma unroll
     for (int jg = 0; jg < NG; ++jg) {
       const int g = lane + TEAM * jg;
       if (g < G) {
-        float out[4];
+        real out[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float base = (i == row0[jg][q]) ? j0[jg][q] : ((i == row0[jg][q] + 1) ? j1[jg][q] : 0.f);
+          const real base = (i == row0[jg][q]) ? j0[jg][q] : ((i == row0[jg][q] + 1) ? j1[jg][q] : 0.f);
           out[q] = base - (vv.x * M0[jg][q] + vv.y * M1[jg][q] + vv.z * M2[jg][q]);
         }
-        row[g] = make_float4(out[0], out[1], out[2], out[3]);
+        row[g] = make_real4(out[0], out[1], out[2], out[3]);
       }
     }
   }
@@ -624,30 +635,30 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
 // On return Rh holds the damped upper triangle, qrh the damped Q1^T r and
 // dr the residuals of the three rotated damping rows.
 struct Givens6 {
-  float c[6], s[6];
+  real c[6], s[6];
 };
 
-__device__ __forceinline__ void damping_rotations(const float* lmd, float sqlam, Givens6& G, float Rh[3][3],
-                                                  float qrh[3], float dr[3]) {
-  float t[3][4];  // top rows: 3 landmark columns + residual
+__device__ __forceinline__ void damping_rotations(const real* lmd, real sqlam, Givens6& G, real Rh[3][3],
+                                                  real qrh[3], real dr[3]) {
+  real t[3][4];  // top rows: 3 landmark columns + residual
   t[0][0] = lmd[LMD_R + 0]; t[0][1] = lmd[LMD_R + 1]; t[0][2] = lmd[LMD_R + 2]; t[0][3] = lmd[LMD_QR + 0];
   t[1][0] = 0.f;            t[1][1] = lmd[LMD_R + 3]; t[1][2] = lmd[LMD_R + 4]; t[1][3] = lmd[LMD_QR + 1];
   t[2][0] = 0.f;            t[2][1] = 0.f;            t[2][2] = lmd[LMD_R + 5]; t[2][3] = lmd[LMD_QR + 2];
   int idx = 0;
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    float dd[4] = {0.f, 0.f, 0.f, 0.f};
+    real dd[4] = {0.f, 0.f, 0.f, 0.f};
     dd[e] = sqlam;
 #pragma unroll
     for (int j = e; j < 3; ++j) {
-      const float a = t[j][j], b = dd[j];
-      const float rho = hypotf(a, b);
-      float c = 1.f, s = 0.f;
+      const real a = t[j][j], b = dd[j];
+      const real rho = hypot(a, b);
+      real c = 1.f, s = 0.f;
       if (rho > 0.f) { c = a / rho; s = b / rho; }
       G.c[idx] = c; G.s[idx] = s; ++idx;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const float tm = t[j][m], dm = dd[m];
+        const real tm = t[j][m], dm = dd[m];
         t[j][m] = c * tm + s * dm;
         dd[m] = -s * tm + c * dm;
       }
@@ -665,16 +676,16 @@ __device__ __forceinline__ void damping_rotations(const float* lmd, float sqlam,
 
 // Apply the same rotation sequence to one column: top rows t[3] (in: undamped,
 // out: damped) and damping rows dd[3] (in: 0, out: the three new B rows).
-__device__ __forceinline__ void rotate_column(const Givens6& G, float t[3], float dd[3]) {
+__device__ __forceinline__ void rotate_column(const Givens6& G, real t[3], real dd[3]) {
   int idx = 0;
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     dd[e] = 0.f;
 #pragma unroll
     for (int j = e; j < 3; ++j) {
-      const float c = G.c[idx], s = G.s[idx];
+      const real c = G.c[idx], s = G.s[idx];
       ++idx;
-      const float tm = t[j], dm = dd[e];
+      const real tm = t[j], dm = dd[e];
       t[j] = c * tm + s * dm;
       dd[e] = -s * tm + c * dm;
     }
@@ -692,11 +703,11 @@ __device__ __forceinline__ void damp_one(const Dev& d, int slot, int lane, const
   const int obs0 = d.slot_obs0[slot];
   const int W = width_of(k);
   const int G = W >> 2;
-  float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
-  const float lam = (float)d.lambda[prob];
+  real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const real lam = (real)d.lambda[prob];
   Givens6 Gv;
-  float Rh[3][3], qrh[3], dr[3];
-  damping_rotations(lmd, sqrtf(lam), Gv, Rh, qrh, dr);
+  real Rh[3][3], qrh[3], dr[3];
+  damping_rotations(lmd, sqrt(lam), Gv, Rh, qrh, dr);
   if (lane == 0) {
     lmd[LMD_RH + 0] = Rh[0][0]; lmd[LMD_RH + 1] = Rh[0][1]; lmd[LMD_RH + 2] = Rh[0][2];
     lmd[LMD_RH + 3] = Rh[1][1]; lmd[LMD_RH + 4] = Rh[1][2]; lmd[LMD_RH + 5] = Rh[2][2];
@@ -704,12 +715,12 @@ __device__ __forceinline__ void damp_one(const Dev& d, int slot, int lane, const
     lmd[LMD_LAM] = lam;
   }
   if (lane < 3) d.rhoB[2 * (size_t)obs0 + 2 * k - 3 + lane] = dr[lane];
-  const float4* T = reinterpret_cast<const float4*>(d.poolT + d.slot_toff[slot]);
-  float4* B = reinterpret_cast<float4*>(d.poolB + d.slot_boff[slot] + (size_t)(2 * k - 3) * W);
+  const real4* T = reinterpret_cast<const real4*>(d.poolT + d.slot_toff[slot]);
+  real4* B = reinterpret_cast<real4*>(d.poolB + d.slot_boff[slot] + (size_t)(2 * k - 3) * W);
   for (int g = lane; g < G; g += TEAM) {
-    const float4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
-    float a[3], b[3];
-    float4 o0, o1, o2;
+    const real4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
+    real a[3], b[3];
+    real4 o0, o1, o2;
     a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b); o0.x = b[0]; o1.x = b[1]; o2.x = b[2];
     a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b); o0.y = b[0]; o1.y = b[1]; o2.y = b[2];
     a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, b); o0.z = b[0]; o1.z = b[1]; o2.z = b[2];
@@ -732,21 +743,21 @@ __device__ __forceinline__ void precond_one(const Dev& d, int slot, int lane) {
   const int k = d.slot_k[slot];
   const int obs0 = d.slot_obs0[slot];
   const int W = width_of(k);
-  const float* B = d.poolB + d.slot_boff[slot];
-  const float* rho = d.rhoB + 2 * (size_t)obs0;
+  const real* B = d.poolB + d.slot_boff[slot];
+  const real* rho = d.rhoB + 2 * (size_t)obs0;
   for (int o = lane; o < k; o += TEAM) {
-    float g[45], h[9];
+    real g[45], h[9];
 #pragma unroll
     for (int e = 0; e < 45; ++e) g[e] = 0.f;
 #pragma unroll
     for (int e = 0; e < 9; ++e) h[e] = 0.f;
 #pragma unroll 2
     for (int r = 0; r < 2 * k; ++r) {
-      const float* row = B + (size_t)r * W + 9 * o;
-      float b[9];
+      const real* row = B + (size_t)r * W + 9 * o;
+      real b[9];
 #pragma unroll
       for (int e = 0; e < 9; ++e) b[e] = row[e];
-      const float rr = rho[r];
+      const real rr = rho[r];
       int e = 0;
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
@@ -755,7 +766,7 @@ __device__ __forceinline__ void precond_one(const Dev& d, int slot, int lane) {
         for (int c = a; c < 9; ++c) g[e++] += b[a] * b[c];
       }
     }
-    float* out = d.obsbuf + (size_t)(obs0 + o) * 54;
+    real* out = d.obsbuf + (size_t)(obs0 + o) * 54;
 #pragma unroll
     for (int e = 0; e < 45; ++e) out[e] = g[e];
 #pragma unroll
@@ -771,29 +782,29 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
   const int lane = threadIdx.x;
   const int prob = d.cam_prob[c];
   if (!d.active[prob]) return;
-  float acc[54];
+  real acc[54];
 #pragma unroll
   for (int e = 0; e < 54; ++e) acc[e] = 0.f;
   const int b = d.cam_obs_off[c], e1 = d.cam_obs_off[c + 1];
   for (int i = b + lane; i < e1; i += 64) {
-    const float* src = d.obsbuf + (size_t)d.cam_obs_idx[i] * 54;
+    const real* src = d.obsbuf + (size_t)d.cam_obs_idx[i] * 54;
 #pragma unroll
     for (int e = 0; e < 54; ++e) acc[e] += src[e];
   }
 #pragma unroll
   for (int e = 0; e < 54; ++e) acc[e] = wave_sum_f(acc[e]);
   if (lane != 0) return;
-  float s[9];
+  real s[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) s[a] = d.s_cam[9 * c + a];
-  const float lam = (float)d.lambda[prob];
-  float P[9][9];
+  const real lam = (real)d.lambda[prob];
+  real P[9][9];
   int e = 0;
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
 #pragma unroll
     for (int q = a; q < 9; ++q) {
-      const float v = s[a] * acc[e++] * s[q];
+      const real v = s[a] * acc[e++] * s[q];
       P[a][q] = v;
       P[q][a] = v;
     }
@@ -804,20 +815,20 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
     d.vb[9 * c + a] = s[a] * acc[45 + a];
   }
   // Cholesky P = L L^T (lower, in place)
-  float L[9][9];
+  real L[9][9];
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
-    float dj = P[j][j];
+    real dj = P[j][j];
 #pragma unroll
     for (int q = 0; q < j; ++q) dj -= L[j][q] * L[j][q];
     if (!(dj > 0.f)) { ok = false; dj = 1.f; }
-    const float ljj = sqrtf(dj);
+    const real ljj = sqrt(dj);
     L[j][j] = ljj;
-    const float il = 1.0f / ljj;
+    const real il = 1.0f / ljj;
 #pragma unroll
     for (int i = j + 1; i < 9; ++i) {
-      float v = P[i][j];
+      real v = P[i][j];
 #pragma unroll
       for (int q = 0; q < j; ++q) v -= L[i][q] * L[j][q];
       L[i][j] = v * il;
@@ -825,13 +836,13 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
 #pragma unroll
     for (int i = 0; i < j; ++i) L[i][j] = 0.f;
   }
-  float* mi = d.minv + 81 * (size_t)c;
+  real* mi = d.minv + 81 * (size_t)c;
   // features of the block for the learned preconditioner, and its Cholesky
   // factor (a failed factorization is replaced by the square root of the diagonal)
   {
     float* f = d.feats + 64 * (size_t)c;
     float* lf = d.lfac + 45 * (size_t)c;
-    float tr = 0.f;
+    real tr = 0.f;
     int e2 = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -850,7 +861,7 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
 #pragma unroll
     for (int a = 0; a < 9; ++a)
 #pragma unroll
-      for (int q = 0; q <= a; ++q) lf[e3++] = ok ? L[a][q] : (a == q ? sqrtf(P[a][a]) : 0.f);
+      for (int q = 0; q <= a; ++q) lf[e3++] = ok ? L[a][q] : (a == q ? sqrt(P[a][a]) : 0.f);
   }
   if (!ok) {
     atomicAdd(d.chol_fail, 1);
@@ -861,7 +872,7 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
     return;
   }
   // inverse of L (lower), then M^-1 = L^-T L^-1
-  float Li[9][9];
+  real Li[9][9];
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
 #pragma unroll
@@ -869,7 +880,7 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
     Li[j][j] = 1.0f / L[j][j];
 #pragma unroll
     for (int i = j + 1; i < 9; ++i) {
-      float v = 0.f;
+      real v = 0.f;
 #pragma unroll
       for (int q = j; q < i; ++q) v -= L[i][q] * Li[q][j];
       Li[i][j] = v / L[i][i];
@@ -879,7 +890,7 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
   for (int a = 0; a < 9; ++a) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      float v = 0.f;
+      real v = 0.f;
 #pragma unroll
       for (int i = (a > q ? a : q); i < 9; ++i) v += Li[i][a] * Li[i][q];
       mi[9 * a + q] = v;
@@ -892,12 +903,12 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
 // Gather of the landmark's slice of the scaled direction vector for the 4
 // columns of column group g: p'[c] = s[cam, m] * v[cam, m].  Columns past 9k
 // read a valid entry and give 0 (no conditional loads).
-__device__ __forceinline__ float4 gather_cols(const Dev& d, const float* __restrict__ v, int obs0, int k, int g) {
+__device__ __forceinline__ real4 gather_cols(const Dev& d, const real* __restrict__ v, int obs0, int k, int g) {
   const int n = 9 * k;
   const int c0 = min(4 * g, n - 1), c3 = min(4 * g + 3, n - 1);
   const int oa = (unsigned)c0 / 9u, ob = (unsigned)c3 / 9u;  // at most two observations
   const int ca = 9 * d.obs_cam[obs0 + oa], cb = 9 * d.obs_cam[obs0 + ob];
-  float out[4];
+  real out[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int c = min(4 * g + q, n - 1);
@@ -905,12 +916,12 @@ __device__ __forceinline__ float4 gather_cols(const Dev& d, const float* __restr
     const int idx = (o == oa ? ca : cb) + (c - 9 * o);
     out[q] = (4 * g + q < n) ? d.s_cam[idx] * v[idx] : 0.f;
   }
-  return make_float4(out[0], out[1], out[2], out[3]);
+  return make_real4(out[0], out[1], out[2], out[3]);
 }
 
-__device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
+__device__ __forceinline__ real dot4(real4 a, real4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 
-__device__ __forceinline__ void axpy4(float4& z, float y, float4 b) {
+__device__ __forceinline__ void axpy4(real4& z, real y, real4 b) {
   z.x += y * b.x;
   z.y += y * b.y;
   z.z += y * b.z;
@@ -920,8 +931,8 @@ __device__ __forceinline__ void axpy4(float4& z, float y, float4 b) {
 // Store the outputs of column group g: every landmark owns a 16-byte aligned
 // region of W floats at obsbuf[slot_zoff] (its 9k outputs, observation-major,
 // then padding), written as whole float4s so no cache line is partly written.
-__device__ __forceinline__ void store_cols(const Dev& d, int zoff, int g, float4 z) {
-  reinterpret_cast<float4*>(d.obsbuf + zoff)[g] = z;
+__device__ __forceinline__ void store_cols(const Dev& d, int zoff, int g, real4 z) {
+  reinterpret_cast<real4*>(d.obsbuf + zoff)[g] = z;
 }
 
 
@@ -937,7 +948,7 @@ __device__ __forceinline__ void store_cols(const Dev& d, int zoff, int g, float4
 // the last batch re-read row 2k-1 (cached) and are given y = 0.  Writes z
 // (unscaled, 9 values per observation) to obsbuf.
 template <int TEAM, int RB, bool PCG>
-__device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, const float* __restrict__ v) {
+__device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, const real* __restrict__ v) {
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
   const int slot = s0 + team;
@@ -946,7 +957,7 @@ __device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, con
   const int k = d.slot_k[slot];
   const int obs0 = d.slot_obs0[slot];
   const int zoff = d.slot_zoff[slot];
-  const float4* __restrict__ Bs = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
+  const real4* __restrict__ Bs = reinterpret_cast<const real4*>(d.poolB + d.slot_boff[slot]);
   // While every problem of the PCG solve is still running, the first rows and the
   // camera gather are requested before the problem's flags are tested (all these
   // addresses are in bounds whatever the flags say); once one has stopped, its
@@ -955,23 +966,23 @@ __device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, con
   const int dn = PCG ? d.done[prob] : 0;
   if (PCG && d.pcg_skip[0] && (!act || dn)) return;
   const int G = width_of(k) >> 2, n = 2 * k;
-  const float4* __restrict__ Bj = Bs + min(lane, G - 1);
-  float4 c[RB];
+  const real4* __restrict__ Bj = Bs + min(lane, G - 1);
+  real4 c[RB];
 #pragma unroll
   for (int i = 0; i < RB; ++i) c[i] = Bj[(size_t)min(i, n - 1) * G];
-  const float4 pv = lane < G ? gather_cols(d, v, obs0, k, lane) : make_float4(0.f, 0.f, 0.f, 0.f);
+  const real4 pv = lane < G ? gather_cols(d, v, obs0, k, lane) : make_real4(0.f, 0.f, 0.f, 0.f);
   if (!act || dn) return;  // uniform over the team
-  float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  real4 z = make_real4(0.f, 0.f, 0.f, 0.f);
   for (int r = 0; r < n; r += RB) {
     const int rn = r + RB;
-    float4 nx[RB];
+    real4 nx[RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i) nx[i] = c[i];
     if (rn < n) {
 #pragma unroll
       for (int i = 0; i < RB; ++i) nx[i] = Bj[(size_t)min(rn + i, n - 1) * G];
     }
-    float y[RB];
+    real y[RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i) y[i] = team_sum<TEAM>(dot4(c[i], pv));
 #pragma unroll
@@ -988,38 +999,38 @@ __device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, con
 // step's rows are requested before the current ones are reduced.  The 4
 // partial z vectors are summed through LDS in a fixed order.
 template <int NCG, int RS, bool PCG>
-__device__ __forceinline__ void matvec_large(const Dev& d, int slot, const float* v, float4 (*zred)[64]) {
+__device__ __forceinline__ void matvec_large(const Dev& d, int slot, const real* v, real4 (*zred)[64]) {
   const int prob = d.slot_prob[slot];
   const int k = d.slot_k[slot];
   const int obs0 = d.slot_obs0[slot];
   const int zoff = d.slot_zoff[slot];
-  const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
+  const real4* __restrict__ B = reinterpret_cast<const real4*>(d.poolB + d.slot_boff[slot]);
   if (!d.active[prob] || (PCG && d.done[prob])) return;
   const int G = width_of(k) >> 2;
   const int n = 2 * k;
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  auto load = [&](int r, float4 (&b)[RS][NCG]) {
+  auto load = [&](int r, real4 (&b)[RS][NCG]) {
 #pragma unroll
     for (int i = 0; i < RS; ++i) {
       const int rr = min(r + 4 * i, n - 1);
 #pragma unroll
       for (int j = 0; j < NCG; ++j) {
-        b[i][j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        b[i][j] = make_real4(0.f, 0.f, 0.f, 0.f);
         if (64 * j < G) b[i][j] = B[(size_t)rr * G + min(lane + 64 * j, G - 1)];
       }
     }
   };
-  float4 b[RS][NCG], pv[NCG], z[NCG];
+  real4 b[RS][NCG], pv[NCG], z[NCG];
   load(w, b);  // n >= 58 > w
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
     const int g = lane + 64 * j;
-    pv[j] = g < G ? gather_cols(d, v, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
-    z[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    pv[j] = g < G ? gather_cols(d, v, obs0, k, g) : make_real4(0.f, 0.f, 0.f, 0.f);
+    z[j] = make_real4(0.f, 0.f, 0.f, 0.f);
   }
   for (int r = w; r < n; r += 4 * RS) {
-    float4 nb[RS][NCG];
+    real4 nb[RS][NCG];
     if (r + 4 * RS < n) {
       load(r + 4 * RS, nb);
     } else {
@@ -1030,7 +1041,7 @@ __device__ __forceinline__ void matvec_large(const Dev& d, int slot, const float
     }
 #pragma unroll
     for (int i = 0; i < RS; ++i) {
-      float y = 0.f;
+      real y = 0.f;
 #pragma unroll
       for (int j = 0; j < NCG; ++j) y += dot4(b[i][j], pv[j]);
       y = wave_sum_f(y);
@@ -1049,8 +1060,8 @@ __device__ __forceinline__ void matvec_large(const Dev& d, int slot, const float
     zred[w][lane] = z[j];
     __syncthreads();
     if (w == 0) {
-      const float4 a = zred[0][lane], b2 = zred[1][lane], c = zred[2][lane], e = zred[3][lane];
-      const float4 s = make_float4((a.x + b2.x) + (c.x + e.x), (a.y + b2.y) + (c.y + e.y),
+      const real4 a = zred[0][lane], b2 = zred[1][lane], c = zred[2][lane], e = zred[3][lane];
+      const real4 s = make_real4((a.x + b2.x) + (c.x + e.x), (a.y + b2.y) + (c.y + e.y),
                                    (a.z + b2.z) + (c.z + e.z), (a.w + b2.w) + (c.w + e.w));
       const int g = lane + 64 * j;
       if (g < G) store_cols(d, zoff, g, s);
@@ -1073,8 +1084,8 @@ __host__ __device__ constexpr int mv_per_wg(int j) {  // j: launch-order class i
 // holds no class-4 code and needs fewer registers (more resident wavefronts);
 // class 4 then runs as its own launch (k_matvec_large).
 template <bool PCG, bool LARGE, int RBS>
-__device__ __forceinline__ void matvec_block(const Dev& d, const ClassGrid& m, int b, const float* v,
-                                             float4 (*zred)[64]) {
+__device__ __forceinline__ void matvec_block(const Dev& d, const ClassGrid& m, int b, const real* v,
+                                             real4 (*zred)[64]) {
   if constexpr (LARGE) {
     if (b < m.nblk[0]) { matvec_large<4, MV_RS, PCG>(d, m.first[0] + b, v, zred); return; }
     b -= m.nblk[0];
@@ -1092,8 +1103,8 @@ __device__ __forceinline__ void matvec_block(const Dev& d, const ClassGrid& m, i
 // block, or, PERSIST, a fixed grid whose workgroups take blocks b, b + grid,
 // ... in turn (largest landmarks first, so the static round-robin balances).
 template <bool PCG, bool LARGE, int RBS, bool PERSIST>
-__global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, int nwork, const float* v) {
-  __shared__ float4 zred[LARGE ? 4 : 1][64];
+__global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, int nwork, const real* v) {
+  __shared__ real4 zred[LARGE ? 4 : 1][64];
   if constexpr (PERSIST) {
     for (int b = blockIdx.x; b < nwork; b += gridDim.x) matvec_block<PCG, LARGE, RBS>(d, m, b, v, zred);
   } else {
@@ -1103,8 +1114,8 @@ __global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, int nwork, co
 
 // Class 4 on its own: one landmark per workgroup.
 template <bool PCG>
-__global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int slot0, const float* v) {
-  __shared__ float4 zred[4][64];
+__global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int slot0, const real* v) {
+  __shared__ real4 zred[4][64];
   matvec_large<4, MV_RS, PCG>(d, slot0 + blockIdx.x, v, zred);
 }
 
@@ -1114,36 +1125,36 @@ __global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int slot0, const flo
 // (wave w takes rows w, w+4, ... of the block) and writes its partial z for
 // the block; a landmark with a single block writes its outputs directly.
 template <bool PCG>
-__global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, int rows, const float* v) {
+__global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, int rows, const real* v) {
   constexpr int NCG = 18;  // ceil(width_of(512) / 4 / 64)
-  __shared__ float4 zred[4][64];
+  __shared__ real4 zred[4][64];
   const int2 job = d.hjob[blockIdx.x];
   const int slot = job.x;
   const int prob = d.slot_prob[slot];
   const int k = d.slot_k[slot];
   const int obs0 = d.slot_obs0[slot];
-  const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
+  const real4* __restrict__ B = reinterpret_cast<const real4*>(d.poolB + d.slot_boff[slot]);
   if (!d.active[prob] || (PCG && d.done[prob])) return;
   const int G = width_of(k) >> 2;
   const int n = 2 * k;
   const int r0 = job.y * rows, r1 = min(n, r0 + rows);
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  float4 b[NCG], pv[NCG], z[NCG];
+  real4 b[NCG], pv[NCG], z[NCG];
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
     const int g = lane + 64 * j;
-    pv[j] = g < G ? gather_cols(d, v, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
-    z[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    pv[j] = g < G ? gather_cols(d, v, obs0, k, g) : make_real4(0.f, 0.f, 0.f, 0.f);
+    z[j] = make_real4(0.f, 0.f, 0.f, 0.f);
   }
   for (int r = r0 + w; r < r1; r += 4) {
-    const float4* row = B + (size_t)r * G + lane;
+    const real4* row = B + (size_t)r * G + lane;
 #pragma unroll
     for (int j = 0; j < NCG; ++j) {
-      b[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+      b[j] = make_real4(0.f, 0.f, 0.f, 0.f);
       if (lane + 64 * j < G) b[j] = row[64 * j];
     }
-    float y = 0.f;
+    real y = 0.f;
 #pragma unroll
     for (int j = 0; j < NCG; ++j) y += dot4(b[j], pv[j]);
     y = wave_sum_f(y);
@@ -1151,16 +1162,16 @@ __global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, int rows, 
     for (int j = 0; j < NCG; ++j) axpy4(z[j], y, b[j]);
   }
   const bool single = n <= rows;
-  float4* dst = single ? reinterpret_cast<float4*>(d.obsbuf + d.slot_zoff[slot])
-                       : reinterpret_cast<float4*>(d.zpart + d.hz_off[slot - slot0] + (size_t)job.y * (4 * G));
+  real4* dst = single ? reinterpret_cast<real4*>(d.obsbuf + d.slot_zoff[slot])
+                       : reinterpret_cast<real4*>(d.zpart + d.hz_off[slot - slot0] + (size_t)job.y * (4 * G));
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
     if (64 * j >= G) break;  // uniform across the workgroup
     zred[w][lane] = z[j];
     __syncthreads();
     if (w == 0) {
-      const float4 a = zred[0][lane], b2 = zred[1][lane], c = zred[2][lane], e = zred[3][lane];
-      const float4 s = make_float4((a.x + b2.x) + (c.x + e.x), (a.y + b2.y) + (c.y + e.y),
+      const real4 a = zred[0][lane], b2 = zred[1][lane], c = zred[2][lane], e = zred[3][lane];
+      const real4 s = make_real4((a.x + b2.x) + (c.x + e.x), (a.y + b2.y) + (c.y + e.y),
                                    (a.z + b2.z) + (c.z + e.z), (a.w + b2.w) + (c.w + e.w));
       const int g = lane + 64 * j;
       if (g < G) dst[g] = s;
@@ -1182,12 +1193,12 @@ __global__ __launch_bounds__(WG) void k_matvec_combine(Dev d, int slot0, int row
   if (n <= rows) return;
   const int nblk = (n + rows - 1) / rows;
   const int G = width_of(k) >> 2;
-  const float4* __restrict__ src = reinterpret_cast<const float4*>(d.zpart + d.hz_off[blockIdx.x]);
-  float4* dst = reinterpret_cast<float4*>(d.obsbuf + d.slot_zoff[slot]);
+  const real4* __restrict__ src = reinterpret_cast<const real4*>(d.zpart + d.hz_off[blockIdx.x]);
+  real4* dst = reinterpret_cast<real4*>(d.obsbuf + d.slot_zoff[slot]);
   for (int g = threadIdx.x; g < G; g += WG) {
-    float4 s = src[g];
+    real4 s = src[g];
     for (int r = 1; r < nblk; ++r) {
-      const float4 t = src[(size_t)r * G + g];
+      const real4 t = src[(size_t)r * G + g];
       s.x += t.x; s.y += t.y; s.z += t.z; s.w += t.w;
     }
     dst[g] = s;
@@ -1236,10 +1247,10 @@ __device__ __forceinline__ void problem_sum2(const Dev& d, const double* __restr
   sb = wave_sum_d(sb);
 }
 
-__device__ __forceinline__ void minv_apply(const float* __restrict__ mi, const float r[9], float z[9]) {
+__device__ __forceinline__ void minv_apply(const real* __restrict__ mi, const real r[9], real z[9]) {
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
-    float v = 0.f;
+    real v = 0.f;
 #pragma unroll
     for (int q = 0; q < 9; ++q) v += mi[9 * a + q] * r[q];
     z[a] = v;
@@ -1253,7 +1264,7 @@ __global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
   const int prob = d.cam_prob[c];
   double rz = 0.0, rr = 0.0;
   if (d.active[prob]) {
-    float r[9], z[9];
+    real r[9], z[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       r[a] = -d.vb[9 * c + a];
@@ -1332,9 +1343,9 @@ __device__ __forceinline__ void q_positions(const Dev& d, int i0, int e, int zp[
 }
 
 __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
-  __shared__ float part[4][9];
-  __shared__ float pqs[9];
-  __shared__ float beta_s;
+  __shared__ real part[4][9];
+  __shared__ real pqs[9];
+  __shared__ real beta_s;
   __shared__ int go_s;
   const int c = blockIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1344,7 +1355,7 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
   const int prob = d.cam_prob[c];
   int zp[Q_UNROLL];
   q_positions(d, b, e, zp);
-  float zc = 0.f, pc = 0.f, qc = 0.f, sc = 0.f;
+  real zc = 0.f, pc = 0.f, qc = 0.f, sc = 0.f;
   if (threadIdx.x < 9) {
     const int idx = 9 * c + threadIdx.x;
     zc = d.vz[idx];
@@ -1374,11 +1385,11 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
       }
     }
     if (lane == 0) {
-      beta_s = (float)beta;
+      beta_s = (real)beta;
       go_s = t == 0;
     }
   }
-  float acc[9];
+  real acc[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = 0.f;
   if (d.sc) {  // the Schur-complement product is already per camera
@@ -1394,14 +1405,14 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
 #pragma unroll
     for (int j = 0; j < Q_UNROLL; ++j) {
       if (zp[j] >= 0) {
-        if (d.implicit) {  // 16-byte aligned rows of 12 floats
-          const float4* s4 = reinterpret_cast<const float4*>(d.obsbuf + zp[j]);
-          const float4 a0 = s4[0], a1 = s4[1], a2 = s4[2];
+        if (d.implicit) {  // 4-element aligned rows of 12 elements
+          const real4* s4 = reinterpret_cast<const real4*>(d.obsbuf + zp[j]);
+          const real4 a0 = s4[0], a1 = s4[1], a2 = s4[2];
           acc[0] += a0.x; acc[1] += a0.y; acc[2] += a0.z; acc[3] += a0.w;
           acc[4] += a1.x; acc[5] += a1.y; acc[6] += a1.z; acc[7] += a1.w;
           acc[8] += a2.x;
         } else {
-          const float* src = d.obsbuf + zp[j];
+          const real* src = d.obsbuf + zp[j];
 #pragma unroll
           for (int a = 0; a < 9; ++a) acc[a] += src[a];
         }
@@ -1423,11 +1434,11 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
   if (threadIdx.x < 9) {
     const int a = threadIdx.x;
     const int idx = 9 * c + a;
-    const float s = (part[0][a] + part[1][a]) + (part[2][a] + part[3][a]);
-    const float beta = beta_s;
-    const float az = sc * s + (float)d.lambda[prob] * zc;  // (A z) of this camera
-    const float pn = zc + beta * pc;
-    const float qn = az + beta * qc;
+    const real s = (part[0][a] + part[1][a]) + (part[2][a] + part[3][a]);
+    const real beta = beta_s;
+    const real az = sc * s + (real)d.lambda[prob] * zc;  // (A z) of this camera
+    const real pn = zc + beta * pc;
+    const real qn = az + beta * qc;
     d.vp[idx] = pn;
     d.vq[idx] = qn;
     pqs[a] = pn * qn;
@@ -1448,10 +1459,10 @@ constexpr int UPD_CAMS = 28;
 constexpr int UPD_THREADS = 9 * UPD_CAMS;  // 252
 
 __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
-  __shared__ float rs[UPD_CAMS][9];
-  __shared__ float prz[UPD_CAMS][9];
-  __shared__ float prr[UPD_CAMS][9];
-  __shared__ float alpha_s[UPD_CAMS];
+  __shared__ real rs[UPD_CAMS][9];
+  __shared__ real prz[UPD_CAMS][9];
+  __shared__ real prr[UPD_CAMS][9];
+  __shared__ real alpha_s[UPD_CAMS];
   const int lc = threadIdx.x / 9, a = threadIdx.x - 9 * (threadIdx.x / 9);
   const int c0 = blockIdx.x * UPD_CAMS;
   const int c = c0 + lc;
@@ -1459,7 +1470,7 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
   const bool valid = c < d.NC && lc < UPD_CAMS;
   // loads that do not depend on alpha first
   int prob = 0;
-  float xv = 0.f, pv = 0.f, rv = 0.f, qv = 0.f, sv = 0.f, mrow[9];
+  real xv = 0.f, pv = 0.f, rv = 0.f, qv = 0.f, sv = 0.f, mrow[9];
   const int idx = 9 * c + a;
   if (valid) {
     prob = d.cam_prob[c];
@@ -1468,7 +1479,7 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
     pv = d.vp[idx];
     rv = d.vr[idx];
     qv = d.vq[idx];
-    const float* mi = d.minv + 81 * (size_t)c + 9 * a;
+    const real* mi = d.minv + 81 * (size_t)c + 9 * a;
 #pragma unroll
     for (int j = 0; j < 9; ++j) mrow[j] = mi[j];
   }
@@ -1484,11 +1495,11 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
       const int h = __builtin_ctzll(heads);
       heads &= heads - 1;
       const int p = __shfl(pl, h);
-      float al = 0.f;
+      real al = 0.f;
       if (d.active[p] && !d.done[p]) {
         const double pq = problem_sum(d, d.cam_part, p, lane);
         const bool ok = pq > 0.0 && isfinite(pq);
-        al = ok ? (float)(d.rz_next[p] / pq) : 0.f;
+        al = ok ? (real)(d.rz_next[p] / pq) : 0.f;
         const int f = d.prob_cam_off[p];
         if (lane == 0 && f >= c0 && f < c0 + UPD_CAMS) {  // designated writer
           if (ok) {
@@ -1510,9 +1521,9 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
   }
   __syncthreads();
   bool live = false;
-  float r = 0.f, z = 0.f;
+  real r = 0.f, z = 0.f;
   if (valid) {
-    const float alpha = alpha_s[lc];
+    const real alpha = alpha_s[lc];
     live = d.active[prob] && alpha != 0.f;
     if (live) {
       d.vx[idx] = xv + alpha * pv;
@@ -1574,7 +1585,7 @@ __global__ __launch_bounds__(WG) void k_pcg_final(Dev d) {
 // undamped linear model, summed over all its rotated rows:
 //   pred_l = -sum u (2 rho + u) + lambda |dx~_l|^2,   u = rows . (S dx_p, dx~_l).
 template <int TEAM, int NCG>
-__device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, float* red4) {
+__device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, real* red4) {
   const int prob = d.slot_prob[slot];
   const int lm = d.slot_lm[slot];
   if (!d.active[prob]) return;
@@ -1582,23 +1593,23 @@ __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, fl
   const int obs0 = d.slot_obs0[slot];
   const int W = width_of(k);
   const int G = W >> 2;
-  const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
-  const float lam = (float)d.lambda[prob];
+  const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const real lam = (real)d.lambda[prob];
   Givens6 Gv;
-  float Rh[3][3], qrh[3], dr[3];
-  damping_rotations(lmd, sqrtf(lam), Gv, Rh, qrh, dr);
-  const float4* T = reinterpret_cast<const float4*>(d.poolT + d.slot_toff[slot]);
-  const float4* B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
-  float4 pv[NCG];
-  float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+  real Rh[3][3], qrh[3], dr[3];
+  damping_rotations(lmd, sqrt(lam), Gv, Rh, qrh, dr);
+  const real4* T = reinterpret_cast<const real4*>(d.poolT + d.slot_toff[slot]);
+  const real4* B = reinterpret_cast<const real4*>(d.poolB + d.slot_boff[slot]);
+  real4 pv[NCG];
+  real u0 = 0.f, u1 = 0.f, u2 = 0.f;
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
     const int g = lane + TEAM * j;
-    pv[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    pv[j] = make_real4(0.f, 0.f, 0.f, 0.f);
     if (g < G) {
       pv[j] = gather_cols(d, d.vx, obs0, k, g);
-      const float4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
-      float a[3], b[3];
+      const real4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
+      real a[3], b[3];
       a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b);
       u0 += a[0] * pv[j].x; u1 += a[1] * pv[j].x; u2 += a[2] * pv[j].x;
       a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b);
@@ -1613,22 +1624,22 @@ __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, fl
   u1 = tsum<TEAM>(u1, red4);
   u2 = tsum<TEAM>(u2, red4);
   // R^ dx~ = -(qrh + u), upper triangular
-  const float c0 = -(qrh[0] + u0), c1 = -(qrh[1] + u1), c2 = -(qrh[2] + u2);
-  const float x2 = c2 / Rh[2][2];
-  const float x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
-  const float x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
+  const real c0 = -(qrh[0] + u0), c1 = -(qrh[1] + u1), c2 = -(qrh[2] + u2);
+  const real x2 = c2 / Rh[2][2];
+  const real x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
+  const real x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
   // predicted decrease: top rows, then the 2k B rows
   double pred = 0.0;
   if (lane == 0) {
-    const float ut0 = u0 + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
-    const float ut1 = u1 + Rh[1][1] * x1 + Rh[1][2] * x2;
-    const float ut2 = u2 + Rh[2][2] * x2;
+    const real ut0 = u0 + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
+    const real ut1 = u1 + Rh[1][1] * x1 + Rh[1][2] * x2;
+    const real ut2 = u2 + Rh[2][2] * x2;
     pred = -(double)(ut0 * (2.f * qrh[0] + ut0)) - (double)(ut1 * (2.f * qrh[1] + ut1)) -
            (double)(ut2 * (2.f * qrh[2] + ut2)) + (double)lam * ((double)x0 * x0 + (double)x1 * x1 + (double)x2 * x2);
   }
-  const float* rho = d.rhoB + 2 * (size_t)obs0;
+  const real* rho = d.rhoB + 2 * (size_t)obs0;
   for (int r = 0; r < 2 * k; ++r) {
-    float y = 0.f;
+    real y = 0.f;
 #pragma unroll
     for (int j = 0; j < NCG; ++j) {
       const int g = lane + TEAM * j;
@@ -1638,7 +1649,7 @@ __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, fl
     if (lane == 0) pred -= (double)(y * (2.f * rho[r] + y));
   }
   if (lane == 0) {
-    const float* sl = lmd + LMD_SL;
+    const real* sl = lmd + LMD_SL;
     d.dxl[3 * (size_t)lm + 0] = sl[0] * x0;
     d.dxl[3 * (size_t)lm + 1] = sl[1] * x1;
     d.dxl[3 * (size_t)lm + 2] = sl[2] * x2;
@@ -1659,18 +1670,18 @@ __device__ __forceinline__ void backsub_large(const Dev& d, int slot, double* pr
   const int obs0 = d.slot_obs0[slot];
   const int G = width_of(k) >> 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const float4* __restrict__ B = reinterpret_cast<const float4*>(d.poolB + d.slot_boff[slot]);
-  float4 pv[NCG];
+  const real4* __restrict__ B = reinterpret_cast<const real4*>(d.poolB + d.slot_boff[slot]);
+  real4 pv[NCG];
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
     const int g = lane + 64 * j;
-    pv[j] = g < G ? gather_cols(d, d.vx, obs0, k, g) : make_float4(0.f, 0.f, 0.f, 0.f);
+    pv[j] = g < G ? gather_cols(d, d.vx, obs0, k, g) : make_real4(0.f, 0.f, 0.f, 0.f);
   }
-  const float* rho = d.rhoB + 2 * (size_t)obs0;
+  const real* rho = d.rhoB + 2 * (size_t)obs0;
   double pred = 0.0;
   for (int r = w; r < 2 * k; r += 4) {
-    const float4* row = B + (size_t)r * G + lane;
-    float y = 0.f;
+    const real4* row = B + (size_t)r * G + lane;
+    real y = 0.f;
 #pragma unroll
     for (int j = 0; j < NCG; ++j)
       if (lane + 64 * j < G) y += dot4(row[64 * j], pv[j]);
@@ -1679,19 +1690,19 @@ __device__ __forceinline__ void backsub_large(const Dev& d, int slot, double* pr
   }
   if (lane == 0) predw[w] = pred;
   if (w == 0) {
-    const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
-    const float lam = (float)d.lambda[prob];
+    const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+    const real lam = (real)d.lambda[prob];
     Givens6 Gv;
-    float Rh[3][3], qrh[3], dr[3];
-    damping_rotations(lmd, sqrtf(lam), Gv, Rh, qrh, dr);
-    const float4* T = reinterpret_cast<const float4*>(d.poolT + d.slot_toff[slot]);
-    float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+    real Rh[3][3], qrh[3], dr[3];
+    damping_rotations(lmd, sqrt(lam), Gv, Rh, qrh, dr);
+    const real4* T = reinterpret_cast<const real4*>(d.poolT + d.slot_toff[slot]);
+    real u0 = 0.f, u1 = 0.f, u2 = 0.f;
 #pragma unroll
     for (int j = 0; j < NCG; ++j) {
       const int g = lane + 64 * j;
       if (g < G) {
-        const float4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
-        float a[3], b[3];
+        const real4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
+        real a[3], b[3];
         a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b);
         u0 += a[0] * pv[j].x; u1 += a[1] * pv[j].x; u2 += a[2] * pv[j].x;
         a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b);
@@ -1705,18 +1716,18 @@ __device__ __forceinline__ void backsub_large(const Dev& d, int slot, double* pr
     u0 = wave_sum_f(u0);
     u1 = wave_sum_f(u1);
     u2 = wave_sum_f(u2);
-    const float c0 = -(qrh[0] + u0), c1 = -(qrh[1] + u1), c2 = -(qrh[2] + u2);
-    const float x2 = c2 / Rh[2][2];
-    const float x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
-    const float x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
+    const real c0 = -(qrh[0] + u0), c1 = -(qrh[1] + u1), c2 = -(qrh[2] + u2);
+    const real x2 = c2 / Rh[2][2];
+    const real x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
+    const real x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
     if (lane == 0) {
-      const float ut0 = u0 + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
-      const float ut1 = u1 + Rh[1][1] * x1 + Rh[1][2] * x2;
-      const float ut2 = u2 + Rh[2][2] * x2;
+      const real ut0 = u0 + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
+      const real ut1 = u1 + Rh[1][1] * x1 + Rh[1][2] * x2;
+      const real ut2 = u2 + Rh[2][2] * x2;
       const double top = -(double)(ut0 * (2.f * qrh[0] + ut0)) - (double)(ut1 * (2.f * qrh[1] + ut1)) -
                          (double)(ut2 * (2.f * qrh[2] + ut2)) +
                          (double)lam * ((double)x0 * x0 + (double)x1 * x1 + (double)x2 * x2);
-      const float* sl = lmd + LMD_SL;
+      const real* sl = lmd + LMD_SL;
       d.dxl[3 * (size_t)lm + 0] = sl[0] * x0;
       d.dxl[3 * (size_t)lm + 1] = sl[1] * x1;
       d.dxl[3 * (size_t)lm + 2] = sl[2] * x2;
@@ -1736,8 +1747,8 @@ template <bool IMPLICIT>
 struct MargF {
   const Dev& d;
   const uint8_t* mask;
-  float* lds;
-  float* red;
+  real* lds;
+  real* red;
   template <int TEAM, int CLS>
   __device__ __forceinline__ void run(int slot, int lane, int team) const {
     marginalize_one<TEAM, class_kmax(CLS), IMPLICIT>(d, slot, lane, lds + team * marg_stride(class_kmax(CLS)), red,
@@ -1754,15 +1765,15 @@ constexpr int MARG_LDS_SMALL =
 
 template <bool IMPLICIT>
 __global__ __launch_bounds__(WG) void k_marginalize(Dev d, ClassGrid m, const uint8_t* mask) {
-  __shared__ __align__(16) float lds[MARG_LDS_SMALL];
-  __shared__ float red[MARG_RED];
+  __shared__ __align__(alignof(real4)) real lds[MARG_LDS_SMALL];
+  __shared__ real red[MARG_RED];
   class_dispatch(m, MargF<IMPLICIT>{d, mask, lds, red});
 }
 
 template <bool IMPLICIT>
 __global__ __launch_bounds__(WG) void k_marginalize_huge(Dev d, int slot0, const uint8_t* mask) {
-  __shared__ __align__(16) float lds[marg_stride(class_kmax(5))];
-  __shared__ float red[MARG_RED];
+  __shared__ __align__(alignof(real4)) real lds[marg_stride(class_kmax(5))];
+  __shared__ real red[MARG_RED];
   marginalize_one<256, class_kmax(5), IMPLICIT>(d, slot0 + blockIdx.x, threadIdx.x, lds, red, mask);
 }
 
@@ -1770,8 +1781,8 @@ __global__ __launch_bounds__(WG) void k_marginalize_huge(Dev d, int slot0, const
 // a block of up to 1024 x 4608 floats is written by several workgroups, each
 // repeating the landmark's QR (O(k)) and writing its rows.
 __global__ __launch_bounds__(WG) void k_marginalize_chunks(Dev d, const uint8_t* mask) {
-  __shared__ __align__(16) float lds[marg_stride(class_kmax(5))];
-  __shared__ float red[MARG_RED];
+  __shared__ __align__(alignof(real4)) real lds[marg_stride(class_kmax(5))];
+  __shared__ real red[MARG_RED];
   const int2 j = d.qjob[blockIdx.x];
   marginalize_one<256, class_kmax(5), false>(d, j.x, threadIdx.x, lds, red, mask, j.y & 0xffff, j.y >> 16);
 }
@@ -1805,7 +1816,7 @@ __global__ __launch_bounds__(WG) void k_precond_obs_huge(Dev d, int slot0) {
 
 struct BacksubF {
   const Dev& d;
-  float* red4;
+  real* red4;
   double* predw;
   template <int TEAM, int CLS>
   __device__ __forceinline__ void run(int slot, int lane, int) const {
@@ -1817,7 +1828,7 @@ struct BacksubF {
 };
 
 __global__ __launch_bounds__(WG) void k_backsub(Dev d, ClassGrid m) {
-  __shared__ float red4[4];
+  __shared__ real red4[4];
   __shared__ double predw[5];
   class_dispatch(m, BacksubF{d, red4, predw});
 }
@@ -1829,25 +1840,25 @@ __global__ __launch_bounds__(WG) void k_backsub_huge(Dev d, int slot0) {
 
 // ----------------------------------------------------- update and commit
 
-__device__ __forceinline__ void so3_exp_f(float w0, float w1, float w2, float R[9]) {
-  const float th2 = w0 * w0 + w1 * w1 + w2 * w2;
-  const float th = sqrtf(th2);
-  float a, b;
+__device__ __forceinline__ void so3_exp_f(real w0, real w1, real w2, real R[9]) {
+  const real th2 = w0 * w0 + w1 * w1 + w2 * w2;
+  const real th = sqrt(th2);
+  real a, b;
   if (th < 1e-4f) {  // series, accurate to FP32 rounding below 1e-4
     a = 1.0f - th2 / 6.0f;
     b = 0.5f - th2 / 24.0f;
   } else {
-    const float sh = sinf(0.5f * th);
-    a = sinf(th) / th;
+    const real sh = sin(0.5f * th);
+    a = sin(th) / th;
     b = 2.0f * sh * sh / th2;
   }
   // R = I + a W + b W^2
-  const float W[9] = {0.f, -w2, w1, w2, 0.f, -w0, -w1, w0, 0.f};
+  const real W[9] = {0.f, -w2, w1, w2, 0.f, -w0, -w1, w0, 0.f};
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      float w2ij = 0.f;
+      real w2ij = 0.f;
 #pragma unroll
       for (int q = 0; q < 3; ++q) w2ij += W[3 * i + q] * W[3 * q + j];
       R[3 * i + j] = (i == j ? 1.0f : 0.0f) + a * W[3 * i + j] + b * w2ij;
@@ -1860,16 +1871,16 @@ __global__ __launch_bounds__(WG) void k_update(Dev d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < d.NC) {
     const int c = i;
-    const float* src = d.cam + 16 * (size_t)c;
-    float* dst = d.cam_new + 16 * (size_t)c;
+    const real* src = d.cam + 16 * (size_t)c;
+    real* dst = d.cam_new + 16 * (size_t)c;
     if (!d.active[d.cam_prob[c]]) {
 #pragma unroll
       for (int a = 0; a < 16; ++a) dst[a] = src[a];
     } else {
-      float dx[9];
+      real dx[9];
 #pragma unroll
       for (int a = 0; a < 9; ++a) dx[a] = d.s_cam[9 * c + a] * d.vx[9 * c + a];
-      float E[9], R[9];
+      real E[9], R[9];
       so3_exp_f(dx[0], dx[1], dx[2], E);
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -1884,8 +1895,8 @@ __global__ __launch_bounds__(WG) void k_update(Dev d) {
     }
   }
   if (i < d.NL) {
-    const float4 X = d.pts[i];
-    float4 Y = X;
+    const real4 X = d.pts[i];
+    real4 Y = X;
     if (d.active[d.lm_prob[i]] && d.lm_slot[i] >= 0) {
       Y.x += d.dxl[3 * (size_t)i + 0];
       Y.y += d.dxl[3 * (size_t)i + 1];
@@ -1913,16 +1924,16 @@ __global__ __launch_bounds__(WG) void k_commit(Dev d) {
 
 // ----------------------------------------------------- test helpers
 
-__global__ __launch_bounds__(WG) void k_debug_lin(Dev d, float* r, float* Jp, float* Jl) {
+__global__ __launch_bounds__(WG) void k_debug_lin(Dev d, real* r, real* Jp, real* Jl) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= d.NO) return;
   Cam C;
   load_cam(d.cam, d.obs_cam[o], C);
-  const float4 X = d.pts[d.obs_lm[o]];
-  const float2 uv = d.obs_uv[o];
-  float rr[2], J[2][9], L[2][3];
+  const real4 X = d.pts[d.obs_lm[o]];
+  const real2 uv = d.obs_uv[o];
+  real rr[2], J[2][9], L[2][3];
   project<true>(C, X.x, X.y, X.z, uv.x, uv.y, rr, J, L);
-  float sw;  // the rows the QR consumes (Huber IRLS weight applied)
+  real sw;  // the rows the QR consumes (Huber IRLS weight applied)
   (void)robust_term(rr[0] * rr[0] + rr[1] * rr[1], d.huber, sw);
   rr[0] *= sw;
   rr[1] *= sw;
@@ -1939,10 +1950,10 @@ __global__ __launch_bounds__(WG) void k_debug_lin(Dev d, float* r, float* Jp, fl
 }
 
 // out = S sum_obs z + lambda v_scaled (no PCG state involved)
-__global__ __launch_bounds__(64) void k_cam_gather_product(Dev d, const float* v, float* out) {
+__global__ __launch_bounds__(64) void k_cam_gather_product(Dev d, const real* v, real* out) {
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
-  float acc[9];
+  real acc[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = 0.f;
   if (d.sc) {
@@ -1952,7 +1963,7 @@ __global__ __launch_bounds__(64) void k_cam_gather_product(Dev d, const float* v
     }
   } else {
     for (int i = d.cam_obs_off[c] + lane; i < d.cam_obs_off[c + 1]; i += 64) {
-      const float* src = d.obsbuf + d.cam_zpos[i];
+      const real* src = d.obsbuf + d.cam_zpos[i];
 #pragma unroll
       for (int a = 0; a < 9; ++a) acc[a] += src[a];
     }
@@ -1960,11 +1971,11 @@ __global__ __launch_bounds__(64) void k_cam_gather_product(Dev d, const float* v
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = wave_sum_f(acc[a]);
   if (lane < 9) {
-    float s = acc[0];
+    real s = acc[0];
 #pragma unroll
     for (int a = 1; a < 9; ++a) s = (lane == a) ? acc[a] : s;
     const int idx = 9 * c + lane;
-    out[idx] = d.s_cam[idx] * s + (float)d.lambda[d.cam_prob[c]] * v[idx];
+    out[idx] = d.s_cam[idx] * s + (real)d.lambda[d.cam_prob[c]] * v[idx];
   }
 }
 
@@ -1984,52 +1995,52 @@ __global__ __launch_bounds__(WG) void k_damp_implicit(Dev d, const uint8_t* mask
   if (slot >= d.NS) return;
   const int prob = d.slot_prob[slot];
   if (mask && !mask[prob]) return;
-  float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
-  const float lam = (float)d.lambda[prob];
+  real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const real lam = (real)d.lambda[prob];
   Givens6 Gv;
-  float Rh[3][3], qrh[3], dr[3];
-  damping_rotations(lmd, sqrtf(lam), Gv, Rh, qrh, dr);
+  real Rh[3][3], qrh[3], dr[3];
+  damping_rotations(lmd, sqrt(lam), Gv, Rh, qrh, dr);
   lmd[LMD_RH + 0] = Rh[0][0]; lmd[LMD_RH + 1] = Rh[0][1]; lmd[LMD_RH + 2] = Rh[0][2];
   lmd[LMD_RH + 3] = Rh[1][1]; lmd[LMD_RH + 4] = Rh[1][2]; lmd[LMD_RH + 5] = Rh[2][2];
   lmd[LMD_QRH + 0] = qrh[0]; lmd[LMD_QRH + 1] = qrh[1]; lmd[LMD_QRH + 2] = qrh[2];
   lmd[LMD_LAM] = lam;
-  const float R1[3][3] = {{lmd[LMD_R + 0], lmd[LMD_R + 1], lmd[LMD_R + 2]},
+  const real R1[3][3] = {{lmd[LMD_R + 0], lmd[LMD_R + 1], lmd[LMD_R + 2]},
                           {0.f, lmd[LMD_R + 3], lmd[LMD_R + 4]},
                           {0.f, 0.f, lmd[LMD_R + 5]}};
   // M Rh = R1 for the upper triangular M (a zero pivot, only possible at lambda = 0
   // for a rank-deficient J_l, drops that column)
-  float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  real M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = i; j < 3; ++j) {
-      float v = R1[i][j];
+      real v = R1[i][j];
 #pragma unroll
       for (int m = i; m < j; ++m) v -= M[i][m] * Rh[m][j];
       M[i][j] = Rh[j][j] != 0.f ? v / Rh[j][j] : 0.f;
     }
-  float P[6];
+  real P[6];
   int e = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = a; b < 3; ++b) P[e++] = M[a][0] * M[b][0] + M[a][1] * M[b][1] + M[a][2] * M[b][2];
-  reinterpret_cast<float4*>(lmd + LMD_P)[0] = make_float4(P[0], P[1], P[2], P[3]);
-  reinterpret_cast<float2*>(lmd + LMD_P + 4)[0] = make_float2(P[4], P[5]);
+  reinterpret_cast<real4*>(lmd + LMD_P)[0] = make_real4(P[0], P[1], P[2], P[3]);
+  reinterpret_cast<real2*>(lmd + LMD_P + 4)[0] = make_real2(P[4], P[5]);
 }
 
-__device__ __forceinline__ void load_p(const float* lmd, float P[3][3]) {
-  const float4 a = reinterpret_cast<const float4*>(lmd + LMD_P)[0];
-  const float2 b = reinterpret_cast<const float2*>(lmd + LMD_P + 4)[0];
+__device__ __forceinline__ void load_p(const real* lmd, real P[3][3]) {
+  const real4 a = reinterpret_cast<const real4*>(lmd + LMD_P)[0];
+  const real2 b = reinterpret_cast<const real2*>(lmd + LMD_P + 4)[0];
   P[0][0] = a.x; P[0][1] = P[1][0] = a.y; P[0][2] = P[2][0] = a.z;
   P[1][1] = a.w; P[1][2] = P[2][1] = b.x; P[2][2] = b.y;
 }
 
 // The pose Jacobian rows (2 x 9) and Q1 rows (2 x 3) of record i.
-__device__ __forceinline__ void load_rec(const Dev& d, int i, float (&J)[2][9], float (&Q)[2][3]) {
-  const float4* rec = rec_plane(d, 0) + i;
+__device__ __forceinline__ void load_rec(const Dev& d, int i, real (&J)[2][9], real (&Q)[2][3]) {
+  const real4* rec = rec_plane(d, 0) + i;
   const size_t P = (size_t)d.NO;
-  const float4 a = rec[0], b = rec[P], c = rec[2 * P], e = rec[3 * P], f = rec[4 * P], g = rec[5 * P];
+  const real4 a = rec[0], b = rec[P], c = rec[2 * P], e = rec[3 * P], f = rec[4 * P], g = rec[5 * P];
   J[0][0] = a.x; J[0][1] = a.y; J[0][2] = a.z; J[0][3] = a.w; J[0][4] = b.x; J[0][5] = b.y; J[0][6] = b.z;
   J[0][7] = b.w; J[0][8] = c.x;
   J[1][0] = c.y; J[1][1] = c.z; J[1][2] = c.w; J[1][3] = e.x; J[1][4] = e.y; J[1][5] = e.z; J[1][6] = e.w;
@@ -2048,34 +2059,34 @@ __global__ __launch_bounds__(WG) void k_precond_obs_implicit(Dev d) {
   const int slot = d.lm_slot[d.obs_lm[q]];
   const int prob = d.slot_prob[slot];
   if (!d.active[prob]) return;
-  const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
   const int ri = d.slot_zoff[slot] + (q - d.slot_obs0[slot]);
-  float P[3][3], J[2][9], Q[2][3];
+  real P[3][3], J[2][9], Q[2][3];
   load_p(lmd, P);
   load_rec(d, ri, J, Q);
-  const float4 rv = rec_plane(d, 6)[ri];
-  const float qr[3] = {lmd[LMD_QR + 0], lmd[LMD_QR + 1], lmd[LMD_QR + 2]};
-  float PQ[2][3], Pqr[3];
+  const real4 rv = rec_plane(d, 6)[ri];
+  const real qr[3] = {lmd[LMD_QR + 0], lmd[LMD_QR + 1], lmd[LMD_QR + 2]};
+  real PQ[2][3], Pqr[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     PQ[0][a] = P[a][0] * Q[0][0] + P[a][1] * Q[0][1] + P[a][2] * Q[0][2];
     PQ[1][a] = P[a][0] * Q[1][0] + P[a][1] * Q[1][1] + P[a][2] * Q[1][2];
     Pqr[a] = P[a][0] * qr[0] + P[a][1] * qr[1] + P[a][2] * qr[2];
   }
-  float Pi[2][2];
+  real Pi[2][2];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int h2 = 0; h2 < 2; ++h2)
       Pi[h][h2] = (h == h2 ? 1.f : 0.f) - (Q[h][0] * PQ[h2][0] + Q[h][1] * PQ[h2][1] + Q[h][2] * PQ[h2][2]);
-  const float rp[2] = {rv.x - (Q[0][0] * Pqr[0] + Q[0][1] * Pqr[1] + Q[0][2] * Pqr[2]),
+  const real rp[2] = {rv.x - (Q[0][0] * Pqr[0] + Q[0][1] * Pqr[1] + Q[0][2] * Pqr[2]),
                        rv.y - (Q[1][0] * Pqr[0] + Q[1][1] * Pqr[1] + Q[1][2] * Pqr[2])};
-  float K[2][9];  // Pi J
+  real K[2][9];  // Pi J
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int b = 0; b < 9; ++b) K[h][b] = Pi[h][0] * J[0][b] + Pi[h][1] * J[1][b];
-  float* out = d.obsbuf + (size_t)q * 54;
+  real* out = d.obsbuf + (size_t)q * 54;
   int e = 0;
 #pragma unroll
   for (int a = 0; a < 9; ++a)
@@ -2131,8 +2142,8 @@ __device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane
   const int act = d.active[prob];
   const int dn = PCG ? d.done[prob] : 0;
   if (PCG && d.pcg_skip[0] && (!act || dn)) return;
-  float u[OPL][2];
-  float J[OPL][2][9], Q[OPL][2][3];
+  real u[OPL][2];
+  real J[OPL][2][9], Q[OPL][2][3];
   int cm[OPL];
 #pragma unroll
   for (int m = 0; m < (KEEP ? OPL : 1); ++m) {
@@ -2143,7 +2154,7 @@ __device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane
     }
   }
   if (!act || dn) return;  // uniform over the team
-  float c[3] = {0.f, 0.f, 0.f};
+  real c[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
@@ -2153,9 +2164,9 @@ __device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane
         cm[m] = d.rec_cam[r0 + o];
         load_rec(d, r0 + o, J[m], Q[m]);
       }
-      const float4* vs = reinterpret_cast<const float4*>(d.vzs) + 3 * (size_t)cm[m];
-      const float4 v0 = vs[0], v1 = vs[1], v2 = vs[2];
-      const float pa[9] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x};
+      const real4* vs = reinterpret_cast<const real4*>(d.vzs) + 3 * (size_t)cm[m];
+      const real4 v0 = vs[0], v1 = vs[1], v2 = vs[2];
+      const real pa[9] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x};
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
         u[m][0] += J[m][0][a] * pa[a];
@@ -2167,24 +2178,24 @@ __device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane
   }
   int buf = 0;
   team_sum_n<TEAM, 3>(c, nullptr, buf);
-  float P[3][3];
+  real P[3][3];
   load_p(d.lmd + (size_t)slot * LMD_STRIDE, P);
-  const float e[3] = {P[0][0] * c[0] + P[0][1] * c[1] + P[0][2] * c[2], P[1][0] * c[0] + P[1][1] * c[1] + P[1][2] * c[2],
+  const real e[3] = {P[0][0] * c[0] + P[0][1] * c[1] + P[0][2] * c[2], P[1][0] * c[0] + P[1][1] * c[1] + P[1][2] * c[2],
                       P[2][0] * c[0] + P[2][1] * c[1] + P[2][2] * c[2]};
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     if (o < k) {
       if constexpr (!KEEP) load_rec(d, r0 + o, J[m], Q[m]);
-      const float w0 = u[m][0] - (Q[m][0][0] * e[0] + Q[m][0][1] * e[1] + Q[m][0][2] * e[2]);
-      const float w1 = u[m][1] - (Q[m][1][0] * e[0] + Q[m][1][1] * e[1] + Q[m][1][2] * e[2]);
-      float z[9];
+      const real w0 = u[m][0] - (Q[m][0][0] * e[0] + Q[m][0][1] * e[1] + Q[m][0][2] * e[2]);
+      const real w1 = u[m][1] - (Q[m][1][0] * e[0] + Q[m][1][1] * e[1] + Q[m][1][2] * e[2]);
+      real z[9];
 #pragma unroll
       for (int a = 0; a < 9; ++a) z[a] = J[m][0][a] * w0 + J[m][1][a] * w1;
-      float4* out = reinterpret_cast<float4*>(d.obsbuf) + 3 * (size_t)(r0 + o);
-      out[0] = make_float4(z[0], z[1], z[2], z[3]);
-      out[1] = make_float4(z[4], z[5], z[6], z[7]);
-      out[2] = make_float4(z[8], 0.f, 0.f, 0.f);
+      real4* out = reinterpret_cast<real4*>(d.obsbuf) + 3 * (size_t)(r0 + o);
+      out[0] = make_real4(z[0], z[1], z[2], z[3]);
+      out[1] = make_real4(z[4], z[5], z[6], z[7]);
+      out[2] = make_real4(z[8], 0.f, 0.f, 0.f);
     }
   }
 }
@@ -2202,7 +2213,7 @@ __global__ __launch_bounds__(WG) void k_matvec_implicit(Dev d, ImplGrid m) {
 }
 
 // vzs = S v (12 floats per camera, the pad stays zero) for a product outside PCG.
-__global__ __launch_bounds__(WG) void k_prescale(Dev d, const float* v) {
+__global__ __launch_bounds__(WG) void k_prescale(Dev d, const real* v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 9 * d.NC) return;
   const int c = i / 9, a = i - 9 * c;
@@ -2221,21 +2232,21 @@ __device__ __forceinline__ void backsub_implicit(const Dev& d, int slot, int lan
   if (!d.active[prob]) return;  // uniform over the team
   const int k = d.slot_k[slot];
   const int r0 = d.slot_zoff[slot];
-  const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
-  const float lam = (float)d.lambda[prob];
-  float u[OPL][2];
-  float c[3] = {0.f, 0.f, 0.f};
+  const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const real lam = (real)d.lambda[prob];
+  real u[OPL][2];
+  real c[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     u[m][0] = u[m][1] = 0.f;
     if (o < k) {
-      float J[2][9], Q[2][3];
+      real J[2][9], Q[2][3];
       load_rec(d, r0 + o, J, Q);
       const int cam = 9 * d.rec_cam[r0 + o];
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
-        const float pa = d.s_cam[cam + a] * d.vx[cam + a];
+        const real pa = d.s_cam[cam + a] * d.vx[cam + a];
         u[m][0] += J[0][a] * pa;
         u[m][1] += J[1][a] * pa;
       }
@@ -2245,16 +2256,16 @@ __device__ __forceinline__ void backsub_implicit(const Dev& d, int slot, int lan
   }
   int buf = 0;
   team_sum_n<TEAM, 3>(c, nullptr, buf);
-  float s2[2] = {0.f, 0.f};  // |u'|^2, u'.r
+  real s2[2] = {0.f, 0.f};  // |u'|^2, u'.r
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     if (o < k) {
-      float J[2][9], Q[2][3];
+      real J[2][9], Q[2][3];
       load_rec(d, r0 + o, J, Q);
-      const float4 rv = rec_plane(d, 6)[r0 + o];
-      const float w0 = u[m][0] - (Q[0][0] * c[0] + Q[0][1] * c[1] + Q[0][2] * c[2]);
-      const float w1 = u[m][1] - (Q[1][0] * c[0] + Q[1][1] * c[1] + Q[1][2] * c[2]);
+      const real4 rv = rec_plane(d, 6)[r0 + o];
+      const real w0 = u[m][0] - (Q[0][0] * c[0] + Q[0][1] * c[1] + Q[0][2] * c[2]);
+      const real w1 = u[m][1] - (Q[1][0] * c[0] + Q[1][1] * c[1] + Q[1][2] * c[2]);
       s2[0] += w0 * w0 + w1 * w1;
       s2[1] += w0 * rv.x + w1 * rv.y;
     }
@@ -2262,23 +2273,23 @@ __device__ __forceinline__ void backsub_implicit(const Dev& d, int slot, int lan
   team_sum_n<TEAM, 2>(s2, nullptr, buf);
   if (lane == 0) {
     Givens6 Gv;
-    float Rh[3][3], qrh[3], dr[3];
-    damping_rotations(lmd, sqrtf(lam), Gv, Rh, qrh, dr);
-    float t[3] = {c[0], c[1], c[2]}, dd[3];
+    real Rh[3][3], qrh[3], dr[3];
+    damping_rotations(lmd, sqrt(lam), Gv, Rh, qrh, dr);
+    real t[3] = {c[0], c[1], c[2]}, dd[3];
     rotate_column(Gv, t, dd);  // t = T^ p', dd = D p'
-    const float c0 = -(qrh[0] + t[0]), c1 = -(qrh[1] + t[1]), c2 = -(qrh[2] + t[2]);
-    const float x2 = c2 / Rh[2][2];
-    const float x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
-    const float x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
-    const float ut0 = t[0] + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
-    const float ut1 = t[1] + Rh[1][1] * x1 + Rh[1][2] * x2;
-    const float ut2 = t[2] + Rh[2][2] * x2;
+    const real c0 = -(qrh[0] + t[0]), c1 = -(qrh[1] + t[1]), c2 = -(qrh[2] + t[2]);
+    const real x2 = c2 / Rh[2][2];
+    const real x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
+    const real x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
+    const real ut0 = t[0] + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
+    const real ut1 = t[1] + Rh[1][1] * x1 + Rh[1][2] * x2;
+    const real ut2 = t[2] + Rh[2][2] * x2;
     double pred = -(double)(ut0 * (2.f * qrh[0] + ut0)) - (double)(ut1 * (2.f * qrh[1] + ut1)) -
                   (double)(ut2 * (2.f * qrh[2] + ut2)) + (double)lam * ((double)x0 * x0 + (double)x1 * x1 + (double)x2 * x2);
     const double ddr = (double)dd[0] * dr[0] + (double)dd[1] * dr[1] + (double)dd[2] * dr[2];
     const double dd2 = (double)dd[0] * dd[0] + (double)dd[1] * dd[1] + (double)dd[2] * dd[2];
     pred -= 2.0 * ((double)s2[1] + ddr) + (double)s2[0] + dd2;
-    const float* sl = lmd + LMD_SL;
+    const real* sl = lmd + LMD_SL;
     d.dxl[3 * (size_t)lm + 0] = sl[0] * x0;
     d.dxl[3 * (size_t)lm + 1] = sl[1] * x1;
     d.dxl[3 * (size_t)lm + 2] = sl[2] * x2;
@@ -2305,7 +2316,7 @@ __global__ __launch_bounds__(WG) void k_backsub_implicit(Dev d, ImplGrid m) { im
 // preconditioner, the PCG vector kernels and the LM loop are shared.
 
 // Float f (0..27) of record i: planes of 4 floats, plane-major.
-__device__ __forceinline__ float rec_float(const Dev& d, int i, int f) {
+__device__ __forceinline__ real rec_float(const Dev& d, int i, int f) {
   return d.obsrec[4 * ((size_t)(f >> 2) * d.NO + i) + (f & 3)];
 }
 
@@ -2316,18 +2327,18 @@ __device__ __forceinline__ void sc_prepare(const Dev& d, int slot, int lane, con
   const int prob = d.slot_prob[slot];
   if (mask && !mask[prob]) return;
   const int k = d.slot_k[slot], obs0 = d.slot_obs0[slot], r0 = d.slot_zoff[slot];
-  const float4 X = d.pts[d.slot_lm[slot]];
-  float h[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // H_ll upper (6), b_l (3), unscaled
+  const real4 X = d.pts[d.slot_lm[slot]];
+  real h[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // H_ll upper (6), b_l (3), unscaled
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     if (o < k) {
       Cam C;
       load_cam(d.cam, d.obs_cam[obs0 + o], C);
-      const float2 uv = d.obs_uv[obs0 + o];
-      float r[2], Jp[2][9], Jl[2][3];
+      const real2 uv = d.obs_uv[obs0 + o];
+      real r[2], Jp[2][9], Jl[2][3];
       project<true>(C, X.x, X.y, X.z, uv.x, uv.y, r, Jp, Jl);
-      float sw;
+      real sw;
       (void)robust_term(r[0] * r[0] + r[1] * r[1], d.huber, sw);
       r[0] *= sw;
       r[1] *= sw;
@@ -2348,25 +2359,25 @@ __device__ __forceinline__ void sc_prepare(const Dev& d, int slot, int lane, con
         for (int b = a; b < 3; ++b) h[e++] += Jl[0][a] * Jl[0][b] + Jl[1][a] * Jl[1][b];
 #pragma unroll
       for (int a = 0; a < 3; ++a) h[6 + a] += Jl[0][a] * r[0] + Jl[1][a] * r[1];
-      float4* rec = rec_plane(d, 0) + r0 + o;
+      real4* rec = rec_plane(d, 0) + r0 + o;
       const size_t P = (size_t)d.NO;
-      rec[0] = make_float4(Jp[0][0], Jp[0][1], Jp[0][2], Jp[0][3]);
-      rec[P] = make_float4(Jp[0][4], Jp[0][5], Jp[0][6], Jp[0][7]);
-      rec[2 * P] = make_float4(Jp[0][8], Jp[1][0], Jp[1][1], Jp[1][2]);
-      rec[3 * P] = make_float4(Jp[1][3], Jp[1][4], Jp[1][5], Jp[1][6]);
-      rec[4 * P] = make_float4(Jp[1][7], Jp[1][8], Jl[0][0], Jl[0][1]);
-      rec[5 * P] = make_float4(Jl[0][2], Jl[1][0], Jl[1][1], Jl[1][2]);
-      rec[6 * P] = make_float4(r[0], r[1], 0.f, 0.f);
+      rec[0] = make_real4(Jp[0][0], Jp[0][1], Jp[0][2], Jp[0][3]);
+      rec[P] = make_real4(Jp[0][4], Jp[0][5], Jp[0][6], Jp[0][7]);
+      rec[2 * P] = make_real4(Jp[0][8], Jp[1][0], Jp[1][1], Jp[1][2]);
+      rec[3 * P] = make_real4(Jp[1][3], Jp[1][4], Jp[1][5], Jp[1][6]);
+      rec[4 * P] = make_real4(Jp[1][7], Jp[1][8], Jl[0][0], Jl[0][1]);
+      rec[5 * P] = make_real4(Jl[0][2], Jl[1][0], Jl[1][1], Jl[1][2]);
+      rec[6 * P] = make_real4(r[0], r[1], 0.f, 0.f);
     }
   }
   int buf = 0;
   team_sum_n<TEAM, 9>(h, nullptr, buf);
   if (lane == 0) {
     // unit-norm landmark columns (an empty column keeps scale 1), then S_l H S_l, S_l b
-    const float s0 = h[0] > 0.f ? 1.0f / sqrtf(h[0]) : 1.0f;
-    const float s1 = h[3] > 0.f ? 1.0f / sqrtf(h[3]) : 1.0f;
-    const float s2 = h[5] > 0.f ? 1.0f / sqrtf(h[5]) : 1.0f;
-    float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+    const real s0 = h[0] > 0.f ? 1.0f / sqrt(h[0]) : 1.0f;
+    const real s1 = h[3] > 0.f ? 1.0f / sqrt(h[3]) : 1.0f;
+    const real s2 = h[5] > 0.f ? 1.0f / sqrt(h[5]) : 1.0f;
+    real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
     lmd[LMD_R + 0] = s0 * h[0] * s0; lmd[LMD_R + 1] = s0 * h[1] * s1; lmd[LMD_R + 2] = s0 * h[2] * s2;
     lmd[LMD_R + 3] = s1 * h[3] * s1; lmd[LMD_R + 4] = s1 * h[4] * s2; lmd[LMD_R + 5] = s2 * h[5] * s2;
     lmd[LMD_QR + 0] = s0 * h[6]; lmd[LMD_QR + 1] = s1 * h[7]; lmd[LMD_QR + 2] = s2 * h[8];
@@ -2394,26 +2405,26 @@ __global__ __launch_bounds__(WG) void k_sc_damp(Dev d, const uint8_t* mask) {
   if (slot >= d.NS) return;
   const int prob = d.slot_prob[slot];
   if (mask && !mask[prob]) return;
-  float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
-  const float lam = (float)d.lambda[prob];
-  const float a00 = lmd[LMD_R + 0] + lam, a01 = lmd[LMD_R + 1], a02 = lmd[LMD_R + 2];
-  const float a11 = lmd[LMD_R + 3] + lam, a12 = lmd[LMD_R + 4], a22 = lmd[LMD_R + 5] + lam;
-  float P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  const float l00 = a00 > 0.f ? sqrtf(a00) : 0.f;
+  real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const real lam = (real)d.lambda[prob];
+  const real a00 = lmd[LMD_R + 0] + lam, a01 = lmd[LMD_R + 1], a02 = lmd[LMD_R + 2];
+  const real a11 = lmd[LMD_R + 3] + lam, a12 = lmd[LMD_R + 4], a22 = lmd[LMD_R + 5] + lam;
+  real P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const real l00 = a00 > 0.f ? sqrt(a00) : 0.f;
   if (l00 > 0.f) {
-    const float l10 = a01 / l00, l20 = a02 / l00;
-    const float d11 = a11 - l10 * l10;
-    const float l11 = d11 > 0.f ? sqrtf(d11) : 0.f;
+    const real l10 = a01 / l00, l20 = a02 / l00;
+    const real d11 = a11 - l10 * l10;
+    const real l11 = d11 > 0.f ? sqrt(d11) : 0.f;
     if (l11 > 0.f) {
-      const float l21 = (a12 - l20 * l10) / l11;
-      const float d22 = a22 - l20 * l20 - l21 * l21;
-      const float l22 = d22 > 0.f ? sqrtf(d22) : 0.f;
+      const real l21 = (a12 - l20 * l10) / l11;
+      const real d22 = a22 - l20 * l20 - l21 * l21;
+      const real l22 = d22 > 0.f ? sqrt(d22) : 0.f;
       if (l22 > 0.f) {
         // L^-1 (lower), then A^-1 = L^-T L^-1
-        const float i00 = 1.0f / l00, i11 = 1.0f / l11, i22 = 1.0f / l22;
-        const float i10 = -l10 * i00 * i11;
-        const float i21 = -l21 * i11 * i22;
-        const float i20 = -(l20 * i00 + l21 * i10) * i22;
+        const real i00 = 1.0f / l00, i11 = 1.0f / l11, i22 = 1.0f / l22;
+        const real i10 = -l10 * i00 * i11;
+        const real i21 = -l21 * i11 * i22;
+        const real i20 = -(l20 * i00 + l21 * i10) * i22;
         P[0] = i00 * i00 + i10 * i10 + i20 * i20;
         P[1] = i10 * i11 + i20 * i21;
         P[2] = i20 * i22;
@@ -2423,14 +2434,14 @@ __global__ __launch_bounds__(WG) void k_sc_damp(Dev d, const uint8_t* mask) {
       }
     }
   }
-  reinterpret_cast<float4*>(lmd + LMD_P)[0] = make_float4(P[0], P[1], P[2], P[3]);
-  reinterpret_cast<float2*>(lmd + LMD_P + 4)[0] = make_float2(P[4], P[5]);
+  reinterpret_cast<real4*>(lmd + LMD_P)[0] = make_real4(P[0], P[1], P[2], P[3]);
+  reinterpret_cast<real2*>(lmd + LMD_P + 4)[0] = make_real2(P[4], P[5]);
   lmd[LMD_LAM] = lam;
 }
 
 // G = J_p^T (J_l S_l) (9 x 3) of record i, and the record's pose Jacobian rows.
-__device__ __forceinline__ void sc_load_g(const Dev& d, int i, const float sl[3], float (&J)[2][9], float (&G)[9][3]) {
-  float Lu[2][3];
+__device__ __forceinline__ void sc_load_g(const Dev& d, int i, const real sl[3], real (&J)[2][9], real (&G)[9][3]) {
+  real Lu[2][3];
   load_rec(d, i, J, Lu);
 #pragma unroll
   for (int a = 0; a < 9; ++a)
@@ -2446,20 +2457,20 @@ __global__ __launch_bounds__(WG) void k_sc_precond_obs(Dev d) {
   if (q >= d.NO) return;
   const int slot = d.lm_slot[d.obs_lm[q]];
   if (!d.active[d.slot_prob[slot]]) return;
-  const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
   const int ri = d.slot_zoff[slot] + (q - d.slot_obs0[slot]);
-  const float sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
-  float Hi[3][3], J[2][9], G[9][3];
+  const real sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
+  real Hi[3][3], J[2][9], G[9][3];
   load_p(lmd, Hi);
   sc_load_g(d, ri, sl, J, G);
-  const float4 rv = rec_plane(d, 6)[ri];
-  const float bl[3] = {lmd[LMD_QR + 0], lmd[LMD_QR + 1], lmd[LMD_QR + 2]};
-  float T[9][3];  // G H~^-1
+  const real4 rv = rec_plane(d, 6)[ri];
+  const real bl[3] = {lmd[LMD_QR + 0], lmd[LMD_QR + 1], lmd[LMD_QR + 2]};
+  real T[9][3];  // G H~^-1
 #pragma unroll
   for (int a = 0; a < 9; ++a)
 #pragma unroll
     for (int n = 0; n < 3; ++n) T[a][n] = G[a][0] * Hi[0][n] + G[a][1] * Hi[1][n] + G[a][2] * Hi[2][n];
-  float* out = d.obsbuf + (size_t)q * 54;
+  real* out = d.obsbuf + (size_t)q * 54;
   int e = 0;
 #pragma unroll
   for (int a = 0; a < 9; ++a)
@@ -2480,28 +2491,28 @@ __global__ __launch_bounds__(WG) void k_sc_assemble_off(Dev d, const uint8_t* ma
   const int e0 = d.sc_coff[blk], e1 = d.sc_coff[blk + 1];
   if (e0 == e1) return;
   if (mask && !mask[d.slot_prob[d.sc_contrib[e0].z]]) return;
-  float acc[9];
+  real acc[9];
 #pragma unroll
   for (int j = 0; j < 9; ++j) acc[j] = 0.f;
   for (int e = e0; e < e1; ++e) {
     const int4 c = d.sc_contrib[e];
-    const float* lmd = d.lmd + (size_t)c.z * LMD_STRIDE;
-    const float sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
-    float Hi[3][3];
+    const real* lmd = d.lmd + (size_t)c.z * LMD_STRIDE;
+    const real sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
+    real Hi[3][3];
     load_p(lmd, Hi);
     // row i of G_a
-    const float ja0 = rec_float(d, c.x, i), ja1 = rec_float(d, c.x, 9 + i);
-    float ga[3], tn[3];
+    const real ja0 = rec_float(d, c.x, i), ja1 = rec_float(d, c.x, 9 + i);
+    real ga[3], tn[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) ga[m] = (ja0 * rec_float(d, c.x, 18 + m) + ja1 * rec_float(d, c.x, 21 + m)) * sl[m];
 #pragma unroll
     for (int n = 0; n < 3; ++n) tn[n] = ga[0] * Hi[0][n] + ga[1] * Hi[1][n] + ga[2] * Hi[2][n];
-    float Jb[2][9], Gb[9][3];
+    real Jb[2][9], Gb[9][3];
     sc_load_g(d, c.y, sl, Jb, Gb);
 #pragma unroll
     for (int j = 0; j < 9; ++j) acc[j] -= tn[0] * Gb[j][0] + tn[1] * Gb[j][1] + tn[2] * Gb[j][2];
   }
-  float* out = d.scb + (size_t)blk * 81 + 9 * i;
+  real* out = d.scb + (size_t)blk * 81 + 9 * i;
 #pragma unroll
   for (int j = 0; j < 9; ++j) out[j] = acc[j];
 }
@@ -2513,26 +2524,26 @@ __global__ __launch_bounds__(WG) void k_sc_assemble_diag(Dev d, const uint8_t* m
   if (t >= 9 * d.NC) return;
   const int c = t / 9, i = t - 9 * c;
   if (mask && !mask[d.cam_prob[c]]) return;
-  float acc[9];
+  real acc[9];
 #pragma unroll
   for (int j = 0; j < 9; ++j) acc[j] = 0.f;
   for (int e = d.cam_obs_off[c]; e < d.cam_obs_off[c + 1]; ++e) {
     const int q = d.cam_obs_idx[e];
     const int slot = d.lm_slot[d.obs_lm[q]];
     const int ri = d.slot_zoff[slot] + (q - d.slot_obs0[slot]);
-    const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
-    const float sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
-    float Hi[3][3], J[2][9], G[9][3];
+    const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+    const real sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
+    real Hi[3][3], J[2][9], G[9][3];
     load_p(lmd, Hi);
     sc_load_g(d, ri, sl, J, G);
-    float tn[3];
+    real tn[3];
 #pragma unroll
     for (int n = 0; n < 3; ++n) tn[n] = G[i][0] * Hi[0][n] + G[i][1] * Hi[1][n] + G[i][2] * Hi[2][n];
 #pragma unroll
     for (int j = 0; j < 9; ++j)
       acc[j] += J[0][i] * J[0][j] + J[1][i] * J[1][j] - (tn[0] * G[j][0] + tn[1] * G[j][1] + tn[2] * G[j][2]);
   }
-  float* out = d.scb + (size_t)(d.sc_noff + c) * 81 + 9 * i;
+  real* out = d.scb + (size_t)(d.sc_noff + c) * 81 + 9 * i;
 #pragma unroll
   for (int j = 0; j < 9; ++j) out[j] = acc[j];
 }
@@ -2545,15 +2556,15 @@ __global__ __launch_bounds__(64) void k_sc_matvec(Dev d) {
   const int c = blockIdx.x, lane = threadIdx.x;
   const int prob = d.cam_prob[c];
   if (!d.active[prob] || (PCG && d.done[prob])) return;
-  float acc[9];
+  real acc[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = 0.f;
   for (int e = d.sc_rowoff[c] + lane; e < d.sc_rowoff[c + 1]; e += 64) {
     const int2 en = d.sc_rowent[e];
-    const float* B = d.scb + (size_t)(en.x & 0x7fffffff) * 81;
-    const float4* vs = reinterpret_cast<const float4*>(d.vzs) + 3 * (size_t)en.y;
-    const float4 v0 = vs[0], v1 = vs[1], v2 = vs[2];
-    const float v[9] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x};
+    const real* B = d.scb + (size_t)(en.x & 0x7fffffff) * 81;
+    const real4* vs = reinterpret_cast<const real4*>(d.vzs) + 3 * (size_t)en.y;
+    const real4 v0 = vs[0], v1 = vs[1], v2 = vs[2];
+    const real v[9] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x};
     if (en.x >= 0) {
 #pragma unroll
       for (int a = 0; a < 9; ++a)
@@ -2569,7 +2580,7 @@ __global__ __launch_bounds__(64) void k_sc_matvec(Dev d) {
 #pragma unroll
   for (int a = 0; a < 9; ++a) acc[a] = wave_sum_f(acc[a]);
   if (lane < 9) {
-    float s = acc[0];
+    real s = acc[0];
 #pragma unroll
     for (int a = 1; a < 9; ++a) s = (lane == a) ? acc[a] : s;
     d.vy[9 * c + lane] = s;
@@ -2584,21 +2595,21 @@ __device__ __forceinline__ void sc_backsub(const Dev& d, int slot, int lane) {
   if (!d.active[prob]) return;
   const int lm = d.slot_lm[slot];
   const int k = d.slot_k[slot], r0 = d.slot_zoff[slot];
-  const float* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
-  const float sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
-  float u[OPL][2];
-  float c[3] = {0.f, 0.f, 0.f};
+  const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const real sl[3] = {lmd[LMD_SL + 0], lmd[LMD_SL + 1], lmd[LMD_SL + 2]};
+  real u[OPL][2];
+  real c[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     u[m][0] = u[m][1] = 0.f;
     if (o < k) {
-      float J[2][9], Lu[2][3];
+      real J[2][9], Lu[2][3];
       load_rec(d, r0 + o, J, Lu);
       const int cam = 9 * d.rec_cam[r0 + o];
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
-        const float pa = d.s_cam[cam + a] * d.vx[cam + a];
+        const real pa = d.s_cam[cam + a] * d.vx[cam + a];
         u[m][0] += J[0][a] * pa;
         u[m][1] += J[1][a] * pa;
       }
@@ -2608,22 +2619,22 @@ __device__ __forceinline__ void sc_backsub(const Dev& d, int slot, int lane) {
   }
   int buf = 0;
   team_sum_n<TEAM, 3>(c, nullptr, buf);
-  float Hi[3][3];
+  real Hi[3][3];
   load_p(lmd, Hi);
-  const float g[3] = {lmd[LMD_QR + 0] + c[0], lmd[LMD_QR + 1] + c[1], lmd[LMD_QR + 2] + c[2]};
-  float dl[3];
+  const real g[3] = {lmd[LMD_QR + 0] + c[0], lmd[LMD_QR + 1] + c[1], lmd[LMD_QR + 2] + c[2]};
+  real dl[3];
 #pragma unroll
   for (int n = 0; n < 3; ++n) dl[n] = -(Hi[n][0] * g[0] + Hi[n][1] * g[1] + Hi[n][2] * g[2]);
-  float s2[1] = {0.f};
+  real s2[1] = {0.f};
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     if (o < k) {
-      float J[2][9], Lu[2][3];
+      real J[2][9], Lu[2][3];
       load_rec(d, r0 + o, J, Lu);
-      const float4 rv = rec_plane(d, 6)[r0 + o];
-      const float w0 = u[m][0] + Lu[0][0] * sl[0] * dl[0] + Lu[0][1] * sl[1] * dl[1] + Lu[0][2] * sl[2] * dl[2];
-      const float w1 = u[m][1] + Lu[1][0] * sl[0] * dl[0] + Lu[1][1] * sl[1] * dl[1] + Lu[1][2] * sl[2] * dl[2];
+      const real4 rv = rec_plane(d, 6)[r0 + o];
+      const real w0 = u[m][0] + Lu[0][0] * sl[0] * dl[0] + Lu[0][1] * sl[1] * dl[1] + Lu[0][2] * sl[2] * dl[2];
+      const real w1 = u[m][1] + Lu[1][0] * sl[0] * dl[0] + Lu[1][1] * sl[1] * dl[1] + Lu[1][2] * sl[2] * dl[2];
       s2[0] += w0 * (2.f * rv.x + w0) + w1 * (2.f * rv.y + w1);
     }
   }
@@ -2689,8 +2700,8 @@ static ImplGrid impl_grid(const Launch& L, int* n) {
 
 hipError_t launch_cam_linearize(const Dev& d, const Launch& L, bool jac, bool use_new, const uint8_t* mask) {
   if (d.NC == 0) return hipSuccess;
-  const float* cam = use_new ? d.cam_new : d.cam;
-  const float4* pts = use_new ? d.pts_new : d.pts;
+  const real* cam = use_new ? d.cam_new : d.cam;
+  const real4* pts = use_new ? d.pts_new : d.pts;
   if (jac)
     hipLaunchKernelGGL(k_cam_linearize<true>, dim3(d.NC), dim3(64), 0, L.stream, d, cam, pts, mask);
   else
@@ -2807,7 +2818,7 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
 // main launch, or on its own when large_sep), classes 0..3, then the sum of
 // the class-5 partials.  The launch shapes are the tunables of Launch.
 template <bool PCG, bool LARGE, int RBS>
-static void launch_small3(const Dev& d, const Launch& L, const ClassGrid& m, int n, const float* v) {
+static void launch_small3(const Dev& d, const Launch& L, const ClassGrid& m, int n, const real* v) {
   if (L.persist > 0 && n > L.persist)
     hipLaunchKernelGGL((k_matvec<PCG, LARGE, RBS, true>), dim3(L.persist), dim3(WG), 0, L.stream, d, m, n, v);
   else
@@ -2815,7 +2826,7 @@ static void launch_small3(const Dev& d, const Launch& L, const ClassGrid& m, int
 }
 
 template <bool PCG, bool LARGE>
-static void launch_small(const Dev& d, const Launch& L, const ClassGrid& m, int n, const float* v) {
+static void launch_small(const Dev& d, const Launch& L, const ClassGrid& m, int n, const real* v) {
   if (L.mv_rbs == 0)
     launch_small3<PCG, LARGE, 0>(d, L, m, n, v);
   else
@@ -2829,7 +2840,7 @@ static void launch_small(const Dev& d, const Launch& L, const ClassGrid& m, int 
 // main launch, or on its own when large_sep), then classes 0..3, then the sum
 // of the row-block partials.
 template <bool PCG>
-static hipError_t launch_matvec(const Dev& d, const Launch& L, const float* v) {
+static hipError_t launch_matvec(const Dev& d, const Launch& L, const real* v) {
   if (d.sc) {  // product with the assembled reduced matrix into vy (S z as for implicit blocks)
     if (!PCG && v && d.NC) {
       hipLaunchKernelGGL(k_prescale, dim3(nblocks(9 * d.NC, WG)), dim3(WG), 0, L.stream, d, v);
@@ -2974,7 +2985,7 @@ hipError_t launch_prescale_z(const Dev& d, const Launch& L) {
   return hipSuccess;
 }
 
-hipError_t launch_matvec_only(const Dev& d, const Launch& L, const float* v_scaled, float* out) {
+hipError_t launch_matvec_only(const Dev& d, const Launch& L, const real* v_scaled, real* out) {
   hipError_t e = launch_matvec<false>(d, L, v_scaled);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cam_gather_product, dim3(d.NC), dim3(64), 0, L.stream, d, v_scaled, out);
@@ -2982,7 +2993,7 @@ hipError_t launch_matvec_only(const Dev& d, const Launch& L, const float* v_scal
   return hipSuccess;
 }
 
-hipError_t launch_debug_linearization(const Dev& d, const Launch& L, float* r, float* Jp, float* Jl) {
+hipError_t launch_debug_linearization(const Dev& d, const Launch& L, real* r, real* Jp, real* Jl) {
   if (d.NO == 0) return hipSuccess;
   hipLaunchKernelGGL(k_debug_lin, dim3(nblocks(d.NO, WG)), dim3(WG), 0, L.stream, d, r, Jp, Jl);
   LAUNCH_CHECK();

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(TPB) void k_mlp_precond(Dev d, LearnDev m) {
     unpack_L(m.lfac + 45 * (size_t)c, L);
     make_T(eo + NOUT * threadIdx.x, T, th);
     factor_C(L, T, Cm);
-    float* mi = d.minv + 81 * (size_t)c;
+    real* mi = d.minv + 81 * (size_t)c;
 #pragma unroll
     for (int a = 0; a < 9; ++a)
 #pragma unroll

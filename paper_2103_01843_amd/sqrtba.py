@@ -1,9 +1,10 @@
-"""Python binding of libsqrtba.so (ctypes).  Argument marshalling only.
+"""Python binding of libsqrtba.so and libsqrtba64.so (ctypes).  Argument marshalling only.
 
-Every numerical step runs in the library's HIP kernels; this module converts
-numpy arrays to the C ABI of include/sqrtba.h, raises SqrtBAError on a
-non-zero status, and uses PyTorch only for device memory (the workspace) and
-the HIP stream.  It fails loudly when the library has not been built.
+Every numerical step runs in the libraries' HIP kernels; this module converts
+numpy arrays to the C ABIs of include/sqrtba.h (FP32) and include/sqrtba64.h
+(FP64, ``Context(precision=64)``), raises SqrtBAError on a non-zero status, and
+uses PyTorch only for device memory (the workspace) and the HIP stream.  It
+fails loudly when a library has not been built.
 """
 
 from __future__ import annotations
@@ -17,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsqrtba.so")
+LIB64_PATH = os.path.join(_HERE, "libsqrtba64.so")
 
 OK, E_INVALID, E_OOM, E_HIP, E_STATE, E_NONFINITE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_OOM", -3: "E_HIP", -4: "E_STATE", -5: "E_NONFINITE",
@@ -79,6 +81,7 @@ class Profile(C.Structure):
 
 
 _lib = None
+_lib64 = None
 
 P = C.c_void_p
 I32, I64, U64 = C.c_int32, C.c_int64, C.c_uint64
@@ -143,21 +146,53 @@ _SIGS = {
 }
 EXPORTED = tuple(_SIGS)
 
+# The FP64 library exports every call except the learned preconditioner's, under the
+# prefix sqrtba64_, with double in place of float arrays.
+FP32_ONLY = ("sqrtba_mlp_num_params", "sqrtba_mlp_init", "sqrtba_mlp_set_params", "sqrtba_mlp_get_params",
+             "sqrtba_set_preconditioner", "sqrtba_pcg_trace", "sqrtba_trace_size", "sqrtba_mlp_train",
+             "sqrtba_mlp_eval", "sqrtba_learned_stats", "sqrtba_debug_features", "sqrtba_debug_learned_precond")
+_SIGS64 = {"sqrtba64_" + name[len("sqrtba_"):]: (res, [PD if a is PF else a for a in args])
+           for name, (res, args) in _SIGS.items() if name not in FP32_ONLY}
+EXPORTED64 = tuple(_SIGS64)
 
-def lib():
-    """The loaded library; raises ImportError if it has not been built."""
-    global _lib
+
+def _load(path, sigs):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2103_01843_amd.build` "
+                          "(the HIP library is required; there is no fallback)")
+    h = C.CDLL(path)
+    for name, (res, args) in sigs.items():
+        f = getattr(h, name)
+        f.restype = res
+        f.argtypes = args
+    return h
+
+
+def lib(precision: int = 32):
+    """The loaded FP32 (or FP64) library; raises ImportError if it has not been built."""
+    global _lib, _lib64
+    if precision == 64:
+        if _lib64 is None:
+            _lib64 = _load(LIB64_PATH, _SIGS64)
+        return _lib64
+    if precision != 32:
+        raise ValueError("precision is 32 or 64")
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_01843_amd.build` "
-                              "(the HIP library is required; there is no fallback)")
-        h = C.CDLL(LIB_PATH)
-        for name, (res, args) in _SIGS.items():
-            f = getattr(h, name)
-            f.restype = res
-            f.argtypes = args
-        _lib = h
+        _lib = _load(LIB_PATH, _SIGS)
     return _lib
+
+
+class _Api:
+    """The entry points of one library by their unprefixed names (linearize, solve, ...)."""
+
+    def __init__(self, precision: int):
+        self._h = lib(precision)
+        self._prefix = "sqrtba64_" if precision == 64 else "sqrtba_"
+
+    def __getattr__(self, name):
+        if self._prefix == "sqrtba64_" and "sqrtba_" + name in FP32_ONLY:
+            raise SqrtBAError(E_UNSUPPORTED, f"{name}: the learned preconditioner is FP32 only")
+        return getattr(self._h, self._prefix + name)
 
 
 def _ptr(a: Optional[np.ndarray], ctype):
@@ -198,8 +233,11 @@ class Report:
 class Context:
     """One sqrtba context (one or a batch of problems) on the current HIP device."""
 
-    def __init__(self, options: Optional[Options] = None, stream=None, **kw):
-        L = lib()
+    def __init__(self, options: Optional[Options] = None, stream=None, precision: int = 32, **kw):
+        self._api = _Api(precision)
+        self.precision = precision
+        self._rt = np.float64 if precision == 64 else np.float32  # element type of the state arrays
+        self._rc = C.c_double if precision == 64 else C.c_float
         if options is None:
             options = default_options(**kw)
         elif kw:
@@ -209,9 +247,9 @@ class Context:
         if stream is not None:
             handle = int(getattr(stream, "cuda_stream", stream))
         self._h = P()
-        st = L.sqrtba_create(C.byref(self._h), C.byref(options), P(handle) if handle else None)
+        st = self._api.create(C.byref(self._h), C.byref(options), P(handle) if handle else None)
         if st != OK:
-            raise SqrtBAError(st, "sqrtba_create failed")
+            raise SqrtBAError(st, "create failed")
         self.n_problems = 1
         self.n_cams = 0
         self.n_points = 0
@@ -225,13 +263,13 @@ class Context:
             if k not in dict(Options._fields_):
                 raise TypeError(f"unknown option {k}")
             setattr(opt, k, v)
-        self._check(lib().sqrtba_set_options(self._h, C.byref(opt)))
+        self._check(self._api.set_options(self._h, C.byref(opt)))
         self.options = opt
 
     # -- lifetime
     def close(self):
         if getattr(self, "_h", None):
-            lib().sqrtba_destroy(self._h)
+            self._api.destroy(self._h)
             self._h = None
         self._workspace = None
 
@@ -249,31 +287,31 @@ class Context:
 
     def _check(self, st: int):
         if st != OK:
-            msg = lib().sqrtba_last_error(self._h)
+            msg = self._api.last_error(self._h)
             raise SqrtBAError(st, msg.decode() if msg else "")
 
     # -- problem definition
     def set_problems(self, cam_off: Sequence[int], pt_off: Sequence[int]):
         co, po = _arr(cam_off, np.int64), _arr(pt_off, np.int64)
-        self._check(lib().sqrtba_set_problems(self._h, len(co) - 1, _ptr(co, C.c_int64), _ptr(po, C.c_int64)))
+        self._check(self._api.set_problems(self._h, len(co) - 1, _ptr(co, C.c_int64), _ptr(po, C.c_int64)))
         self.n_problems = len(co) - 1
 
     def set_cameras(self, params):
-        a = _arr(params, np.float32)
-        self._check(lib().sqrtba_set_cameras(self._h, a.size // 9 if a.size else 0, _ptr(a, C.c_float)))
+        a = _arr(params, self._rt)
+        self._check(self._api.set_cameras(self._h, a.size // 9 if a.size else 0, _ptr(a, self._rc)))
         self.n_cams = a.size // 9
 
     def set_landmarks(self, xyz):
-        a = _arr(xyz, np.float32)
-        self._check(lib().sqrtba_set_landmarks(self._h, a.size // 3 if a.size else 0, _ptr(a, C.c_float)))
+        a = _arr(xyz, self._rt)
+        self._check(self._api.set_landmarks(self._h, a.size // 3 if a.size else 0, _ptr(a, self._rc)))
         self.n_points = a.size // 3
 
     def set_observations(self, cam, pt, uv):
-        c, p, u = _arr(cam, np.int32), _arr(pt, np.int32), _arr(uv, np.float32)
+        c, p, u = _arr(cam, np.int32), _arr(pt, np.int32), _arr(uv, self._rt)
         if c.shape != p.shape or u.size != 2 * c.size:
             raise ValueError("observation arrays have inconsistent shapes")
-        self._check(lib().sqrtba_set_observations(self._h, c.size, _ptr(c, C.c_int32), _ptr(p, C.c_int32),
-                                                  _ptr(u, C.c_float)))
+        self._check(self._api.set_observations(self._h, c.size, _ptr(c, C.c_int32), _ptr(p, C.c_int32),
+                                                  _ptr(u, self._rc)))
 
     def load(self, cameras, points, obs_cam, obs_pt, obs_uv, cam_off=None, pt_off=None):
         if cam_off is not None:
@@ -285,7 +323,7 @@ class Context:
 
     def workspace_bytes(self) -> int:
         n = C.c_uint64()
-        self._check(lib().sqrtba_workspace_bytes(self._h, C.byref(n)))
+        self._check(self._api.workspace_bytes(self._h, C.byref(n)))
         return int(n.value)
 
     def bind_torch_workspace(self, device="cuda"):
@@ -295,153 +333,153 @@ class Context:
         ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         addr = ws.data_ptr()
         off = (-addr) % 256
-        self._check(lib().sqrtba_bind_workspace(self._h, P(addr + off), nbytes))
+        self._check(self._api.bind_workspace(self._h, P(addr + off), nbytes))
         self._workspace = ws
         return ws
 
     def set_active(self, mask):
         m = _arr(mask, np.uint8)
-        self._check(lib().sqrtba_set_active(self._h, _ptr(m, C.c_uint8)))
+        self._check(self._api.set_active(self._h, _ptr(m, C.c_uint8)))
 
     # -- the LM step
     def linearize(self) -> np.ndarray:
         out = np.zeros(self.n_problems)
-        self._check(lib().sqrtba_linearize(self._h, _ptr(out, C.c_double)))
+        self._check(self._api.linearize(self._h, _ptr(out, C.c_double)))
         return out
 
     def marginalize(self):
-        self._check(lib().sqrtba_marginalize(self._h))
+        self._check(self._api.marginalize(self._h))
 
     def damp(self, lam):
         l = _arr(np.broadcast_to(np.asarray(lam, dtype=np.float64), (self.n_problems,)), np.float64)
-        self._check(lib().sqrtba_damp(self._h, _ptr(l, C.c_double)))
+        self._check(self._api.damp(self._h, _ptr(l, C.c_double)))
 
     def solve(self):
         it = np.zeros(self.n_problems, np.int32)
         rel = np.zeros(self.n_problems)
         st = np.zeros(self.n_problems, np.int32)
-        self._check(lib().sqrtba_solve(self._h, _ptr(it, C.c_int32), _ptr(rel, C.c_double), _ptr(st, C.c_int32)))
+        self._check(self._api.solve(self._h, _ptr(it, C.c_int32), _ptr(rel, C.c_double), _ptr(st, C.c_int32)))
         return it, rel, st
 
     def back_substitute(self) -> np.ndarray:
         out = np.zeros(self.n_problems)
-        self._check(lib().sqrtba_back_substitute(self._h, _ptr(out, C.c_double)))
+        self._check(self._api.back_substitute(self._h, _ptr(out, C.c_double)))
         return out
 
     def update(self) -> np.ndarray:
         out = np.zeros(self.n_problems)
-        self._check(lib().sqrtba_update(self._h, _ptr(out, C.c_double)))
+        self._check(self._api.update(self._h, _ptr(out, C.c_double)))
         return out
 
     def commit(self, accept):
         a = _arr(np.broadcast_to(np.asarray(accept, dtype=np.uint8), (self.n_problems,)), np.uint8)
-        self._check(lib().sqrtba_commit(self._h, _ptr(a, C.c_uint8)))
+        self._check(self._api.commit(self._h, _ptr(a, C.c_uint8)))
 
     def lm_solve(self, tol_cost=None) -> List[Report]:
         reps = (LMReport * self.n_problems)()
         if tol_cost is None:
-            self._check(lib().sqrtba_lm_solve(self._h, reps))
+            self._check(self._api.lm_solve(self._h, reps))
         else:
             t = _arr(np.broadcast_to(np.asarray(tol_cost, dtype=np.float64), (self.n_problems,)), np.float64)
-            self._check(lib().sqrtba_lm_solve_tracked(self._h, _ptr(t, C.c_double), reps))
+            self._check(self._api.lm_solve_tracked(self._h, _ptr(t, C.c_double), reps))
         return [Report(r.initial_cost, r.final_cost, r.iterations, r.accepted, r.total_pcg_iters,
                        LM_STATUS.get(r.status, str(r.status)), r.solve_seconds, r.time_to_tol) for r in reps]
 
     def history(self, problem: int = 0) -> List[dict]:
         n = C.c_int32()
-        self._check(lib().sqrtba_get_lm_history(self._h, problem, None, 0, C.byref(n)))
+        self._check(self._api.get_lm_history(self._h, problem, None, 0, C.byref(n)))
         recs = (LMRecord * max(1, n.value))()
-        self._check(lib().sqrtba_get_lm_history(self._h, problem, recs, n.value, C.byref(n)))
+        self._check(self._api.get_lm_history(self._h, problem, recs, n.value, C.byref(n)))
         return [{"iter": r.iter, "accepted": bool(r.accepted), "pcg_iters": r.pcg_iters,
                  "pcg_status": PCG_STATUS.get(r.pcg_status, r.pcg_status), "lambda": r.lambda_, "cost": r.cost,
                  "new_cost": r.new_cost, "pred": r.model_decrease, "rel_res": r.rel_res, "t": r.t_seconds}
                 for r in recs[: n.value]]
 
     def get_cameras(self) -> np.ndarray:
-        out = np.zeros((self.n_cams, 9), np.float32)
-        self._check(lib().sqrtba_get_cameras(self._h, _ptr(out, C.c_float)))
+        out = np.zeros((self.n_cams, 9), self._rt)
+        self._check(self._api.get_cameras(self._h, _ptr(out, self._rc)))
         return out
 
     def get_landmarks(self) -> np.ndarray:
-        out = np.zeros((self.n_points, 3), np.float32)
-        self._check(lib().sqrtba_get_landmarks(self._h, _ptr(out, C.c_float)))
+        out = np.zeros((self.n_points, 3), self._rt)
+        self._check(self._api.get_landmarks(self._h, _ptr(out, self._rc)))
         return out
 
     # -- learned preconditioner
     def mlp_init(self, seed: int = 0):
-        self._check(lib().sqrtba_mlp_init(self._h, seed))
+        self._check(self._api.mlp_init(self._h, seed))
 
     def mlp_set_params(self, params):
         a = _arr(params, np.float32)
-        if a.size != lib().sqrtba_mlp_num_params():
+        if a.size != self._api.mlp_num_params():
             raise ValueError("wrong parameter count")
-        self._check(lib().sqrtba_mlp_set_params(self._h, _ptr(a, C.c_float)))
+        self._check(self._api.mlp_set_params(self._h, _ptr(a, C.c_float)))
 
     def mlp_get_params(self) -> np.ndarray:
-        out = np.zeros(lib().sqrtba_mlp_num_params(), np.float32)
-        self._check(lib().sqrtba_mlp_get_params(self._h, _ptr(out, C.c_float)))
+        out = np.zeros(self._api.mlp_num_params(), np.float32)
+        self._check(self._api.mlp_get_params(self._h, _ptr(out, C.c_float)))
         return out
 
     def set_preconditioner(self, mode: str):
-        self._check(lib().sqrtba_set_preconditioner(self._h, {"block_jacobi": 0, "learned": 1}[mode]))
+        self._check(self._api.set_preconditioner(self._h, {"block_jacobi": 0, "learned": 1}[mode]))
 
     def pcg_trace(self, max_solves: int, iters_per_solve: int):
-        self._check(lib().sqrtba_pcg_trace(self._h, max_solves, iters_per_solve))
+        self._check(self._api.pcg_trace(self._h, max_solves, iters_per_solve))
 
     def trace_size(self):
         a, b = C.c_int32(), C.c_int32()
-        self._check(lib().sqrtba_trace_size(self._h, C.byref(a), C.byref(b)))
+        self._check(self._api.trace_size(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
     def mlp_train(self, steps: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0) -> np.ndarray:
         out = np.zeros(max(steps, 1))
-        self._check(lib().sqrtba_mlp_train(self._h, steps, batch, lr, seed, _ptr(out, C.c_double)))
+        self._check(self._api.mlp_train(self._h, steps, batch, lr, seed, _ptr(out, C.c_double)))
         return out[:steps]
 
     def mlp_eval(self, feats, lfac, p, q):
         f, l, pp, qq = (_arr(a, np.float32) for a in (feats, lfac, p, q))
         n = f.shape[0]
         loss = C.c_double()
-        grad = np.zeros(lib().sqrtba_mlp_num_params(), np.float32)
-        self._check(lib().sqrtba_mlp_eval(self._h, n, _ptr(f, C.c_float), _ptr(l, C.c_float), _ptr(pp, C.c_float),
+        grad = np.zeros(self._api.mlp_num_params(), np.float32)
+        self._check(self._api.mlp_eval(self._h, n, _ptr(f, C.c_float), _ptr(l, C.c_float), _ptr(pp, C.c_float),
                                           _ptr(qq, C.c_float), C.byref(loss), _ptr(grad, C.c_float)))
         return loss.value, grad
 
     def learned_stats(self) -> dict:
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
-        self._check(lib().sqrtba_learned_stats(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        self._check(self._api.learned_stats(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return {"learned_solves": a.value, "fallbacks": b.value, "wasted_iters": c.value}
 
     def debug_features(self):
         f = np.zeros((self.n_cams, 64), np.float32)
         l = np.zeros((self.n_cams, 45), np.float32)
-        self._check(lib().sqrtba_debug_features(self._h, _ptr(f, C.c_float), _ptr(l, C.c_float)))
+        self._check(self._api.debug_features(self._h, _ptr(f, C.c_float), _ptr(l, C.c_float)))
         return f, l
 
     def debug_learned_precond(self) -> np.ndarray:
         out = np.zeros((self.n_cams, 9, 9), np.float32)
-        self._check(lib().sqrtba_debug_learned_precond(self._h, _ptr(out, C.c_float)))
+        self._check(self._api.debug_learned_precond(self._h, _ptr(out, C.c_float)))
         return out
 
     # -- measurement and snapshots
     def profile_enable(self, on: bool = True):
-        self._check(lib().sqrtba_profile_enable(self._h, 1 if on else 0))
+        self._check(self._api.profile_enable(self._h, 1 if on else 0))
 
     def profile(self) -> dict:
         pr = Profile()
-        self._check(lib().sqrtba_profile_get(self._h, C.byref(pr)))
+        self._check(self._api.profile_get(self._h, C.byref(pr)))
         return {name: {"ms": pr.ms[i], "launches": int(pr.launches[i]), "bytes": pr.bytes[i],
                        "units": int(pr.units[i])} for i, name in enumerate(STAGES)}
 
     # -- launch shapes of the product
     def get_tuning(self) -> dict:
         t = Tuning()
-        self._check(lib().sqrtba_get_tuning(self._h, C.byref(t)))
+        self._check(self._api.get_tuning(self._h, C.byref(t)))
         return t.as_dict()
 
     def set_tuning(self, **shape):
         t = Tuning(**{**self.get_tuning(), **shape})
-        self._check(lib().sqrtba_set_tuning(self._h, C.byref(t)))
+        self._check(self._api.set_tuning(self._h, C.byref(t)))
 
     def autotune(self, reps: int = 10):
         """Pick the fastest product launch shapes on this problem; returns
@@ -449,83 +487,83 @@ class Context:
         best = Tuning()
         trials = (TuningTrial * 32)()
         n = C.c_int32()
-        self._check(lib().sqrtba_autotune(self._h, reps, C.byref(best), trials, 32, C.byref(n)))
+        self._check(self._api.autotune(self._h, reps, C.byref(best), trials, 32, C.byref(n)))
         return best.as_dict(), [(trials[i].shape.as_dict(), trials[i].ms) for i in range(min(n.value, 32))]
 
     def time_product(self, reps: int = 50):
         """(mean ms per product over reps back-to-back launches, algorithmic bytes per product)."""
         ms, by = C.c_double(), C.c_double()
-        self._check(lib().sqrtba_time_product(self._h, reps, C.byref(ms), C.byref(by)))
+        self._check(self._api.time_product(self._h, reps, C.byref(ms), C.byref(by)))
         return ms.value, by.value
 
     def save_state(self):
-        self._check(lib().sqrtba_save_state(self._h))
+        self._check(self._api.save_state(self._h))
 
     def restore_state(self):
-        self._check(lib().sqrtba_restore_state(self._h))
+        self._check(self._api.restore_state(self._h))
 
     # -- inspection exports
     def debug_bookkeeping(self) -> dict:
         n = C.c_int64()
-        self._check(lib().sqrtba_debug_bookkeeping(self._h, C.byref(n), None, None, None, None))
+        self._check(self._api.debug_bookkeeping(self._h, C.byref(n), None, None, None, None))
         perm = np.zeros(n.value, np.int64)
         lm_off = np.zeros(self.n_points + 1, np.int64)
         la = np.zeros(self.n_points, np.uint8)
         ca = np.zeros(self.n_cams, np.uint8)
-        self._check(lib().sqrtba_debug_bookkeeping(self._h, C.byref(n), _ptr(perm, C.c_int64),
+        self._check(self._api.debug_bookkeeping(self._h, C.byref(n), _ptr(perm, C.c_int64),
                                                    _ptr(lm_off, C.c_int64), _ptr(la, C.c_uint8),
                                                    _ptr(ca, C.c_uint8)))
         return {"obs_perm": perm, "lm_off": lm_off, "lm_active": la.astype(bool), "cam_active": ca.astype(bool)}
 
     def debug_linearization(self):
         n = len(self.debug_bookkeeping()["obs_perm"])
-        r = np.zeros((n, 2), np.float32)
-        Jp = np.zeros((n, 2, 9), np.float32)
-        Jl = np.zeros((n, 2, 3), np.float32)
-        self._check(lib().sqrtba_debug_linearization(self._h, _ptr(r, C.c_float), _ptr(Jp, C.c_float),
-                                                     _ptr(Jl, C.c_float)))
+        r = np.zeros((n, 2), self._rt)
+        Jp = np.zeros((n, 2, 9), self._rt)
+        Jl = np.zeros((n, 2, 3), self._rt)
+        self._check(self._api.debug_linearization(self._h, _ptr(r, self._rc), _ptr(Jp, self._rc),
+                                                     _ptr(Jl, self._rc)))
         return r, Jp, Jl
 
     def debug_scales(self):
-        sc = np.zeros((self.n_cams, 9), np.float32)
-        sp = np.zeros((self.n_points, 3), np.float32)
-        self._check(lib().sqrtba_debug_scales(self._h, _ptr(sc, C.c_float), _ptr(sp, C.c_float)))
+        sc = np.zeros((self.n_cams, 9), self._rt)
+        sp = np.zeros((self.n_points, 3), self._rt)
+        self._check(self._api.debug_scales(self._h, _ptr(sc, self._rc), _ptr(sp, self._rc)))
         return sc, sp
 
     def debug_rcs_matvec(self, V) -> np.ndarray:
-        V = _arr(V, np.float32)
+        V = _arr(V, self._rt)
         V2 = V.reshape(-1, 9 * self.n_cams)
         out = np.zeros_like(V2)
-        self._check(lib().sqrtba_debug_rcs_matvec(self._h, V2.shape[0], _ptr(V2, C.c_float), _ptr(out, C.c_float)))
+        self._check(self._api.debug_rcs_matvec(self._h, V2.shape[0], _ptr(V2, self._rc), _ptr(out, self._rc)))
         return out.reshape(V.shape)
 
     def debug_rhs(self) -> np.ndarray:
-        out = np.zeros(9 * self.n_cams, np.float32)
-        self._check(lib().sqrtba_debug_rhs(self._h, _ptr(out, C.c_float)))
+        out = np.zeros(9 * self.n_cams, self._rt)
+        self._check(self._api.debug_rhs(self._h, _ptr(out, self._rc)))
         return out
 
     def debug_precond(self) -> np.ndarray:
-        out = np.zeros((self.n_cams, 9, 9), np.float32)
-        self._check(lib().sqrtba_debug_precond(self._h, _ptr(out, C.c_float)))
+        out = np.zeros((self.n_cams, 9, 9), self._rt)
+        self._check(self._api.debug_precond(self._h, _ptr(out, self._rc)))
         return out
 
     def debug_block(self, pt: int):
         k = C.c_int32()
-        self._check(lib().sqrtba_debug_block(self._h, pt, C.byref(k), None, None))
+        self._check(self._api.debug_block(self._h, pt, C.byref(k), None, None))
         if k.value == 0:
             return 0, None, None
         kk = k.value
-        out = np.zeros((2 * kk + 3, 9 * kk + 4), np.float32)
-        fac = np.zeros(24, np.float32)
-        self._check(lib().sqrtba_debug_block(self._h, pt, C.byref(k), _ptr(out, C.c_float), _ptr(fac, C.c_float)))
+        out = np.zeros((2 * kk + 3, 9 * kk + 4), self._rt)
+        fac = np.zeros(24, self._rt)
+        self._check(self._api.debug_block(self._h, pt, C.byref(k), _ptr(out, self._rc), _ptr(fac, self._rc)))
         return kk, out, fac
 
     def debug_solution(self):
-        dxp = np.zeros(9 * self.n_cams, np.float32)
-        dxl = np.zeros((self.n_points, 3), np.float32)
-        self._check(lib().sqrtba_debug_solution(self._h, _ptr(dxp, C.c_float), _ptr(dxl, C.c_float)))
+        dxp = np.zeros(9 * self.n_cams, self._rt)
+        dxl = np.zeros((self.n_points, 3), self._rt)
+        self._check(self._api.debug_solution(self._h, _ptr(dxp, self._rc), _ptr(dxl, self._rc)))
         return dxp, dxl
 
     def debug_set_pose_increment(self, dxp):
-        a = _arr(dxp, np.float32)
-        self._check(lib().sqrtba_debug_set_pose_increment(self._h, _ptr(a, C.c_float)))
+        a = _arr(dxp, self._rt)
+        self._check(self._api.debug_set_pose_increment(self._h, _ptr(a, self._rc)))

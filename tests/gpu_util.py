@@ -43,6 +43,21 @@ def mixed_problem(seed: int = 5, n_cams: int = 160, n_points: int = 260) -> Prob
     return make_ring_problem(rng, n_cams, n_points, k_mix_sampler(CLASS_EDGES), name="mixed")
 
 
+KCLASS = [(2, 3), (4, 7), (8, 14), (15, 28), (29, 113), (114, 512)]
+
+
+def sample_landmarks(bk, rng, per_class=4, largest=4):
+    """Active landmarks stratified over the kernels' size classes, plus the largest ones."""
+    k = np.diff(bk.lm_off)
+    act = np.nonzero(bk.lm_active)[0]
+    pick = list(act[np.argsort(-k[act], kind="stable")[:largest]])
+    for lo, hi in KCLASS:
+        cand = act[(k[act] >= lo) & (k[act] <= hi)]
+        if len(cand):
+            pick += list(rng.choice(cand, min(per_class, len(cand)), replace=False))
+    return sorted(set(int(l) for l in pick))
+
+
 def landmark_sc_contribution(lin, l: int, lam: float):
     """Oracle per-landmark Schur-complement term H_pp,l - H_pl,l (H_ll,l + lam I)^-1 H_lp,l
     (scaled coordinates) and its right-hand side, restricted to the landmark's cameras."""

@@ -1,4 +1,5 @@
-"""The C-ABI library loads on the CPU and exports every function include/sqrtba.h declares (no GPU calls)."""
+"""The C-ABI libraries load on the CPU and export every function their headers declare
+(include/sqrtba.h for libsqrtba.so, include/sqrtba64.h for libsqrtba64.so; no GPU calls)."""
 
 import os
 import re
@@ -8,10 +9,10 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    src = open(os.path.join(ROOT, "include", "sqrtba.h")).read()
+def declared_functions(header="sqrtba.h", prefix="sqrtba_"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(sqrtba_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(%s[a-z0-9_]+)\s*\(" % prefix, src)))
 
 
 def test_header_declares_the_steps_of_the_method():
@@ -33,10 +34,31 @@ def test_library_exports_every_declared_symbol():
     assert lib.sqrtba_version() >= 1
 
 
+def test_fp64_library_exports_every_declared_symbol():
+    import paper_2103_01843_amd as pkg
+
+    lib = pkg.lib(64)
+    names = declared_functions("sqrtba64.h", "sqrtba64_")
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(pkg.EXPORTED64) == names
+    # every call of the FP32 ABI except the learned preconditioner's
+    fp32 = {n[len("sqrtba_"):] for n in declared_functions()}
+    fp64 = {n[len("sqrtba64_"):] for n in names}
+    assert fp64 <= fp32 and all(n.startswith(("mlp_", "set_preconditioner", "pcg_trace", "trace_size",
+                                              "learned_stats", "debug_features", "debug_learned"))
+                                for n in fp32 - fp64)
+    assert lib.sqrtba64_version() >= 1
+
+
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     import paper_2103_01843_amd.sqrtba as s
 
     monkeypatch.setattr(s, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(s, "LIB64_PATH", str(tmp_path / "missing64.so"))
     monkeypatch.setattr(s, "_lib", None)
+    monkeypatch.setattr(s, "_lib64", None)
     with pytest.raises(ImportError):
         s.lib()
+    with pytest.raises(ImportError):
+        s.lib(64)

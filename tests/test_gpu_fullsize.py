@@ -28,13 +28,12 @@ import oracle
 from oracle.lm import cost_of
 from bal_synth import make_config
 
-from gpu_util import gpu_context, landmark_sc_contribution, oracle_lin
+from gpu_util import gpu_context, landmark_sc_contribution, oracle_lin, sample_landmarks
 
 pytestmark = pytest.mark.gpu
 
 CONFIGS = [1, 3] + ([2, 4] if os.environ.get("SQRTBA_FULLSIZE_ALL") == "1" else [])
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_lm_config{}.json")
-KCLASS = [(2, 3), (4, 7), (8, 14), (15, 28), (29, 113), (114, 512)]
 
 
 @pytest.fixture(scope="module", params=CONFIGS)
@@ -49,17 +48,6 @@ def full(request):
     ctx.close()
 
 
-def _sample_landmarks(bk, rng, per_class=4, largest=4):
-    k = np.diff(bk.lm_off)
-    act = np.nonzero(bk.lm_active)[0]
-    pick = list(act[np.argsort(-k[act], kind="stable")[:largest]])
-    for lo, hi in KCLASS:
-        cand = act[(k[act] >= lo) & (k[act] <= hi)]
-        if len(cand):
-            pick += list(rng.choice(cand, min(per_class, len(cand)), replace=False))
-    return sorted(set(int(l) for l in pick))
-
-
 def test_sampled_landmark_blocks(full):
     cfg, p, bk, lin, ctx = full
     lam = 1e-4
@@ -68,7 +56,7 @@ def test_sampled_landmark_blocks(full):
     ctx.damp(lam)
     sc, _ = ctx.debug_scales()
     worst = 0.0
-    for l in _sample_landmarks(bk, np.random.default_rng(cfg)):
+    for l in sample_landmarks(bk, np.random.default_rng(cfg)):
         cams, H, b, Jp, Jl, r = landmark_sc_contribution(lin, l, lam)
         k, blk, fac = ctx.debug_block(l)
         assert k == len(cams)
