@@ -319,3 +319,37 @@ def test_full_size_ladybug_like():
     assert abs(h0["new_cost"] - g0["new_cost"]) <= 1e-5 * g0["new_cost"], (h0["new_cost"], g0["new_cost"])
     assert abs(c - rep.final_cost) <= 1e-10 * rep.final_cost
     assert abs(rep.final_cost - gold["final_cost"]) <= 1e-3 * gold["final_cost"], (rep.final_cost, gold["final_cost"])
+
+
+def test_full_size_venice_like():
+    """The venice-like workload (1M landmarks, k up to 400, 11 GB of FP64 blocks): sampled
+    landmark blocks over every size class, the largest included, against the oracle's
+    per-landmark terms (1e-11); the product symmetric and damped positive definite on
+    seeded vectors (1e-12)."""
+    p = make_config(3)
+    bk, st, lin = oracle_lin(p)
+    ctx = gpu_context(p, precision=64)
+    lam = 1e-4
+    ctx.linearize()
+    ctx.marginalize()
+    ctx.damp(lam)
+    sc, _ = ctx.debug_scales()
+    worst = 0.0
+    for l in sample_landmarks(bk, np.random.default_rng(3)):
+        cams, H, b, Jp, Jl, r = landmark_sc_contribution(lin, l, lam)
+        k, blk, fac = ctx.debug_block(l)
+        assert k == len(cams)
+        s = np.concatenate([sc[c] for c in cams])
+        B = blk[3:, :9 * k] * s[None, :]
+        rho = blk[3:, 9 * k + 3]
+        eb = np.linalg.norm(B.T @ rho - b) / (np.linalg.norm(b) + 64 * 2.0 ** -53 * np.linalg.norm(Jp, 2)
+                                              * np.linalg.norm(r))
+        worst = max(worst, np.linalg.norm(B.T @ B - H) / np.linalg.norm(H), eb)
+    assert worst < 1e-11, worst
+    V = np.random.default_rng(7).normal(size=(2, 9 * p.n_cams))
+    Av, Aw = ctx.debug_rcs_matvec(V)
+    v, w = V
+    ctx.close()
+    scale = np.linalg.norm(v) * np.linalg.norm(Aw) + np.linalg.norm(w) * np.linalg.norm(Av)
+    assert abs(v @ Aw - w @ Av) <= 1e-12 * scale
+    assert v @ Av >= lam * (v @ v) and w @ Aw >= lam * (w @ w)
