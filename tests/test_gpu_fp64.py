@@ -31,7 +31,7 @@ import pytest
 
 import oracle
 from oracle.lm import cost_of
-from bal_synth import make_config
+from bal_synth import concat_problems, make_batch, make_config
 
 from gpu_util import gpu_context, landmark_sc_contribution, mixed_problem, oracle_lin, sample_landmarks
 
@@ -257,6 +257,29 @@ def test_deterministic_reruns():
         ctx.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+def test_batch_matches_single_runs_and_oracle():
+    """A batch of uneven problems in one context: each problem bitwise equal to its own
+    single-problem run, and its LM history equal to the oracle's (decisions, PCG counts,
+    costs to 1e-9)."""
+    probs = make_batch(np.random.default_rng(23), 5, cams=(5, 16), points=(40, 150), k_hi=9)
+    batch = concat_problems(probs)
+    ctx = gpu_context(batch, precision=64, max_lm_iters=8)
+    reps = ctx.lm_solve()
+    cams_b, pts_b = ctx.get_cameras(), ctx.get_landmarks()
+    hist_b = [ctx.history(i) for i in range(len(probs))]
+    ctx.close()
+    for i, p in enumerate(probs):
+        c1 = gpu_context(p, precision=64, max_lm_iters=8)
+        r1 = c1.lm_solve()[0]
+        cams1, pts1 = c1.get_cameras(), c1.get_landmarks()
+        c1.close()
+        assert r1.final_cost == reps[i].final_cost
+        np.testing.assert_array_equal(cams1, cams_b[batch.cam_off[i]:batch.cam_off[i + 1]])
+        np.testing.assert_array_equal(pts1, pts_b[batch.pt_off[i]:batch.pt_off[i + 1]])
+        ref = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, oracle.LMOptions(max_iters=8))
+        _same_history(hist_b[i], ref.history, 1e-9)
 
 
 def test_learned_preconditioner_is_fp32_only():
