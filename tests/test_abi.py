@@ -62,3 +62,21 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
         s.lib()
     with pytest.raises(ImportError):
         s.lib(64)
+
+
+def test_binding_precision_selection():
+    """Context(precision=...) takes 32 or 64; the FP64 API refuses the FP32-only
+    learned-preconditioner calls by name, before any GPU call."""
+    import paper_2103_01843_amd.sqrtba as s
+
+    with pytest.raises(ValueError):
+        s.lib(16)
+    api = s._Api(64)
+    for name in ("mlp_init", "set_preconditioner", "pcg_trace", "debug_learned_precond"):
+        with pytest.raises(s.SqrtBAError):
+            getattr(api, name)
+    assert api.linearize is s.lib(64).sqrtba64_linearize
+    assert s._Api(32).mlp_init is s.lib(32).sqrtba_mlp_init
+    # every float array of the FP32 ABI is a double array in the FP64 one
+    for name, (_, args) in s._SIGS64.items():
+        assert s.PF not in args, name
