@@ -73,3 +73,18 @@ def landmark_sc_contribution(lin, l: int, lam: float):
     H = Jp.T @ Jp - Hpl @ np.linalg.solve(Hll, Hpl.T)
     b = Jp.T @ r - Hpl @ np.linalg.solve(Hll, Jl.T @ r)
     return lin.ci[idx], H, b, Jp, Jl, r
+
+
+def with_extras(p: Problem) -> Problem:
+    """Add a camera without observations, a landmark seen once (inactive), and a
+    rank-deficient landmark seen only by two cameras with the same centre."""
+    cams = np.vstack([p.cameras, p.cameras[0:1] * 1.0, p.cameras[0:1]])  # cam n: unused; cam n+1 = copy of cam 0
+    cams[-2, 3:6] += 100.0  # far away, unused
+    n = p.n_cams
+    X1 = np.array([[0.3, -0.2, 0.1]], np.float32)
+    X2 = np.array([[-0.4, 0.5, 0.2]], np.float32)
+    pts = np.vstack([p.points, X1, X2]).astype(np.float32)
+    oc = np.concatenate([p.obs_cam, [3], [0, n + 1]]).astype(np.int32)
+    op = np.concatenate([p.obs_pt, [p.n_points], [p.n_points + 1, p.n_points + 1]]).astype(np.int32)
+    uv = np.vstack([p.obs_uv, [[1.0, 2.0]], [[3.0, -4.0], [3.5, -4.5]]]).astype(np.float32)
+    return Problem("extras", cams.astype(np.float32), pts, oc, op, uv, p.gt_cameras, p.gt_points)

@@ -4,9 +4,9 @@ import numpy as np
 import pytest
 
 import oracle
-from bal_synth import make_config, make_ring_problem, make_batch, concat_problems, Problem
+from bal_synth import make_config, make_batch, concat_problems
 
-from gpu_util import gpu_context, oracle_lin, landmark_sc_contribution
+from gpu_util import gpu_context, oracle_lin, with_extras
 
 pytestmark = pytest.mark.gpu
 
@@ -53,23 +53,8 @@ def test_invalid_input_is_rejected(case, code):
         assert ei.value.status in (-4,)
 
 
-def _with_extras(p: Problem) -> Problem:
-    """Add a camera without observations, a landmark seen once (inactive), and a
-    rank-deficient landmark seen only by two cameras with the same centre."""
-    cams = np.vstack([p.cameras, p.cameras[0:1] * 1.0, p.cameras[0:1]])  # cam n: unused; cam n+1 = copy of cam 0
-    cams[-2, 3:6] += 100.0  # far away, unused
-    n = p.n_cams
-    X1 = np.array([[0.3, -0.2, 0.1]], np.float32)
-    X2 = np.array([[-0.4, 0.5, 0.2]], np.float32)
-    pts = np.vstack([p.points, X1, X2]).astype(np.float32)
-    oc = np.concatenate([p.obs_cam, [3], [0, n + 1]]).astype(np.int32)
-    op = np.concatenate([p.obs_pt, [p.n_points], [p.n_points + 1, p.n_points + 1]]).astype(np.int32)
-    uv = np.vstack([p.obs_uv, [[1.0, 2.0]], [[3.0, -4.0], [3.5, -4.5]]]).astype(np.float32)
-    return Problem("extras", cams.astype(np.float32), pts, oc, op, uv, p.gt_cameras, p.gt_points)
-
-
 def test_inactive_and_degenerate_cases():
-    p = _with_extras(make_config(0))
+    p = with_extras(make_config(0))
     bk, st, lin = oracle_lin(p)
     assert not bk.lm_active[p.n_points - 2] and bk.lm_active[p.n_points - 1]
     assert not bk.cam_active[p.n_cams - 2]
