@@ -2,6 +2,8 @@
  * sqrtba.h -- C ABI of libsqrtba.so: square-root bundle adjustment on one
  * AMD Instinct MI355X (gfx950), FP32, after Demmel, Sommer, Cremers, Usenko,
  * "Square Root Bundle Adjustment for Large-Scale Reconstruction" (CVPR 2021).
+ * The same calls in double precision (the method's FP64 variant) are declared
+ * in sqrtba64.h and exported by libsqrtba64.so.
  *
  * The calls follow the problem statement of the paper (Sec. 4): cameras,
  * landmarks and observations define the energy E = sum |r_ij|^2
