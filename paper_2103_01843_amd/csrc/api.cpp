@@ -406,11 +406,11 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
   // so that no single workgroup writes a whole multi-megabyte block
   nb.qjob.clear();
   for (int64_t sl = nb.wc[5].first_slot; sl < nb.wc[5].first_slot + nb.wc[5].slots; ++sl) {
-    const int64_t n = 2 * nb.slot_k[sl];
+    const int64_t nrows = 2 * nb.slot_k[sl];
     const int64_t rows = std::max<int64_t>(1, QR_CHUNK_BYTES / ((int64_t)sizeof(real) * width_of_h(nb.slot_k[sl])));
-    for (int64_t r = 0; r < n; r += rows) {
+    for (int64_t r = 0; r < nrows; r += rows) {
       nb.qjob.push_back((int32_t)sl);
-      nb.qjob.push_back((int32_t)(r | (std::min(n, r + rows) << 16)));
+      nb.qjob.push_back((int32_t)(r | (std::min(nrows, r + rows) << 16)));
     }
   }
   if (nb.qjob.size() / 2 > (size_t)INT32_MAX) return fail(c, SQRTBA_E_UNSUPPORTED, "too many QR chunks");
@@ -438,21 +438,21 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
       for (int64_t w = wlo; w <= whi; ++w) lm[w] = 0;
     }
     for (int64_t cc = 0; cc < nc; ++cc) {
-      const int64_t cam = c0 + cc;
+      const int64_t ci = c0 + cc;
       int64_t cov = 0;
       for (int64_t w = 0; w < words; ++w) cov += __builtin_popcountll(bits[cc * words + w]);
-      const int64_t nob = nb.cam_obs_off[cam + 1] - nb.cam_obs_off[cam];
+      const int64_t nob = nb.cam_obs_off[ci + 1] - nb.cam_obs_off[ci];
       double sk = 0, mk = 0;
-      for (int64_t i = nb.cam_obs_off[cam]; i < nb.cam_obs_off[cam + 1]; ++i) {
+      for (int64_t i = nb.cam_obs_off[ci]; i < nb.cam_obs_off[ci + 1]; ++i) {
         const int32_t l = nb.olm[nb.cam_obs_idx[i]];
         const double lk = std::log((double)count[l]);
         sk += lk;
         mk = std::max(mk, lk);
       }
-      nb.cam_stats[4 * cam + 0] = (float)std::log1p((double)nob);
-      nb.cam_stats[4 * cam + 1] = (float)std::log1p((double)std::max<int64_t>(cov - 1, 0));
-      nb.cam_stats[4 * cam + 2] = nob ? (float)(sk / nob) : 0.f;
-      nb.cam_stats[4 * cam + 3] = (float)mk;
+      nb.cam_stats[4 * ci + 0] = (float)std::log1p((double)nob);
+      nb.cam_stats[4 * ci + 1] = (float)std::log1p((double)std::max<int64_t>(cov - 1, 0));
+      nb.cam_stats[4 * ci + 2] = nob ? (float)(sk / nob) : 0.f;
+      nb.cam_stats[4 * ci + 3] = (float)mk;
     }
   }
   nb.obs_set = true;
@@ -1042,7 +1042,7 @@ int ensure_learned(sqrtba_ctx* c) {
 
 // Xavier-uniform first two layers, zero biases and zero last layer: the initial
 // network reproduces plain block-Jacobi exactly.
-int init_params(sqrtba_ctx* c, uint64_t seed) {
+[[maybe_unused]] int init_params(sqrtba_ctx* c, uint64_t seed) {
   TRY(ensure_learned(c));
   std::vector<float> w(MLP_PARAMS, 0.f);
   std::mt19937_64 rng(seed);
