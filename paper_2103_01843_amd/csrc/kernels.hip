@@ -1452,11 +1452,14 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
   }
 }
 
-// One thread per (camera, row), UPD_CAMS cameras per workgroup.  Wave 0 forms
+// One thread per (camera, row), UPD_CAMS cameras per workgroup (seven: more
+// workgroups shorten this latency-bound kernel; 28 per workgroup took 7% longer).  Wave 0 forms
 // alpha = rz / p^T q for each problem that owns cameras of the workgroup
 // (alpha = 0 and a breakdown status when p^T q is not positive and finite).
-constexpr int UPD_CAMS = 28;
-constexpr int UPD_THREADS = 9 * UPD_CAMS;  // 252
+constexpr int UPD_CAMS = 7;
+// whole wavefronts: wave 0 forms the problem sums with all 64 lanes
+constexpr int UPD_THREADS = (9 * UPD_CAMS + 63) / 64 * 64;
+static_assert(UPD_THREADS >= 64 && UPD_THREADS <= WG, "k_pcg_update needs a complete wave 0");
 
 __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
   __shared__ real rs[UPD_CAMS][9];
