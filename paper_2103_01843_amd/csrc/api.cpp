@@ -99,6 +99,10 @@ struct sqrtba_ctx {
   // pinned host staging for per-problem scalars
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  // coherent pinned host memory the PCG update kernel writes the done flags to
+  int32_t* done_host = nullptr;
+  int32_t* done_host_dev = nullptr;
+  int64_t done_host_n = 0;
   // pipeline state
   bool linearized = false, marginalized = false, damped = false, solved = false, backsubbed = false,
        updated = false;
@@ -754,6 +758,7 @@ int upload(sqrtba_ctx* c) {
   const HostData& h = c->h;
   Dev& d = c->d;
   layout(h, c->opt.landmark_blocks, c->arena.base, &d);
+  d.done_host = c->done_host_dev;
   d.pcg_tol = (real)c->opt.pcg_rel_tol;
   d.pcg_eta = (real)c->opt.pcg_forcing_eta;
   d.huber = (real)c->opt.huber_delta;
@@ -838,6 +843,16 @@ int upload(sqrtba_ctx* c) {
     HIP_TRY(c, hipHostMalloc(&c->pinned, need, hipHostMallocDefault));
     c->pinned_bytes = need;
   }
+  if (c->done_host_n < h.P) {
+    if (c->done_host) (void)hipHostFree(c->done_host);
+    c->done_host = nullptr;
+    c->done_host_n = 0;
+    HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->done_host), sizeof(int32_t) * std::max<int64_t>(1, h.P),
+                             hipHostMallocCoherent | hipHostMallocMapped));
+    HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->done_host_dev), c->done_host, 0));
+    c->done_host_n = h.P;
+  }
+  c->d.done_host = c->done_host_dev;
   if (c->graph) {
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
@@ -1082,6 +1097,9 @@ int run_pcg(sqrtba_ctx* c, int cap) {
   LAUNCH(c, launch_pcg_init(c->d, c->L));
   std::vector<int32_t> done(P);
   TRY(readback(c, c->d.done, done.data()));
+  // the update kernels of this solve overwrite every flag before the host reads it;
+  // until then a stale value can only be 0 (one more chunk, whose kernels exit at once)
+  std::memset(c->done_host, 0, sizeof(int32_t) * P);
   auto all_done = [&]() {
     for (int p = 0; p < P; ++p)
       if (!done[p]) return false;
@@ -1109,7 +1127,8 @@ int run_pcg(sqrtba_ctx* c, int cap) {
       TRY(run_pcg_chunk(c, n, &mv));
     }
     it += n;
-    TRY(readback(c, c->d.done, done.data()));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::memcpy(done.data(), c->done_host, sizeof(int32_t) * P);
     if (c->prof_on) {
       // matvecs of iterations that did work; later ones in the chunk exit at once
       TRY(readback(c, c->d.iters, its_after.data()));
@@ -1461,6 +1480,7 @@ void SQRTBA_API(destroy)(sqrtba_ctx* c) {
   }
   release_arena(c);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->done_host) (void)hipHostFree(c->done_host);
   if (c->side) {
     (void)hipStreamSynchronize(c->side);
     (void)hipStreamDestroy(c->side);

@@ -131,6 +131,9 @@ struct Dev {
   int32_t* sc_rowoff;    // NC + 1: blocks of each camera's row of the reduced matrix (CSR)
   int2* sc_rowent;       // (block | transposed << 31, other camera)
   real* vy;             // 9 NC: the Schur-complement product of the last launch
+  int32_t* done_host;    // P ints in coherent pinned host memory (device view): the done flags of
+                         // the last convergence test, written by the PCG update kernel, read by the
+                         // host between chunks of iterations without a copy
   int32_t* pcg_skip;     // 1 int: some problem is inactive or done in the running PCG solve (the
                          // products then test a landmark's problem before reading its data)
   real* obsbuf;  // NO * 54 elements: per-observation preconditioner terms; the product outputs

@@ -1471,6 +1471,11 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
   const int c = c0 + lc;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool valid = c < d.NC && lc < UPD_CAMS;
+  // the done flags of the convergence test just made (by k_pcg_q) go to the
+  // host's copy; a breakdown found below is seen by the host one chunk later,
+  // when the kernels of that problem have already stopped
+  if (blockIdx.x == 0 && d.done_host)
+    for (int p = threadIdx.x; p < d.P; p += blockDim.x) d.done_host[p] = d.done[p];
   // loads that do not depend on alpha first
   int prob = 0;
   real xv = 0.f, pv = 0.f, rv = 0.f, qv = 0.f, sv = 0.f, mrow[9];
