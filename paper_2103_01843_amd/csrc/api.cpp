@@ -844,13 +844,26 @@ int upload(sqrtba_ctx* c) {
     c->pinned_bytes = need;
   }
   if (c->done_host_n < h.P) {
+    // without coherent mapped host memory the host copies the flags back instead
     if (c->done_host) (void)hipHostFree(c->done_host);
-    c->done_host = nullptr;
+    c->done_host = c->done_host_dev = nullptr;
     c->done_host_n = 0;
-    HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->done_host), sizeof(int32_t) * std::max<int64_t>(1, h.P),
-                             hipHostMallocCoherent | hipHostMallocMapped));
-    HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->done_host_dev), c->done_host, 0));
-    c->done_host_n = h.P;
+    void* hp = nullptr;
+    const hipError_t ae =
+        hipHostMalloc(&hp, sizeof(int32_t) * std::max<int64_t>(1, h.P), hipHostMallocCoherent | hipHostMallocMapped);
+    if (ae == hipSuccess) {
+      void* dp = nullptr;
+      if (hipHostGetDevicePointer(&dp, hp, 0) == hipSuccess) {
+        c->done_host = static_cast<int32_t*>(hp);
+        c->done_host_dev = static_cast<int32_t*>(dp);
+        c->done_host_n = h.P;
+      } else {
+        (void)hipGetLastError();  // the refusal leaves no error behind
+        (void)hipHostFree(hp);
+      }
+    } else {
+      (void)hipGetLastError();
+    }
   }
   c->d.done_host = c->done_host_dev;
   if (c->graph) {
@@ -1099,7 +1112,7 @@ int run_pcg(sqrtba_ctx* c, int cap) {
   TRY(readback(c, c->d.done, done.data()));
   // the update kernels of this solve overwrite every flag before the host reads it;
   // until then a stale value can only be 0 (one more chunk, whose kernels exit at once)
-  std::memset(c->done_host, 0, sizeof(int32_t) * P);
+  if (c->done_host) std::memset(c->done_host, 0, sizeof(int32_t) * P);
   auto all_done = [&]() {
     for (int p = 0; p < P; ++p)
       if (!done[p]) return false;
@@ -1127,8 +1140,12 @@ int run_pcg(sqrtba_ctx* c, int cap) {
       TRY(run_pcg_chunk(c, n, &mv));
     }
     it += n;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    std::memcpy(done.data(), c->done_host, sizeof(int32_t) * P);
+    if (c->done_host) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      std::memcpy(done.data(), c->done_host, sizeof(int32_t) * P);
+    } else {
+      TRY(readback(c, c->d.done, done.data()));
+    }
     if (c->prof_on) {
       // matvecs of iterations that did work; later ones in the chunk exit at once
       TRY(readback(c, c->d.iters, its_after.data()));
