@@ -1258,8 +1258,10 @@ __device__ __forceinline__ void minv_apply(const real* __restrict__ mi, const re
 }
 
 // x = 0, r = -b, z = M^-1 r (and S z), p = q = 0; per-camera partials r.z (cam_part2), r.r (cam_part3).
+// Thread 0 also clears the solve's "some problem stopped" flag (launched with at least one workgroup).
 __global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) d.pcg_skip[0] = 0;
   if (c >= d.NC) return;
   const int prob = d.cam_prob[c];
   double rz = 0.0, rr = 0.0;
@@ -1286,13 +1288,12 @@ __global__ __launch_bounds__(WG) void k_pcg_init(Dev d) {
   d.cam_part3[c] = rr;
 }
 
-// One workgroup: per-problem start scalars.  rz holds r0.z0, so the first
-// beta is exactly 1 and p = z0 (p and q start at 0).
+// One wavefront per problem: per-problem start scalars.  rz holds r0.z0, so
+// the first beta is exactly 1 and p = z0 (p and q start at 0).
 __global__ __launch_bounds__(WG) void k_pcg_init_scalars(Dev d) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (threadIdx.x == 0) d.pcg_skip[0] = 0;
-  __syncthreads();
-  for (int p = w; p < d.P; p += WG / 64) {
+  const int p = blockIdx.x * (WG / 64) + w;
+  if (p < d.P) {  // uniform over the wavefront
     double rz, rr;
     problem_sum2(d, d.cam_part2, d.cam_part3, p, lane, rz, rr);
     if (lane == 0) {
@@ -2916,9 +2917,9 @@ static hipError_t launch_matvec(const Dev& d, const Launch& L, const real* v) {
 }
 
 hipError_t launch_pcg_init(const Dev& d, const Launch& L) {
-  hipLaunchKernelGGL(k_pcg_init, dim3(nblocks(d.NC, WG)), dim3(WG), 0, L.stream, d);
+  hipLaunchKernelGGL(k_pcg_init, dim3(nblocks(d.NC > 0 ? d.NC : 1, WG)), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_pcg_init_scalars, dim3(1), dim3(WG), 0, L.stream, d);
+  hipLaunchKernelGGL(k_pcg_init_scalars, dim3(nblocks(d.P > 0 ? d.P : 1, WG / 64)), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
   return hipSuccess;
 }
