@@ -260,7 +260,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}): this build has no multi-GPU path; "
-              "the landmark-sharded design is described in DESIGN.md", file=sys.stderr)
+              "landmark-sharded multi-GPU execution is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
