@@ -259,8 +259,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}): this build has no multi-GPU path; "
-              "landmark-sharded multi-GPU execution is not implemented", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}): the library has no multi-GPU "
+              "path (landmark-sharded execution is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
