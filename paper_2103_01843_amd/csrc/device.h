@@ -46,8 +46,9 @@ __host__ __device__ constexpr int class_of_k(int k) {
 
 // Small per-landmark record (elements): R1 upper (6), Q1^T r (3), damped R upper (6),
 // damped Q1^T r (3), landmark column scales (3), lambda used (1), pad (2), and for
-// implicit landmark blocks the projection matrix P = R1 (R1^T R1 + lambda I)^-1 R1^T
-// (6, upper triangle row by row, 4-element aligned), pad (2).
+// implicit landmark blocks the damping part D = N^T N = lambda (R1 R1^T + lambda I)^-1
+// of the landmark's projector (N the damping rows of the rotated unit columns; 6,
+// upper triangle row by row, 4-element aligned), pad (2).
 enum {
   LMD_R = 0, LMD_QR = 6, LMD_RH = 9, LMD_QRH = 15, LMD_SL = 18, LMD_LAM = 21, LMD_P = 24, LMD_STRIDE = 32
 };

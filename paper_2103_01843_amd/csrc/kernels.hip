@@ -1990,15 +1990,22 @@ __global__ __launch_bounds__(64) void k_cam_gather_product(Dev d, const real* v,
 
 // ----------------------------------------------- implicit landmark blocks
 //
-// With implicit blocks the rows of B are never formed.  In scaled pose
-// coordinates B^T B = J_p^T (I - Q1 P Q1^T) J_p and B^T rho = J_p^T (I - Q1 P
-// Q1^T) r, with P = R1 (R1^T R1 + lambda I)^-1 R1^T = M M^T, M = R1 Rh^-1 (Rh the
-// damped R of the Givens damping, Rh^T Rh = R1^T R1 + lambda I): the landmark
-// term of eq. red_H taken from the QR of J_l, never from its normal equations.
-// Each observation carries its record (pose Jacobian rows, its two rows of Q1,
-// residual), so every stage below is O(k) per landmark.
+// With implicit blocks the rows of B are never formed.  The six damping
+// rotations G of Sec. 5.3 map the top rows [I_3; 0] of the landmark's thin
+// factor to [T; N]: T the damped top rows, N the three damping rows, and
+// T^T T + N^T N = I since G is orthogonal.  The B rows of the explicit form are
+// [Q2^T J_p; N Q1^T J_p], so in scaled pose coordinates
+//   B^T B   = J_p^T (I - Q1 Q1^T + Q1 D Q1^T) J_p,
+//   B^T rho = J_p^T (I - Q1 Q1^T + Q1 D Q1^T) r,      D = N^T N,
+// which is the landmark term of eq. red_H / red_b taken from the QR of J_l,
+// never from its normal equations.  D = lambda (R1 R1^T + lambda I)^-1 is small
+// when lambda is small, so it is kept as its own term: forming I - D first
+// would leave the damping part at the level of FP32 rounding of an O(1)
+// number.  Each observation carries its record (pose Jacobian rows, its two
+// rows of Q1, residual), so every stage below is O(k) per landmark.
 
-// Per landmark (one thread): the damped factors (as the explicit damping) and P.
+// Per landmark (one thread): the damped factors (as the explicit damping) and
+// D = N^T N, N the images of the unit columns under the damping rotations.
 __global__ __launch_bounds__(WG) void k_damp_implicit(Dev d, const uint8_t* mask) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= d.NS) return;
@@ -2013,29 +2020,22 @@ __global__ __launch_bounds__(WG) void k_damp_implicit(Dev d, const uint8_t* mask
   lmd[LMD_RH + 3] = Rh[1][1]; lmd[LMD_RH + 4] = Rh[1][2]; lmd[LMD_RH + 5] = Rh[2][2];
   lmd[LMD_QRH + 0] = qrh[0]; lmd[LMD_QRH + 1] = qrh[1]; lmd[LMD_QRH + 2] = qrh[2];
   lmd[LMD_LAM] = lam;
-  const real R1[3][3] = {{lmd[LMD_R + 0], lmd[LMD_R + 1], lmd[LMD_R + 2]},
-                          {0.f, lmd[LMD_R + 3], lmd[LMD_R + 4]},
-                          {0.f, 0.f, lmd[LMD_R + 5]}};
-  // M Rh = R1 for the upper triangular M (a zero pivot, only possible at lambda = 0
-  // for a rank-deficient J_l, drops that column)
-  real M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  // column j of N: the damping rows of the rotated unit column e_j
+  real N[3][3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = i; j < 3; ++j) {
-      real v = R1[i][j];
-#pragma unroll
-      for (int m = i; m < j; ++m) v -= M[i][m] * Rh[m][j];
-      M[i][j] = Rh[j][j] != 0.f ? v / Rh[j][j] : 0.f;
-    }
-  real P[6];
+  for (int j = 0; j < 3; ++j) {
+    real t[3] = {j == 0 ? 1.f : 0.f, j == 1 ? 1.f : 0.f, j == 2 ? 1.f : 0.f}, dd[3];
+    rotate_column(Gv, t, dd);
+    N[0][j] = dd[0]; N[1][j] = dd[1]; N[2][j] = dd[2];
+  }
+  real D[6];
   int e = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = a; b < 3; ++b) P[e++] = M[a][0] * M[b][0] + M[a][1] * M[b][1] + M[a][2] * M[b][2];
-  reinterpret_cast<real4*>(lmd + LMD_P)[0] = make_real4(P[0], P[1], P[2], P[3]);
-  reinterpret_cast<real2*>(lmd + LMD_P + 4)[0] = make_real2(P[4], P[5]);
+    for (int b = a; b < 3; ++b) D[e++] = N[0][a] * N[0][b] + N[1][a] * N[1][b] + N[2][a] * N[2][b];
+  reinterpret_cast<real4*>(lmd + LMD_P)[0] = make_real4(D[0], D[1], D[2], D[3]);
+  reinterpret_cast<real2*>(lmd + LMD_P + 4)[0] = make_real2(D[4], D[5]);
 }
 
 __device__ __forceinline__ void load_p(const real* lmd, real P[3][3]) {
@@ -2059,9 +2059,9 @@ __device__ __forceinline__ void load_rec(const Dev& d, int i, real (&J)[2][9], r
 }
 
 // Per observation (one thread): its block-Jacobi terms G = J_o^T Pi J_o (45 upper
-// entries, Pi = I - Q1o P Q1o^T the observation's 2 x 2 block of the projector)
-// and right-hand side g = J_o^T (r_o - Q1o P Q1^T r), unscaled, to obsbuf[obs][0..53]
-// (the layout of the explicit pass).
+// entries, Pi = (I - Q1o Q1o^T) + Q1o D Q1o^T the observation's 2 x 2 block of the
+// projector) and right-hand side g = J_o^T ((r_o - Q1o Q1^T r) + Q1o D Q1^T r),
+// unscaled, to obsbuf[obs][0..53] (the layout of the explicit pass).
 __global__ __launch_bounds__(WG) void k_precond_obs_implicit(Dev d) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= d.NO) return;
@@ -2070,26 +2070,32 @@ __global__ __launch_bounds__(WG) void k_precond_obs_implicit(Dev d) {
   if (!d.active[prob]) return;
   const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
   const int ri = d.slot_zoff[slot] + (q - d.slot_obs0[slot]);
-  real P[3][3], J[2][9], Q[2][3];
-  load_p(lmd, P);
+  real D[3][3], J[2][9], Q[2][3];
+  load_p(lmd, D);
   load_rec(d, ri, J, Q);
   const real4 rv = rec_plane(d, 6)[ri];
   const real qr[3] = {lmd[LMD_QR + 0], lmd[LMD_QR + 1], lmd[LMD_QR + 2]};
-  real PQ[2][3], Pqr[3];
+  real DQ[2][3], Dqr[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    PQ[0][a] = P[a][0] * Q[0][0] + P[a][1] * Q[0][1] + P[a][2] * Q[0][2];
-    PQ[1][a] = P[a][0] * Q[1][0] + P[a][1] * Q[1][1] + P[a][2] * Q[1][2];
-    Pqr[a] = P[a][0] * qr[0] + P[a][1] * qr[1] + P[a][2] * qr[2];
+    DQ[0][a] = D[a][0] * Q[0][0] + D[a][1] * Q[0][1] + D[a][2] * Q[0][2];
+    DQ[1][a] = D[a][0] * Q[1][0] + D[a][1] * Q[1][1] + D[a][2] * Q[1][2];
+    Dqr[a] = D[a][0] * qr[0] + D[a][1] * qr[1] + D[a][2] * qr[2];
   }
   real Pi[2][2];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int h2 = 0; h2 < 2; ++h2)
-      Pi[h][h2] = (h == h2 ? 1.f : 0.f) - (Q[h][0] * PQ[h2][0] + Q[h][1] * PQ[h2][1] + Q[h][2] * PQ[h2][2]);
-  const real rp[2] = {rv.x - (Q[0][0] * Pqr[0] + Q[0][1] * Pqr[1] + Q[0][2] * Pqr[2]),
-                       rv.y - (Q[1][0] * Pqr[0] + Q[1][1] * Pqr[1] + Q[1][2] * Pqr[2])};
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const real proj = (h == h2 ? 1.f : 0.f) - (Q[h][0] * Q[h2][0] + Q[h][1] * Q[h2][1] + Q[h][2] * Q[h2][2]);
+      Pi[h][h2] = proj + (Q[h][0] * DQ[h2][0] + Q[h][1] * DQ[h2][1] + Q[h][2] * DQ[h2][2]);
+    }
+  real rp[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const real rq = (h == 0 ? rv.x : rv.y) - (Q[h][0] * qr[0] + Q[h][1] * qr[1] + Q[h][2] * qr[2]);
+    rp[h] = rq + (Q[h][0] * Dqr[0] + Q[h][1] * Dqr[1] + Q[h][2] * Dqr[2]);
+  }
   real K[2][9];  // Pi J
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -2135,8 +2141,8 @@ __device__ __forceinline__ void impl_dispatch(const ImplGrid& m, const F& f) {
 }
 
 // Product for one landmark: u_o = J_o p'_o per observation (p' = S z, gathered
-// from vzs), c = Q1^T u (team sum),
-// e = P c, z_o = J_o^T (u_o - Q1o e), written as 12 floats (3 float4, the last 3
+// from vzs), c = Q1^T u (team sum), e = D c,
+// z_o = J_o^T ((u_o - Q1o c) + Q1o e), written as 12 floats (3 float4, the last 3
 // zero) per record.  Teams with at most two observations per lane keep their
 // records in registers; the others read them again (from cache) after the sum.
 template <int TEAM, int OPL, bool PCG>
@@ -2187,17 +2193,19 @@ __device__ __forceinline__ void matvec_implicit(const Dev& d, int slot, int lane
   }
   int buf = 0;
   team_sum_n<TEAM, 3>(c, nullptr, buf);
-  real P[3][3];
-  load_p(d.lmd + (size_t)slot * LMD_STRIDE, P);
-  const real e[3] = {P[0][0] * c[0] + P[0][1] * c[1] + P[0][2] * c[2], P[1][0] * c[0] + P[1][1] * c[1] + P[1][2] * c[2],
-                      P[2][0] * c[0] + P[2][1] * c[1] + P[2][2] * c[2]};
+  real D[3][3];
+  load_p(d.lmd + (size_t)slot * LMD_STRIDE, D);
+  const real e[3] = {D[0][0] * c[0] + D[0][1] * c[1] + D[0][2] * c[2], D[1][0] * c[0] + D[1][1] * c[1] + D[1][2] * c[2],
+                      D[2][0] * c[0] + D[2][1] * c[1] + D[2][2] * c[2]};
 #pragma unroll
   for (int m = 0; m < OPL; ++m) {
     const int o = lane + TEAM * m;
     if (o < k) {
       if constexpr (!KEEP) load_rec(d, r0 + o, J[m], Q[m]);
-      const real w0 = u[m][0] - (Q[m][0][0] * e[0] + Q[m][0][1] * e[1] + Q[m][0][2] * e[2]);
-      const real w1 = u[m][1] - (Q[m][1][0] * e[0] + Q[m][1][1] * e[1] + Q[m][1][2] * e[2]);
+      const real t0 = u[m][0] - (Q[m][0][0] * c[0] + Q[m][0][1] * c[1] + Q[m][0][2] * c[2]);
+      const real t1 = u[m][1] - (Q[m][1][0] * c[0] + Q[m][1][1] * c[1] + Q[m][1][2] * c[2]);
+      const real w0 = t0 + (Q[m][0][0] * e[0] + Q[m][0][1] * e[1] + Q[m][0][2] * e[2]);
+      const real w1 = t1 + (Q[m][1][0] * e[0] + Q[m][1][1] * e[1] + Q[m][1][2] * e[2]);
       real z[9];
 #pragma unroll
       for (int a = 0; a < 9; ++a) z[a] = J[m][0][a] * w0 + J[m][1][a] * w1;

@@ -88,3 +88,31 @@ def with_extras(p: Problem) -> Problem:
     op = np.concatenate([p.obs_pt, [p.n_points], [p.n_points + 1, p.n_points + 1]]).astype(np.int32)
     uv = np.vstack([p.obs_uv, [[1.0, 2.0]], [[3.0, -4.0], [3.5, -4.5]]]).astype(np.float32)
     return Problem("extras", cams.astype(np.float32), pts, oc, op, uv, p.gt_cameras, p.gt_points)
+
+
+EPS32 = 2.0 ** -24
+
+
+def check_precond_blocks(ctx, Bo, slack=None, tol=1e-4):
+    """The block-Jacobi pin on every camera: the GPU's damped 9x9 block (L L^T from
+    the Cholesky factor it exports with its features) against the oracle's diagonal
+    block of H~ to `tol` relative (Frobenius), plus an optional per-block absolute
+    slack derived by the caller; and the applied inverse block against the inverse
+    of the GPU's own block, to the FP32 bound of a 9x9 Cholesky inverse scaled by
+    the block's condition number."""
+    _, lf = ctx.debug_features()
+    Mi = ctx.debug_precond().astype(np.float64)
+    n = Bo.shape[0]
+    L = np.zeros((n, 9, 9))
+    L[(slice(None),) + np.tril_indices(9)] = lf.astype(np.float64)
+    P = L @ L.transpose(0, 2, 1)
+    worst = 0.0
+    for i in range(n):
+        e = np.linalg.norm(P[i] - Bo[i])
+        bound = tol * np.linalg.norm(Bo[i]) + (0.0 if slack is None else slack[i])
+        assert e <= bound, (i, e / np.linalg.norm(Bo[i]), bound / np.linalg.norm(Bo[i]))
+        worst = max(worst, e / np.linalg.norm(Bo[i]))
+        kappa = np.linalg.cond(P[i])
+        ei = np.linalg.norm(Mi[i] @ P[i] - np.eye(9))
+        assert ei <= 200 * EPS32 * kappa, (i, ei, kappa)
+    return worst

@@ -20,7 +20,7 @@ from oracle.lm import cost_of
 from bal_synth import make_config, make_ring_problem, concat_problems
 from paper_2103_01843_amd import SqrtBAError
 
-from gpu_util import gpu_context, mixed_problem, oracle_lin
+from gpu_util import check_precond_blocks, gpu_context, mixed_problem, oracle_lin
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +60,8 @@ def _subtracted_magnitude(lin, lam):
         np.add.at(M, (rows[:, :, None, :, None], rows[:, None, :, None, :]), T)
         bl = np.einsum("lhm,lh->lm", Jlk, r[idx].reshape(len(s0), 2 * k))
         np.add.at(mb, rows, np.abs(np.einsum("laim,lmn,ln->lai", Gk, Hi, bl)))
-    return np.linalg.norm(M), np.linalg.norm(mb)
+    blk = np.array([np.linalg.norm(M[9 * i:9 * i + 9, 9 * i:9 * i + 9]) for i in range(lin.n_cams)])
+    return np.linalg.norm(M), np.linalg.norm(mb), blk
 
 
 @pytest.mark.parametrize("lam", [1e-4, 0.3])
@@ -72,16 +73,15 @@ def test_reduced_system_dense(case, lam):
     rs = oracle.reduced_camera_system(lin, lam)
     N = rs.H.shape[0]
     Hg = ctx.debug_rcs_matvec(np.eye(N, dtype=np.float32)).astype(np.float64)
-    mH, mb = _subtracted_magnitude(lin, lam)
+    mH, mb, mblk = _subtracted_magnitude(lin, lam)
     eH = np.linalg.norm(Hg - rs.H)
     assert eH <= 1e-4 * np.linalg.norm(rs.H) + 32 * EPS32 * mH, (eH / np.linalg.norm(rs.H), mH / np.linalg.norm(rs.H))
     bg = ctx.debug_rhs().astype(np.float64)
     eb = np.linalg.norm(bg - rs.b)
     assert eb <= 1e-4 * np.linalg.norm(rs.b) + 32 * EPS32 * mb, (eb / np.linalg.norm(rs.b), mb / np.linalg.norm(rs.b))
-    Mi = ctx.debug_precond().astype(np.float64)
-    Bo = oracle.block_jacobi_blocks(rs.H)
-    for i in range(0, len(Bo), max(1, len(Bo) // 20)):
-        np.testing.assert_allclose(Mi[i] @ Bo[i], np.eye(9), atol=5e-3)
+    # block-Jacobi: every camera's block against the oracle's, with the same derived
+    # allowance for the FP32 subtraction on that block
+    check_precond_blocks(ctx, oracle.block_jacobi_blocks(rs.H), slack=32 * EPS32 * mblk)
 
 
 def test_pcg_and_back_substitution(case):
@@ -183,7 +183,7 @@ def test_full_size_ladybug_like():
     AV = ctx.debug_rcs_matvec(V).astype(np.float64)
     rs = oracle.reduced_camera_system(lin, lam)
     Ho = rs.H @ V.T.astype(np.float64)
-    mH, _ = _subtracted_magnitude(lin, lam)
+    mH, _, _ = _subtracted_magnitude(lin, lam)
     tol = 1e-4 * np.linalg.norm(rs.H) + 32 * EPS32 * mH
     assert np.linalg.norm(AV.T - Ho) <= tol * np.linalg.norm(V), np.linalg.norm(AV.T - Ho) / np.linalg.norm(Ho)
     v, w = V.astype(np.float64)

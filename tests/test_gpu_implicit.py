@@ -1,16 +1,19 @@
 """Implicit landmark blocks (option landmark_blocks = 1) against the FP64 oracle.
 
-The implicit form never stores the rows of B: with the thin QR factor Q1 and
-P = R1 (R1^T R1 + lambda I)^-1 R1^T it applies B^T B = J_p^T (I - Q1 P Q1^T) J_p,
-the landmark term of eq. red_H.  It is held to the explicit path's bar: the dense
-reduced system and right-hand side to 1e-4 relative (Frobenius), block-Jacobi
-blocks, the PCG solution and the back-substitution and model decrease from the
-oracle's exact pose step to 1e-4, the LM final cost to 1e-3; it agrees with the
-explicit form on the same problem, runs are bitwise deterministic, and at the
+The implicit form never stores the rows of B: with the thin QR factor Q1 and the
+damping part D = N^T N of the landmark's projector (N the damping rows of the
+rotated unit columns, D = lambda (R1 R1^T + lambda I)^-1) it applies
+B^T B = J_p^T (I - Q1 Q1^T + Q1 D Q1^T) J_p, the landmark term of eq. red_H.  It
+is held to the explicit path's bar: the dense reduced system and right-hand side
+to 1e-4 relative (Frobenius) at damping from 1e-6 (where the damping part is
+small and must keep its own relative precision) to 0.3, block-Jacobi blocks, the
+PCG solution and the back-substitution and model decrease from the oracle's
+exact pose step to 1e-4, the LM final cost to 1e-3; it agrees with the explicit
+form on the same problem, runs are bitwise deterministic, and at the
 ladybug-like and venice-like sizes the product is checked against the explicit
 form and on symmetry, the final cost against the oracle's cost at the GPU's
-final state, and (ladybug-like) the first LM attempt against the oracle's and the
-converged cost against the oracle's after 20 attempts.
+final state, and (ladybug-like) the first LM attempt and the final cost after
+the oracle's 20 attempts against the oracle's (two-sided, 1e-3).
 """
 
 import json
@@ -24,7 +27,7 @@ from oracle.lm import cost_of
 from bal_synth import make_config, concat_problems, make_ring_problem
 from paper_2103_01843_amd import SqrtBAError
 
-from gpu_util import gpu_context, mixed_problem, oracle_lin
+from gpu_util import check_precond_blocks, gpu_context, mixed_problem, oracle_lin
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +41,7 @@ def case(request):
     ctx.close()
 
 
-@pytest.mark.parametrize("lam", [1e-4, 0.3])
+@pytest.mark.parametrize("lam", [1e-6, 1e-5, 1e-4, 0.3])
 def test_reduced_camera_system_dense(case, lam):
     p, bk, st, lin, ctx = case
     ctx.linearize()
@@ -52,10 +55,7 @@ def test_reduced_camera_system_dense(case, lam):
     bg = ctx.debug_rhs().astype(np.float64)
     eb = np.linalg.norm(bg - rs.b) / np.linalg.norm(rs.b)
     assert eb <= 1e-4, eb
-    Mi = ctx.debug_precond().astype(np.float64)
-    Bo = oracle.block_jacobi_blocks(rs.H)
-    for i in range(0, len(Bo), max(1, len(Bo) // 20)):
-        np.testing.assert_allclose(Mi[i] @ Bo[i], np.eye(9), atol=5e-3)
+    check_precond_blocks(ctx, oracle.block_jacobi_blocks(rs.H))
 
 
 def test_pcg_and_back_substitution(case):
@@ -147,7 +147,7 @@ def test_block_rows_are_not_stored_and_mode_is_fixed_after_upload():
 def test_full_size_product_and_final_cost(cfg):
     p = make_config(cfg)
     bk, st, lin = oracle_lin(p)
-    imp = gpu_context(p, max_lm_iters=40, landmark_blocks=1)
+    imp = gpu_context(p, max_lm_iters=20, landmark_blocks=1)
     exp = gpu_context(p, max_lm_iters=20)
     lam = 1e-4
     n = 9 * p.n_cams
@@ -175,8 +175,6 @@ def test_full_size_product_and_final_cost(cfg):
         g0 = gold["history"][0]
         assert abs(h0["pred"] - g0["pred"]) <= 1e-5 * abs(g0["pred"]), (h0["pred"], g0["pred"])
         assert abs(h0["new_cost"] - g0["new_cost"]) <= 1e-3 * g0["new_cost"], (h0["new_cost"], g0["new_cost"])
-        # later attempts depend on float32 rounding (steps rejected at small lambda
-        # make the path sensitive to it), so the run is held to the converged level:
-        # within 40 attempts at least as low as the oracle's cost after 20 (1e-3)
-        assert rep.final_cost <= (1 + 1e-3) * gold["final_cost"], (rep.final_cost, gold["final_cost"])
+        # the final cost after the oracle's attempt count
+        assert abs(rep.final_cost - gold["final_cost"]) <= 1e-3 * gold["final_cost"], (rep.final_cost, gold["final_cost"])
     imp.close()
