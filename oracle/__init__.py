@@ -35,6 +35,8 @@ from .normal_equations import (  # noqa: F401
     column_scales,
     scaled_jacobian_sparse,
     reduced_camera_system,
+    reduced_system_operator,
+    ReducedOperator,
     back_substitute,
     model_decrease,
 )

@@ -26,7 +26,7 @@ import numpy as np
 from .bookkeeping import Bookkeeping, build_bookkeeping
 from .camera import CameraState, apply_update, bal_from_state, project_residuals, state_from_bal
 from .normal_equations import (Linearization, back_substitute, linearize, model_decrease,
-                               reduced_camera_system)
+                               reduced_camera_system, reduced_system_operator)
 from .robust import huber_terms
 from .solvers import block_jacobi_blocks, dense_spd_solve, pcg
 
@@ -40,7 +40,10 @@ class LMOptions:
     pcg_max_iters: int = 500
     pcg_eta: float = 0.0  # > 0: also the Nash-Sofer forcing test of oracle.solvers.pcg
     huber_delta: Optional[float] = None  # Huber loss parameter in pixels (None: squared loss)
-    solver: str = "pcg"  # "pcg" (block-Jacobi) or "dense" (Cholesky)
+    # "pcg": block-Jacobi PCG on the assembled Schur complement; "pcg_operator":
+    # the same PCG on the Schur complement applied to vectors (large problems);
+    # "dense": Cholesky of the assembled Schur complement
+    solver: str = "pcg"
     lambda_min: float = 1e-16
     lambda_max: float = 1e32
     accept_ratio: float = 1e-3
@@ -72,14 +75,21 @@ def cost_of(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray,
 def lm_attempt(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray, lin: Linearization,
                lam: float, opts: LMOptions, trace: bool = False) -> dict:
     """One damped step at fixed linearization: reduce, solve, back-substitute, evaluate."""
-    rs = reduced_camera_system(lin, lam)
-    if opts.solver == "dense":
+    if opts.solver == "pcg_operator":
+        rs = reduced_system_operator(lin, lam)
+        pres = pcg(rs.matvec, rs.b, rs.blocks, opts.pcg_tol, opts.pcg_max_iters, trace=trace, eta=opts.pcg_eta)
+        dxp, iters, rel, status = pres.x, pres.iters, pres.rel_res, pres.status
+    elif opts.solver == "dense":
+        rs = reduced_camera_system(lin, lam)
         dxp = dense_spd_solve(rs.H, -rs.b)
         iters, rel, status, pres = 0, 0.0, "direct", None
-    else:
+    elif opts.solver == "pcg":
+        rs = reduced_camera_system(lin, lam)
         pres = pcg(lambda v: rs.H @ v, rs.b, block_jacobi_blocks(rs.H), opts.pcg_tol,
                    opts.pcg_max_iters, trace=trace, eta=opts.pcg_eta)
         dxp, iters, rel, status = pres.x, pres.iters, pres.rel_res, pres.status
+    else:
+        raise ValueError(f"unknown solver {opts.solver!r}")
     dxl = back_substitute(rs, dxp)
     pred = model_decrease(lin, dxp, dxl)
     dp = dxp.reshape(lin.n_cams, 9) * lin.sp
@@ -93,7 +103,9 @@ def lm_attempt(state: CameraState, bk: Bookkeeping, obs_uv: np.ndarray, lin: Lin
 
 def lm_solve(cameras: np.ndarray, points: np.ndarray, obs_cam: np.ndarray, obs_pt: np.ndarray,
              obs_uv: np.ndarray, opts: Optional[LMOptions] = None,
-             bk: Optional[Bookkeeping] = None) -> LMResult:
+             bk: Optional[Bookkeeping] = None, progress=None) -> LMResult:
+    """The LM loop; `progress`, if given, is called with each attempt's history record
+    and ends the loop (status "stopped") when it returns True."""
     opts = opts or LMOptions()
     if bk is None:
         bk = build_bookkeeping(cameras.shape[0], points.shape[0], obs_cam, obs_pt, obs_uv)
@@ -112,6 +124,11 @@ def lm_solve(cameras: np.ndarray, points: np.ndarray, obs_cam: np.ndarray, obs_p
                             "rho": float(rho), "accepted": accepted, "pcg_iters": a["pcg_iters"],
                             "rel_res": a["rel_res"], "t": time.perf_counter() - t0})
         res.iterations = it + 1
+        if progress is not None and progress(res.history[-1]):
+            if accepted:
+                state, E = a["new_state"], E_new
+            res.status = "stopped"
+            break
         if accepted:
             rel_dec = (E - E_new) / E
             state, E = a["new_state"], E_new

@@ -133,8 +133,95 @@ def reduced_camera_system(lin: Linearization, lam: float) -> ReducedSystem:
     return ReducedSystem(H, b, lam, Hll_inv, Hpl, bl)
 
 
-def back_substitute(rs: ReducedSystem, dxp_scaled: np.ndarray) -> np.ndarray:
-    """Scaled landmark increment dx~_l = -H_ll^-1 (b_l + H_lp dx~_p) (eq. backsub_sc)."""
+def _sum_by(index: np.ndarray, values: np.ndarray, n: int) -> np.ndarray:
+    """out[i] = sum of values[o] over all rows o with index[o] == i (values: (m, d))."""
+    return np.stack([np.bincount(index, weights=values[:, j], minlength=n) for j in range(values.shape[1])],
+                    axis=1)
+
+
+def _chunks(n: int, size: int = 1 << 18):
+    """Observation ranges of at most `size` rows (keeps temporaries small)."""
+    return [(s, min(s + size, n)) for s in range(0, n, size)]
+
+
+@dataclass
+class ReducedOperator:
+    """The damped reduced camera system of `reduced_camera_system`, applied to
+    vectors instead of assembled (Sec. 4.2, eq. red_normal_eq):
+
+        H~ v = (H_pp + lam I) v - H_pl (H_ll + lam I)^-1 H_lp v,
+
+    with every product formed from the per-observation rows of the scaled
+    Jacobian, so it needs O(#observations) memory.  b, the diagonal 9x9 blocks
+    of H~ (the block-Jacobi preconditioner) and the back-substitution follow the
+    same definitions.  For the large workloads, where the dense matrix of
+    `reduced_camera_system` does not fit the CPU's memory or time."""
+    lam: float
+    n_cams: int
+    n_points: int
+    ci: np.ndarray
+    pi: np.ndarray
+    Jps: np.ndarray  # (n, 2, 9) scaled pose rows
+    Jls: np.ndarray  # (n, 2, 3) scaled landmark rows
+    Hll_inv: np.ndarray  # (n_points, 3, 3) (H_ll,l + lam I)^-1, zero for landmarks without rows
+    bl: np.ndarray  # (n_points, 3)
+    b: np.ndarray  # (9 n_cams,)
+    blocks: np.ndarray  # (n_cams, 9, 9) diagonal blocks of H~
+
+    def lp(self, v: np.ndarray) -> np.ndarray:
+        """H_lp v as (n_points, 3)."""
+        u = np.einsum("nij,nj->ni", self.Jps, v.reshape(self.n_cams, 9)[self.ci])  # J_p v per observation
+        return _sum_by(self.pi, np.einsum("nki,nk->ni", self.Jls, u), self.n_points)
+
+    def matvec(self, v: np.ndarray) -> np.ndarray:
+        V = v.reshape(self.n_cams, 9)
+        u = np.einsum("nij,nj->ni", self.Jps, V[self.ci])  # J_p v per observation
+        hl = _sum_by(self.pi, np.einsum("nki,nk->ni", self.Jls, u), self.n_points)  # H_lp v
+        w = np.einsum("lij,lj->li", self.Hll_inv, hl)  # (H_ll + lam I)^-1 H_lp v
+        t = u - np.einsum("nij,nj->ni", self.Jls, w[self.pi])  # J_p v - J_l w per observation
+        out = _sum_by(self.ci, np.einsum("nki,nk->ni", self.Jps, t), self.n_cams)  # J_p^T (...)
+        return (out + self.lam * V).reshape(-1)
+
+
+def reduced_system_operator(lin: Linearization, lam: float) -> ReducedOperator:
+    """`reduced_camera_system` as an operator (see ReducedOperator)."""
+    Jps = lin.Jp * lin.sp[lin.ci][:, None, :]
+    Jls = lin.Jl * lin.sl[lin.pi][:, None, :]
+    n = lin.ci.shape[0]
+    Hll = np.zeros((lin.n_points, 9))
+    bl = np.zeros((lin.n_points, 3))
+    bp = np.zeros((lin.n_cams, 9))
+    for s, e in _chunks(n):
+        Hll += _sum_by(lin.pi[s:e], np.einsum("nki,nkj->nij", Jls[s:e], Jls[s:e]).reshape(-1, 9), lin.n_points)
+        bl += _sum_by(lin.pi[s:e], np.einsum("nki,nk->ni", Jls[s:e], lin.r[s:e]), lin.n_points)
+        bp += _sum_by(lin.ci[s:e], np.einsum("nki,nk->ni", Jps[s:e], lin.r[s:e]), lin.n_cams)
+    Hll = Hll.reshape(-1, 3, 3) + lam * np.eye(3)[None]
+    used = np.zeros(lin.n_points, dtype=bool)
+    used[lin.pi] = True
+    Hll[~used] = np.eye(3)
+    inv = np.linalg.inv(Hll)
+    inv[~used] = 0.0
+    w = np.einsum("lij,lj->li", inv, bl)
+    # b~ = b_p - H_pl w; diagonal blocks: per observation J_p^T J_p - G (H_ll + lam I)^-1 G^T, G = J_p^T J_l
+    b = bp
+    blocks = np.zeros((lin.n_cams, 81))
+    for s, e in _chunks(n):
+        A, L = Jps[s:e], Jls[s:e]
+        b -= _sum_by(lin.ci[s:e], np.einsum("nki,nk->ni", A, np.einsum("nij,nj->ni", L, w[lin.pi[s:e]])), lin.n_cams)
+        At = np.swapaxes(A, 1, 2)
+        G = At @ L
+        term = At @ A - (G @ inv[lin.pi[s:e]]) @ np.swapaxes(G, 1, 2)
+        blocks += _sum_by(lin.ci[s:e], term.reshape(-1, 81), lin.n_cams)
+    blocks = blocks.reshape(-1, 9, 9) + lam * np.eye(9)[None]
+    return ReducedOperator(lam, lin.n_cams, lin.n_points, lin.ci, lin.pi, Jps, Jls, inv, bl, b.reshape(-1), blocks)
+
+
+def back_substitute(rs, dxp_scaled: np.ndarray) -> np.ndarray:
+    """Scaled landmark increment dx~_l = -H_ll^-1 (b_l + H_lp dx~_p) (eq. backsub_sc).
+
+    `rs` is the assembled ReducedSystem or the ReducedOperator of the same system."""
+    if isinstance(rs, ReducedOperator):
+        return -np.einsum("lij,lj->li", rs.Hll_inv, rs.bl + rs.lp(dxp_scaled)).reshape(-1)
     return -(rs.Hll_inv @ (rs.bl + rs.Hpl.T @ dxp_scaled))
 
 

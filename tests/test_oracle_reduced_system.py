@@ -144,3 +144,75 @@ def test_model_decrease_equals_direct_model_evaluation():
     pred = oracle.model_decrease(lin, dxp, dxl)
     assert pred > 0
     np.testing.assert_allclose(pred, lin.cost - model, rtol=1e-9)
+
+
+def _with_inactive(p):
+    """Add a landmark seen once (inactive: no rows) and a camera without observations."""
+    from bal_synth import Problem
+    cams = np.vstack([p.cameras, p.cameras[0:1]]).astype(np.float32)
+    cams[-1, 3:6] += 50.0
+    pts = np.vstack([p.points, [[0.1, 0.2, 0.3]]]).astype(np.float32)
+    oc = np.concatenate([p.obs_cam, [1]]).astype(np.int32)
+    op = np.concatenate([p.obs_pt, [p.n_points]]).astype(np.int32)
+    uv = np.vstack([p.obs_uv, [[2.0, -1.0]]]).astype(np.float32)
+    return Problem("inactive", cams, pts, oc, op, uv, p.gt_cameras, p.gt_points)
+
+
+@pytest.mark.parametrize("lam", [1e-6, 1e-4, 0.3])
+def test_operator_equals_dense_schur_complement_of_the_full_system(lam):
+    """The operator form (Sec. 4.2 applied to vectors) against the Schur complement of
+    the full damped matrix J~^T J~ + lam I formed densely over all unknowns and reduced
+    with a dense inverse of its landmark part (brute force, tiny problem)."""
+    p, _, _, _ = _tiny(seed=7)
+    p = _with_inactive(p)
+    bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv)
+    lin = oracle.linearize(oracle.state_from_bal(p.cameras, p.points), bk, p.obs_uv)
+    op = oracle.reduced_system_operator(lin, lam)
+    Jp_m, Jl_m, r = scaled_jacobian_sparse(lin)
+    Jp, Jl = Jp_m.toarray(), Jl_m.toarray()
+    used = np.abs(Jl).sum(axis=0) > 0  # landmark columns with rows
+    Jl = Jl[:, used]
+    N = Jp.shape[1]
+    App = Jp.T @ Jp + lam * np.eye(N)
+    Apl = Jp.T @ Jl
+    All = Jl.T @ Jl + lam * np.eye(Jl.shape[1])
+    H = App - Apl @ np.linalg.inv(All) @ Apl.T
+    b = Jp.T @ r - Apl @ np.linalg.solve(All, Jl.T @ r)
+    Hop = np.stack([op.matvec(e) for e in np.eye(N)], axis=1)
+    scale = np.abs(H).max()
+    np.testing.assert_allclose(Hop, H, atol=1e-10 * scale)
+    np.testing.assert_allclose(op.b, b, atol=1e-10 * np.abs(b).max())
+    for i in range(lin.n_cams):
+        np.testing.assert_allclose(op.blocks[i], H[9 * i:9 * i + 9, 9 * i:9 * i + 9], atol=1e-10 * scale)
+    # back-substitution: the landmark rows of the full damped solve
+    Hf = np.block([[App, Apl], [Apl.T, All]])
+    full = np.linalg.solve(Hf, -np.concatenate([Jp.T @ r, Jl.T @ r]))
+    dxl = oracle.back_substitute(op, full[:N]).reshape(-1, 3)
+    np.testing.assert_allclose(dxl[used.reshape(-1, 3).all(axis=1)].ravel(), full[N:],
+                               atol=1e-9 * np.abs(full).max())
+    # the unused camera's column block is lam I
+    np.testing.assert_allclose(op.blocks[-1], lam * np.eye(9), atol=1e-300)
+
+
+def test_operator_equals_assembled_schur_complement():
+    """Operator and assembled forms give the same reduced system, preconditioner blocks,
+    back-substitution and LM trajectory (ring problem with every landmark size 3..8)."""
+    p, bk, st, lin = _tiny(seed=8, n_cams=10, n_pts=150)
+    for lam in (1e-4, 2.0):
+        rs = oracle.reduced_camera_system(lin, lam)
+        op = oracle.reduced_system_operator(lin, lam)
+        rng = np.random.default_rng(0)
+        for _ in range(4):
+            v = rng.normal(size=rs.b.shape)
+            np.testing.assert_allclose(op.matvec(v), rs.H @ v, rtol=1e-10, atol=1e-12 * np.abs(rs.H @ v).max())
+        np.testing.assert_allclose(op.b, rs.b, atol=1e-12 * np.abs(rs.b).max())
+        np.testing.assert_allclose(op.blocks, oracle.block_jacobi_blocks(rs.H), atol=1e-12 * np.abs(rs.H).max())
+        x = rng.normal(size=rs.b.shape)
+        np.testing.assert_allclose(oracle.back_substitute(op, x), oracle.back_substitute(rs, x), rtol=1e-10,
+                                   atol=1e-12)
+    a = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, oracle.LMOptions(max_iters=8))
+    b = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv,
+                        oracle.LMOptions(max_iters=8, solver="pcg_operator"))
+    assert [h["accepted"] for h in a.history] == [h["accepted"] for h in b.history]
+    assert [h["pcg_iters"] for h in a.history] == [h["pcg_iters"] for h in b.history]
+    assert b.final_cost == pytest.approx(a.final_cost, rel=1e-9)

@@ -75,17 +75,67 @@ def test_lm_monotone_and_statistically_sane():
     assert abs(res.final_cost - dof) < 5 * np.sqrt(2 * dof) + 0.01 * dof
 
 
-def test_lm_nielsen_rule_sequence():
-    p = make_config(0)
-    res = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, oracle.LMOptions(max_iters=10))
-    lam, nu = 1e-4, 2.0
-    for h in res.history:
-        assert h["lambda"] == pytest.approx(lam, rel=1e-12)
-        if h["accepted"]:
-            lam = lam * max(1 / 3, 1 - (2 * h["rho"] - 1) ** 3)
-            nu = 2.0
-        else:
-            lam, nu = lam * nu, 2 * nu
+def test_lm_nielsen_rule_hand_worked_sequence(monkeypatch):
+    """The damping rule of Sec. 6.1 read as Nielsen's (accept iff rho > 1e-3; accept:
+    lambda * max(1/3, 1 - (2 rho - 1)^3), nu = 2; reject: lambda * nu, nu * 2), driven
+    through the LM loop with scripted attempt outcomes.  The expected damping values
+    were worked out by hand from lambda0 = 1e-4, nu0 = 2:
+      1 reject (rho -1)        -> 2e-4,  nu 4
+      2 reject (rho -0.05)     -> 8e-4,  nu 8
+      3 accept (rho 0.75)      -> 8e-4 * 0.875            = 7e-4, nu 2
+      4 accept (rho 1.0)       -> 7e-4 * 1/3 (clamped)    = 2.3333...e-4
+      5 accept (rho 0.5)       -> factor 1                = 2.3333...e-4
+      6 accept (rho 0.002)     -> factor 1 + 0.996^3 = 1.988047936 -> 4.6387785173...e-4
+      7 reject (rho 0.0005)    -> * 2 = 9.2775570346...e-4, nu 4
+      8 reject (pred 0)        -> * 4 = 3.7110228138...e-3, nu 8
+      9 accept, relative decrease 5e-7 < 1e-6 -> stop (func_tol)"""
+    import oracle.lm as lm
+
+    script = [(110.0, 10.0), (100.5, 10.0), (92.5, 10.0), (82.5, 10.0), (77.5, 10.0), (77.48, 10.0),
+              (77.475, 10.0), (70.0, 0.0), (77.48 * (1 - 5e-7), 1e-5)]
+    calls = []
+
+    class Lin:
+        cost = 100.0
+
+    def fake_attempt(state, bk, obs_uv, lin, lam, opts, trace=False):
+        new_cost, pred = script[len(calls)]
+        calls.append(lam)
+        return {"new_cost": new_cost, "pred": pred, "new_state": state, "pcg_iters": 0, "rel_res": 0.0}
+
+    monkeypatch.setattr(lm, "lm_attempt", fake_attempt)
+    monkeypatch.setattr(lm, "linearize", lambda *a, **k: Lin())
+    monkeypatch.setattr(lm, "state_from_bal", lambda c, p: None)
+    res = lm.lm_solve(None, None, None, None, None, oracle.LMOptions(max_iters=20), bk=object())
+    expected = [1e-4, 2e-4, 8e-4, 7e-4, 2.3333333333333333e-4, 2.3333333333333333e-4, 4.6387785173333333e-4,
+                9.2775570346666667e-4, 3.7110228138666667e-3]
+    assert len(calls) == 9 and res.status == "func_tol" and res.iterations == 9
+    np.testing.assert_allclose(calls, expected, rtol=1e-12)
+    assert [h["accepted"] for h in res.history] == [False, False, True, True, True, True, False, False, True]
+    assert res.final_cost == pytest.approx(77.48 * (1 - 5e-7), rel=1e-15)
+
+
+def test_lm_damping_reaches_its_upper_clamp(monkeypatch):
+    """Only rejections: after k of them lambda is 1e-4 * 2^(1 + 2 + ... + k) = 1e-4 * 2^(k(k+1)/2).
+    It first reaches 1e32 when k(k+1)/2 >= log2(1e36) = 119.6, i.e. at k = 15 (2^120 = 1.3e36;
+    k = 14 gives 2^105 = 4.1e31), so the solve ends with status lambda_max after 15 attempts."""
+    import oracle.lm as lm
+
+    class Lin:
+        cost = 1.0
+
+    lams = []
+
+    def fake_attempt(state, bk, obs_uv, lin, lam, opts, trace=False):
+        lams.append(lam)
+        return {"new_cost": 2.0, "pred": 1.0, "new_state": state, "pcg_iters": 0, "rel_res": 0.0}
+
+    monkeypatch.setattr(lm, "lm_attempt", fake_attempt)
+    monkeypatch.setattr(lm, "linearize", lambda *a, **k: Lin())
+    monkeypatch.setattr(lm, "state_from_bal", lambda c, p: None)
+    res = lm.lm_solve(None, None, None, None, None, oracle.LMOptions(max_iters=100), bk=object())
+    assert res.status == "lambda_max" and len(lams) == 15
+    np.testing.assert_allclose(lams[:4], [1e-4, 2e-4, 8e-4, 6.4e-3], rtol=1e-12)
 
 
 def _brute_bookkeeping(n_cams, n_pts, oc, op):
