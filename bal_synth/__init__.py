@@ -14,5 +14,6 @@ from .generate import (  # noqa: F401
     make_forward_problem,
     make_batch,
     concat_problems,
+    split_batch,
     problem_stats,
 )

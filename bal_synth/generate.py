@@ -295,6 +295,21 @@ def concat_problems(probs: List[Problem], name: str = "batch") -> Problem:
     )
 
 
+def split_batch(p: Problem) -> List[Problem]:
+    """The independent problems of a stacked batch (inverse of concat_problems)."""
+    if p.cam_off is None:
+        return [p]
+    prob = np.searchsorted(p.cam_off, p.obs_cam.astype(np.int64), side="right") - 1
+    out = []
+    for i in range(p.n_problems):
+        c0, c1, l0, l1 = p.cam_off[i], p.cam_off[i + 1], p.pt_off[i], p.pt_off[i + 1]
+        m = prob == i
+        out.append(Problem(f"{p.name}[{i}]", p.cameras[c0:c1], p.points[l0:l1],
+                           (p.obs_cam[m] - c0).astype(np.int32), (p.obs_pt[m] - l0).astype(np.int32),
+                           p.obs_uv[m], p.gt_cameras[c0:c1], p.gt_points[l0:l1]))
+    return out
+
+
 CONFIG_NAMES = ["tiny-ring", "ladybug-like", "batch-256", "venice-like", "dense-stress"]
 
 

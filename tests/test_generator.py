@@ -39,3 +39,12 @@ def test_batch_offsets():
     prob_c = np.searchsorted(b.cam_off, b.obs_cam, side="right") - 1
     prob_p = np.searchsorted(b.pt_off, b.obs_pt, side="right") - 1
     assert np.array_equal(prob_c, prob_p)
+
+
+def test_split_batch_inverts_concat():
+    from bal_synth import split_batch
+    rng = np.random.default_rng(8)
+    probs = make_batch(rng, 4, cams=(5, 9), points=(20, 40), k_hi=6)
+    for p, q in zip(probs, split_batch(concat_problems(probs))):
+        for f in ["cameras", "points", "obs_cam", "obs_pt", "obs_uv"]:
+            assert np.array_equal(getattr(p, f), getattr(q, f)), f

@@ -1,21 +1,27 @@
 """Parity at the full workload sizes, in the launch configuration bench.py times.
 
-The oracle cannot form the whole reduced system of the large workloads in
-seconds, so at full size the GPU path is checked on outputs the oracle computes
-one at a time, and on properties that hold at any size:
+Every workload runs here: ladybug-like, the batch of 256, venice-like and the
+dense stress workload (210 GB of HBM).  The oracle cannot assemble the reduced
+system of the large workloads in seconds, so it applies it to vectors (the
+Schur complement of Sec. 4.2 as an operator, pinned to the assembled form on
+the CPU), and the checks are:
 
 * sampled landmark blocks (stratified over the size classes, plus the largest
   landmarks): S B^T B S and S B^T rho against the oracle's per-landmark Schur
   terms (eq. red_H / red_b), R^T R against R1^T R1 + lambda I;
-* the product: symmetric and positive definite on seeded random vectors, and
-  equal (to rounding) under the default and the autotuned launch shapes; for the
-  ladybug-like workload also against the oracle's explicit reduced system;
-* the LM solve (20 attempts, as benchmarked): the GPU's final cost equals the
-  oracle's cost function at the GPU's final state (1e-5), and for the
-  ladybug-like workload the oracle's own final cost (1e-3, stored fixture).
-
-The ladybug-like and venice-like workloads run by default; the batch of 256
-and the dense-stress workload (210 GB of HBM) run when SQRTBA_FULLSIZE_ALL=1.
+* the reduced camera system at the initial linearization: the product on 8
+  seeded random vectors and the right-hand side against the oracle's to 1e-4
+  relative, every camera's block-Jacobi block to 1e-4; the product symmetric,
+  positive definite and equal (to rounding) under the default and the
+  autotuned launch shapes;
+* the first LM attempt (lambda0) against the oracle's stored first attempt:
+  model decrease 1e-5, new cost 1e-3;
+* the LM solve at the attempt count bench.py uses (20 ladybug-like, 50 for
+  the others): the final cost against the oracle's cost function at the GPU's
+  final state (1e-5) and against the oracle's stored run at the same attempt
+  count (1e-3; per problem for the batch).  The dense stress workload's stored
+  oracle run covers its first attempt; its final cost is compared when a whole
+  stored run exists.
 """
 
 import json
@@ -28,29 +34,46 @@ import oracle
 from oracle.lm import cost_of
 from bal_synth import make_config
 
-from gpu_util import gpu_context, landmark_sc_contribution, oracle_lin, sample_landmarks
+from gpu_util import check_precond_blocks, gpu_context, landmark_sc_contribution, oracle_lin, sample_landmarks
 
 pytestmark = pytest.mark.gpu
 
-CONFIGS = [1, 3] + ([2, 4] if os.environ.get("SQRTBA_FULLSIZE_ALL") == "1" else [])
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_lm_config{}.json")
+# all four by default; SQRTBA_FULLSIZE_CONFIGS="1,3" selects some
+CONFIGS = [int(c) for c in os.environ.get("SQRTBA_FULLSIZE_CONFIGS", "1,2,3,4").split(",")]
+LM_ITERS = {1: 20, 2: 50, 3: 50, 4: 50}
+HERE = os.path.dirname(__file__)
+GOLDEN = os.path.join(HERE, "golden", "oracle_lm_config{}.json")
+FIRST = os.path.join(HERE, "golden", "oracle_first_attempt_config{}.json")
+LAM0 = 1e-4
+
+
+def _load(path):
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
 
 
 @pytest.fixture(scope="module", params=CONFIGS)
 def full(request):
+    import torch
     cfg = request.param
+    print(f"config {cfg}: generating", flush=True)
     p = make_config(cfg)
     bk, st, lin = oracle_lin(p)
-    ctx = gpu_context(p, max_lm_iters=20)
+    print(f"config {cfg}: {p.n_obs} observations, oracle linearized", flush=True)
+    ctx = gpu_context(p, max_lm_iters=LM_ITERS[cfg])
     best, _ = ctx.autotune(reps=3)
     print(f"config {cfg}: autotuned shapes {best}", flush=True)
     yield cfg, p, bk, lin, ctx
     ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
 
 
 def test_sampled_landmark_blocks(full):
     cfg, p, bk, lin, ctx = full
-    lam = 1e-4
+    lam = LAM0
     ctx.linearize()
     ctx.marginalize()
     ctx.damp(lam)
@@ -69,13 +92,36 @@ def test_sampled_landmark_blocks(full):
         worst = max(worst, eH, eb)
         Rh = np.zeros((3, 3))
         Rh[np.triu_indices(3)] = fac[9:15]
-        np.testing.assert_allclose(Rh.T @ Rh, Jl.T @ Jl + lam * np.eye(3), atol=2e-5 * (1 + lam) * max(1.0, np.abs(Jl.T @ Jl).max()))
+        np.testing.assert_allclose(Rh.T @ Rh, Jl.T @ Jl + lam * np.eye(3),
+                                   atol=2e-5 * (1 + lam) * max(1.0, np.abs(Jl.T @ Jl).max()))
     assert worst < 1e-4, worst
+
+
+def test_reduced_camera_system_probes(full):
+    """8 seeded random vectors through the GPU's product against the oracle's Schur
+    complement applied to them (eq. red_H), the right-hand side (eq. red_b) and every
+    camera's block-Jacobi block, all to 1e-4 relative, at the initial linearization."""
+    cfg, p, bk, lin, ctx = full
+    ctx.linearize()
+    ctx.marginalize()
+    ctx.damp(LAM0)
+    op = oracle.reduced_system_operator(lin, LAM0)
+    n = 9 * p.n_cams
+    V = np.random.default_rng(1000 + cfg).normal(size=(8, n)).astype(np.float32)
+    AV = ctx.debug_rcs_matvec(V).astype(np.float64)
+    for j in range(8):
+        ref = op.matvec(V[j].astype(np.float64))
+        e = np.linalg.norm(AV[j] - ref) / np.linalg.norm(ref)
+        assert e <= 1e-4, (j, e)
+    bg = ctx.debug_rhs().astype(np.float64)
+    eb = np.linalg.norm(bg - op.b) / np.linalg.norm(op.b)
+    assert eb <= 1e-4, eb
+    check_precond_blocks(ctx, op.blocks)
 
 
 def test_product_properties(full):
     cfg, p, bk, lin, ctx = full
-    lam = 1e-4
+    lam = LAM0
     ctx.linearize()
     ctx.marginalize()
     ctx.damp(lam)
@@ -95,10 +141,35 @@ def test_product_properties(full):
     AV0 = ctx.debug_rcs_matvec(V).astype(np.float64)
     ctx.set_tuning(**tuned)
     assert np.linalg.norm(AV - AV0) <= 1e-5 * np.linalg.norm(AV0)
-    if cfg == 1:
-        rs = oracle.reduced_camera_system(lin, lam)
-        Ho = rs.H @ V.T.astype(np.float64)
-        assert np.linalg.norm(AV.T - Ho) <= 1e-4 * np.linalg.norm(Ho)
+
+
+def test_first_attempt(full):
+    """The first LM attempt from the perturbed start against the oracle's: the same
+    cost, the model decrease to 1e-5 and the new cost to 1e-3 (a few PCG iterations
+    more or less move the step of these systems by up to 1e-4)."""
+    cfg, p, bk, lin, ctx = full
+    if p.n_problems > 1:
+        pytest.skip("the batch's first attempts are covered by its per-problem final costs")
+    gold = _load(FIRST.format(cfg))
+    if gold is None:
+        g = _load(GOLDEN.format(cfg))
+        assert g is not None, "no stored oracle run for this workload"
+        gold = {"initial_cost": g["initial_cost"], "lambda": g["history"][0]["lambda"], **g["history"][0]}
+    assert gold["lambda"] == LAM0
+    cost = ctx.linearize()[0]
+    ctx.marginalize()
+    ctx.damp(LAM0)
+    its, rel, st = ctx.solve()
+    pred = ctx.back_substitute()[0]
+    new_cost = ctx.update()[0]
+    ctx.commit(False)
+    print(f"config {cfg}: first attempt: cost {cost:.10g} (oracle {gold['initial_cost']:.10g}), PCG {int(its[0])} "
+          f"(oracle {gold['pcg_iters']}), pred {pred:.10g} (oracle {gold['pred']:.10g}), new cost {new_cost:.10g} "
+          f"(oracle {gold['new_cost']:.10g})", flush=True)
+    assert abs(cost - gold["initial_cost"]) <= 1e-5 * gold["initial_cost"]
+    assert st[0] == 0
+    assert abs(pred - gold["pred"]) <= 1e-5 * abs(gold["pred"]), (pred, gold["pred"])
+    assert abs(new_cost - gold["new_cost"]) <= 1e-3 * gold["new_cost"], (new_cost, gold["new_cost"])
 
 
 def test_lm_final_cost(full):
@@ -110,7 +181,15 @@ def test_lm_final_cost(full):
     c = cost_of(oracle.state_from_bal(cams, pts), bk, p.obs_uv)
     total = sum(r.final_cost for r in rep)
     assert abs(c - total) <= 1e-5 * total, (c, total)
-    if os.path.exists(GOLDEN.format(cfg)) and p.n_problems == 1:
-        with open(GOLDEN.format(cfg)) as f:
-            gold = json.load(f)
+    gold = _load(GOLDEN.format(cfg))
+    if cfg == 4 and gold is None:
+        pytest.skip("the stored oracle run of the dense stress workload covers its first attempt only")
+    assert gold is not None and gold["lm_iters"] == LM_ITERS[cfg]
+    if p.n_problems > 1:
+        rel = [abs(r.final_cost - g["final_cost"]) / g["final_cost"] for r, g in zip(rep, gold["problems"])]
+        print(f"config {cfg}: per-problem final cost vs oracle: max {max(rel):.3g}, median {np.median(rel):.3g}",
+              flush=True)
+        assert len(rel) == p.n_problems and max(rel) <= 1e-3, (int(np.argmax(rel)), max(rel))
+    else:
+        print(f"config {cfg}: final cost {total:.10g}, oracle {gold['final_cost']:.10g}", flush=True)
         assert abs(total - gold["final_cost"]) <= 1e-3 * gold["final_cost"], (total, gold["final_cost"])
