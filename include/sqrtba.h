@@ -15,9 +15,10 @@
  * Conventions shared by every call
  *  - Every function returns a sqrtba_status; no C++ exception crosses the ABI.
  *    On error the context state is unchanged and sqrtba_last_error() explains.
- *  - Array arguments are HOST pointers unless stated otherwise; the library
- *    copies inputs during the call and writes outputs before returning, so the
- *    caller keeps ownership of all its buffers.  Device memory is owned by the
+ *  - Array arguments are HOST pointers unless stated otherwise (the *_device
+ *    calls take DEVICE pointers for the problem's inputs and state); the
+ *    library copies inputs during the call and writes outputs before
+ *    returning, so the caller keeps ownership of all its buffers.  Device memory is owned by the
  *    context (allocated by the library, or a caller-provided workspace bound
  *    with sqrtba_bind_workspace) and released by sqrtba_destroy.
  *  - All kernels run on the HIP stream given at creation (NULL = default).
@@ -186,6 +187,18 @@ int32_t sqrtba_set_landmarks(sqrtba_ctx* ctx, int64_t n_points, const float* xyz
 int32_t sqrtba_set_observations(sqrtba_ctx* ctx, int64_t n_obs, const int32_t* cam, const int32_t* pt,
                                 const float* uv);
 
+/* The three calls above with DEVICE pointers (e.g. torch.Tensor.data_ptr() of
+ * contiguous CUDA tensors, same layouts and element types).  The library
+ * copies the arrays to the host on the context's stream (the bookkeeping of
+ * set_observations and the rotation conversion of set_cameras run there) and
+ * then behaves exactly like the host-pointer call, errors included; the
+ * caller keeps ownership.  A pointer that HIP does not report as device (or
+ * managed) memory is SQRTBA_E_INVALID. */
+int32_t sqrtba_set_cameras_device(sqrtba_ctx* ctx, int64_t n_cams, const float* params);
+int32_t sqrtba_set_landmarks_device(sqrtba_ctx* ctx, int64_t n_points, const float* xyz);
+int32_t sqrtba_set_observations_device(sqrtba_ctx* ctx, int64_t n_obs, const int32_t* cam, const int32_t* pt,
+                                       const float* uv);
+
 /* Device bytes the context needs once cameras, landmarks and observations are set. */
 int32_t sqrtba_workspace_bytes(const sqrtba_ctx* ctx, uint64_t* bytes);
 
@@ -244,6 +257,10 @@ int32_t sqrtba_get_lm_history(const sqrtba_ctx* ctx, int32_t problem, sqrtba_lm_
 /* Current state: n_cams x 9 (BAL order; w from the rotation matrix, host FP64) and n_points x 3. */
 int32_t sqrtba_get_cameras(sqrtba_ctx* ctx, float* params);
 int32_t sqrtba_get_landmarks(sqrtba_ctx* ctx, float* xyz);
+/* The same into caller-owned DEVICE arrays (n_cams x 9, n_points x 3), written on
+ * the context's stream, which is synchronized before returning. */
+int32_t sqrtba_get_cameras_device(sqrtba_ctx* ctx, float* params);
+int32_t sqrtba_get_landmarks_device(sqrtba_ctx* ctx, float* xyz);
 
 /* ---- inspection exports for tests (small problems) ---- */
 

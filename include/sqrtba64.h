@@ -52,6 +52,11 @@ int32_t sqrtba64_set_cameras(sqrtba64_ctx* ctx, int64_t n_cams, const double* pa
 int32_t sqrtba64_set_landmarks(sqrtba64_ctx* ctx, int64_t n_points, const double* xyz);
 int32_t sqrtba64_set_observations(sqrtba64_ctx* ctx, int64_t n_obs, const int32_t* cam, const int32_t* pt,
                                   const double* uv);
+/* device-pointer forms (sqrtba_set_*_device, sqrtba_get_*_device) */
+int32_t sqrtba64_set_cameras_device(sqrtba64_ctx* ctx, int64_t n_cams, const double* params);
+int32_t sqrtba64_set_landmarks_device(sqrtba64_ctx* ctx, int64_t n_points, const double* xyz);
+int32_t sqrtba64_set_observations_device(sqrtba64_ctx* ctx, int64_t n_obs, const int32_t* cam, const int32_t* pt,
+                                         const double* uv);
 
 /* Device workspace: about twice the FP32 size (every element is 8 bytes); owned by the caller when
  * bound, otherwise allocated by the library on first use (SQRTBA_E_OOM when it does not fit). */
@@ -78,6 +83,8 @@ int32_t sqrtba64_get_lm_history(const sqrtba64_ctx* ctx, int32_t problem, sqrtba
 /* State out: n_cams x 9 and n_points x 3 doubles, written before the call returns. */
 int32_t sqrtba64_get_cameras(sqrtba64_ctx* ctx, double* params);
 int32_t sqrtba64_get_landmarks(sqrtba64_ctx* ctx, double* xyz);
+int32_t sqrtba64_get_cameras_device(sqrtba64_ctx* ctx, double* params);
+int32_t sqrtba64_get_landmarks_device(sqrtba64_ctx* ctx, double* xyz);
 
 /* Inspection exports used by the tests, with the layouts of sqrtba_debug_* in double. */
 int32_t sqrtba64_debug_bookkeeping(const sqrtba64_ctx* ctx, int64_t* n_active, int64_t* obs_perm,

@@ -1205,7 +1205,8 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
     L.cur_solve = L.n_solves++;
   }
   const bool learned = L.mode == 1 && L.alloc;
-  std::vector<int32_t> its(P), st(P);
+  std::vector<int32_t> its(P), st(P), kept_its, kept_st;
+  std::vector<double> kept_rr, kept_rr0;
   std::vector<uint8_t> fell_back(P, 0);
   if (learned) {
     LAUNCH(c, launch_mlp_precond(c->d, learn_dev(c), c->stream));
@@ -1240,6 +1241,15 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
       }
     }
     if (any) {
+      // the restart runs only the fallback problems; the PCG start kernels reset
+      // the scalars of every other problem (their x is kept), so the kept
+      // problems' outcomes of the learned run are saved and merged back below
+      kept_rr.resize(P);
+      kept_rr0.resize(P);
+      TRY(readback(c, c->d.rr, kept_rr.data()));
+      TRY(readback(c, c->d.rr0, kept_rr0.data()));
+      kept_its = its;
+      kept_st = st;
       TRY(set_active_mask(c, fb));
       TRY(precond_stage(c));  // plain block-Jacobi blocks for these problems
       TRY(run_pcg(c, c->opt.pcg_max_iters));
@@ -1255,6 +1265,14 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
   TRY(readback(c, c->d.pstatus, st.data()));
   TRY(readback(c, c->d.rr, rr.data()));
   TRY(readback(c, c->d.rr0, rr0.data()));
+  if (!kept_its.empty())
+    for (int p = 0; p < P; ++p)
+      if (c->active[p] && !fell_back[p]) {
+        its[p] = kept_its[p];
+        st[p] = kept_st[p];
+        rr[p] = kept_rr[p];
+        rr0[p] = kept_rr0[p];
+      }
   flush_profile(c);
   for (int p = 0; p < P; ++p) {
     if (c->active[p] && (!learned || fell_back[p])) {
@@ -1400,6 +1418,36 @@ int lm_loop(sqrtba_ctx* c, const double* tol_cost, sqrtba_lm_report* rep) {
       rep[p].solve_seconds = t_fin[p];
       rep[p].time_to_tol = t_tol[p];
     }
+  return SQRTBA_OK;
+}
+
+// caller-owned device arrays: checked, then copied over on the context's stream
+int32_t check_device_ptr(sqrtba_ctx* c, const void* p, const char* what) {
+  if (!p) return fail(c, SQRTBA_E_INVALID, "%s: null pointer", what);
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, SQRTBA_E_INVALID, "%s is not a device pointer", what);
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+    return fail(c, SQRTBA_E_INVALID, "%s is not a device pointer", what);
+  return SQRTBA_OK;
+}
+
+template <class T>
+int32_t from_device(sqrtba_ctx* c, const T* p, int64_t n, std::vector<T>& out, const char* what) {
+  TRY(check_device_ptr(c, p, what));
+  out.resize((size_t)n);
+  HIP_TRY(c, hipMemcpyAsync(out.data(), p, sizeof(T) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return SQRTBA_OK;
+}
+
+template <class T>
+int32_t to_device(sqrtba_ctx* c, T* p, const std::vector<T>& in, const char* what) {
+  TRY(check_device_ptr(c, p, what));
+  HIP_TRY(c, hipMemcpyAsync(p, in.data(), sizeof(T) * in.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return SQRTBA_OK;
 }
 
@@ -1658,6 +1706,55 @@ int32_t SQRTBA_API(get_landmarks)(sqrtba_ctx* c, real* xyz) {
   for (int64_t i = 0; i < c->h.NL; ++i)
     for (int j = 0; j < 3; ++j) xyz[3 * i + j] = p[4 * i + j];
   return SQRTBA_OK;
+}
+
+// ---- device-resident inputs and outputs: the same calls on caller-owned device arrays.
+// The bookkeeping (sort by landmark and camera, CSR, size classes) and the rotation
+// conversion run on the host, so the arrays are copied over on the context's stream.
+
+
+int32_t SQRTBA_API(set_cameras_device)(sqrtba_ctx* c, int64_t n, const real* params) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (n <= 0) return fail(c, SQRTBA_E_INVALID, "need n_cams > 0 and parameters");
+  std::vector<real> h;
+  TRY(from_device(c, params, 9 * n, h, "camera parameters"));
+  return SQRTBA_API(set_cameras)(c, n, h.data());
+}
+
+int32_t SQRTBA_API(set_landmarks_device)(sqrtba_ctx* c, int64_t n, const real* xyz) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (n <= 0) return fail(c, SQRTBA_E_INVALID, "need n_points > 0 and coordinates");
+  std::vector<real> h;
+  TRY(from_device(c, xyz, 3 * n, h, "landmark coordinates"));
+  return SQRTBA_API(set_landmarks)(c, n, h.data());
+}
+
+int32_t SQRTBA_API(set_observations_device)(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_t* pt,
+                                            const real* uv) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (n <= 0) return fail(c, SQRTBA_E_INVALID, "need n_obs > 0 and observation arrays");
+  std::vector<int32_t> hc, hp;
+  std::vector<real> huv;
+  TRY(from_device(c, cam, n, hc, "observation cameras"));
+  TRY(from_device(c, pt, n, hp, "observation landmarks"));
+  TRY(from_device(c, uv, 2 * n, huv, "observation pixels"));
+  return SQRTBA_API(set_observations)(c, n, hc.data(), hp.data(), huv.data());
+}
+
+int32_t SQRTBA_API(get_cameras_device)(sqrtba_ctx* c, real* params) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (c->h.NC < 0) return fail(c, SQRTBA_E_STATE, "no cameras");
+  std::vector<real> h(9 * (size_t)c->h.NC);
+  TRY(SQRTBA_API(get_cameras)(c, h.data()));
+  return to_device(c, params, h, "camera output");
+}
+
+int32_t SQRTBA_API(get_landmarks_device)(sqrtba_ctx* c, real* xyz) {
+  if (!c) return SQRTBA_E_INVALID;
+  if (c->h.NL < 0) return fail(c, SQRTBA_E_STATE, "no landmarks");
+  std::vector<real> h(3 * (size_t)c->h.NL);
+  TRY(SQRTBA_API(get_landmarks)(c, h.data()));
+  return to_device(c, xyz, h, "landmark output");
 }
 
 int32_t SQRTBA_API(debug_bookkeeping)(const sqrtba_ctx* c, int64_t* n_active, int64_t* obs_perm, int64_t* lm_off,

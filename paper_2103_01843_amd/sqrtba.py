@@ -99,6 +99,9 @@ _SIGS = {
     "sqrtba_set_cameras": (I32, [P, I64, PF]),
     "sqrtba_set_landmarks": (I32, [P, I64, PF]),
     "sqrtba_set_observations": (I32, [P, I64, PI32, PI32, PF]),
+    "sqrtba_set_cameras_device": (I32, [P, I64, P]),
+    "sqrtba_set_landmarks_device": (I32, [P, I64, P]),
+    "sqrtba_set_observations_device": (I32, [P, I64, P, P, P]),
     "sqrtba_workspace_bytes": (I32, [P, C.POINTER(U64)]),
     "sqrtba_bind_workspace": (I32, [P, P, U64]),
     "sqrtba_set_active": (I32, [P, PU8]),
@@ -114,6 +117,8 @@ _SIGS = {
     "sqrtba_get_lm_history": (I32, [P, I32, C.POINTER(LMRecord), I32, PI32]),
     "sqrtba_get_cameras": (I32, [P, PF]),
     "sqrtba_get_landmarks": (I32, [P, PF]),
+    "sqrtba_get_cameras_device": (I32, [P, P]),
+    "sqrtba_get_landmarks_device": (I32, [P, P]),
     "sqrtba_debug_bookkeeping": (I32, [P, PI64, PI64, PI64, PU8, PU8]),
     "sqrtba_debug_linearization": (I32, [P, PF, PF, PF]),
     "sqrtba_debug_scales": (I32, [P, PF, PF]),
@@ -320,6 +325,54 @@ class Context:
         self.set_landmarks(points)
         self.set_observations(obs_cam, obs_pt, obs_uv)
         return self
+
+    # -- the same from device-resident arrays (e.g. CUDA tensors); the library copies them
+    def _device(self, t, dtype, n, what):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous() and t.dtype == dtype
+                and t.numel() == n):
+            raise ValueError(f"{what}: need a contiguous CUDA tensor of {n} {dtype} elements")
+        return P(t.data_ptr())
+
+    def _tdtype(self):
+        import torch
+        return torch.float64 if self.precision == 64 else torch.float32
+
+    def set_cameras_device(self, params):
+        n = params.numel() // 9
+        self._check(self._api.set_cameras_device(self._h, n, self._device(params, self._tdtype(), 9 * n, "cameras")))
+        self.n_cams = n
+
+    def set_landmarks_device(self, xyz):
+        n = xyz.numel() // 3
+        self._check(self._api.set_landmarks_device(self._h, n, self._device(xyz, self._tdtype(), 3 * n, "landmarks")))
+        self.n_points = n
+
+    def set_observations_device(self, cam, pt, uv):
+        import torch
+        n = cam.numel()
+        self._check(self._api.set_observations_device(
+            self._h, n, self._device(cam, torch.int32, n, "observation cameras"),
+            self._device(pt, torch.int32, n, "observation landmarks"),
+            self._device(uv, self._tdtype(), 2 * n, "observation pixels")))
+
+    def load_device(self, cameras, points, obs_cam, obs_pt, obs_uv, cam_off=None, pt_off=None):
+        """load() from CUDA tensors (offsets, if any, stay host sequences)."""
+        if cam_off is not None:
+            self.set_problems(cam_off, pt_off)
+        self.set_cameras_device(cameras)
+        self.set_landmarks_device(points)
+        self.set_observations_device(obs_cam, obs_pt, obs_uv)
+        return self
+
+    def get_cameras_device(self, out):
+        self._check(self._api.get_cameras_device(self._h, self._device(out, self._tdtype(), 9 * self.n_cams, "out")))
+        return out
+
+    def get_landmarks_device(self, out):
+        self._check(self._api.get_landmarks_device(self._h, self._device(out, self._tdtype(), 3 * self.n_points,
+                                                                          "out")))
+        return out
 
     def workspace_bytes(self) -> int:
         n = C.c_uint64()

@@ -150,3 +150,38 @@ def test_bad_network_falls_back_to_block_jacobi():
         dx, _ = ctx.debug_solution()
         np.testing.assert_array_equal(dx, dx_plain)
     ctx.close()
+
+
+def test_batch_fallback_keeps_the_other_problems_outcome():
+    """A batch in learned mode where one problem falls back to block-Jacobi: the
+    other problems keep the outcome of their learned solve (converged, with their
+    own iteration count), and the fallback problem converges with plain blocks.
+    Set-up: the untrained network emits exactly block-Jacobi (last layer zero),
+    so the easy problem's learned solve equals its plain one; the hard problem's
+    last plain solve is recorded under a 3-iteration limit, so the learned cap
+    (1.5 x the largest last plain count) is set by the easy problem and the hard
+    problem cannot reach the tolerance within it."""
+    from bal_synth import concat_problems, make_forward_problem
+    easy = make_ring_problem(np.random.default_rng(41), 6, 60, lambda r, n: r.integers(2, 6, size=n))
+    hard = make_forward_problem(np.random.default_rng(42), 40, 2000, 20)
+    batch = concat_problems([easy, hard])
+    ctx = gpu_context(batch)
+    ctx.mlp_init(0)
+    ctx.linearize()
+    ctx.marginalize()
+    ctx.damp(1e-4)
+    ctx.set_active([1, 0])
+    its_plain, _, st_plain = ctx.solve()
+    assert st_plain[0] == 0
+    ctx.set_active([0, 1])
+    ctx.set_options(pcg_max_iters=3)
+    ctx.solve()
+    ctx.set_options(pcg_max_iters=500)
+    ctx.set_active([1, 1])
+    ctx.set_preconditioner("learned")
+    its, rel, st = ctx.solve()
+    stats = ctx.learned_stats()
+    ctx.close()
+    assert stats["fallbacks"] == 1, stats
+    assert st[0] == 0 and abs(int(its[0]) - int(its_plain[0])) <= 2 and 0 < rel[0] <= 1e-6, (st, its, rel, its_plain)
+    assert st[1] == 0 and its[1] > 1.5 * its_plain[0] and 0 < rel[1] <= 1e-6, (st, its, rel)
