@@ -92,6 +92,9 @@ int32_t sqrtba64_debug_bookkeeping(const sqrtba64_ctx* ctx, int64_t* n_active, i
 int32_t sqrtba64_debug_linearization(sqrtba64_ctx* ctx, double* r, double* Jp, double* Jl);
 int32_t sqrtba64_debug_scales(sqrtba64_ctx* ctx, double* s_cam, double* s_pt);
 int32_t sqrtba64_debug_rcs_matvec(sqrtba64_ctx* ctx, int32_t m, const double* v, double* out);
+/* sqrtba_rcs_matvec_noalloc in double precision (device pointers, no allocation; the
+ * FP64 library holds its own array of SQRTBA_NOALLOC_SCRATCH_BYTES per GPU). */
+int32_t sqrtba64_rcs_matvec_noalloc(sqrtba64_ctx* ctx, const double* v, double* out);
 int32_t sqrtba64_debug_rhs(sqrtba64_ctx* ctx, double* rhs);
 int32_t sqrtba64_debug_precond(sqrtba64_ctx* ctx, double* minv);
 int32_t sqrtba64_debug_block(sqrtba64_ctx* ctx, int64_t pt, int32_t* k, double* out, double* factors);

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsqrtba.so")
 LIB64 = os.path.join(HERE, "libsqrtba64.so")
-SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "learned.hip"), os.path.join(CSRC, "api.cpp")]
+SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "learned.hip"), os.path.join(CSRC, "noalloc.hip"),
+           os.path.join(CSRC, "api.cpp")]
 ARCH = "gfx950"
 
 # packed-FP32 instructions are disabled for every HIP file (numerical safety

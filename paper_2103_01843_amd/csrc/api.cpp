@@ -31,6 +31,8 @@
 
 using namespace sqrtba;
 
+static_assert(NOALLOC_SCRATCH_BYTES == SQRTBA_NOALLOC_SCRATCH_BYTES, "no-allocation scratch size of the header");
+
 namespace {
 
 constexpr int32_t kVersion = 1;
@@ -61,6 +63,7 @@ struct HostData {
   std::vector<int32_t> qjob;   // (slot, first row | end row << 16) chunks of the class-5 QR
   std::vector<int64_t> hz_off; // per slot with k >= ROWS_MIN_K, offset of its partial outputs
   int64_t hz_floats = 0;
+  int64_t z_floats = 0;        // elements of the product's per-observation output area (explicit blocks)
   int64_t poolB = 0, poolT = 0;
   // explicit Schur complement (landmark_blocks = 2): camera-pair blocks of the
   // reduced matrix, built on demand (O(sum k^2) host work and memory)
@@ -90,6 +93,7 @@ struct sqrtba_ctx {
   hipStream_t side = nullptr;  // side stream for the largest landmark blocks
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device = 0;
+  void* noalloc_scratch = nullptr;  // device address of the no-allocation product's scratch on `device`
   std::string err;
   HostData h;
   Arena arena;
@@ -374,6 +378,7 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
     oz += W;
   }
   if (oz > 54 * nb.NO || oz > INT32_MAX) return fail(c, SQRTBA_E_UNSUPPORTED, "product output area too large");
+  nb.z_floats = oz;
   // offsets of each camera's observation outputs, in camera order
   {
     std::vector<int32_t> zpos_of_obs(nb.NO);
@@ -1498,6 +1503,11 @@ int32_t SQRTBA_API(create)(sqrtba_ctx** out, const sqrtba_options* opt, void* hi
     delete c;
     return SQRTBA_E_HIP;
   }
+  // the no-allocation product's scratch on this device (looked up once per device)
+  if (noalloc_scratch(c->device, &c->noalloc_scratch) != hipSuccess) {
+    delete c;
+    return SQRTBA_E_HIP;
+  }
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -1820,6 +1830,18 @@ int32_t SQRTBA_API(debug_rcs_matvec)(sqrtba_ctx* c, int32_t m, const real* v, re
   }
   (void)hipFree(buf);
   if (e != hipSuccess) return fail(c, SQRTBA_E_HIP, "rcs_matvec: %s", hipGetErrorString(e));
+  return SQRTBA_OK;
+}
+
+int32_t SQRTBA_API(rcs_matvec_noalloc)(sqrtba_ctx* c, const real* v, real* out) {
+  if (!c || !v || !out) return SQRTBA_E_INVALID;
+  if (!c->damped) return fail(c, SQRTBA_E_STATE, "rcs_matvec_noalloc needs damp");
+  if (c->opt.landmark_blocks != 0) return fail(c, SQRTBA_E_UNSUPPORTED, "rcs_matvec_noalloc: explicit landmark blocks only");
+  const uint64_t need = sizeof(real) * (uint64_t)(noalloc_out_elems(c->h.z_floats) + c->h.hz_floats);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(c, SQRTBA_E_UNSUPPORTED, "rcs_matvec_noalloc: the product needs %llu bytes of scratch, the limit is %llu",
+                (unsigned long long)need, (unsigned long long)NOALLOC_SCRATCH_BYTES);
+  LAUNCH(c, launch_matvec_noalloc(c->d, c->L, c->noalloc_scratch, c->h.z_floats, v, out));
   return SQRTBA_OK;
 }
 

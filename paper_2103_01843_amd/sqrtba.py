@@ -124,6 +124,7 @@ _SIGS = {
     "sqrtba_debug_scales": (I32, [P, PF, PF]),
     "sqrtba_debug_rcs_matvec": (I32, [P, I32, PF, PF]),
     "sqrtba_debug_rhs": (I32, [P, PF]),
+    "sqrtba_rcs_matvec_noalloc": (I32, [P, P, P]),
     "sqrtba_debug_precond": (I32, [P, PF]),
     "sqrtba_debug_block": (I32, [P, I64, PI32, PF, PF]),
     "sqrtba_debug_solution": (I32, [P, PF, PF]),
@@ -589,6 +590,14 @@ class Context:
         out = np.zeros_like(V2)
         self._check(self._api.debug_rcs_matvec(self._h, V2.shape[0], _ptr(V2, self._rc), _ptr(out, self._rc)))
         return out.reshape(V.shape)
+
+    def rcs_matvec_noalloc(self, v, out):
+        """out = (B^T B + lambda I) v for CUDA tensors v, out of 9 n_cams elements, on the
+        context's stream without synchronizing or allocating (static scratch)."""
+        n = 9 * self.n_cams
+        self._check(self._api.rcs_matvec_noalloc(self._h, self._device(v, self._tdtype(), n, "v"),
+                                                 self._device(out, self._tdtype(), n, "out")))
+        return out
 
     def debug_rhs(self) -> np.ndarray:
         out = np.zeros(9 * self.n_cams, self._rt)
