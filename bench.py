@@ -1,13 +1,14 @@
 #!/usr/bin/env python
 """Benchmark of the square-root BA hot path on one MI355X.
 
-Workload: the ladybug-like problem (500 cameras on a forward trajectory,
-100k landmarks with k = 2 + Geom(1/3) observations clamped to 50, ~400k
-observations), seeded synthetic data, FP32.  One step is one full
-Levenberg-Marquardt solve (at most 20 attempts) from the same perturbed start,
-with every input resident in HBM: each attempt runs linearize, QR
-marginalization, Givens damping, block-Jacobi + right-hand side, PCG,
-back-substitution, update and cost.
+Workload (default): the venice-like problem (1,778-camera ring, 1M landmarks
+with k = min(400, 2 + floor(LogNormal(0.40, 1.30))) observations, ~5M
+observations, 5.4 GB of landmark blocks resident in HBM), seeded synthetic
+data, FP32.  One step is one full Levenberg-Marquardt solve (at most 50
+attempts, the paper's limit) from the same perturbed start, with every input
+resident in HBM: each attempt runs linearize, QR marginalization, Givens
+damping, block-Jacobi + right-hand side, PCG, back-substitution, update and
+cost.
 
 Printed JSON line: time-to-1%-cost (the headline value, from the timed steps in
 the production configuration: graph-captured PCG, no profiler), QR blocks/s
@@ -50,7 +51,10 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_lm_config{}.json")
 GOLDEN_HUBER = os.path.join(ROOT, "tests", "golden", "oracle_lm_huber_config{}.json")
 # HBM counter readings of the product per workload (valid for the kernels and
 # launch shapes they were taken with)
-TRAFFIC_TAG = {1: "ladybug", 2: "batch256", 3: "venice"}  # profiles/matvec_traffic_<tag>_<blocks>.json
+TRAFFIC_TAG = {1: "ladybug", 2: "batch256", 3: "venice", 4: "dense"}
+# LM attempts per workload: 20 for the ladybug-like one (its stored oracle run),
+# the paper's limit of 50 for the others (Sec. 6.1)
+LM_ITERS = {1: 20, 2: 50, 3: 50, 4: 50}  # profiles/matvec_traffic_<tag>_<blocks>.json
 KERNELS = os.path.join(ROOT, "paper_2103_01843_amd", "csrc", "kernels.hip")
 
 
@@ -70,69 +74,147 @@ def time_to_tol(hist, t_tol_cost):
     return float("inf")
 
 
-def cpu_baseline(problem, f_tau, budget_s: float):
-    """Oracle (FP64, numpy/scipy) timed on a bounded sample and scaled to time-to-1%-cost.
+def _host_cpu() -> dict:
+    """Host facts recorded next to the CPU baseline: logical cores, model, sockets."""
+    model, sockets = None, set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and model is None:
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("physical id"):
+                    sockets.add(line.split(":", 1)[1].strip())
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "cpu_model": model, "sockets": len(sockets) or None}
 
-    Sample: the oracle's first LM attempt on the full workload, split into its
-    stages (linearization, explicit Schur complement, PCG per iteration, back-
-    substitution + cost).  The oracle's own trajectory (the stored oracle run)
-    gives the number of attempts and PCG iterations it needs to reach the 1%
-    threshold; the estimate is the sum of the measured stage times over them.
-    """
-    import numpy as np
-    import oracle
-    from oracle.solvers import pcg
+
+def _oracle_threads() -> str:
     try:
         from threadpoolctl import threadpool_info
-        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        return ", ".join(f"{i.get('internal_api')} {i.get('num_threads')}" for i in threadpool_info())
     except Exception:
-        blas_threads = 1
-    gpath = GOLDEN.format(1)
-    if not os.path.exists(gpath):
+        return "unknown"
+
+
+def _golden(cfg: int, lm_iters: int):
+    """The stored oracle run of a workload if it used the same number of LM attempts."""
+    if not os.path.exists(GOLDEN.format(cfg)):
         return None
-    with open(gpath) as f:
+    with open(GOLDEN.format(cfg)) as f:
         gold = json.load(f)
-    p = problem
-    t0 = time.perf_counter()
-    bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv)
-    st = oracle.state_from_bal(p.cameras, p.points)
-    ta = time.perf_counter()
-    lin = oracle.linearize(st, bk, p.obs_uv)
-    t_lin = time.perf_counter() - ta
-    ta = time.perf_counter()
-    rs = oracle.reduced_camera_system(lin, 1e-4)
-    t_sc = time.perf_counter() - ta
-    n_pcg = 40
-    ta = time.perf_counter()
-    res = pcg(lambda v: rs.H @ v, rs.b, oracle.block_jacobi_blocks(rs.H), 0.0, n_pcg)
-    t_pcg = (time.perf_counter() - ta) / max(1, res.iters)
-    ta = time.perf_counter()
-    dxl = oracle.back_substitute(rs, res.x)
-    oracle.model_decrease(lin, res.x, dxl)
+    return gold if gold.get("lm_iters") == lm_iters else None
+
+
+def cpu_baseline(problem, cfg: int, f_taus, lm_iters: int, budget_s: float = 30.0):
+    """The FP64 oracle (numpy/scipy, as it is) timed on the host's cores.
+
+    ladybug-like: the oracle's own LM loop on the whole workload, measured until
+    its first accepted attempt at or below the 1% threshold (~20 s).
+    batch of 256: the oracle's LM loop problem by problem, each until it reaches
+    its own threshold, for as many problems as fit the budget; scaled to the
+    whole batch by the observation count.
+    venice-like and dense stress: one oracle attempt is minutes of CPU work, so
+    the sample is the first attempt on a prefix of the landmarks (about 1M
+    observations): linearization, the Schur complement applied to vectors with
+    its preconditioner blocks, 10 PCG iterations, back-substitution and the new
+    cost, each stage timed and scaled to the whole workload by the observation
+    count; the stored oracle run of the workload gives the number of attempts,
+    linearizations and PCG iterations until its cost first reaches the
+    threshold, over which the scaled stage times are summed."""
+    import numpy as np
+    import oracle
+    from bal_synth import split_batch
     from oracle.lm import cost_of
-    cost_of(oracle.apply_update(st, res.x.reshape(-1, 9) * lin.sp, dxl.reshape(-1, 3) * lin.sl), bk, p.obs_uv)
-    t_bs = time.perf_counter() - ta
-    sample_s = time.perf_counter() - t0
-    # oracle trajectory until its cost first reaches the threshold
-    est, attempts, iters = 0.0, 0, 0
-    reached = False
+    from oracle.solvers import pcg
+
+    host = _host_cpu()
+    base = {"unit": "s", "kind": "oracle", "host": host, "threads": _oracle_threads()}
+    p = problem
+    if cfg == 1:
+        f_tau = f_taus[0][2]
+        t0 = time.perf_counter()
+        bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv)
+        res = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, oracle.LMOptions(max_iters=lm_iters),
+                              bk, progress=lambda h: h["accepted"] and h["new_cost"] <= f_tau)
+        reached = res.status == "stopped"
+        h = res.history[-1]
+        return {**base, "value": h["t"] if reached else None, "cores": 1,
+                "sample": (f"the oracle's LM loop (assembled Schur complement, block-Jacobi PCG) on the whole workload "
+                           f"until its first accepted attempt at or below the 1% threshold: {res.iterations} attempts, "
+                           f"{sum(x['pcg_iters'] for x in res.history)} PCG iterations, measured, "
+                           f"{time.perf_counter() - t0:.1f} s including bookkeeping")}
+    if cfg == 2:
+        probs = split_batch(p)
+        t0 = time.perf_counter()
+        spent, obs_done, n_done = 0.0, 0, 0
+        for i, q in enumerate(probs):
+            f_tau = f_taus[i][2]
+            res = oracle.lm_solve(q.cameras, q.points, q.obs_cam, q.obs_pt, q.obs_uv,
+                                  oracle.LMOptions(max_iters=lm_iters),
+                                  progress=lambda h, f=f_tau: h["accepted"] and h["new_cost"] <= f)
+            if res.status != "stopped":
+                return {**base, "value": None, "cores": 1, "sample": f"problem {i} did not reach its threshold"}
+            spent += res.history[-1]["t"]
+            obs_done += q.n_obs
+            n_done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        return {**base, "value": spent * p.n_obs / obs_done, "cores": 1,
+                "sample": (f"the oracle's LM loop on the first {n_done} of {len(probs)} problems, each until it "
+                           f"reaches its own 1% threshold (measured {spent:.1f} s over {obs_done} observations), "
+                           f"scaled to all {p.n_obs} observations")}
+    gold = _golden(cfg, lm_iters)
+    if gold is None or "history" not in gold:
+        return None
+    f_tau = f_taus[0][2]
+    n_lin, n_att, n_pcg, reached = 1, 0, 0, False
     for h in gold["history"]:
-        attempts += 1
-        iters += h["pcg_iters"]
-        est += t_lin + t_sc + t_pcg * h["pcg_iters"] + t_bs
+        n_att += 1
+        n_pcg += h["pcg_iters"]
         if h["accepted"] and h["new_cost"] <= f_tau:
             reached = True
             break
-    return {
-        "value": est if reached else None,
-        "unit": "s",
-        "cores": int(blas_threads),
-        "kind": "oracle",
-        "sample": (f"one FP64 oracle LM attempt on the full workload ({sample_s:.1f} s: linearize {t_lin:.2f} s, "
-                   f"explicit Schur complement {t_sc:.2f} s, PCG {1e3 * t_pcg:.1f} ms/iteration over {res.iters} "
-                   f"iterations, back-substitution + cost {t_bs:.2f} s), scaled by the oracle's own trajectory to the "
-                   f"1% threshold: {attempts} attempts, {iters} PCG iterations"),
-    }
+        n_lin += 1 if h["accepted"] else 0
+    if not reached:
+        return {**base, "value": None, "cores": 1, "sample": "the stored oracle run never reaches the threshold"}
+    # prefix of the landmarks holding about 1M observations
+    n_sub = int(np.searchsorted(np.cumsum(np.bincount(p.obs_pt, minlength=p.n_points)), 1_000_000)) + 1
+    m = p.obs_pt < n_sub
+    t = {}
+    ta = time.perf_counter()
+    bk = oracle.build_bookkeeping(p.n_cams, n_sub, p.obs_cam[m], p.obs_pt[m], p.obs_uv[m])
+    st = oracle.state_from_bal(p.cameras, p.points[:n_sub])
+    tb = time.perf_counter()
+    lin = oracle.linearize(st, bk, p.obs_uv[m])
+    t["linearize"] = time.perf_counter() - tb
+    tb = time.perf_counter()
+    op = oracle.reduced_system_operator(lin, 1e-4)
+    t["reduced_system"] = time.perf_counter() - tb
+    tb = time.perf_counter()
+    res = pcg(op.matvec, op.b, op.blocks, 0.0, 10)
+    t["pcg_iteration"] = (time.perf_counter() - tb) / max(1, res.iters)
+    tb = time.perf_counter()
+    dxl = oracle.back_substitute(op, res.x)
+    oracle.model_decrease(lin, res.x, dxl)
+    cost_of(oracle.apply_update(st, res.x.reshape(-1, 9) * lin.sp, dxl.reshape(-1, 3) * lin.sl), bk, p.obs_uv[m])
+    t["back_substitution_and_cost"] = time.perf_counter() - tb
+    sample_s = time.perf_counter() - ta
+    scale = p.n_obs / float(m.sum())
+    est = scale * (n_lin * t["linearize"] + n_att * (t["reduced_system"] + t["back_substitution_and_cost"])
+                   + n_pcg * t["pcg_iteration"])
+    return {**base, "value": est, "cores": 1,
+            "sample_stage_s": t, "sample_obs": int(m.sum()), "scale_by_obs": scale,
+            "sample": (f"the oracle's first attempt on the first {n_sub} landmarks ({int(m.sum())} of {p.n_obs} "
+                       f"observations, {sample_s:.1f} s: linearize, Schur complement applied to vectors with its "
+                       f"block-Jacobi blocks, {res.iters} PCG iterations, back-substitution and cost), each stage "
+                       f"scaled by the observation count, summed over the stored oracle run to the 1% threshold: "
+                       f"{n_att} attempts, {n_lin} linearizations, {n_pcg} PCG iterations"),
+            "oracle_run_in_build_container_s": gold["history"][n_att - 1]["t"]}
 
 
 def learned_run(ctx, n_problems: int, lm_iters: int):
@@ -229,9 +311,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--lm-iters", type=int, default=20)
-    ap.add_argument("--config", type=int, default=1, choices=[1, 2, 3, 4],
-                    help="workload: 1 ladybug-like (default), 2 batch of 256, 3 venice-like, 4 dense stress")
+    ap.add_argument("--lm-iters", type=int, default=None, help="LM attempts (default: 20 ladybug-like, 50 else)")
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4],
+                    help="workload: 1 ladybug-like, 2 batch of 256, 3 venice-like (default), 4 dense stress")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default product launch shapes")
@@ -273,6 +355,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     cfg = args.config
+    if args.lm_iters is None:
+        args.lm_iters = LM_ITERS[cfg]
     log(f"generating workload {cfg}: {WORKLOADS[cfg]}")
     p = make_config(cfg)
     stats = problem_stats(p)
@@ -396,10 +480,12 @@ def main():
             fp64 = {"skipped": str(e)}
 
     # time to 1% cost per problem (appendix A.2), f* over the runs (and the oracle where stored)
-    gold = None
-    if os.path.exists(GOLDEN.format(cfg)):
-        with open(GOLDEN.format(cfg)) as f:
-            gold = json.load(f)
+    gold = _golden(cfg, args.lm_iters)
+    oracle_finals = [None] * p.n_problems
+    if gold and "problems" in gold and len(gold["problems"]) == p.n_problems:
+        oracle_finals = [g["final_cost"] for g in gold["problems"]]
+    elif gold and "final_cost" in gold and p.n_problems == 1:
+        oracle_finals = [gold["final_cost"]]
     ttt_all, f_taus = [], []
     for i in range(p.n_problems):
         f0 = runs[0][0][i].initial_cost
@@ -414,7 +500,7 @@ def main():
             finals += [reps[i].final_cost for reps, _ in sc["runs"]]
         if fp64 and "runs" in fp64:
             finals += [reps[i].final_cost for reps, _ in fp64["runs"]]
-        fstar = min(finals + ([gold["final_cost"]] if gold and p.n_problems == 1 else []))
+        fstar = min(finals + ([oracle_finals[i]] if oracle_finals[i] is not None else []))
         f_tau = fstar + 0.01 * (f0 - fstar)
         f_taus.append((f0, fstar, f_tau))
         ttt_all.append([time_to_tol(h[i], f_tau) for _, h in runs])
@@ -452,6 +538,10 @@ def main():
     elif sc:
         def rejected(hist):
             return sum(sum(1 for h in hh if not h["accepted"]) for hh in hist)
+
+        def breakdowns(hist, only_rejected=False):  # PCG stopped by p^T A p <= 0 (or r^T z <= 0, non-finite)
+            return sum(sum(1 for h in hh if h["pcg_status"] == "breakdown" and not (only_rejected and h["accepted"]))
+                       for hh in hist)
         ttt_sc = [max(time_to_tol(h[i], f_taus[i][2]) for i in range(p.n_problems)) for _, h in sc["runs"]]
         ach_sc = sc["mv_bytes"] / (sc["mv_ms"] * 1e-3) / 1e9 if sc["mv_ms"] > 0 else None
         sc_out = {
@@ -461,6 +551,9 @@ def main():
             "final_costs": [sum(r.final_cost for r in reps) for reps, _ in sc["runs"]],
             "rejected_attempts": rejected(sc["runs"][-1][1]),
             "sqrt_ba_rejected_attempts": rejected(runs[-1][1]),
+            "pcg_breakdowns": breakdowns(sc["runs"][-1][1]),
+            "rejected_with_pcg_breakdown": breakdowns(sc["runs"][-1][1], True),
+            "sqrt_ba_pcg_breakdowns": breakdowns(runs[-1][1]),
             "pcg_iters": sum(r.total_pcg_iters for r in sc["runs"][-1][0]),
             "workspace_bytes": sc["workspace_bytes"],
             "product": {"avg_launch_ms": sc["mv_ms"], "algorithmic_bytes_per_launch": sc["mv_bytes"],
@@ -556,11 +649,16 @@ def main():
         batch = {"problems": p.n_problems, "problems_per_s": p.n_problems * len(runs) / wall,
                  "p50_solve_s": solve_s[len(solve_s) // 2], "p99_solve_s": solve_s[min(len(solve_s) - 1,
                                                                                       int(0.99 * len(solve_s)))]}
+    rel_oracle = None
+    if all(f is not None for f in oracle_finals):
+        tot = sum(r.final_cost for r in runs[0][0])
+        rel_oracle = {"total": abs(tot - sum(oracle_finals)) / sum(oracle_finals),
+                      "max_per_problem": max(abs(r.final_cost - o) / o for r, o in zip(runs[0][0], oracle_finals))}
     cpu = None
-    if not args.no_cpu_baseline and cfg == 1:
+    if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample")
         try:
-            cpu = cpu_baseline(p, f_tau, 30.0)
+            cpu = cpu_baseline(p, cfg, f_taus, args.lm_iters)
         except Exception as e:  # the baseline is reported, never required
             log(f"cpu baseline failed: {e!r}")
     out = {
@@ -584,7 +682,8 @@ def main():
         "upload_s": upload_s,
         "time_to_1pct_cost_incl_upload_s": value + upload_s,
         "f0": f0, "f_star": fstar, "f_tau": f_tau, "final_costs": finals,
-        "oracle_final_cost": gold["final_cost"] if gold else None,
+        "oracle_final_cost": (sum(oracle_finals) if all(f is not None for f in oracle_finals) else None),
+        "final_cost_rel_to_oracle": rel_oracle,
         "batch": batch,
         "qr_blocks_per_s": qr_blocks_per_s,
         "qr_GBps": qr_gbps,

@@ -19,9 +19,7 @@ the CPU), and the checks are:
 * the LM solve at the attempt count bench.py uses (20 ladybug-like, 50 for
   the others): the final cost against the oracle's cost function at the GPU's
   final state (1e-5) and against the oracle's stored run at the same attempt
-  count (1e-3; per problem for the batch).  The dense stress workload's stored
-  oracle run covers its first attempt; its final cost is compared when a whole
-  stored run exists.
+  count (1e-3; per problem for the batch).
 """
 
 import json
@@ -182,8 +180,6 @@ def test_lm_final_cost(full):
     total = sum(r.final_cost for r in rep)
     assert abs(c - total) <= 1e-5 * total, (c, total)
     gold = _load(GOLDEN.format(cfg))
-    if cfg == 4 and gold is None:
-        pytest.skip("the stored oracle run of the dense stress workload covers its first attempt only")
     assert gold is not None and gold["lm_iters"] == LM_ITERS[cfg]
     if p.n_problems > 1:
         rel = [abs(r.final_cost - g["final_cost"]) / g["final_cost"] for r, g in zip(rep, gold["problems"])]
