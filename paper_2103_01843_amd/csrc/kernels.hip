@@ -2776,6 +2776,24 @@ hipError_t launch_marginalize(const Dev& d, const Launch& L, const uint8_t* mask
   return hipSuccess;
 }
 
+// The landmarks of class 5 (k > 113: few, each a long stream for one workgroup)
+// run on the side stream concurrently with the other classes, forked from and
+// joined back into the context stream by events; without a side stream they
+// run first on the context stream.
+static hipError_t side_fork(const Launch& L, bool side) {
+  if (!side) return hipSuccess;
+  hipError_t e = hipEventRecord(L.fork, L.stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(L.side, L.fork, 0);
+  return e;
+}
+
+static hipError_t side_join(const Launch& L, bool side) {
+  if (!side) return hipSuccess;
+  hipError_t e = hipEventRecord(L.join, L.side);
+  if (e == hipSuccess) e = hipStreamWaitEvent(L.stream, L.join, 0);
+  return e;
+}
+
 hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
   const WorkClass* w = L.wc;
   if (d.sc) {  // (H_ll + lambda I)^-1, then the reduced matrix assembled anew
@@ -2793,11 +2811,19 @@ hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
     LAUNCH_CHECK();
     return hipSuccess;
   }
-  if (w[5].slots) hipLaunchKernelGGL(k_damp_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot, mask);
   int n = 0;
   const ClassGrid m = class_grid(L, &n);
+  const bool side = w[5].slots && n && L.side && L.fork && L.join;
+  hipError_t e = side_fork(L, side);
+  if (e != hipSuccess) return e;
+  if (w[5].slots)
+    hipLaunchKernelGGL(k_damp_huge, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d, w[5].first_slot,
+                       mask);
+  LAUNCH_CHECK();
   if (n) hipLaunchKernelGGL(k_damp, dim3(n), dim3(WG), 0, L.stream, d, m, mask);
   LAUNCH_CHECK();
+  e = side_join(L, side);
+  if (e != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -2817,11 +2843,19 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
     LAUNCH_CHECK();
     return hipSuccess;
   }
-  if (w[5].slots) hipLaunchKernelGGL(k_precond_obs_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot);
   int n = 0;
   const ClassGrid m = class_grid(L, &n);
+  const bool side = w[5].slots && n && L.side && L.fork && L.join;
+  hipError_t e = side_fork(L, side);
+  if (e != hipSuccess) return e;
+  if (w[5].slots)
+    hipLaunchKernelGGL(k_precond_obs_huge, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d,
+                       w[5].first_slot);
+  LAUNCH_CHECK();
   if (n) hipLaunchKernelGGL(k_precond_obs, dim3(n), dim3(WG), 0, L.stream, d, m);
   LAUNCH_CHECK();
+  e = side_join(L, side);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_precond_cam, dim3(d.NC), dim3(64), 0, L.stream, d);
   LAUNCH_CHECK();
   return hipSuccess;
@@ -2970,12 +3004,17 @@ hipError_t launch_backsub(const Dev& d, const Launch& L) {
     LAUNCH_CHECK();
     return hipSuccess;
   }
-  if (w[5].slots) hipLaunchKernelGGL(k_backsub_huge, dim3(w[5].slots), dim3(WG), 0, L.stream, d, w[5].first_slot);
   int n = 0;
   const ClassGrid m = class_grid(L, &n);
+  const bool side = w[5].slots && n && L.side && L.fork && L.join;
+  hipError_t e = side_fork(L, side);
+  if (e != hipSuccess) return e;
+  if (w[5].slots)
+    hipLaunchKernelGGL(k_backsub_huge, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d, w[5].first_slot);
+  LAUNCH_CHECK();
   if (n) hipLaunchKernelGGL(k_backsub, dim3(n), dim3(WG), 0, L.stream, d, m);
   LAUNCH_CHECK();
-  return hipSuccess;
+  return side_join(L, side);
 }
 
 hipError_t launch_update(const Dev& d, const Launch& L) {
