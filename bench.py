@@ -637,7 +637,8 @@ def main():
                           "the product with the assembled FP32 Schur complement (k_sc_matvec)")
                 + (", FP64 build (libsqrtba64.so)" if args.precision == 64 else ""),
                 "avg_launch_ms": mv_ms, "algorithmic_bytes_per_launch": mv_bytes, "launches_timed": 50,
-                "timing": "HIP events around 50 back-to-back products on the resident blocks, context stream",
+                "timing": ("HIP events around a captured graph of 50 back-to-back products on the resident blocks "
+                           "(the PCG iterations run as graphs too), context stream"),
                 "traffic_source": traffic_note,
                 "profiled_pass_matvec_ms": prof["matvec"]["ms"] / max(1, prof["matvec"]["launches"])}
     qr_blocks_per_s = qr["units"] / (qr["ms"] * 1e-3) if qr["ms"] > 0 else None

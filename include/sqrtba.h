@@ -472,7 +472,9 @@ int32_t sqrtba_autotune(sqrtba_ctx* ctx, int32_t reps, sqrtba_tuning* best, sqrt
 
 /* Mean milliseconds of one PCG product (kernel (c), current shapes) over reps
  * back-to-back launches on the resident landmark blocks of the active
- * problems, HIP events on the context stream; *bytes (may be NULL) receives
+ * problems, captured as one HIP graph as the PCG iterations are, with HIP
+ * events on the context stream around its second launch (the first warms
+ * up); the autotuner times its candidates the same way; *bytes (may be NULL) receives
  * the algorithmic bytes of one product, 4 (18 k^2 + 9 k) per active landmark.
  * Overwrites only scratch (the product outputs). */
 int32_t sqrtba_time_product(sqrtba_ctx* ctx, int32_t reps, double* ms, double* bytes);

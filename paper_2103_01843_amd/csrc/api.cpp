@@ -2203,19 +2203,38 @@ int apply_tuning(sqrtba_ctx* c, const sqrtba_tuning& t) {
 
 // Mean milliseconds of one product over `reps` back-to-back launches (after two
 // untimed ones), HIP events on the context stream.
+// Average duration of one product over `reps` back-to-back products, launched as
+// one captured HIP graph as the PCG iterations are (graph-launched products have
+// no launch gaps between their kernels and their side-stream branch); HIP events
+// around the second launch of the graph.
 int time_products(sqrtba_ctx* c, int reps, double* ms) {
   hipEvent_t e0 = take_event(c), e1 = take_event(c);
   if (!e0 || !e1) return fail(c, SQRTBA_E_HIP, "no events");
-  if (c->d.implicit) LAUNCH(c, launch_prescale_z(c->d, c->L));
-  for (int i = 0; i < 2; ++i) LAUNCH(c, launch_matvec_timing(c->d, c->L));
-  HIP_TRY(c, hipEventRecord(e0, c->stream));
-  for (int i = 0; i < reps; ++i) LAUNCH(c, launch_matvec_timing(c->d, c->L));
-  HIP_TRY(c, hipEventRecord(e1, c->stream));
-  HIP_TRY(c, hipEventSynchronize(e1));
-  float f = 0.f;
-  HIP_TRY(c, hipEventElapsedTime(&f, e0, e1));
   c->event_pool.push_back(e0);
   c->event_pool.push_back(e1);
+  if (c->d.implicit) LAUNCH(c, launch_prescale_z(c->d, c->L));
+  hipGraph_t g = nullptr;
+  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < reps && le == hipSuccess; ++i) le = launch_matvec_timing(c->d, c->L);
+  const hipError_t ee = hipStreamEndCapture(c->stream, &g);
+  if (le != hipSuccess || ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(c, SQRTBA_E_HIP, "product capture: %s", hipGetErrorString(le != hipSuccess ? le : ee));
+  }
+  hipGraphExec_t ge = nullptr;
+  hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(c, SQRTBA_E_HIP, "product graph instantiate: %s", hipGetErrorString(e));
+  e = hipGraphLaunch(ge, c->stream);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+  if (e == hipSuccess) e = hipGraphLaunch(ge, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float f = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+  (void)hipGraphExecDestroy(ge);
+  if (e != hipSuccess) return fail(c, SQRTBA_E_HIP, "product timing: %s", hipGetErrorString(e));
   *ms = (double)f / reps;
   return SQRTBA_OK;
 }
