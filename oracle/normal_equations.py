@@ -205,12 +205,18 @@ def reduced_system_operator(lin: Linearization, lam: float) -> ReducedOperator:
     # b~ = b_p - H_pl w; diagonal blocks: per observation J_p^T J_p - G (H_ll + lam I)^-1 G^T, G = J_p^T J_l
     b = bp
     blocks = np.zeros((lin.n_cams, 81))
-    for s, e in _chunks(n):
+    for s, e in _chunks(n, 1 << 15):  # (m, 9, 9) temporaries of a few MB
         A, L = Jps[s:e], Jls[s:e]
         b -= _sum_by(lin.ci[s:e], np.einsum("nki,nk->ni", A, np.einsum("nij,nj->ni", L, w[lin.pi[s:e]])), lin.n_cams)
-        At = np.swapaxes(A, 1, 2)
-        G = At @ L
-        term = At @ A - (G @ inv[lin.pi[s:e]]) @ np.swapaxes(G, 1, 2)
+        # per observation (two rows): J_p^T J_p, G = J_p^T J_l and G Hinv G^T, written
+        # out over the two rows and the three landmark columns
+        G = A[:, 0, :, None] * L[:, 0, None, :] + A[:, 1, :, None] * L[:, 1, None, :]  # (m, 9, 3)
+        Hi = inv[lin.pi[s:e]]
+        GH = G[:, :, 0, None] * Hi[:, None, 0, :] + G[:, :, 1, None] * Hi[:, None, 1, :] + \
+            G[:, :, 2, None] * Hi[:, None, 2, :]  # G Hinv, (m, 9, 3)
+        term = (A[:, 0, :, None] * A[:, 0, None, :] + A[:, 1, :, None] * A[:, 1, None, :]
+                - (GH[:, :, 0, None] * G[:, None, :, 0] + GH[:, :, 1, None] * G[:, None, :, 1]
+                   + GH[:, :, 2, None] * G[:, None, :, 2]))
         blocks += _sum_by(lin.ci[s:e], term.reshape(-1, 81), lin.n_cams)
     blocks = blocks.reshape(-1, 9, 9) + lam * np.eye(9)[None]
     return ReducedOperator(lam, lin.n_cams, lin.n_points, lin.ci, lin.pi, Jps, Jls, inv, bl, b.reshape(-1), blocks)
