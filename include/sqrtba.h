@@ -290,12 +290,13 @@ int32_t sqrtba_debug_rhs(sqrtba_ctx* ctx, float* rhs);
  * sqrtba_debug_rcs_matvec for ONE vector, with DEVICE pointers v[9 n_cams] and
  * out[9 n_cams] (scaled coordinates, out = (B^T B + lambda I) v), enqueued on the
  * context's stream without synchronizing.  It allocates nothing: the product's
- * per-observation outputs and row-block partials go to a static device array
+ * scaled input (12 elements per camera), per-observation outputs and row-block
+ * partials go to a static device array
  * of SQRTBA_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
  * the process ends (looked up at sqrtba_create).  Every call on a GPU shares
  * that array: calls that overlap on one GPU (two streams, two contexts, two
  * threads) race.  Explicit landmark blocks only (SQRTBA_E_UNSUPPORTED for the
- * other forms); a problem whose outputs and partials exceed the array is
+ * other forms); a problem whose scratch exceeds the array is
  * SQRTBA_E_UNSUPPORTED.  Needs damp. */
 #define SQRTBA_NOALLOC_SCRATCH_BYTES (64ull << 20)
 int32_t sqrtba_rcs_matvec_noalloc(sqrtba_ctx* ctx, const float* v, float* out);

@@ -1837,7 +1837,7 @@ int32_t SQRTBA_API(rcs_matvec_noalloc)(sqrtba_ctx* c, const real* v, real* out) 
   if (!c || !v || !out) return SQRTBA_E_INVALID;
   if (!c->damped) return fail(c, SQRTBA_E_STATE, "rcs_matvec_noalloc needs damp");
   if (c->opt.landmark_blocks != 0) return fail(c, SQRTBA_E_UNSUPPORTED, "rcs_matvec_noalloc: explicit landmark blocks only");
-  const uint64_t need = sizeof(real) * (uint64_t)(noalloc_out_elems(c->h.z_floats) + c->h.hz_floats);
+  const uint64_t need = sizeof(real) * (uint64_t)noalloc_elems(c->h.NC, c->h.z_floats, c->h.hz_floats);
   if (need > NOALLOC_SCRATCH_BYTES)
     return fail(c, SQRTBA_E_UNSUPPORTED, "rcs_matvec_noalloc: the product needs %llu bytes of scratch, the limit is %llu",
                 (unsigned long long)need, (unsigned long long)NOALLOC_SCRATCH_BYTES);
@@ -2212,7 +2212,7 @@ int time_products(sqrtba_ctx* c, int reps, double* ms) {
   if (!e0 || !e1) return fail(c, SQRTBA_E_HIP, "no events");
   c->event_pool.push_back(e0);
   c->event_pool.push_back(e1);
-  if (c->d.implicit) LAUNCH(c, launch_prescale_z(c->d, c->L));
+  LAUNCH(c, launch_prescale_z(c->d, c->L));
   hipGraph_t g = nullptr;
   HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;

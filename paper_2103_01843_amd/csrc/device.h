@@ -112,7 +112,7 @@ struct Dev {
   real* vr;
   real* vz;
   real* vzs;     // NC * 12: S z per camera, 9 elements and 3 zero pad (4-element aligned), kept by the
-                  // PCG kernels for the implicit product's gather
+                  // PCG kernels for the products' gather (outside PCG: S of the vector to multiply)
   real* vp;
   real* vq;
   real* vb;      // right-hand side b~
@@ -221,18 +221,21 @@ hipError_t launch_commit(const Dev& d, const Launch& L);
 hipError_t launch_matvec_only(const Dev& d, const Launch& L, const real* v_scaled, real* out);
 
 // Scratch of the no-allocation product (noalloc.hip): a static device array of
-// this many bytes per device, holding the product's per-observation outputs
-// (rounded up to 64 elements) and then its row-block partials.
+// this many bytes per device, holding the scaled input vector (12 elements per
+// camera), the product's per-observation outputs and then its row-block
+// partials, each part rounded up to 64 elements.
 constexpr uint64_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
 // Device address of the array on `device` (which must be current), looked up
 // once per device and kept.
 hipError_t noalloc_scratch(int device, void** out);
 int64_t noalloc_out_elems(int64_t out_elems);
+// Elements of the array one call uses (cameras, output and row-block partial elements).
+int64_t noalloc_elems(int64_t n_cams, int64_t out_elems, int64_t partial_elems);
 // launch_matvec_only with the product's scratch in the array at scratch_ptr.
 hipError_t launch_matvec_noalloc(const Dev& d, const Launch& L, void* scratch_ptr, int64_t out_elems,
                                  const real* v, real* out);
 hipError_t launch_matvec_timing(const Dev& d, const Launch& L);  // product of z over all active landmarks
-// implicit blocks: S z into vzs once, before timed launch_matvec_timing calls (which then read it)
+// S z into vzs once, before timed launch_matvec_timing calls (which then read it)
 hipError_t launch_prescale_z(const Dev& d, const Launch& L);
 hipError_t launch_debug_linearization(const Dev& d, const Launch& L, real* r, real* Jp, real* Jl);
 

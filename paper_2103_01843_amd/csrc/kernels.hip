@@ -901,20 +901,21 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
 // ----------------------------------------------------- kernel (c): matvec
 
 // Gather of the landmark's slice of the scaled direction vector for the 4
-// columns of column group g: p'[c] = s[cam, m] * v[cam, m].  Columns past 9k
-// read a valid entry and give 0 (no conditional loads).
-__device__ __forceinline__ real4 gather_cols(const Dev& d, const real* __restrict__ v, int obs0, int k, int g) {
+// columns of column group g: p'[c] = (S v)[cam, m], read from vs, which holds
+// S v with 12 elements per camera (9 values and 3 pad, as vzs).  Columns past
+// 9k read a valid entry and give 0 (no conditional loads).
+__device__ __forceinline__ real4 gather_cols(const Dev& d, const real* __restrict__ vs, int obs0, int k, int g) {
   const int n = 9 * k;
   const int c0 = min(4 * g, n - 1), c3 = min(4 * g + 3, n - 1);
   const int oa = (unsigned)c0 / 9u, ob = (unsigned)c3 / 9u;  // at most two observations
-  const int ca = 9 * d.obs_cam[obs0 + oa], cb = 9 * d.obs_cam[obs0 + ob];
+  const int ca = 12 * d.obs_cam[obs0 + oa], cb = 12 * d.obs_cam[obs0 + ob];
   real out[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int c = min(4 * g + q, n - 1);
     const int o = (unsigned)c / 9u;
     const int idx = (o == oa ? ca : cb) + (c - 9 * o);
-    out[q] = (4 * g + q < n) ? d.s_cam[idx] * v[idx] : 0.f;
+    out[q] = (4 * g + q < n) ? vs[idx] : 0.f;
   }
   return make_real4(out[0], out[1], out[2], out[3]);
 }
@@ -1616,7 +1617,7 @@ __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, re
     const int g = lane + TEAM * j;
     pv[j] = make_real4(0.f, 0.f, 0.f, 0.f);
     if (g < G) {
-      pv[j] = gather_cols(d, d.vx, obs0, k, g);
+      pv[j] = gather_cols(d, d.vzs, obs0, k, g);
       const real4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
       real a[3], b[3];
       a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b);
@@ -1684,7 +1685,7 @@ __device__ __forceinline__ void backsub_large(const Dev& d, int slot, double* pr
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
     const int g = lane + 64 * j;
-    pv[j] = g < G ? gather_cols(d, d.vx, obs0, k, g) : make_real4(0.f, 0.f, 0.f, 0.f);
+    pv[j] = g < G ? gather_cols(d, d.vzs, obs0, k, g) : make_real4(0.f, 0.f, 0.f, 0.f);
   }
   const real* rho = d.rhoB + 2 * (size_t)obs0;
   double pred = 0.0;
@@ -2229,7 +2230,8 @@ __global__ __launch_bounds__(WG) void k_matvec_implicit(Dev d, ImplGrid m) {
   impl_dispatch(m, MatvecImplF<PCG>{d});
 }
 
-// vzs = S v (12 floats per camera, the pad stays zero) for a product outside PCG.
+// vzs = S v (12 floats per camera, the pad stays zero): the gathered vector of a
+// product outside PCG, and S dx_p for the explicit back-substitution.
 __global__ __launch_bounds__(WG) void k_prescale(Dev d, const real* v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 9 * d.NC) return;
@@ -2892,28 +2894,25 @@ static void launch_small(const Dev& d, const Launch& L, const ClassGrid& m, int 
 // of the row-block partials.
 template <bool PCG>
 static hipError_t launch_matvec(const Dev& d, const Launch& L, const real* v) {
-  if (d.sc) {  // product with the assembled reduced matrix into vy (S z as for implicit blocks)
-    if (!PCG && v && d.NC) {
-      hipLaunchKernelGGL(k_prescale, dim3(nblocks(9 * d.NC, WG)), dim3(WG), 0, L.stream, d, v);
-      LAUNCH_CHECK();
-    }
+  // every form gathers S v from vzs: in PCG the PCG kernels keep vzs = S z;
+  // otherwise it is formed from v here (v == nullptr: already formed)
+  if (!PCG && v && d.NC) {
+    hipLaunchKernelGGL(k_prescale, dim3(nblocks(9 * d.NC, WG)), dim3(WG), 0, L.stream, d, v);
+    LAUNCH_CHECK();
+  }
+  if (d.sc) {  // product with the assembled reduced matrix into vy
     if (d.NC) hipLaunchKernelGGL(k_sc_matvec<PCG>, dim3(d.NC), dim3(64), 0, L.stream, d);
     LAUNCH_CHECK();
     return hipSuccess;
   }
   if (d.implicit) {
-    // in PCG the update kernels keep vzs = S z; otherwise it is formed from v here
-    // (v == nullptr: already formed)
-    if (!PCG && v && d.NC) {
-      hipLaunchKernelGGL(k_prescale, dim3(nblocks(9 * d.NC, WG)), dim3(WG), 0, L.stream, d, v);
-      LAUNCH_CHECK();
-    }
     int n = 0;
     const ImplGrid m = impl_grid(L, &n);
     if (n) hipLaunchKernelGGL(k_matvec_implicit<PCG>, dim3(n), dim3(WG), 0, L.stream, d, m);
     LAUNCH_CHECK();
     return hipSuccess;
   }
+  v = d.vzs;
   const bool rows = L.rows_n > 0 && L.hjobs > 0;
   const bool side = rows && L.huge_side && L.side && L.fork && L.join;
   const hipStream_t hs = side ? L.side : L.stream;
@@ -2966,7 +2965,7 @@ hipError_t launch_pcg_init(const Dev& d, const Launch& L) {
   return hipSuccess;
 }
 
-hipError_t launch_matvec(const Dev& d, const Launch& L) { return launch_matvec<true>(d, L, d.vz); }
+hipError_t launch_matvec(const Dev& d, const Launch& L) { return launch_matvec<true>(d, L, nullptr); }
 
 hipError_t launch_pcg_vector(const Dev& d, const Launch& L) {
   hipLaunchKernelGGL(k_pcg_q, dim3(d.NC), dim3(WG), 0, L.stream, d);
@@ -3004,6 +3003,9 @@ hipError_t launch_backsub(const Dev& d, const Launch& L) {
     LAUNCH_CHECK();
     return hipSuccess;
   }
+  // the landmark kernels gather S dx_p from vzs
+  if (d.NC) hipLaunchKernelGGL(k_prescale, dim3(nblocks(9 * d.NC, WG)), dim3(WG), 0, L.stream, d, d.vx);
+  LAUNCH_CHECK();
   int n = 0;
   const ClassGrid m = class_grid(L, &n);
   const bool side = w[5].slots && n && L.side && L.fork && L.join;
@@ -3031,9 +3033,7 @@ hipError_t launch_commit(const Dev& d, const Launch& L) {
   return hipSuccess;
 }
 
-hipError_t launch_matvec_timing(const Dev& d, const Launch& L) {
-  return launch_matvec<false>(d, L, d.implicit ? nullptr : d.vz);
-}
+hipError_t launch_matvec_timing(const Dev& d, const Launch& L) { return launch_matvec<false>(d, L, nullptr); }
 
 hipError_t launch_prescale_z(const Dev& d, const Launch& L) {
   if (d.NC) hipLaunchKernelGGL(k_prescale, dim3(nblocks(9 * d.NC, WG)), dim3(WG), 0, L.stream, d, d.vz);

@@ -1,5 +1,6 @@
 // The reduced-camera-system product without allocation: the scratch of the
-// product kernels (per-observation outputs and row-block partials) lives in a
+// product kernels (the scaled input vector, per-observation outputs and
+// row-block partials) lives in a
 // file-scope device array instead of the context's workspace, so the entry
 // point that uses it (sqrtba_rcs_matvec_noalloc) calls no allocator and can be
 // used under HIP graph capture or in loops that must not allocate.
@@ -46,10 +47,15 @@ hipError_t noalloc_scratch(int device, void** out) {
 
 int64_t noalloc_out_elems(int64_t out_elems) { return (out_elems + 63) & ~int64_t(63); }
 
+int64_t noalloc_elems(int64_t n_cams, int64_t out_elems, int64_t partial_elems) {
+  return noalloc_out_elems(12 * n_cams) + noalloc_out_elems(out_elems) + partial_elems;
+}
+
 hipError_t launch_matvec_noalloc(const Dev& d, const Launch& L, void* scratch_ptr, int64_t out_elems,
                                  const real* v, real* out) {
   Dev s = d;
-  s.obsbuf = static_cast<real*>(scratch_ptr);
+  s.vzs = static_cast<real*>(scratch_ptr);  // pads are never read
+  s.obsbuf = s.vzs + noalloc_out_elems(12 * (int64_t)d.NC);
   s.zpart = s.obsbuf + noalloc_out_elems(out_elems);
   // the outputs of problems the product skips (inactive ones) read as zero, not
   // as what the previous call left in the shared array
