@@ -110,6 +110,14 @@ def _golden(cfg: int, lm_iters: int):
     return gold if gold.get("lm_iters") == lm_iters else None
 
 
+def _cores_used(cpu0: float, wall0: float) -> dict:
+    """Threads the oracle actually kept busy since (cpu0, wall0): its process CPU
+    time over the wall time (numpy's element-wise and gather steps run on one
+    thread, BLAS calls on the pool)."""
+    cpu, wall = time.process_time() - cpu0, time.perf_counter() - wall0
+    return {"cores": max(1, round(cpu / wall)) if wall > 0 else 1, "cpu_s": cpu, "wall_s": wall}
+
+
 def cpu_baseline(problem, cfg: int, f_taus, lm_iters: int, budget_s: float = 30.0):
     """The FP64 oracle (numpy/scipy, as it is) timed on the host's cores.
 
@@ -137,20 +145,20 @@ def cpu_baseline(problem, cfg: int, f_taus, lm_iters: int, budget_s: float = 30.
     p = problem
     if cfg == 1:
         f_tau = f_taus[0][2]
-        t0 = time.perf_counter()
+        t0, c0 = time.perf_counter(), time.process_time()
         bk = oracle.build_bookkeeping(p.n_cams, p.n_points, p.obs_cam, p.obs_pt, p.obs_uv)
         res = oracle.lm_solve(p.cameras, p.points, p.obs_cam, p.obs_pt, p.obs_uv, oracle.LMOptions(max_iters=lm_iters),
                               bk, progress=lambda h: h["accepted"] and h["new_cost"] <= f_tau)
         reached = res.status == "stopped"
         h = res.history[-1]
-        return {**base, "value": h["t"] if reached else None, "cores": 1,
+        return {**base, "value": h["t"] if reached else None, **_cores_used(c0, t0),
                 "sample": (f"the oracle's LM loop (assembled Schur complement, block-Jacobi PCG) on the whole workload "
                            f"until its first accepted attempt at or below the 1% threshold: {res.iterations} attempts, "
                            f"{sum(x['pcg_iters'] for x in res.history)} PCG iterations, measured, "
                            f"{time.perf_counter() - t0:.1f} s including bookkeeping")}
     if cfg == 2:
         probs = split_batch(p)
-        t0 = time.perf_counter()
+        t0, c0 = time.perf_counter(), time.process_time()
         spent, obs_done, n_done = 0.0, 0, 0
         for i, q in enumerate(probs):
             f_tau = f_taus[i][2]
@@ -158,13 +166,13 @@ def cpu_baseline(problem, cfg: int, f_taus, lm_iters: int, budget_s: float = 30.
                                   oracle.LMOptions(max_iters=lm_iters),
                                   progress=lambda h, f=f_tau: h["accepted"] and h["new_cost"] <= f)
             if res.status != "stopped":
-                return {**base, "value": None, "cores": 1, "sample": f"problem {i} did not reach its threshold"}
+                return {**base, "value": None, **_cores_used(c0, t0), "sample": f"problem {i} did not reach its threshold"}
             spent += res.history[-1]["t"]
             obs_done += q.n_obs
             n_done += 1
             if time.perf_counter() - t0 > budget_s:
                 break
-        return {**base, "value": spent * p.n_obs / obs_done, "cores": 1,
+        return {**base, "value": spent * p.n_obs / obs_done, **_cores_used(c0, t0),
                 "sample": (f"the oracle's LM loop on the first {n_done} of {len(probs)} problems, each until it "
                            f"reaches its own 1% threshold (measured {spent:.1f} s over {obs_done} observations), "
                            f"scaled to all {p.n_obs} observations")}
@@ -181,12 +189,12 @@ def cpu_baseline(problem, cfg: int, f_taus, lm_iters: int, budget_s: float = 30.
             break
         n_lin += 1 if h["accepted"] else 0
     if not reached:
-        return {**base, "value": None, "cores": 1, "sample": "the stored oracle run never reaches the threshold"}
+        return {**base, "value": None, "cores": None, "sample": "the stored oracle run never reaches the threshold"}
     # prefix of the landmarks holding about 1M observations
     n_sub = int(np.searchsorted(np.cumsum(np.bincount(p.obs_pt, minlength=p.n_points)), 1_000_000)) + 1
     m = p.obs_pt < n_sub
     t = {}
-    ta = time.perf_counter()
+    ta, ca = time.perf_counter(), time.process_time()
     bk = oracle.build_bookkeeping(p.n_cams, n_sub, p.obs_cam[m], p.obs_pt[m], p.obs_uv[m])
     st = oracle.state_from_bal(p.cameras, p.points[:n_sub])
     tb = time.perf_counter()
@@ -203,11 +211,12 @@ def cpu_baseline(problem, cfg: int, f_taus, lm_iters: int, budget_s: float = 30.
     oracle.model_decrease(lin, res.x, dxl)
     cost_of(oracle.apply_update(st, res.x.reshape(-1, 9) * lin.sp, dxl.reshape(-1, 3) * lin.sl), bk, p.obs_uv[m])
     t["back_substitution_and_cost"] = time.perf_counter() - tb
-    sample_s = time.perf_counter() - ta
+    used = _cores_used(ca, ta)
+    sample_s = used["wall_s"]
     scale = p.n_obs / float(m.sum())
     est = scale * (n_lin * t["linearize"] + n_att * (t["reduced_system"] + t["back_substitution_and_cost"])
                    + n_pcg * t["pcg_iteration"])
-    return {**base, "value": est, "cores": 1,
+    return {**base, "value": est, **used,
             "sample_stage_s": t, "sample_obs": int(m.sum()), "scale_by_obs": scale,
             "sample": (f"the oracle's first attempt on the first {n_sub} landmarks ({int(m.sum())} of {p.n_obs} "
                        f"observations, {sample_s:.1f} s: linearize, Schur complement applied to vectors with its "
@@ -333,10 +342,10 @@ def main():
                     help="skip the FP64 solve of the same workload (reported as sqrt_ba_64)")
     ap.add_argument("--no-sc", action="store_true",
                     help="skip the explicit FP32 Schur-complement comparator (landmark_blocks = 2)")
-    ap.add_argument("--tuning", default=None, metavar="EDGE,ROWS,SIDE,SEP,BATCH,PERSIST",
+    ap.add_argument("--tuning", default=None, metavar="EDGE,ROWS,SIDE,SEP,BATCH,PERSIST[,NT]",
                     help="fixed product bucket edge and launch shapes (rows_min_k, huge_rows, huge_side, "
-                         "large_separate, small_rows, persist_wgs) instead of autotuning, e.g. for counter runs "
-                         "under a profiler")
+                         "large_separate, small_rows, persist_wgs, and optionally stream_loads, else 0) instead "
+                         "of autotuning, e.g. for counter runs under a profiler")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -374,8 +383,12 @@ def main():
     log(f"uploaded: workspace {ctx.workspace_bytes() / 1e9:.2f} GB in {upload_s:.2f} s (host bookkeeping + PCIe)")
     tuning = {"shape": ctx.get_tuning(), "autotuned": False}
     if args.tuning:
-        keys = ["rows_min_k", "huge_rows", "huge_side", "large_separate", "small_rows", "persist_wgs"]
-        ctx.set_tuning(**dict(zip(keys, (int(x) for x in args.tuning.split(",")))))
+        keys = ["rows_min_k", "huge_rows", "huge_side", "large_separate", "small_rows", "persist_wgs",
+                "stream_loads"]
+        vals = [int(x) for x in args.tuning.split(",")]
+        if len(vals) not in (6, 7):
+            raise SystemExit("--tuning takes 6 or 7 comma-separated integers")
+        ctx.set_tuning(**dict(zip(keys, vals + [0] * (7 - len(vals)))))
         tuning = {"shape": ctx.get_tuning(), "autotuned": False}
     elif blocks == 1:
         tuning["note"] = "the launch shapes belong to the explicit-block product; the implicit product has one"

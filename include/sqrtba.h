@@ -429,7 +429,7 @@ int32_t sqrtba_restore_state(sqrtba_ctx* ctx);
 /* ---- launch shapes of the PCG product and their autotuner ---- */
 
 /* The product runs size-bucketed kernels (landmarks by observation count k).
- * These are its tunable bucket edge and launch shapes.  None of them changes
+ * These are its tunable bucket edge, launch shapes and load policy.  None of them changes
  * the arithmetic except rows_min_k and huge_rows, which decide how the rows
  * of the largest blocks are grouped before their partial products are added. */
 typedef struct {
@@ -445,6 +445,10 @@ typedef struct {
   int32_t small_rows;     /* rows per batch for k <= 28: 4 or 8 */
   int32_t persist_wgs;    /* 0: one workgroup per block of small landmarks; 1024, 2048
                              or 4096: a persistent launch of that many workgroups */
+  int32_t stream_loads;   /* 1: the row-block and four-wavefront landmark kernels read the
+                             blocks with non-temporal loads (no cache allocation), which
+                             helps when the blocks are much larger than the last-level
+                             cache and hurts when they fit in it; 0: ordinary loads */
 } sqrtba_tuning;
 
 typedef struct {

@@ -817,6 +817,7 @@ int upload(sqrtba_ctx* c) {
   TRY(upload_vec(c, d.hz_off, h.hz_off));
   TRY(upload_vec(c, d.cam_stats, h.cam_stats));
   c->active.assign(h.P, 1);
+  d.all_active = 1;
   TRY(upload_vec(c, d.active, c->active));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->L.stream = c->stream;
@@ -832,6 +833,7 @@ int upload(sqrtba_ctx* c) {
   c->L.large_sep = h.wc[4].slots >= 256;
   c->L.mv_rbs = 0;
   c->L.persist = 0;
+  c->L.nt = 0;
   TRY(set_row_blocks(c, class_kmax(4) + 1, HUGE_ROWS_MIN));
   if (!c->side) {
     HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
@@ -944,6 +946,7 @@ int readback(sqrtba_ctx* c, const T* dev, T* out, bool sync = true) {
 
 int set_active_mask(sqrtba_ctx* c, const std::vector<uint8_t>& m) {
   c->active = m;
+  c->d.all_active = std::all_of(m.begin(), m.end(), [](uint8_t a) { return a != 0; }) ? 1 : 0;
   HIP_TRY(c, hipMemcpyAsync(c->d.active, c->active.data(), c->active.size(), hipMemcpyHostToDevice, c->stream));
   return SQRTBA_OK;
 }
@@ -2174,7 +2177,8 @@ bool valid_tuning(const sqrtba_tuning& t) {
   const int r = t.huge_rows, e = t.rows_min_k, p = t.persist_wgs;
   return (r == 64 || r == 128 || r == 256 || r == 512 || r == 1024) && (e == 114 || e == 61 || e == 29) &&
          (t.huge_side == 0 || t.huge_side == 1) && (t.large_separate == 0 || t.large_separate == 1) &&
-         (t.small_rows == 4 || t.small_rows == 8) && (p == 0 || p == 1024 || p == 2048 || p == 4096);
+         (t.small_rows == 4 || t.small_rows == 8) && (p == 0 || p == 1024 || p == 2048 || p == 4096) &&
+         (t.stream_loads == 0 || t.stream_loads == 1);
 }
 
 sqrtba_tuning current_tuning(const sqrtba_ctx* c) {
@@ -2185,6 +2189,7 @@ sqrtba_tuning current_tuning(const sqrtba_ctx* c) {
   t.large_separate = c->L.large_sep;
   t.small_rows = c->L.mv_rbs ? 8 : 4;
   t.persist_wgs = c->L.persist;
+  t.stream_loads = c->L.nt;
   return t;
 }
 
@@ -2194,6 +2199,7 @@ int apply_tuning(sqrtba_ctx* c, const sqrtba_tuning& t) {
   c->L.large_sep = t.large_separate;
   c->L.mv_rbs = t.small_rows == 8 ? 1 : 0;
   c->L.persist = t.persist_wgs;
+  c->L.nt = t.stream_loads;
   if (c->graph) {  // the captured PCG iterations hold the old launches
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
@@ -2284,14 +2290,15 @@ int32_t SQRTBA_API(autotune)(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, s
   sqrtba_tuning cur = current_tuning(c);
   double cur_ms = 0.0;
   TRY(measure(cur, &cur_ms));
-  auto try_field = [&](int sqrtba_tuning::*field, std::initializer_list<int> values) -> int {
+  // a candidate replaces the current shape when it is faster by more than `margin`
+  auto try_field = [&](int sqrtba_tuning::*field, std::initializer_list<int> values, double margin = 0.0) -> int {
     for (int v : values) {
       if (cur.*field == v) continue;
       sqrtba_tuning t = cur;
       t.*field = v;
       double ms = 0.0;
       TRY(measure(t, &ms));
-      if (ms < cur_ms) {
+      if (ms < (1.0 - margin) * cur_ms) {
         cur = t;
         cur_ms = ms;
       }
@@ -2311,6 +2318,9 @@ int32_t SQRTBA_API(autotune)(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, s
     if (c->L.n45 > c->L.rows_n) TRY(try_field(&sqrtba_tuning::large_separate, {0, 1}));
     TRY(try_field(&sqrtba_tuning::small_rows, {4, 8}));
     TRY(try_field(&sqrtba_tuning::persist_wgs, {0, 1024, 2048, 4096}));
+    // non-temporal loads only on a clear gain: a solve also rereads the blocks
+    // outside the product (preconditioner, back-substitution), which they may slow
+    if (c->L.n45 > 0) TRY(try_field(&sqrtba_tuning::stream_loads, {0, 1}, 0.01));
   }
   TRY(apply_tuning(c, cur));
   HIP_TRY(c, hipStreamSynchronize(c->stream));

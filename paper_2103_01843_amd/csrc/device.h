@@ -159,6 +159,7 @@ struct Dev {
   double* pcost;
   double* ppred;
   uint8_t* active;
+  int32_t all_active;  // 1: every problem is active (the per-landmark stages then skip the flag test)
   uint8_t* flag;     // generic per-problem mask (relinearize / accept)
   int32_t* chol_fail;  // count of preconditioner blocks that fell back to the diagonal
   float* feats;        // NC * 64 learned-preconditioner features of the last preconditioner build
@@ -195,6 +196,7 @@ struct Launch {
   int large_sep;   // the rest of k >= 29 as its own launch (else inside the small-class launch)
   int mv_rbs;      // row-batch set of the small classes (0: 4 rows, 1: 8 rows)
   int persist;     // > 0: the small-class launch is persistent with this many workgroups
+  int nt;          // 1: the row-block and four-wavefront landmark kernels use non-temporal loads
   int qjobs;       // row-chunk jobs of the class-5 QR (explicit blocks)
   hipStream_t stream;
   hipStream_t side;   // second stream for the largest landmarks (may be null)

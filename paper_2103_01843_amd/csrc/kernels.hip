@@ -735,15 +735,111 @@ __device__ __forceinline__ void damp_one(const Dev& d, int slot, int lane, const
 
 // Per landmark and observation (camera slab j of its B rows, 2k x 9):
 // G_j = B_j^T B_j (45 upper entries) and g_j = B_j^T rho_B, unscaled, written
-// to obsbuf[obs][0..53].  One lane owns one observation and walks the rows.
+// to obsbuf[obs][0..53]; one lane owns one observation and sums over the rows.
+// For k <= 28 each lane's rows arrive through LDS: the block is read from HBM
+// as a contiguous stream of float4s (one slab is 9 floats at a 36-byte
+// stride, so loading slabs directly touches every cache line nine times), and
+// the landmark's k x 54 outputs, contiguous in obsbuf, leave through LDS as
+// one stream of float2s.  The larger landmarks, a workgroup each, read their
+// slabs directly.
+
+// The rows of one landmark and observation slab.
+__device__ __forceinline__ void precond_rows(const real* __restrict__ rows, int W, const real* __restrict__ rho,
+                                             int n, real (&g)[54]) {
+  for (int i = 0; i < n; ++i) {
+    real b[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) b[e] = rows[i * W + e];
+    const real rr = rho[i];
+    int e = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      g[45 + a] += b[a] * rr;
+#pragma unroll
+      for (int c = a; c < 9; ++c) g[e++] += b[a] * b[c];
+    }
+  }
+}
+
+// Rows per staged batch, and the LDS of a workgroup of the small-class kernel:
+// every team stages PC_RB rows of its block, pc_loads float4s per lane (all
+// stored, those past the batch being copies that are never read; stride plus
+// 4 floats: 16-byte aligned, and the teams of a wavefront start on different
+// banks), then its k x 54 outputs.
+constexpr int PC_RB = sizeof(real) == 4 ? 8 : 4;
+__host__ __device__ constexpr int pc_loads(int cls) {
+  return (PC_RB * (((9 * class_kmax(cls) + 3) & ~3) >> 2) + class_team(cls) - 1) / class_team(cls);
+}
+__host__ __device__ constexpr int pc_team_stride(int cls) { return 4 * pc_loads(cls) * class_team(cls) + 4; }
+__host__ __device__ constexpr int pc_out_stride(int cls) { return 54 * class_kmax(cls) + 2; }
+__host__ __device__ constexpr int pc_lds(int cls) {
+  return (WG / class_team(cls)) * (pc_team_stride(cls) > pc_out_stride(cls) ? pc_team_stride(cls) : pc_out_stride(cls));
+}
+constexpr int PC_LDS_SMALL = pc_lds(0) > pc_lds(1) ? (pc_lds(0) > pc_lds(2) ? (pc_lds(0) > pc_lds(3) ? pc_lds(0) : pc_lds(3))
+                                                                           : (pc_lds(2) > pc_lds(3) ? pc_lds(2) : pc_lds(3)))
+                                                   : (pc_lds(1) > pc_lds(2) ? (pc_lds(1) > pc_lds(3) ? pc_lds(1) : pc_lds(3))
+                                                                           : (pc_lds(2) > pc_lds(3) ? pc_lds(2) : pc_lds(3)));
+
+// Classes 0..3: team TEAM of the workgroup takes slot s0 + team (the teams of
+// a workgroup belong to one class; slots past send, and landmarks of inactive
+// problems, do no work but join every barrier).  The batches run to the
+// largest k of the workgroup, its first slot's (slots are in decreasing k).
+template <int TEAM, int CLS>
+__device__ __forceinline__ void precond_team(const Dev& d, int s0, int send, real* lds) {
+  const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
+  const int slot = s0 + team;
+  // the block's rows are requested before the problem's flag is tested (a
+  // block of an inactive problem is read but not used)
+  const bool in = slot < send;
+  const int sl = in ? slot : s0;
+  const int prob = d.slot_prob[sl];
+  const int k = in ? d.slot_k[sl] : 0;
+  const int obs0 = d.slot_obs0[sl];
+  const int64_t boff = d.slot_boff[sl];
+  const int kmax = d.slot_k[s0];
+  const int W = width_of(k), G = W >> 2;
+  real* tb = lds + team * pc_team_stride(CLS);
+  const real4* __restrict__ B4 = reinterpret_cast<const real4*>(d.poolB + boff);
+  const real* __restrict__ rho = d.rhoB + 2 * (size_t)obs0;
+  constexpr int NL = pc_loads(CLS);
+  real g[54];
+#pragma unroll
+  for (int e = 0; e < 54; ++e) g[e] = 0.f;
+  for (int r0 = 0; r0 < 2 * kmax; r0 += PC_RB) {  // uniform over the workgroup
+    // every load is issued before the first LDS store, and every store is
+    // made (no branches to sink the loads into): a lane past the batch re-reads
+    // the batch's last float4 (in the block) into a slot that is never read
+    const int f0 = r0 * G, f1 = min(2 * k, r0 + PC_RB) * G, fl = max(f1 - 1, 0);
+    real4 t[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) t[j] = B4[min(f0 + lane + j * TEAM, fl)];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) reinterpret_cast<real4*>(tb)[lane + j * TEAM] = t[j];
+    __syncthreads();
+    if (lane < k) precond_rows(tb + 9 * lane, W, rho + r0, min(2 * k - r0, PC_RB), g);
+    __syncthreads();
+  }
+  const int kw = (d.all_active || d.active[prob]) ? k : 0;  // outputs of active problems only
+  real* ob = lds + team * pc_out_stride(CLS);
+  if (lane < kw) {
+#pragma unroll
+    for (int e = 0; e < 54; ++e) ob[54 * lane + e] = g[e];
+  }
+  __syncthreads();
+  real2* dst = reinterpret_cast<real2*>(d.obsbuf + (size_t)obs0 * 54);  // 8-byte aligned
+  for (int j = lane; j < 27 * kw; j += TEAM) dst[j] = reinterpret_cast<const real2*>(ob)[j];
+}
+
+// Classes 4 and 5: one lane per observation walks the rows of its slab.
 template <int TEAM>
 __device__ __forceinline__ void precond_one(const Dev& d, int slot, int lane) {
   const int prob = d.slot_prob[slot];
-  if (!d.active[prob]) return;
   const int k = d.slot_k[slot];
   const int obs0 = d.slot_obs0[slot];
+  const int64_t boff = d.slot_boff[slot];
+  if (!d.all_active && !d.active[prob]) return;
   const int W = width_of(k);
-  const real* B = d.poolB + d.slot_boff[slot];
+  const real* B = d.poolB + boff;
   const real* rho = d.rhoB + 2 * (size_t)obs0;
   for (int o = lane; o < k; o += TEAM) {
     real g[45], h[9];
@@ -920,6 +1016,20 @@ __device__ __forceinline__ real4 gather_cols(const Dev& d, const real* __restric
   return make_real4(out[0], out[1], out[2], out[3]);
 }
 
+// A float4 of a landmark block, with a non-temporal load when NT (streamed
+// once: no allocation in the caches, which keeps them for the other data of
+// the product when the blocks are much larger than the last-level cache).
+template <bool NT>
+__device__ __forceinline__ real4 load_block(const real4* p) {
+  if constexpr (NT) {
+    typedef real v4 __attribute__((ext_vector_type(4)));
+    const v4 v = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+    return make_real4(v.x, v.y, v.z, v.w);
+  } else {
+    return *p;
+  }
+}
+
 __device__ __forceinline__ real dot4(real4 a, real4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 
 __device__ __forceinline__ void axpy4(real4& z, real y, real4 b) {
@@ -999,7 +1109,7 @@ __device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, con
 // w+4(RS-1)); each lane owns up to NCG column groups (strided by 64).  The next
 // step's rows are requested before the current ones are reduced.  The 4
 // partial z vectors are summed through LDS in a fixed order.
-template <int NCG, int RS, bool PCG>
+template <int NCG, int RS, bool PCG, bool NT>
 __device__ __forceinline__ void matvec_large(const Dev& d, int slot, const real* v, real4 (*zred)[64]) {
   const int prob = d.slot_prob[slot];
   const int k = d.slot_k[slot];
@@ -1018,7 +1128,7 @@ __device__ __forceinline__ void matvec_large(const Dev& d, int slot, const real*
 #pragma unroll
       for (int j = 0; j < NCG; ++j) {
         b[i][j] = make_real4(0.f, 0.f, 0.f, 0.f);
-        if (64 * j < G) b[i][j] = B[(size_t)rr * G + min(lane + 64 * j, G - 1)];
+        if (64 * j < G) b[i][j] = load_block<NT>(&B[(size_t)rr * G + min(lane + 64 * j, G - 1)]);
       }
     }
   };
@@ -1088,7 +1198,7 @@ template <bool PCG, bool LARGE, int RBS>
 __device__ __forceinline__ void matvec_block(const Dev& d, const ClassGrid& m, int b, const real* v,
                                              real4 (*zred)[64]) {
   if constexpr (LARGE) {
-    if (b < m.nblk[0]) { matvec_large<4, MV_RS, PCG>(d, m.first[0] + b, v, zred); return; }
+    if (b < m.nblk[0]) { matvec_large<4, MV_RS, PCG, false>(d, m.first[0] + b, v, zred); return; }
     b -= m.nblk[0];
   }
   if (b < m.nblk[1]) { matvec_teams<64, mv_rb(RBS, 0), PCG>(d, m.first[1] + b * mv_per_wg(1), m.end[1], v); return; }
@@ -1114,10 +1224,10 @@ __global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, int nwork, co
 }
 
 // Class 4 on its own: one landmark per workgroup.
-template <bool PCG>
+template <bool PCG, bool NT>
 __global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int slot0, const real* v) {
   __shared__ real4 zred[4][64];
-  matvec_large<4, MV_RS, PCG>(d, slot0 + blockIdx.x, v, zred);
+  matvec_large<4, MV_RS, PCG, NT>(d, slot0 + blockIdx.x, v, zred);
 }
 
 // The largest landmarks (k at least the tuned edge, 29..512), split into blocks
@@ -1125,7 +1235,7 @@ __global__ __launch_bounds__(WG) void k_matvec_large(Dev d, int slot0, const rea
 // whole chip: job j (slot, row block) runs on one workgroup of four wavefronts
 // (wave w takes rows w, w+4, ... of the block) and writes its partial z for
 // the block; a landmark with a single block writes its outputs directly.
-template <bool PCG>
+template <bool PCG, bool NT>
 __global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, int rows, const real* v) {
   constexpr int NCG = 18;  // ceil(width_of(512) / 4 / 64)
   __shared__ real4 zred[4][64];
@@ -1153,7 +1263,7 @@ __global__ __launch_bounds__(WG) void k_matvec_rows(Dev d, int slot0, int rows, 
 #pragma unroll
     for (int j = 0; j < NCG; ++j) {
       b[j] = make_real4(0.f, 0.f, 0.f, 0.f);
-      if (lane + 64 * j < G) b[j] = row[64 * j];
+      if (lane + 64 * j < G) b[j] = load_block<NT>(&row[64 * j]);
     }
     real y = 0.f;
 #pragma unroll
@@ -1596,11 +1706,14 @@ __global__ __launch_bounds__(WG) void k_pcg_final(Dev d) {
 //   pred_l = -sum u (2 rho + u) + lambda |dx~_l|^2,   u = rows . (S dx_p, dx~_l).
 template <int TEAM, int NCG>
 __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, real* red4) {
+  // the landmark's metadata is requested at once; the problem's flag only when
+  // some problem is inactive
   const int prob = d.slot_prob[slot];
   const int lm = d.slot_lm[slot];
-  if (!d.active[prob]) return;
   const int k = d.slot_k[slot];
   const int obs0 = d.slot_obs0[slot];
+  const int64_t toff = d.slot_toff[slot], boff = d.slot_boff[slot];
+  if (!d.all_active && !d.active[prob]) return;
   const int W = width_of(k);
   const int G = W >> 2;
   const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
@@ -1608,8 +1721,8 @@ __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, re
   Givens6 Gv;
   real Rh[3][3], qrh[3], dr[3];
   damping_rotations(lmd, sqrt(lam), Gv, Rh, qrh, dr);
-  const real4* T = reinterpret_cast<const real4*>(d.poolT + d.slot_toff[slot]);
-  const real4* B = reinterpret_cast<const real4*>(d.poolB + d.slot_boff[slot]);
+  const real4* T = reinterpret_cast<const real4*>(d.poolT + toff);
+  const real4* B = reinterpret_cast<const real4*>(d.poolB + boff);
   real4 pv[NCG];
   real u0 = 0.f, u1 = 0.f, u2 = 0.f;
 #pragma unroll
@@ -1648,15 +1761,45 @@ __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, re
            (double)(ut2 * (2.f * qrh[2] + ut2)) + (double)lam * ((double)x0 * x0 + (double)x1 * x1 + (double)x2 * x2);
   }
   const real* rho = d.rhoB + 2 * (size_t)obs0;
-  for (int r = 0; r < 2 * k; ++r) {
-    real y = 0.f;
+  if constexpr (NCG == 1) {
+    // rows in batches of BS_RB, the next batch requested before the current one
+    // is reduced (rows past 2k re-read row 2k-1 and are not counted)
+    constexpr int BS_RB = 8;
+    const int n = 2 * k;
+    const real4* __restrict__ Bj = B + min(lane, G - 1);
+    real4 c[BS_RB];
 #pragma unroll
-    for (int j = 0; j < NCG; ++j) {
-      const int g = lane + TEAM * j;
-      if (g < G) y += dot4(B[(size_t)r * G + g], pv[j]);
+    for (int i = 0; i < BS_RB; ++i) c[i] = Bj[(size_t)min(i, n - 1) * G];
+    for (int r = 0; r < n; r += BS_RB) {
+      real4 nx[BS_RB];
+#pragma unroll
+      for (int i = 0; i < BS_RB; ++i) nx[i] = c[i];
+      if (r + BS_RB < n) {
+#pragma unroll
+        for (int i = 0; i < BS_RB; ++i) nx[i] = Bj[(size_t)min(r + BS_RB + i, n - 1) * G];
+      }
+      real y[BS_RB];
+#pragma unroll
+      for (int i = 0; i < BS_RB; ++i) y[i] = tsum<TEAM>(dot4(c[i], pv[0]), red4);
+      if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < BS_RB; ++i)
+          if (r + i < n) pred -= (double)(y[i] * (2.f * rho[r + i] + y[i]));
+      }
+#pragma unroll
+      for (int i = 0; i < BS_RB; ++i) c[i] = nx[i];
     }
-    y = tsum<TEAM>(y, red4);
-    if (lane == 0) pred -= (double)(y * (2.f * rho[r] + y));
+  } else {
+    for (int r = 0; r < 2 * k; ++r) {
+      real y = 0.f;
+#pragma unroll
+      for (int j = 0; j < NCG; ++j) {
+        const int g = lane + TEAM * j;
+        if (g < G) y += dot4(B[(size_t)r * G + g], pv[j]);
+      }
+      y = tsum<TEAM>(y, red4);
+      if (lane == 0) pred -= (double)(y * (2.f * rho[r] + y));
+    }
   }
   if (lane == 0) {
     const real* sl = lmd + LMD_SL;
@@ -1667,20 +1810,122 @@ __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, re
   }
 }
 
+// The B-row part of the predicted decrease over rows [rbeg, rend) for one
+// wavefront of a four-wavefront workgroup: wave w takes rows rbeg + w,
+// rbeg + w + 4, ... in steps of RS rows, the next step's rows requested before
+// the current ones are reduced (rows past rend re-read row rend-1 and are not
+// counted; lanes past the width read column group G-1 against p' = 0).  Lane 0
+// returns the wave's sum in row order.
+template <int NCG, int RS>
+__device__ __forceinline__ double backsub_b_rows(const real4* __restrict__ B, int G, const real4 (&pv)[NCG],
+                                                 const real* __restrict__ rho, int rbeg, int rend, int w, int lane) {
+  double pred = 0.0;
+  if (rbeg + w >= rend) return pred;  // uniform over the wavefront
+  auto load = [&](int r, real4 (&b)[RS][NCG]) {
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+      const int rr = min(r + 4 * i, rend - 1);
+#pragma unroll
+      for (int j = 0; j < NCG; ++j) {
+        b[i][j] = make_real4(0.f, 0.f, 0.f, 0.f);
+        if (64 * j < G) b[i][j] = B[(size_t)rr * G + min(lane + 64 * j, G - 1)];
+      }
+    }
+  };
+  real4 b[RS][NCG];
+  load(rbeg + w, b);
+  for (int r = rbeg + w; r < rend; r += 4 * RS) {
+    real4 nb[RS][NCG];
+    if (r + 4 * RS < rend) {
+      load(r + 4 * RS, nb);
+    } else {
+#pragma unroll
+      for (int i = 0; i < RS; ++i)
+#pragma unroll
+        for (int j = 0; j < NCG; ++j) nb[i][j] = b[i][j];
+    }
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+      real y = 0.f;
+#pragma unroll
+      for (int j = 0; j < NCG; ++j) y += dot4(b[i][j], pv[j]);
+      y = wave_sum_f(y);
+      if (lane == 0 && r + 4 * i < rend) pred -= (double)(y * (2.f * rho[r + 4 * i] + y));
+    }
+#pragma unroll
+    for (int i = 0; i < RS; ++i)
+#pragma unroll
+      for (int j = 0; j < NCG; ++j) b[i][j] = nb[i][j];
+  }
+  return pred;
+}
+
+// The damped top rows of a landmark on wave 0 of its workgroup: u = T^ p' by
+// the damping rotations of the undamped top rows, dx~_l, dx_l = S_l dx~_l
+// (written), and the top rows' share of the predicted decrease (lane 0).
+template <int NCG>
+__device__ __forceinline__ double backsub_top(const Dev& d, int slot, int prob, int lm, int G, const real4 (&pv)[NCG],
+                                              int lane) {
+  const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
+  const real lam = (real)d.lambda[prob];
+  Givens6 Gv;
+  real Rh[3][3], qrh[3], dr[3];
+  damping_rotations(lmd, sqrt(lam), Gv, Rh, qrh, dr);
+  const real4* T = reinterpret_cast<const real4*>(d.poolT + d.slot_toff[slot]);
+  real u0 = 0.f, u1 = 0.f, u2 = 0.f;
+#pragma unroll
+  for (int j = 0; j < NCG; ++j) {
+    const int g = lane + 64 * j;
+    if (g < G) {
+      const real4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
+      real a[3], b[3];
+      a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b);
+      u0 += a[0] * pv[j].x; u1 += a[1] * pv[j].x; u2 += a[2] * pv[j].x;
+      a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b);
+      u0 += a[0] * pv[j].y; u1 += a[1] * pv[j].y; u2 += a[2] * pv[j].y;
+      a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, b);
+      u0 += a[0] * pv[j].z; u1 += a[1] * pv[j].z; u2 += a[2] * pv[j].z;
+      a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, b);
+      u0 += a[0] * pv[j].w; u1 += a[1] * pv[j].w; u2 += a[2] * pv[j].w;
+    }
+  }
+  u0 = wave_sum_f(u0);
+  u1 = wave_sum_f(u1);
+  u2 = wave_sum_f(u2);
+  const real c0 = -(qrh[0] + u0), c1 = -(qrh[1] + u1), c2 = -(qrh[2] + u2);
+  const real x2 = c2 / Rh[2][2];
+  const real x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
+  const real x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
+  double top = 0.0;
+  if (lane == 0) {
+    const real ut0 = u0 + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
+    const real ut1 = u1 + Rh[1][1] * x1 + Rh[1][2] * x2;
+    const real ut2 = u2 + Rh[2][2] * x2;
+    top = -(double)(ut0 * (2.f * qrh[0] + ut0)) - (double)(ut1 * (2.f * qrh[1] + ut1)) -
+          (double)(ut2 * (2.f * qrh[2] + ut2)) + (double)lam * ((double)x0 * x0 + (double)x1 * x1 + (double)x2 * x2);
+    const real* sl = lmd + LMD_SL;
+    d.dxl[3 * (size_t)lm + 0] = sl[0] * x0;
+    d.dxl[3 * (size_t)lm + 1] = sl[1] * x1;
+    d.dxl[3 * (size_t)lm + 2] = sl[2] * x2;
+  }
+  return top;
+}
+
 // Large landmarks (one workgroup of 4 wavefronts): the B rows are split over
 // the wavefronts as in the product (wave w takes rows w, w+4, ...), with no
 // workgroup barrier per row; wave 0 also forms the damped top-row terms and
 // dx~_l.  The four partial predictions are added in a fixed order.
-template <int NCG>
+template <int NCG, int RS>
 __device__ __forceinline__ void backsub_large(const Dev& d, int slot, double* predw) {
   const int prob = d.slot_prob[slot];
   const int lm = d.slot_lm[slot];
-  if (!d.active[prob]) return;  // uniform over the workgroup
   const int k = d.slot_k[slot];
   const int obs0 = d.slot_obs0[slot];
+  const int64_t boff = d.slot_boff[slot];
+  if (!d.all_active && !d.active[prob]) return;  // uniform over the workgroup
   const int G = width_of(k) >> 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const real4* __restrict__ B = reinterpret_cast<const real4*>(d.poolB + d.slot_boff[slot]);
+  const real4* __restrict__ B = reinterpret_cast<const real4*>(d.poolB + boff);
   real4 pv[NCG];
 #pragma unroll
   for (int j = 0; j < NCG; ++j) {
@@ -1688,61 +1933,11 @@ __device__ __forceinline__ void backsub_large(const Dev& d, int slot, double* pr
     pv[j] = g < G ? gather_cols(d, d.vzs, obs0, k, g) : make_real4(0.f, 0.f, 0.f, 0.f);
   }
   const real* rho = d.rhoB + 2 * (size_t)obs0;
-  double pred = 0.0;
-  for (int r = w; r < 2 * k; r += 4) {
-    const real4* row = B + (size_t)r * G + lane;
-    real y = 0.f;
-#pragma unroll
-    for (int j = 0; j < NCG; ++j)
-      if (lane + 64 * j < G) y += dot4(row[64 * j], pv[j]);
-    y = wave_sum_f(y);
-    if (lane == 0) pred -= (double)(y * (2.f * rho[r] + y));
-  }
+  const double pred = backsub_b_rows<NCG, RS>(B, G, pv, rho, 0, 2 * k, w, lane);
   if (lane == 0) predw[w] = pred;
   if (w == 0) {
-    const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
-    const real lam = (real)d.lambda[prob];
-    Givens6 Gv;
-    real Rh[3][3], qrh[3], dr[3];
-    damping_rotations(lmd, sqrt(lam), Gv, Rh, qrh, dr);
-    const real4* T = reinterpret_cast<const real4*>(d.poolT + d.slot_toff[slot]);
-    real u0 = 0.f, u1 = 0.f, u2 = 0.f;
-#pragma unroll
-    for (int j = 0; j < NCG; ++j) {
-      const int g = lane + 64 * j;
-      if (g < G) {
-        const real4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
-        real a[3], b[3];
-        a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b);
-        u0 += a[0] * pv[j].x; u1 += a[1] * pv[j].x; u2 += a[2] * pv[j].x;
-        a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b);
-        u0 += a[0] * pv[j].y; u1 += a[1] * pv[j].y; u2 += a[2] * pv[j].y;
-        a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, b);
-        u0 += a[0] * pv[j].z; u1 += a[1] * pv[j].z; u2 += a[2] * pv[j].z;
-        a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, b);
-        u0 += a[0] * pv[j].w; u1 += a[1] * pv[j].w; u2 += a[2] * pv[j].w;
-      }
-    }
-    u0 = wave_sum_f(u0);
-    u1 = wave_sum_f(u1);
-    u2 = wave_sum_f(u2);
-    const real c0 = -(qrh[0] + u0), c1 = -(qrh[1] + u1), c2 = -(qrh[2] + u2);
-    const real x2 = c2 / Rh[2][2];
-    const real x1 = (c1 - Rh[1][2] * x2) / Rh[1][1];
-    const real x0 = (c0 - Rh[0][1] * x1 - Rh[0][2] * x2) / Rh[0][0];
-    if (lane == 0) {
-      const real ut0 = u0 + Rh[0][0] * x0 + Rh[0][1] * x1 + Rh[0][2] * x2;
-      const real ut1 = u1 + Rh[1][1] * x1 + Rh[1][2] * x2;
-      const real ut2 = u2 + Rh[2][2] * x2;
-      const double top = -(double)(ut0 * (2.f * qrh[0] + ut0)) - (double)(ut1 * (2.f * qrh[1] + ut1)) -
-                         (double)(ut2 * (2.f * qrh[2] + ut2)) +
-                         (double)lam * ((double)x0 * x0 + (double)x1 * x1 + (double)x2 * x2);
-      const real* sl = lmd + LMD_SL;
-      d.dxl[3 * (size_t)lm + 0] = sl[0] * x0;
-      d.dxl[3 * (size_t)lm + 1] = sl[1] * x1;
-      d.dxl[3 * (size_t)lm + 2] = sl[2] * x2;
-      predw[4] = top;
-    }
+    const double top = backsub_top<NCG>(d, slot, prob, lm, G, pv, lane);
+    if (lane == 0) predw[4] = top;
   }
   __syncthreads();
   if (threadIdx.x == 0) d.lm_part[lm] = predw[4] + ((predw[0] + predw[1]) + (predw[2] + predw[3]));
@@ -1812,14 +2007,25 @@ __global__ __launch_bounds__(WG) void k_damp_huge(Dev d, int slot0, const uint8_
   damp_one<256>(d, slot0 + blockIdx.x, threadIdx.x, mask);
 }
 
-struct PrecondF {
-  const Dev& d;
-  template <int TEAM, int CLS>
-  __device__ __forceinline__ void run(int slot, int lane, int) const { precond_one<TEAM>(d, slot, lane); }
-};
+// Classes 0..3 of m (launch-order entries 1..4; entry 0 is unused).
+__global__ __launch_bounds__(WG) void k_precond_obs(Dev d, ClassGrid m) {
+  __shared__ __align__(16) real lds[PC_LDS_SMALL];
+  int b = blockIdx.x;
+  if (b < m.nblk[1]) { precond_team<64, 3>(d, m.first[1] + b * (WG / 64), m.end[1], lds); return; }
+  b -= m.nblk[1];
+  if (b < m.nblk[2]) { precond_team<32, 2>(d, m.first[2] + b * (WG / 32), m.end[2], lds); return; }
+  b -= m.nblk[2];
+  if (b < m.nblk[3]) { precond_team<16, 1>(d, m.first[3] + b * (WG / 16), m.end[3], lds); return; }
+  b -= m.nblk[3];
+  precond_team<8, 0>(d, m.first[4] + b * (WG / 8), m.end[4], lds);
+}
 
-__global__ __launch_bounds__(WG) void k_precond_obs(Dev d, ClassGrid m) { class_dispatch(m, PrecondF{d}); }
+// Class 4 (one workgroup per landmark).
+__global__ __launch_bounds__(WG) void k_precond_obs_large(Dev d, int slot0) {
+  precond_one<256>(d, slot0 + blockIdx.x, threadIdx.x);
+}
 
+// Class 5 (one workgroup per landmark, on the side stream).
 __global__ __launch_bounds__(WG) void k_precond_obs_huge(Dev d, int slot0) {
   precond_one<256>(d, slot0 + blockIdx.x, threadIdx.x);
 }
@@ -1831,7 +2037,7 @@ struct BacksubF {
   template <int TEAM, int CLS>
   __device__ __forceinline__ void run(int slot, int lane, int) const {
     if constexpr (TEAM == 256)
-      backsub_large<4>(d, slot, predw);
+      backsub_large<4, 2>(d, slot, predw);
     else
       backsub_one<TEAM, 1>(d, slot, lane, red4);
   }
@@ -1845,7 +2051,7 @@ __global__ __launch_bounds__(WG) void k_backsub(Dev d, ClassGrid m) {
 
 __global__ __launch_bounds__(WG) void k_backsub_huge(Dev d, int slot0) {
   __shared__ double predw[5];
-  backsub_large<18>(d, slot0 + blockIdx.x, predw);
+  backsub_large<18, 1>(d, slot0 + blockIdx.x, predw);
 }
 
 // ----------------------------------------------------- update and commit
@@ -2846,13 +3052,15 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
     return hipSuccess;
   }
   int n = 0;
-  const ClassGrid m = class_grid(L, &n);
-  const bool side = w[5].slots && n && L.side && L.fork && L.join;
+  const ClassGrid m = class_grid(L, &n, true);  // classes 0..3
+  const bool side = w[5].slots && (n || w[4].slots) && L.side && L.fork && L.join;
   hipError_t e = side_fork(L, side);
   if (e != hipSuccess) return e;
   if (w[5].slots)
     hipLaunchKernelGGL(k_precond_obs_huge, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d,
                        w[5].first_slot);
+  LAUNCH_CHECK();
+  if (w[4].slots) hipLaunchKernelGGL(k_precond_obs_large, dim3(w[4].slots), dim3(WG), 0, L.stream, d, w[4].first_slot);
   LAUNCH_CHECK();
   if (n) hipLaunchKernelGGL(k_precond_obs, dim3(n), dim3(WG), 0, L.stream, d, m);
   LAUNCH_CHECK();
@@ -2922,7 +3130,10 @@ static hipError_t launch_matvec(const Dev& d, const Launch& L, const real* v) {
       if (e == hipSuccess) e = hipStreamWaitEvent(L.side, L.fork, 0);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_matvec_rows<PCG>, dim3(L.hjobs), dim3(WG), 0, hs, d, 0, L.huge_rows, v);
+    if (L.nt)
+      hipLaunchKernelGGL((k_matvec_rows<PCG, true>), dim3(L.hjobs), dim3(WG), 0, hs, d, 0, L.huge_rows, v);
+    else
+      hipLaunchKernelGGL((k_matvec_rows<PCG, false>), dim3(L.hjobs), dim3(WG), 0, hs, d, 0, L.huge_rows, v);
     LAUNCH_CHECK();
     if (L.huge_rows < 2 * class_kmax(5))
       hipLaunchKernelGGL(k_matvec_combine<PCG>, dim3(L.rows_n), dim3(WG), 0, hs, d, 0, L.huge_rows);
@@ -2931,7 +3142,10 @@ static hipError_t launch_matvec(const Dev& d, const Launch& L, const real* v) {
   const int nlarge = L.n45 - L.rows_n;
   const bool sep = L.large_sep && nlarge > 0;
   if (sep) {
-    hipLaunchKernelGGL(k_matvec_large<PCG>, dim3(nlarge), dim3(WG), 0, L.stream, d, L.rows_n, v);
+    if (L.nt)
+      hipLaunchKernelGGL((k_matvec_large<PCG, true>), dim3(nlarge), dim3(WG), 0, L.stream, d, L.rows_n, v);
+    else
+      hipLaunchKernelGGL((k_matvec_large<PCG, false>), dim3(nlarge), dim3(WG), 0, L.stream, d, L.rows_n, v);
     LAUNCH_CHECK();
   }
   int n = 0;

@@ -65,7 +65,8 @@ STAGES = ["linearize", "marginalize", "damp", "precond", "matvec", "pcg_vector",
 
 class Tuning(C.Structure):
     _fields_ = [("rows_min_k", C.c_int32), ("huge_rows", C.c_int32), ("huge_side", C.c_int32),
-                ("large_separate", C.c_int32), ("small_rows", C.c_int32), ("persist_wgs", C.c_int32)]
+                ("large_separate", C.c_int32), ("small_rows", C.c_int32), ("persist_wgs", C.c_int32),
+                ("stream_loads", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
