@@ -639,8 +639,10 @@ def main():
             tr = json.load(f)
         if tr.get("kernels_sha") == kernels_hash():  # counters of the current kernels only
             traffic = tr.get("bytes_per_launch")
+            cur = ",".join(str(v) for v in tuning["shape"].values())
             traffic_note = (f"FETCH_SIZE x {tr['fetch_scale']:.3f} + WRITE_SIZE x {tr['write_scale']:.3f} per product, "
-                            f"launch shapes {tr['shape']}")
+                            f"counters taken with launch shapes {tr['shape']}"
+                            + ("" if tr["shape"] in (cur, "x", "default") else f" (this run's shapes: {cur})"))
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": traffic,
                 "kernel": (("the PCG product over all landmark blocks (k_matvec, plus k_matvec_large / "
