@@ -575,14 +575,25 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
   // phase 4: pose columns, Q^T J_p = J_p - V M with M = T^T (V^T J_p).  Lane
   // g-groups are g = lane + TEAM jg; for a workgroup team the rows are the
   // outer loop, so every output row (up to 18 KB) is written whole, in order.
+  // A workgroup team with one column group per lane (k <= 113: G <= 255)
+  // would leave the lanes past G idle through the row loop; it takes
+  // rstep = 256 / GP rows at a time instead (GP: G rounded up to whole
+  // wavefronts), lane t writing column group t % GP of row i + t / GP.
   real* outT = d.poolT + d.slot_toff[slot];
   real* outB = d.poolB + d.slot_boff[slot];
   constexpr int NG = (((9 * KMAX + 3) / 4) + TEAM - 1) / TEAM;  // column groups per lane
+  int glane = lane, rsub = 0, rstep = 1;
+  if constexpr (TEAM == 256 && NG == 1) {
+    const int GP = (G + 63) & ~63;  // 64 .. 256
+    rstep = 256 / GP;
+    glane = lane % GP;
+    rsub = lane / GP;  // >= rstep: a lane with no row (256 not a multiple of GP)
+  }
   real M0[NG][4], M1[NG][4], M2[NG][4], j0[NG][4], j1[NG][4];
   int row0[NG][4];
 #pragma unroll
   for (int jg = 0; jg < NG; ++jg) {
-    const int g = lane + TEAM * jg;
+    const int g = glane + TEAM * jg;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int c = 4 * g + q;
@@ -606,12 +617,12 @@ __device__ __forceinline__ void marginalize_one(const Dev& d, int slot, int lane
     }
   }
   const int i_end = row_hi < n ? row_hi : n;
-  for (int i = row_lo; i < i_end; ++i) {
+  for (int i = row_lo + rsub; i < i_end && rsub < rstep; i += rstep) {
     const real4 vv = V[i];
     real4* row = reinterpret_cast<real4*>(i < 3 ? outT + (size_t)i * W : outB + (size_t)(i - 3) * W);
 #pragma unroll
     for (int jg = 0; jg < NG; ++jg) {
-      const int g = lane + TEAM * jg;
+      const int g = glane + TEAM * jg;
       if (g < G) {
         real out[4];
 #pragma unroll
