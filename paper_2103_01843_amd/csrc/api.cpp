@@ -604,6 +604,11 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
   for (int i = 0; i < 6; ++i) o_v[i] = fr(9 * NC);
   uint64_t o_minv = fr(81 * NC), o_ob = fr(54 * NO), o_dxl = fr(3 * NL);
   uint64_t o_cp = f64(NC), o_cp2 = f64(NC), o_cp3 = f64(NC), o_lp = f64(NL);
+  int64_t longest = 1;  // longest per-problem range of landmark or camera partials
+  for (int64_t p = 0; p < (int64_t)P; ++p)
+    longest = std::max({longest, h.pt_off[p + 1] - h.pt_off[p], h.cam_off[p + 1] - h.cam_off[p]});
+  const uint64_t nchunks = (uint64_t)((longest + SUM_CHUNK_VALUES - 1) / SUM_CHUNK_VALUES);
+  uint64_t o_psum = f64(P * nchunks);
   uint64_t o_s[10];
   for (int i = 0; i < 10; ++i) o_s[i] = f64(P);
   uint64_t o_it = f32(P), o_dn = f32(P), o_ps = f32(P), o_act = L.take(P), o_flag = L.take(P);
@@ -643,6 +648,8 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
     t.minv = at<real>(base, o_minv); t.obsbuf = at<real>(base, o_ob); t.dxl = at<real>(base, o_dxl);
     t.cam_part = at<double>(base, o_cp); t.cam_part2 = at<double>(base, o_cp2); t.cam_part3 = at<double>(base, o_cp3);
     t.lm_part = at<double>(base, o_lp);
+    t.psum = at<double>(base, o_psum);
+    t.sum_chunks = (int32_t)nchunks;
     t.lambda = at<double>(base, o_s[0]); t.rz_next = at<double>(base, o_s[1]); t.beta = at<double>(base, o_s[2]);
     t.rz = at<double>(base, o_s[3]); t.rr = at<double>(base, o_s[4]); t.rr0 = at<double>(base, o_s[5]);
     t.pcost = at<double>(base, o_s[6]); t.ppred = at<double>(base, o_s[7]);

@@ -144,6 +144,8 @@ struct Dev {
   double* cam_part2; // NC
   double* cam_part3; // NC
   double* lm_part;   // NL, per-landmark partial sums
+  double* psum;      // P * sum_chunks: chunk sums of the per-problem sums
+  int32_t sum_chunks;  // chunks of SUM_CHUNK values in the longest per-problem range (landmarks or cameras)
   // per-problem scalars
   double* lambda;
   double* rz_next;  // r.z of the last update, for alpha
@@ -184,6 +186,8 @@ enum { HUGE_ROWS_MIN = 64 };
 enum { QR_CHUNK_BYTES = 2 << 20 };
 // Smallest bucket edge of the row-block product (sizes its slot range).
 enum { ROWS_MIN_K = 29 };
+// Values per chunk of the per-problem sums (kernels.hip, k_prob_sum_chunks).
+enum { SUM_CHUNK_VALUES = 16384 };
 
 struct Launch {
   // launch shapes of the product (set by the autotuner or sqrtba_set_tuning)

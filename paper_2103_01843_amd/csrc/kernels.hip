@@ -224,26 +224,42 @@ __global__ __launch_bounds__(64) void k_cam_linearize(Dev d, const real* __restr
   if (lane == 0) d.cam_part[c] = cost;
 }
 
-// One 1024-thread workgroup per problem: out[p] = sum of vals[off[p] .. off[p+1])
-// (strided per thread, then a fixed tree).
-constexpr int SUM_THREADS = 1024;
+// Per-problem sums out[p] = sum of vals[off[p] .. off[p+1]) in two passes, so
+// that a problem of a million landmarks does not leave the sum to one
+// workgroup: chunk c of SUM_CHUNK values of problem p is summed by workgroup
+// (p, c) into psum[p * chunks + c] (strided per thread, then the wavefront
+// sums in a fixed order), and one wavefront per problem adds its chunks in a
+// fixed tree.  The order depends only on the problem's own length, so a
+// problem's sum has the same bits alone and in a batch.
+constexpr int SUM_CHUNK = SUM_CHUNK_VALUES;
+constexpr int SUM_THREADS = 256;
 
-__global__ __launch_bounds__(SUM_THREADS) void k_prob_sum(const double* __restrict__ vals,
-                                                          const int32_t* __restrict__ off, double* out,
-                                                          const uint8_t* mask) {
+__global__ __launch_bounds__(SUM_THREADS) void k_prob_sum_chunks(const double* __restrict__ vals,
+                                                                 const int32_t* __restrict__ off, double* psum,
+                                                                 int chunks, const uint8_t* mask) {
   __shared__ double red[SUM_THREADS / 64];
-  const int p = blockIdx.x;
+  const int p = blockIdx.x / chunks, c = blockIdx.x % chunks;
   if (mask && !mask[p]) return;
+  const int b = off[p] + c * SUM_CHUNK, e = min(off[p + 1], b + SUM_CHUNK);
+  if (b >= e) return;  // uniform over the workgroup
   double s = 0.0;
-  for (int i = off[p] + (int)threadIdx.x; i < off[p + 1]; i += SUM_THREADS) s += vals[i];
+#pragma unroll 8
+  for (int i = b + (int)threadIdx.x; i < e; i += SUM_THREADS) s += vals[i];
   s = wave_sum_d(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < SUM_THREADS / 64; ++w) t += red[w];
-    out[p] = t;
-  }
+  if (threadIdx.x == 0) psum[(size_t)p * chunks + c] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(64) void k_prob_sum_final(const int32_t* __restrict__ off, const double* psum,
+                                                       int chunks, double* out, const uint8_t* mask) {
+  const int p = blockIdx.x;
+  if (mask && !mask[p]) return;
+  const int n = (off[p + 1] - off[p] + SUM_CHUNK - 1) / SUM_CHUNK;
+  double s = 0.0;
+  for (int c = (int)threadIdx.x; c < n; c += 64) s += psum[(size_t)p * chunks + c];
+  s = wave_sum_d(s);
+  if (threadIdx.x == 0) out[p] = s;
 }
 
 // Slot ranges of the size classes, in launch order (class 4, 3, 2, 1, 0):
@@ -2948,7 +2964,10 @@ hipError_t launch_cam_linearize(const Dev& d, const Launch& L, bool jac, bool us
 
 hipError_t launch_prob_sum(const Dev& d, const Launch& L, const double* vals, const int32_t* off, double* out,
                            const uint8_t* mask) {
-  hipLaunchKernelGGL(k_prob_sum, dim3(d.P), dim3(SUM_THREADS), 0, L.stream, vals, off, out, mask);
+  hipLaunchKernelGGL(k_prob_sum_chunks, dim3(d.P * d.sum_chunks), dim3(SUM_THREADS), 0, L.stream, vals, off, d.psum,
+                     d.sum_chunks, mask);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_prob_sum_final, dim3(d.P), dim3(64), 0, L.stream, off, d.psum, d.sum_chunks, out, mask);
   LAUNCH_CHECK();
   return hipSuccess;
 }
