@@ -680,6 +680,7 @@ hipEvent_t take_event(sqrtba_ctx* c) {
 void flush_profile(sqrtba_ctx* c) {
   for (auto& p : c->pending) {
     float ms = 0.f;
+    (void)hipEventSynchronize(p.b);  // stages may return without waiting for the device
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       c->prof.ms[p.stage] += ms;
       c->prof.launches[p.stage] += 1;
@@ -951,6 +952,31 @@ int readback(sqrtba_ctx* c, const T* dev, T* out, bool sync = true) {
   return SQRTBA_OK;
 }
 
+// The pinned staging buffer holds 8 slices of 8 bytes per problem: slice 0
+// for readback, slices 0..3 for readback_all, 4 for a deferred copy of the
+// model decrease, 6 for the accept mask and 7 for lambda.
+char* pinned_slice(sqrtba_ctx* c, int j) { return static_cast<char*>(c->pinned) + (size_t)8 * c->h.P * j; }
+
+// Several per-problem arrays copied back with one wait (array j to slice j).
+struct Readback {
+  const void* dev;
+  void* out;
+  size_t elem;
+};
+int readback_all(sqrtba_ctx* c, std::initializer_list<Readback> list) {
+  const size_t P = c->h.P;
+  int j = 0;
+  for (const Readback& r : list)
+    HIP_TRY(c, hipMemcpyAsync(pinned_slice(c, j++), r.dev, r.elem * P, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  j = 0;
+  for (const Readback& r : list) {
+    if (r.out) std::memcpy(r.out, pinned_slice(c, j), r.elem * P);
+    ++j;
+  }
+  return SQRTBA_OK;
+}
+
 int set_active_mask(sqrtba_ctx* c, const std::vector<uint8_t>& m) {
   c->active = m;
   c->d.all_active = std::all_of(m.begin(), m.end(), [](uint8_t a) { return a != 0; }) ? 1 : 0;
@@ -978,33 +1004,37 @@ int do_linearize(sqrtba_ctx* c, double* cost) {
   return SQRTBA_OK;
 }
 
-int do_marginalize(sqrtba_ctx* c) {
+// sync = false (inside the LM loop): the stage is enqueued and the host goes
+// on; the next stage that reads results back waits for it.
+int do_marginalize(sqrtba_ctx* c, bool sync = true) {
   TRY(ensure_uploaded(c));
   if (!c->linearized) return fail(c, SQRTBA_E_STATE, "marginalize needs linearize");
   TRY(timed(c, SQRTBA_STAGE_MARGINALIZE, active_sum(c, c->qr_bytes), active_blocks(c), [&]() {
     LAUNCH(c, launch_marginalize(c->d, c->L, c->d.active));
     return (int)SQRTBA_OK;
   }));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (sync) HIP_TRY(c, hipStreamSynchronize(c->stream));
   flush_profile(c);
   c->marginalized = true;
   c->damped = c->solved = c->backsubbed = c->updated = false;
   return SQRTBA_OK;
 }
 
-int do_damp(sqrtba_ctx* c, const double* lambda) {
+int do_damp(sqrtba_ctx* c, const double* lambda, bool sync = true) {
   if (!c->marginalized) return fail(c, SQRTBA_E_STATE, "damp needs marginalize");
   if (!lambda) return fail(c, SQRTBA_E_INVALID, "null lambda");
   for (int32_t p = 0; p < c->h.P; ++p)
     if (c->active[p] && !(lambda[p] > 0.0 && std::isfinite(lambda[p])))
       return fail(c, SQRTBA_E_INVALID, "lambda[%d] = %g must be positive and finite", p, lambda[p]);
-  std::memcpy(c->pinned, lambda, sizeof(double) * c->h.P);
-  HIP_TRY(c, hipMemcpyAsync(c->d.lambda, c->pinned, sizeof(double) * c->h.P, hipMemcpyHostToDevice, c->stream));
+  // (the slice is rewritten only by the next damp, after a later stage has waited)
+  std::memcpy(pinned_slice(c, 7), lambda, sizeof(double) * c->h.P);
+  HIP_TRY(c, hipMemcpyAsync(c->d.lambda, pinned_slice(c, 7), sizeof(double) * c->h.P, hipMemcpyHostToDevice,
+                            c->stream));
   TRY(timed(c, SQRTBA_STAGE_DAMP, 0.0, active_blocks(c), [&]() {
     LAUNCH(c, launch_damp(c->d, c->L, c->d.active));
     return (int)SQRTBA_OK;
   }));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (sync) HIP_TRY(c, hipStreamSynchronize(c->stream));
   flush_profile(c);
   c->damped = true;
   c->solved = c->backsubbed = c->updated = false;
@@ -1276,10 +1306,8 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
   }
   L.cur_solve = -1;
   std::vector<double> rr(P), rr0(P);
-  TRY(readback(c, c->d.iters, its.data()));
-  TRY(readback(c, c->d.pstatus, st.data()));
-  TRY(readback(c, c->d.rr, rr.data()));
-  TRY(readback(c, c->d.rr0, rr0.data()));
+  TRY(readback_all(c, {{c->d.iters, its.data(), sizeof(int32_t)}, {c->d.pstatus, st.data(), sizeof(int32_t)},
+                       {c->d.rr, rr.data(), sizeof(double)}, {c->d.rr0, rr0.data(), sizeof(double)}}));
   if (!kept_its.empty())
     for (int p = 0; p < P; ++p)
       if (c->active[p] && !fell_back[p]) {
@@ -1303,14 +1331,21 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
   return SQRTBA_OK;
 }
 
-int do_backsub(sqrtba_ctx* c, double* pred) {
+// sync = false: the model decrease is copied to pinned slice 4 without a wait;
+// the caller takes it from there after the next wait (do_update's).
+int do_backsub(sqrtba_ctx* c, double* pred, bool sync = true) {
   if (!c->solved) return fail(c, SQRTBA_E_STATE, "back_substitute needs solve");
   TRY(timed(c, SQRTBA_STAGE_BACKSUB, 0.0, active_blocks(c), [&]() {
     LAUNCH(c, launch_backsub(c->d, c->L));
     LAUNCH(c, launch_prob_sum(c->d, c->L, c->d.lm_part, c->d.prob_lm_off, c->d.ppred, c->d.active));
     return (int)SQRTBA_OK;
   }));
-  TRY(readback(c, c->d.ppred, pred));
+  if (sync) {
+    TRY(readback(c, c->d.ppred, pred));
+  } else {
+    HIP_TRY(c, hipMemcpyAsync(pinned_slice(c, 4), c->d.ppred, sizeof(double) * c->h.P, hipMemcpyDeviceToHost,
+                              c->stream));
+  }
   flush_profile(c);
   c->backsubbed = true;
   c->updated = false;
@@ -1331,12 +1366,14 @@ int do_update(sqrtba_ctx* c, double* new_cost) {
   return SQRTBA_OK;
 }
 
-int do_commit(sqrtba_ctx* c, const uint8_t* accept) {
+int do_commit(sqrtba_ctx* c, const uint8_t* accept, bool sync = true) {
   if (!c->updated) return fail(c, SQRTBA_E_STATE, "commit needs update");
   if (!accept) return fail(c, SQRTBA_E_INVALID, "null accept mask");
-  HIP_TRY(c, hipMemcpyAsync(c->d.flag, accept, c->h.P, hipMemcpyHostToDevice, c->stream));
+  // (the slice is rewritten only by the next commit, after later stages have waited)
+  std::memcpy(pinned_slice(c, 6), accept, c->h.P);
+  HIP_TRY(c, hipMemcpyAsync(c->d.flag, pinned_slice(c, 6), c->h.P, hipMemcpyHostToDevice, c->stream));
   LAUNCH(c, launch_commit(c->d, c->L));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (sync) HIP_TRY(c, hipStreamSynchronize(c->stream));
   bool any = false;
   for (int p = 0; p < c->h.P; ++p) any |= (c->active[p] && accept[p]);
   c->updated = false;
@@ -1355,7 +1392,7 @@ int lm_loop(sqrtba_ctx* c, const double* tol_cost, sqrtba_lm_report* rep) {
   const double t0 = now_s();
   TRY(set_active_mask(c, all));
   TRY(do_linearize(c, E.data()));
-  TRY(do_marginalize(c));
+  TRY(do_marginalize(c, false));
   std::vector<double> E0 = E;
   for (int p = 0; p < P; ++p) {
     if (!std::isfinite(E[p])) { fin[p] = 1; lm_status[p] = SQRTBA_LM_NONFINITE; }
@@ -1368,17 +1405,18 @@ int lm_loop(sqrtba_ctx* c, const double* tol_cost, sqrtba_lm_report* rep) {
     for (int p = 0; p < P; ++p) { act[p] = !fin[p]; any |= act[p]; }
     if (!any) break;
     TRY(set_active_mask(c, act));
-    TRY(do_damp(c, lam.data()));
+    TRY(do_damp(c, lam.data(), false));
     TRY(do_solve(c, its.data(), rel.data(), st.data()));
-    TRY(do_backsub(c, pred.data()));
-    TRY(do_update(c, Enew.data()));
+    TRY(do_backsub(c, nullptr, false));
+    TRY(do_update(c, Enew.data()));  // waits, so the model decrease is in slice 4 too
+    std::memcpy(pred.data(), pinned_slice(c, 4), sizeof(double) * P);
     for (int p = 0; p < P; ++p) {
       acc[p] = 0;
       if (!act[p]) continue;
       const double rho = pred[p] > 0 ? (E[p] - Enew[p]) / pred[p] : -INFINITY;
       acc[p] = std::isfinite(Enew[p]) && rho > o.accept_ratio;
     }
-    TRY(do_commit(c, acc.data()));
+    TRY(do_commit(c, acc.data(), false));
     const double tnow = now_s() - t0;
     bool any_relin = false;
     for (int p = 0; p < P; ++p) {
@@ -1413,7 +1451,7 @@ int lm_loop(sqrtba_ctx* c, const double* tol_cost, sqrtba_lm_report* rep) {
       std::vector<double> Er(P);
       TRY(set_active_mask(c, relin));
       TRY(do_linearize(c, Er.data()));
-      TRY(do_marginalize(c));
+      TRY(do_marginalize(c, false));
       for (int p = 0; p < P; ++p)
         if (relin[p]) E[p] = Er[p];
     }
