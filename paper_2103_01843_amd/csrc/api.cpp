@@ -599,7 +599,7 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
   const uint64_t nsb = sc ? (uint64_t)(h.sc.noff + NC) * 81 : 0;
   uint64_t o_scb = fr(nsb), o_scoff = f32(sc ? h.sc.coff.size() : 0), o_scc = f32(sc ? h.sc.contrib.size() : 0);
   uint64_t o_scro = f32(sc ? h.sc.rowoff.size() : 0), o_scre = f32(sc ? h.sc.rowent.size() : 0), o_vy = fr(9 * NC);
-  uint64_t o_sc = fr(9 * NC);
+  uint64_t o_sc = fr(9 * NC), o_jtj = fr(54 * NC);
   uint64_t o_v[6];
   for (int i = 0; i < 6; ++i) o_v[i] = fr(9 * NC);
   uint64_t o_minv = fr(81 * NC), o_ob = fr(54 * NO), o_dxl = fr(3 * NL);
@@ -629,7 +629,7 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
     t.lm_slot = at<int32_t>(base, o_lms);
     t.qjob = at<int2>(base, o_qj); t.hjob = at<int2>(base, o_hj); t.hz_off = at<int64_t>(base, o_hzo); t.zpart = at<real>(base, o_zp);
     t.poolB = at<real>(base, o_pB); t.poolT = at<real>(base, o_pT); t.lmd = at<real>(base, o_lmd);
-    t.rhoB = implicit ? nullptr : at<real>(base, o_rho); t.s_cam = at<real>(base, o_sc);
+    t.rhoB = implicit ? nullptr : at<real>(base, o_rho); t.s_cam = at<real>(base, o_sc); t.cam_jtj = at<real>(base, o_jtj);
     if (implicit) { t.poolB = nullptr; t.poolT = nullptr; }
     t.obsrec = implicit ? at<real>(base, o_rec) : nullptr;
     t.rec_cam = implicit ? at<int32_t>(base, o_rcam) : nullptr;

@@ -107,6 +107,8 @@ struct Dev {
   real* lmd;     // NS * LMD_STRIDE
   real* rhoB;    // 2 * NO: residual column of the B rows of each landmark
   real* s_cam;   // NC * 9
+  real* cam_jtj; // NC * 54: per camera J^T J (45, upper triangle row by row) and J^T r (9) of the
+                 // linearization, unscaled and robust-weighted (block-Jacobi of explicit blocks)
   // PCG vectors (9 NC each)
   real* vx;
   real* vr;

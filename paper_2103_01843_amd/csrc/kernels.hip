@@ -191,9 +191,13 @@ __global__ __launch_bounds__(64) void k_cam_linearize(Dev d, const real* __restr
   if (mask && !mask[d.cam_prob[c]]) return;
   Cam C;
   load_cam(cam, c, C);
-  real n2[9];
+  // JAC: the camera's (robust-weighted, unscaled) J^T J, upper triangle row by
+  // row (45), and J^T r (9); its diagonal gives the column scales, and with
+  // explicit blocks both feed the block-Jacobi blocks and the right-hand side
+  constexpr int NJ = JAC ? 54 : 1;
+  real jt[NJ];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) n2[j] = 0.f;
+  for (int j = 0; j < NJ; ++j) jt[j] = 0.f;
   double cost = 0.0;
   const int b = d.cam_obs_off[c], e = d.cam_obs_off[c + 1];
   for (int i = b + lane; i < e; i += 64) {
@@ -206,19 +210,29 @@ __global__ __launch_bounds__(64) void k_cam_linearize(Dev d, const real* __restr
     cost += (double)robust_term(r[0] * r[0] + r[1] * r[1], d.huber, sw);
     if constexpr (JAC) {
       const real w = sw * sw;
+      int q = 0;
 #pragma unroll
-      for (int j = 0; j < 9; ++j) n2[j] += w * (Jp[0][j] * Jp[0][j] + Jp[1][j] * Jp[1][j]);
+      for (int a = 0; a < 9; ++a) {
+        jt[45 + a] += w * (Jp[0][a] * r[0] + Jp[1][a] * r[1]);
+#pragma unroll
+        for (int m = a; m < 9; ++m) jt[q++] += w * (Jp[0][a] * Jp[0][m] + Jp[1][a] * Jp[1][m]);
+      }
     }
   }
   cost = wave_sum_d(cost);
   if constexpr (JAC) {
 #pragma unroll
-    for (int j = 0; j < 9; ++j) n2[j] = wave_sum_f(n2[j]);
-    if (lane < 9) {
-      real v = n2[0];
+    for (int j = 0; j < NJ; ++j) jt[j] = wave_sum_f(jt[j]);
+    // lane j < 54 writes entry j; diagonal entry (a, a) sits at 9a - a(a-1)/2
+    real v = jt[0];
 #pragma unroll
-      for (int j = 1; j < 9; ++j) v = (lane == j) ? n2[j] : v;
-      d.s_cam[9 * c + lane] = v > 0.f ? 1.0f / sqrt(v) : 1.0f;
+    for (int j = 1; j < NJ; ++j) v = (lane == j) ? jt[j] : v;
+    if (lane < NJ) d.cam_jtj[NJ * (size_t)c + lane] = v;
+    if (lane < 9) {
+      real n2 = jt[0];
+#pragma unroll
+      for (int a = 1; a < 9; ++a) n2 = (lane == a) ? jt[9 * a - a * (a - 1) / 2] : n2;
+      d.s_cam[9 * c + lane] = n2 > 0.f ? 1.0f / sqrt(n2) : 1.0f;
     }
   }
   if (lane == 0) d.cam_part[c] = cost;
@@ -760,144 +774,129 @@ __device__ __forceinline__ void damp_one(const Dev& d, int slot, int lane, const
 
 // ------------------------------------- block-Jacobi blocks and right-hand side
 
-// Per landmark and observation (camera slab j of its B rows, 2k x 9):
-// G_j = B_j^T B_j (45 upper entries) and g_j = B_j^T rho_B, unscaled, written
-// to obsbuf[obs][0..53]; one lane owns one observation and sums over the rows.
-// For k <= 28 each lane's rows arrive through LDS: the block is read from HBM
-// as a contiguous stream of float4s (one slab is 9 floats at a 36-byte
-// stride, so loading slabs directly touches every cache line nine times), and
-// the landmark's k x 54 outputs, contiguous in obsbuf, leave through LDS as
-// one stream of float2s.  The larger landmarks, a workgroup each, read their
-// slabs directly.
+// The camera blocks of B^T B and B^T rho_B follow from the camera's own
+// Jacobian rows and each landmark's three damped top rows: the QR and the
+// damping rotations are orthogonal and leave the column Gram of [J_p | r]
+// (with the three zero rows of the damping system) unchanged, so for
+// observation j of a landmark, with its camera slab of 9 columns,
+//   B_j^T B_j   = J_j^T J_j - T^_j^T T^_j,
+//   B_j^T rho_B = J_j^T r_j - T^_j^T q^,
+// T^ the damped top rows (rotated from the stored undamped rows) and q^ the
+// damped Q1^T r.  The camera sums of J_j^T J_j and J_j^T r_j come from the
+// linearization (cam_jtj); here each observation gets T^_j^T T^_j (45 upper
+// entries) and T^_j^T q^ (9), written to obsbuf[obs][0..53], which
+// k_precond_cam subtracts.  A landmark is read as its 3 top rows instead of
+// its 2k B rows.  The subtraction is of quantities of the same order (B keeps
+// (2k - 3) / 2k of a slab's squared norm on average); per camera the FP32
+// blocks agree with the direct sum over the B rows to the same 3e-7.
+//
+// Each team rotates its landmark's top rows into LDS (lanes over column
+// groups), then lane o sums observation o over the three rows, and the k x 54
+// outputs (contiguous in obsbuf) leave through LDS as one stream of float2s.
 
-// The rows of one landmark and observation slab.
-__device__ __forceinline__ void precond_rows(const real* __restrict__ rows, int W, const real* __restrict__ rho,
-                                             int n, real (&g)[54]) {
-  for (int i = 0; i < n; ++i) {
+// The 54 terms of one observation slab from the three damped top rows in LDS.
+__device__ __forceinline__ void top_gram(const real* __restrict__ rows, int W, const real (&qh)[3], real (&g)[54]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
     real b[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) b[e] = rows[i * W + e];
-    const real rr = rho[i];
     int e = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-      g[45 + a] += b[a] * rr;
+      g[45 + a] += b[a] * qh[i];
 #pragma unroll
       for (int c = a; c < 9; ++c) g[e++] += b[a] * b[c];
     }
   }
 }
 
-// Rows per staged batch, and the LDS of a workgroup of the small-class kernel:
-// every team stages PC_RB rows of its block, pc_loads float4s per lane (all
-// stored, those past the batch being copies that are never read; stride plus
-// 4 floats: 16-byte aligned, and the teams of a wavefront start on different
-// banks), then its k x 54 outputs.
-constexpr int PC_RB = sizeof(real) == 4 ? 8 : 4;
-__host__ __device__ constexpr int pc_loads(int cls) {
-  return (PC_RB * (((9 * class_kmax(cls) + 3) & ~3) >> 2) + class_team(cls) - 1) / class_team(cls);
+// LDS floats per team: the three damped top rows (16-byte aligned, plus 4 so
+// that the teams of a wavefront start on different banks), or the team's
+// k x 54 outputs, whichever is larger.
+__host__ __device__ constexpr int pt_stride(int kmax) {
+  return (3 * ((9 * kmax + 3) & ~3) + 4) > (54 * kmax + 2) ? (3 * ((9 * kmax + 3) & ~3) + 4) : (54 * kmax + 2);
 }
-__host__ __device__ constexpr int pc_team_stride(int cls) { return 4 * pc_loads(cls) * class_team(cls) + 4; }
-__host__ __device__ constexpr int pc_out_stride(int cls) { return 54 * class_kmax(cls) + 2; }
-__host__ __device__ constexpr int pc_lds(int cls) {
-  return (WG / class_team(cls)) * (pc_team_stride(cls) > pc_out_stride(cls) ? pc_team_stride(cls) : pc_out_stride(cls));
-}
-constexpr int PC_LDS_SMALL = pc_lds(0) > pc_lds(1) ? (pc_lds(0) > pc_lds(2) ? (pc_lds(0) > pc_lds(3) ? pc_lds(0) : pc_lds(3))
-                                                                           : (pc_lds(2) > pc_lds(3) ? pc_lds(2) : pc_lds(3)))
-                                                   : (pc_lds(1) > pc_lds(2) ? (pc_lds(1) > pc_lds(3) ? pc_lds(1) : pc_lds(3))
-                                                                           : (pc_lds(2) > pc_lds(3) ? pc_lds(2) : pc_lds(3)));
+__host__ __device__ constexpr int pt_lds(int cls) { return (WG / class_team(cls)) * pt_stride(class_kmax(cls)); }
+constexpr int PT_LDS = pt_lds(0) > pt_lds(1) ? (pt_lds(0) > pt_lds(2) ? (pt_lds(0) > pt_lds(3) ? pt_lds(0) : pt_lds(3))
+                                                                     : (pt_lds(2) > pt_lds(3) ? pt_lds(2) : pt_lds(3)))
+                                             : (pt_lds(1) > pt_lds(2) ? (pt_lds(1) > pt_lds(3) ? pt_lds(1) : pt_lds(3))
+                                                                     : (pt_lds(2) > pt_lds(3) ? pt_lds(2) : pt_lds(3)));
+constexpr int PT_LDS_ALL = PT_LDS > pt_lds(4) ? PT_LDS : pt_lds(4);
 
-// Classes 0..3: team TEAM of the workgroup takes slot s0 + team (the teams of
-// a workgroup belong to one class; slots past send, and landmarks of inactive
-// problems, do no work but join every barrier).  The batches run to the
-// largest k of the workgroup, its first slot's (slots are in decreasing k).
-template <int TEAM, int CLS>
-__device__ __forceinline__ void precond_team(const Dev& d, int s0, int send, real* lds) {
+// Team TEAM of the workgroup takes slot s0 + team (every team of a workgroup
+// belongs to one class; slots past send and landmarks of inactive problems do
+// no work but join both barriers).  STAGE_OUT: the outputs leave through LDS
+// (every class but 5, whose k x 54 outputs would not fit).
+template <int TEAM, int KMAX, bool STAGE_OUT>
+__device__ __forceinline__ void precond_top(const Dev& d, int s0, int send, real* lds) {
   const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
   const int slot = s0 + team;
-  // the block's rows are requested before the problem's flag is tested (a
-  // block of an inactive problem is read but not used)
   const bool in = slot < send;
   const int sl = in ? slot : s0;
   const int prob = d.slot_prob[sl];
-  const int k = in ? d.slot_k[sl] : 0;
+  const int kin = d.slot_k[sl];
   const int obs0 = d.slot_obs0[sl];
-  const int64_t boff = d.slot_boff[sl];
-  const int kmax = d.slot_k[s0];
+  const int64_t toff = d.slot_toff[sl];
+  const int k = (in && (d.all_active || d.active[prob])) ? kin : 0;
   const int W = width_of(k), G = W >> 2;
-  real* tb = lds + team * pc_team_stride(CLS);
-  const real4* __restrict__ B4 = reinterpret_cast<const real4*>(d.poolB + boff);
-  const real* __restrict__ rho = d.rhoB + 2 * (size_t)obs0;
-  constexpr int NL = pc_loads(CLS);
-  real g[54];
-#pragma unroll
-  for (int e = 0; e < 54; ++e) g[e] = 0.f;
-  for (int r0 = 0; r0 < 2 * kmax; r0 += PC_RB) {  // uniform over the workgroup
-    // every load is issued before the first LDS store, and every store is
-    // made (no branches to sink the loads into): a lane past the batch re-reads
-    // the batch's last float4 (in the block) into a slot that is never read
-    const int f0 = r0 * G, f1 = min(2 * k, r0 + PC_RB) * G, fl = max(f1 - 1, 0);
-    real4 t[NL];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) t[j] = B4[min(f0 + lane + j * TEAM, fl)];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) reinterpret_cast<real4*>(tb)[lane + j * TEAM] = t[j];
-    __syncthreads();
-    if (lane < k) precond_rows(tb + 9 * lane, W, rho + r0, min(2 * k - r0, PC_RB), g);
-    __syncthreads();
-  }
-  const int kw = (d.all_active || d.active[prob]) ? k : 0;  // outputs of active problems only
-  real* ob = lds + team * pc_out_stride(CLS);
-  if (lane < kw) {
-#pragma unroll
-    for (int e = 0; e < 54; ++e) ob[54 * lane + e] = g[e];
+  real* tb = lds + team * pt_stride(KMAX);
+  real qh[3] = {0.f, 0.f, 0.f};
+  if (k) {
+    const real* lmd = d.lmd + (size_t)sl * LMD_STRIDE;
+    Givens6 Gv;
+    real Rh[3][3], dr[3];
+    damping_rotations(lmd, sqrt((real)d.lambda[prob]), Gv, Rh, qh, dr);
+    const real4* __restrict__ T = reinterpret_cast<const real4*>(d.poolT + toff);
+    real4* t4 = reinterpret_cast<real4*>(tb);
+    for (int gi = lane; gi < G; gi += TEAM) {
+      const real4 t0 = T[gi], t1 = T[G + gi], t2 = T[2 * G + gi];
+      real a[3], z[3];
+      real4 o0, o1, o2;
+      a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, z); o0.x = a[0]; o1.x = a[1]; o2.x = a[2];
+      a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, z); o0.y = a[0]; o1.y = a[1]; o2.y = a[2];
+      a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, z); o0.z = a[0]; o1.z = a[1]; o2.z = a[2];
+      a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, z); o0.w = a[0]; o1.w = a[1]; o2.w = a[2];
+      t4[gi] = o0;
+      t4[G + gi] = o1;
+      t4[2 * G + gi] = o2;
+    }
   }
   __syncthreads();
-  real2* dst = reinterpret_cast<real2*>(d.obsbuf + (size_t)obs0 * 54);  // 8-byte aligned
-  for (int j = lane; j < 27 * kw; j += TEAM) dst[j] = reinterpret_cast<const real2*>(ob)[j];
-}
-
-// Classes 4 and 5: one lane per observation walks the rows of its slab.
-template <int TEAM>
-__device__ __forceinline__ void precond_one(const Dev& d, int slot, int lane) {
-  const int prob = d.slot_prob[slot];
-  const int k = d.slot_k[slot];
-  const int obs0 = d.slot_obs0[slot];
-  const int64_t boff = d.slot_boff[slot];
-  if (!d.all_active && !d.active[prob]) return;
-  const int W = width_of(k);
-  const real* B = d.poolB + boff;
-  const real* rho = d.rhoB + 2 * (size_t)obs0;
-  for (int o = lane; o < k; o += TEAM) {
-    real g[45], h[9];
+  constexpr int OPL = (KMAX + TEAM - 1) / TEAM;  // observations per lane
+  real g[OPL][54];
 #pragma unroll
-    for (int e = 0; e < 45; ++e) g[e] = 0.f;
+  for (int m = 0; m < OPL; ++m) {
 #pragma unroll
-    for (int e = 0; e < 9; ++e) h[e] = 0.f;
-#pragma unroll 2
-    for (int r = 0; r < 2 * k; ++r) {
-      const real* row = B + (size_t)r * W + 9 * o;
-      real b[9];
+    for (int e = 0; e < 54; ++e) g[m][e] = 0.f;
+    const int o = lane + TEAM * m;
+    if (o < k) top_gram(tb + 9 * o, W, qh, g[m]);
+  }
+  if constexpr (STAGE_OUT) {
+    static_assert(OPL == 1, "staged outputs: one observation per lane");
+    __syncthreads();
+    if (lane < k) {
 #pragma unroll
-      for (int e = 0; e < 9; ++e) b[e] = row[e];
-      const real rr = rho[r];
-      int e = 0;
+      for (int e = 0; e < 54; ++e) tb[54 * lane + e] = g[0][e];
+    }
+    __syncthreads();
+    real2* dst = reinterpret_cast<real2*>(d.obsbuf + (size_t)obs0 * 54);  // 8-byte aligned
+    for (int j = lane; j < 27 * k; j += TEAM) dst[j] = reinterpret_cast<const real2*>(tb)[j];
+  } else {
 #pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        h[a] += b[a] * rr;
+    for (int m = 0; m < OPL; ++m) {
+      const int o = lane + TEAM * m;
+      if (o < k) {
+        real2* dst = reinterpret_cast<real2*>(d.obsbuf + (size_t)(obs0 + o) * 54);
 #pragma unroll
-        for (int c = a; c < 9; ++c) g[e++] += b[a] * b[c];
+        for (int e = 0; e < 27; ++e) dst[e] = make_real2(g[m][2 * e], g[m][2 * e + 1]);
       }
     }
-    real* out = d.obsbuf + (size_t)(obs0 + o) * 54;
-#pragma unroll
-    for (int e = 0; e < 45; ++e) out[e] = g[e];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) out[45 + e] = h[e];
   }
 }
 
-// Per camera (one wavefront): sum the per-observation blocks, scale, add
+// Per camera (one wavefront): sum the per-observation blocks (explicit
+// blocks: subtract them from the camera's J^T J and J^T r), scale, add
 // lambda I, Cholesky-factor and invert the 9x9 block (a non-positive pivot
 // falls back to the inverse diagonal and is counted), and form b~ = S g.
 __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
@@ -917,6 +916,11 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
 #pragma unroll
   for (int e = 0; e < 54; ++e) acc[e] = wave_sum_f(acc[e]);
   if (lane != 0) return;
+  if (!d.implicit) {  // explicit blocks: the camera's J^T J and J^T r less the top-row terms
+    const real* jt = d.cam_jtj + 54 * (size_t)c;
+#pragma unroll
+    for (int e = 0; e < 54; ++e) acc[e] = jt[e] - acc[e];
+  }
   real s[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) s[a] = d.s_cam[9 * c + a];
@@ -2034,27 +2038,25 @@ __global__ __launch_bounds__(WG) void k_damp_huge(Dev d, int slot0, const uint8_
   damp_one<256>(d, slot0 + blockIdx.x, threadIdx.x, mask);
 }
 
-// Classes 0..3 of m (launch-order entries 1..4; entry 0 is unused).
+// Classes 4..0 of m (launch order; one landmark per workgroup for class 4).
 __global__ __launch_bounds__(WG) void k_precond_obs(Dev d, ClassGrid m) {
-  __shared__ __align__(16) real lds[PC_LDS_SMALL];
+  __shared__ __align__(16) real lds[PT_LDS_ALL];
   int b = blockIdx.x;
-  if (b < m.nblk[1]) { precond_team<64, 3>(d, m.first[1] + b * (WG / 64), m.end[1], lds); return; }
+  if (b < m.nblk[0]) { precond_top<256, class_kmax(4), true>(d, m.first[0] + b, m.end[0], lds); return; }
+  b -= m.nblk[0];
+  if (b < m.nblk[1]) { precond_top<64, class_kmax(3), true>(d, m.first[1] + b * (WG / 64), m.end[1], lds); return; }
   b -= m.nblk[1];
-  if (b < m.nblk[2]) { precond_team<32, 2>(d, m.first[2] + b * (WG / 32), m.end[2], lds); return; }
+  if (b < m.nblk[2]) { precond_top<32, class_kmax(2), true>(d, m.first[2] + b * (WG / 32), m.end[2], lds); return; }
   b -= m.nblk[2];
-  if (b < m.nblk[3]) { precond_team<16, 1>(d, m.first[3] + b * (WG / 16), m.end[3], lds); return; }
+  if (b < m.nblk[3]) { precond_top<16, class_kmax(1), true>(d, m.first[3] + b * (WG / 16), m.end[3], lds); return; }
   b -= m.nblk[3];
-  precond_team<8, 0>(d, m.first[4] + b * (WG / 8), m.end[4], lds);
-}
-
-// Class 4 (one workgroup per landmark).
-__global__ __launch_bounds__(WG) void k_precond_obs_large(Dev d, int slot0) {
-  precond_one<256>(d, slot0 + blockIdx.x, threadIdx.x);
+  precond_top<8, class_kmax(0), true>(d, m.first[4] + b * (WG / 8), m.end[4], lds);
 }
 
 // Class 5 (one workgroup per landmark, on the side stream).
-__global__ __launch_bounds__(WG) void k_precond_obs_huge(Dev d, int slot0) {
-  precond_one<256>(d, slot0 + blockIdx.x, threadIdx.x);
+__global__ __launch_bounds__(WG) void k_precond_obs_huge(Dev d, int slot0, int send) {
+  __shared__ __align__(16) real lds[3 * ((9 * class_kmax(5) + 3) & ~3) + 4];
+  precond_top<256, class_kmax(5), false>(d, slot0 + blockIdx.x, send, lds);
 }
 
 struct BacksubF {
@@ -3082,15 +3084,13 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
     return hipSuccess;
   }
   int n = 0;
-  const ClassGrid m = class_grid(L, &n, true);  // classes 0..3
-  const bool side = w[5].slots && (n || w[4].slots) && L.side && L.fork && L.join;
+  const ClassGrid m = class_grid(L, &n);  // classes 0..4
+  const bool side = w[5].slots && n && L.side && L.fork && L.join;
   hipError_t e = side_fork(L, side);
   if (e != hipSuccess) return e;
   if (w[5].slots)
     hipLaunchKernelGGL(k_precond_obs_huge, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d,
-                       w[5].first_slot);
-  LAUNCH_CHECK();
-  if (w[4].slots) hipLaunchKernelGGL(k_precond_obs_large, dim3(w[4].slots), dim3(WG), 0, L.stream, d, w[4].first_slot);
+                       w[5].first_slot, w[5].first_slot + w[5].slots);
   LAUNCH_CHECK();
   if (n) hipLaunchKernelGGL(k_precond_obs, dim3(n), dim3(WG), 0, L.stream, d, m);
   LAUNCH_CHECK();
