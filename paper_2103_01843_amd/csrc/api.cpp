@@ -387,6 +387,10 @@ int build_bookkeeping(sqrtba_ctx* c, int64_t n, const int32_t* cam, const int32_
         zpos_of_obs[nb.slot_obs0[sl] + o] = nb.slot_zoff[sl] + (int32_t)(9 * o);
     nb.cam_zpos.resize(nb.NO);
     for (int64_t q = 0; q < nb.NO; ++q) nb.cam_zpos[q] = zpos_of_obs[nb.cam_obs_idx[q]];
+    // each camera's outputs are summed in increasing address order (its reads
+    // then move through memory in one direction)
+    for (int64_t cc = 0; cc < h.NC; ++cc)
+      std::sort(nb.cam_zpos.begin() + nb.cam_obs_off[cc], nb.cam_zpos.begin() + nb.cam_obs_off[cc + 1]);
   }
   nb.poolB = ob;
   nb.poolT = ot;
