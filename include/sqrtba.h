@@ -445,10 +445,12 @@ typedef struct {
   int32_t small_rows;     /* rows per batch for k <= 28: 4 or 8 */
   int32_t persist_wgs;    /* 0: one workgroup per block of small landmarks; 1024, 2048
                              or 4096: a persistent launch of that many workgroups */
-  int32_t stream_loads;   /* 1: the row-block and four-wavefront landmark kernels read the
-                             blocks with non-temporal loads (no cache allocation), which
-                             helps when the blocks are much larger than the last-level
-                             cache and hurts when they fit in it; 0: ordinary loads */
+  int32_t stream_loads;   /* 0..3, two bits; bit 0 (1): the row-block and four-wavefront
+                             landmark kernels read the blocks with non-temporal loads (no
+                             cache allocation); bit 1 (2): so does the kernel of the
+                             landmarks with k <= 28.  They help when the blocks are much
+                             larger than the last-level cache and hurt when they fit in
+                             it; 0: ordinary loads everywhere */
 } sqrtba_tuning;
 
 typedef struct {

@@ -2227,7 +2227,7 @@ bool valid_tuning(const sqrtba_tuning& t) {
   return (r == 64 || r == 128 || r == 256 || r == 512 || r == 1024) && (e == 114 || e == 61 || e == 29) &&
          (t.huge_side == 0 || t.huge_side == 1) && (t.large_separate == 0 || t.large_separate == 1) &&
          (t.small_rows == 4 || t.small_rows == 8) && (p == 0 || p == 1024 || p == 2048 || p == 4096) &&
-         (t.stream_loads == 0 || t.stream_loads == 1);
+         (t.stream_loads >= 0 && t.stream_loads <= 3);
 }
 
 sqrtba_tuning current_tuning(const sqrtba_ctx* c) {
@@ -2368,8 +2368,11 @@ int32_t SQRTBA_API(autotune)(sqrtba_ctx* c, int32_t reps, sqrtba_tuning* best, s
     TRY(try_field(&sqrtba_tuning::small_rows, {4, 8}));
     TRY(try_field(&sqrtba_tuning::persist_wgs, {0, 1024, 2048, 4096}));
     // non-temporal loads only on a clear gain: a solve also rereads the blocks
-    // outside the product (preconditioner, back-substitution), which they may slow
-    if (c->L.n45 > 0) TRY(try_field(&sqrtba_tuning::stream_loads, {0, 1}, 0.01));
+    // outside the product (back-substitution), which they may slow
+    if (c->L.n45 > 0)
+      TRY(try_field(&sqrtba_tuning::stream_loads, {0, 1, 2, 3}, 0.01));
+    else
+      TRY(try_field(&sqrtba_tuning::stream_loads, {0, 2}, 0.01));
   }
   TRY(apply_tuning(c, cur));
   HIP_TRY(c, hipStreamSynchronize(c->stream));

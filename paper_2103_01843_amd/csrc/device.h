@@ -202,7 +202,7 @@ struct Launch {
   int large_sep;   // the rest of k >= 29 as its own launch (else inside the small-class launch)
   int mv_rbs;      // row-batch set of the small classes (0: 4 rows, 1: 8 rows)
   int persist;     // > 0: the small-class launch is persistent with this many workgroups
-  int nt;          // 1: the row-block and four-wavefront landmark kernels use non-temporal loads
+  int nt;          // non-temporal block loads: bit 0 the row-block and four-wavefront kernels, bit 1 classes 0..3
   int qjobs;       // row-chunk jobs of the class-5 QR (explicit blocks)
   hipStream_t stream;
   hipStream_t side;   // second stream for the largest landmarks (may be null)

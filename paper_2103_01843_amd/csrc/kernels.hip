@@ -1089,7 +1089,7 @@ __device__ __forceinline__ void store_cols(const Dev& d, int zoff, int g, real4 
 // one is reduced, so up to 2 RB rows are in flight per lane.  Rows past 2k of
 // the last batch re-read row 2k-1 (cached) and are given y = 0.  Writes z
 // (unscaled, 9 values per observation) to obsbuf.
-template <int TEAM, int RB, bool PCG>
+template <int TEAM, int RB, bool PCG, bool NT>
 __device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, const real* __restrict__ v) {
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
@@ -1111,7 +1111,7 @@ __device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, con
   const real4* __restrict__ Bj = Bs + min(lane, G - 1);
   real4 c[RB];
 #pragma unroll
-  for (int i = 0; i < RB; ++i) c[i] = Bj[(size_t)min(i, n - 1) * G];
+  for (int i = 0; i < RB; ++i) c[i] = load_block<NT>(&Bj[(size_t)min(i, n - 1) * G]);
   const real4 pv = lane < G ? gather_cols(d, v, obs0, k, lane) : make_real4(0.f, 0.f, 0.f, 0.f);
   if (!act || dn) return;  // uniform over the team
   real4 z = make_real4(0.f, 0.f, 0.f, 0.f);
@@ -1122,7 +1122,7 @@ __device__ __forceinline__ void matvec_teams(const Dev& d, int s0, int send, con
     for (int i = 0; i < RB; ++i) nx[i] = c[i];
     if (rn < n) {
 #pragma unroll
-      for (int i = 0; i < RB; ++i) nx[i] = Bj[(size_t)min(rn + i, n - 1) * G];
+      for (int i = 0; i < RB; ++i) nx[i] = load_block<NT>(&Bj[(size_t)min(rn + i, n - 1) * G]);
     }
     real y[RB];
 #pragma unroll
@@ -1225,32 +1225,32 @@ __host__ __device__ constexpr int mv_per_wg(int j) {  // j: launch-order class i
 // a single kernel with no tail gaps between classes.  Without LARGE the kernel
 // holds no class-4 code and needs fewer registers (more resident wavefronts);
 // class 4 then runs as its own launch (k_matvec_large).
-template <bool PCG, bool LARGE, int RBS>
+template <bool PCG, bool LARGE, int RBS, bool NT>
 __device__ __forceinline__ void matvec_block(const Dev& d, const ClassGrid& m, int b, const real* v,
                                              real4 (*zred)[64]) {
   if constexpr (LARGE) {
     if (b < m.nblk[0]) { matvec_large<4, MV_RS, PCG, false>(d, m.first[0] + b, v, zred); return; }
     b -= m.nblk[0];
   }
-  if (b < m.nblk[1]) { matvec_teams<64, mv_rb(RBS, 0), PCG>(d, m.first[1] + b * mv_per_wg(1), m.end[1], v); return; }
+  if (b < m.nblk[1]) { matvec_teams<64, mv_rb(RBS, 0), PCG, NT>(d, m.first[1] + b * mv_per_wg(1), m.end[1], v); return; }
   b -= m.nblk[1];
-  if (b < m.nblk[2]) { matvec_teams<32, mv_rb(RBS, 1), PCG>(d, m.first[2] + b * mv_per_wg(2), m.end[2], v); return; }
+  if (b < m.nblk[2]) { matvec_teams<32, mv_rb(RBS, 1), PCG, NT>(d, m.first[2] + b * mv_per_wg(2), m.end[2], v); return; }
   b -= m.nblk[2];
-  if (b < m.nblk[3]) { matvec_teams<16, mv_rb(RBS, 2), PCG>(d, m.first[3] + b * mv_per_wg(3), m.end[3], v); return; }
+  if (b < m.nblk[3]) { matvec_teams<16, mv_rb(RBS, 2), PCG, NT>(d, m.first[3] + b * mv_per_wg(3), m.end[3], v); return; }
   b -= m.nblk[3];
-  matvec_teams<8, mv_rb(RBS, 3), PCG>(d, m.first[4] + b * mv_per_wg(4), m.end[4], v);
+  matvec_teams<8, mv_rb(RBS, 3), PCG, NT>(d, m.first[4] + b * mv_per_wg(4), m.end[4], v);
 }
 
 // One launch of the product over classes 0..3 (and 4): one workgroup per
 // block, or, PERSIST, a fixed grid whose workgroups take blocks b, b + grid,
 // ... in turn (largest landmarks first, so the static round-robin balances).
-template <bool PCG, bool LARGE, int RBS, bool PERSIST>
+template <bool PCG, bool LARGE, int RBS, bool PERSIST, bool NT>
 __global__ __launch_bounds__(WG) void k_matvec(Dev d, ClassGrid m, int nwork, const real* v) {
   __shared__ real4 zred[LARGE ? 4 : 1][64];
   if constexpr (PERSIST) {
-    for (int b = blockIdx.x; b < nwork; b += gridDim.x) matvec_block<PCG, LARGE, RBS>(d, m, b, v, zred);
+    for (int b = blockIdx.x; b < nwork; b += gridDim.x) matvec_block<PCG, LARGE, RBS, NT>(d, m, b, v, zred);
   } else {
-    matvec_block<PCG, LARGE, RBS>(d, m, blockIdx.x, v, zred);
+    matvec_block<PCG, LARGE, RBS, NT>(d, m, blockIdx.x, v, zred);
   }
 }
 
@@ -3108,20 +3108,29 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
 // stream, concurrently with the rest, when huge_side), class 4 (inside the
 // main launch, or on its own when large_sep), classes 0..3, then the sum of
 // the class-5 partials.  The launch shapes are the tunables of Launch.
-template <bool PCG, bool LARGE, int RBS>
+template <bool PCG, bool LARGE, int RBS, bool NT>
 static void launch_small3(const Dev& d, const Launch& L, const ClassGrid& m, int n, const real* v) {
   if (L.persist > 0 && n > L.persist)
-    hipLaunchKernelGGL((k_matvec<PCG, LARGE, RBS, true>), dim3(L.persist), dim3(WG), 0, L.stream, d, m, n, v);
+    hipLaunchKernelGGL((k_matvec<PCG, LARGE, RBS, true, NT>), dim3(L.persist), dim3(WG), 0, L.stream, d, m, n, v);
   else
-    hipLaunchKernelGGL((k_matvec<PCG, LARGE, RBS, false>), dim3(n), dim3(WG), 0, L.stream, d, m, n, v);
+    hipLaunchKernelGGL((k_matvec<PCG, LARGE, RBS, false, NT>), dim3(n), dim3(WG), 0, L.stream, d, m, n, v);
 }
 
+// Launch::nt bit 1: non-temporal loads of the blocks of classes 0..3.
 template <bool PCG, bool LARGE>
 static void launch_small(const Dev& d, const Launch& L, const ClassGrid& m, int n, const real* v) {
-  if (L.mv_rbs == 0)
-    launch_small3<PCG, LARGE, 0>(d, L, m, n, v);
-  else
-    launch_small3<PCG, LARGE, 1>(d, L, m, n, v);
+  const bool nt = (L.nt & 2) != 0;
+  if (L.mv_rbs == 0) {
+    if (nt)
+      launch_small3<PCG, LARGE, 0, true>(d, L, m, n, v);
+    else
+      launch_small3<PCG, LARGE, 0, false>(d, L, m, n, v);
+  } else {
+    if (nt)
+      launch_small3<PCG, LARGE, 1, true>(d, L, m, n, v);
+    else
+      launch_small3<PCG, LARGE, 1, false>(d, L, m, n, v);
+  }
 }
 
 // Product over all landmark blocks.  Slots are ordered by decreasing k, so the
@@ -3160,7 +3169,7 @@ static hipError_t launch_matvec(const Dev& d, const Launch& L, const real* v) {
       if (e == hipSuccess) e = hipStreamWaitEvent(L.side, L.fork, 0);
       if (e != hipSuccess) return e;
     }
-    if (L.nt)
+    if (L.nt & 1)
       hipLaunchKernelGGL((k_matvec_rows<PCG, true>), dim3(L.hjobs), dim3(WG), 0, hs, d, 0, L.huge_rows, v);
     else
       hipLaunchKernelGGL((k_matvec_rows<PCG, false>), dim3(L.hjobs), dim3(WG), 0, hs, d, 0, L.huge_rows, v);
@@ -3172,7 +3181,7 @@ static hipError_t launch_matvec(const Dev& d, const Launch& L, const real* v) {
   const int nlarge = L.n45 - L.rows_n;
   const bool sep = L.large_sep && nlarge > 0;
   if (sep) {
-    if (L.nt)
+    if (L.nt & 1)
       hipLaunchKernelGGL((k_matvec_large<PCG, true>), dim3(nlarge), dim3(WG), 0, L.stream, d, L.rows_n, v);
     else
       hipLaunchKernelGGL((k_matvec_large<PCG, false>), dim3(nlarge), dim3(WG), 0, L.stream, d, L.rows_n, v);

@@ -38,6 +38,9 @@ SHAPES = [
     dict(DEFAULT, stream_loads=1),
     dict(DEFAULT, stream_loads=1, large_separate=1, huge_side=1),
     dict(DEFAULT, rows_min_k=29, huge_rows=256, huge_side=1, large_separate=1, stream_loads=1),
+    dict(DEFAULT, stream_loads=2),
+    dict(DEFAULT, stream_loads=3, small_rows=8, large_separate=1, huge_side=1),
+    dict(DEFAULT, stream_loads=2, persist_wgs=2048),
 ]
 
 
@@ -74,7 +77,7 @@ def test_every_shape_gives_the_reduced_system(mixed):
 @pytest.mark.parametrize("bad", [dict(huge_rows=100), dict(huge_rows=32), dict(small_rows=5),
                                  dict(huge_side=2), dict(large_separate=-1), dict(rows_min_k=30),
                                  dict(rows_min_k=200), dict(persist_wgs=1000), dict(persist_wgs=-1),
-                                 dict(stream_loads=2)])
+                                 dict(stream_loads=4), dict(stream_loads=-1)])
 def test_invalid_shapes_are_rejected(mixed, bad):
     p, _ = mixed
     ctx = gpu_context(p)
