@@ -117,6 +117,13 @@ typedef struct {
                             scaled by sqrt(rho'(s)) = sqrt(min(1, delta / |r_o|)).  Costs,
                             reports and histories are then robust costs; the model decrease is
                             the reweighted linear model's. */
+  int32_t pcg_test_kernel; /* where the PCG convergence test runs (the result is the same bit for
+                              bit): 0 in the per-camera kernel after the next product, which is
+                              wasted once the test succeeds (one product per solve); 1 in a
+                              kernel of its own after each update, which skips that product at
+                              the cost of one small launch per iteration; -1 (default): 1 when
+                              the product's algorithmic bytes over the problems of the solve
+                              are at least 1 GiB, else 0 */
 } sqrtba_options;
 
 typedef struct {

@@ -1153,9 +1153,28 @@ int trace_iteration(sqrtba_ctx* c) {
   return SQRTBA_OK;
 }
 
+// Where the convergence test runs (sqrtba_options::pcg_test_kernel): its own
+// kernel when the product it saves once per solve outweighs one small launch
+// per iteration, i.e. when the product moves at least 1 GiB.
+int pcg_test_sep(const sqrtba_ctx* c) {
+  if (c->opt.pcg_test_kernel >= 0) return c->opt.pcg_test_kernel;
+  double b = 0.0;
+  for (int p = 0; p < c->h.P; ++p)
+    if (c->active[p]) b += c->mv_bytes[p];
+  return b >= 1073741824.0 ? 1 : 0;
+}
+
 // PCG on the current minv blocks from x0 = 0, at most cap iterations.
 int run_pcg(sqrtba_ctx* c, int cap) {
   const int P = c->h.P;
+  const int ts = pcg_test_sep(c);
+  if (ts != c->d.test_sep) {
+    c->d.test_sep = ts;
+    if (c->graph) {  // captured launches hold the old Dev values
+      (void)hipGraphExecDestroy(c->graph);
+      c->graph = nullptr;
+    }
+  }
   LAUNCH(c, launch_pcg_init(c->d, c->L));
   std::vector<int32_t> done(P);
   TRY(readback(c, c->d.done, done.data()));
@@ -1531,13 +1550,14 @@ void SQRTBA_API(default_options)(sqrtba_options* o) {
   o->pcg_forcing_eta = 0.0;
   o->landmark_blocks = 0;
   o->huber_delta = 0.0;
+  o->pcg_test_kernel = -1;
 }
 
 static bool valid_options(const sqrtba_options& o) {
   return o.pcg_max_iters >= 0 && o.max_lm_iters >= 0 && o.lambda0 > 0 && o.pcg_check_every >= 1 &&
          std::isfinite(o.pcg_forcing_eta) && o.pcg_forcing_eta >= 0.0 &&
          (o.landmark_blocks >= 0 && o.landmark_blocks <= 2) && std::isfinite(o.huber_delta) &&
-         o.huber_delta >= 0.0;
+         o.huber_delta >= 0.0 && o.pcg_test_kernel >= -1 && o.pcg_test_kernel <= 1;
 }
 
 int32_t SQRTBA_API(create)(sqrtba_ctx** out, const sqrtba_options* opt, void* hip_stream) {

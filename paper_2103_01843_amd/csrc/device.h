@@ -164,6 +164,7 @@ struct Dev {
   double* ppred;
   uint8_t* active;
   int32_t all_active;  // 1: every problem is active (the per-landmark stages then skip the flag test)
+  int32_t test_sep;    // 1: the PCG convergence test is its own kernel after each update (k_pcg_test)
   uint8_t* flag;     // generic per-problem mask (relinearize / accept)
   int32_t* chol_fail;  // count of preconditioner blocks that fell back to the diagonal
   float* feats;        // NC * 64 learned-preconditioner features of the last preconditioner build

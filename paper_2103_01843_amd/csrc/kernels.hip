@@ -1356,6 +1356,12 @@ __global__ __launch_bounds__(WG) void k_matvec_combine(Dev d, int slot0, int row
 //             beta; p = z + beta p, q = A z + beta q (= A p), partial p.q,
 //   k_pcg_update  alpha = r.z / p.q; x += alpha p, r -= alpha q, z = M^-1 r,
 //             partials r.z, r.r.
+// The test needs the sums of every camera of a problem, so in this form it
+// runs after the next product, which is wasted once the test succeeds.  With
+// Dev::test_sep a fourth kernel, k_pcg_test, takes the test right after each
+// update (one wavefront per problem, the same sums and decisions, so the same
+// bits); the product after convergence is then skipped, at the price of one
+// small launch per iteration.
 // Every workgroup that needs a per-problem scalar forms it itself from the
 // per-camera FP64 partials with the same fixed-order wavefront tree, so all of
 // them hold the same bits.  Per-problem state is written by one designated
@@ -1507,7 +1513,12 @@ __global__ __launch_bounds__(WG) void k_pcg_q(Dev d) {
     sc = d.s_cam[idx];
   }
   if (!d.active[prob] || d.done[prob]) return;  // see the note at the top of this section
-  if (w == 0) {
+  if (d.test_sep) {  // k_pcg_test has taken the test and formed beta
+    if (threadIdx.x == 0) {
+      beta_s = (real)d.beta[prob];
+      go_s = 1;
+    }
+  } else if (w == 0) {
     int t = 3;  // 3: the problem's solve has ended (or it is inactive)
     double beta = 0.0;
     {
@@ -1616,8 +1627,9 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
   const bool valid = c < d.NC && lc < UPD_CAMS;
   // the done flags of the convergence test just made (by k_pcg_q) go to the
   // host's copy; a breakdown found below is seen by the host one chunk later,
-  // when the kernels of that problem have already stopped
-  if (blockIdx.x == 0 && d.done_host)
+  // when the kernels of that problem have already stopped (with test_sep,
+  // k_pcg_test writes the copy after this kernel)
+  if (blockIdx.x == 0 && d.done_host && !d.test_sep)
     for (int p = threadIdx.x; p < d.P; p += blockDim.x) d.done_host[p] = d.done[p];
   // loads that do not depend on alpha first
   int prob = 0;
@@ -1705,6 +1717,35 @@ __global__ __launch_bounds__(WG) void k_pcg_update(Dev d) {
     d.cam_part2[c] = rz;
     d.cam_part3[c] = rr;
   }
+}
+
+// One wavefront per problem, after each update (and after k_pcg_init_scalars)
+// when Dev::test_sep: the convergence test of k_pcg_q's wave 0 on the same
+// sums, in the same order, with the same writes, and the problem's flag into
+// the host's copy.  Taking it twice on the same sums changes nothing.
+__global__ __launch_bounds__(WG) void k_pcg_test(Dev d) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = blockIdx.x * (WG / 64) + w;
+  if (p >= d.P) return;  // uniform over the wavefront
+  int dn = d.done[p];
+  if (d.active[p] && !dn) {
+    double rz, rr;
+    problem_sum2(d, d.cam_part2, d.cam_part3, p, lane, rz, rr);
+    if (lane == 0) {
+      const int t = pcg_test(d, p, rz, rr);
+      d.rr[p] = rr;
+      if (t) {
+        d.done[p] = 1;
+        d.pstatus[p] = t == 1 ? 0 : 2;
+        d.pcg_skip[0] = 1;
+        dn = 1;
+      } else {
+        d.rz_next[p] = rz;
+        d.beta[p] = rz / d.rz[p];
+      }
+    }
+  }
+  if (lane == 0 && d.done_host) d.done_host[p] = d.active[p] ? dn : 1;
 }
 
 // One workgroup, once after the last iteration of a solve: the convergence
@@ -3215,6 +3256,8 @@ hipError_t launch_pcg_init(const Dev& d, const Launch& L) {
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_pcg_init_scalars, dim3(nblocks(d.P > 0 ? d.P : 1, WG / 64)), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
+  if (d.test_sep && d.P > 0) hipLaunchKernelGGL(k_pcg_test, dim3(nblocks(d.P, WG / 64)), dim3(WG), 0, L.stream, d);
+  LAUNCH_CHECK();
   return hipSuccess;
 }
 
@@ -3224,6 +3267,8 @@ hipError_t launch_pcg_vector(const Dev& d, const Launch& L) {
   hipLaunchKernelGGL(k_pcg_q, dim3(d.NC), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(d.NC, UPD_CAMS)), dim3(UPD_THREADS), 0, L.stream, d);
+  LAUNCH_CHECK();
+  if (d.test_sep && d.P > 0) hipLaunchKernelGGL(k_pcg_test, dim3(nblocks(d.P, WG / 64)), dim3(WG), 0, L.stream, d);
   LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -40,7 +40,7 @@ class Options(C.Structure):
         ("accept_ratio", C.c_double), ("max_lm_iters", C.c_int32), ("func_tol", C.c_double),
         ("pcg_max_iters", C.c_int32), ("pcg_rel_tol", C.c_double), ("pcg_check_every", C.c_int32),
         ("use_graph", C.c_int32), ("pcg_forcing_eta", C.c_double), ("landmark_blocks", C.c_int32),
-        ("huber_delta", C.c_double),
+        ("huber_delta", C.c_double), ("pcg_test_kernel", C.c_int32),
     ]
 
 
