@@ -549,8 +549,11 @@ def main():
     if sc and "skipped" in sc:
         sc_out = {"skipped": sc["skipped"]}
     elif sc:
-        def rejected(hist):
-            return sum(sum(1 for h in hh if not h["accepted"]) for hh in hist)
+        def rejected(hist, resolvable=False):
+            # resolvable: the model predicts a decrease of at least 1e-6 of the cost, which an FP32
+            # evaluation of the cost can tell apart from rounding (past that both solvers decide on noise)
+            return sum(sum(1 for h in hh if not h["accepted"] and (not resolvable or h["pred"] >= 1e-6 * h["cost"]))
+                       for hh in hist)
 
         def breakdowns(hist, only_rejected=False):  # PCG stopped by p^T A p <= 0 (or r^T z <= 0, non-finite)
             return sum(sum(1 for h in hh if h["pcg_status"] == "breakdown" and not (only_rejected and h["accepted"]))
@@ -564,6 +567,8 @@ def main():
             "final_costs": [sum(r.final_cost for r in reps) for reps, _ in sc["runs"]],
             "rejected_attempts": rejected(sc["runs"][-1][1]),
             "sqrt_ba_rejected_attempts": rejected(runs[-1][1]),
+            "rejected_resolvable": rejected(sc["runs"][-1][1], True),
+            "sqrt_ba_rejected_resolvable": rejected(runs[-1][1], True),
             "pcg_breakdowns": breakdowns(sc["runs"][-1][1]),
             "rejected_with_pcg_breakdown": breakdowns(sc["runs"][-1][1], True),
             "sqrt_ba_pcg_breakdowns": breakdowns(runs[-1][1]),
