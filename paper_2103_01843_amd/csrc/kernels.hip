@@ -65,6 +65,13 @@ __device__ __forceinline__ real team_sum(real v) {
   return v;
 }
 
+// The value v of lane j of the caller's team (j < TEAM <= 64).
+template <int TEAM>
+__device__ __forceinline__ real team_lane(real v, int j) {
+  static_assert(TEAM <= 64, "a team within one wavefront");
+  return __shfl(v, j, TEAM);
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
@@ -1776,8 +1783,9 @@ __global__ __launch_bounds__(WG) void k_pcg_final(Dev d) {
 // dx_l = S_l dx~_l, and the landmark's share of the predicted decrease of the
 // undamped linear model, summed over all its rotated rows:
 //   pred_l = -sum u (2 rho + u) + lambda |dx~_l|^2,   u = rows . (S dx_p, dx~_l).
-template <int TEAM, int NCG>
+template <int TEAM>
 __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, real* red4) {
+  static_assert(TEAM <= 64 && TEAM >= 2 * 3, "one wavefront at most; the smallest team holds the rows of k = 3");
   // the landmark's metadata is requested at once; the problem's flag only when
   // some problem is inactive
   const int prob = d.slot_prob[slot];
@@ -1788,32 +1796,40 @@ __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, re
   if (!d.all_active && !d.active[prob]) return;
   const int W = width_of(k);
   const int G = W >> 2;
+  const int n = 2 * k;
+  const real4* T = reinterpret_cast<const real4*>(d.poolT + toff);
+  const real4* B = reinterpret_cast<const real4*>(d.poolB + boff);
+  // the first batch of B rows and the rows' residuals are requested before the
+  // top-row work: a team has at least 2k lanes, so lane j holds rho of row j
+  // and lane 0 later takes them by a team shuffle (rows in batches of BS_RB,
+  // the next batch requested before the current one is reduced; rows past 2k
+  // re-read row 2k-1 and are not counted)
+  constexpr int BS_RB = 8;
+  const real* rho = d.rhoB + 2 * (size_t)obs0;
+  const real4* __restrict__ Bj = B + min(lane, G - 1);
+  real4 c[BS_RB];
+#pragma unroll
+  for (int i = 0; i < BS_RB; ++i) c[i] = Bj[(size_t)min(i, n - 1) * G];
+  const real rho_l = rho[min(lane, n - 1)];
   const real* lmd = d.lmd + (size_t)slot * LMD_STRIDE;
   const real lam = (real)d.lambda[prob];
   Givens6 Gv;
   real Rh[3][3], qrh[3], dr[3];
   damping_rotations(lmd, sqrt(lam), Gv, Rh, qrh, dr);
-  const real4* T = reinterpret_cast<const real4*>(d.poolT + toff);
-  const real4* B = reinterpret_cast<const real4*>(d.poolB + boff);
-  real4 pv[NCG];
+  real4 pv = make_real4(0.f, 0.f, 0.f, 0.f);
   real u0 = 0.f, u1 = 0.f, u2 = 0.f;
-#pragma unroll
-  for (int j = 0; j < NCG; ++j) {
-    const int g = lane + TEAM * j;
-    pv[j] = make_real4(0.f, 0.f, 0.f, 0.f);
-    if (g < G) {
-      pv[j] = gather_cols(d, d.vzs, obs0, k, g);
-      const real4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
-      real a[3], b[3];
-      a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b);
-      u0 += a[0] * pv[j].x; u1 += a[1] * pv[j].x; u2 += a[2] * pv[j].x;
-      a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b);
-      u0 += a[0] * pv[j].y; u1 += a[1] * pv[j].y; u2 += a[2] * pv[j].y;
-      a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, b);
-      u0 += a[0] * pv[j].z; u1 += a[1] * pv[j].z; u2 += a[2] * pv[j].z;
-      a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, b);
-      u0 += a[0] * pv[j].w; u1 += a[1] * pv[j].w; u2 += a[2] * pv[j].w;
-    }
+  if (lane < G) {
+    pv = gather_cols(d, d.vzs, obs0, k, lane);
+    const real4 t0 = T[lane], t1 = T[G + lane], t2 = T[2 * G + lane];
+    real a[3], b[3];
+    a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b);
+    u0 += a[0] * pv.x; u1 += a[1] * pv.x; u2 += a[2] * pv.x;
+    a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b);
+    u0 += a[0] * pv.y; u1 += a[1] * pv.y; u2 += a[2] * pv.y;
+    a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, b);
+    u0 += a[0] * pv.z; u1 += a[1] * pv.z; u2 += a[2] * pv.z;
+    a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, b);
+    u0 += a[0] * pv.w; u1 += a[1] * pv.w; u2 += a[2] * pv.w;
   }
   u0 = tsum<TEAM>(u0, red4);
   u1 = tsum<TEAM>(u1, red4);
@@ -1832,46 +1848,26 @@ __device__ __forceinline__ void backsub_one(const Dev& d, int slot, int lane, re
     pred = -(double)(ut0 * (2.f * qrh[0] + ut0)) - (double)(ut1 * (2.f * qrh[1] + ut1)) -
            (double)(ut2 * (2.f * qrh[2] + ut2)) + (double)lam * ((double)x0 * x0 + (double)x1 * x1 + (double)x2 * x2);
   }
-  const real* rho = d.rhoB + 2 * (size_t)obs0;
-  if constexpr (NCG == 1) {
-    // rows in batches of BS_RB, the next batch requested before the current one
-    // is reduced (rows past 2k re-read row 2k-1 and are not counted)
-    constexpr int BS_RB = 8;
-    const int n = 2 * k;
-    const real4* __restrict__ Bj = B + min(lane, G - 1);
-    real4 c[BS_RB];
+  for (int r = 0; r < n; r += BS_RB) {
+    real4 nx[BS_RB];
 #pragma unroll
-    for (int i = 0; i < BS_RB; ++i) c[i] = Bj[(size_t)min(i, n - 1) * G];
-    for (int r = 0; r < n; r += BS_RB) {
-      real4 nx[BS_RB];
+    for (int i = 0; i < BS_RB; ++i) nx[i] = c[i];
+    if (r + BS_RB < n) {
 #pragma unroll
-      for (int i = 0; i < BS_RB; ++i) nx[i] = c[i];
-      if (r + BS_RB < n) {
-#pragma unroll
-        for (int i = 0; i < BS_RB; ++i) nx[i] = Bj[(size_t)min(r + BS_RB + i, n - 1) * G];
-      }
-      real y[BS_RB];
-#pragma unroll
-      for (int i = 0; i < BS_RB; ++i) y[i] = tsum<TEAM>(dot4(c[i], pv[0]), red4);
-      if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < BS_RB; ++i)
-          if (r + i < n) pred -= (double)(y[i] * (2.f * rho[r + i] + y[i]));
-      }
-#pragma unroll
-      for (int i = 0; i < BS_RB; ++i) c[i] = nx[i];
+      for (int i = 0; i < BS_RB; ++i) nx[i] = Bj[(size_t)min(r + BS_RB + i, n - 1) * G];
     }
-  } else {
-    for (int r = 0; r < 2 * k; ++r) {
-      real y = 0.f;
+    real y[BS_RB], rr[BS_RB];
 #pragma unroll
-      for (int j = 0; j < NCG; ++j) {
-        const int g = lane + TEAM * j;
-        if (g < G) y += dot4(B[(size_t)r * G + g], pv[j]);
-      }
-      y = tsum<TEAM>(y, red4);
-      if (lane == 0) pred -= (double)(y * (2.f * rho[r] + y));
+    for (int i = 0; i < BS_RB; ++i) y[i] = tsum<TEAM>(dot4(c[i], pv), red4);
+#pragma unroll
+    for (int i = 0; i < BS_RB; ++i) rr[i] = team_lane<TEAM>(rho_l, min(r + i, n - 1));
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < BS_RB; ++i)
+        if (r + i < n) pred -= (double)(y[i] * (2.f * rr[i] + y[i]));
     }
+#pragma unroll
+    for (int i = 0; i < BS_RB; ++i) c[i] = nx[i];
   }
   if (lane == 0) {
     const real* sl = lmd + LMD_SL;
@@ -1893,10 +1889,11 @@ __device__ __forceinline__ double backsub_b_rows(const real4* __restrict__ B, in
                                                  const real* __restrict__ rho, int rbeg, int rend, int w, int lane) {
   double pred = 0.0;
   if (rbeg + w >= rend) return pred;  // uniform over the wavefront
-  auto load = [&](int r, real4 (&b)[RS][NCG]) {
+  auto load = [&](int r, real4 (&b)[RS][NCG], real (&rh)[RS]) {
 #pragma unroll
     for (int i = 0; i < RS; ++i) {
       const int rr = min(r + 4 * i, rend - 1);
+      rh[i] = rho[rr];
 #pragma unroll
       for (int j = 0; j < NCG; ++j) {
         b[i][j] = make_real4(0.f, 0.f, 0.f, 0.f);
@@ -1905,16 +1902,20 @@ __device__ __forceinline__ double backsub_b_rows(const real4* __restrict__ B, in
     }
   };
   real4 b[RS][NCG];
-  load(rbeg + w, b);
+  real rh[RS];
+  load(rbeg + w, b, rh);
   for (int r = rbeg + w; r < rend; r += 4 * RS) {
     real4 nb[RS][NCG];
+    real nrh[RS];
     if (r + 4 * RS < rend) {
-      load(r + 4 * RS, nb);
+      load(r + 4 * RS, nb, nrh);
     } else {
 #pragma unroll
-      for (int i = 0; i < RS; ++i)
+      for (int i = 0; i < RS; ++i) {
+        nrh[i] = rh[i];
 #pragma unroll
         for (int j = 0; j < NCG; ++j) nb[i][j] = b[i][j];
+      }
     }
 #pragma unroll
     for (int i = 0; i < RS; ++i) {
@@ -1922,12 +1923,14 @@ __device__ __forceinline__ double backsub_b_rows(const real4* __restrict__ B, in
 #pragma unroll
       for (int j = 0; j < NCG; ++j) y += dot4(b[i][j], pv[j]);
       y = wave_sum_f(y);
-      if (lane == 0 && r + 4 * i < rend) pred -= (double)(y * (2.f * rho[r + 4 * i] + y));
+      if (lane == 0 && r + 4 * i < rend) pred -= (double)(y * (2.f * rh[i] + y));
     }
 #pragma unroll
-    for (int i = 0; i < RS; ++i)
+    for (int i = 0; i < RS; ++i) {
+      rh[i] = nrh[i];
 #pragma unroll
       for (int j = 0; j < NCG; ++j) b[i][j] = nb[i][j];
+    }
   }
   return pred;
 }
@@ -2109,7 +2112,7 @@ struct BacksubF {
     if constexpr (TEAM == 256)
       backsub_large<4, 2>(d, slot, predw);
     else
-      backsub_one<TEAM, 1>(d, slot, lane, red4);
+      backsub_one<TEAM>(d, slot, lane, red4);
   }
 };
 
