@@ -606,7 +606,7 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
   uint64_t o_sc = fr(9 * NC), o_jtj = fr(54 * NC);
   uint64_t o_v[6];
   for (int i = 0; i < 6; ++i) o_v[i] = fr(9 * NC);
-  uint64_t o_minv = fr(81 * NC), o_ob = fr(54 * NO), o_dxl = fr(3 * NL);
+  uint64_t o_minv = fr(81 * NC), o_ob = fr(54 * NO), o_dxl = fr(3 * NL), o_tt = fr(implicit ? 0 : 32 * NO);
   uint64_t o_cp = f64(NC), o_cp2 = f64(NC), o_cp3 = f64(NC), o_lp = f64(NL);
   int64_t longest = 1;  // longest per-problem range of landmark or camera partials
   for (int64_t p = 0; p < (int64_t)P; ++p)
@@ -650,6 +650,7 @@ uint64_t layout(const HostData& h, int mode, void* base, Dev* d) {
     t.vx = at<real>(base, o_v[0]); t.vr = at<real>(base, o_v[1]); t.vz = at<real>(base, o_v[2]);
     t.vp = at<real>(base, o_v[3]); t.vq = at<real>(base, o_v[4]); t.vb = at<real>(base, o_v[5]);
     t.minv = at<real>(base, o_minv); t.obsbuf = at<real>(base, o_ob); t.dxl = at<real>(base, o_dxl);
+    t.ttop = implicit ? nullptr : at<real>(base, o_tt);
     t.cam_part = at<double>(base, o_cp); t.cam_part2 = at<double>(base, o_cp2); t.cam_part3 = at<double>(base, o_cp3);
     t.lm_part = at<double>(base, o_lp);
     t.psum = at<double>(base, o_psum);

@@ -139,8 +139,11 @@ struct Dev {
                          // host between chunks of iterations without a copy
   int32_t* pcg_skip;     // 1 int: some problem is inactive or done in the running PCG solve (the
                          // products then test a landmark's problem before reading its data)
-  real* obsbuf;  // NO * 54 elements: per-observation preconditioner terms; the product outputs
-                  // reuse it in per-landmark aligned regions (slot_zoff)
+  real* obsbuf;  // NO * 54 elements: per-observation preconditioner terms (implicit blocks and the
+                  // explicit Schur complement); the product outputs reuse it in per-landmark aligned
+                  // regions (slot_zoff)
+  real* ttop;    // explicit blocks: NO * 32 elements, per observation the damped top rows' 3 x 9
+                 // camera entries (row-major), then q^ (3) and 2 zeros; written by the damping
   real* dxl;     // NL * 3, unscaled landmark increment
   double* cam_part;  // NC, per-camera partial sums
   double* cam_part2; // NC

@@ -742,9 +742,19 @@ __device__ __forceinline__ void rotate_column(const Givens6& G, real t[3], real 
 
 // Damping of every landmark block from its stored undamped top rows (so a new
 // lambda never needs a new QR): writes the three damping rows of B, their
-// residuals, and the damped R and Q1^T r into the landmark record.
+// residuals, and the damped R and Q1^T r into the landmark record; the same
+// rotations give the damped top rows, whose camera entries go to the
+// per-observation records of the block-Jacobi stage (ttop).
+// Observations per chunk of the per-observation records (a multiple of 4, so
+// that every chunk starts on a column group), and LDS floats per team.
+__host__ __device__ constexpr int damp_chunk(int team) { return team >= 256 ? 64 : (team >= 16 ? team / 4 : 4); }
+__host__ __device__ constexpr int damp_lds(int team) { return 3 * 9 * damp_chunk(team); }
+constexpr int DAMP_LDS = (WG / 8) * damp_lds(8);  // the largest over the team sizes
+static_assert(DAMP_LDS >= (WG / 16) * damp_lds(16) && DAMP_LDS >= (WG / 32) * damp_lds(32) &&
+              DAMP_LDS >= (WG / 64) * damp_lds(64) && DAMP_LDS >= damp_lds(256), "LDS of the damping");
+
 template <int TEAM>
-__device__ __forceinline__ void damp_one(const Dev& d, int slot, int lane, const uint8_t* mask) {
+__device__ __forceinline__ void damp_one(const Dev& d, int slot, int lane, const uint8_t* mask, real* lds) {
   const int prob = d.slot_prob[slot];
   if (mask && !mask[prob]) return;
   const int k = d.slot_k[slot];
@@ -765,17 +775,48 @@ __device__ __forceinline__ void damp_one(const Dev& d, int slot, int lane, const
   if (lane < 3) d.rhoB[2 * (size_t)obs0 + 2 * k - 3 + lane] = dr[lane];
   const real4* T = reinterpret_cast<const real4*>(d.poolT + d.slot_toff[slot]);
   real4* B = reinterpret_cast<real4*>(d.poolB + d.slot_boff[slot] + (size_t)(2 * k - 3) * W);
-  for (int g = lane; g < G; g += TEAM) {
-    const real4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
-    real a[3], b[3];
-    real4 o0, o1, o2;
-    a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b); o0.x = b[0]; o1.x = b[1]; o2.x = b[2];
-    a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b); o0.y = b[0]; o1.y = b[1]; o2.y = b[2];
-    a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, b); o0.z = b[0]; o1.z = b[1]; o2.z = b[2];
-    a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, b); o0.w = b[0]; o1.w = b[1]; o2.w = b[2];
-    B[g] = o0;
-    B[G + g] = o1;
-    B[2 * G + g] = o2;
+  // the damped top rows of a chunk of CH observations go to LDS (3 rows of 9 CH
+  // columns), from which the chunk's records leave as whole float4s
+  constexpr int CH = damp_chunk(TEAM), CW = 9 * CH;
+  real4* tt = reinterpret_cast<real4*>(d.ttop + (size_t)obs0 * 32);  // the landmark's k records
+  for (int j0 = 0; j0 < k; j0 += CH) {
+    const int nj = min(CH, k - j0);
+    const int g0 = (9 * j0) >> 2, g1 = min(G, (9 * (j0 + nj) + 3) >> 2);
+    for (int gg = lane; gg < g1 - g0; gg += TEAM) {
+      const int g = g0 + gg;
+      const real4 t0 = T[g], t1 = T[G + g], t2 = T[2 * G + g];
+      real a[3], b[3];
+      real4 o0, o1, o2, h0, h1, h2;  // damping rows, damped top rows
+      a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, b); o0.x = b[0]; o1.x = b[1]; o2.x = b[2];
+      h0.x = a[0]; h1.x = a[1]; h2.x = a[2];
+      a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, b); o0.y = b[0]; o1.y = b[1]; o2.y = b[2];
+      h0.y = a[0]; h1.y = a[1]; h2.y = a[2];
+      a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, b); o0.z = b[0]; o1.z = b[1]; o2.z = b[2];
+      h0.z = a[0]; h1.z = a[1]; h2.z = a[2];
+      a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, b); o0.w = b[0]; o1.w = b[1]; o2.w = b[2];
+      h0.w = a[0]; h1.w = a[1]; h2.w = a[2];
+      B[g] = o0;
+      B[G + g] = o1;
+      B[2 * G + g] = o2;
+      if (4 * gg < CW) {  // the chunk's last group may run past 9 CH columns (padding)
+        reinterpret_cast<real4*>(lds)[gg] = h0;
+        reinterpret_cast<real4*>(lds + CW)[gg] = h1;
+        reinterpret_cast<real4*>(lds + 2 * CW)[gg] = h2;
+      }
+    }
+    team_sync<TEAM>();
+    for (int p = lane; p < 8 * nj; p += TEAM) {  // float4 q of record jj
+      const int jj = p >> 3, q = p & 7;
+      real v[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int e = 4 * q + c;
+        const int i = e / 9, a = e - 9 * i;
+        v[c] = e < 27 ? lds[i * CW + 9 * jj + a] : (e < 30 ? qrh[e - 27] : 0.f);
+      }
+      tt[8 * (j0 + jj) + q] = make_real4(v[0], v[1], v[2], v[3]);
+    }
+    team_sync<TEAM>();
   }
 }
 
@@ -790,18 +831,17 @@ __device__ __forceinline__ void damp_one(const Dev& d, int slot, int lane, const
 //   B_j^T rho_B = J_j^T r_j - T^_j^T q^,
 // T^ the damped top rows (rotated from the stored undamped rows) and q^ the
 // damped Q1^T r.  The camera sums of J_j^T J_j and J_j^T r_j come from the
-// linearization (cam_jtj); here each observation gets T^_j^T T^_j (45 upper
-// entries) and T^_j^T q^ (9), written to obsbuf[obs][0..53], which
-// k_precond_cam subtracts.  A landmark is read as its 3 top rows instead of
-// its 2k B rows.  The subtraction is of quantities of the same order (B keeps
-// (2k - 3) / 2k of a slab's squared norm on average); per camera the FP32
-// blocks agree with the direct sum over the B rows to the same 3e-7.
-//
-// Each team rotates its landmark's top rows into LDS (lanes over column
-// groups), then lane o sums observation o over the three rows, and the k x 54
-// outputs (contiguous in obsbuf) leave through LDS as one stream of float2s.
+// linearization (cam_jtj); the damping, which rotates the top rows anyway,
+// writes each observation's T^_j (3 x 9) and q^ to its 32-element record
+// (ttop), and k_precond_cam forms T^_j^T T^_j (45 upper entries) and
+// T^_j^T q^ (9) per observation and subtracts their sums.  A landmark costs
+// its 3 top rows instead of its 2k B rows, read once by the damping.  The
+// subtraction is of quantities of the same order (B keeps (2k - 3) / 2k of a
+// slab's squared norm on average); per camera the FP32 blocks agree with the
+// direct sum over the B rows to the same 3e-7.
 
-// The 54 terms of one observation slab from the three damped top rows in LDS.
+// The 54 terms of one observation slab from its three damped top rows (row i
+// at rows[i W], 9 entries).
 __device__ __forceinline__ void top_gram(const real* __restrict__ rows, int W, const real (&qh)[3], real (&g)[54]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -814,90 +854,6 @@ __device__ __forceinline__ void top_gram(const real* __restrict__ rows, int W, c
       g[45 + a] += b[a] * qh[i];
 #pragma unroll
       for (int c = a; c < 9; ++c) g[e++] += b[a] * b[c];
-    }
-  }
-}
-
-// LDS floats per team: the three damped top rows (16-byte aligned, plus 4 so
-// that the teams of a wavefront start on different banks), or the team's
-// k x 54 outputs, whichever is larger.
-__host__ __device__ constexpr int pt_stride(int kmax) {
-  return (3 * ((9 * kmax + 3) & ~3) + 4) > (54 * kmax + 2) ? (3 * ((9 * kmax + 3) & ~3) + 4) : (54 * kmax + 2);
-}
-__host__ __device__ constexpr int pt_lds(int cls) { return (WG / class_team(cls)) * pt_stride(class_kmax(cls)); }
-constexpr int PT_LDS = pt_lds(0) > pt_lds(1) ? (pt_lds(0) > pt_lds(2) ? (pt_lds(0) > pt_lds(3) ? pt_lds(0) : pt_lds(3))
-                                                                     : (pt_lds(2) > pt_lds(3) ? pt_lds(2) : pt_lds(3)))
-                                             : (pt_lds(1) > pt_lds(2) ? (pt_lds(1) > pt_lds(3) ? pt_lds(1) : pt_lds(3))
-                                                                     : (pt_lds(2) > pt_lds(3) ? pt_lds(2) : pt_lds(3)));
-constexpr int PT_LDS_ALL = PT_LDS > pt_lds(4) ? PT_LDS : pt_lds(4);
-
-// Team TEAM of the workgroup takes slot s0 + team (every team of a workgroup
-// belongs to one class; slots past send and landmarks of inactive problems do
-// no work but join both barriers).  STAGE_OUT: the outputs leave through LDS
-// (every class but 5, whose k x 54 outputs would not fit).
-template <int TEAM, int KMAX, bool STAGE_OUT>
-__device__ __forceinline__ void precond_top(const Dev& d, int s0, int send, real* lds) {
-  const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
-  const int slot = s0 + team;
-  const bool in = slot < send;
-  const int sl = in ? slot : s0;
-  const int prob = d.slot_prob[sl];
-  const int kin = d.slot_k[sl];
-  const int obs0 = d.slot_obs0[sl];
-  const int64_t toff = d.slot_toff[sl];
-  const int k = (in && (d.all_active || d.active[prob])) ? kin : 0;
-  const int W = width_of(k), G = W >> 2;
-  real* tb = lds + team * pt_stride(KMAX);
-  real qh[3] = {0.f, 0.f, 0.f};
-  if (k) {
-    const real* lmd = d.lmd + (size_t)sl * LMD_STRIDE;
-    Givens6 Gv;
-    real Rh[3][3], dr[3];
-    damping_rotations(lmd, sqrt((real)d.lambda[prob]), Gv, Rh, qh, dr);
-    const real4* __restrict__ T = reinterpret_cast<const real4*>(d.poolT + toff);
-    real4* t4 = reinterpret_cast<real4*>(tb);
-    for (int gi = lane; gi < G; gi += TEAM) {
-      const real4 t0 = T[gi], t1 = T[G + gi], t2 = T[2 * G + gi];
-      real a[3], z[3];
-      real4 o0, o1, o2;
-      a[0] = t0.x; a[1] = t1.x; a[2] = t2.x; rotate_column(Gv, a, z); o0.x = a[0]; o1.x = a[1]; o2.x = a[2];
-      a[0] = t0.y; a[1] = t1.y; a[2] = t2.y; rotate_column(Gv, a, z); o0.y = a[0]; o1.y = a[1]; o2.y = a[2];
-      a[0] = t0.z; a[1] = t1.z; a[2] = t2.z; rotate_column(Gv, a, z); o0.z = a[0]; o1.z = a[1]; o2.z = a[2];
-      a[0] = t0.w; a[1] = t1.w; a[2] = t2.w; rotate_column(Gv, a, z); o0.w = a[0]; o1.w = a[1]; o2.w = a[2];
-      t4[gi] = o0;
-      t4[G + gi] = o1;
-      t4[2 * G + gi] = o2;
-    }
-  }
-  __syncthreads();
-  constexpr int OPL = (KMAX + TEAM - 1) / TEAM;  // observations per lane
-  real g[OPL][54];
-#pragma unroll
-  for (int m = 0; m < OPL; ++m) {
-#pragma unroll
-    for (int e = 0; e < 54; ++e) g[m][e] = 0.f;
-    const int o = lane + TEAM * m;
-    if (o < k) top_gram(tb + 9 * o, W, qh, g[m]);
-  }
-  if constexpr (STAGE_OUT) {
-    static_assert(OPL == 1, "staged outputs: one observation per lane");
-    __syncthreads();
-    if (lane < k) {
-#pragma unroll
-      for (int e = 0; e < 54; ++e) tb[54 * lane + e] = g[0][e];
-    }
-    __syncthreads();
-    real2* dst = reinterpret_cast<real2*>(d.obsbuf + (size_t)obs0 * 54);  // 8-byte aligned
-    for (int j = lane; j < 27 * k; j += TEAM) dst[j] = reinterpret_cast<const real2*>(tb)[j];
-  } else {
-#pragma unroll
-    for (int m = 0; m < OPL; ++m) {
-      const int o = lane + TEAM * m;
-      if (o < k) {
-        real2* dst = reinterpret_cast<real2*>(d.obsbuf + (size_t)(obs0 + o) * 54);
-#pragma unroll
-        for (int e = 0; e < 27; ++e) dst[e] = make_real2(g[m][2 * e], g[m][2 * e + 1]);
-      }
     }
   }
 }
@@ -915,10 +871,29 @@ __global__ __launch_bounds__(64) void k_precond_cam(Dev d) {
 #pragma unroll
   for (int e = 0; e < 54; ++e) acc[e] = 0.f;
   const int b = d.cam_obs_off[c], e1 = d.cam_obs_off[c + 1];
-  for (int i = b + lane; i < e1; i += 64) {
-    const real* src = d.obsbuf + (size_t)d.cam_obs_idx[i] * 54;
+  if (!d.implicit) {  // explicit blocks: the top-row terms from the damping's records
+    for (int i = b + lane; i < e1; i += 64) {
+      const real4* rec = reinterpret_cast<const real4*>(d.ttop + (size_t)d.cam_obs_idx[i] * 32);
+      real t[32];
 #pragma unroll
-    for (int e = 0; e < 54; ++e) acc[e] += src[e];
+      for (int q = 0; q < 8; ++q) {
+        const real4 v = rec[q];
+        t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
+      }
+      const real qh[3] = {t[27], t[28], t[29]};
+      real g[54];
+#pragma unroll
+      for (int e = 0; e < 54; ++e) g[e] = 0.f;
+      top_gram(t, 9, qh, g);
+#pragma unroll
+      for (int e = 0; e < 54; ++e) acc[e] += g[e];
+    }
+  } else {
+    for (int i = b + lane; i < e1; i += 64) {
+      const real* src = d.obsbuf + (size_t)d.cam_obs_idx[i] * 54;
+#pragma unroll
+      for (int e = 0; e < 54; ++e) acc[e] += src[e];
+    }
   }
 #pragma unroll
   for (int e = 0; e < 54; ++e) acc[e] = wave_sum_f(acc[e]);
@@ -2070,39 +2045,24 @@ __global__ __launch_bounds__(WG) void k_marginalize_chunks(Dev d, const uint8_t*
 struct DampF {
   const Dev& d;
   const uint8_t* mask;
+  real* lds;
   template <int TEAM, int CLS>
-  __device__ __forceinline__ void run(int slot, int lane, int) const { damp_one<TEAM>(d, slot, lane, mask); }
+  __device__ __forceinline__ void run(int slot, int lane, int team) const {
+    damp_one<TEAM>(d, slot, lane, mask, lds + team * damp_lds(TEAM));
+  }
 };
 
 __global__ __launch_bounds__(WG) void k_damp(Dev d, ClassGrid m, const uint8_t* mask) {
-  class_dispatch(m, DampF{d, mask});
+  __shared__ __align__(16) real lds[DAMP_LDS];
+  class_dispatch(m, DampF{d, mask, lds});
 }
 
 __global__ __launch_bounds__(WG) void k_damp_huge(Dev d, int slot0, const uint8_t* mask) {
-  damp_one<256>(d, slot0 + blockIdx.x, threadIdx.x, mask);
+  __shared__ __align__(16) real lds[damp_lds(256)];
+  damp_one<256>(d, slot0 + blockIdx.x, threadIdx.x, mask, lds);
 }
 
 // Classes 4..0 of m (launch order; one landmark per workgroup for class 4).
-__global__ __launch_bounds__(WG) void k_precond_obs(Dev d, ClassGrid m) {
-  __shared__ __align__(16) real lds[PT_LDS_ALL];
-  int b = blockIdx.x;
-  if (b < m.nblk[0]) { precond_top<256, class_kmax(4), true>(d, m.first[0] + b, m.end[0], lds); return; }
-  b -= m.nblk[0];
-  if (b < m.nblk[1]) { precond_top<64, class_kmax(3), true>(d, m.first[1] + b * (WG / 64), m.end[1], lds); return; }
-  b -= m.nblk[1];
-  if (b < m.nblk[2]) { precond_top<32, class_kmax(2), true>(d, m.first[2] + b * (WG / 32), m.end[2], lds); return; }
-  b -= m.nblk[2];
-  if (b < m.nblk[3]) { precond_top<16, class_kmax(1), true>(d, m.first[3] + b * (WG / 16), m.end[3], lds); return; }
-  b -= m.nblk[3];
-  precond_top<8, class_kmax(0), true>(d, m.first[4] + b * (WG / 8), m.end[4], lds);
-}
-
-// Class 5 (one workgroup per landmark, on the side stream).
-__global__ __launch_bounds__(WG) void k_precond_obs_huge(Dev d, int slot0, int send) {
-  __shared__ __align__(16) real lds[3 * ((9 * class_kmax(5) + 3) & ~3) + 4];
-  precond_top<256, class_kmax(5), false>(d, slot0 + blockIdx.x, send, lds);
-}
-
 struct BacksubF {
   const Dev& d;
   real* red4;
@@ -3112,7 +3072,6 @@ hipError_t launch_damp(const Dev& d, const Launch& L, const uint8_t* mask) {
 }
 
 hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
-  const WorkClass* w = L.wc;
   if (d.sc) {
     if (d.NO) hipLaunchKernelGGL(k_sc_precond_obs, dim3(nblocks(d.NO, WG)), dim3(WG), 0, L.stream, d);
     LAUNCH_CHECK();
@@ -3127,19 +3086,7 @@ hipError_t launch_precond_rhs(const Dev& d, const Launch& L) {
     LAUNCH_CHECK();
     return hipSuccess;
   }
-  int n = 0;
-  const ClassGrid m = class_grid(L, &n);  // classes 0..4
-  const bool side = w[5].slots && n && L.side && L.fork && L.join;
-  hipError_t e = side_fork(L, side);
-  if (e != hipSuccess) return e;
-  if (w[5].slots)
-    hipLaunchKernelGGL(k_precond_obs_huge, dim3(w[5].slots), dim3(WG), 0, side ? L.side : L.stream, d,
-                       w[5].first_slot, w[5].first_slot + w[5].slots);
-  LAUNCH_CHECK();
-  if (n) hipLaunchKernelGGL(k_precond_obs, dim3(n), dim3(WG), 0, L.stream, d, m);
-  LAUNCH_CHECK();
-  e = side_join(L, side);
-  if (e != hipSuccess) return e;
+  // explicit blocks: the per-observation records come from the damping
   hipLaunchKernelGGL(k_precond_cam, dim3(d.NC), dim3(64), 0, L.stream, d);
   LAUNCH_CHECK();
   return hipSuccess;
