@@ -108,12 +108,14 @@ def test_invalid_delta_is_rejected():
 # side carries an FP32 error of 8.5e-5 relative after the first step, the stored
 # FP32 blocks' rounding under cancellation), so the truncated step, and every
 # decision after it, depends on rounding.  Measured at 20 attempts: explicit FP32
-# 415,375 (+1.28e-3), implicit FP32 415,001 (+3.9e-4), FP64 library 414,996
+# 414,982 to 415,375 (+3e-4 to +1.28e-3 with successive kernel versions, whose
+# rounding differs), implicit FP32 415,001 (+3.9e-4), FP64 library 414,996
 # (+3.6e-4) against the oracle's 414,845; the FP64 library itself departs from the
 # oracle's accept/reject sequence at attempt 8.
 EXPLICIT32_SPLIT = pytest.mark.xfail(strict=False, reason=(
-    "FP32 trajectory split at attempt 1 (truncated PCG at the 500-iteration cap): explicit FP32 ends 1.28e-3 "
-    "above the oracle at 20 attempts; implicit FP32 and the FP64 library end within 4e-4"))
+    "FP32 trajectory split at attempt 1 (truncated PCG at the 500-iteration cap): explicit FP32 ends 3e-4 to "
+    "1.3e-3 above the oracle at 20 attempts, depending on rounding; implicit FP32 and the FP64 library end "
+    "within 4e-4"))
 
 
 @pytest.mark.parametrize("form", [pytest.param("explicit32", marks=EXPLICIT32_SPLIT), "implicit32", "explicit64"])
