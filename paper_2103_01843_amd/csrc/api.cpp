@@ -86,6 +86,9 @@ struct Arena {
 
 }  // namespace
 
+// slices of 8 bytes per problem in the pinned staging buffer (pinned_slice)
+constexpr int PINNED_SLICES = 10;
+
 struct sqrtba_ctx {
   sqrtba_options opt;
   hipStream_t stream = nullptr;
@@ -110,6 +113,7 @@ struct sqrtba_ctx {
   // pipeline state
   bool linearized = false, marginalized = false, damped = false, solved = false, backsubbed = false,
        updated = false;
+  bool solve_pending = false;  // a solve's outcome is on its way to the pinned slices 5, 8 and 9
   std::vector<uint8_t> active;
   // PCG graph
   hipGraphExec_t graph = nullptr;
@@ -856,7 +860,7 @@ int upload(sqrtba_ctx* c) {
   c->L.side = c->side;
   c->L.fork = c->ev_fork;
   c->L.join = c->ev_join;
-  const size_t need = (size_t)h.P * 64 + 64;
+  const size_t need = (size_t)h.P * 8 * PINNED_SLICES + 64;
   if (c->pinned_bytes < need) {
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
@@ -957,9 +961,11 @@ int readback(sqrtba_ctx* c, const T* dev, T* out, bool sync = true) {
   return SQRTBA_OK;
 }
 
-// The pinned staging buffer holds 8 slices of 8 bytes per problem: slice 0
-// for readback, slices 0..3 for readback_all, 4 for a deferred copy of the
-// model decrease, 6 for the accept mask and 7 for lambda.
+// The pinned staging buffer holds PINNED_SLICES slices of 8 bytes per problem:
+// slice 0 for readback, slices 0..3 for readback_all, 4 for a deferred copy of
+// the model decrease, 5 (PCG iteration counts, then statuses), 8 (r.r) and 9
+// (r0.r0) for a deferred copy of a solve's outcome, 6 for the accept mask and 7
+// for lambda.
 char* pinned_slice(sqrtba_ctx* c, int j) { return static_cast<char*>(c->pinned) + (size_t)8 * c->h.P * j; }
 
 // Several per-problem arrays copied back with one wait (array j to slice j).
@@ -1178,10 +1184,17 @@ int run_pcg(sqrtba_ctx* c, int cap) {
   }
   LAUNCH(c, launch_pcg_init(c->d, c->L));
   std::vector<int32_t> done(P);
-  TRY(readback(c, c->d.done, done.data()));
-  // the update kernels of this solve overwrite every flag before the host reads it;
-  // until then a stale value can only be 0 (one more chunk, whose kernels exit at once)
-  if (c->done_host) std::memset(c->done_host, 0, sizeof(int32_t) * P);
+  if (c->done_host) {
+    // no wait here: every active problem counts as running until the first
+    // chunk's flags arrive (a problem the start kernels found done, e.g. with a
+    // zero right-hand side, costs one chunk whose kernels exit at once).  The
+    // kernels of this solve overwrite every flag before the host reads it;
+    // until then a stale value can only be 0 (one more chunk).
+    for (int p = 0; p < P; ++p) done[p] = c->active[p] ? 0 : 1;
+    std::memset(c->done_host, 0, sizeof(int32_t) * P);
+  } else {
+    TRY(readback(c, c->d.done, done.data()));
+  }
   auto all_done = [&]() {
     for (int p = 0; p < P; ++p)
       if (!done[p]) return false;
@@ -1257,7 +1270,38 @@ int precond_stage(sqrtba_ctx* c) {
   });
 }
 
-int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
+// The per-problem outputs of a solve from its outcome arrays (and, after a
+// learned run with fallbacks, the kept problems' outcomes of the learned run).
+void finish_solve(sqrtba_ctx* c, bool learned, const std::vector<uint8_t>& fell_back, std::vector<int32_t>& its,
+                  std::vector<int32_t>& st, std::vector<double>& rr, std::vector<double>& rr0,
+                  const std::vector<int32_t>& kept_its, const std::vector<int32_t>& kept_st,
+                  const std::vector<double>& kept_rr, const std::vector<double>& kept_rr0, int32_t* iters,
+                  double* rel_res, int32_t* status) {
+  const int P = c->h.P;
+  auto& L = c->ln;
+  if (!kept_its.empty())
+    for (int p = 0; p < P; ++p)
+      if (c->active[p] && !fell_back[p]) {
+        its[p] = kept_its[p];
+        st[p] = kept_st[p];
+        rr[p] = kept_rr[p];
+        rr0[p] = kept_rr0[p];
+      }
+  for (int p = 0; p < P; ++p) {
+    if (c->active[p] && (!learned || fell_back[p])) {
+      L.last_plain_iters[p] = its[p];
+      L.last_plain_status[p] = st[p];
+    }
+    if (iters) iters[p] = its[p];
+    if (status) status[p] = st[p];
+    if (rel_res) rel_res[p] = rr0[p] > 0 ? std::sqrt(std::max(rr[p], 0.0) / rr0[p]) : 0.0;
+  }
+}
+
+// sync = false (inside the LM loop, plain block-Jacobi only): the outcome
+// arrays are copied to pinned slices 5, 8 and 9 without a wait, and
+// collect_solve turns them into the outputs after the caller's next wait.
+int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status, bool sync = true) {
   if (!c->damped) return fail(c, SQRTBA_E_STATE, "solve needs damp");
   const int P = c->h.P;
   auto& L = c->ln;
@@ -1329,29 +1373,40 @@ int do_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
     TRY(run_pcg(c, c->opt.pcg_max_iters));
   }
   L.cur_solve = -1;
+  c->solved = true;
+  c->backsubbed = c->updated = false;
+  if (!sync && !learned) {
+    const size_t P4 = sizeof(int32_t) * P, P8 = sizeof(double) * P;
+    HIP_TRY(c, hipMemcpyAsync(pinned_slice(c, 5), c->d.iters, P4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(pinned_slice(c, 5) + P4, c->d.pstatus, P4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(pinned_slice(c, 8), c->d.rr, P8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(pinned_slice(c, 9), c->d.rr0, P8, hipMemcpyDeviceToHost, c->stream));
+    c->solve_pending = true;
+    flush_profile(c);
+    return SQRTBA_OK;
+  }
   std::vector<double> rr(P), rr0(P);
   TRY(readback_all(c, {{c->d.iters, its.data(), sizeof(int32_t)}, {c->d.pstatus, st.data(), sizeof(int32_t)},
                        {c->d.rr, rr.data(), sizeof(double)}, {c->d.rr0, rr0.data(), sizeof(double)}}));
-  if (!kept_its.empty())
-    for (int p = 0; p < P; ++p)
-      if (c->active[p] && !fell_back[p]) {
-        its[p] = kept_its[p];
-        st[p] = kept_st[p];
-        rr[p] = kept_rr[p];
-        rr0[p] = kept_rr0[p];
-      }
   flush_profile(c);
-  for (int p = 0; p < P; ++p) {
-    if (c->active[p] && (!learned || fell_back[p])) {
-      L.last_plain_iters[p] = its[p];
-      L.last_plain_status[p] = st[p];
-    }
-    if (iters) iters[p] = its[p];
-    if (status) status[p] = st[p];
-    if (rel_res) rel_res[p] = rr0[p] > 0 ? std::sqrt(std::max(rr[p], 0.0) / rr0[p]) : 0.0;
-  }
-  c->solved = true;
-  c->backsubbed = c->updated = false;
+  finish_solve(c, learned, fell_back, its, st, rr, rr0, kept_its, kept_st, kept_rr, kept_rr0, iters, rel_res,
+               status);
+  return SQRTBA_OK;
+}
+
+// The outputs of a solve enqueued with sync = false; the stream must have been
+// waited for since (do_update waits).
+int collect_solve(sqrtba_ctx* c, int32_t* iters, double* rel_res, int32_t* status) {
+  const int P = c->h.P;
+  const size_t P4 = sizeof(int32_t) * P, P8 = sizeof(double) * P;
+  std::vector<int32_t> its(P), st(P);
+  std::vector<double> rr(P), rr0(P);
+  std::memcpy(its.data(), pinned_slice(c, 5), P4);
+  std::memcpy(st.data(), pinned_slice(c, 5) + P4, P4);
+  std::memcpy(rr.data(), pinned_slice(c, 8), P8);
+  std::memcpy(rr0.data(), pinned_slice(c, 9), P8);
+  c->solve_pending = false;
+  finish_solve(c, false, std::vector<uint8_t>(P, 0), its, st, rr, rr0, {}, {}, {}, {}, iters, rel_res, status);
   return SQRTBA_OK;
 }
 
@@ -1430,10 +1485,11 @@ int lm_loop(sqrtba_ctx* c, const double* tol_cost, sqrtba_lm_report* rep) {
     if (!any) break;
     TRY(set_active_mask(c, act));
     TRY(do_damp(c, lam.data(), false));
-    TRY(do_solve(c, its.data(), rel.data(), st.data()));
+    TRY(do_solve(c, its.data(), rel.data(), st.data(), false));
     TRY(do_backsub(c, nullptr, false));
     TRY(do_update(c, Enew.data()));  // waits, so the model decrease is in slice 4 too
     std::memcpy(pred.data(), pinned_slice(c, 4), sizeof(double) * P);
+    if (c->solve_pending) TRY(collect_solve(c, its.data(), rel.data(), st.data()));
     for (int p = 0; p < P; ++p) {
       acc[p] = 0;
       if (!act[p]) continue;
