@@ -16,6 +16,8 @@ CASES = {
     "forcing": dict(pcg_forcing_eta=0.1),
     "check_every_3": dict(pcg_check_every=3),
     "iteration_cap": dict(pcg_max_iters=7),
+    "cap_at_chunk_end": dict(pcg_max_iters=8),
+    "cap_two_chunks_of_4": dict(pcg_max_iters=8, pcg_check_every=4),
     "no_graph": dict(use_graph=0),
     "implicit": dict(landmark_blocks=1),
     "explicit_sc": dict(landmark_blocks=2),
@@ -72,3 +74,32 @@ def test_invalid_option_is_rejected(problems, bad):
     with pytest.raises(SqrtBAError) as ei:
         gpu_context(problems["mixed"], pcg_test_kernel=bad)
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_zero_right_hand_side(graph):
+    """Two cameras on one axis and landmarks on it, observed at the image centre:
+    every residual is exactly zero, so the reduced right-hand side is zero and
+    both forms stop before the first iteration (status zero_rhs), with a zero
+    step and a zero model decrease."""
+    import torch
+    from paper_2103_01843_amd import Context
+    cams = np.array([[0, 0, 0, 0, 0, -10, 500, 0, 0], [0, 0, 0, 0, 0, -20, 500, 0, 0]], np.float32)
+    pts = np.array([[0, 0, 1], [0, 0, 2], [0, 0, 3]], np.float32)
+    oc = np.array([0, 1, 0, 1, 0, 1], np.int32)
+    op = np.array([0, 0, 1, 1, 2, 2], np.int32)
+    uv = np.zeros((6, 2), np.float32)
+    out = []
+    for t in (0, 1):
+        with Context(stream=torch.cuda.current_stream(), pcg_test_kernel=t, use_graph=graph) as ctx:
+            ctx.load(cams, pts, oc, op, uv)
+            ctx.bind_torch_workspace()
+            assert ctx.linearize()[0] == 0.0
+            ctx.marginalize()
+            ctx.damp(1e-4)
+            it, rel, st = ctx.solve()
+            pred = ctx.back_substitute()
+            new = ctx.update()
+            out.append((it.tolist(), st.tolist(), pred.tolist(), new.tolist()))
+    assert out[0] == out[1]
+    assert out[0][0] == [0] and out[0][1] == [3] and out[0][2] == [0.0] and out[0][3] == [0.0]
