@@ -116,6 +116,15 @@ int64_t noalloc_elems(int64_t n_cams, int64_t out_elems, int64_t partial_elems) 
   return 12 * n_cams + out_elems + partial_elems;
 }
 hipError_t launch_matvec_noalloc(const Dev&, const Launch&, void*, int64_t, const real*, real*) { return hipSuccess; }
+#ifndef SQRTBA_FP64
+hipError_t launch_mlp_precond(const Dev&, const LearnDev&, hipStream_t) { return hipSuccess; }
+hipError_t launch_mlp_grad(const LearnDev&, const SampleSrc&, int, float*, double*, float*, hipStream_t) {
+  return hipSuccess;
+}
+hipError_t launch_adam(const LearnDev&, const float*, float, int, hipStream_t) { return hipSuccess; }
+hipError_t launch_to_bf16(const LearnDev&, hipStream_t) { return hipSuccess; }
+int mlp_tiles(int n) { return (n + 255) / 256; }
+#endif
 }  // namespace sqrtba
 
 namespace {
@@ -206,6 +215,35 @@ void run_case(uint64_t seed, int parts, int cams_per, int pts_per, int kmin, int
   check(SQRTBA_API(get_lm_history)(c, 0, nullptr, 0, &nh) == SQRTBA_OK, "history size");
   std::vector<sqrtba_lm_record> hist((size_t)std::max(1, nh));
   check(SQRTBA_API(get_lm_history)(c, 0, hist.data(), nh, &nh) == SQRTBA_OK, "history");
+  // the learned preconditioner: traces of the solves, training, learned solves with fallbacks
+  check(SQRTBA_API(mlp_init)(c, 3) == SQRTBA_OK, "mlp_init");
+  check(SQRTBA_API(pcg_trace)(c, 2, 8) == SQRTBA_OK, "pcg_trace");
+  check(SQRTBA_API(lm_solve)(c, rep.data()) == SQRTBA_OK, "lm_solve (traced)");
+  int32_t ns = 0, nr = 0;
+  check(SQRTBA_API(trace_size)(c, &ns, &nr) == SQRTBA_OK, "trace_size");
+  std::vector<double> losses(3);
+  if (nr > 0) check(SQRTBA_API(mlp_train)(c, 3, 64, 1e-3, 5, losses.data()) == SQRTBA_OK, "mlp_train");
+  std::vector<float> theta(SQRTBA_API(mlp_num_params)());
+  check(SQRTBA_API(mlp_get_params)(c, theta.data()) == SQRTBA_OK, "mlp_get_params");
+  check(SQRTBA_API(mlp_set_params)(c, theta.data()) == SQRTBA_OK, "mlp_set_params");
+  check(SQRTBA_API(set_preconditioner)(c, 1) == SQRTBA_OK, "set_preconditioner");
+  check(SQRTBA_API(lm_solve)(c, rep.data()) == SQRTBA_OK, "lm_solve (learned)");
+  int64_t ls = 0, fb = 0, wi = 0;
+  check(SQRTBA_API(learned_stats)(c, &ls, &fb, &wi) == SQRTBA_OK, "learned_stats");
+  check(SQRTBA_API(set_preconditioner)(c, 0) == SQRTBA_OK, "set_preconditioner back");
+  // inspection exports and the product without allocation
+  {
+    const int64_t nc9 = 9 * NC;
+    std::vector<float> v(2 * nc9, 0.5f), out(2 * nc9), rhs(nc9), minv(81 * NC);
+    check(SQRTBA_API(linearize)(c, cost.data()) == SQRTBA_OK, "linearize (exports)");
+    check(SQRTBA_API(marginalize)(c) == SQRTBA_OK, "marginalize (exports)");
+    check(SQRTBA_API(damp)(c, lam.data()) == SQRTBA_OK, "damp (exports)");
+    check(SQRTBA_API(debug_rcs_matvec)(c, 2, v.data(), out.data()) == SQRTBA_OK, "debug_rcs_matvec");
+    check(SQRTBA_API(rcs_matvec_noalloc)(c, v.data(), out.data()) == SQRTBA_OK, "rcs_matvec_noalloc");
+    check(SQRTBA_API(solve)(c, its.data(), rel.data(), st.data()) == SQRTBA_OK, "solve (exports)");
+    check(SQRTBA_API(debug_rhs)(c, rhs.data()) == SQRTBA_OK, "debug_rhs");
+    check(SQRTBA_API(debug_precond)(c, minv.data()) == SQRTBA_OK, "debug_precond");
+  }
   // a subset of the problems active
   if (parts > 1) {
     std::vector<uint8_t> mask(parts, 0);
